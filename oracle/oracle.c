@@ -1,0 +1,433 @@
+/*
+ * Plain FP64 CPU oracle for the SU(3) x SU(3) streaming product and the
+ * fixed set of fused site-local expressions.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code
+ * with the GPU library: its own complex arithmetic, its own walk over the
+ * stored layouts, its own float -> half rounding.
+ *
+ * Built with gcc -O2 -ffp-contract=off (no fused multiply-add, no
+ * intrinsics), so every result is the textbook sequence of IEEE double
+ * operations written below.
+ *
+ * Canonical host layout: double at ((s*3 + i)*3 + j)*2 + c for site s,
+ * row i, column j, c = 0 real / 1 imaginary.
+ *
+ * Paper anchors (Boyle et al., "Performance Portability Strategies for Grid
+ * C++ Expression Templates", Lattice 2017):
+ *   - the streaming test assigns z = x*y site by site over a lattice of
+ *     3x3 single-precision complex matrices (Section 4, Listing 3); the
+ *     matrix class is a templated N x N complex matrix (Section 4);
+ *   - expressions are evaluated site by site, _odata[ss] = eval(ss, expr)
+ *     (Section 3, Listing 1), and composite expressions such as v1+v2 and
+ *     v1+v2+v1*v2 associate left to right (Section 3, Listing 2);
+ *   - the scalar (AoS) layout and the vector (AoSoV) layout whose scalar
+ *     leaves hold several lanes (Sections 4 and 5).
+ * The reduced-precision storage forms (single, half with single-precision
+ * arithmetic, two-row compressed) are not in the paper; their steps follow
+ * the stated convention: quantise with round-to-nearest-even, widen
+ * exactly, rebuild the third row as conj(row0 x row1).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+enum { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_C12 = 3 };
+enum { L_AOS = 0, L_SOA = 1, L_AOSOA = 2 };
+enum { X_MUL = 0, X_MUL3 = 1, X_MULADD = 2, X_ADD = 3, X_APB_AB = 4 };
+
+/* ------------------------------------------------------------ one site */
+
+/* 3x3 complex matrix as 18 doubles, entry (i,j) at 2*(3i+j) (+1 for im). */
+static double re_(const double *m, int i, int j) { return m[2 * (3 * i + j)]; }
+static double im_(const double *m, int i, int j) { return m[2 * (3 * i + j) + 1]; }
+
+/* c = a * b, plain definition z_ij = sum_k a_ik b_kj, k ascending. */
+static void mat_mul(const double *a, const double *b, double *c)
+{
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double ar = re_(a, i, k), ai = im_(a, i, k);
+                double br = re_(b, k, j), bi = im_(b, k, j);
+                re += (ar * br) - (ai * bi);
+                im += (ar * bi) + (ai * br);
+            }
+            c[2 * (3 * i + j)] = re;
+            c[2 * (3 * i + j) + 1] = im;
+        }
+    }
+}
+
+static void mat_add(const double *a, const double *b, double *c)
+{
+    for (int t = 0; t < 18; ++t)
+        c[t] = a[t] + b[t];
+}
+
+/* ------------------------------------------------------- whole lattice */
+
+/* z(s) = x(s) * y(s) for every site. */
+void oracle_mult(const double *x, const double *y, double *z, int64_t V)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < V; ++s)
+        mat_mul(x + 18 * s, y + 18 * s, z + 18 * s);
+}
+
+/* Fixed fused expressions, evaluated with C++ left-to-right association:
+ *   MUL    = a*b
+ *   MUL3   = (a*b)*c
+ *   MULADD = (a*b) + (c*d)
+ *   ADD    = a + b
+ *   APB_AB = (a + b) + (a*b)
+ * Intermediates stay in double.  Returns 0, or -1 for an unknown expr. */
+int oracle_fused(int expr, const double *a, const double *b, const double *c,
+                 const double *d, double *z, int64_t V)
+{
+    if (expr < X_MUL || expr > X_APB_AB)
+        return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < V; ++s) {
+        const double *as = a + 18 * s, *bs = b + 18 * s;
+        double t1[18], t2[18];
+        double *zs = z + 18 * s;
+        switch (expr) {
+        case X_MUL:
+            mat_mul(as, bs, zs);
+            break;
+        case X_MUL3:
+            mat_mul(as, bs, t1);
+            mat_mul(t1, c + 18 * s, zs);
+            break;
+        case X_MULADD:
+            mat_mul(as, bs, t1);
+            mat_mul(c + 18 * s, d + 18 * s, t2);
+            mat_add(t1, t2, zs);
+            break;
+        case X_ADD:
+            mat_add(as, bs, zs);
+            break;
+        case X_APB_AB:
+            mat_add(as, bs, t1);
+            mat_mul(as, bs, t2);
+            mat_add(t1, t2, zs);
+            break;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------ half precision */
+
+/* IEEE binary32 -> binary16, round to nearest, ties to even, subnormals
+ * kept, overflow to infinity.  NaN stays NaN (quiet). */
+static uint16_t half_from_float(float f)
+{
+    uint32_t x;
+    memcpy(&x, &f, 4);
+    uint16_t sign = (uint16_t)((x >> 16) & 0x8000u);
+    uint32_t bexp = (x >> 23) & 0xffu;
+    uint32_t frac = x & 0x7fffffu;
+    if (bexp == 0xffu)
+        return (uint16_t)(sign | 0x7c00u | (frac ? 0x0200u : 0u));
+    if (bexp == 0u) /* float zero or subnormal: below 2^-126, rounds to 0 */
+        return sign;
+    int e = (int)bexp - 127;        /* value = m * 2^(e-23) */
+    uint32_t m = frac | 0x800000u;  /* 24-bit significand */
+    int shift;                      /* bits to drop from m */
+    int he;                         /* biased half exponent, 0 = subnormal */
+    if (e >= -14) {
+        shift = 13;
+        he = e + 15;
+    } else {
+        shift = -e - 1;             /* unit of the result is 2^-24 */
+        he = 0;
+    }
+    if (shift >= 25)
+        return sign;
+    uint32_t q = m >> shift;
+    uint32_t rem = m & ((1u << shift) - 1u);
+    uint32_t halfway = 1u << (shift - 1);
+    if (rem > halfway || (rem == halfway && (q & 1u)))
+        q += 1u;
+    if (he == 0)                    /* q <= 0x400; 0x400 is the least normal */
+        return (uint16_t)(sign | q);
+    if (q == 0x800u) {              /* carried into the next binade */
+        q = 0x400u;
+        he += 1;
+    }
+    if (he >= 31)
+        return (uint16_t)(sign | 0x7c00u);
+    return (uint16_t)(sign | ((uint32_t)he << 10) | (q & 0x3ffu));
+}
+
+static double double_from_half(uint16_t h)
+{
+    int sgn = (h >> 15) & 1;
+    int e = (h >> 10) & 31;
+    int frac = h & 0x3ff;
+    double v;
+    if (e == 0)
+        v = ldexp((double)frac, -24);
+    else if (e == 31)
+        v = frac ? NAN : INFINITY;
+    else
+        v = ldexp((double)(frac + 1024), e - 25);
+    return sgn ? -v : v;
+}
+
+/* Quantisers on flat arrays of reals. */
+void oracle_quant_f32(const double *in, float *out, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t)
+        out[t] = (float)in[t];
+}
+
+/* double -> float (RNE) -> half (RNE): two roundings, the declared
+ * convention for half storage. */
+void oracle_quant_f16(const double *in, uint16_t *out, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t)
+        out[t] = half_from_float((float)in[t]);
+}
+
+void oracle_dequant_f16(const uint16_t *in, double *out, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t)
+        out[t] = double_from_half(in[t]);
+}
+
+/* ------------------------------------------- two-row compressed storage */
+
+/* Overwrite row 2 of every matrix with conj(row0 x row1):
+ *   r2_0 = conj(r0_1 r1_2 - r0_2 r1_1)
+ *   r2_1 = conj(r0_2 r1_0 - r0_0 r1_2)
+ *   r2_2 = conj(r0_0 r1_1 - r0_1 r1_0)                                   */
+void oracle_c12_rebuild(double *m, int64_t V)
+{
+    for (int64_t s = 0; s < V; ++s) {
+        double *ms = m + 18 * s;
+        for (int k = 0; k < 3; ++k) {
+            int p = (k + 1) % 3, q = (k + 2) % 3;
+            double ar = re_(ms, 0, p), ai = im_(ms, 0, p);
+            double br = re_(ms, 1, q), bi = im_(ms, 1, q);
+            double cr = re_(ms, 0, q), ci = im_(ms, 0, q);
+            double dr = re_(ms, 1, p), di = im_(ms, 1, p);
+            double xr = (ar * br - ai * bi) - (cr * dr - ci * di);
+            double xi = (ar * bi + ai * br) - (cr * di + ci * dr);
+            ms[2 * (6 + k)] = xr;
+            ms[2 * (6 + k) + 1] = -xi;
+        }
+    }
+}
+
+/* What a stored field holds, widened back to canonical double:
+ * quantise every real, widen exactly; for the compressed form keep rows
+ * 0-1 (single precision) and rebuild row 2 in double. */
+int oracle_roundtrip(int prec, const double *in, double *out, int64_t V)
+{
+    int64_t n = 18 * V;
+    switch (prec) {
+    case P_F64:
+        memcpy(out, in, (size_t)n * sizeof(double));
+        return 0;
+    case P_F32:
+    case P_C12:
+        for (int64_t t = 0; t < n; ++t)
+            out[t] = (double)(float)in[t];
+        if (prec == P_C12)
+            oracle_c12_rebuild(out, V);
+        return 0;
+    case P_F16:
+        for (int64_t t = 0; t < n; ++t)
+            out[t] = double_from_half(half_from_float((float)in[t]));
+        return 0;
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------- stored layouts */
+
+/* Entries stored per site: 9, or 6 (rows 0-1) for the compressed form. */
+static int entries_of(int prec) { return prec == P_C12 ? 6 : 9; }
+static int real_bytes(int prec)
+{
+    return prec == P_F64 ? 8 : (prec == P_F16 ? 2 : 4);
+}
+
+/* Sites per lane-block L and padded site count for a layout:
+ *   AoS: L = 1, no padding;  AoSoA(lanes): L = lanes, pad to L;
+ *   SoA: one block holding every site, padded to a multiple of 64.       */
+static int layout_shape(int layout, int lanes, int64_t V, int64_t *L,
+                        int64_t *Vpad)
+{
+    if (layout == L_AOS) {
+        *L = 1;
+        *Vpad = V;
+    } else if (layout == L_SOA) {
+        *Vpad = (V + 63) / 64 * 64;
+        *L = *Vpad;
+    } else if (layout == L_AOSOA) {
+        if (lanes < 1)
+            return -1;
+        *L = lanes;
+        *Vpad = (V + lanes - 1) / lanes * lanes;
+    } else {
+        return -1;
+    }
+    return 0;
+}
+
+int64_t oracle_field_bytes(int prec, int layout, int lanes, int64_t V)
+{
+    int64_t L, Vpad;
+    if (layout_shape(layout, lanes, V, &L, &Vpad))
+        return -1;
+    return Vpad * entries_of(prec) * 2 * real_bytes(prec);
+}
+
+/* Write the stored image of a canonical field.  The stored order is the
+ * nested walk: lane-block b, then entry e (row-major over the stored rows),
+ * then site-in-block l, then re/im; padding sites are zero.  `out` must
+ * hold oracle_field_bytes() bytes. */
+int oracle_pack(const double *canon, int64_t V, int prec, int layout,
+                int lanes, void *out)
+{
+    int64_t L, Vpad;
+    if (layout_shape(layout, lanes, V, &L, &Vpad))
+        return -1;
+    int E = entries_of(prec);
+    int64_t w = 0;
+    for (int64_t b = 0; b < Vpad / L; ++b) {
+        for (int e = 0; e < E; ++e) {
+            for (int64_t l = 0; l < L; ++l) {
+                int64_t s = b * L + l;
+                for (int c = 0; c < 2; ++c, ++w) {
+                    double v = s < V ? canon[18 * s + 2 * e + c] : 0.0;
+                    if (prec == P_F64)
+                        ((double *)out)[w] = v;
+                    else if (prec == P_F16)
+                        ((uint16_t *)out)[w] = half_from_float((float)v);
+                    else
+                        ((float *)out)[w] = (float)v;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/* Inverse walk: stored image -> canonical double (exact widening); the
+ * compressed form gets row 2 rebuilt in double. */
+int oracle_unpack(const void *in, int64_t V, int prec, int layout, int lanes,
+                  double *canon)
+{
+    int64_t L, Vpad;
+    if (layout_shape(layout, lanes, V, &L, &Vpad))
+        return -1;
+    int E = entries_of(prec);
+    int64_t w = 0;
+    for (int64_t b = 0; b < Vpad / L; ++b) {
+        for (int e = 0; e < E; ++e) {
+            for (int64_t l = 0; l < L; ++l) {
+                int64_t s = b * L + l;
+                for (int c = 0; c < 2; ++c, ++w) {
+                    if (s >= V)
+                        continue;
+                    double v;
+                    if (prec == P_F64)
+                        v = ((const double *)in)[w];
+                    else if (prec == P_F16)
+                        v = double_from_half(((const uint16_t *)in)[w]);
+                    else
+                        v = (double)((const float *)in)[w];
+                    canon[18 * s + 2 * e + c] = v;
+                }
+            }
+        }
+    }
+    if (prec == P_C12)
+        oracle_c12_rebuild(canon, V);
+    return 0;
+}
+
+/* ------------------------------------------------------------- metrics */
+
+/* det of a 3x3 complex matrix by cofactor expansion along row 0. */
+static void mat_det(const double *m, double *dr, double *di)
+{
+    double r = 0.0, i = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        int p = (j + 1) % 3, q = (j + 2) % 3;
+        /* cofactor C_0j = m1p m2q - m1q m2p (cyclic order keeps the sign) */
+        double cr = (re_(m, 1, p) * re_(m, 2, q) - im_(m, 1, p) * im_(m, 2, q))
+                  - (re_(m, 1, q) * re_(m, 2, p) - im_(m, 1, q) * im_(m, 2, p));
+        double ci = (re_(m, 1, p) * im_(m, 2, q) + im_(m, 1, p) * re_(m, 2, q))
+                  - (re_(m, 1, q) * im_(m, 2, p) + im_(m, 1, q) * re_(m, 2, p));
+        r += re_(m, 0, j) * cr - im_(m, 0, j) * ci;
+        i += re_(m, 0, j) * ci + im_(m, 0, j) * cr;
+    }
+    *dr = r;
+    *di = i;
+}
+
+/* out[0] = E_max   = max |zh - z| over all reals
+ * out[1] = r_max   = max over sites of max_ij |zh_ij - z_ij| / max_ij |z_ij|
+ *                    (complex moduli; a site with z = 0 counts its
+ *                    absolute error)
+ * out[2] = D_U     = max over sites of max_ij |(zh zh^dagger)_ij - delta_ij|
+ * out[3] = D_det   = max over sites of |det zh - 1|
+ * `z` may be NULL: then only D_U and D_det of zh are computed.           */
+void oracle_metrics(const double *zh, const double *z, int64_t V, double *out)
+{
+    double emax = 0.0, rmax = 0.0, du = 0.0, dd = 0.0;
+    for (int64_t s = 0; s < V; ++s) {
+        const double *a = zh + 18 * s;
+        if (z) {
+            const double *b = z + 18 * s;
+            double num = 0.0, den = 0.0;
+            for (int t = 0; t < 9; ++t) {
+                double er = a[2 * t] - b[2 * t], ei = a[2 * t + 1] - b[2 * t + 1];
+                double ae = fabs(er) > fabs(ei) ? fabs(er) : fabs(ei);
+                if (ae > emax)
+                    emax = ae;
+                double d = sqrt(er * er + ei * ei);
+                double m = sqrt(b[2 * t] * b[2 * t] + b[2 * t + 1] * b[2 * t + 1]);
+                if (d > num)
+                    num = d;
+                if (m > den)
+                    den = m;
+            }
+            double r = den > 0.0 ? num / den : num;
+            if (r > rmax)
+                rmax = r;
+        }
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) {
+                double re = 0.0, im = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    /* a_ik * conj(a_jk) */
+                    re += re_(a, i, k) * re_(a, j, k) + im_(a, i, k) * im_(a, j, k);
+                    im += im_(a, i, k) * re_(a, j, k) - re_(a, i, k) * im_(a, j, k);
+                }
+                if (i == j)
+                    re -= 1.0;
+                double dev = sqrt(re * re + im * im);
+                if (dev > du)
+                    du = dev;
+            }
+        }
+        double dr, di;
+        mat_det(a, &dr, &di);
+        double dv = sqrt((dr - 1.0) * (dr - 1.0) + di * di);
+        if (dv > dd)
+            dd = dv;
+    }
+    out[0] = emax;
+    out[1] = rmax;
+    out[2] = du;
+    out[3] = dd;
+}

@@ -1,0 +1,340 @@
+"""Pins of the FP64 oracle against facts fixed by mathematics, by library
+routines or by the worked example of the paper -- never by the oracle
+itself.
+
+Each pin takes an ``oracle.Oracle`` and raises AssertionError when the
+oracle is wrong.  ``test_oracle_pins`` runs them on the real oracle;
+``test_oracle_mutants`` runs them on copies with planted mistakes and
+requires every mistake to be caught.
+"""
+from __future__ import annotations
+
+import itertools
+import os
+
+import numpy as np
+
+import oracle as O
+import testgen
+
+U64 = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def to_complex(a):
+    a = np.asarray(a)
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def from_complex(c):
+    c = np.asarray(c)
+    return np.stack([c.real, c.imag], axis=-1).astype(np.float64)
+
+
+def read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split()
+            vals[k] = float(v)
+    return vals
+
+
+# ------------------------------------------------------------ O1 product
+
+def pin_identity(orc):
+    """I*y = y and x*I = x bit-exactly (1*a and 0*b are exact; adding a
+    signed zero to a nonzero value is exact)."""
+    V = 97
+    x = testgen.su3_field(V, field_id=11)
+    eye = testgen.identity(V)
+    assert np.array_equal(orc.mult(eye, x), x)
+    assert np.array_equal(orc.mult(x, eye), x)
+
+
+def pin_phase_diag(orc):
+    """Closed form: diag(e^{ia}, e^{ib}, e^{-i(a+b)}) products are diagonal
+    with summed phases."""
+    rng = np.random.default_rng(5)
+    V = 64
+    a1, b1, a2, b2 = (rng.uniform(-np.pi, np.pi, V) for _ in range(4))
+    z = orc.mult(testgen.phase_diag(a1, b1), testgen.phase_diag(a2, b2))
+    want = testgen.phase_diag(a1 + a2, b1 + b2)
+    assert np.max(np.abs(z - want)) <= 8 * U64
+
+
+def pin_signed_permutations(orc):
+    """The 24 signed permutation matrices with det 1 form a group; every
+    product is exact and equals the integer matrix product."""
+    mats = testgen.signed_permutations()
+    assert len(mats) == 24
+    pairs = list(itertools.product(range(24), repeat=2))
+    x = testgen.from_int_matrices([mats[i] for i, _ in pairs])
+    y = testgen.from_int_matrices([mats[j] for _, j in pairs])
+    want = testgen.from_int_matrices([mats[i] @ mats[j] for i, j in pairs])
+    assert np.array_equal(orc.mult(x, y), want)
+
+
+def pin_unitary_inverse(orc):
+    """x * x^dagger = I within a few ulps for x in SU(3)."""
+    V = 256
+    x = testgen.su3_field(V, field_id=12)
+    xd = from_complex(np.conj(np.transpose(to_complex(x), (0, 2, 1))))
+    z = orc.mult(x, xd)
+    assert np.max(np.abs(z - testgen.identity(V))) <= 8 * U64
+
+
+def pin_numpy_matmul(orc):
+    """Brute force on 1^4 and 2^4 lattices (and a 3^4 one) against a
+    pure-Python triple loop on complex numbers and numpy.matmul on
+    complex128."""
+    for V, fx, fy in ((1, 13, 14), (16, 15, 16), (81, 17, 18)):
+        x = testgen.su3_field(V, field_id=fx)
+        y = testgen.su3_field(V, field_id=fy)
+        z = to_complex(orc.mult(x, y))
+        xc, yc = to_complex(x), to_complex(y)
+        assert np.max(np.abs(z - np.matmul(xc, yc))) <= 4 * U64
+        if V <= 16:
+            for s in range(V):
+                for i in range(3):
+                    for j in range(3):
+                        acc = 0j
+                        for k in range(3):
+                            acc += complex(xc[s, i, k]) * complex(yc[s, k, j])
+                        assert abs(z[s, i, j] - acc) <= 4 * U64
+
+
+def pin_nonsymmetric(orc):
+    """Integer-valued, non-symmetric, non-unitary matrices: every product
+    is exact, so a transposed operand or a lost term shows as a mismatch."""
+    rng = np.random.default_rng(7)
+    V = 200
+    xr, xi, yr, yi = (rng.integers(-9, 10, (V, 3, 3)) for _ in range(4))
+    x = np.stack([xr, xi], -1).astype(np.float64)
+    y = np.stack([yr, yi], -1).astype(np.float64)
+    want = np.matmul(xr + 1j * xi, yr + 1j * yi)
+    assert np.array_equal(to_complex(orc.mult(x, y)), want)
+
+
+def pin_product_invariants(orc):
+    """SU(3) x SU(3) stays in SU(3): unitarity and det = 1 (checked with
+    numpy, independent of the oracle's metrics)."""
+    V = 512
+    z = to_complex(orc.mult(testgen.su3_field(V, field_id=19),
+                            testgen.su3_field(V, field_id=20)))
+    zzd = np.matmul(z, np.conj(np.transpose(z, (0, 2, 1))))
+    assert np.max(np.abs(zzd - np.eye(3))) <= 8e-15
+    assert np.max(np.abs(np.linalg.det(z) - 1.0)) <= 8e-15
+
+
+def pin_associative(orc):
+    V = 256
+    x, y, w = (testgen.su3_field(V, field_id=f) for f in (21, 22, 23))
+    lhs = orc.mult(orc.mult(x, y), w)
+    rhs = orc.mult(x, orc.mult(y, w))
+    assert np.max(np.abs(lhs - rhs)) <= 3e-15
+
+
+# --------------------------------------------------------- O2 fused
+
+def pin_listing2(orc):
+    """The composite expressions of Listing 2 on SU(3)-typed fields."""
+    g = read_golden("listing2_composite.txt")
+    V = 8
+    a = testgen.identity(V, g["v1"])
+    b = testgen.identity(V, g["v2"])
+    assert np.array_equal(orc.fused(O.ADD, [a, b]), testgen.identity(V, g["ADD"]))
+    assert np.array_equal(orc.fused(O.APB_AB, [a, b]),
+                          testgen.identity(V, g["APB_AB"]))
+
+
+def pin_fused_reductions(orc):
+    """MUL3(a, I, c) = MUL(a, c) and MULADD(a, b, 0, 0) = MUL(a, b)
+    bit-exactly; MUL equals the product."""
+    V = 128
+    a, b, c = (testgen.su3_field(V, field_id=f) for f in (24, 25, 26))
+    eye, zero = testgen.identity(V), np.zeros_like(a)
+    ac = orc.mult(a, c)
+    assert np.array_equal(orc.fused(O.MUL3, [a, eye, c]), ac)
+    assert np.array_equal(orc.fused(O.MULADD, [a, c, zero, zero]), ac)
+    assert np.array_equal(orc.fused(O.MUL, [a, c]), ac)
+
+
+def pin_fused_numpy(orc):
+    """Each expression against numpy on complex128 (integer-valued inputs,
+    so every result is exact)."""
+    rng = np.random.default_rng(8)
+    V = 100
+    ops = [rng.integers(-5, 6, (V, 3, 3, 2)).astype(np.float64)
+           for _ in range(4)]
+    a, b, c, d = (to_complex(o) for o in ops)
+    want = {O.MUL: a @ b, O.MUL3: (a @ b) @ c, O.MULADD: a @ b + c @ d,
+            O.ADD: a + b, O.APB_AB: (a + b) + a @ b}
+    for expr, w in want.items():
+        got = orc.fused(expr, ops[:O.N_OPERANDS[expr]])
+        assert np.array_equal(to_complex(got), w), expr
+
+
+def pin_fused_unitary(orc):
+    V = 256
+    a, b, c = (testgen.su3_field(V, field_id=f) for f in (27, 28, 29))
+    z = to_complex(orc.fused(O.MUL3, [a, b, c]))
+    zzd = np.matmul(z, np.conj(np.transpose(z, (0, 2, 1))))
+    assert np.max(np.abs(zzd - np.eye(3))) <= 1.2e-14
+    assert np.max(np.abs(np.linalg.det(z) - 1.0)) <= 1.2e-14
+
+
+# ---------------------------------------------- O3 quantisers and layouts
+
+def special_reals():
+    f16max = 65504.0
+    vals = [0.0, -0.0, 1.0, -1.0, 0.5, 1.0 / 3.0, 2.0 ** -14, 2.0 ** -24,
+            2.0 ** -25, 1.5 * 2.0 ** -25, 2.0 ** -26, 3 * 2.0 ** -25,
+            2.0 ** -24 * 1.5, 2.0 ** -24 * 2.5, f16max, 65519.0, 65520.0,
+            65536.0, 1e6, 1e-10, 2.0 ** -149, 2.0 ** -126, 1e39, -1e39,
+            np.inf, -np.inf, 1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11,
+            1 + 2.0 ** -11 + 2.0 ** -30, 2049.0, 2051.0, 4097.0]
+    # ties and near-ties in float -> half at several binades
+    for e in range(-24, 16):
+        for m in (1025, 1027, 2047):
+            v = m * 2.0 ** (e - 11)
+            vals += [v, -v, np.nextafter(v, 0), np.nextafter(v, np.inf)]
+    return np.array(vals, dtype=np.float64)
+
+
+def pin_quantisers(orc):
+    """double->float and double->float->half are bit-exact against numpy's
+    round-to-nearest-even conversions; half->double is exact."""
+    rng = np.random.default_rng(9)
+    v = np.concatenate([special_reals(),
+                        rng.standard_normal(20000),
+                        rng.standard_normal(20000) * 10.0 ** rng.integers(-9, 6, 20000)])
+    f = orc.quant_f32(v)
+    assert np.array_equal(f.view(np.uint32), v.astype(np.float32).view(np.uint32))
+    h = orc.quant_f16(v)
+    want = v.astype(np.float32).astype(np.float16)
+    assert np.array_equal(h, want.view(np.uint16))
+    back = orc.dequant_f16(h)
+    assert np.array_equal(back, want.astype(np.float64))
+    # every half bit pattern except NaNs widens exactly
+    allh = np.arange(65536, dtype=np.uint16)
+    ref = allh.view(np.float16).astype(np.float64)
+    got = orc.dequant_f16(allh)
+    ok = ~np.isnan(ref)
+    assert np.array_equal(got[ok], ref[ok])
+    assert np.all(np.isnan(got[~ok]))
+
+
+def pin_c12_rebuild(orc):
+    """Row 2 rebuilt as conj(row0 x row1) against numpy.cross; on SU(3)
+    input the rebuilt matrix equals the original."""
+    V = 300
+    rng = np.random.default_rng(10)
+    m = rng.standard_normal((V, 3, 3, 2))
+    got = to_complex(orc.c12_rebuild(m))
+    mc = to_complex(m)
+    want_row2 = np.conj(np.cross(mc[:, 0, :], mc[:, 1, :]))
+    assert np.max(np.abs(got[:, 2, :] - want_row2)) <= 1e-13 * np.max(np.abs(want_row2))
+    assert np.array_equal(got[:, :2, :], mc[:, :2, :])
+    u = testgen.su3_field(V, field_id=30)
+    assert np.max(np.abs(orc.c12_rebuild(u) - u)) <= 4 * U64
+
+
+def _stored_numpy(a, prec, layout, lanes):
+    """Stored image built with numpy reshapes: the entry axis is moved
+    outside the site-in-block axis, padding sites are zero."""
+    V = a.shape[0]
+    E = 6 if prec == O.C12 else 9
+    ent = a.reshape(V, 9, 2)[:, :E, :]
+    if layout == O.AOS:
+        L, Vpad = 1, V
+    elif layout == O.SOA:
+        Vpad = -(-V // 64) * 64
+        L = Vpad
+    else:
+        L, Vpad = lanes, -(-V // lanes) * lanes
+    padded = np.zeros((Vpad, E, 2))
+    padded[:V] = ent
+    img = padded.reshape(Vpad // L, L, E, 2).transpose(0, 2, 1, 3).reshape(-1)
+    if prec == O.F64:
+        return img.view(np.uint8)
+    if prec == O.F16:
+        return img.astype(np.float32).astype(np.float16).view(np.uint8)
+    return img.astype(np.float32).view(np.uint8)
+
+
+LAYOUT_CASES = [(O.AOS, 0), (O.SOA, 0), (O.AOSOA, 8), (O.AOSOA, 16),
+                (O.AOSOA, 32), (O.AOSOA, 64)]
+
+
+def pin_layouts(orc):
+    """Stored images equal numpy's reshape/transpose construction for every
+    precision and layout, including ragged volumes; unpack inverts pack
+    (exactly for double)."""
+    for V in (1, 5, 64, 77, 130):
+        x = testgen.su3_field(V, field_id=31)
+        for prec in (O.F64, O.F32, O.F16, O.C12):
+            for layout, lanes in LAYOUT_CASES:
+                img = orc.pack(x, prec, layout, lanes)
+                want = _stored_numpy(x, prec, layout, lanes)
+                assert img.size == want.size == orc.field_bytes(prec, layout, lanes, V)
+                assert np.array_equal(img, want), (V, prec, layout, lanes)
+                back = orc.unpack(img, V, prec, layout, lanes)
+                assert np.array_equal(back, orc.roundtrip(prec, x)), (V, prec, layout)
+        assert np.array_equal(orc.unpack(orc.pack(x, O.F64, O.SOA), V, O.F64, O.SOA), x)
+
+
+def pin_roundtrip(orc):
+    V = 50
+    x = testgen.su3_field(V, field_id=32)
+    assert np.array_equal(orc.roundtrip(O.F64, x), x)
+    assert np.array_equal(orc.roundtrip(O.F32, x),
+                          x.astype(np.float32).astype(np.float64))
+    assert np.array_equal(orc.roundtrip(O.F16, x),
+                          x.astype(np.float32).astype(np.float16).astype(np.float64))
+    r = orc.roundtrip(O.C12, x)
+    xc = to_complex(x.astype(np.float32).astype(np.float64))
+    assert np.array_equal(to_complex(r)[:, :2], xc[:, :2])
+    assert np.max(np.abs(to_complex(r)[:, 2] -
+                         np.conj(np.cross(xc[:, 0], xc[:, 1])))) <= 1e-15
+
+
+# ------------------------------------------------------------ O5 metrics
+
+def pin_metrics(orc):
+    """Closed-form values: 2I has |2I (2I)^dagger - I| = 3 and det 8; a
+    single perturbed entry gives the expected absolute and relative
+    error."""
+    V = 4
+    m = orc.metrics(testgen.identity(V, 2.0))
+    assert m["d_u"] == 3.0 and m["d_det"] == 7.0
+    u = testgen.su3_field(V, field_id=33)
+    m0 = orc.metrics(u, u)
+    assert m0["e_max"] == 0.0 and m0["r_max"] == 0.0
+    assert m0["d_u"] < 1e-15 and m0["d_det"] < 1e-15
+    p = u.copy()
+    p[2, 1, 2, 1] += 1e-3
+    m1 = orc.metrics(p, u)
+    assert abs(m1["e_max"] - 1e-3) < 1e-15
+    den = np.max(np.abs(to_complex(u[2])))
+    assert abs(m1["r_max"] - 1e-3 / den) < 1e-12
+    # diag(i, i, -1): unitary with det = i*i*(-1) = 1
+    dph = testgen.phase_diag(np.full(V, np.pi / 2), np.full(V, np.pi / 2))
+    m2 = orc.metrics(dph)
+    assert m2["d_u"] < 1e-15 and m2["d_det"] < 1e-15
+    # diag(i, 1, 1): unitary, det = i -> |i - 1| = sqrt 2
+    q = testgen.identity(V)
+    q[:, 0, 0] = (0.0, 1.0)
+    m3 = orc.metrics(q)
+    assert m3["d_u"] < 1e-15 and abs(m3["d_det"] - np.sqrt(2.0)) < 1e-15
+
+
+ALL_PINS = [pin_identity, pin_phase_diag, pin_signed_permutations,
+            pin_unitary_inverse, pin_numpy_matmul, pin_nonsymmetric,
+            pin_product_invariants, pin_associative, pin_listing2,
+            pin_fused_reductions, pin_fused_numpy, pin_fused_unitary,
+            pin_quantisers, pin_c12_rebuild, pin_layouts, pin_roundtrip,
+            pin_metrics]
