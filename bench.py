@@ -1,0 +1,440 @@
+#!/usr/bin/env python3
+"""SU(3) x SU(3) streaming benchmark on one MI355X.
+
+A step is one evaluation of z(x) = x(x) * y(x) over a 48^4 lattice of SU(3)
+matrices stored in double precision, structure-of-arrays layout (the
+streaming test of Section 4, Listing 3).  Inputs are seeded synthetic
+Haar-random SU(3) fields already resident in HBM; the timed region is K
+back-to-back launches bracketed by device synchronisation.
+
+Prints ONE JSON line on stdout (progress goes to stderr):
+  value        achieved GB/s = 432 B/site * V / (time per step)
+  roofline     the dominant kernel against the 8 TB/s HBM peak, timed with
+               HIP events on the launch stream; traffic from the committed
+               PMC summary (null if the kernel changed since)
+  cpu_baseline the FP64 oracle on the host cores, on a bounded sample
+  variants     the precision forms (F32, F16 with F32 arithmetic, two-row
+               compressed F32) at 48^4, the layouts (AoS, AoS+LDS, AoSoA),
+               the volume sweep, fused vs chained expressions at 32^4, the
+               64-lattice batch replayed from a HIP graph, and the triad
+               ceiling -- each in GB/s of its own algorithmic bytes
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = ("SU(3)×SU(3) achieved HBM GB/s (% of peak) at 48^4, "
+          "FP64 vs FP32/compressed")
+
+# algorithmic bytes per site: every operand read once, the result written
+# once, in its stored format
+BYTES_PER_SITE = {0: 432, 1: 216, 2: 108, 3: 144}   # MUL by precision
+FLOPS_PER_SITE = {0: 198, 1: 396, 2: 414, 3: 18, 4: 234}
+REAL_BYTES = {0: 8, 1: 4, 2: 2, 3: 4}
+PREC_NAME = {0: "f64", 1: "f32", 2: "f16_f32acc", 3: "c12_f32"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def expr_bytes_per_site(prec, expr):
+    E = 6 if prec == 3 else 9
+    site = E * 2 * REAL_BYTES[prec]
+    nops = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}[expr]
+    return site * (nops + 1)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=1710)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="headline only (for profiler runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's default launch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run plain copies of known size (PMC scaling)")
+    return ap.parse_args()
+
+
+class Timer:
+    """K launches between two events on `stream`, plus host wall time
+    between synchronisations."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def run(self, launch, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            launch()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(self.stream)
+        for _ in range(steps):
+            launch()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        host_s = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / steps, host_s  # ms per launch (events)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1710_09409_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """Counter-derived HBM bytes per launch of the headline kernel, from the
+    committed PMC summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "su3_mult_f64_soa_48x48x48x48_pmc.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every "
+              "site is independent, so a multi-GPU run would shard the lattice "
+              "with no exchange step; see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import testgen
+    import paper_1710_09409_amd as su3
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    timer = Timer(torch, stream)
+    props = torch.cuda.get_device_properties(0)
+    log(f"device: {props.name} ({getattr(props, 'gcnArchName', '?')}), "
+        f"{props.multi_processor_count} CUs")
+
+    host_cache = {}
+
+    def host_field(V, fid):
+        key = (V, fid)
+        if key not in host_cache:
+            host_cache[key] = testgen.su3_field(V, seed=args.seed, field_id=fid)
+        return host_cache[key]
+
+    def make(dims, prec, layout, lanes, fid):
+        f = su3.field_tensor(dims, prec, layout, lanes)
+        su3.su3_field_upload(f, host_field(testgen.volume(dims), fid), stream)
+        return f
+
+    def tune(expr, prec, layout, lanes, dims):
+        if args.no_tune:
+            return su3.su3_launch_get(expr, prec, layout, lanes, dims).as_dict()
+        return su3.su3_autotune(expr, prec, layout, lanes, dims, stream).as_dict()
+
+    # ------------------------------------------------------------ headline
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    F64, SOA = su3.SU3_F64, su3.SU3_LAYOUT_SOA
+    log(f"headline: z = x*y, {V} sites, FP64 SoA; generating inputs")
+    x = make(dims, F64, SOA, 0, testgen.FID_X)
+    y = make(dims, F64, SOA, 0, testgen.FID_Y)
+    z = su3.field_tensor(dims, F64, SOA, 0)
+    cfg = tune(su3.SU3_EXPR_MUL, F64, SOA, 0, dims)
+    log(f"launch: {cfg}")
+    step_bytes = BYTES_PER_SITE[0] * V
+    ms_ev, host_s = timer.run(lambda: su3.su3_mult(z, x, y, stream),
+                              args.steps, args.warmup)
+    ms_per_step = host_s * 1e3 / args.steps
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    achieved = step_bytes / (ms_ev * 1e-3) / 1e9
+    log(f"headline: {ms_ev * 1e3:.1f} us/launch (events), {achieved:.0f} GB/s "
+        f"= {100 * achieved / HBM_PEAK_GBPS:.1f}% of 8 TB/s")
+    traffic = committed_traffic()
+
+    # triad ceiling over the same bytes (2 read streams + 1 write stream)
+    n = step_bytes // 24
+    ta = torch.empty(n, dtype=torch.float64, device="cuda")
+    tb = torch.ones(n, dtype=torch.float64, device="cuda")
+    tc = torch.ones(n, dtype=torch.float64, device="cuda")
+    ms_tr, _ = timer.run(lambda: su3.su3_triad(ta.data_ptr(), tb.data_ptr(),
+                                               tc.data_ptr(), 3.0, n, stream),
+                         args.steps, args.warmup)
+    triad = 24 * n / (ms_tr * 1e-3) / 1e9
+    log(f"triad: {triad:.0f} GB/s")
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        cs = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        cd = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        for _ in range(5):
+            su3.su3_copy(cd.data_ptr(), cs.data_ptr(), nbytes, stream)
+        torch.cuda.synchronize()
+        del cs, cd
+    del ta, tb, tc
+
+    variants = {"triad_gbps": round(triad, 1),
+                "headline_frac_of_triad": round(achieved / triad, 4)}
+
+    if not args.no_variants:
+        variants.update(run_variants(args, su3, torch, testgen, np, stream,
+                                     timer, make, tune, x, y, z, dims, ms_ev))
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(host_field(V, testgen.FID_X),
+                           host_field(V, testgen.FID_Y))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Haar-random SU(3), seed %d)" % args.seed,
+        "config": {
+            "workload": "su3_mult z=x*y, 48^4 lattice (5,308,416 sites), FP64 "
+                        "storage and arithmetic, SoA layout, 432 B/site",
+            "dims": list(dims), "sites": V, "bytes_per_step": step_bytes,
+            "flops_per_step": FLOPS_PER_SITE[0] * V,
+            "gflops": round(FLOPS_PER_SITE[0] * V / (ms_ev * 1e-3) / 1e9, 1),
+            "launch": cfg,
+            "input_sha256": {"x": testgen.buffer_sha256(host_field(V, testgen.FID_X))[:16],
+                             "y": testgen.buffer_sha256(host_field(V, testgen.FID_Y))[:16]},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "kernel": "k_site<MUL, 1 site/lane> (FP64 SoA)",
+            "avg_launch_us": round(ms_ev * 1e3, 2),
+            "bytes_per_launch": step_bytes,
+        },
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
+                 x64, y64, z64, dims, ms_f64):
+    out = {}
+    V = testgen.volume(dims)
+    steps = max(10, min(args.steps, 50))
+    SOA, AOS, AOSOA = su3.SU3_LAYOUT_SOA, su3.SU3_LAYOUT_AOS, su3.SU3_LAYOUT_AOSOA
+
+    # precision forms at 48^4 (SoA)
+    prec_out = {}
+    for prec in (su3.SU3_F32, su3.SU3_F16_F32ACC, su3.SU3_C12_F32):
+        x = make(dims, prec, SOA, 0, testgen.FID_X)
+        y = make(dims, prec, SOA, 0, testgen.FID_Y)
+        z = su3.field_tensor(dims, prec, SOA, 0)
+        cfg = tune(su3.SU3_EXPR_MUL, prec, SOA, 0, dims)
+        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
+        b = BYTES_PER_SITE[prec] * V
+        prec_out[PREC_NAME[prec]] = {
+            "us": round(ms * 1e3, 2), "gbps": round(b / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "speedup_vs_f64": round(ms_f64 / ms, 3), "launch": cfg}
+        log(f"precision {PREC_NAME[prec]}: {prec_out[PREC_NAME[prec]]}")
+        del x, y, z
+    out["precision_48^4"] = prec_out
+
+    # layouts at 48^4 (FP64)
+    lay_out = {}
+    cases = [("aos", AOS, 0, 0), ("aos_lds", AOS, 0, 1)] + \
+        [(f"aosoa{L}", AOSOA, L, 0) for L in (8, 16, 32, 64)]
+    for name, lay, lanes, lds in cases:
+        x = make(dims, su3.SU3_F64, lay, lanes, testgen.FID_X)
+        y = make(dims, su3.SU3_F64, lay, lanes, testgen.FID_Y)
+        z = su3.field_tensor(dims, su3.SU3_F64, lay, lanes)
+        if lay == AOS:
+            cfg = su3.su3_launch_get(0, 0, lay, lanes, dims).as_dict()
+            cfg.update(lds_stage=lds, block=64)
+            su3.su3_launch_set(0, 0, lay, lanes, dims, cfg)
+        else:
+            cfg = tune(su3.SU3_EXPR_MUL, su3.SU3_F64, lay, lanes, dims)
+        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
+        lay_out[name] = {"us": round(ms * 1e3, 2),
+                         "gbps": round(432 * V / (ms * 1e-3) / 1e9, 1),
+                         "launch": cfg}
+        log(f"layout {name}: {lay_out[name]}")
+        del x, y, z
+    out["layouts_f64_48^4"] = lay_out
+
+    # volume sweep (FP64 SoA); sizes below 2x the 256 MiB Infinity Cache
+    # are cache-resident when hot, not HBM figures
+    sweep = {}
+    for L in (16, 24, 32):
+        d = (L, L, L, L)
+        Vs = testgen.volume(d)
+        x = make(d, su3.SU3_F64, SOA, 0, 10 + L)
+        y = make(d, su3.SU3_F64, SOA, 0, 11 + L)
+        z = su3.field_tensor(d, su3.SU3_F64, SOA, 0)
+        cfg = tune(su3.SU3_EXPR_MUL, su3.SU3_F64, SOA, 0, d)
+        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
+        ws = 432 * Vs
+        sweep[f"{L}^4"] = {"us": round(ms * 1e3, 2),
+                           "gbps": round(ws / (ms * 1e-3) / 1e9, 1),
+                           "working_set_bytes": ws,
+                           "cache_resident": ws < 2 * 268435456}
+        log(f"sweep {L}^4: {sweep[f'{L}^4']}")
+        del x, y, z
+    sweep["48^4"] = {"us": round(ms_f64 * 1e3, 2),
+                     "gbps": round(432 * V / (ms_f64 * 1e-3) / 1e9, 1),
+                     "working_set_bytes": 432 * V, "cache_resident": False}
+    out["sweep_f64_soa"] = sweep
+
+    # fused vs chained at 32^4 with four link fields
+    d = (32, 32, 32, 32)
+    Vf = testgen.volume(d)
+    fused = {}
+    for prec in (su3.SU3_F64, su3.SU3_F32):
+        U = [make(d, prec, SOA, 0, testgen.FID_U0 + mu) for mu in range(4)]
+        z = su3.field_tensor(d, prec, SOA, 0)
+        t1 = su3.field_tensor(d, prec, SOA, 0)
+        t2 = su3.field_tensor(d, prec, SOA, 0)
+        for expr, name in ((su3.SU3_EXPR_MUL3, "mul3"), (su3.SU3_EXPR_MULADD, "muladd")):
+            nops = 3 if expr == su3.SU3_EXPR_MUL3 else 4
+            cfg = tune(expr, prec, SOA, 0, d)
+            ms_f, _ = timer.run(lambda: su3.su3_fused_eval(z, expr, U[:nops], stream),
+                                steps, 3)
+            if expr == su3.SU3_EXPR_MUL3:
+                def chained():
+                    su3.su3_mult(t1, U[0], U[1], stream)
+                    su3.su3_mult(z, t1, U[2], stream)
+            else:
+                def chained():
+                    su3.su3_mult(t1, U[0], U[1], stream)
+                    su3.su3_mult(t2, U[2], U[3], stream)
+                    su3.su3_fused_eval(z, su3.SU3_EXPR_ADD, [t1, t2], stream)
+            ms_c, _ = timer.run(chained, steps, 3)
+            b = expr_bytes_per_site(prec, expr) * Vf
+            fused[f"{PREC_NAME[prec]}_{name}"] = {
+                "fused_us": round(ms_f * 1e3, 2), "chained_us": round(ms_c * 1e3, 2),
+                "fused_gbps": round(b / (ms_f * 1e-3) / 1e9, 1),
+                "speedup": round(ms_c / ms_f, 3), "launch": cfg}
+            log(f"fused {PREC_NAME[prec]} {name}: {fused[f'{PREC_NAME[prec]}_{name}']}")
+        del U, z, t1, t2
+    out["fused_32^4"] = fused
+
+    # 64 uneven lattices, mixed FP64 and compressed FP32, one graph replay
+    lat = testgen.batch_lattices(64, seed=args.seed)
+    zs, ops, exprs = [], [], []
+    total_bytes = 0
+    log("batch: generating 64 lattices")
+    for i, (d, comp) in enumerate(lat):
+        prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
+        Vi = testgen.volume(d)
+        ops.append([make(d, prec, SOA, 0, testgen.FID_BATCH_BASE + 4 * i + k)
+                    for k in range(2)])
+        zs.append(su3.field_tensor(d, prec, SOA, 0))
+        exprs.append(su3.SU3_EXPR_MUL)
+        total_bytes += BYTES_PER_SITE[prec] * Vi
+    total_sites = sum(testgen.volume(d) for d, _ in lat)
+    key_prec = zs[0].prec
+    bcfg = None
+    if not args.no_tune:
+        bcfg = tune_batch(su3, timer, stream, exprs, zs, ops, key_prec,
+                          total_sites)
+    b = su3.su3_batch_create(exprs, zs, ops, stream)
+    ms_b, _ = timer.run(lambda: su3.su3_batch_launch(b, stream), 100, 3)
+    out["batch_64"] = {
+        "lattices": 64, "sites": total_sites, "bytes": total_bytes,
+        "n_c12": sum(1 for _, c in lat if c),
+        "us": round(ms_b * 1e3, 2),
+        "gbps": round(total_bytes / (ms_b * 1e-3) / 1e9, 1),
+        "replays": 100, "tile_sites": (bcfg or {}).get("tile_sites")}
+    log(f"batch: {out['batch_64']}")
+    su3.su3_batch_destroy(b)
+    del zs, ops
+    return out
+
+
+def tune_batch(su3, timer, stream, exprs, zs, ops, key_prec, total_sites):
+    """The batch's tile size and per-CU workgroups: time a small grid of
+    candidates (each a captured graph) and keep the fastest."""
+    best, best_ms = None, 1e30
+    key = (exprs[0], key_prec, zs[0].layout, zs[0].lanes, (total_sites, 1, 1, 1))
+    base = su3.su3_launch_get(*key).as_dict()
+    for tile in (1024, 2048, 4096, 8192, 16384):
+        for per_cu in (4, 8, 16):
+            for nt in (0, 3):
+                cfg = dict(base, tile_sites=tile, persistent=per_cu, block=256,
+                           nontemporal=nt, xcd_remap=0, lds_stage=0)
+                su3.su3_launch_set(*key, cfg)
+                b = su3.su3_batch_create(exprs, zs, ops, stream)
+                ms, _ = timer.run(lambda: su3.su3_batch_launch(b, stream), 10, 2)
+                su3.su3_batch_destroy(b)
+                if ms < best_ms:
+                    best, best_ms = cfg, ms
+    su3.su3_launch_set(*key, best)
+    log(f"batch tune: {best} {best_ms * 1e3:.1f} us")
+    return best
+
+
+def cpu_baseline(x, y):
+    """The FP64 oracle, as it stands, on the host cores: full 48^4 products
+    repeated until at least 10 s have passed."""
+    import oracle
+    orc = oracle.get()
+    V = x.shape[0]
+    passes, t0 = 0, time.perf_counter()
+    while True:
+        orc.mult(x, y)
+        passes += 1
+        el = time.perf_counter() - t0
+        if el >= 10.0 or passes >= 5000:
+            break
+    gbps = 432 * V * passes / el / 1e9
+    log(f"cpu baseline: {passes} passes in {el:.1f} s, {gbps:.2f} GB/s, "
+        f"{orc.threads()} threads")
+    return {"value": round(gbps, 3), "unit": "GB/s", "cores": orc.threads(),
+            "kind": "oracle",
+            "sample": f"{passes} full z=x*y passes over the 48^4 lattice "
+                      f"({V} sites, same seeded inputs), {el:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

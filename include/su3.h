@@ -1,0 +1,265 @@
+/*
+ * su3.h -- C ABI of the MI355X (gfx950) SU(3) x SU(3) streaming library.
+ *
+ * The library evaluates site-local expressions of 3x3 complex matrix
+ * fields over a 4D lattice, z(x) = x(x) * y(x) first of all: the
+ * lattice-wide SU(3) x SU(3) streaming test of Boyle et al., "Performance
+ * Portability Strategies for Grid C++ Expression Templates" (Lattice 2017),
+ * Section 4 (Listing 3), evaluated site by site as in Section 3
+ * (Listing 1: _odata[ss] = eval(ss, expr)), in the coalesced layouts that
+ * Sections 4 and 5 motivate.
+ *
+ * Conventions shared by every entry point:
+ *   - Plain C types only.  Handles are opaque.  No C++ exception crosses
+ *     the boundary; every call returns an su3_status, and su3_last_error()
+ *     gives a thread-local text for the last failing call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream of
+ *     the current device), e.g. torch.cuda.current_stream().cuda_stream.
+ *     Compute calls are asynchronous on that stream.  Uploads and downloads
+ *     complete before they return.
+ *   - Arguments are validated before any HIP call; a failed validation
+ *     launches nothing and changes nothing.
+ *   - Asynchronous kernel faults surface at the next call that
+ *     synchronises (su3_sync, upload, download) as SU3_ERR_HIP.
+ *   - Values are not inspected: NaN and Inf pass through.
+ *
+ * Canonical host layout (upload/download): double at
+ * ((s*3 + i)*3 + j)*2 + c for site s = x + Lx*(y + Ly*(z + Lz*t)), row i,
+ * column j, c = 0 real / 1 imaginary (18 doubles per site).
+ *
+ * Stored layouts on the device.  A field of V sites stores E complex
+ * entries per site (E = 9; E = 6 for SU3_C12_F32, rows 0 and 1).  Sites are
+ * grouped in lane-blocks of L sites, padded to V_pad = a multiple of L:
+ *     AOS    L = 1,        V_pad = V          (Section 4's scalar layout)
+ *     AOSOA  L = lanes,    V_pad = roundup(V, lanes), lanes in {8,16,32,64}
+ *            (Section 5's vector layout: each scalar leaf holds L lanes)
+ *     SOA    L = V_pad,    V_pad = roundup(V, 64)  (one block: entry planes)
+ * Real number (s, e, c) sits at element
+ *     ((s / L) * E + e) * 2L + (s % L) * 2 + c
+ * of an array of the stored real type (double, float, or IEEE half).  The
+ * field occupies V_pad * E * 2 * sizeof(real) bytes.  Padding sites are
+ * zero after su3_field_alloc/su3_field_upload and are never written by a
+ * compute call.
+ */
+#ifndef SU3_H
+#define SU3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum su3_status {
+    SU3_OK = 0,
+    SU3_ERR_INVALID_ARG = -1,   /* null pointer, bad size/enum, bad buffer */
+    SU3_ERR_MISMATCH = -2,      /* operands differ in dims/precision/layout */
+    SU3_ERR_UNSUPPORTED = -3,   /* valid arguments, combination not offered */
+    SU3_ERR_OUT_OF_MEMORY = -4, /* device allocation failed */
+    SU3_ERR_ALIAS = -5,         /* output partially overlaps an operand */
+    SU3_ERR_HIP = -6            /* HIP runtime error (text in su3_last_error) */
+} su3_status;
+
+/* Storage precision.  Arithmetic is double for SU3_F64 and single for the
+ * others (fused multiply-add allowed).  Quantisation from double uses
+ * round-to-nearest-even: F32 once; F16 double->float->half (two roundings,
+ * subnormals kept); C12 stores rows 0-1 as float and rebuilds row 2 as
+ * conj(row0 x row1) in registers. */
+typedef enum su3_precision {
+    SU3_F64 = 0,
+    SU3_F32 = 1,
+    SU3_F16_F32ACC = 2,
+    SU3_C12_F32 = 3
+} su3_precision;
+
+typedef enum su3_layout {
+    SU3_LAYOUT_AOS = 0,
+    SU3_LAYOUT_SOA = 1,
+    SU3_LAYOUT_AOSOA = 2
+} su3_layout;
+
+/* Fixed site-local expressions (Section 3, Listings 1-2; left-to-right
+ * association as in v1+v2+v1*v2):
+ *   MUL    z = a*b            (2 operands)  -- the streaming test, Listing 3
+ *   MUL3   z = (a*b)*c        (3 operands)
+ *   MULADD z = (a*b) + (c*d)  (4 operands)
+ *   ADD    z = a + b          (2 operands)
+ *   APB_AB z = (a+b) + (a*b)  (2 operands)
+ * Intermediates stay in registers in the arithmetic precision.
+ * SU3_C12_F32 supports MUL and MUL3 only (sums leave SU(3)). */
+typedef enum su3_expr {
+    SU3_EXPR_MUL = 0,
+    SU3_EXPR_MUL3 = 1,
+    SU3_EXPR_MULADD = 2,
+    SU3_EXPR_ADD = 3,
+    SU3_EXPR_APB_AB = 4
+} su3_expr;
+
+typedef struct su3_field su3_field;
+typedef struct su3_batch su3_batch;
+
+/* How a compute call is launched.  Any valid setting gives bit-identical
+ * results; only speed differs.
+ *   block       lanes per workgroup: 64, 128, 256, 512 or 1024
+ *   persistent  0: one lane per site group (one-shot grid);
+ *               k > 0: k workgroups per compute unit, grid-stride loop
+ *   nontemporal bit 0: nontemporal loads, bit 1: nontemporal stores
+ *   xcd_remap   1: hand each of the 8 XCDs a contiguous range of
+ *               workgroups instead of the hardware's round-robin
+ *   lds_stage   AOS only: 1 stages each workgroup's sites through LDS with
+ *               coalesced 16-byte copies
+ *   tile_sites  batched launch only: sites per tile (multiple of 64)    */
+typedef struct su3_launch {
+    int32_t block;
+    int32_t persistent;
+    int32_t nontemporal;
+    int32_t xcd_remap;
+    int32_t lds_stage;
+    int32_t tile_sites;
+} su3_launch;
+
+/* ------------------------------------------------------------- fields */
+
+/* Bytes a field of lattice `dims` (4 extents, each > 0) occupies in the
+ * given precision and layout.  `lanes` is read for SU3_LAYOUT_AOSOA only
+ * (power of two in [8, 64]).  Fails with SU3_ERR_INVALID_ARG when the
+ * stored field would hold 2^31 reals or more.  Pure host computation. */
+su3_status su3_field_bytes(const int32_t dims[4], su3_precision prec,
+                           su3_layout layout, int32_t lanes, size_t *bytes);
+
+/* Allocate a zeroed field on the current device.  The handle owns its
+ * memory; su3_field_free releases it.  SU3_ERR_OUT_OF_MEMORY when the
+ * device allocation fails. */
+su3_status su3_field_alloc(su3_field **out, const int32_t dims[4],
+                           su3_precision prec, su3_layout layout,
+                           int32_t lanes);
+
+/* Describe caller-owned device memory (e.g. a torch tensor's storage) as a
+ * field.  Non-owning: the caller keeps the memory alive until
+ * su3_field_free(handle).  `dev_ptr` must be 16-byte aligned device memory
+ * of the current device with at least su3_field_bytes() bytes
+ * (SU3_ERR_INVALID_ARG otherwise).  Contents are used as they are. */
+su3_status su3_field_wrap(su3_field **out, void *dev_ptr, size_t bytes,
+                          const int32_t dims[4], su3_precision prec,
+                          su3_layout layout, int32_t lanes);
+
+/* Release a handle (and its memory if owning).  NULL is accepted. */
+su3_status su3_field_free(su3_field *f);
+
+/* Device address and size of a field's storage. */
+su3_status su3_field_data(const su3_field *f, void **dev_ptr, size_t *bytes);
+
+/* Quantise and pack V*18 canonical doubles into the field (padding sites
+ * written as zero).  Completes before returning. */
+su3_status su3_field_upload(su3_field *f, const double *host_aos,
+                            void *stream);
+
+/* Unpack the field into V*18 canonical doubles (exact widening).  For
+ * SU3_C12_F32, rows 0-1 are the stored values and row 2 is rebuilt in
+ * double as conj(row0 x row1).  Completes before returning. */
+su3_status su3_field_download(const su3_field *f, double *host_aos,
+                              void *stream);
+
+/* Copy the stored image byte for byte into host memory (`bytes` must be at
+ * least the field's size).  Completes before returning. */
+su3_status su3_field_download_raw(const su3_field *f, void *host,
+                                  size_t bytes, void *stream);
+
+/* ------------------------------------------------------------ compute */
+
+/* z = x * y at every site (Section 4, Listing 3).  Same as
+ * su3_fused_eval(z, SU3_EXPR_MUL, {x, y}, 2, stream). */
+su3_status su3_mult(su3_field *z, const su3_field *x, const su3_field *y,
+                    void *stream);
+
+/* z = expr(ops[0..n_ops-1]) at every site, in one kernel.  All fields
+ * share dims, precision, layout and lanes (SU3_ERR_MISMATCH otherwise);
+ * n_ops must match the expression (SU3_ERR_INVALID_ARG).  z may be one of
+ * the operands exactly (in-place); a partial overlap with any operand is
+ * SU3_ERR_ALIAS. */
+su3_status su3_fused_eval(su3_field *z, su3_expr expr,
+                          const su3_field *const *ops, int32_t n_ops,
+                          void *stream);
+
+/* ------------------------------------------------------------ batches */
+
+/* A batch evaluates n independent (expr, z, operands) items -- fields of
+ * different lattices, precisions and layouts -- in one persistent launch
+ * over a table of tiles, captured once in a HIP graph and replayed by
+ * su3_batch_launch.  ops holds 4 pointers per item (unused = NULL).  Each
+ * item obeys the rules of su3_fused_eval.  The tile table (see
+ * su3_batch_tiles) is built on the host from the items' volumes and the
+ * tuned tile size; the batch owns its device copy and its graph.  Fields
+ * must outlive the batch.  Creation runs on `stream` and completes before
+ * returning. */
+su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
+                            su3_field *const *z, const su3_field *const *ops,
+                            int32_t n, void *stream);
+
+/* Replay the batch's graph on `stream` (asynchronous). */
+su3_status su3_batch_launch(su3_batch *b, void *stream);
+
+su3_status su3_batch_destroy(su3_batch *b);
+
+/* Copy the batch's tile table from the device: 4 int32 per tile, (item,
+ * first site, site count, precision); item i's tiles are consecutive, in
+ * site order, each covering tile_sites sites except the item's last.
+ * `*n_tiles` receives the tile count; rows are written when cap >= it. */
+su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows, int64_t cap,
+                           int64_t *n_tiles);
+
+/* ------------------------------------------------------ launch tuning */
+
+/* Run the autotuner for one (expr, precision, layout, lanes) at lattice
+ * dims: time each candidate launch (median of 10 after 3 warm-ups) on
+ * scratch fields and keep the fastest for every later call whose volume
+ * falls in the same power-of-two bucket.  The result persists in the JSON
+ * file named by the SU3_TUNE_CACHE environment variable, if set.  Fields
+ * are allocated and freed internally.  `best` may be NULL. */
+su3_status su3_autotune(su3_expr expr, su3_precision prec, su3_layout layout,
+                        int32_t lanes, const int32_t dims[4], void *stream,
+                        su3_launch *best);
+
+/* Launch settings used for a key (tuned, set, or the built-in default). */
+su3_status su3_launch_get(su3_expr expr, su3_precision prec,
+                          su3_layout layout, int32_t lanes,
+                          const int32_t dims[4], su3_launch *out);
+
+/* Force the launch settings for a key (validated; SU3_ERR_INVALID_ARG for
+ * an unsupported setting). */
+su3_status su3_launch_set(su3_expr expr, su3_precision prec,
+                          su3_layout layout, int32_t lanes,
+                          const int32_t dims[4], const su3_launch *cfg);
+
+/* Forget every tuned or set launch (the JSON cache file is left alone). */
+su3_status su3_launch_reset(void);
+
+/* ------------------------------------------- bandwidth yardsticks */
+
+/* STREAM-style triad a[i] = b[i] + s*c[i] over n doubles (the practical
+ * HBM ceiling that Section 5 compares against).  Device pointers, 16-byte
+ * aligned, asynchronous on `stream`. */
+su3_status su3_triad(double *a, const double *b, const double *c, double s,
+                     int64_t n, void *stream);
+
+/* Plain copy dst[i] = src[i] over `bytes` bytes (multiple of 16, 16-byte
+ * aligned device pointers), asynchronous on `stream`. */
+su3_status su3_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* --------------------------------------------------------- utilities */
+
+/* Wait for `stream` and report any pending HIP error. */
+su3_status su3_sync(void *stream);
+
+/* Static text of a status code. */
+const char *su3_status_string(su3_status s);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char *su3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SU3_H */

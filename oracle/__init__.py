@@ -65,6 +65,8 @@ def _bind(lib):
     lib.oracle_unpack.restype = i32
     lib.oracle_metrics.argtypes = [vp, vp, i64, vp]
     lib.oracle_metrics.restype = None
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = i32
     return lib
 
 
@@ -86,6 +88,10 @@ class Oracle:
         a = np.ascontiguousarray(a, dtype=np.float64)
         assert a.ndim == 4 and a.shape[1:] == (3, 3, 2), a.shape
         return a
+
+    def threads(self):
+        """OpenMP threads of the oracle's site loops."""
+        return int(self.lib.oracle_threads())
 
     def mult(self, x, y):
         """z(s) = x(s) y(s): the product written out, k ascending."""

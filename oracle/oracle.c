@@ -32,10 +32,23 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_C12 = 3 };
 enum { L_AOS = 0, L_SOA = 1, L_AOSOA = 2 };
 enum { X_MUL = 0, X_MUL3 = 1, X_MULADD = 2, X_ADD = 3, X_APB_AB = 4 };
+
+/* Threads the site loops use (1 without OpenMP). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------ one site */
 

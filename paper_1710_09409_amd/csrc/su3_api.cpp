@@ -1,0 +1,1090 @@
+// C ABI of the SU(3) streaming library: validation, field handles, host
+// pack/unpack, launch planning and tuning, batches.  Declarations and the
+// contract of every entry point are in include/su3.h.
+#include "su3.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "su3_internal.h"
+
+using namespace su3i;
+
+struct su3_field {
+    void *ptr;
+    size_t bytes;
+    int32_t dims[4];
+    int64_t V;
+    int64_t Vpad;
+    int64_t L;  // sites per lane-block (V_pad for SoA)
+    int32_t prec;
+    int32_t layout;
+    int32_t lanes;
+    int32_t E;
+    int32_t rbytes;
+    int32_t owns;
+    int32_t device;
+};
+
+struct su3_batch {
+    BatchItem *d_items;
+    BatchTile *d_tiles;
+    int32_t nitems;
+    int32_t ntiles;
+    int32_t mode;
+    su3_launch cfg;
+    int32_t grid;
+    int32_t device;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+// ------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+static su3_status fail(su3_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+static su3_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(SU3_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(call, what)                 \
+    do {                                    \
+        hipError_t e_ = (call);             \
+        if (e_ != hipSuccess)               \
+            return hip_fail(e_, what);      \
+    } while (0)
+
+// ------------------------------------------------------------- geometry
+
+struct Shape {
+    int64_t V, Vpad, L;
+    int32_t E, rbytes;
+    size_t bytes;
+};
+
+static su3_status make_shape(const int32_t dims[4], int prec, int layout,
+                             int32_t lanes, Shape *out)
+{
+    if (!dims)
+        return fail(SU3_ERR_INVALID_ARG, "dims is NULL");
+    if (prec < SU3_F64 || prec > SU3_C12_F32)
+        return fail(SU3_ERR_INVALID_ARG, "unknown precision %d", prec);
+    if (layout < SU3_LAYOUT_AOS || layout > SU3_LAYOUT_AOSOA)
+        return fail(SU3_ERR_INVALID_ARG, "unknown layout %d", layout);
+    int64_t V = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (dims[d] <= 0)
+            return fail(SU3_ERR_INVALID_ARG, "dims[%d] = %d must be > 0", d,
+                        dims[d]);
+        V *= dims[d];
+        if (V > ((int64_t)1 << 31))
+            return fail(SU3_ERR_INVALID_ARG, "lattice too large");
+    }
+    Shape s;
+    s.V = V;
+    s.E = entries_of(prec);
+    s.rbytes = real_bytes(prec);
+    if (layout == SU3_LAYOUT_AOS) {
+        s.L = 1;
+        s.Vpad = V;
+    } else if (layout == SU3_LAYOUT_SOA) {
+        s.Vpad = (V + 63) / 64 * 64;
+        s.L = s.Vpad;
+    } else {
+        if (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64)
+            return fail(SU3_ERR_INVALID_ARG,
+                        "AoSoA lanes must be 8, 16, 32 or 64 (got %d)", lanes);
+        s.L = lanes;
+        s.Vpad = (V + lanes - 1) / lanes * lanes;
+    }
+    const int64_t reals = s.Vpad * s.E * 2;
+    if (reals >= ((int64_t)1 << 31))
+        return fail(SU3_ERR_INVALID_ARG,
+                    "field holds %lld reals; the limit is 2^31 - 1",
+                    (long long)reals);
+    s.bytes = (size_t)reals * s.rbytes;
+    *out = s;
+    return SU3_OK;
+}
+
+static Geom geom_of(const su3_field *f)
+{
+    Geom g;
+    if (f->layout == SU3_LAYOUT_AOS) {
+        g.lg = 0;
+        g.mask = 0;
+        g.plane = 2;
+        g.bstride = 2 * f->E;
+    } else if (f->layout == SU3_LAYOUT_SOA) {
+        g.lg = 31;
+        g.mask = 0x7fffffffu;
+        g.plane = (uint32_t)(2 * f->Vpad);
+        g.bstride = 0;
+    } else {
+        uint32_t lg = 0;
+        while ((1 << lg) < f->L)
+            ++lg;
+        g.lg = lg;
+        g.mask = (uint32_t)(f->L - 1);
+        g.plane = (uint32_t)(2 * f->L);
+        g.bstride = (uint32_t)(2 * f->E * f->L);
+    }
+    return g;
+}
+
+// Stored-real index of (site s, entry e, c) -- the host twin of the
+// kernels' addressing.
+static inline int64_t stored_index(const su3_field *f, int64_t s, int e, int c)
+{
+    return ((s / f->L) * f->E + e) * 2 * f->L + (s % f->L) * 2 + c;
+}
+
+// ------------------------------------------------------------ fields
+
+extern "C" su3_status su3_field_bytes(const int32_t dims[4],
+                                      su3_precision prec, su3_layout layout,
+                                      int32_t lanes, size_t *bytes)
+{
+    if (!bytes)
+        return fail(SU3_ERR_INVALID_ARG, "bytes is NULL");
+    Shape s;
+    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    if (st != SU3_OK)
+        return st;
+    *bytes = s.bytes;
+    return SU3_OK;
+}
+
+static su3_field *new_handle(const int32_t dims[4], int prec, int layout,
+                             int32_t lanes, const Shape &s)
+{
+    su3_field *f = new su3_field();
+    f->ptr = nullptr;
+    f->bytes = s.bytes;
+    std::memcpy(f->dims, dims, sizeof f->dims);
+    f->V = s.V;
+    f->Vpad = s.Vpad;
+    f->L = s.L;
+    f->prec = prec;
+    f->layout = layout;
+    f->lanes = layout == SU3_LAYOUT_AOSOA ? lanes : 0;
+    f->E = s.E;
+    f->rbytes = s.rbytes;
+    f->owns = 0;
+    f->device = -1;
+    return f;
+}
+
+extern "C" su3_status su3_field_alloc(su3_field **out, const int32_t dims[4],
+                                      su3_precision prec, su3_layout layout,
+                                      int32_t lanes)
+{
+    if (!out)
+        return fail(SU3_ERR_INVALID_ARG, "out is NULL");
+    Shape s;
+    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    if (st != SU3_OK)
+        return st;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, s.bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SU3_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", s.bytes,
+                    hipGetErrorString(e));
+    }
+    e = hipMemset(p, 0, s.bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "hipMemset");
+    }
+    su3_field *f = new_handle(dims, prec, layout, lanes, s);
+    f->ptr = p;
+    f->owns = 1;
+    f->device = dev;
+    *out = f;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_field_wrap(su3_field **out, void *dev_ptr,
+                                     size_t bytes, const int32_t dims[4],
+                                     su3_precision prec, su3_layout layout,
+                                     int32_t lanes)
+{
+    if (!out)
+        return fail(SU3_ERR_INVALID_ARG, "out is NULL");
+    if (!dev_ptr)
+        return fail(SU3_ERR_INVALID_ARG, "dev_ptr is NULL");
+    if (((uintptr_t)dev_ptr & 15) != 0)
+        return fail(SU3_ERR_INVALID_ARG, "dev_ptr is not 16-byte aligned");
+    Shape s;
+    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    if (st != SU3_OK)
+        return st;
+    if (bytes < s.bytes)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "buffer of %zu bytes is smaller than the field (%zu)",
+                    bytes, s.bytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, dev_ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SU3_ERR_INVALID_ARG,
+                    "dev_ptr is not device memory known to HIP (%s)",
+                    hipGetErrorString(e));
+    }
+    if (attr.type != hipMemoryTypeDevice || attr.device != dev)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "dev_ptr is not device memory of the current device %d",
+                    dev);
+    su3_field *f = new_handle(dims, prec, layout, lanes, s);
+    f->ptr = dev_ptr;
+    f->owns = 0;
+    f->device = dev;
+    *out = f;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_field_free(su3_field *f)
+{
+    if (!f)
+        return SU3_OK;
+    hipError_t e = hipSuccess;
+    if (f->owns && f->ptr)
+        e = hipFree(f->ptr);
+    delete f;
+    if (e != hipSuccess)
+        return hip_fail(e, "hipFree");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_field_data(const su3_field *f, void **dev_ptr,
+                                     size_t *bytes)
+{
+    if (!f)
+        return fail(SU3_ERR_INVALID_ARG, "field is NULL");
+    if (dev_ptr)
+        *dev_ptr = f->ptr;
+    if (bytes)
+        *bytes = f->bytes;
+    return SU3_OK;
+}
+
+// double -> float -> half, each step rounding to nearest even.  The empty
+// asm keeps the intermediate float: without it the optimiser folds the two
+// conversions into one double -> half rounding, which differs whenever the
+// float lands exactly halfway between two halves.
+static inline _Float16 half_of(double v)
+{
+    float f = (float)v;
+    __asm__ volatile("" : "+x"(f));
+    return (_Float16)f;
+}
+
+// Host quantisers: round to nearest even (float: one rounding; half:
+// double -> float -> half).
+static inline void put_real(void *img, int prec, int64_t idx, double v)
+{
+    if (prec == SU3_F64)
+        static_cast<double *>(img)[idx] = v;
+    else if (prec == SU3_F16_F32ACC)
+        static_cast<_Float16 *>(img)[idx] = half_of(v);
+    else
+        static_cast<float *>(img)[idx] = (float)v;
+}
+
+static inline double get_real(const void *img, int prec, int64_t idx)
+{
+    if (prec == SU3_F64)
+        return static_cast<const double *>(img)[idx];
+    if (prec == SU3_F16_F32ACC)
+        return (double)(float)static_cast<const _Float16 *>(img)[idx];
+    return (double)static_cast<const float *>(img)[idx];
+}
+
+extern "C" su3_status su3_field_upload(su3_field *f, const double *host,
+                                       void *stream)
+{
+    if (!f || !host)
+        return fail(SU3_ERR_INVALID_ARG, "field or host buffer is NULL");
+    std::vector<unsigned char> img(f->bytes, 0);
+    for (int64_t s = 0; s < f->V; ++s)
+        for (int e = 0; e < f->E; ++e)
+            for (int c = 0; c < 2; ++c)
+                put_real(img.data(), f->prec, stored_index(f, s, e, c),
+                         host[18 * s + 2 * e + c]);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(f->ptr, img.data(), f->bytes,
+                           hipMemcpyHostToDevice, st),
+            "upload copy");
+    HIP_TRY(hipStreamSynchronize(st), "upload sync");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_field_download_raw(const su3_field *f, void *host,
+                                             size_t bytes, void *stream)
+{
+    if (!f || !host)
+        return fail(SU3_ERR_INVALID_ARG, "field or host buffer is NULL");
+    if (bytes < f->bytes)
+        return fail(SU3_ERR_INVALID_ARG, "host buffer of %zu bytes < %zu",
+                    bytes, f->bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(host, f->ptr, f->bytes, hipMemcpyDeviceToHost, st),
+            "download copy");
+    HIP_TRY(hipStreamSynchronize(st), "download sync");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_field_download(const su3_field *f, double *host,
+                                         void *stream)
+{
+    if (!f || !host)
+        return fail(SU3_ERR_INVALID_ARG, "field or host buffer is NULL");
+    std::vector<unsigned char> img(f->bytes);
+    su3_status st = su3_field_download_raw(f, img.data(), img.size(), stream);
+    if (st != SU3_OK)
+        return st;
+    for (int64_t s = 0; s < f->V; ++s) {
+        double *m = host + 18 * s;
+        for (int e = 0; e < f->E; ++e)
+            for (int c = 0; c < 2; ++c)
+                m[2 * e + c] = get_real(img.data(), f->prec,
+                                        stored_index(f, s, e, c));
+        if (f->prec == SU3_C12_F32) {
+            // row 2 = conj(row0 x row1), in double
+            for (int k = 0; k < 3; ++k) {
+                const int p = (k + 1) % 3, q = (k + 2) % 3;
+                const double ar = m[2 * p], ai = m[2 * p + 1];
+                const double br = m[2 * (3 + q)], bi = m[2 * (3 + q) + 1];
+                const double cr = m[2 * q], ci = m[2 * q + 1];
+                const double dr = m[2 * (3 + p)], di = m[2 * (3 + p) + 1];
+                m[2 * (6 + k)] = (ar * br - ai * bi) - (cr * dr - ci * di);
+                m[2 * (6 + k) + 1] = -((ar * bi + ai * br) - (cr * di + ci * dr));
+            }
+        }
+    }
+    return SU3_OK;
+}
+
+// -------------------------------------------------------- device facts
+
+static int device_cus(int dev)
+{
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end())
+        return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess ||
+        n <= 0)
+        n = 256;
+    cache[dev] = n;
+    return n;
+}
+
+// ------------------------------------------------------- launch table
+
+using Key = std::tuple<int, int, int, int, int>;  // expr prec layout lanes vbucket
+
+static int vbucket(int64_t V)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < V)
+        ++b;
+    return b;
+}
+
+static std::mutex g_tune_mu;
+static std::map<Key, su3_launch> g_tuned;
+static bool g_cache_loaded = false;
+
+static su3_launch default_launch(int expr, int prec, int layout)
+{
+    (void)expr;
+    (void)prec;
+    su3_launch c;
+    c.block = layout == SU3_LAYOUT_AOS ? 64 : 256;
+    c.persistent = 0;
+    c.nontemporal = 3;
+    c.xcd_remap = 0;
+    c.lds_stage = 0;
+    c.tile_sites = 4096;
+    return c;
+}
+
+static su3_status check_launch(const su3_launch &c, int layout)
+{
+    if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512 &&
+        c.block != 1024)
+        return fail(SU3_ERR_INVALID_ARG, "block %d not in {64..1024}", c.block);
+    if (c.persistent < 0 || c.persistent > 64)
+        return fail(SU3_ERR_INVALID_ARG, "persistent %d not in [0, 64]",
+                    c.persistent);
+    if (c.nontemporal < 0 || c.nontemporal > 3)
+        return fail(SU3_ERR_INVALID_ARG, "nontemporal %d not in [0, 3]",
+                    c.nontemporal);
+    if (c.xcd_remap < 0 || c.xcd_remap > 1)
+        return fail(SU3_ERR_INVALID_ARG, "xcd_remap must be 0 or 1");
+    if (c.lds_stage < 0 || c.lds_stage > 1 ||
+        (c.lds_stage && layout != SU3_LAYOUT_AOS))
+        return fail(SU3_ERR_INVALID_ARG, "lds_stage is for the AoS layout only");
+    if (c.lds_stage && c.block > 128)
+        return fail(SU3_ERR_INVALID_ARG, "lds_stage needs block <= 128");
+    if (c.tile_sites < 64 || c.tile_sites % 64 != 0 || c.tile_sites > (1 << 24))
+        return fail(SU3_ERR_INVALID_ARG,
+                    "tile_sites must be a positive multiple of 64");
+    return SU3_OK;
+}
+
+static void load_cache_locked();
+
+static su3_launch lookup_launch(int expr, int prec, int layout, int lanes,
+                                int64_t V)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    auto it = g_tuned.find(Key(expr, prec, layout, lanes, vbucket(V)));
+    if (it != g_tuned.end())
+        return it->second;
+    return default_launch(expr, prec, layout);
+}
+
+// JSON cache: one object per line with integer fields.
+static std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return "unknown";
+    char buf[300];
+    snprintf(buf, sizeof buf, "%s:%d", p.gcnArchName, p.multiProcessorCount);
+    return buf;
+}
+
+static bool parse_int(const std::string &line, const char *key, int *v)
+{
+    std::string pat = std::string("\"") + key + "\":";
+    size_t pos = line.find(pat);
+    if (pos == std::string::npos)
+        return false;
+    *v = atoi(line.c_str() + pos + pat.size());
+    return true;
+}
+
+static void load_cache_locked()
+{
+    if (g_cache_loaded)
+        return;
+    g_cache_loaded = true;
+    const char *path = getenv("SU3_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *fp = fopen(path, "r");
+    if (!fp)
+        return;
+    const std::string tag = device_tag();
+    char buf[1024];
+    while (fgets(buf, sizeof buf, fp)) {
+        std::string line(buf);
+        if (line.find("\"device\":\"" + tag + "\"") == std::string::npos)
+            continue;
+        int ex, pr, la, ln, vb;
+        su3_launch c;
+        if (!parse_int(line, "expr", &ex) || !parse_int(line, "prec", &pr) ||
+            !parse_int(line, "layout", &la) || !parse_int(line, "lanes", &ln) ||
+            !parse_int(line, "vbucket", &vb) ||
+            !parse_int(line, "block", &c.block) ||
+            !parse_int(line, "persistent", &c.persistent) ||
+            !parse_int(line, "nontemporal", &c.nontemporal) ||
+            !parse_int(line, "xcd_remap", &c.xcd_remap) ||
+            !parse_int(line, "lds_stage", &c.lds_stage) ||
+            !parse_int(line, "tile_sites", &c.tile_sites))
+            continue;
+        if (check_launch(c, la) != SU3_OK)
+            continue;
+        g_tuned[Key(ex, pr, la, ln, vb)] = c;
+    }
+    fclose(fp);
+}
+
+static void append_cache(const Key &k, const su3_launch &c, double us)
+{
+    const char *path = getenv("SU3_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *fp = fopen(path, "a");
+    if (!fp)
+        return;
+    fprintf(fp,
+            "{\"device\":\"%s\",\"expr\":%d,\"prec\":%d,\"layout\":%d,"
+            "\"lanes\":%d,\"vbucket\":%d,\"block\":%d,\"persistent\":%d,"
+            "\"nontemporal\":%d,\"xcd_remap\":%d,\"lds_stage\":%d,"
+            "\"tile_sites\":%d,\"us\":%.3f}\n",
+            device_tag().c_str(), std::get<0>(k), std::get<1>(k),
+            std::get<2>(k), std::get<3>(k), std::get<4>(k), c.block,
+            c.persistent, c.nontemporal, c.xcd_remap, c.lds_stage,
+            c.tile_sites, us);
+    fclose(fp);
+}
+
+// --------------------------------------------------------- validation
+
+static bool same_shape(const su3_field *a, const su3_field *b)
+{
+    return a->prec == b->prec && a->layout == b->layout &&
+           a->lanes == b->lanes && a->dims[0] == b->dims[0] &&
+           a->dims[1] == b->dims[1] && a->dims[2] == b->dims[2] &&
+           a->dims[3] == b->dims[3] && a->device == b->device;
+}
+
+static bool overlaps(const su3_field *a, const su3_field *b)
+{
+    const uintptr_t a0 = (uintptr_t)a->ptr, a1 = a0 + a->bytes;
+    const uintptr_t b0 = (uintptr_t)b->ptr, b1 = b0 + b->bytes;
+    return a0 < b1 && b0 < a1;
+}
+
+static su3_status validate_item(const su3_field *z, int expr,
+                                const su3_field *const *ops, int32_t n_ops)
+{
+    if (!z)
+        return fail(SU3_ERR_INVALID_ARG, "output field is NULL");
+    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_APB_AB)
+        return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
+    if (!ops)
+        return fail(SU3_ERR_INVALID_ARG, "operand list is NULL");
+    if (n_ops != operands_of(expr))
+        return fail(SU3_ERR_INVALID_ARG, "expression %d takes %d operands, got %d",
+                    expr, operands_of(expr), n_ops);
+    for (int k = 0; k < n_ops; ++k) {
+        if (!ops[k])
+            return fail(SU3_ERR_INVALID_ARG, "operand %d is NULL", k);
+        if (!same_shape(z, ops[k]))
+            return fail(SU3_ERR_MISMATCH,
+                        "operand %d differs from the output in dims, "
+                        "precision, layout, lanes or device", k);
+    }
+    if (z->prec == SU3_C12_F32 && expr != SU3_EXPR_MUL &&
+        expr != SU3_EXPR_MUL3)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "the two-row compressed form supports MUL and MUL3 only "
+                    "(sums leave SU(3))");
+    for (int k = 0; k < n_ops; ++k)
+        if (overlaps(z, ops[k]) &&
+            !(z->ptr == ops[k]->ptr && z->bytes == ops[k]->bytes))
+            return fail(SU3_ERR_ALIAS,
+                        "output partially overlaps operand %d", k);
+    return SU3_OK;
+}
+
+// ------------------------------------------------------------ compute
+
+// LDS one staged workgroup may take (operand tiles, reused for the result).
+static const size_t kLdsStageMaxBytes = 65536;
+
+static su3_status launch_item(su3_field *z, int expr,
+                              const su3_field *const *ops, int32_t n_ops,
+                              const su3_launch &c, hipStream_t st)
+{
+    SiteArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.z = z->ptr;
+    for (int k = 0; k < n_ops; ++k)
+        a.op[k] = ops[k]->ptr;
+    a.g = geom_of(z);
+    a.nsites = (int32_t)z->V;
+    a.xcd_remap = c.xcd_remap;
+    hipError_t e;
+    if (z->layout == SU3_LAYOUT_AOS && c.lds_stage) {
+        const size_t shm = (size_t)n_ops * c.block * z->E * 2 * z->rbytes;
+        if (shm > kLdsStageMaxBytes)
+            return fail(SU3_ERR_UNSUPPORTED,
+                        "LDS staging of %d operands x %d sites needs %zu bytes "
+                        "of LDS (limit %zu)", n_ops, c.block, shm,
+                        kLdsStageMaxBytes);
+        const int64_t tiles = (z->V + c.block - 1) / c.block;
+        int64_t grid = tiles;
+        if (c.persistent)
+            grid = std::min<int64_t>(grid, (int64_t)c.persistent *
+                                               device_cus(z->device));
+        a.ngroups = (int32_t)z->V;
+        e = launch_site_lds(z->prec, expr, c.nontemporal, c.block, (int)grid,
+                            a, st);
+    } else {
+        const int S = z->layout == SU3_LAYOUT_AOS ? 1
+                                                  : natural_sites(z->prec, expr);
+        a.ngroups = (int32_t)((z->V + S - 1) / S);
+        int64_t grid = (a.ngroups + c.block - 1) / c.block;
+        if (c.persistent)
+            grid = std::min<int64_t>(grid, (int64_t)c.persistent *
+                                               device_cus(z->device));
+        e = launch_site(z->prec, expr, S, c.nontemporal, c.block, (int)grid, a,
+                        st);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "kernel launch");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_fused_eval(su3_field *z, su3_expr expr,
+                                     const su3_field *const *ops,
+                                     int32_t n_ops, void *stream)
+{
+    su3_status st = validate_item(z, expr, ops, n_ops);
+    if (st != SU3_OK)
+        return st;
+    const su3_launch c =
+        lookup_launch(expr, z->prec, z->layout, z->lanes, z->V);
+    return launch_item(z, expr, ops, n_ops, c,
+                       static_cast<hipStream_t>(stream));
+}
+
+extern "C" su3_status su3_mult(su3_field *z, const su3_field *x,
+                               const su3_field *y, void *stream)
+{
+    const su3_field *ops[2] = {x, y};
+    return su3_fused_eval(z, SU3_EXPR_MUL, ops, 2, stream);
+}
+
+// ------------------------------------------------------- launch tuning
+
+static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
+                         int32_t lanes, const int32_t dims[4], Key *k,
+                         Shape *shape)
+{
+    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_APB_AB)
+        return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
+    Shape s;
+    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    if (st != SU3_OK)
+        return st;
+    if (prec == SU3_C12_F32 && expr != SU3_EXPR_MUL && expr != SU3_EXPR_MUL3)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "the two-row compressed form supports MUL and MUL3 only");
+    *k = Key(expr, prec, layout, layout == SU3_LAYOUT_AOSOA ? lanes : 0,
+             vbucket(s.V));
+    if (shape)
+        *shape = s;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_launch_get(su3_expr expr, su3_precision prec,
+                                     su3_layout layout, int32_t lanes,
+                                     const int32_t dims[4], su3_launch *out)
+{
+    if (!out)
+        return fail(SU3_ERR_INVALID_ARG, "out is NULL");
+    Key k;
+    Shape s;
+    su3_status st = key_of(expr, prec, layout, lanes, dims, &k, &s);
+    if (st != SU3_OK)
+        return st;
+    *out = lookup_launch(expr, prec, layout, std::get<3>(k), s.V);
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_launch_set(su3_expr expr, su3_precision prec,
+                                     su3_layout layout, int32_t lanes,
+                                     const int32_t dims[4],
+                                     const su3_launch *cfg)
+{
+    if (!cfg)
+        return fail(SU3_ERR_INVALID_ARG, "cfg is NULL");
+    Key k;
+    su3_status st = key_of(expr, prec, layout, lanes, dims, &k, nullptr);
+    if (st != SU3_OK)
+        return st;
+    st = check_launch(*cfg, layout);
+    if (st != SU3_OK)
+        return st;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    g_tuned[k] = *cfg;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_launch_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    g_cache_loaded = true;  // do not reload the file
+    return SU3_OK;
+}
+
+// Candidate launches of the autotuner's sweep.
+static std::vector<su3_launch> candidates(int layout)
+{
+    std::vector<su3_launch> out;
+    const int blocks[] = {64, 128, 256, 512, 1024};
+    const int pers[] = {0, 4, 8};
+    const int nts[] = {0, 2, 3};
+    for (int b : blocks)
+        for (int p : pers)
+            for (int nt : nts)
+                for (int x = 0; x < 2; ++x)
+                    for (int lds = 0; lds < (layout == SU3_LAYOUT_AOS ? 2 : 1);
+                         ++lds) {
+                        if (lds && b > 128)
+                            continue;
+                        if (p && x)
+                            continue;  // remap only matters for one-shot grids
+                        su3_launch c;
+                        c.block = b;
+                        c.persistent = p;
+                        c.nontemporal = nt;
+                        c.xcd_remap = x;
+                        c.lds_stage = lds;
+                        c.tile_sites = 4096;
+                        out.push_back(c);
+                    }
+    return out;
+}
+
+// Median time (microseconds) of `reps` launches after `warm` warm-ups, each
+// launch bracketed by its own events.
+template <class F>
+static su3_status time_launch(F launch, hipStream_t st, int warm, int reps,
+                              double *us)
+{
+    for (int i = 0; i < warm; ++i) {
+        su3_status s = launch();
+        if (s != SU3_OK)
+            return s;
+    }
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto &e : ev)
+        HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    su3_status result = SU3_OK;
+    for (int i = 0; i < reps && result == SU3_OK; ++i) {
+        (void)hipEventRecord(ev[2 * i], st);
+        result = launch();
+        (void)hipEventRecord(ev[2 * i + 1], st);
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    std::vector<double> t;
+    for (int i = 0; i < reps && result == SU3_OK && e == hipSuccess; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess)
+            t.push_back(ms * 1000.0);
+    }
+    for (auto &x : ev)
+        (void)hipEventDestroy(x);
+    if (result != SU3_OK)
+        return result;
+    if (e != hipSuccess)
+        return hip_fail(e, "autotune sync");
+    if (t.empty())
+        return fail(SU3_ERR_HIP, "no timing recorded");
+    std::sort(t.begin(), t.end());
+    *us = t[t.size() / 2];
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
+                                   su3_layout layout, int32_t lanes,
+                                   const int32_t dims[4], void *stream,
+                                   su3_launch *best)
+{
+    Key k;
+    Shape s;
+    su3_status st = key_of(expr, prec, layout, lanes, dims, &k, &s);
+    if (st != SU3_OK)
+        return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int nops = operands_of(expr);
+    su3_field *f[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int i = 0; i <= nops && st == SU3_OK; ++i) {
+        st = su3_field_alloc(&f[i], dims, prec, layout, lanes);
+        if (st == SU3_OK) {
+            // a non-zero bit pattern (finite in every precision)
+            hipError_t e = hipMemsetD32Async((hipDeviceptr_t)f[i]->ptr,
+                                             0x3c003c00u, f[i]->bytes / 4, hs);
+            if (e != hipSuccess)
+                st = hip_fail(e, "fill");
+        }
+    }
+    su3_launch win = default_launch(expr, prec, layout);
+    double win_us = 1e300;
+    if (st == SU3_OK) {
+        const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
+        for (const su3_launch &c : candidates(layout)) {
+            double us = 0;
+            su3_status r = time_launch(
+                [&]() { return launch_item(f[0], expr, ops, nops, c, hs); }, hs,
+                3, 10, &us);
+            if (r != SU3_OK) {
+                (void)hipGetLastError();
+                continue;  // a launch shape the device refused
+            }
+            if (us < win_us) {
+                win_us = us;
+                win = c;
+            }
+        }
+        if (win_us >= 1e300)
+            st = fail(SU3_ERR_HIP, "no candidate launch ran");
+    }
+    for (int i = 0; i < 5; ++i)
+        su3_field_free(f[i]);
+    if (st != SU3_OK)
+        return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache_locked();
+        g_tuned[k] = win;
+    }
+    append_cache(k, win, win_us);
+    if (best)
+        *best = win;
+    return SU3_OK;
+}
+
+// ------------------------------------------------------------ batches
+
+extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
+                                       su3_field *const *z,
+                                       const su3_field *const *ops, int32_t n,
+                                       void *stream)
+{
+    if (!out || !exprs || !z || !ops)
+        return fail(SU3_ERR_INVALID_ARG, "NULL argument");
+    if (n <= 0)
+        return fail(SU3_ERR_INVALID_ARG, "batch needs at least one item");
+    std::vector<BatchItem> items(n);
+    int mode = 0;
+    int64_t total_sites = 0;
+    int dev = -1;
+    for (int i = 0; i < n; ++i) {
+        const int nops = (exprs[i] >= SU3_EXPR_MUL && exprs[i] <= SU3_EXPR_APB_AB)
+                             ? operands_of(exprs[i])
+                             : 0;
+        su3_status st = validate_item(z[i], exprs[i], ops + 4 * i, nops);
+        if (st != SU3_OK)
+            return fail(st, "batch item %d: %s", i, g_last_error.c_str());
+        for (int k = nops; k < 4; ++k)
+            if (ops[4 * i + k])
+                return fail(SU3_ERR_INVALID_ARG,
+                            "batch item %d: unused operand slot %d not NULL",
+                            i, k);
+        if (dev < 0)
+            dev = z[i]->device;
+        else if (z[i]->device != dev)
+            return fail(SU3_ERR_MISMATCH, "batch items on different devices");
+        if (z[i]->layout == SU3_LAYOUT_AOS)
+            return fail(SU3_ERR_UNSUPPORTED,
+                        "batch item %d: batches take SoA or AoSoA fields", i);
+        BatchItem &it = items[i];
+        std::memset(&it, 0, sizeof it);
+        it.z = z[i]->ptr;
+        for (int k = 0; k < nops; ++k)
+            it.op[k] = ops[4 * i + k]->ptr;
+        it.g = geom_of(z[i]);
+        it.nsites = (int32_t)z[i]->V;
+        it.prec = z[i]->prec;
+        it.expr = exprs[i];
+        if (!(exprs[i] == SU3_EXPR_MUL &&
+              (z[i]->prec == SU3_F64 || z[i]->prec == SU3_C12_F32)))
+            mode = 1;
+        total_sites += z[i]->V;
+    }
+    // tile size: the tuned value for the dominant item, else the default
+    const su3_launch c =
+        lookup_launch(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
+                      total_sites);
+    su3_launch cfg = c;
+    if (cfg.block > 256)
+        cfg.block = 256;
+    const int T = cfg.tile_sites;
+    std::vector<BatchTile> tiles;
+    for (int i = 0; i < n; ++i) {
+        const int64_t V = z[i]->V;
+        for (int64_t first = 0; first < V; first += T) {
+            BatchTile t;
+            t.item = i;
+            t.first = (int32_t)first;
+            t.count = (int32_t)std::min<int64_t>(T, V - first);
+            t.prec = z[i]->prec;
+            tiles.push_back(t);
+        }
+    }
+    if (tiles.size() >= ((size_t)1 << 31))
+        return fail(SU3_ERR_INVALID_ARG, "too many tiles");
+    su3_batch *b = new su3_batch();
+    std::memset(b, 0, sizeof *b);
+    b->nitems = n;
+    b->ntiles = (int32_t)tiles.size();
+    b->mode = mode;
+    b->cfg = cfg;
+    b->device = dev;
+    const int per_cu = cfg.persistent > 0 ? cfg.persistent : 8;
+    b->grid = (int32_t)std::min<int64_t>(b->ntiles,
+                                         (int64_t)per_cu * device_cus(dev));
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMalloc(&b->d_items, sizeof(BatchItem) * n);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_tiles, sizeof(BatchTile) * tiles.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * n,
+                           hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_tiles, tiles.data(),
+                           sizeof(BatchTile) * tiles.size(),
+                           hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(hs);
+    // Capture the one launch on a private stream and instantiate the graph.
+    hipStream_t cap = nullptr;
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_batch(b->mode, b->d_items, b->d_tiles, b->ntiles,
+                                     cfg.nontemporal, cfg.block, b->grid, cap);
+        hipError_t ce = hipStreamEndCapture(cap, &b->graph);
+        e = le != hipSuccess ? le : ce;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (cap)
+        (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        su3_status r = hip_fail(e, "batch create");
+        su3_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_batch_launch(su3_batch *b, void *stream)
+{
+    if (!b)
+        return fail(SU3_ERR_INVALID_ARG, "batch is NULL");
+    HIP_TRY(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)),
+            "hipGraphLaunch");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_batch_destroy(su3_batch *b)
+{
+    if (!b)
+        return SU3_OK;
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    if (b->d_items)
+        (void)hipFree(b->d_items);
+    if (b->d_tiles)
+        (void)hipFree(b->d_tiles);
+    delete b;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows,
+                                      int64_t cap, int64_t *n_tiles)
+{
+    if (!b || !n_tiles)
+        return fail(SU3_ERR_INVALID_ARG, "NULL argument");
+    *n_tiles = b->ntiles;
+    if (!rows || cap < b->ntiles)
+        return SU3_OK;
+    HIP_TRY(hipMemcpy(rows, b->d_tiles, sizeof(BatchTile) * b->ntiles,
+                      hipMemcpyDeviceToHost),
+            "tile table copy");
+    return SU3_OK;
+}
+
+// ------------------------------------------------------ yardsticks
+
+extern "C" su3_status su3_triad(double *a, const double *b, const double *c,
+                                double s, int64_t n, void *stream)
+{
+    if (!a || !b || !c)
+        return fail(SU3_ERR_INVALID_ARG, "NULL array");
+    if (n <= 0)
+        return fail(SU3_ERR_INVALID_ARG, "n must be > 0");
+    if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15)
+        return fail(SU3_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
+    hipError_t e = launch_triad(a, b, c, s, n, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "triad launch");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_copy(void *dst, const void *src, size_t bytes,
+                               void *stream)
+{
+    if (!dst || !src)
+        return fail(SU3_ERR_INVALID_ARG, "NULL pointer");
+    if (bytes == 0 || bytes % 16)
+        return fail(SU3_ERR_INVALID_ARG, "bytes must be a positive multiple of 16");
+    if (((uintptr_t)dst | (uintptr_t)src) & 15)
+        return fail(SU3_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "copy launch");
+    return SU3_OK;
+}
+
+// ------------------------------------------------------------ misc
+
+extern "C" su3_status su3_sync(void *stream)
+{
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)),
+            "hipStreamSynchronize");
+    HIP_TRY(hipGetLastError(), "pending error");
+    return SU3_OK;
+}
+
+extern "C" const char *su3_status_string(su3_status s)
+{
+    switch (s) {
+    case SU3_OK: return "SU3_OK";
+    case SU3_ERR_INVALID_ARG: return "SU3_ERR_INVALID_ARG";
+    case SU3_ERR_MISMATCH: return "SU3_ERR_MISMATCH";
+    case SU3_ERR_UNSUPPORTED: return "SU3_ERR_UNSUPPORTED";
+    case SU3_ERR_OUT_OF_MEMORY: return "SU3_ERR_OUT_OF_MEMORY";
+    case SU3_ERR_ALIAS: return "SU3_ERR_ALIAS";
+    case SU3_ERR_HIP: return "SU3_ERR_HIP";
+    }
+    return "SU3_ERR_UNKNOWN";
+}
+
+extern "C" const char *su3_last_error(void)
+{
+    return g_last_error.c_str();
+}

@@ -1,0 +1,325 @@
+// Device-side building blocks of the site-local kernels (gfx950, wave64).
+//
+// One lane evaluates the expression for S consecutive sites.  In the
+// blocked layouts (SoA, AoSoA with L >= S) the S sites' copies of one
+// complex entry are adjacent, so each entry of each operand is a single
+// 16-byte load per lane and a wave moves 1 KB per instruction: the
+// coalesced access that the paper's AoS-vs-coalesced measurements
+// (Section 4) and its vector layout (Section 5) are about.  S = 16 bytes /
+// (2 * sizeof(stored real)): double 1, float 2, half 4.
+//
+// Arithmetic: double for F64 storage, single otherwise; products use fused
+// multiply-add.  The compressed form keeps rows 0-1 and rebuilds row 2 of
+// every right-hand operand as conj(row0 x row1) in registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "su3_internal.h"
+
+namespace su3k {
+
+using su3i::Geom;
+
+template <int P> struct PrecT;
+template <> struct PrecT<su3i::F64> {
+    using R = double;   // stored real
+    using T = double;   // arithmetic
+    static constexpr int E = 9;
+    static constexpr int SN = 1;
+};
+template <> struct PrecT<su3i::F32> {
+    using R = float;
+    using T = float;
+    static constexpr int E = 9;
+    static constexpr int SN = 2;
+};
+template <> struct PrecT<su3i::F16> {
+    using R = _Float16;
+    using T = float;
+    static constexpr int E = 9;
+    static constexpr int SN = 4;
+};
+template <> struct PrecT<su3i::C12> {
+    using R = float;
+    using T = float;
+    static constexpr int E = 6;
+    static constexpr int SN = 2;
+};
+
+template <int P, int X> struct Supported {
+    static constexpr bool value =
+        P != su3i::C12 || X == su3i::MUL || X == su3i::MUL3;
+};
+
+template <int X> struct NOps {
+    static constexpr int value =
+        X == su3i::MUL3 ? 3 : (X == su3i::MULADD ? 4 : 2);
+};
+
+template <class T> struct Cx {
+    T re, im;
+};
+
+template <class R, int N> struct VecOf {
+    typedef R type __attribute__((ext_vector_type(N)));
+};
+
+// Nontemporal bit 0 = loads, bit 1 = stores.
+template <int NT, class V>
+__device__ __forceinline__ V vload(const V *p)
+{
+    if constexpr (NT & 1)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <int NT, class V>
+__device__ __forceinline__ void vstore(V *p, V v)
+{
+    if constexpr (NT & 2)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// Offset (stored reals) of entry 0 of site s; s is a multiple of S.
+__device__ __forceinline__ uint32_t site_offset(const Geom &g, uint32_t s)
+{
+    return (s >> g.lg) * g.bstride + ((s & g.mask) << 1);
+}
+
+// ------------------------------------------------------- matrix algebra
+
+// Fused multiply-add in the arithmetic type (float stays float).
+__device__ __forceinline__ float fma_t(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fma_t(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
+}
+
+// c = a * b for rows 0 .. ROWS-1 of c:  c_ij = sum_k a_ik b_kj.
+template <int ROWS, class T>
+__device__ __forceinline__ void mat_mul(const Cx<T> (&a)[9],
+                                        const Cx<T> (&b)[9], Cx<T> (&c)[9])
+{
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T re = a[3 * i].re * b[j].re;
+            T im = a[3 * i].re * b[j].im;
+            re = fma_t(-a[3 * i].im, b[j].im, re);
+            im = fma_t(a[3 * i].im, b[j].re, im);
+#pragma unroll
+            for (int k = 1; k < 3; ++k) {
+                re = fma_t(a[3 * i + k].re, b[3 * k + j].re, re);
+                re = fma_t(-a[3 * i + k].im, b[3 * k + j].im, re);
+                im = fma_t(a[3 * i + k].re, b[3 * k + j].im, im);
+                im = fma_t(a[3 * i + k].im, b[3 * k + j].re, im);
+            }
+            c[3 * i + j].re = re;
+            c[3 * i + j].im = im;
+        }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void mat_add(const Cx<T> (&a)[9],
+                                        const Cx<T> (&b)[9], Cx<T> (&c)[9])
+{
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        c[t].re = a[t].re + b[t].re;
+        c[t].im = a[t].im + b[t].im;
+    }
+}
+
+// Row 2 of an SU(3) matrix from rows 0 and 1: r2_k = conj(r0_p r1_q -
+// r0_q r1_p) with (k, p, q) cyclic.
+template <class T>
+__device__ __forceinline__ void rebuild_row2(Cx<T> (&m)[9])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int p = (k + 1) % 3, q = (k + 2) % 3;
+        const Cx<T> a = m[p], b = m[3 + q], c = m[q], d = m[3 + p];
+        T re = a.re * b.re;
+        re = fma_t(-a.im, b.im, re);
+        re = fma_t(-c.re, d.re, re);
+        re = fma_t(c.im, d.im, re);
+        T im = a.re * b.im;
+        im = fma_t(a.im, b.re, im);
+        im = fma_t(-c.re, d.im, im);
+        im = fma_t(-c.im, d.re, im);
+        m[6 + k].re = re;
+        m[6 + k].im = -im;
+    }
+}
+
+// z = X(ops) for one site.  For the compressed form only rows 0-1 of z are
+// produced and right-hand operands get row 2 rebuilt first.
+template <int P, int X, class T>
+__device__ __forceinline__ void eval_site(Cx<T> (&o)[NOps<X>::value][9],
+                                          Cx<T> (&z)[9])
+{
+    constexpr bool c12 = P == su3i::C12;
+    constexpr int ROWS = c12 ? 2 : 3;
+    if constexpr (X == su3i::MUL) {
+        if constexpr (c12)
+            rebuild_row2(o[1]);
+        mat_mul<ROWS>(o[0], o[1], z);
+    } else if constexpr (X == su3i::MUL3) {
+        Cx<T> t[9];
+        if constexpr (c12) {
+            rebuild_row2(o[1]);
+            rebuild_row2(o[2]);
+        }
+        mat_mul<ROWS>(o[0], o[1], t);
+        mat_mul<ROWS>(t, o[2], z);
+    } else if constexpr (X == su3i::MULADD) {
+        Cx<T> t[9], u[9];
+        mat_mul<3>(o[0], o[1], t);
+        mat_mul<3>(o[2], o[3], u);
+        mat_add(t, u, z);
+    } else if constexpr (X == su3i::ADD) {
+        mat_add(o[0], o[1], z);
+    } else {  // APB_AB = (a + b) + (a * b)
+        Cx<T> t[9], u[9];
+        mat_add(o[0], o[1], t);
+        mat_mul<3>(o[0], o[1], u);
+        mat_add(t, u, z);
+    }
+}
+
+// ----------------------------------------------- one group of S sites
+
+// Sites per lane: one 16-byte access per entry (double 1, float 2, half 4),
+// except half storage with 3-4 operands, which takes 2 sites (8-byte
+// accesses, still whole 128-byte lines per wave) to stay within the
+// register file.
+template <int P, int X> struct SitesPerLane {
+    static constexpr int value =
+        (P == su3i::F16 && NOps<X>::value > 2) ? 2 : PrecT<P>::SN;
+};
+
+// Load the E stored entries of S adjacent sites of one operand as raw
+// vectors (FULL), or of the first `cnt` of them (tail group; the other
+// slots are zero and never stored).
+template <int P, int S, int NT, bool FULL>
+__device__ __forceinline__ void load_raw(
+    const typename PrecT<P>::R *base, uint32_t off, uint32_t plane, int cnt,
+    typename VecOf<typename PrecT<P>::R, 2 * S>::type (&raw)[PrecT<P>::E])
+{
+    using R = typename PrecT<P>::R;
+    using V = typename VecOf<R, 2 * S>::type;
+    using V2 = typename VecOf<R, 2>::type;
+    constexpr int E = PrecT<P>::E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const R *p = base + off + e * plane;
+        if constexpr (FULL) {
+            raw[e] = vload<NT>(reinterpret_cast<const V *>(p));
+        } else {
+            V v;
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                V2 w;
+                if (j < cnt) {
+                    w = vload<NT>(reinterpret_cast<const V2 *>(p + 2 * j));
+                } else {
+                    w[0] = R(0);
+                    w[1] = R(0);
+                }
+                v[2 * j] = w[0];
+                v[2 * j + 1] = w[1];
+            }
+            raw[e] = v;
+        }
+    }
+}
+
+template <int P, int S, int NT, bool FULL>
+__device__ __forceinline__ void store_raw(
+    typename PrecT<P>::R *base, uint32_t off, uint32_t plane, int cnt,
+    const typename VecOf<typename PrecT<P>::R, 2 * S>::type (&raw)[PrecT<P>::E])
+{
+    using R = typename PrecT<P>::R;
+    using V = typename VecOf<R, 2 * S>::type;
+    using V2 = typename VecOf<R, 2>::type;
+    constexpr int E = PrecT<P>::E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        R *p = base + off + e * plane;
+        if constexpr (FULL) {
+            vstore<NT>(reinterpret_cast<V *>(p), raw[e]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                if (j < cnt) {
+                    V2 w;
+                    w[0] = raw[e][2 * j];
+                    w[1] = raw[e][2 * j + 1];
+                    vstore<NT>(reinterpret_cast<V2 *>(p + 2 * j), w);
+                }
+            }
+        }
+    }
+}
+
+// Evaluate X for the group of S sites at stored offset `off`.  All operand
+// entries are loaded (as raw stored vectors) before any result entry is
+// stored, so z may be one of the operands (in-place).  Each site's values
+// are widened to the arithmetic type where they are used.
+template <int P, int X, int S, int NT, bool FULL>
+__device__ __forceinline__ void do_group(void *zp, const void *const (&opp)[4],
+                                         uint32_t off, uint32_t plane, int cnt)
+{
+    using R = typename PrecT<P>::R;
+    using T = typename PrecT<P>::T;
+    using V = typename VecOf<R, 2 * S>::type;
+    constexpr int N = NOps<X>::value;
+    constexpr int E = PrecT<P>::E;
+    V raw[N][E];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        load_raw<P, S, NT, FULL>(static_cast<const R *>(opp[k]), off, plane,
+                                 cnt, raw[k]);
+    V zr[E];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        Cx<T> o[N][9];
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                o[k][e].re = (T)raw[k][e][2 * j];
+                o[k][e].im = (T)raw[k][e][2 * j + 1];
+            }
+        Cx<T> z[9];
+        eval_site<P, X>(o, z);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            zr[e][2 * j] = (R)z[e].re;
+            zr[e][2 * j + 1] = (R)z[e].im;
+        }
+    }
+    store_raw<P, S, NT, FULL>(static_cast<R *>(zp), off, plane, cnt, zr);
+}
+
+// Workgroup id remapped so that each XCD (workgroups are dealt to the 8
+// XCDs round-robin) owns one contiguous range of ids.  A bijection on
+// [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+}  // namespace su3k

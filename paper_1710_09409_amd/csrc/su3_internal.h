@@ -1,0 +1,99 @@
+// Internal interface between the host C-ABI unit (su3_api.cpp) and the
+// kernel unit (su3_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace su3i {
+
+enum Prec { F64 = 0, F32 = 1, F16 = 2, C12 = 3, NPREC = 4 };
+enum Expr { MUL = 0, MUL3 = 1, MULADD = 2, ADD = 3, APB_AB = 4, NEXPR = 5 };
+enum Layout { AOS = 0, SOA = 1, AOSOA = 2 };
+
+// Stored complex entries per site and bytes per stored real.
+inline int entries_of(int prec) { return prec == C12 ? 6 : 9; }
+inline int real_bytes(int prec) { return prec == F64 ? 8 : (prec == F16 ? 2 : 4); }
+inline int operands_of(int expr)
+{
+    return expr == MUL3 ? 3 : (expr == MULADD ? 4 : 2);
+}
+// Sites one lane handles in the blocked layouts: 16-byte accesses (double
+// 1, float 2, half 4), except half storage with 3-4 operands (2 sites).
+inline int natural_sites(int prec, int expr)
+{
+    if (prec == F64)
+        return 1;
+    if (prec == F16)
+        return operands_of(expr) > 2 ? 2 : 4;
+    return 2;
+}
+
+// Index geometry of a stored field, in units of stored reals: site s (a
+// multiple of the sites-per-lane count), entry e, re/im c live at
+//     (s >> lg) * bstride + e * plane + ((s & mask) << 1) + c.
+// AoS: lg 0, mask 0, plane 2, bstride 2E.  AoSoA(L): lg log2 L,
+// mask L-1, plane 2L, bstride 2EL.  SoA: lg 31, mask 2^31-1 (one block),
+// plane 2 V_pad.
+struct Geom {
+    uint32_t lg;
+    uint32_t mask;
+    uint32_t plane;
+    uint32_t bstride;
+};
+
+// Arguments of the one-launch site kernels.
+struct SiteArgs {
+    void *z;
+    const void *op[4];
+    Geom g;
+    int32_t nsites;   // V
+    int32_t ngroups;  // ceil(V / S)
+    int32_t xcd_remap;
+};
+
+// One item of a batched launch (device-resident table).
+struct BatchItem {
+    void *z;
+    const void *op[4];
+    Geom g;
+    int32_t nsites;
+    int32_t prec;
+    int32_t expr;
+    int32_t pad_;
+};
+
+// One tile of a batched launch: `count` sites of item `item` starting at
+// site `first`; `prec` repeats the item's precision (the wave-uniform
+// branch key).
+struct BatchTile {
+    int32_t item;
+    int32_t first;
+    int32_t count;
+    int32_t prec;
+};
+
+// Kernel-unit entry points.  Each returns the launch's hipError_t.
+// `sites_per_lane` must be natural_sites(prec) for blocked layouts or 1.
+hipError_t launch_site(int prec, int expr, int sites_per_lane, int nt,
+                       int block, int grid, const SiteArgs &a,
+                       hipStream_t stream);
+// AoS with LDS staging: one lane per site, `block` sites per workgroup.
+hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
+                           const SiteArgs &a, hipStream_t stream);
+// Batched persistent launch over `ntiles` tiles, `grid` workgroups each
+// taking tiles blockIdx.x, blockIdx.x + grid, ...
+// mode 0: every item is MUL in F64 or C12 (the mixed-precision streaming
+// workload, smallest register footprint); mode 1: any supported item.
+hipError_t launch_batch(int mode, const BatchItem *items,
+                        const BatchTile *tiles, int32_t ntiles, int nt,
+                        int block, int grid, hipStream_t stream);
+hipError_t launch_triad(double *a, const double *b, const double *c,
+                        double s, int64_t n, hipStream_t stream);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes,
+                       hipStream_t stream);
+
+// Largest block the kernel family was compiled for.
+constexpr int kMaxBlock = 1024;
+
+}  // namespace su3i
