@@ -101,15 +101,23 @@ typedef struct su3_batch su3_batch;
 
 /* How a compute call is launched.  Any valid setting gives bit-identical
  * results; only speed differs.
- *   block       lanes per workgroup: 64, 128, 256, 512 or 1024
- *   persistent  0: one lane per site group (one-shot grid);
- *               k > 0: k workgroups per compute unit, grid-stride loop
+ *   block       lanes per workgroup: 64, 128 or 256
+ *   persistent  0: one lane per site group (one-shot grid); batches: one
+ *               workgroup per tile.  k > 0: k workgroups per compute unit
+ *               loop over the work (grid-stride over site groups or tiles)
  *   nontemporal bit 0: nontemporal loads, bit 1: nontemporal stores
  *   xcd_remap   1: hand each of the 8 XCDs a contiguous range of
  *               workgroups instead of the hardware's round-robin
  *   lds_stage   AOS only: 1 stages each workgroup's sites through LDS with
- *               coalesced 16-byte copies
- *   tile_sites  batched launch only: sites per tile (multiple of 64)    */
+ *               coalesced 16-byte copies (block <= 128)
+ *   tile_sites  batched launch only: sites per tile (multiple of 64)
+ *   occupancy   0: no cap; k > 0: at most k workgroups per compute unit
+ *               (enforced by reserving LDS): fewer waves with their loads
+ *               in flight keep HBM streaming efficiently
+ *   schedule    0: each lane loads every operand entry, then stores every
+ *               result entry; 1: row-phased -- right-hand operands in
+ *               full, then per result row the left operands' row, the
+ *               row's evaluation and its stores                          */
 typedef struct su3_launch {
     int32_t block;
     int32_t persistent;
@@ -117,6 +125,8 @@ typedef struct su3_launch {
     int32_t xcd_remap;
     int32_t lds_stage;
     int32_t tile_sites;
+    int32_t occupancy;
+    int32_t schedule;
 } su3_launch;
 
 /* ------------------------------------------------------------- fields */

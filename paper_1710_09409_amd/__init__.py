@@ -59,7 +59,8 @@ class Su3Error(RuntimeError):
 class su3_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("lds_stage", ctypes.c_int32), ("tile_sites", ctypes.c_int32)]
+                ("lds_stage", ctypes.c_int32), ("tile_sites", ctypes.c_int32),
+                ("occupancy", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -396,21 +396,48 @@ extern "C" su3_status su3_field_download(const su3_field *f, double *host,
 
 // -------------------------------------------------------- device facts
 
-static int device_cus(int dev)
+struct DeviceFacts {
+    int cus;
+    int lds_per_cu;
+    int lds_per_block;
+};
+
+static DeviceFacts device_facts(int dev)
 {
     static std::mutex mu;
-    static std::map<int, int> cache;
+    static std::map<int, DeviceFacts> cache;
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(dev);
     if (it != cache.end())
         return it->second;
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
-            hipSuccess ||
-        n <= 0)
-        n = 256;
-    cache[dev] = n;
-    return n;
+    DeviceFacts f;
+    if (hipDeviceGetAttribute(&f.cus, hipDeviceAttributeMultiprocessorCount,
+                              dev) != hipSuccess || f.cus <= 0)
+        f.cus = 256;
+    if (hipDeviceGetAttribute(&f.lds_per_cu,
+                              hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              dev) != hipSuccess || f.lds_per_cu <= 0)
+        f.lds_per_cu = 64 * 1024;
+    if (hipDeviceGetAttribute(&f.lds_per_block,
+                              hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              dev) != hipSuccess || f.lds_per_block <= 0)
+        f.lds_per_block = 64 * 1024;
+    cache[dev] = f;
+    return f;
+}
+
+static int device_cus(int dev) { return device_facts(dev).cus; }
+
+// LDS to reserve per workgroup so that at most `occupancy` workgroups fit
+// on a CU (0: none).  The reserve is never read by the kernels.
+static size_t occupancy_reserve(int dev, int occupancy)
+{
+    if (occupancy <= 0)
+        return 0;
+    const DeviceFacts f = device_facts(dev);
+    size_t r = (size_t)f.lds_per_cu / (size_t)occupancy;
+    r = std::min(r, (size_t)f.lds_per_block);
+    return r / 256 * 256;
 }
 
 // ------------------------------------------------------- launch table
@@ -434,20 +461,22 @@ static su3_launch default_launch(int expr, int prec, int layout)
     (void)expr;
     (void)prec;
     su3_launch c;
-    c.block = layout == SU3_LAYOUT_AOS ? 64 : 256;
+    c.block = 64;
     c.persistent = 0;
     c.nontemporal = 3;
     c.xcd_remap = 0;
     c.lds_stage = 0;
     c.tile_sites = 4096;
+    c.occupancy = layout == SU3_LAYOUT_AOS ? 0 : 5;
+    c.schedule = layout == SU3_LAYOUT_AOS ? 0 : 1;
     return c;
 }
 
 static su3_status check_launch(const su3_launch &c, int layout)
 {
-    if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512 &&
-        c.block != 1024)
-        return fail(SU3_ERR_INVALID_ARG, "block %d not in {64..1024}", c.block);
+    if (c.block != 64 && c.block != 128 && c.block != 256)
+        return fail(SU3_ERR_INVALID_ARG, "block %d not in {64, 128, 256}",
+                    c.block);
     if (c.persistent < 0 || c.persistent > 64)
         return fail(SU3_ERR_INVALID_ARG, "persistent %d not in [0, 64]",
                     c.persistent);
@@ -464,6 +493,11 @@ static su3_status check_launch(const su3_launch &c, int layout)
     if (c.tile_sites < 64 || c.tile_sites % 64 != 0 || c.tile_sites > (1 << 24))
         return fail(SU3_ERR_INVALID_ARG,
                     "tile_sites must be a positive multiple of 64");
+    if (c.occupancy < 0 || c.occupancy > 64)
+        return fail(SU3_ERR_INVALID_ARG, "occupancy %d not in [0, 64]",
+                    c.occupancy);
+    if (c.schedule < 0 || c.schedule > 1)
+        return fail(SU3_ERR_INVALID_ARG, "schedule must be 0 or 1");
     return SU3_OK;
 }
 
@@ -530,7 +564,9 @@ static void load_cache_locked()
             !parse_int(line, "nontemporal", &c.nontemporal) ||
             !parse_int(line, "xcd_remap", &c.xcd_remap) ||
             !parse_int(line, "lds_stage", &c.lds_stage) ||
-            !parse_int(line, "tile_sites", &c.tile_sites))
+            !parse_int(line, "tile_sites", &c.tile_sites) ||
+            !parse_int(line, "occupancy", &c.occupancy) ||
+            !parse_int(line, "schedule", &c.schedule))
             continue;
         if (check_launch(c, la) != SU3_OK)
             continue;
@@ -551,11 +587,12 @@ static void append_cache(const Key &k, const su3_launch &c, double us)
             "{\"device\":\"%s\",\"expr\":%d,\"prec\":%d,\"layout\":%d,"
             "\"lanes\":%d,\"vbucket\":%d,\"block\":%d,\"persistent\":%d,"
             "\"nontemporal\":%d,\"xcd_remap\":%d,\"lds_stage\":%d,"
-            "\"tile_sites\":%d,\"us\":%.3f}\n",
+            "\"tile_sites\":%d,\"occupancy\":%d,\"schedule\":%d,"
+            "\"us\":%.3f}\n",
             device_tag().c_str(), std::get<0>(k), std::get<1>(k),
             std::get<2>(k), std::get<3>(k), std::get<4>(k), c.block,
             c.persistent, c.nontemporal, c.xcd_remap, c.lds_stage,
-            c.tile_sites, us);
+            c.tile_sites, c.occupancy, c.schedule, us);
     fclose(fp);
 }
 
@@ -650,7 +687,8 @@ static su3_status launch_item(su3_field *z, int expr,
         if (c.persistent)
             grid = std::min<int64_t>(grid, (int64_t)c.persistent *
                                                device_cus(z->device));
-        e = launch_site(z->prec, expr, S, c.nontemporal, c.block, (int)grid, a,
+        e = launch_site(z->prec, expr, S, c.nontemporal, c.schedule, c.block,
+                        (int)grid, occupancy_reserve(z->device, c.occupancy), a,
                         st);
     }
     if (e != hipSuccess)
@@ -743,32 +781,55 @@ extern "C" su3_status su3_launch_reset(void)
     return SU3_OK;
 }
 
-// Candidate launches of the autotuner's sweep.
+// Candidate launches of the autotuner's sweep.  Persistent grid-stride
+// launches are kept as a few samples only: on this hardware one-shot grids
+// stream writes far better.
 static std::vector<su3_launch> candidates(int layout)
 {
     std::vector<su3_launch> out;
-    const int blocks[] = {64, 128, 256, 512, 1024};
-    const int pers[] = {0, 4, 8};
-    const int nts[] = {0, 2, 3};
-    for (int b : blocks)
-        for (int p : pers)
-            for (int nt : nts)
-                for (int x = 0; x < 2; ++x)
-                    for (int lds = 0; lds < (layout == SU3_LAYOUT_AOS ? 2 : 1);
-                         ++lds) {
-                        if (lds && b > 128)
-                            continue;
-                        if (p && x)
-                            continue;  // remap only matters for one-shot grids
-                        su3_launch c;
+    su3_launch c;
+    c.persistent = 0;
+    c.xcd_remap = 0;
+    c.lds_stage = 0;
+    c.tile_sites = 4096;
+    if (layout == SU3_LAYOUT_AOS) {
+        for (int b : {64, 128, 256})
+            for (int nt : {0, 3})
+                for (int lds = 0; lds < 2; ++lds) {
+                    if (lds && b > 128)
+                        continue;
+                    c.block = b;
+                    c.nontemporal = nt;
+                    c.lds_stage = lds;
+                    c.occupancy = 0;
+                    c.schedule = 0;
+                    out.push_back(c);
+                }
+        return out;
+    }
+    for (int b : {64, 128, 256})
+        for (int occ : {0, 2, 3, 4, 5, 6, 8})
+            for (int sched : {0, 1})
+                for (int nt : {0, 2, 3})
+                    for (int x : {0, 1}) {
                         c.block = b;
-                        c.persistent = p;
+                        c.occupancy = occ;
+                        c.schedule = sched;
                         c.nontemporal = nt;
                         c.xcd_remap = x;
-                        c.lds_stage = lds;
-                        c.tile_sites = 4096;
                         out.push_back(c);
                     }
+    c.xcd_remap = 0;
+    c.nontemporal = 3;
+    for (int b : {64, 256})
+        for (int p : {2, 4})
+            for (int sched : {0, 1}) {
+                c.block = b;
+                c.persistent = p;
+                c.occupancy = 0;
+                c.schedule = sched;
+                out.push_back(c);
+            }
     return out;
 }
 
@@ -924,8 +985,6 @@ extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
         lookup_launch(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
                       total_sites);
     su3_launch cfg = c;
-    if (cfg.block > 256)
-        cfg.block = 256;
     const int T = cfg.tile_sites;
     std::vector<BatchTile> tiles;
     for (int i = 0; i < n; ++i) {
@@ -948,9 +1007,12 @@ extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
     b->mode = mode;
     b->cfg = cfg;
     b->device = dev;
-    const int per_cu = cfg.persistent > 0 ? cfg.persistent : 8;
-    b->grid = (int32_t)std::min<int64_t>(b->ntiles,
-                                         (int64_t)per_cu * device_cus(dev));
+    // persistent k > 0: k workgroups per CU loop over the tiles; 0: one
+    // workgroup per tile
+    b->grid = cfg.persistent > 0
+                  ? (int32_t)std::min<int64_t>(b->ntiles, (int64_t)cfg.persistent *
+                                                              device_cus(dev))
+                  : b->ntiles;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     hipError_t e = hipMalloc(&b->d_items, sizeof(BatchItem) * n);
     if (e == hipSuccess)
@@ -972,7 +1034,9 @@ extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = launch_batch(b->mode, b->d_items, b->d_tiles, b->ntiles,
-                                     cfg.nontemporal, cfg.block, b->grid, cap);
+                                     cfg.nontemporal, cfg.schedule, cfg.block,
+                                     b->grid, occupancy_reserve(dev, cfg.occupancy),
+                                     cap);
         hipError_t ce = hipStreamEndCapture(cap, &b->graph);
         e = le != hipSuccess ? le : ce;
     }

@@ -208,23 +208,25 @@ template <int P, int X> struct SitesPerLane {
         (P == su3i::F16 && NOps<X>::value > 2) ? 2 : PrecT<P>::SN;
 };
 
-// Load the E stored entries of S adjacent sites of one operand as raw
-// vectors (FULL), or of the first `cnt` of them (tail group; the other
+template <int P, int S>
+using RawVec = typename VecOf<typename PrecT<P>::R, 2 * S>::type;
+
+// Load stored entries e0 .. e0+NE-1 of S adjacent sites of one operand as
+// raw vectors (FULL), or of the first `cnt` of them (tail group; the other
 // slots are zero and never stored).
-template <int P, int S, int NT, bool FULL>
-__device__ __forceinline__ void load_raw(
-    const typename PrecT<P>::R *base, uint32_t off, uint32_t plane, int cnt,
-    typename VecOf<typename PrecT<P>::R, 2 * S>::type (&raw)[PrecT<P>::E])
+template <int P, int S, int NT, bool FULL, int E0, int NE>
+__device__ __forceinline__ void load_entries(const typename PrecT<P>::R *base,
+                                             uint32_t off, uint32_t plane,
+                                             int cnt, RawVec<P, S> *raw)
 {
     using R = typename PrecT<P>::R;
-    using V = typename VecOf<R, 2 * S>::type;
+    using V = RawVec<P, S>;
     using V2 = typename VecOf<R, 2>::type;
-    constexpr int E = PrecT<P>::E;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const R *p = base + off + e * plane;
+    for (int t = 0; t < NE; ++t) {
+        const R *p = base + off + (E0 + t) * plane;
         if constexpr (FULL) {
-            raw[e] = vload<NT>(reinterpret_cast<const V *>(p));
+            raw[t] = vload<NT>(reinterpret_cast<const V *>(p));
         } else {
             V v;
 #pragma unroll
@@ -239,32 +241,32 @@ __device__ __forceinline__ void load_raw(
                 v[2 * j] = w[0];
                 v[2 * j + 1] = w[1];
             }
-            raw[e] = v;
+            raw[t] = v;
         }
     }
 }
 
-template <int P, int S, int NT, bool FULL>
-__device__ __forceinline__ void store_raw(
-    typename PrecT<P>::R *base, uint32_t off, uint32_t plane, int cnt,
-    const typename VecOf<typename PrecT<P>::R, 2 * S>::type (&raw)[PrecT<P>::E])
+template <int P, int S, int NT, bool FULL, int E0, int NE>
+__device__ __forceinline__ void store_entries(typename PrecT<P>::R *base,
+                                              uint32_t off, uint32_t plane,
+                                              int cnt,
+                                              const RawVec<P, S> *raw)
 {
     using R = typename PrecT<P>::R;
-    using V = typename VecOf<R, 2 * S>::type;
+    using V = RawVec<P, S>;
     using V2 = typename VecOf<R, 2>::type;
-    constexpr int E = PrecT<P>::E;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        R *p = base + off + e * plane;
+    for (int t = 0; t < NE; ++t) {
+        R *p = base + off + (E0 + t) * plane;
         if constexpr (FULL) {
-            vstore<NT>(reinterpret_cast<V *>(p), raw[e]);
+            vstore<NT>(reinterpret_cast<V *>(p), raw[t]);
         } else {
 #pragma unroll
             for (int j = 0; j < S; ++j) {
                 if (j < cnt) {
                     V2 w;
-                    w[0] = raw[e][2 * j];
-                    w[1] = raw[e][2 * j + 1];
+                    w[0] = raw[t][2 * j];
+                    w[1] = raw[t][2 * j + 1];
                     vstore<NT>(reinterpret_cast<V2 *>(p + 2 * j), w);
                 }
             }
@@ -272,44 +274,233 @@ __device__ __forceinline__ void store_raw(
     }
 }
 
-// Evaluate X for the group of S sites at stored offset `off`.  All operand
-// entries are loaded (as raw stored vectors) before any result entry is
-// stored, so z may be one of the operands (in-place).  Each site's values
-// are widened to the arithmetic type where they are used.
-template <int P, int X, int S, int NT, bool FULL>
-__device__ __forceinline__ void do_group(void *zp, const void *const (&opp)[4],
-                                         uint32_t off, uint32_t plane, int cnt)
+// Widen entry slot `t` of site `j` from a raw vector.
+template <int P, int S>
+__device__ __forceinline__ Cx<typename PrecT<P>::T> widen(const RawVec<P, S> &v,
+                                                          int j)
+{
+    using T = typename PrecT<P>::T;
+    Cx<T> c;
+    c.re = (T)v[2 * j];
+    c.im = (T)v[2 * j + 1];
+    return c;
+}
+
+template <int P, int S>
+__device__ __forceinline__ void narrow(RawVec<P, S> &v, int j,
+                                       const Cx<typename PrecT<P>::T> &c)
 {
     using R = typename PrecT<P>::R;
     using T = typename PrecT<P>::T;
-    using V = typename VecOf<R, 2 * S>::type;
+    T re = c.re, im = c.im;
+    if constexpr (P == su3i::F16) {
+        // Keep the single-precision result: without the barrier the
+        // compiler fuses the last FMA with the conversion (v_fma_mixlo_f16,
+        // one rounding) in some code shapes and not in others, so results
+        // would depend on the launch settings.  The declared convention is
+        // FP32 arithmetic, then one round-to-nearest-even to half.
+        __asm__("" : "+v"(re));
+        __asm__("" : "+v"(im));
+    }
+    v[2 * j] = (R)re;
+    v[2 * j + 1] = (R)im;
+}
+
+// Schedule 0: every operand entry of the group is loaded (as raw stored
+// vectors), then evaluated, then every result entry is stored.
+template <int P, int X, int S, int NT, bool FULL>
+__device__ __forceinline__ void group_all(void *zp, const void *const (&opp)[4],
+                                          uint32_t off, uint32_t plane, int cnt)
+{
+    using R = typename PrecT<P>::R;
+    using T = typename PrecT<P>::T;
     constexpr int N = NOps<X>::value;
     constexpr int E = PrecT<P>::E;
-    V raw[N][E];
+    RawVec<P, S> raw[N][E];
 #pragma unroll
     for (int k = 0; k < N; ++k)
-        load_raw<P, S, NT, FULL>(static_cast<const R *>(opp[k]), off, plane,
-                                 cnt, raw[k]);
-    V zr[E];
+        load_entries<P, S, NT, FULL, 0, E>(static_cast<const R *>(opp[k]), off,
+                                           plane, cnt, raw[k]);
+    RawVec<P, S> zr[E];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         Cx<T> o[N][9];
 #pragma unroll
         for (int k = 0; k < N; ++k)
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                o[k][e].re = (T)raw[k][e][2 * j];
-                o[k][e].im = (T)raw[k][e][2 * j + 1];
-            }
+            for (int e = 0; e < E; ++e)
+                o[k][e] = widen<P, S>(raw[k][e], j);
         Cx<T> z[9];
         eval_site<P, X>(o, z);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            zr[e][2 * j] = (R)z[e].re;
-            zr[e][2 * j + 1] = (R)z[e].im;
-        }
+        for (int e = 0; e < E; ++e)
+            narrow<P, S>(zr[e], j, z[e]);
     }
-    store_raw<P, S, NT, FULL>(static_cast<R *>(zp), off, plane, cnt, zr);
+    store_entries<P, S, NT, FULL, 0, E>(static_cast<R *>(zp), off, plane, cnt,
+                                        zr);
+}
+
+// Row i of a product: c_i = a_i * b, the same FMA sequence as mat_mul.
+template <class T>
+__device__ __forceinline__ void row_mul(const Cx<T> *a, const Cx<T> (&b)[9],
+                                        Cx<T> *c)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T re = a[0].re * b[j].re;
+        T im = a[0].re * b[j].im;
+        re = fma_t(-a[0].im, b[j].im, re);
+        im = fma_t(a[0].im, b[j].re, im);
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+            re = fma_t(a[k].re, b[3 * k + j].re, re);
+            re = fma_t(-a[k].im, b[3 * k + j].im, re);
+            im = fma_t(a[k].re, b[3 * k + j].im, im);
+            im = fma_t(a[k].im, b[3 * k + j].re, im);
+        }
+        c[j].re = re;
+        c[j].im = im;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void row_add(const Cx<T> *a, const Cx<T> *b, Cx<T> *c)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        c[j].re = a[j].re + b[j].re;
+        c[j].im = a[j].im + b[j].im;
+    }
+}
+
+// Which operands an expression reads row by row (left) and in full (right).
+template <int X> struct Split;
+template <> struct Split<su3i::MUL> {
+    static constexpr int NL = 1, NR = 1;
+    static constexpr int L[1] = {0}, Rt[1] = {1};
+};
+template <> struct Split<su3i::MUL3> {
+    static constexpr int NL = 1, NR = 2;
+    static constexpr int L[1] = {0}, Rt[2] = {1, 2};
+};
+template <> struct Split<su3i::MULADD> {
+    static constexpr int NL = 2, NR = 2;
+    static constexpr int L[2] = {0, 2}, Rt[2] = {1, 3};
+};
+template <> struct Split<su3i::ADD> {
+    static constexpr int NL = 2, NR = 0;
+    static constexpr int L[2] = {0, 1}, Rt[1] = {0};
+};
+template <> struct Split<su3i::APB_AB> {
+    static constexpr int NL = 1, NR = 1;
+    static constexpr int L[1] = {0}, Rt[1] = {1};
+};
+
+// Row i of z from the rows i of the left operands and the full right ones.
+template <int X, class T>
+__device__ __forceinline__ void eval_row(const Cx<T> (&l)[2][3],
+                                         const Cx<T> (&r)[2][9], int i,
+                                         Cx<T> *z)
+{
+    if constexpr (X == su3i::MUL) {
+        row_mul(l[0], r[0], z);
+    } else if constexpr (X == su3i::MUL3) {
+        Cx<T> t[3];
+        row_mul(l[0], r[0], t);
+        row_mul(t, r[1], z);
+    } else if constexpr (X == su3i::MULADD) {
+        Cx<T> t[3], u[3];
+        row_mul(l[0], r[0], t);
+        row_mul(l[1], r[1], u);
+        row_add(t, u, z);
+    } else if constexpr (X == su3i::ADD) {
+        row_add(l[0], l[1], z);
+    } else {  // APB_AB = (a + b) + (a * b)
+        Cx<T> t[3], u[3];
+        row_add(l[0], &r[0][3 * i], t);
+        row_mul(l[0], r[0], u);
+        row_add(t, u, z);
+    }
+}
+
+// Schedule 1, row-phased: the right-hand operands are loaded in full, then
+// for each result row the left operands' row is loaded, the row evaluated
+// and stored before the next row's loads, so every wave alternates loads
+// and stores instead of issuing all loads and then all stores.  Same
+// arithmetic, same bits as schedule 0.
+template <int P, int X, int S, int NT, bool FULL>
+__device__ __forceinline__ void group_rows(void *zp, const void *const (&opp)[4],
+                                           uint32_t off, uint32_t plane, int cnt)
+{
+    using R = typename PrecT<P>::R;
+    using T = typename PrecT<P>::T;
+    using SP = Split<X>;
+    constexpr int E = PrecT<P>::E;
+    constexpr int ROWS = E / 3;
+    RawVec<P, S> rr[SP::NR > 0 ? SP::NR : 1][E];
+#pragma unroll
+    for (int k = 0; k < SP::NR; ++k)
+        load_entries<P, S, NT, FULL, 0, E>(static_cast<const R *>(opp[SP::Rt[k]]),
+                                           off, plane, cnt, rr[k]);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+        RawVec<P, S> lr[SP::NL][3];
+#pragma unroll
+        for (int k = 0; k < SP::NL; ++k) {
+            const R *base = static_cast<const R *>(opp[SP::L[k]]);
+            if (i == 0)
+                load_entries<P, S, NT, FULL, 0, 3>(base, off, plane, cnt, lr[k]);
+            else if (i == 1)
+                load_entries<P, S, NT, FULL, 3, 3>(base, off, plane, cnt, lr[k]);
+            else
+                load_entries<P, S, NT, FULL, 6, 3>(base, off, plane, cnt, lr[k]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        RawVec<P, S> zr[3];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            Cx<T> l[2][3], r[2][9];
+#pragma unroll
+            for (int k = 0; k < SP::NL; ++k)
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    l[k][e] = widen<P, S>(lr[k][e], j);
+#pragma unroll
+            for (int k = 0; k < SP::NR; ++k) {
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    r[k][e] = widen<P, S>(rr[k][e], j);
+                if constexpr (P == su3i::C12)
+                    rebuild_row2(r[k]);
+            }
+            Cx<T> z[3];
+            eval_row<X>(l, r, i, z);
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+                narrow<P, S>(zr[e], j, z[e]);
+        }
+        R *zb = static_cast<R *>(zp);
+        if (i == 0)
+            store_entries<P, S, NT, FULL, 0, 3>(zb, off, plane, cnt, zr);
+        else if (i == 1)
+            store_entries<P, S, NT, FULL, 3, 3>(zb, off, plane, cnt, zr);
+        else
+            store_entries<P, S, NT, FULL, 6, 3>(zb, off, plane, cnt, zr);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Evaluate X for the group of S sites at stored offset `off`.  Every
+// operand entry a result entry depends on is loaded before that result
+// entry is stored, so z may be one of the operands (in-place).
+template <int P, int X, int S, int NT, bool FULL, int SCHED>
+__device__ __forceinline__ void do_group(void *zp, const void *const (&opp)[4],
+                                         uint32_t off, uint32_t plane, int cnt)
+{
+    if constexpr (SCHED == 0)
+        group_all<P, X, S, NT, FULL>(zp, opp, off, plane, cnt);
+    else
+        group_rows<P, X, S, NT, FULL>(zp, opp, off, plane, cnt);
 }
 
 // Workgroup id remapped so that each XCD (workgroups are dealt to the 8

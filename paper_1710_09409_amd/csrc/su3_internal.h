@@ -74,10 +74,12 @@ struct BatchTile {
 };
 
 // Kernel-unit entry points.  Each returns the launch's hipError_t.
-// `sites_per_lane` must be natural_sites(prec) for blocked layouts or 1.
+// `sites_per_lane` must be natural_sites(prec, expr) for blocked layouts or
+// 1; `sched` 0 = all loads then all stores, 1 = row-phased; `shm` is LDS
+// reserved per workgroup to cap occupancy (never read); block <= 256.
 hipError_t launch_site(int prec, int expr, int sites_per_lane, int nt,
-                       int block, int grid, const SiteArgs &a,
-                       hipStream_t stream);
+                       int sched, int block, int grid, size_t shm,
+                       const SiteArgs &a, hipStream_t stream);
 // AoS with LDS staging: one lane per site, `block` sites per workgroup.
 hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
                            const SiteArgs &a, hipStream_t stream);
@@ -87,13 +89,14 @@ hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
 // workload, smallest register footprint); mode 1: any supported item.
 hipError_t launch_batch(int mode, const BatchItem *items,
                         const BatchTile *tiles, int32_t ntiles, int nt,
-                        int block, int grid, hipStream_t stream);
+                        int sched, int block, int grid, size_t shm,
+                        hipStream_t stream);
 hipError_t launch_triad(double *a, const double *b, const double *c,
                         double s, int64_t n, hipStream_t stream);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,
                        hipStream_t stream);
 
 // Largest block the kernel family was compiled for.
-constexpr int kMaxBlock = 1024;
+constexpr int kMaxBlock = 256;
 
 }  // namespace su3i

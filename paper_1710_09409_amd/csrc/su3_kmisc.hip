@@ -3,10 +3,10 @@
 #include "su3_device.h"
 
 namespace su3i {
-hipError_t launch_site_p0(int, int, int, int, int, const SiteArgs &, hipStream_t);
-hipError_t launch_site_p1(int, int, int, int, int, const SiteArgs &, hipStream_t);
-hipError_t launch_site_p2(int, int, int, int, int, const SiteArgs &, hipStream_t);
-hipError_t launch_site_p3(int, int, int, int, int, const SiteArgs &, hipStream_t);
+hipError_t launch_site_p0(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
+hipError_t launch_site_p1(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
+hipError_t launch_site_p2(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
+hipError_t launch_site_p3(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
 hipError_t launch_site_lds_p0(int, int, int, int, const SiteArgs &, hipStream_t);
 hipError_t launch_site_lds_p1(int, int, int, int, const SiteArgs &, hipStream_t);
 hipError_t launch_site_lds_p2(int, int, int, int, const SiteArgs &, hipStream_t);
@@ -20,7 +20,7 @@ using su3i::BatchTile;
 
 // Evaluate one tile: `count` sites of item `it` from site `first` (a
 // multiple of the tile size, hence of S), lanes striding over its groups.
-template <int P, int X, int NT>
+template <int P, int X, int NT, int SCHED>
 __device__ __forceinline__ void tile_run(const BatchItem &it, int first,
                                          int count)
 {
@@ -32,25 +32,25 @@ __device__ __forceinline__ void tile_run(const BatchItem &it, int first,
         const uint32_t off = site_offset(it.g, s0);
         const int cnt = first + count - int(s0);
         if (cnt >= S)
-            do_group<P, X, S, NT, true>(it.z, ops, off, it.g.plane, S);
+            do_group<P, X, S, NT, true, SCHED>(it.z, ops, off, it.g.plane, S);
         else
-            do_group<P, X, S, NT, false>(it.z, ops, off, it.g.plane, cnt);
+            do_group<P, X, S, NT, false, SCHED>(it.z, ops, off, it.g.plane, cnt);
     }
 }
 
-template <int P, int NT>
+template <int P, int NT, int SCHED>
 __device__ __forceinline__ void tile_any_expr(const BatchItem &it, int first,
                                               int count)
 {
     switch (it.expr) {
-    case su3i::MUL: tile_run<P, su3i::MUL, NT>(it, first, count); break;
-    case su3i::MUL3: tile_run<P, su3i::MUL3, NT>(it, first, count); break;
+    case su3i::MUL: tile_run<P, su3i::MUL, NT, SCHED>(it, first, count); break;
+    case su3i::MUL3: tile_run<P, su3i::MUL3, NT, SCHED>(it, first, count); break;
     default:
         if constexpr (P != su3i::C12) {
             switch (it.expr) {
-            case su3i::MULADD: tile_run<P, su3i::MULADD, NT>(it, first, count); break;
-            case su3i::ADD: tile_run<P, su3i::ADD, NT>(it, first, count); break;
-            case su3i::APB_AB: tile_run<P, su3i::APB_AB, NT>(it, first, count); break;
+            case su3i::MULADD: tile_run<P, su3i::MULADD, NT, SCHED>(it, first, count); break;
+            case su3i::ADD: tile_run<P, su3i::ADD, NT, SCHED>(it, first, count); break;
+            case su3i::APB_AB: tile_run<P, su3i::APB_AB, NT, SCHED>(it, first, count); break;
             }
         }
         break;
@@ -60,28 +60,32 @@ __device__ __forceinline__ void tile_any_expr(const BatchItem &it, int first,
 // Persistent batched kernel: workgroup b takes tiles b, b + G, b + 2G, ...
 // The per-tile branch on precision and expression is uniform across the
 // workgroup.  Every workgroup leaves after its last tile.
-template <int MODE, int NT>
+template <int MODE, int NT, int SCHED>
 __global__ __launch_bounds__(256) void k_batch(const BatchItem *items,
                                                const BatchTile *tiles,
                                                int ntiles)
 {
+    // dynamic LDS only caps the workgroups per CU; never read
+    extern __shared__ char occupancy_reserve[];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const BatchTile tl = tiles[t];
         const BatchItem &it = items[tl.item];
         if constexpr (MODE == 0) {
             if (tl.prec == su3i::F64)
-                tile_run<su3i::F64, su3i::MUL, NT>(it, tl.first, tl.count);
+                tile_run<su3i::F64, su3i::MUL, NT, SCHED>(it, tl.first, tl.count);
             else
-                tile_run<su3i::C12, su3i::MUL, NT>(it, tl.first, tl.count);
+                tile_run<su3i::C12, su3i::MUL, NT, SCHED>(it, tl.first, tl.count);
         } else {
             switch (tl.prec) {
-            case su3i::F64: tile_any_expr<su3i::F64, NT>(it, tl.first, tl.count); break;
-            case su3i::F32: tile_any_expr<su3i::F32, NT>(it, tl.first, tl.count); break;
-            case su3i::F16: tile_any_expr<su3i::F16, NT>(it, tl.first, tl.count); break;
-            case su3i::C12: tile_any_expr<su3i::C12, NT>(it, tl.first, tl.count); break;
+            case su3i::F64: tile_any_expr<su3i::F64, NT, SCHED>(it, tl.first, tl.count); break;
+            case su3i::F32: tile_any_expr<su3i::F32, NT, SCHED>(it, tl.first, tl.count); break;
+            case su3i::F16: tile_any_expr<su3i::F16, NT, SCHED>(it, tl.first, tl.count); break;
+            case su3i::C12: tile_any_expr<su3i::C12, NT, SCHED>(it, tl.first, tl.count); break;
             }
         }
     }
+    if (ntiles < 0)
+        occupancy_reserve[threadIdx.x] = 0;
 }
 
 template <int NT>
@@ -118,14 +122,14 @@ __global__ __launch_bounds__(256) void k_copy(void *dst, const void *src,
 
 namespace su3i {
 
-hipError_t launch_site(int prec, int expr, int S, int nt, int block, int grid,
-                       const SiteArgs &a, hipStream_t st)
+hipError_t launch_site(int prec, int expr, int S, int nt, int sched, int block,
+                       int grid, size_t shm, const SiteArgs &a, hipStream_t st)
 {
     switch (prec) {
-    case F64: return launch_site_p0(expr, S, nt, block, grid, a, st);
-    case F32: return launch_site_p1(expr, S, nt, block, grid, a, st);
-    case F16: return launch_site_p2(expr, S, nt, block, grid, a, st);
-    case C12: return launch_site_p3(expr, S, nt, block, grid, a, st);
+    case F64: return launch_site_p0(expr, S, nt, sched, block, grid, shm, a, st);
+    case F32: return launch_site_p1(expr, S, nt, sched, block, grid, shm, a, st);
+    case F16: return launch_site_p2(expr, S, nt, sched, block, grid, shm, a, st);
+    case C12: return launch_site_p3(expr, S, nt, sched, block, grid, shm, a, st);
     }
     return hipErrorInvalidValue;
 }
@@ -142,28 +146,33 @@ hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
     return hipErrorInvalidValue;
 }
 
+template <int MODE, int NT, int SCHED>
+static void batch_go(const BatchItem *items, const BatchTile *tiles,
+                     int32_t ntiles, int block, int grid, size_t shm,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL((su3k::k_batch<MODE, NT, SCHED>), dim3(grid), dim3(block),
+                       shm, st, items, tiles, ntiles);
+}
+
 hipError_t launch_batch(int mode, const BatchItem *items,
                         const BatchTile *tiles, int32_t ntiles, int nt,
-                        int block, int grid, hipStream_t st)
+                        int sched, int block, int grid, size_t shm,
+                        hipStream_t st)
 {
-    using namespace su3k;
     if (block > 256)
         return hipErrorInvalidValue;
     const bool ntb = (nt & 3) == 3;
-    if (mode == 0) {
-        if (ntb)
-            hipLaunchKernelGGL((k_batch<0, 3>), dim3(grid), dim3(block), 0, st,
-                               items, tiles, ntiles);
-        else
-            hipLaunchKernelGGL((k_batch<0, 0>), dim3(grid), dim3(block), 0, st,
-                               items, tiles, ntiles);
-    } else {
-        if (ntb)
-            hipLaunchKernelGGL((k_batch<1, 3>), dim3(grid), dim3(block), 0, st,
-                               items, tiles, ntiles);
-        else
-            hipLaunchKernelGGL((k_batch<1, 0>), dim3(grid), dim3(block), 0, st,
-                               items, tiles, ntiles);
+    const int v = (mode ? 4 : 0) + (ntb ? 2 : 0) + (sched ? 1 : 0);
+    switch (v) {
+    case 0: batch_go<0, 0, 0>(items, tiles, ntiles, block, grid, shm, st); break;
+    case 1: batch_go<0, 0, 1>(items, tiles, ntiles, block, grid, shm, st); break;
+    case 2: batch_go<0, 3, 0>(items, tiles, ntiles, block, grid, shm, st); break;
+    case 3: batch_go<0, 3, 1>(items, tiles, ntiles, block, grid, shm, st); break;
+    case 4: batch_go<1, 0, 0>(items, tiles, ntiles, block, grid, shm, st); break;
+    case 5: batch_go<1, 0, 1>(items, tiles, ntiles, block, grid, shm, st); break;
+    case 6: batch_go<1, 3, 0>(items, tiles, ntiles, block, grid, shm, st); break;
+    default: batch_go<1, 3, 1>(items, tiles, ntiles, block, grid, shm, st); break;
     }
     return hipGetLastError();
 }

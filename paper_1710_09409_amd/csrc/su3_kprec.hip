@@ -23,12 +23,16 @@ namespace su3k {
 namespace SU3_CAT(p, SU3_PREC) {
 
 constexpr int P = SU3_PREC;
+constexpr int kMaxSiteBlock = 256;
 using R = typename PrecT<P>::R;
 using T = typename PrecT<P>::T;
 
-template <int X, int S, int NT, int MAXB>
-__global__ __launch_bounds__(MAXB) void k_site(su3i::SiteArgs a)
+template <int X, int S, int NT, int SCHED>
+__global__ __launch_bounds__(kMaxSiteBlock) void k_site(su3i::SiteArgs a)
 {
+    // Dynamic LDS is reserved only to cap how many workgroups share a CU
+    // (the launch's occupancy setting); it is never read.
+    extern __shared__ char occupancy_reserve[];
     const int nb = gridDim.x;
     const int b = a.xcd_remap ? xcd_remap(blockIdx.x, nb) : (int)blockIdx.x;
     const int B = blockDim.x;
@@ -38,10 +42,12 @@ __global__ __launch_bounds__(MAXB) void k_site(su3i::SiteArgs a)
         const uint32_t off = site_offset(a.g, s0);
         const int cnt = a.nsites - int(s0);
         if (cnt >= S)
-            do_group<P, X, S, NT, true>(a.z, ops, off, a.g.plane, S);
+            do_group<P, X, S, NT, true, SCHED>(a.z, ops, off, a.g.plane, S);
         else
-            do_group<P, X, S, NT, false>(a.z, ops, off, a.g.plane, cnt);
+            do_group<P, X, S, NT, false, SCHED>(a.z, ops, off, a.g.plane, cnt);
     }
+    if (a.nsites < 0)
+        occupancy_reserve[threadIdx.x] = 0;
 }
 
 // Copy `nbytes` bytes between global memory and LDS with the whole
@@ -123,9 +129,8 @@ __global__ __launch_bounds__(kLdsMaxBlock) void k_site_lds(su3i::SiteArgs a)
             R *site = reinterpret_cast<R *>(lds + t * REC);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                V2 v;
-                v[0] = (R)z[e].re;
-                v[1] = (R)z[e].im;
+                RawVec<P, 1> v;
+                narrow<P, 1>(v, 0, z[e]);
                 reinterpret_cast<V2 *>(site)[e] = v;
             }
         }
@@ -138,41 +143,44 @@ __global__ __launch_bounds__(kLdsMaxBlock) void k_site_lds(su3i::SiteArgs a)
 // ------------------------------------------------------------ dispatch
 
 template <int X, int S, int NT>
-static hipError_t run_site(int block, int grid, const su3i::SiteArgs &a,
-                           hipStream_t st)
+static hipError_t run_site(int sched, int block, int grid, size_t shm,
+                           const su3i::SiteArgs &a, hipStream_t st)
 {
-    if (block <= 256)
-        hipLaunchKernelGGL((k_site<X, S, NT, 256>), dim3(grid), dim3(block), 0,
+    if (block > kMaxSiteBlock)
+        return hipErrorInvalidValue;
+    if (sched)
+        hipLaunchKernelGGL((k_site<X, S, NT, 1>), dim3(grid), dim3(block), shm,
                            st, a);
     else
-        hipLaunchKernelGGL((k_site<X, S, NT, 1024>), dim3(grid), dim3(block),
-                           0, st, a);
+        hipLaunchKernelGGL((k_site<X, S, NT, 0>), dim3(grid), dim3(block), shm,
+                           st, a);
     return hipGetLastError();
 }
 
 template <int X, int S>
-static hipError_t pick_nt(int nt, int block, int grid,
+static hipError_t pick_nt(int nt, int sched, int block, int grid, size_t shm,
                           const su3i::SiteArgs &a, hipStream_t st)
 {
     switch (nt) {
-    case 0: return run_site<X, S, 0>(block, grid, a, st);
-    case 1: return run_site<X, S, 1>(block, grid, a, st);
-    case 2: return run_site<X, S, 2>(block, grid, a, st);
-    default: return run_site<X, S, 3>(block, grid, a, st);
+    case 0: return run_site<X, S, 0>(sched, block, grid, shm, a, st);
+    case 1: return run_site<X, S, 1>(sched, block, grid, shm, a, st);
+    case 2: return run_site<X, S, 2>(sched, block, grid, shm, a, st);
+    default: return run_site<X, S, 3>(sched, block, grid, shm, a, st);
     }
 }
 
 template <int X>
-static hipError_t pick_s(int S, int nt, int block, int grid,
-                         const su3i::SiteArgs &a, hipStream_t st)
+static hipError_t pick_s(int S, int nt, int sched, int block, int grid,
+                         size_t shm, const su3i::SiteArgs &a, hipStream_t st)
 {
     if constexpr (!Supported<P, X>::value) {
         return hipErrorInvalidValue;
     } else {
         if (S == 1)
-            return pick_nt<X, 1>(nt, block, grid, a, st);
+            return pick_nt<X, 1>(nt, sched, block, grid, shm, a, st);
         if (S == SitesPerLane<P, X>::value)
-            return pick_nt<X, SitesPerLane<P, X>::value>(nt, block, grid, a, st);
+            return pick_nt<X, SitesPerLane<P, X>::value>(nt, sched, block, grid,
+                                                         shm, a, st);
         return hipErrorInvalidValue;
     }
 }
@@ -204,17 +212,17 @@ static hipError_t run_lds(int nt, int block, int grid,
 namespace su3i {
 
 hipError_t SU3_CAT(launch_site_p, SU3_PREC)(int expr, int S, int nt,
-                                             int block, int grid,
-                                             const SiteArgs &a,
+                                             int sched, int block, int grid,
+                                             size_t shm, const SiteArgs &a,
                                              hipStream_t st)
 {
     using namespace su3k::SU3_CAT(p, SU3_PREC);
     switch (expr) {
-    case MUL: return pick_s<MUL>(S, nt, block, grid, a, st);
-    case MUL3: return pick_s<MUL3>(S, nt, block, grid, a, st);
-    case MULADD: return pick_s<MULADD>(S, nt, block, grid, a, st);
-    case ADD: return pick_s<ADD>(S, nt, block, grid, a, st);
-    case APB_AB: return pick_s<APB_AB>(S, nt, block, grid, a, st);
+    case MUL: return pick_s<MUL>(S, nt, sched, block, grid, shm, a, st);
+    case MUL3: return pick_s<MUL3>(S, nt, sched, block, grid, shm, a, st);
+    case MULADD: return pick_s<MULADD>(S, nt, sched, block, grid, shm, a, st);
+    case ADD: return pick_s<ADD>(S, nt, sched, block, grid, shm, a, st);
+    case APB_AB: return pick_s<APB_AB>(S, nt, sched, block, grid, shm, a, st);
     }
     return hipErrorInvalidValue;
 }

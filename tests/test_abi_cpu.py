@@ -102,16 +102,17 @@ def test_launch_table():
     su3.su3_launch_reset()
     d = su3.su3_launch_get(0, 0, 1, 0, dims)
     assert d.block in (64, 128, 256, 512, 1024)
-    cfg = dict(block=512, persistent=4, nontemporal=2, xcd_remap=0,
-               lds_stage=0, tile_sites=2048)
+    cfg = dict(block=128, persistent=4, nontemporal=2, xcd_remap=0,
+               lds_stage=0, tile_sites=2048, occupancy=3, schedule=1)
     su3.su3_launch_set(0, 0, 1, 0, dims, cfg)
     assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == cfg
     # same power-of-two volume bucket shares the setting
     assert su3.su3_launch_get(0, 0, 1, 0, (47, 48, 48, 48)).as_dict() == cfg
     # validation of settings
-    for bad in (dict(cfg, block=96), dict(cfg, nontemporal=4),
+    for bad in (dict(cfg, block=96), dict(cfg, block=512), dict(cfg, nontemporal=4),
                 dict(cfg, persistent=-1), dict(cfg, lds_stage=1),
-                dict(cfg, tile_sites=100), dict(cfg, xcd_remap=2)):
+                dict(cfg, tile_sites=100), dict(cfg, xcd_remap=2),
+                dict(cfg, occupancy=-1), dict(cfg, schedule=2)):
         assert _status(su3.su3_launch_set, 0, 0, 1, 0, dims, bad) == \
             su3.SU3_ERR_INVALID_ARG
     assert _status(su3.su3_launch_set, 0, 0, 0, 0, dims,

@@ -37,18 +37,18 @@ def _build(items, stream, tile_sites):
         zs.append(su3.field_tensor(dims, prec, lay, lanes))
         hosts.append(h)
         exprs.append(expr)
-        cfg = su3.su3_launch_get(expr, prec, lay, lanes, dims)
     return zs, ops, hosts, exprs
 
 
 @pytest.mark.parametrize("items", [ITEMS_MIXED, ITEMS_ANY], ids=["mixed", "any"])
-@pytest.mark.parametrize("tile", [64, 256, 4096])
-def test_batch_matches_unbatched(items, tile):
+@pytest.mark.parametrize("tile,pers,sched", [(64, 0, 1), (256, 2, 0), (4096, 0, 0),
+                                             (4096, 4, 1)])
+def test_batch_matches_unbatched(items, tile, pers, sched):
     s = torch.cuda.current_stream()
     dims0, prec0, lay0, lanes0, expr0 = items[0]
     total = sum(testgen.volume(d) for d, *_ in items)
     cfg = su3.su3_launch_get(expr0, prec0, lay0, lanes0, (total, 1, 1, 1))
-    cfg.tile_sites = tile
+    cfg.tile_sites, cfg.persistent, cfg.schedule = tile, pers, sched
     su3.su3_launch_set(expr0, prec0, lay0, lanes0, (total, 1, 1, 1), cfg)
     try:
         zs, ops, hosts, exprs = _build(items, s, tile)

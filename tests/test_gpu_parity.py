@@ -85,29 +85,30 @@ def test_layouts_bit_identical(prec):
 
 
 LAUNCHES = [dict(block=b, persistent=p, nontemporal=nt, xcd_remap=x,
-                 lds_stage=0, tile_sites=4096)
-            for b, p, nt, x in itertools.product((64, 256, 1024), (0, 1),
-                                                 (0, 1, 2, 3), (0, 1))]
+                 lds_stage=0, tile_sites=4096, occupancy=occ, schedule=sc)
+            for b, p, nt, x, occ, sc in itertools.product(
+                (64, 256), (0, 1), (0, 3), (0, 1), (0, 3), (0, 1))]
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=[PREC_NAMES[p] for p in PRECS])
 def test_launch_settings_bit_identical(prec):
     """Every launch setting (block, persistent grid-stride, nontemporal
-    bits, XCD remap) yields the same bits; the persistent grid of one
-    workgroup per CU exercises the grid-stride loop at 16^4."""
+    bits, XCD remap, occupancy cap, load/store schedule) yields the same
+    bits for every expression; the persistent grid of one workgroup per CU
+    exercises the grid-stride loop at 16^4."""
     dims = (16, 16, 16, 16)
     layout = su3.SU3_LAYOUT_SOA
-    expr = su3.SU3_EXPR_MUL
-    ops, want = _inputs_and_ref(prec, expr, dims)
-    base = None
     try:
-        for cfg in LAUNCHES:
-            su3.su3_launch_set(expr, prec, layout, 0, dims, cfg)
-            got, _ = run_expr(dims, prec, layout, 0, expr, ops)
-            if base is None:
-                base = got
-                assert_parity(prec, expr, got, want, f"launch {cfg}")
-            assert np.array_equal(got, base), cfg
+        for expr in exprs_for(prec):
+            ops, want = _inputs_and_ref(prec, expr, dims)
+            base = None
+            for cfg in LAUNCHES:
+                su3.su3_launch_set(expr, prec, layout, 0, dims, cfg)
+                got, _ = run_expr(dims, prec, layout, 0, expr, ops)
+                if base is None:
+                    base = got
+                    assert_parity(prec, expr, got, want, f"launch {cfg}")
+                assert np.array_equal(got, base), (expr, cfg)
     finally:
         su3.su3_launch_reset()
 
