@@ -67,6 +67,8 @@ def _bind(lib):
     lib.oracle_metrics.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = i32
+    lib.oracle_set_threads.argtypes = [i32]
+    lib.oracle_set_threads.restype = None
     return lib
 
 
@@ -92,6 +94,9 @@ class Oracle:
     def threads(self):
         """OpenMP threads of the oracle's site loops."""
         return int(self.lib.oracle_threads())
+
+    def set_threads(self, n):
+        self.lib.oracle_set_threads(int(n))
 
     def mult(self, x, y):
         """z(s) = x(s) y(s): the product written out, k ascending."""

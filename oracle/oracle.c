@@ -50,6 +50,17 @@ int oracle_threads(void)
 #endif
 }
 
+/* Set the thread count of later site loops (n <= 0: leave unchanged). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------ one site */
 
 /* 3x3 complex matrix as 18 doubles, entry (i,j) at 2*(3i+j) (+1 for im). */

@@ -185,10 +185,11 @@ static int one_shot_grid(int64_t items, int block)
     return (int)(g < 1 ? 1 : g);
 }
 
+// Yardsticks: one-shot grids of 64-lane workgroups stream best here.
 hipError_t launch_triad(double *a, const double *b, const double *c, double s,
                         int64_t n, hipStream_t st)
 {
-    const int block = 256;
+    const int block = 64;
     hipLaunchKernelGGL(su3k::k_triad<3>, dim3(one_shot_grid(n / 2, block)),
                        dim3(block), 0, st, a, b, c, s, n);
     return hipGetLastError();
@@ -197,7 +198,7 @@ hipError_t launch_triad(double *a, const double *b, const double *c, double s,
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,
                        hipStream_t st)
 {
-    const int block = 256;
+    const int block = 64;
     const int64_t n16 = (int64_t)(bytes / 16);
     hipLaunchKernelGGL(su3k::k_copy<3>, dim3(one_shot_grid(n16, block)),
                        dim3(block), 0, st, dst, src, n16);
