@@ -377,11 +377,10 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
         exprs.append(su3.SU3_EXPR_MUL)
         total_bytes += BYTES_PER_SITE[prec] * Vi
     total_sites = sum(testgen.volume(d) for d, _ in lat)
-    key_prec = zs[0].prec
     bcfg = None
     if not args.no_tune:
-        bcfg = tune_batch(su3, timer, stream, exprs, zs, ops, key_prec,
-                          total_sites)
+        bcfg = su3.su3_batch_autotune(exprs, zs, ops, stream).as_dict()
+        log(f"batch tune: {bcfg}")
     b = su3.su3_batch_create(exprs, zs, ops, stream)
     ms_b, _ = timer.run(lambda: su3.su3_batch_launch(b, stream), 100, 3)
     out["batch_64"] = {
@@ -389,33 +388,11 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
         "n_c12": sum(1 for _, c in lat if c),
         "us": round(ms_b * 1e3, 2),
         "gbps": round(total_bytes / (ms_b * 1e-3) / 1e9, 1),
-        "replays": 100, "tile_sites": (bcfg or {}).get("tile_sites")}
+        "replays": 100, "launch": bcfg}
     log(f"batch: {out['batch_64']}")
     su3.su3_batch_destroy(b)
     del zs, ops
     return out
-
-
-def tune_batch(su3, timer, stream, exprs, zs, ops, key_prec, total_sites):
-    """The batch's tile size and per-CU workgroups: time a small grid of
-    candidates (each a captured graph) and keep the fastest."""
-    best, best_ms = None, 1e30
-    key = (exprs[0], key_prec, zs[0].layout, zs[0].lanes, (total_sites, 1, 1, 1))
-    base = su3.su3_launch_get(*key).as_dict()
-    for tile in (1024, 2048, 4096, 8192, 16384):
-        for per_cu in (4, 8, 16):
-            for nt in (0, 3):
-                cfg = dict(base, tile_sites=tile, persistent=per_cu, block=256,
-                           nontemporal=nt, xcd_remap=0, lds_stage=0)
-                su3.su3_launch_set(*key, cfg)
-                b = su3.su3_batch_create(exprs, zs, ops, stream)
-                ms, _ = timer.run(lambda: su3.su3_batch_launch(b, stream), 10, 2)
-                su3.su3_batch_destroy(b)
-                if ms < best_ms:
-                    best, best_ms = cfg, ms
-    su3.su3_launch_set(*key, best)
-    log(f"batch tune: {best} {best_ms * 1e3:.1f} us")
-    return best
 
 
 def cpu_baseline(x, y):

@@ -231,6 +231,18 @@ su3_status su3_autotune(su3_expr expr, su3_precision prec, su3_layout layout,
                         int32_t lanes, const int32_t dims[4], void *stream,
                         su3_launch *best);
 
+/* Autotune a batch: build the batch with each candidate launch (tile size,
+ * one workgroup per tile or k per CU, occupancy cap, schedule, nontemporal
+ * bits), time graph replays (median of 5 after 2), and keep the fastest for
+ * later su3_batch_create calls on items of the same leading (expr,
+ * precision, layout, lanes) and total-volume bucket.  Arguments as for
+ * su3_batch_create.  The candidates write the items' outputs (with the
+ * correct values).  Persists in SU3_TUNE_CACHE like su3_autotune.  `best`
+ * may be NULL. */
+su3_status su3_batch_autotune(const su3_expr *exprs, su3_field *const *z,
+                              const su3_field *const *ops, int32_t n,
+                              void *stream, su3_launch *best);
+
 /* Launch settings used for a key (tuned, set, or the built-in default). */
 su3_status su3_launch_get(su3_expr expr, su3_precision prec,
                           su3_layout layout, int32_t lanes,

@@ -44,7 +44,8 @@ SYMBOLS = (
     "su3_field_data", "su3_field_upload", "su3_field_download",
     "su3_field_download_raw", "su3_mult", "su3_fused_eval",
     "su3_batch_create", "su3_batch_launch", "su3_batch_destroy",
-    "su3_batch_tiles", "su3_autotune", "su3_launch_get", "su3_launch_set",
+    "su3_batch_tiles", "su3_autotune", "su3_batch_autotune", "su3_launch_get",
+    "su3_launch_set",
     "su3_launch_reset", "su3_triad", "su3_copy", "su3_sync",
     "su3_status_string", "su3_last_error",
 )
@@ -115,6 +116,7 @@ def load():
         "su3_batch_destroy": [vp],
         "su3_batch_tiles": [vp, vp, i64, ctypes.POINTER(i64)],
         "su3_autotune": [i32, i32, i32, i32, dims_t, vp, L],
+        "su3_batch_autotune": [vp, vp, vp, i32, vp, L],
         "su3_launch_get": [i32, i32, i32, i32, dims_t, L],
         "su3_launch_set": [i32, i32, i32, i32, dims_t, L],
         "su3_launch_reset": [],
@@ -294,18 +296,30 @@ class Batch:
 
 def su3_batch_create(exprs, zs, ops, stream=None):
     """exprs[i], zs[i] and ops[i] (a list of operand Fields) per item."""
+    n, ex, zz, oo = _batch_args(exprs, zs, ops)
+    h = ctypes.c_void_p()
+    _check("su3_batch_create",
+           load().su3_batch_create(ctypes.byref(h), ex, zz, oo, n, _stream(stream)))
+    return Batch(h.value, (list(zs), [list(o) for o in ops]))
+
+
+def _batch_args(exprs, zs, ops):
     n = len(exprs)
     ex = (ctypes.c_int32 * n)(*exprs)
     zz = (ctypes.c_void_p * n)(*[z.handle for z in zs])
     flat = []
     for o in ops:
-        row = [f.handle for f in o] + [None] * (4 - len(o))
-        flat.extend(row)
+        flat.extend([f.handle for f in o] + [None] * (4 - len(o)))
     oo = (ctypes.c_void_p * (4 * n))(*flat)
-    h = ctypes.c_void_p()
-    _check("su3_batch_create",
-           load().su3_batch_create(ctypes.byref(h), ex, zz, oo, n, _stream(stream)))
-    return Batch(h.value, (list(zs), [list(o) for o in ops]))
+    return n, ex, zz, oo
+
+
+def su3_batch_autotune(exprs, zs, ops, stream=None):
+    n, ex, zz, oo = _batch_args(exprs, zs, ops)
+    best = su3_launch()
+    _check("su3_batch_autotune",
+           load().su3_batch_autotune(ex, zz, oo, n, _stream(stream), ctypes.byref(best)))
+    return best
 
 
 def su3_batch_launch(b: Batch, stream=None):

@@ -934,10 +934,9 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
 
 // ------------------------------------------------------------ batches
 
-extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
-                                       su3_field *const *z,
-                                       const su3_field *const *ops, int32_t n,
-                                       void *stream)
+static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
+                               su3_field *const *z, const su3_field *const *ops,
+                               int32_t n, void *stream, const su3_launch *forced)
 {
     if (!out || !exprs || !z || !ops)
         return fail(SU3_ERR_INVALID_ARG, "NULL argument");
@@ -980,11 +979,12 @@ extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
             mode = 1;
         total_sites += z[i]->V;
     }
-    // tile size: the tuned value for the dominant item, else the default
-    const su3_launch c =
-        lookup_launch(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
-                      total_sites);
-    su3_launch cfg = c;
+    // launch: forced by the autotuner, else the tuned (or default) setting
+    // of the leading item's key at the batch's total volume
+    const su3_launch cfg =
+        forced ? *forced
+               : lookup_launch(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
+                               total_sites);
     const int T = cfg.tile_sites;
     std::vector<BatchTile> tiles;
     for (int i = 0; i < n; ++i) {
@@ -1053,6 +1053,14 @@ extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
     return SU3_OK;
 }
 
+extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
+                                       su3_field *const *z,
+                                       const su3_field *const *ops, int32_t n,
+                                       void *stream)
+{
+    return batch_create(out, exprs, z, ops, n, stream, nullptr);
+}
+
 extern "C" su3_status su3_batch_launch(su3_batch *b, void *stream)
 {
     if (!b)
@@ -1075,6 +1083,72 @@ extern "C" su3_status su3_batch_destroy(su3_batch *b)
     if (b->d_tiles)
         (void)hipFree(b->d_tiles);
     delete b;
+    return SU3_OK;
+}
+
+// Candidate launches of the batch autotuner.
+static std::vector<su3_launch> batch_candidates()
+{
+    std::vector<su3_launch> out;
+    su3_launch c;
+    c.xcd_remap = 0;
+    c.lds_stage = 0;
+    c.nontemporal = 3;
+    for (int tile : {128, 512, 2048, 8192})
+        for (int pers : {0, 8})
+            for (int occ : {0, 4, 6})
+                for (int sched : {0, 1}) {
+                    c.tile_sites = tile;
+                    c.persistent = pers;
+                    c.block = pers ? 256 : 64;
+                    c.occupancy = occ;
+                    c.schedule = sched;
+                    out.push_back(c);
+                }
+    return out;
+}
+
+extern "C" su3_status su3_batch_autotune(const su3_expr *exprs,
+                                         su3_field *const *z,
+                                         const su3_field *const *ops,
+                                         int32_t n, void *stream,
+                                         su3_launch *best)
+{
+    if (!exprs || !z || !ops || n <= 0 || !z[0])
+        return fail(SU3_ERR_INVALID_ARG, "NULL argument or empty batch");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i)
+        if (z[i])
+            total += z[i]->V;
+    su3_launch win = default_launch(exprs[0], z[0]->prec, z[0]->layout);
+    double win_us = 1e300;
+    for (const su3_launch &c : batch_candidates()) {
+        su3_batch *b = nullptr;
+        su3_status st = batch_create(&b, exprs, z, ops, n, stream, &c);
+        if (st != SU3_OK)
+            return st;  // invalid items: report, nothing tuned
+        double us = 0;
+        st = time_launch([&]() { return su3_batch_launch(b, stream); }, hs, 2,
+                         5, &us);
+        su3_batch_destroy(b);
+        if (st != SU3_OK)
+            return st;
+        if (us < win_us) {
+            win_us = us;
+            win = c;
+        }
+    }
+    const Key k(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
+                vbucket(total));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache_locked();
+        g_tuned[k] = win;
+    }
+    append_cache(k, win, win_us);
+    if (best)
+        *best = win;
     return SU3_OK;
 }
 

@@ -90,3 +90,24 @@ def test_batch_rejects_bad_items():
     with pytest.raises(su3.Su3Error) as e:
         su3.su3_batch_create([su3.SU3_EXPR_MUL], [b], [[b, c]], s)
     assert e.value.status == su3.SU3_ERR_MISMATCH
+
+
+def test_batch_autotune_then_create():
+    """The batch autotuner's candidates all run; the batch created after it
+    (with the tuned launch) matches unbatched launches bit for bit."""
+    s = torch.cuda.current_stream()
+    try:
+        zs, ops, hosts, exprs = _build(ITEMS_MIXED, s, 0)
+        best = su3.su3_batch_autotune(exprs, zs, ops, s)
+        assert best.tile_sites % 64 == 0
+        b = su3.su3_batch_create(exprs, zs, ops, s)
+        for z in zs:
+            z.owner.fill_(7)
+        su3.su3_batch_launch(b, s)
+        su3.su3_sync(s)
+        for (dims, prec, lay, lanes, expr), h, z in zip(ITEMS_MIXED, hosts, zs):
+            single, _ = run_expr(dims, prec, lay, lanes, expr, h)
+            assert np.array_equal(su3.su3_field_download(z, s), single)
+        su3.su3_batch_destroy(b)
+    finally:
+        su3.su3_launch_reset()
