@@ -330,6 +330,21 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
                      "working_set_bytes": 432 * V, "cache_resident": False}
     out["sweep_f64_soa"] = sweep
 
+    # shifted operands at 48^4 (FP64 SoA): Cshift moves 288 B/site, the
+    # product with a shifted operand 432 B/site
+    shift = {}
+    for mu in range(4):
+        ms_c, _ = timer.run(lambda: su3.su3_cshift(z64, y64, mu, 1, stream), steps, 3)
+        ms_m, _ = timer.run(lambda: su3.su3_mult_shifted(z64, x64, y64, mu, 1, stream),
+                            steps, 3)
+        shift[f"mu{mu}"] = {
+            "cshift_us": round(ms_c * 1e3, 2),
+            "cshift_gbps": round(288 * V / (ms_c * 1e-3) / 1e9, 1),
+            "mult_shifted_us": round(ms_m * 1e3, 2),
+            "mult_shifted_gbps": round(432 * V / (ms_m * 1e-3) / 1e9, 1)}
+        log(f"shift mu {mu}: {shift[f'mu{mu}']}")
+    out["shift_f64_48^4"] = shift
+
     # fused vs chained at 32^4 with four link fields
     d = (32, 32, 32, 32)
     Vf = testgen.volume(d)
@@ -383,11 +398,23 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
         log(f"batch tune: {bcfg}")
     b = su3.su3_batch_create(exprs, zs, ops, stream)
     ms_b, _ = timer.run(lambda: su3.su3_batch_launch(b, stream), 100, 3)
+
+    # the same 64 products as 64 back-to-back launches (tuned per shape)
+    for i, (d, comp) in enumerate(lat):
+        prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
+        tune(su3.SU3_EXPR_MUL, prec, SOA, 0, d)
+
+    def unbatched():
+        for i in range(64):
+            su3.su3_mult(zs[i], ops[i][0], ops[i][1], stream)
+    ms_u, _ = timer.run(unbatched, 20, 2)
     out["batch_64"] = {
         "lattices": 64, "sites": total_sites, "bytes": total_bytes,
         "n_c12": sum(1 for _, c in lat if c),
         "us": round(ms_b * 1e3, 2),
         "gbps": round(total_bytes / (ms_b * 1e-3) / 1e9, 1),
+        "unbatched_us": round(ms_u * 1e3, 2),
+        "unbatched_gbps": round(total_bytes / (ms_u * 1e-3) / 1e9, 1),
         "replays": 100, "launch": bcfg}
     log(f"batch: {out['batch_64']}")
     su3.su3_batch_destroy(b)

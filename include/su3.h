@@ -192,6 +192,26 @@ su3_status su3_fused_eval(su3_field *z, su3_expr expr,
                           const su3_field *const *ops, int32_t n_ops,
                           void *stream);
 
+/* --------------------------------------------------- shifted operands */
+
+/* dst(x) = src(x + shift * mu_hat) at every site, periodic in direction mu
+ * (0..3 = x, y, z, t; site index x + Lx(y + Ly(z + Lz t))): the lattice
+ * shift (Cshift) that the paper's outlook (Section 6) names as the routine
+ * outside the expression engine that a stencil port needs.  Any integer
+ * shift; dst and src share dims, precision, layout and lanes
+ * (SU3_ERR_MISMATCH) and must not overlap at all (SU3_ERR_ALIAS: a shift
+ * is a gather and cannot run in place). */
+su3_status su3_cshift(su3_field *dst, const su3_field *src, int32_t mu,
+                      int32_t shift, void *stream);
+
+/* z(x) = x(x) * y(x + shift * mu_hat), periodic, in one kernel without an
+ * intermediate shifted field.  z may be x exactly; z must not overlap y
+ * (SU3_ERR_ALIAS).  The compressed form rebuilds the shifted operand's
+ * third row in registers. */
+su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
+                            const su3_field *y, int32_t mu, int32_t shift,
+                            void *stream);
+
 /* ------------------------------------------------------------ batches */
 
 /* A batch evaluates n independent (expr, z, operands) items -- fields of

@@ -67,6 +67,8 @@ def _bind(lib):
     lib.oracle_metrics.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = i32
+    lib.oracle_cshift.argtypes = [vp, vp, vp, i32, i64]
+    lib.oracle_cshift.restype = i32
     lib.oracle_set_threads.argtypes = [i32]
     lib.oracle_set_threads.restype = None
     return lib
@@ -119,6 +121,20 @@ class Oracle:
                                    self._p(z), V)
         assert rc == 0
         return z
+
+    def cshift(self, a, dims, mu, shift):
+        """b(c) = a(c + shift * mu_hat), periodic."""
+        a = self._field(a)
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+        assert a.shape[0] == int(np.prod(d))
+        out = np.empty_like(a)
+        rc = self.lib.oracle_cshift(self._p(a), self._p(out), self._p(d), mu, shift)
+        assert rc == 0
+        return out
+
+    def mult_shifted(self, x, y, dims, mu, shift):
+        """z(c) = x(c) * y(c + shift * mu_hat)."""
+        return self.mult(x, self.cshift(y, dims, mu, shift))
 
     def quant_f32(self, a):
         a = np.ascontiguousarray(a, dtype=np.float64)

@@ -144,6 +144,34 @@ int oracle_fused(int expr, const double *a, const double *b, const double *c,
     return 0;
 }
 
+/* ------------------------------------------------------- shifted fields */
+
+/* dst(c) = src(c + shift * mu_hat) with periodic wrap in direction mu, for
+ * every site coordinate c = (x, y, z, t); site index x + Lx(y + Ly(z + Lz t)).
+ * The lattice-wide shift of the paper's outlook (Section 6, Cshift).
+ * Returns -1 for a bad direction or extent. */
+int oracle_cshift(const double *src, double *dst, const int32_t dims[4],
+                  int mu, int64_t shift)
+{
+    if (mu < 0 || mu > 3)
+        return -1;
+    for (int d = 0; d < 4; ++d)
+        if (dims[d] <= 0)
+            return -1;
+    int64_t c[4];
+    for (c[3] = 0; c[3] < dims[3]; ++c[3])
+        for (c[2] = 0; c[2] < dims[2]; ++c[2])
+            for (c[1] = 0; c[1] < dims[1]; ++c[1])
+                for (c[0] = 0; c[0] < dims[0]; ++c[0]) {
+                    int64_t n[4] = {c[0], c[1], c[2], c[3]};
+                    n[mu] = ((c[mu] + shift) % dims[mu] + dims[mu]) % dims[mu];
+                    int64_t s = c[0] + dims[0] * (c[1] + dims[1] * (c[2] + dims[2] * c[3]));
+                    int64_t t = n[0] + dims[0] * (n[1] + dims[1] * (n[2] + dims[2] * n[3]));
+                    memcpy(dst + 18 * s, src + 18 * t, 18 * sizeof(double));
+                }
+    return 0;
+}
+
 /* ------------------------------------------------------ half precision */
 
 /* IEEE binary32 -> binary16, round to nearest, ties to even, subnormals

@@ -42,7 +42,8 @@ N_OPERANDS = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}
 SYMBOLS = (
     "su3_field_bytes", "su3_field_alloc", "su3_field_wrap", "su3_field_free",
     "su3_field_data", "su3_field_upload", "su3_field_download",
-    "su3_field_download_raw", "su3_mult", "su3_fused_eval",
+    "su3_field_download_raw", "su3_mult", "su3_fused_eval", "su3_cshift",
+    "su3_mult_shifted",
     "su3_batch_create", "su3_batch_launch", "su3_batch_destroy",
     "su3_batch_tiles", "su3_autotune", "su3_batch_autotune", "su3_launch_get",
     "su3_launch_set",
@@ -111,6 +112,8 @@ def load():
         "su3_field_download_raw": [vp, vp, sz, vp],
         "su3_mult": [vp, vp, vp, vp],
         "su3_fused_eval": [vp, i32, vp, i32, vp],
+        "su3_cshift": [vp, vp, i32, i32, vp],
+        "su3_mult_shifted": [vp, vp, vp, i32, i32, vp],
         "su3_batch_create": [pp, vp, vp, vp, i32, vp],
         "su3_batch_launch": [vp, vp],
         "su3_batch_destroy": [vp],
@@ -279,6 +282,17 @@ def su3_fused_eval(z: Field, expr, ops, stream=None):
     _check("su3_fused_eval",
            load().su3_fused_eval(z.handle if z is not None else None, expr, arr,
                                  len(ops), _stream(stream)))
+
+
+def su3_cshift(dst: Field, src: Field, mu, shift, stream=None):
+    _check("su3_cshift", load().su3_cshift(dst.handle, src.handle, int(mu),
+                                           int(shift), _stream(stream)))
+
+
+def su3_mult_shifted(z: Field, x: Field, y: Field, mu, shift, stream=None):
+    _check("su3_mult_shifted",
+           load().su3_mult_shifted(z.handle, x.handle, y.handle, int(mu),
+                                   int(shift), _stream(stream)))
 
 
 # --------------------------------------------------------------- batches

@@ -716,6 +716,73 @@ extern "C" su3_status su3_mult(su3_field *z, const su3_field *x,
     return su3_fused_eval(z, SU3_EXPR_MUL, ops, 2, stream);
 }
 
+// ----------------------------------------------------- shifted operands
+
+// Launch of the shifted-operand kernels: 64-lane workgroups, one-shot grid,
+// at most 5 workgroups per CU, nontemporal loads and stores -- the setting
+// the autotuner settles on for the unshifted product.
+static su3_status launch_shift_op(int mode, su3_field *z, const su3_field *x,
+                                  const su3_field *y, int32_t mu,
+                                  int32_t shift, void *stream)
+{
+    ShiftArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.z = z->ptr;
+    a.x = x ? x->ptr : nullptr;
+    a.y = y->ptr;
+    a.g = geom_of(z);
+    a.nsites = (int32_t)z->V;
+    int64_t stride = 1;
+    for (int d = 0; d < mu; ++d)
+        stride *= z->dims[d];
+    const int64_t L = z->dims[mu];
+    a.stride = (uint32_t)stride;
+    a.extent = (uint32_t)L;
+    a.shift = (uint32_t)(((int64_t)shift % L + L) % L);
+    const int block = 64;
+    const int64_t grid = (z->V + block - 1) / block;
+    hipError_t e = launch_shift(z->prec, mode, 3, block, (int)grid,
+                                occupancy_reserve(z->device, 5), a,
+                                static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "shift kernel launch");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_cshift(su3_field *dst, const su3_field *src,
+                                 int32_t mu, int32_t shift, void *stream)
+{
+    if (!dst || !src)
+        return fail(SU3_ERR_INVALID_ARG, "field is NULL");
+    if (mu < 0 || mu > 3)
+        return fail(SU3_ERR_INVALID_ARG, "direction %d not in [0, 3]", mu);
+    if (!same_shape(dst, src))
+        return fail(SU3_ERR_MISMATCH, "dst and src differ in dims, precision, "
+                                      "layout, lanes or device");
+    if (overlaps(dst, src))
+        return fail(SU3_ERR_ALIAS, "dst overlaps src (a shift is a gather: "
+                                   "it cannot run in place)");
+    return launch_shift_op(0, dst, nullptr, src, mu, shift, stream);
+}
+
+extern "C" su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
+                                       const su3_field *y, int32_t mu,
+                                       int32_t shift, void *stream)
+{
+    if (!z || !x || !y)
+        return fail(SU3_ERR_INVALID_ARG, "field is NULL");
+    if (mu < 0 || mu > 3)
+        return fail(SU3_ERR_INVALID_ARG, "direction %d not in [0, 3]", mu);
+    if (!same_shape(z, x) || !same_shape(z, y))
+        return fail(SU3_ERR_MISMATCH, "operands differ in dims, precision, "
+                                      "layout, lanes or device");
+    if (overlaps(z, y))
+        return fail(SU3_ERR_ALIAS, "z overlaps the shifted operand y");
+    if (overlaps(z, x) && !(z->ptr == x->ptr && z->bytes == x->bytes))
+        return fail(SU3_ERR_ALIAS, "z partially overlaps x");
+    return launch_shift_op(1, z, x, y, mu, shift, stream);
+}
+
 // ------------------------------------------------------- launch tuning
 
 static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,

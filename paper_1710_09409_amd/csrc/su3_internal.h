@@ -52,6 +52,20 @@ struct SiteArgs {
     int32_t xcd_remap;
 };
 
+// Arguments of the shifted-operand kernels: the operand y is read at the
+// neighbour s' of site s along one direction, s' = s + (c' - c) * stride
+// with c = (s / stride) % extent and c' = (c + shift) % extent.
+struct ShiftArgs {
+    void *z;
+    const void *x;   // unshifted left operand (product only)
+    const void *y;   // shifted operand
+    Geom g;
+    int32_t nsites;
+    uint32_t stride;  // sites between neighbours along the direction
+    uint32_t extent;  // lattice extent along the direction
+    uint32_t shift;   // in [0, extent)
+};
+
 // One item of a batched launch (device-resident table).
 struct BatchItem {
     void *z;
@@ -91,6 +105,9 @@ hipError_t launch_batch(int mode, const BatchItem *items,
                         const BatchTile *tiles, int32_t ntiles, int nt,
                         int sched, int block, int grid, size_t shm,
                         hipStream_t stream);
+// mode 0: z(s) = y(s'); mode 1: z(s) = x(s) * y(s').  One site per lane.
+hipError_t launch_shift(int prec, int mode, int nt, int block, int grid,
+                        size_t shm, const ShiftArgs &a, hipStream_t stream);
 hipError_t launch_triad(double *a, const double *b, const double *c,
                         double s, int64_t n, hipStream_t stream);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,

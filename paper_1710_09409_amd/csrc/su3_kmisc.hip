@@ -7,6 +7,10 @@ hipError_t launch_site_p0(int, int, int, int, int, int, size_t, const SiteArgs &
 hipError_t launch_site_p1(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
 hipError_t launch_site_p2(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
 hipError_t launch_site_p3(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
+hipError_t launch_shift_p0(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
+hipError_t launch_shift_p1(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
+hipError_t launch_shift_p2(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
+hipError_t launch_shift_p3(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
 hipError_t launch_site_lds_p0(int, int, int, int, const SiteArgs &, hipStream_t);
 hipError_t launch_site_lds_p1(int, int, int, int, const SiteArgs &, hipStream_t);
 hipError_t launch_site_lds_p2(int, int, int, int, const SiteArgs &, hipStream_t);
@@ -130,6 +134,18 @@ hipError_t launch_site(int prec, int expr, int S, int nt, int sched, int block,
     case F32: return launch_site_p1(expr, S, nt, sched, block, grid, shm, a, st);
     case F16: return launch_site_p2(expr, S, nt, sched, block, grid, shm, a, st);
     case C12: return launch_site_p3(expr, S, nt, sched, block, grid, shm, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_shift(int prec, int mode, int nt, int block, int grid,
+                        size_t shm, const ShiftArgs &a, hipStream_t st)
+{
+    switch (prec) {
+    case F64: return launch_shift_p0(mode, nt, block, grid, shm, a, st);
+    case F32: return launch_shift_p1(mode, nt, block, grid, shm, a, st);
+    case F16: return launch_shift_p2(mode, nt, block, grid, shm, a, st);
+    case C12: return launch_shift_p3(mode, nt, block, grid, shm, a, st);
     }
     return hipErrorInvalidValue;
 }

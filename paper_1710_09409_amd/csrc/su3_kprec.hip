@@ -50,6 +50,54 @@ __global__ __launch_bounds__(kMaxSiteBlock) void k_site(su3i::SiteArgs a)
         occupancy_reserve[threadIdx.x] = 0;
 }
 
+// Shifted operand (Cshift and products with a shifted right operand), one
+// site per lane: the lane of site s reads y at the neighbour s' of s along
+// one direction, periodic.  Consecutive lanes read consecutive sites of
+// the neighbouring row/plane, so the gather stays coalesced except at the
+// wrap of the shifted coordinate.
+template <int MODE, int NT>
+__global__ __launch_bounds__(kMaxSiteBlock) void k_shift(su3i::ShiftArgs a)
+{
+    extern __shared__ char occupancy_reserve[];
+    constexpr int E = PrecT<P>::E;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < (uint32_t)a.nsites) {
+        const uint32_t c = (s / a.stride) % a.extent;
+        uint32_t cn = c + a.shift;
+        if (cn >= a.extent)
+            cn -= a.extent;
+        const uint32_t sn = s + (cn - c) * a.stride;  // modulo 2^32, in range
+        const uint32_t off = site_offset(a.g, s);
+        const uint32_t offn = site_offset(a.g, sn);
+        RawVec<P, 1> yr[E];
+        load_entries<P, 1, NT, true, 0, E>(static_cast<const R *>(a.y), offn,
+                                           a.g.plane, 1, yr);
+        if constexpr (MODE == 0) {
+            store_entries<P, 1, NT, true, 0, E>(static_cast<R *>(a.z), off,
+                                                a.g.plane, 1, yr);
+        } else {
+            RawVec<P, 1> xr[E];
+            load_entries<P, 1, NT, true, 0, E>(static_cast<const R *>(a.x), off,
+                                               a.g.plane, 1, xr);
+            Cx<T> o[2][9], z[9];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                o[0][e] = widen<P, 1>(xr[e], 0);
+                o[1][e] = widen<P, 1>(yr[e], 0);
+            }
+            eval_site<P, su3i::MUL>(o, z);
+            RawVec<P, 1> zr[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                narrow<P, 1>(zr[e], 0, z[e]);
+            store_entries<P, 1, NT, true, 0, E>(static_cast<R *>(a.z), off,
+                                                a.g.plane, 1, zr);
+        }
+    }
+    if (a.nsites < 0)
+        occupancy_reserve[threadIdx.x] = 0;
+}
+
 // Copy `nbytes` bytes between global memory and LDS with the whole
 // workgroup: 16-byte pieces when the count allows, else 4-byte pieces
 // (every stored site is a multiple of 4 bytes).
@@ -225,6 +273,24 @@ hipError_t SU3_CAT(launch_site_p, SU3_PREC)(int expr, int S, int nt,
     case APB_AB: return pick_s<APB_AB>(S, nt, sched, block, grid, shm, a, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t SU3_CAT(launch_shift_p, SU3_PREC)(int mode, int nt, int block,
+                                              int grid, size_t shm,
+                                              const ShiftArgs &a,
+                                              hipStream_t st)
+{
+    using namespace su3k::SU3_CAT(p, SU3_PREC);
+    if (block > kMaxSiteBlock)
+        return hipErrorInvalidValue;
+    const int v = (mode ? 2 : 0) + ((nt & 3) == 3 ? 1 : 0);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_shift<0, 0>), dim3(grid), dim3(block), shm, st, a); break;
+    case 1: hipLaunchKernelGGL((k_shift<0, 3>), dim3(grid), dim3(block), shm, st, a); break;
+    case 2: hipLaunchKernelGGL((k_shift<1, 0>), dim3(grid), dim3(block), shm, st, a); break;
+    default: hipLaunchKernelGGL((k_shift<1, 3>), dim3(grid), dim3(block), shm, st, a); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t SU3_CAT(launch_site_lds_p, SU3_PREC)(int expr, int nt, int block,

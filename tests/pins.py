@@ -332,9 +332,56 @@ def pin_metrics(orc):
     assert m3["d_u"] < 1e-15 and abs(m3["d_det"] - np.sqrt(2.0)) < 1e-15
 
 
+# ------------------------------------------------------- shifted fields
+
+def _coord_field(dims):
+    """A field whose site (x,y,z,t) holds the diagonal matrix
+    diag(x, y, z) + i t: each coordinate readable from the value."""
+    V = int(np.prod(dims))
+    f = np.zeros((V, 3, 3, 2))
+    idx = np.arange(V)
+    x = idx % dims[0]
+    y = (idx // dims[0]) % dims[1]
+    z = (idx // (dims[0] * dims[1])) % dims[2]
+    t = idx // (dims[0] * dims[1] * dims[2])
+    f[:, 0, 0, 0], f[:, 1, 1, 0], f[:, 2, 2, 0] = x, y, z
+    f[:, 0, 0, 1] = t
+    return f, (x, y, z, t)
+
+
+def pin_cshift(orc):
+    """Shifting a coordinate-valued field by k along mu reads the value of
+    the site whose mu coordinate is (c_mu + k) mod L_mu (closed form);
+    shifting by L_mu is the identity; +k then -k is the identity; shifts in
+    different directions commute (numpy.roll along the lattice axes as a
+    library check)."""
+    dims = (3, 4, 5, 2)
+    f, coords = _coord_field(dims)
+    for mu in range(4):
+        for k in (1, -1, 2, dims[mu], -3):
+            g = orc.cshift(f, dims, mu, k)
+            want = [c.copy() for c in coords]
+            want[mu] = (coords[mu] + k) % dims[mu]
+            assert np.array_equal(g[:, 0, 0, 0], want[0]), (mu, k)
+            assert np.array_equal(g[:, 1, 1, 0], want[1]), (mu, k)
+            assert np.array_equal(g[:, 2, 2, 0], want[2]), (mu, k)
+            assert np.array_equal(g[:, 0, 0, 1], want[3]), (mu, k)
+    u = testgen.su3_field(int(np.prod(dims)), field_id=34)
+    assert np.array_equal(orc.cshift(u, dims, 2, dims[2]), u)
+    assert np.array_equal(orc.cshift(orc.cshift(u, dims, 1, 1), dims, 1, -1), u)
+    a = orc.cshift(orc.cshift(u, dims, 0, 1), dims, 3, -1)
+    b = orc.cshift(orc.cshift(u, dims, 3, -1), dims, 0, 1)
+    assert np.array_equal(a, b)
+    # numpy.roll on the (t, z, y, x) array: shift by +k reads c + k
+    arr = u.reshape(dims[3], dims[2], dims[1], dims[0], 3, 3, 2)
+    for mu in range(4):
+        want = np.roll(arr, -1, axis=3 - mu).reshape(u.shape)
+        assert np.array_equal(orc.cshift(u, dims, mu, 1), want), mu
+
+
 ALL_PINS = [pin_identity, pin_phase_diag, pin_signed_permutations,
             pin_unitary_inverse, pin_numpy_matmul, pin_nonsymmetric,
             pin_product_invariants, pin_associative, pin_listing2,
             pin_fused_reductions, pin_fused_numpy, pin_fused_unitary,
             pin_quantisers, pin_c12_rebuild, pin_layouts, pin_roundtrip,
-            pin_metrics]
+            pin_metrics, pin_cshift]

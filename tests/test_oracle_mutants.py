@@ -30,6 +30,10 @@ MUTANTS = [
      "double v = s < V ? canon[18 * s + 2 * e + (1 - c)] : 0.0;"),
     ("soa_no_pad", "*Vpad = (V + 63) / 64 * 64;", "*Vpad = V;"),
     ("metrics_no_delta", "if (i == j)\n                    re -= 1.0;", ""),
+    ("cshift_sign", "n[mu] = ((c[mu] + shift) % dims[mu] + dims[mu]) % dims[mu];",
+     "n[mu] = ((c[mu] - shift) % dims[mu] + dims[mu]) % dims[mu];"),
+    ("cshift_no_wrap", "n[mu] = ((c[mu] + shift) % dims[mu] + dims[mu]) % dims[mu];",
+     "n[mu] = (c[mu] + shift < dims[mu] && c[mu] + shift >= 0) ? c[mu] + shift : c[mu];"),
     ("det_sign", "r += re_(m, 0, j) * cr - im_(m, 0, j) * ci;",
      "r += re_(m, 0, j) * cr + im_(m, 0, j) * ci;"),
 ]
