@@ -333,6 +333,8 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
     # shifted operands at 48^4 (FP64 SoA): Cshift moves 288 B/site, the
     # product with a shifted operand 432 B/site
     shift = {}
+    tune(su3.SU3_EXPR_CSHIFT, su3.SU3_F64, SOA, 0, dims)
+    tune(su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_F64, SOA, 0, dims)
     for mu in range(4):
         ms_c, _ = timer.run(lambda: su3.su3_cshift(z64, y64, mu, 1, stream), steps, 3)
         ms_m, _ = timer.run(lambda: su3.su3_mult_shifted(z64, x64, y64, mu, 1, stream),

@@ -93,7 +93,11 @@ typedef enum su3_expr {
     SU3_EXPR_MUL3 = 1,
     SU3_EXPR_MULADD = 2,
     SU3_EXPR_ADD = 3,
-    SU3_EXPR_APB_AB = 4
+    SU3_EXPR_APB_AB = 4,
+    /* launch-tuning keys of su3_cshift and su3_mult_shifted (accepted by
+     * su3_autotune / su3_launch_get / su3_launch_set only) */
+    SU3_EXPR_CSHIFT = 5,
+    SU3_EXPR_MUL_SHIFTED = 6
 } su3_expr;
 
 typedef struct su3_field su3_field;
@@ -238,6 +242,9 @@ su3_status su3_batch_destroy(su3_batch *b);
  * `*n_tiles` receives the tile count; rows are written when cap >= it. */
 su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows, int64_t cap,
                            int64_t *n_tiles);
+/* (The kernel itself holds only each item's first tile index and the tile
+ * size, and finds a tile's item by binary search; su3_batch_tiles expands
+ * the rows from exactly those device-resident values.) */
 
 /* ------------------------------------------------------ launch tuning */
 

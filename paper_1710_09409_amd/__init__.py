@@ -36,6 +36,7 @@ SU3_ERR_HIP = -6
 SU3_F64, SU3_F32, SU3_F16_F32ACC, SU3_C12_F32 = 0, 1, 2, 3
 SU3_LAYOUT_AOS, SU3_LAYOUT_SOA, SU3_LAYOUT_AOSOA = 0, 1, 2
 SU3_EXPR_MUL, SU3_EXPR_MUL3, SU3_EXPR_MULADD, SU3_EXPR_ADD, SU3_EXPR_APB_AB = range(5)
+SU3_EXPR_CSHIFT, SU3_EXPR_MUL_SHIFTED = 5, 6  # launch-tuning keys only
 N_OPERANDS = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}
 
 # exported symbols of su3.h, in declaration order

@@ -39,7 +39,6 @@ struct su3_field {
 
 struct su3_batch {
     BatchItem *d_items;
-    BatchTile *d_tiles;
     int32_t nitems;
     int32_t ntiles;
     int32_t mode;
@@ -718,13 +717,18 @@ extern "C" su3_status su3_mult(su3_field *z, const su3_field *x,
 
 // ----------------------------------------------------- shifted operands
 
-// Launch of the shifted-operand kernels: 64-lane workgroups, one-shot grid,
-// at most 5 workgroups per CU, nontemporal loads and stores -- the setting
-// the autotuner settles on for the unshifted product.
+// Launch of the shifted-operand kernels: the tuned (or default) setting of
+// the key (SU3_EXPR_CSHIFT or SU3_EXPR_MUL_SHIFTED, precision, layout,
+// lanes, volume); one site per lane, one-shot grid.
 static su3_status launch_shift_op(int mode, su3_field *z, const su3_field *x,
                                   const su3_field *y, int32_t mu,
-                                  int32_t shift, void *stream)
+                                  int32_t shift, void *stream,
+                                  const su3_launch *forced = nullptr)
 {
+    const su3_launch c =
+        forced ? *forced
+               : lookup_launch(mode ? SU3_EXPR_MUL_SHIFTED : SU3_EXPR_CSHIFT,
+                               z->prec, z->layout, z->lanes, z->V);
     ShiftArgs a;
     std::memset(&a, 0, sizeof a);
     a.z = z->ptr;
@@ -739,10 +743,10 @@ static su3_status launch_shift_op(int mode, su3_field *z, const su3_field *x,
     a.stride = (uint32_t)stride;
     a.extent = (uint32_t)L;
     a.shift = (uint32_t)(((int64_t)shift % L + L) % L);
-    const int block = 64;
-    const int64_t grid = (z->V + block - 1) / block;
-    hipError_t e = launch_shift(z->prec, mode, 3, block, (int)grid,
-                                occupancy_reserve(z->device, 5), a,
+    const int64_t grid = (z->V + c.block - 1) / c.block;
+    hipError_t e = launch_shift(z->prec, mode, c.nontemporal, c.schedule,
+                                c.block, (int)grid,
+                                occupancy_reserve(z->device, c.occupancy), a,
                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(e, "shift kernel launch");
@@ -789,13 +793,15 @@ static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
                          int32_t lanes, const int32_t dims[4], Key *k,
                          Shape *shape)
 {
-    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_APB_AB)
+    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_MUL_SHIFTED)
         return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
     Shape s;
     su3_status st = make_shape(dims, prec, layout, lanes, &s);
     if (st != SU3_OK)
         return st;
-    if (prec == SU3_C12_F32 && expr != SU3_EXPR_MUL && expr != SU3_EXPR_MUL3)
+    if (prec == SU3_C12_F32 &&
+        (expr == SU3_EXPR_MULADD || expr == SU3_EXPR_ADD ||
+         expr == SU3_EXPR_APB_AB))
         return fail(SU3_ERR_UNSUPPORTED,
                     "the two-row compressed form supports MUL and MUL3 only");
     *k = Key(expr, prec, layout, layout == SU3_LAYOUT_AOSOA ? lanes : 0,
@@ -951,7 +957,7 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     if (st != SU3_OK)
         return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const int nops = operands_of(expr);
+    const int nops = expr == SU3_EXPR_CSHIFT ? 1 : operands_of(expr);
     su3_field *f[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     for (int i = 0; i <= nops && st == SU3_OK; ++i) {
         st = su3_field_alloc(&f[i], dims, prec, layout, lanes);
@@ -968,10 +974,20 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     if (st == SU3_OK) {
         const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
         for (const su3_launch &c : candidates(layout)) {
+            if (expr == SU3_EXPR_CSHIFT && c.schedule)
+                continue;  // a copy has no row phases
             double us = 0;
             su3_status r = time_launch(
-                [&]() { return launch_item(f[0], expr, ops, nops, c, hs); }, hs,
-                3, 10, &us);
+                [&]() {
+                    if (expr == SU3_EXPR_CSHIFT)
+                        return launch_shift_op(0, f[0], nullptr, f[1], 1, 1,
+                                               stream, &c);
+                    if (expr == SU3_EXPR_MUL_SHIFTED)
+                        return launch_shift_op(1, f[0], f[1], f[2], 1, 1,
+                                               stream, &c);
+                    return launch_item(f[0], expr, ops, nops, c, hs);
+                },
+                hs, 3, 10, &us);
             if (r != SU3_OK) {
                 (void)hipGetLastError();
                 continue;  // a launch shape the device refused
@@ -1053,24 +1069,19 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
                : lookup_launch(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
                                total_sites);
     const int T = cfg.tile_sites;
-    std::vector<BatchTile> tiles;
+    // tile table: item i owns ceil(V_i / T) tiles starting at the exclusive
+    // prefix sum of its predecessors' counts
+    int64_t ntiles = 0;
     for (int i = 0; i < n; ++i) {
-        const int64_t V = z[i]->V;
-        for (int64_t first = 0; first < V; first += T) {
-            BatchTile t;
-            t.item = i;
-            t.first = (int32_t)first;
-            t.count = (int32_t)std::min<int64_t>(T, V - first);
-            t.prec = z[i]->prec;
-            tiles.push_back(t);
-        }
+        items[i].tile_start = (int32_t)ntiles;
+        ntiles += (z[i]->V + T - 1) / T;
+        if (ntiles >= ((int64_t)1 << 31))
+            return fail(SU3_ERR_INVALID_ARG, "too many tiles");
     }
-    if (tiles.size() >= ((size_t)1 << 31))
-        return fail(SU3_ERR_INVALID_ARG, "too many tiles");
     su3_batch *b = new su3_batch();
     std::memset(b, 0, sizeof *b);
     b->nitems = n;
-    b->ntiles = (int32_t)tiles.size();
+    b->ntiles = (int32_t)ntiles;
     b->mode = mode;
     b->cfg = cfg;
     b->device = dev;
@@ -1083,13 +1094,7 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
     hipStream_t hs = static_cast<hipStream_t>(stream);
     hipError_t e = hipMalloc(&b->d_items, sizeof(BatchItem) * n);
     if (e == hipSuccess)
-        e = hipMalloc(&b->d_tiles, sizeof(BatchTile) * tiles.size());
-    if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * n,
-                           hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_tiles, tiles.data(),
-                           sizeof(BatchTile) * tiles.size(),
                            hipMemcpyHostToDevice, hs);
     if (e == hipSuccess)
         e = hipStreamSynchronize(hs);
@@ -1100,8 +1105,8 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
     if (e == hipSuccess)
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_batch(b->mode, b->d_items, b->d_tiles, b->ntiles,
-                                     cfg.nontemporal, cfg.schedule, cfg.block,
+        hipError_t le = launch_batch(b->mode, b->d_items, b->nitems, b->ntiles,
+                                     T, cfg.nontemporal, cfg.schedule, cfg.block,
                                      b->grid, occupancy_reserve(dev, cfg.occupancy),
                                      cap);
         hipError_t ce = hipStreamEndCapture(cap, &b->graph);
@@ -1147,8 +1152,6 @@ extern "C" su3_status su3_batch_destroy(su3_batch *b)
         (void)hipGraphDestroy(b->graph);
     if (b->d_items)
         (void)hipFree(b->d_items);
-    if (b->d_tiles)
-        (void)hipFree(b->d_tiles);
     delete b;
     return SU3_OK;
 }
@@ -1227,9 +1230,22 @@ extern "C" su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows,
     *n_tiles = b->ntiles;
     if (!rows || cap < b->ntiles)
         return SU3_OK;
-    HIP_TRY(hipMemcpy(rows, b->d_tiles, sizeof(BatchTile) * b->ntiles,
+    // expand the table from the items the kernel reads (tile starts, sizes)
+    std::vector<BatchItem> items(b->nitems);
+    HIP_TRY(hipMemcpy(items.data(), b->d_items, sizeof(BatchItem) * b->nitems,
                       hipMemcpyDeviceToHost),
-            "tile table copy");
+            "batch items copy");
+    const int64_t T = b->cfg.tile_sites;
+    for (int i = 0; i < b->nitems; ++i) {
+        const int64_t end = i + 1 < b->nitems ? items[i + 1].tile_start : b->ntiles;
+        for (int64_t t = items[i].tile_start; t < end; ++t) {
+            const int64_t first = (t - items[i].tile_start) * T;
+            rows[4 * t + 0] = i;
+            rows[4 * t + 1] = (int32_t)first;
+            rows[4 * t + 2] = (int32_t)std::min<int64_t>(T, items[i].nsites - first);
+            rows[4 * t + 3] = items[i].prec;
+        }
+    }
     return SU3_OK;
 }
 

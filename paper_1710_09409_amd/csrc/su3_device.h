@@ -306,11 +306,44 @@ __device__ __forceinline__ void narrow(RawVec<P, S> &v, int j,
     v[2 * j + 1] = (R)im;
 }
 
+// Which operands an expression reads row by row (left) and in full (right).
+template <int X> struct Split;
+template <> struct Split<su3i::MUL> {
+    static constexpr int NL = 1, NR = 1;
+    static constexpr int L[1] = {0}, Rt[1] = {1};
+};
+template <> struct Split<su3i::MUL3> {
+    static constexpr int NL = 1, NR = 2;
+    static constexpr int L[1] = {0}, Rt[2] = {1, 2};
+};
+template <> struct Split<su3i::MULADD> {
+    static constexpr int NL = 2, NR = 2;
+    static constexpr int L[2] = {0, 2}, Rt[2] = {1, 3};
+};
+template <> struct Split<su3i::ADD> {
+    static constexpr int NL = 2, NR = 0;
+    static constexpr int L[2] = {0, 1}, Rt[1] = {0};
+};
+template <> struct Split<su3i::APB_AB> {
+    static constexpr int NL = 1, NR = 1;
+    static constexpr int L[1] = {0}, Rt[1] = {1};
+};
+
+template <int X>
+__device__ __forceinline__ constexpr bool is_right(int k)
+{
+    for (int i = 0; i < Split<X>::NR; ++i)
+        if (Split<X>::Rt[i] == k)
+            return true;
+    return false;
+}
+
 // Schedule 0: every operand entry of the group is loaded (as raw stored
 // vectors), then evaluated, then every result entry is stored.
 template <int P, int X, int S, int NT, bool FULL>
 __device__ __forceinline__ void group_all(void *zp, const void *const (&opp)[4],
-                                          uint32_t off, uint32_t plane, int cnt)
+                                          uint32_t off, uint32_t off_r,
+                                          uint32_t plane, int cnt)
 {
     using R = typename PrecT<P>::R;
     using T = typename PrecT<P>::T;
@@ -319,8 +352,9 @@ __device__ __forceinline__ void group_all(void *zp, const void *const (&opp)[4],
     RawVec<P, S> raw[N][E];
 #pragma unroll
     for (int k = 0; k < N; ++k)
-        load_entries<P, S, NT, FULL, 0, E>(static_cast<const R *>(opp[k]), off,
-                                           plane, cnt, raw[k]);
+        load_entries<P, S, NT, FULL, 0, E>(static_cast<const R *>(opp[k]),
+                                           is_right<X>(k) ? off_r : off, plane,
+                                           cnt, raw[k]);
     RawVec<P, S> zr[E];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
@@ -373,29 +407,6 @@ __device__ __forceinline__ void row_add(const Cx<T> *a, const Cx<T> *b, Cx<T> *c
     }
 }
 
-// Which operands an expression reads row by row (left) and in full (right).
-template <int X> struct Split;
-template <> struct Split<su3i::MUL> {
-    static constexpr int NL = 1, NR = 1;
-    static constexpr int L[1] = {0}, Rt[1] = {1};
-};
-template <> struct Split<su3i::MUL3> {
-    static constexpr int NL = 1, NR = 2;
-    static constexpr int L[1] = {0}, Rt[2] = {1, 2};
-};
-template <> struct Split<su3i::MULADD> {
-    static constexpr int NL = 2, NR = 2;
-    static constexpr int L[2] = {0, 2}, Rt[2] = {1, 3};
-};
-template <> struct Split<su3i::ADD> {
-    static constexpr int NL = 2, NR = 0;
-    static constexpr int L[2] = {0, 1}, Rt[1] = {0};
-};
-template <> struct Split<su3i::APB_AB> {
-    static constexpr int NL = 1, NR = 1;
-    static constexpr int L[1] = {0}, Rt[1] = {1};
-};
-
 // Row i of z from the rows i of the left operands and the full right ones.
 template <int X, class T>
 __device__ __forceinline__ void eval_row(const Cx<T> (&l)[2][3],
@@ -430,7 +441,8 @@ __device__ __forceinline__ void eval_row(const Cx<T> (&l)[2][3],
 // arithmetic, same bits as schedule 0.
 template <int P, int X, int S, int NT, bool FULL>
 __device__ __forceinline__ void group_rows(void *zp, const void *const (&opp)[4],
-                                           uint32_t off, uint32_t plane, int cnt)
+                                           uint32_t off, uint32_t off_r,
+                                           uint32_t plane, int cnt)
 {
     using R = typename PrecT<P>::R;
     using T = typename PrecT<P>::T;
@@ -441,7 +453,7 @@ __device__ __forceinline__ void group_rows(void *zp, const void *const (&opp)[4]
 #pragma unroll
     for (int k = 0; k < SP::NR; ++k)
         load_entries<P, S, NT, FULL, 0, E>(static_cast<const R *>(opp[SP::Rt[k]]),
-                                           off, plane, cnt, rr[k]);
+                                           off_r, plane, cnt, rr[k]);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
         RawVec<P, S> lr[SP::NL][3];
@@ -490,17 +502,20 @@ __device__ __forceinline__ void group_rows(void *zp, const void *const (&opp)[4]
     }
 }
 
-// Evaluate X for the group of S sites at stored offset `off`.  Every
-// operand entry a result entry depends on is loaded before that result
-// entry is stored, so z may be one of the operands (in-place).
+// Evaluate X for the group of S sites at stored offset `off` (the result
+// and the left operands); the right-hand operands are read at `off_r`
+// (equal to `off` except for a shifted operand).  Every operand entry a
+// result entry depends on is loaded before that result entry is stored, so
+// z may be one of the operands read at `off` (in-place).
 template <int P, int X, int S, int NT, bool FULL, int SCHED>
 __device__ __forceinline__ void do_group(void *zp, const void *const (&opp)[4],
-                                         uint32_t off, uint32_t plane, int cnt)
+                                         uint32_t off, uint32_t off_r,
+                                         uint32_t plane, int cnt)
 {
     if constexpr (SCHED == 0)
-        group_all<P, X, S, NT, FULL>(zp, opp, off, plane, cnt);
+        group_all<P, X, S, NT, FULL>(zp, opp, off, off_r, plane, cnt);
     else
-        group_rows<P, X, S, NT, FULL>(zp, opp, off, plane, cnt);
+        group_rows<P, X, S, NT, FULL>(zp, opp, off, off_r, plane, cnt);
 }
 
 // Workgroup id remapped so that each XCD (workgroups are dealt to the 8

@@ -66,7 +66,9 @@ struct ShiftArgs {
     uint32_t shift;   // in [0, extent)
 };
 
-// One item of a batched launch (device-resident table).
+// One item of a batched launch (device-resident table).  The item owns
+// tiles tile_start .. (next item's tile_start) - 1 of the batch's tile
+// table, each of the batch's tile size T in sites (the last may be short).
 struct BatchItem {
     void *z;
     const void *op[4];
@@ -74,17 +76,7 @@ struct BatchItem {
     int32_t nsites;
     int32_t prec;
     int32_t expr;
-    int32_t pad_;
-};
-
-// One tile of a batched launch: `count` sites of item `item` starting at
-// site `first`; `prec` repeats the item's precision (the wave-uniform
-// branch key).
-struct BatchTile {
-    int32_t item;
-    int32_t first;
-    int32_t count;
-    int32_t prec;
+    int32_t tile_start;
 };
 
 // Kernel-unit entry points.  Each returns the launch's hipError_t.
@@ -97,17 +89,17 @@ hipError_t launch_site(int prec, int expr, int sites_per_lane, int nt,
 // AoS with LDS staging: one lane per site, `block` sites per workgroup.
 hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
                            const SiteArgs &a, hipStream_t stream);
-// Batched persistent launch over `ntiles` tiles, `grid` workgroups each
-// taking tiles blockIdx.x, blockIdx.x + grid, ...
+// Batched launch over `ntiles` tiles of `tile_sites` sites, `grid`
+// workgroups each taking tiles blockIdx.x, blockIdx.x + grid, ...
 // mode 0: every item is MUL in F64 or C12 (the mixed-precision streaming
 // workload, smallest register footprint); mode 1: any supported item.
-hipError_t launch_batch(int mode, const BatchItem *items,
-                        const BatchTile *tiles, int32_t ntiles, int nt,
-                        int sched, int block, int grid, size_t shm,
-                        hipStream_t stream);
+hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
+                        int32_t ntiles, int32_t tile_sites, int nt, int sched,
+                        int block, int grid, size_t shm, hipStream_t stream);
 // mode 0: z(s) = y(s'); mode 1: z(s) = x(s) * y(s').  One site per lane.
-hipError_t launch_shift(int prec, int mode, int nt, int block, int grid,
-                        size_t shm, const ShiftArgs &a, hipStream_t stream);
+hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
+                        int grid, size_t shm, const ShiftArgs &a,
+                        hipStream_t stream);
 hipError_t launch_triad(double *a, const double *b, const double *c,
                         double s, int64_t n, hipStream_t stream);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,

@@ -7,10 +7,10 @@ hipError_t launch_site_p0(int, int, int, int, int, int, size_t, const SiteArgs &
 hipError_t launch_site_p1(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
 hipError_t launch_site_p2(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
 hipError_t launch_site_p3(int, int, int, int, int, int, size_t, const SiteArgs &, hipStream_t);
-hipError_t launch_shift_p0(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
-hipError_t launch_shift_p1(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
-hipError_t launch_shift_p2(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
-hipError_t launch_shift_p3(int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
+hipError_t launch_shift_p0(int, int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
+hipError_t launch_shift_p1(int, int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
+hipError_t launch_shift_p2(int, int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
+hipError_t launch_shift_p3(int, int, int, int, int, size_t, const ShiftArgs &, hipStream_t);
 hipError_t launch_site_lds_p0(int, int, int, int, const SiteArgs &, hipStream_t);
 hipError_t launch_site_lds_p1(int, int, int, int, const SiteArgs &, hipStream_t);
 hipError_t launch_site_lds_p2(int, int, int, int, const SiteArgs &, hipStream_t);
@@ -20,7 +20,6 @@ hipError_t launch_site_lds_p3(int, int, int, int, const SiteArgs &, hipStream_t)
 namespace su3k {
 
 using su3i::BatchItem;
-using su3i::BatchTile;
 
 // Evaluate one tile: `count` sites of item `it` from site `first` (a
 // multiple of the tile size, hence of S), lanes striding over its groups.
@@ -36,9 +35,9 @@ __device__ __forceinline__ void tile_run(const BatchItem &it, int first,
         const uint32_t off = site_offset(it.g, s0);
         const int cnt = first + count - int(s0);
         if (cnt >= S)
-            do_group<P, X, S, NT, true, SCHED>(it.z, ops, off, it.g.plane, S);
+            do_group<P, X, S, NT, true, SCHED>(it.z, ops, off, off, it.g.plane, S);
         else
-            do_group<P, X, S, NT, false, SCHED>(it.z, ops, off, it.g.plane, cnt);
+            do_group<P, X, S, NT, false, SCHED>(it.z, ops, off, off, it.g.plane, cnt);
     }
 }
 
@@ -61,30 +60,43 @@ __device__ __forceinline__ void tile_any_expr(const BatchItem &it, int first,
     }
 }
 
-// Persistent batched kernel: workgroup b takes tiles b, b + G, b + 2G, ...
-// The per-tile branch on precision and expression is uniform across the
-// workgroup.  Every workgroup leaves after its last tile.
+// Batched kernel over the tile table.  Item i owns tiles tile_start_i ..
+// tile_start_{i+1} - 1, each of T sites (the item's last tile may be
+// shorter).  Workgroup b takes tiles b, b + G, b + 2G, ...; it finds a
+// tile's item by binary search over the items' tile starts -- a small
+// array every workgroup reads, so it stays in the scalar cache and no
+// per-tile record has to come from memory before the data loads start.
+// The branch on precision and expression is uniform across the workgroup.
+// Every workgroup leaves after its last tile.
 template <int MODE, int NT, int SCHED>
 __global__ __launch_bounds__(256) void k_batch(const BatchItem *items,
-                                               const BatchTile *tiles,
-                                               int ntiles)
+                                               int nitems, int ntiles, int T)
 {
     // dynamic LDS only caps the workgroups per CU; never read
     extern __shared__ char occupancy_reserve[];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const BatchTile tl = tiles[t];
-        const BatchItem &it = items[tl.item];
-        if constexpr (MODE == 0) {
-            if (tl.prec == su3i::F64)
-                tile_run<su3i::F64, su3i::MUL, NT, SCHED>(it, tl.first, tl.count);
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile_start <= t)
+                lo = mid;
             else
-                tile_run<su3i::C12, su3i::MUL, NT, SCHED>(it, tl.first, tl.count);
+                hi = mid - 1;
+        }
+        const BatchItem &it = items[lo];
+        const int first = (t - it.tile_start) * T;
+        const int count = min(T, it.nsites - first);
+        if constexpr (MODE == 0) {
+            if (it.prec == su3i::F64)
+                tile_run<su3i::F64, su3i::MUL, NT, SCHED>(it, first, count);
+            else
+                tile_run<su3i::C12, su3i::MUL, NT, SCHED>(it, first, count);
         } else {
-            switch (tl.prec) {
-            case su3i::F64: tile_any_expr<su3i::F64, NT, SCHED>(it, tl.first, tl.count); break;
-            case su3i::F32: tile_any_expr<su3i::F32, NT, SCHED>(it, tl.first, tl.count); break;
-            case su3i::F16: tile_any_expr<su3i::F16, NT, SCHED>(it, tl.first, tl.count); break;
-            case su3i::C12: tile_any_expr<su3i::C12, NT, SCHED>(it, tl.first, tl.count); break;
+            switch (it.prec) {
+            case su3i::F64: tile_any_expr<su3i::F64, NT, SCHED>(it, first, count); break;
+            case su3i::F32: tile_any_expr<su3i::F32, NT, SCHED>(it, first, count); break;
+            case su3i::F16: tile_any_expr<su3i::F16, NT, SCHED>(it, first, count); break;
+            case su3i::C12: tile_any_expr<su3i::C12, NT, SCHED>(it, first, count); break;
             }
         }
     }
@@ -138,14 +150,14 @@ hipError_t launch_site(int prec, int expr, int S, int nt, int sched, int block,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_shift(int prec, int mode, int nt, int block, int grid,
-                        size_t shm, const ShiftArgs &a, hipStream_t st)
+hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
+                        int grid, size_t shm, const ShiftArgs &a, hipStream_t st)
 {
     switch (prec) {
-    case F64: return launch_shift_p0(mode, nt, block, grid, shm, a, st);
-    case F32: return launch_shift_p1(mode, nt, block, grid, shm, a, st);
-    case F16: return launch_shift_p2(mode, nt, block, grid, shm, a, st);
-    case C12: return launch_shift_p3(mode, nt, block, grid, shm, a, st);
+    case F64: return launch_shift_p0(mode, nt, sched, block, grid, shm, a, st);
+    case F32: return launch_shift_p1(mode, nt, sched, block, grid, shm, a, st);
+    case F16: return launch_shift_p2(mode, nt, sched, block, grid, shm, a, st);
+    case C12: return launch_shift_p3(mode, nt, sched, block, grid, shm, a, st);
     }
     return hipErrorInvalidValue;
 }
@@ -163,33 +175,34 @@ hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
 }
 
 template <int MODE, int NT, int SCHED>
-static void batch_go(const BatchItem *items, const BatchTile *tiles,
-                     int32_t ntiles, int block, int grid, size_t shm,
-                     hipStream_t st)
+static void batch_go(const BatchItem *items, int32_t nitems, int32_t ntiles,
+                     int32_t T, int block, int grid, size_t shm, hipStream_t st)
 {
     hipLaunchKernelGGL((su3k::k_batch<MODE, NT, SCHED>), dim3(grid), dim3(block),
-                       shm, st, items, tiles, ntiles);
+                       shm, st, items, nitems, ntiles, T);
 }
 
-hipError_t launch_batch(int mode, const BatchItem *items,
-                        const BatchTile *tiles, int32_t ntiles, int nt,
-                        int sched, int block, int grid, size_t shm,
-                        hipStream_t st)
+hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
+                        int32_t ntiles, int32_t tile_sites, int nt, int sched,
+                        int block, int grid, size_t shm, hipStream_t st)
 {
     if (block > 256)
         return hipErrorInvalidValue;
     const bool ntb = (nt & 3) == 3;
     const int v = (mode ? 4 : 0) + (ntb ? 2 : 0) + (sched ? 1 : 0);
+#define SU3_BATCH(M, N, S) \
+    batch_go<M, N, S>(items, nitems, ntiles, tile_sites, block, grid, shm, st)
     switch (v) {
-    case 0: batch_go<0, 0, 0>(items, tiles, ntiles, block, grid, shm, st); break;
-    case 1: batch_go<0, 0, 1>(items, tiles, ntiles, block, grid, shm, st); break;
-    case 2: batch_go<0, 3, 0>(items, tiles, ntiles, block, grid, shm, st); break;
-    case 3: batch_go<0, 3, 1>(items, tiles, ntiles, block, grid, shm, st); break;
-    case 4: batch_go<1, 0, 0>(items, tiles, ntiles, block, grid, shm, st); break;
-    case 5: batch_go<1, 0, 1>(items, tiles, ntiles, block, grid, shm, st); break;
-    case 6: batch_go<1, 3, 0>(items, tiles, ntiles, block, grid, shm, st); break;
-    default: batch_go<1, 3, 1>(items, tiles, ntiles, block, grid, shm, st); break;
+    case 0: SU3_BATCH(0, 0, 0); break;
+    case 1: SU3_BATCH(0, 0, 1); break;
+    case 2: SU3_BATCH(0, 3, 0); break;
+    case 3: SU3_BATCH(0, 3, 1); break;
+    case 4: SU3_BATCH(1, 0, 0); break;
+    case 5: SU3_BATCH(1, 0, 1); break;
+    case 6: SU3_BATCH(1, 3, 0); break;
+    default: SU3_BATCH(1, 3, 1); break;
     }
+#undef SU3_BATCH
     return hipGetLastError();
 }
 

@@ -42,9 +42,9 @@ __global__ __launch_bounds__(kMaxSiteBlock) void k_site(su3i::SiteArgs a)
         const uint32_t off = site_offset(a.g, s0);
         const int cnt = a.nsites - int(s0);
         if (cnt >= S)
-            do_group<P, X, S, NT, true, SCHED>(a.z, ops, off, a.g.plane, S);
+            do_group<P, X, S, NT, true, SCHED>(a.z, ops, off, off, a.g.plane, S);
         else
-            do_group<P, X, S, NT, false, SCHED>(a.z, ops, off, a.g.plane, cnt);
+            do_group<P, X, S, NT, false, SCHED>(a.z, ops, off, off, a.g.plane, cnt);
     }
     if (a.nsites < 0)
         occupancy_reserve[threadIdx.x] = 0;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kMaxSiteBlock) void k_site(su3i::SiteArgs a)
 // one direction, periodic.  Consecutive lanes read consecutive sites of
 // the neighbouring row/plane, so the gather stays coalesced except at the
 // wrap of the shifted coordinate.
-template <int MODE, int NT>
+template <int MODE, int NT, int SCHED>
 __global__ __launch_bounds__(kMaxSiteBlock) void k_shift(su3i::ShiftArgs a)
 {
     extern __shared__ char occupancy_reserve[];
@@ -69,29 +69,16 @@ __global__ __launch_bounds__(kMaxSiteBlock) void k_shift(su3i::ShiftArgs a)
         const uint32_t sn = s + (cn - c) * a.stride;  // modulo 2^32, in range
         const uint32_t off = site_offset(a.g, s);
         const uint32_t offn = site_offset(a.g, sn);
-        RawVec<P, 1> yr[E];
-        load_entries<P, 1, NT, true, 0, E>(static_cast<const R *>(a.y), offn,
-                                           a.g.plane, 1, yr);
         if constexpr (MODE == 0) {
+            RawVec<P, 1> yr[E];
+            load_entries<P, 1, NT, true, 0, E>(static_cast<const R *>(a.y), offn,
+                                               a.g.plane, 1, yr);
             store_entries<P, 1, NT, true, 0, E>(static_cast<R *>(a.z), off,
                                                 a.g.plane, 1, yr);
         } else {
-            RawVec<P, 1> xr[E];
-            load_entries<P, 1, NT, true, 0, E>(static_cast<const R *>(a.x), off,
-                                               a.g.plane, 1, xr);
-            Cx<T> o[2][9], z[9];
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                o[0][e] = widen<P, 1>(xr[e], 0);
-                o[1][e] = widen<P, 1>(yr[e], 0);
-            }
-            eval_site<P, su3i::MUL>(o, z);
-            RawVec<P, 1> zr[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                narrow<P, 1>(zr[e], 0, z[e]);
-            store_entries<P, 1, NT, true, 0, E>(static_cast<R *>(a.z), off,
-                                                a.g.plane, 1, zr);
+            const void *const ops[4] = {a.x, a.y, nullptr, nullptr};
+            do_group<P, su3i::MUL, 1, NT, true, SCHED>(a.z, ops, off, offn,
+                                                       a.g.plane, 1);
         }
     }
     if (a.nsites < 0)
@@ -275,20 +262,28 @@ hipError_t SU3_CAT(launch_site_p, SU3_PREC)(int expr, int S, int nt,
     return hipErrorInvalidValue;
 }
 
-hipError_t SU3_CAT(launch_shift_p, SU3_PREC)(int mode, int nt, int block,
-                                              int grid, size_t shm,
+hipError_t SU3_CAT(launch_shift_p, SU3_PREC)(int mode, int nt, int sched,
+                                              int block, int grid, size_t shm,
                                               const ShiftArgs &a,
                                               hipStream_t st)
 {
     using namespace su3k::SU3_CAT(p, SU3_PREC);
     if (block > kMaxSiteBlock)
         return hipErrorInvalidValue;
-    const int v = (mode ? 2 : 0) + ((nt & 3) == 3 ? 1 : 0);
-    switch (v) {
-    case 0: hipLaunchKernelGGL((k_shift<0, 0>), dim3(grid), dim3(block), shm, st, a); break;
-    case 1: hipLaunchKernelGGL((k_shift<0, 3>), dim3(grid), dim3(block), shm, st, a); break;
-    case 2: hipLaunchKernelGGL((k_shift<1, 0>), dim3(grid), dim3(block), shm, st, a); break;
-    default: hipLaunchKernelGGL((k_shift<1, 3>), dim3(grid), dim3(block), shm, st, a); break;
+    const bool ntb = (nt & 3) == 3;
+    if (mode == 0) {
+        if (ntb)
+            hipLaunchKernelGGL((k_shift<0, 3, 0>), dim3(grid), dim3(block), shm, st, a);
+        else
+            hipLaunchKernelGGL((k_shift<0, 0, 0>), dim3(grid), dim3(block), shm, st, a);
+    } else {
+        const int v = (ntb ? 2 : 0) + (sched ? 1 : 0);
+        switch (v) {
+        case 0: hipLaunchKernelGGL((k_shift<1, 0, 0>), dim3(grid), dim3(block), shm, st, a); break;
+        case 1: hipLaunchKernelGGL((k_shift<1, 0, 1>), dim3(grid), dim3(block), shm, st, a); break;
+        case 2: hipLaunchKernelGGL((k_shift<1, 3, 0>), dim3(grid), dim3(block), shm, st, a); break;
+        default: hipLaunchKernelGGL((k_shift<1, 3, 1>), dim3(grid), dim3(block), shm, st, a); break;
+        }
     }
     return hipGetLastError();
 }

@@ -119,6 +119,11 @@ def test_launch_table():
                    dict(cfg, lds_stage=1, block=128)) == 0
     assert _status(su3.su3_launch_set, 3, 3, 1, 0, dims, cfg) == \
         su3.SU3_ERR_UNSUPPORTED
+    # the shifted operations' tuning keys are accepted, unknown ones not
+    for key in (su3.SU3_EXPR_CSHIFT, su3.SU3_EXPR_MUL_SHIFTED):
+        su3.su3_launch_set(key, 0, 1, 0, dims, cfg)
+        assert su3.su3_launch_get(key, 0, 1, 0, dims).as_dict() == cfg
+    assert _status(su3.su3_launch_set, 7, 0, 1, 0, dims, cfg) == su3.SU3_ERR_INVALID_ARG
     su3.su3_launch_reset()
     assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == d.as_dict()
 

@@ -36,11 +36,23 @@ def test_shift_parity(dims, prec):
                 su3.su3_cshift(fz, fy, mu, k, s)
                 got = su3.su3_field_download(fz, s)
                 assert np.array_equal(got, want), (LAYOUT_NAMES[lay], lanes, mu, k)
-                su3.su3_mult_shifted(fz, fx, fy, mu, k, s)
-                got = su3.su3_field_download(fz, s)
                 ref = O.get().mult(qx, want)
-                assert_parity(prec, su3.SU3_EXPR_MUL, got, ref,
-                              f"shifted {LAYOUT_NAMES[lay]}{lanes} mu {mu} k {k}")
+                prev = None
+                for sched in (0, 1):
+                    cfg = dict(block=64, persistent=0, nontemporal=3, xcd_remap=0,
+                               lds_stage=0, tile_sites=4096, occupancy=4,
+                               schedule=sched)
+                    su3.su3_launch_set(su3.SU3_EXPR_MUL_SHIFTED, prec, lay, lanes,
+                                       dims, cfg)
+                    try:
+                        su3.su3_mult_shifted(fz, fx, fy, mu, k, s)
+                    finally:
+                        su3.su3_launch_reset()
+                    got = su3.su3_field_download(fz, s)
+                    assert_parity(prec, su3.SU3_EXPR_MUL, got, ref,
+                                  f"shifted {LAYOUT_NAMES[lay]}{lanes} mu {mu} k {k}")
+                    assert prev is None or np.array_equal(got, prev)
+                    prev = got
 
 
 def test_shift_rules():
