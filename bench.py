@@ -271,18 +271,20 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
     # precision forms at 48^4 (SoA)
     prec_out = {}
     for prec in (su3.SU3_F32, su3.SU3_F16_F32ACC, su3.SU3_C12_F32):
-        x = make(dims, prec, SOA, 0, testgen.FID_X)
-        y = make(dims, prec, SOA, 0, testgen.FID_Y)
-        z = su3.field_tensor(dims, prec, SOA, 0)
-        cfg = tune(su3.SU3_EXPR_MUL, prec, SOA, 0, dims)
-        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
-        b = BYTES_PER_SITE[prec] * V
-        prec_out[PREC_NAME[prec]] = {
-            "us": round(ms * 1e3, 2), "gbps": round(b / (ms * 1e-3) / 1e9, 1),
-            "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-            "speedup_vs_f64": round(ms_f64 / ms, 3), "launch": cfg}
-        log(f"precision {PREC_NAME[prec]}: {prec_out[PREC_NAME[prec]]}")
-        del x, y, z
+        for lname, lay, lanes in (("soa", SOA, 0), ("aosoa64", AOSOA, 64)):
+            x = make(dims, prec, lay, lanes, testgen.FID_X)
+            y = make(dims, prec, lay, lanes, testgen.FID_Y)
+            z = su3.field_tensor(dims, prec, lay, lanes)
+            cfg = tune(su3.SU3_EXPR_MUL, prec, lay, lanes, dims)
+            ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
+            b = BYTES_PER_SITE[prec] * V
+            key = f"{PREC_NAME[prec]}_{lname}"
+            prec_out[key] = {
+                "us": round(ms * 1e3, 2), "gbps": round(b / (ms * 1e-3) / 1e9, 1),
+                "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "speedup_vs_f64_soa": round(ms_f64 / ms, 3), "launch": cfg}
+            log(f"precision {key}: {prec_out[key]}")
+            del x, y, z
     out["precision_48^4"] = prec_out
 
     # layouts at 48^4 (FP64)
@@ -351,14 +353,18 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
     d = (32, 32, 32, 32)
     Vf = testgen.volume(d)
     fused = {}
-    for prec in (su3.SU3_F64, su3.SU3_F32):
-        U = [make(d, prec, SOA, 0, testgen.FID_U0 + mu) for mu in range(4)]
-        z = su3.field_tensor(d, prec, SOA, 0)
-        t1 = su3.field_tensor(d, prec, SOA, 0)
-        t2 = su3.field_tensor(d, prec, SOA, 0)
+    for prec, lname, lay, lanes in ((su3.SU3_F64, "soa", SOA, 0), (su3.SU3_F32, "soa", SOA, 0),
+                                    (su3.SU3_F64, "aosoa64", AOSOA, 64),
+                                    (su3.SU3_F32, "aosoa64", AOSOA, 64)):
+        U = [make(d, prec, lay, lanes, testgen.FID_U0 + mu) for mu in range(4)]
+        z = su3.field_tensor(d, prec, lay, lanes)
+        t1 = su3.field_tensor(d, prec, lay, lanes)
+        t2 = su3.field_tensor(d, prec, lay, lanes)
         for expr, name in ((su3.SU3_EXPR_MUL3, "mul3"), (su3.SU3_EXPR_MULADD, "muladd")):
             nops = 3 if expr == su3.SU3_EXPR_MUL3 else 4
-            cfg = tune(expr, prec, SOA, 0, d)
+            cfg = tune(expr, prec, lay, lanes, d)
+            tune(su3.SU3_EXPR_MUL, prec, lay, lanes, d)
+            tune(su3.SU3_EXPR_ADD, prec, lay, lanes, d)
             ms_f, _ = timer.run(lambda: su3.su3_fused_eval(z, expr, U[:nops], stream),
                                 steps, 3)
             if expr == su3.SU3_EXPR_MUL3:
@@ -372,15 +378,17 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
                     su3.su3_fused_eval(z, su3.SU3_EXPR_ADD, [t1, t2], stream)
             ms_c, _ = timer.run(chained, steps, 3)
             b = expr_bytes_per_site(prec, expr) * Vf
-            fused[f"{PREC_NAME[prec]}_{name}"] = {
+            fused[f"{PREC_NAME[prec]}_{lname}_{name}"] = {
                 "fused_us": round(ms_f * 1e3, 2), "chained_us": round(ms_c * 1e3, 2),
                 "fused_gbps": round(b / (ms_f * 1e-3) / 1e9, 1),
                 "speedup": round(ms_c / ms_f, 3), "launch": cfg}
-            log(f"fused {PREC_NAME[prec]} {name}: {fused[f'{PREC_NAME[prec]}_{name}']}")
+            log(f"fused {PREC_NAME[prec]} {lname} {name}: {fused[f'{PREC_NAME[prec]}_{lname}_{name}']}")
         del U, z, t1, t2
     out["fused_32^4"] = fused
 
-    # 64 uneven lattices, mixed FP64 and compressed FP32, one graph replay
+    # 64 uneven lattices, mixed FP64 and compressed FP32, one graph replay;
+    # AoSoA(64) storage: most of these volumes are powers of two, whose SoA
+    # entry planes sit at power-of-two strides
     lat = testgen.batch_lattices(64, seed=args.seed)
     zs, ops, exprs = [], [], []
     total_bytes = 0
@@ -388,9 +396,9 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
     for i, (d, comp) in enumerate(lat):
         prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
         Vi = testgen.volume(d)
-        ops.append([make(d, prec, SOA, 0, testgen.FID_BATCH_BASE + 4 * i + k)
+        ops.append([make(d, prec, AOSOA, 64, testgen.FID_BATCH_BASE + 4 * i + k)
                     for k in range(2)])
-        zs.append(su3.field_tensor(d, prec, SOA, 0))
+        zs.append(su3.field_tensor(d, prec, AOSOA, 64))
         exprs.append(su3.SU3_EXPR_MUL)
         total_bytes += BYTES_PER_SITE[prec] * Vi
     total_sites = sum(testgen.volume(d) for d, _ in lat)
@@ -404,14 +412,14 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
     # the same 64 products as 64 back-to-back launches (tuned per shape)
     for i, (d, comp) in enumerate(lat):
         prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
-        tune(su3.SU3_EXPR_MUL, prec, SOA, 0, d)
+        tune(su3.SU3_EXPR_MUL, prec, AOSOA, 64, d)
 
     def unbatched():
         for i in range(64):
             su3.su3_mult(zs[i], ops[i][0], ops[i][1], stream)
     ms_u, _ = timer.run(unbatched, 20, 2)
     out["batch_64"] = {
-        "lattices": 64, "sites": total_sites, "bytes": total_bytes,
+        "lattices": 64, "layout": "aosoa64", "sites": total_sites, "bytes": total_bytes,
         "n_c12": sum(1 for _, c in lat if c),
         "us": round(ms_b * 1e3, 2),
         "gbps": round(total_bytes / (ms_b * 1e-3) / 1e9, 1),

@@ -1164,13 +1164,13 @@ static std::vector<su3_launch> batch_candidates()
     c.xcd_remap = 0;
     c.lds_stage = 0;
     c.nontemporal = 3;
-    for (int tile : {128, 512, 2048, 8192})
-        for (int pers : {0, 8})
+    for (int tile : {64, 128, 256, 512, 2048, 8192})
+        for (int bp : {0, 1, 2})  // block 64 / 128 one-shot, or 256 x 8 per CU
             for (int occ : {0, 4, 6})
                 for (int sched : {0, 1}) {
                     c.tile_sites = tile;
-                    c.persistent = pers;
-                    c.block = pers ? 256 : 64;
+                    c.persistent = bp == 2 ? 8 : 0;
+                    c.block = bp == 0 ? 64 : (bp == 1 ? 128 : 256);
                     c.occupancy = occ;
                     c.schedule = sched;
                     out.push_back(c);

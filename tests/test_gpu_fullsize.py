@@ -50,31 +50,37 @@ def run_tuned(dims, prec, expr, fids, layout=su3.SU3_LAYOUT_SOA, lanes=0):
     return out, cfg
 
 
+LAYS = [(su3.SU3_LAYOUT_SOA, 0), (su3.SU3_LAYOUT_AOSOA, 64)]
+
+
+@pytest.mark.parametrize("lay,lanes", LAYS, ids=["soa", "aosoa64"])
 @pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=[PREC_NAMES[p] for p in range(4)])
-def test_mult_48(prec):
+def test_mult_48(prec, lay, lanes):
     V = testgen.volume(D48)
     fids = (testgen.FID_X, testgen.FID_Y)
-    got, cfg = run_tuned(D48, prec, su3.SU3_EXPR_MUL, fids)
+    got, cfg = run_tuned(D48, prec, su3.SU3_EXPR_MUL, fids, lay, lanes)
     ops = [host(V, f) for f in fids]
     want = O.get().reference(su3.SU3_EXPR_MUL, prec, ops)
     worst = assert_parity(prec, su3.SU3_EXPR_MUL, got, want, f"48^4 {PREC_NAMES[prec]} {cfg.as_dict()}")
     print(f"48^4 {PREC_NAMES[prec]}: worst {worst:.3e} with launch {cfg.as_dict()}")
 
 
+@pytest.mark.parametrize("lay,lanes", LAYS, ids=["soa", "aosoa64"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
 @pytest.mark.parametrize("expr", [su3.SU3_EXPR_MUL3, su3.SU3_EXPR_MULADD], ids=["mul3", "muladd"])
-def test_fused_32(prec, expr):
+def test_fused_32(prec, expr, lay, lanes):
     V = testgen.volume(D32)
     n = su3.N_OPERANDS[expr]
     fids = tuple(testgen.FID_U0 + mu for mu in range(n))
-    got, cfg = run_tuned(D32, prec, expr, fids)
+    got, cfg = run_tuned(D32, prec, expr, fids, lay, lanes)
     want = O.get().reference(expr, prec, [host(V, f) for f in fids])
     assert_parity(prec, expr, got, want, f"32^4 fused {expr} {PREC_NAMES[prec]}")
 
 
 def test_batch_64_sampled():
-    """The benchmark's 64-lattice batch (seed 1710), checked on 512 sampled
-    sites of every lattice plus its first and last site."""
+    """The benchmark's 64-lattice batch (seed 1710, AoSoA(64) storage, the
+    batch autotuner's launch), checked on 512 sampled sites of every
+    lattice plus its first and last site."""
     s = torch.cuda.current_stream()
     lat = testgen.batch_lattices(64)
     zs, ops = [], []
@@ -83,11 +89,12 @@ def test_batch_64_sampled():
         V = testgen.volume(d)
         row = []
         for k in range(2):
-            f = su3.field_tensor(d, prec, su3.SU3_LAYOUT_SOA, 0)
+            f = su3.field_tensor(d, prec, su3.SU3_LAYOUT_AOSOA, 64)
             su3.su3_field_upload(f, testgen.su3_field(V, field_id=testgen.FID_BATCH_BASE + 4 * i + k), s)
             row.append(f)
         ops.append(row)
-        zs.append(su3.field_tensor(d, prec, su3.SU3_LAYOUT_SOA, 0))
+        zs.append(su3.field_tensor(d, prec, su3.SU3_LAYOUT_AOSOA, 64))
+    su3.su3_batch_autotune([su3.SU3_EXPR_MUL] * 64, zs, ops, s)
     b = su3.su3_batch_create([su3.SU3_EXPR_MUL] * 64, zs, ops, s)
     su3.su3_batch_launch(b, s)
     su3.su3_sync(s)
