@@ -1,0 +1,208 @@
+// libsu3's C ABI and kernels run on the CPU (emulated launches, see
+// hip/hip_runtime.h) against the FP64 oracle, under AddressSanitizer and
+// UBSan: every precision x layout x expression on ragged lattices with two
+// launch settings (which must agree), persistent grids, LDS staging, the
+// batch (tile rows, replays, autotuner) and the shifted operands.  Any
+// out-of-bounds access in a kernel's indexing aborts the run.  Prints
+// "fails 0" on success.
+#include "su3.h"
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+#include <hip/hip_runtime.h>
+extern "C" {
+void su3gen_field(uint64_t seed, uint64_t field_id, int64_t s_begin, int64_t count, double *out);
+int oracle_fused(int expr, const double *a, const double *b, const double *c, const double *d, double *z, int64_t V);
+int oracle_roundtrip(int prec, const double *in, double *out, int64_t V);
+int oracle_cshift(const double *src, double *dst, const int32_t dims[4], int mu, int64_t shift);
+void oracle_mult(const double *x, const double *y, double *z, int64_t V);
+}
+static int nops_of(int e) { return e == 1 ? 3 : (e == 2 ? 4 : 2); }
+static int fails = 0;
+
+static double run_case(const int dims[4], int prec, int layout, int lanes, int expr, su3_launch *cfg)
+{
+    int64_t V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+    int n = nops_of(expr);
+    std::vector<std::vector<double>> h(n, std::vector<double>(18 * V)), hq(n, std::vector<double>(18 * V));
+    for (int k = 0; k < n; ++k) {
+        su3gen_field(1710, 100 + k, 0, V, h[k].data());
+        oracle_roundtrip(prec, h[k].data(), hq[k].data(), V);
+    }
+    std::vector<double> want(18 * V), got(18 * V);
+    oracle_fused(expr, hq[0].data(), hq[1].data(), n > 2 ? hq[2].data() : nullptr, n > 3 ? hq[3].data() : nullptr, want.data(), V);
+    su3_field *f[5];
+    for (int k = 0; k <= n; ++k) {
+        if (su3_field_alloc(&f[k], dims, (su3_precision)prec, (su3_layout)layout, lanes) != SU3_OK) { printf("alloc: %s\n", su3_last_error()); fails++; return 1e30; }
+        if (k) su3_field_upload(f[k], h[k - 1].data(), nullptr);
+    }
+    if (cfg) su3_launch_set((su3_expr)expr, (su3_precision)prec, (su3_layout)layout, lanes, dims, cfg);
+    const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
+    su3_status st = su3_fused_eval(f[0], (su3_expr)expr, ops, n, nullptr);
+    if (cfg) su3_launch_reset();
+    if (st != SU3_OK) { printf("eval: %s\n", su3_last_error()); fails++; return 1e30; }
+    su3_field_download(f[0], got.data(), nullptr);
+    double err = 0;
+    int rows = prec == 3 ? 2 : 3;
+    int nbad16 = 0;
+    for (int64_t s = 0; s < V; ++s)
+        for (int t = 0; t < rows * 6; ++t) {
+            double d = std::fabs(got[18 * s + t] - want[18 * s + t]);
+            err = std::max(err, d);
+            if (prec == 2 && d > std::ldexp(std::fabs(want[18 * s + t]), -11) + 12 * std::ldexp(1.0, -24) * 3 + std::ldexp(1.0, -25)) nbad16++;
+        }
+    if (nbad16) printf("F16 elementwise bound violated at %d entries (expr %d)\n", nbad16, expr);
+    for (int k = 0; k <= n; ++k) su3_field_free(f[k]);
+    double tol = prec == 0 ? 1e-13 : (prec == 2 ? 5e-3 : 1e-5);
+    if (!(err <= tol)) { fails++; printf("FAIL "); }
+    return err;
+}
+
+int main(int argc, char **argv)
+{
+    int sizes[][4] = {{1, 1, 1, 1}, {3, 5, 7, 11}, {8, 8, 8, 8}};
+    int lays[][2] = {{0, 0}, {1, 0}, {2, 8}, {2, 16}, {2, 32}, {2, 64}};
+    for (auto &d : sizes)
+        for (int prec = 0; prec < 4; ++prec)
+            for (auto &l : lays)
+                for (int expr = 0; expr < 5; ++expr) {
+                    if (prec == 3 && expr > 1) continue;
+                    su3_launch c0 = {64, 0, 3, 0, 0, 4096, 0, 0};
+                    su3_launch c1 = {128, 0, 3, 1, 0, 4096, 4, 1};
+                    if (l[0] == 0) c1.schedule = 0;
+                    double e = run_case(d, prec, l[0], l[1], expr, &c0);
+                    double e1 = run_case(d, prec, l[0], l[1], expr, &c1);
+                    if (e != e1) { printf("schedules differ: "); fails++; }
+                    if (e > (prec == 0 ? 1e-13 : 1e-5) || argc > 1)
+                        printf("dims %dx%dx%dx%d prec %d layout %d/%d expr %d err %.3e\n", d[0], d[1], d[2], d[3], prec, l[0], l[1], expr, e);
+                }
+    // persistent + remap settings
+    su3_launch c = {64, 1, 3, 1, 0, 4096, 3, 1};
+    int d16[4] = {16, 16, 16, 16};
+    for (int prec = 0; prec < 4; ++prec) {
+        double e = run_case(d16, prec, 1, 0, 0, &c);
+        printf("persistent prec %d err %.3e\n", prec, e);
+    }
+    // LDS staged (threaded emulation for barriers)
+    emu_threaded = true;
+    su3_launch lds = {64, 0, 3, 0, 1, 4096, 0, 0};
+    int dl[4] = {3, 5, 7, 11};
+    for (int prec = 0; prec < 4; ++prec)
+        for (int expr = 0; expr < 5; ++expr) {
+            if (prec == 3 && expr > 1) continue;
+            double e = run_case(dl, prec, 0, 0, expr, &lds);
+            printf("lds prec %d expr %d err %.3e\n", prec, expr, e);
+        }
+    emu_threaded = false;
+    // batch: mixed items, compare each replay with unbatched results
+    {
+        struct It { int d[4]; int prec, lay, lanes, expr; };
+        It items[] = {{{2, 3, 5, 7}, 0, 1, 0, 0}, {{8, 8, 8, 8}, 3, 1, 0, 0}, {{4, 4, 4, 9}, 0, 2, 16, 0},
+                      {{1, 1, 1, 1}, 3, 2, 8, 0}, {{3, 5, 7, 11}, 1, 1, 0, 2}, {{5, 5, 5, 5}, 2, 2, 32, 0},
+                      {{5, 5, 5, 7}, 2, 1, 0, 4}, {{4, 5, 6, 7}, 3, 1, 0, 1}, {{4, 4, 4, 4}, 0, 2, 64, 3}};
+        for (int mode = 0; mode < 2; ++mode)
+        for (int T : {64, 256, 4096}) {
+            int n = mode == 0 ? 4 : 9;
+            std::vector<su3_field *> zs(n), ref(n);
+            std::vector<const su3_field *> ops(4 * n, nullptr);
+            std::vector<su3_expr> ex(n);
+            int64_t total = 0;
+            for (int i = 0; i < n; ++i) {
+                It &it = items[i];
+                int64_t V = (int64_t)it.d[0] * it.d[1] * it.d[2] * it.d[3];
+                total += V;
+                int no = nops_of(it.expr);
+                su3_field_alloc(&zs[i], it.d, (su3_precision)it.prec, (su3_layout)it.lay, it.lanes);
+                su3_field_alloc(&ref[i], it.d, (su3_precision)it.prec, (su3_layout)it.lay, it.lanes);
+                for (int k = 0; k < no; ++k) {
+                    su3_field *f;
+                    su3_field_alloc(&f, it.d, (su3_precision)it.prec, (su3_layout)it.lay, it.lanes);
+                    std::vector<double> h(18 * V);
+                    su3gen_field(7, 1000 + 4 * i + k, 0, V, h.data());
+                    su3_field_upload(f, h.data(), nullptr);
+                    ops[4 * i + k] = f;
+                }
+                ex[i] = (su3_expr)it.expr;
+                if (su3_fused_eval(ref[i], ex[i], &ops[4 * i], no, nullptr) != SU3_OK) { printf("ref eval %s\n", su3_last_error()); fails++; }
+            }
+            int td[4] = {(int)total, 1, 1, 1};
+            su3_launch c = {256, (T == 256 ? 2 : 0), 3, 0, 0, T, 3, (T == 64 ? 1 : 0)};
+            su3_launch_set(ex[0], (su3_precision)items[0].prec, (su3_layout)items[0].lay, items[0].lanes, td, &c);
+            su3_batch *b;
+            if (T == 4096) {
+                su3_launch best;
+                if (su3_batch_autotune(ex.data(), zs.data(), ops.data(), n, nullptr, &best) != SU3_OK) { printf("batch autotune %s\n", su3_last_error()); fails++; }
+                else printf("batch autotune picked tile %d pers %d\n", best.tile_sites, best.persistent);
+                su3_launch_set(ex[0], (su3_precision)items[0].prec, (su3_layout)items[0].lay, items[0].lanes, td, &c);
+            }
+            if (su3_batch_create(&b, ex.data(), zs.data(), ops.data(), n, nullptr) != SU3_OK) { printf("batch %s\n", su3_last_error()); fails++; continue; }
+            su3_launch_reset();
+            int64_t nt;
+            su3_batch_tiles(b, nullptr, 0, &nt);
+            {
+                std::vector<int32_t> rows(4 * nt);
+                su3_batch_tiles(b, rows.data(), nt, &nt);
+                int64_t t = 0; int bad = 0;
+                for (int i = 0; i < n; ++i) {
+                    int64_t V = (int64_t)items[i].d[0] * items[i].d[1] * items[i].d[2] * items[i].d[3];
+                    for (int64_t f = 0; f < V; f += T, ++t)
+                        if (rows[4 * t] != i || rows[4 * t + 1] != f || rows[4 * t + 2] != std::min<int64_t>(T, V - f) || rows[4 * t + 3] != items[i].prec) bad++;
+                }
+                if (bad || t != nt) { printf("tile rows bad %d\n", bad); fails++; }
+            }
+            for (int rep = 0; rep < 2; ++rep) {
+                su3_batch_launch(b, nullptr);
+                int bad = 0;
+                for (int i = 0; i < n; ++i) {
+                    void *p1, *p2; size_t n1, n2;
+                    su3_field_data(zs[i], &p1, &n1);
+                    su3_field_data(ref[i], &p2, &n2);
+                    if (memcmp(p1, p2, n1) != 0) bad++;
+                }
+                printf("batch mode %d T %d tiles %lld rep %d mismatching items %d\n", mode, T, (long long)nt, rep, bad);
+                fails += bad;
+            }
+            su3_batch_destroy(b);
+            for (auto *f : zs) su3_field_free(f);
+            for (auto *f : ref) su3_field_free(f);
+            for (auto *f : ops) su3_field_free((su3_field *)f);
+        }
+    }
+    // shifted operands
+    {
+        int sd[][4] = {{3, 5, 7, 11}, {4, 4, 4, 4}, {1, 2, 1, 3}};
+        for (auto &d : sd)
+            for (int prec = 0; prec < 4; ++prec)
+                for (auto &l : lays)
+                    for (int mu = 0; mu < 4; ++mu)
+                        for (int sh : {1, -1, 2, 13}) {
+                            int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
+                            std::vector<double> hx(18 * V), hy(18 * V), qx(18 * V), qy(18 * V), sy(18 * V), want(18 * V), got(18 * V);
+                            su3gen_field(5, 1, 0, V, hx.data()); su3gen_field(5, 2, 0, V, hy.data());
+                            oracle_roundtrip(prec, hx.data(), qx.data(), V); oracle_roundtrip(prec, hy.data(), qy.data(), V);
+                            oracle_cshift(qy.data(), sy.data(), d, mu, sh);
+                            su3_field *fx, *fy, *fz;
+                            su3_field_alloc(&fx, d, (su3_precision)prec, (su3_layout)l[0], l[1]);
+                            su3_field_alloc(&fy, d, (su3_precision)prec, (su3_layout)l[0], l[1]);
+                            su3_field_alloc(&fz, d, (su3_precision)prec, (su3_layout)l[0], l[1]);
+                            su3_field_upload(fx, hx.data(), nullptr); su3_field_upload(fy, hy.data(), nullptr);
+                            if (su3_cshift(fz, fy, mu, sh, nullptr) != SU3_OK) { printf("cshift %s\n", su3_last_error()); fails++; }
+                            su3_field_download(fz, got.data(), nullptr);
+                            if (memcmp(got.data(), sy.data(), 8 * 18 * V) != 0) { printf("cshift mismatch prec %d lay %d mu %d sh %d\n", prec, l[0], mu, sh); fails++; }
+                            su3_launch cs = {64, 0, 3, 0, 0, 4096, 4, (mu + sh) & 1};
+                            su3_launch_set(SU3_EXPR_MUL_SHIFTED, (su3_precision)prec, (su3_layout)l[0], l[1], d, &cs);
+                            if (su3_mult_shifted(fz, fx, fy, mu, sh, nullptr) != SU3_OK) { printf("mult_shifted %s\n", su3_last_error()); fails++; }
+                            su3_launch_reset();
+                            su3_field_download(fz, got.data(), nullptr);
+                            oracle_mult(qx.data(), sy.data(), want.data(), V);
+                            double err = 0; int rows = prec == 3 ? 2 : 3;
+                            for (int64_t s = 0; s < V; ++s) for (int t = 0; t < rows * 6; ++t) err = std::max(err, std::fabs(got[18 * s + t] - want[18 * s + t]));
+                            if (err > (prec == 0 ? 1e-14 : (prec == 2 ? 2e-3 : 2e-6))) { printf("mult_shifted err %.3e prec %d lay %d mu %d sh %d\n", err, prec, l[0], mu, sh); fails++; }
+                            su3_field_free(fx); su3_field_free(fy); su3_field_free(fz);
+                        }
+        printf("shift cases done\n");
+    }
+    printf("fails %d\n", fails);
+    return fails != 0;
+}
