@@ -69,6 +69,8 @@ def _bind(lib):
     lib.oracle_threads.restype = i32
     lib.oracle_cshift.argtypes = [vp, vp, vp, i32, i64]
     lib.oracle_cshift.restype = i32
+    lib.oracle_dslash.argtypes = [vp, vp, vp, vp]
+    lib.oracle_dslash.restype = i32
     lib.oracle_set_threads.argtypes = [i32]
     lib.oracle_set_threads.restype = None
     return lib
@@ -135,6 +137,21 @@ class Oracle:
     def mult_shifted(self, x, y, dims, mu, shift):
         """z(c) = x(c) * y(c + shift * mu_hat)."""
         return self.mult(x, self.cshift(y, dims, mu, shift))
+
+    def dslash(self, links, psi, dims):
+        """Wilson hopping term: sum over mu of (1 - gamma_mu) U_mu(x)
+        psi(x + mu) + (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu).
+        links: 4 link fields; psi: spinor field, shape (V, 4, 3, 2)."""
+        u = [self._field(l) for l in links]
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        assert psi.shape[1:] == (4, 3, 2)
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+        arr = (ctypes.c_void_p * 4)(*[l.ctypes.data for l in u])
+        out = np.empty_like(psi)
+        rc = self.lib.oracle_dslash(ctypes.cast(arr, ctypes.c_void_p), self._p(psi),
+                                    self._p(out), self._p(d))
+        assert rc == 0
+        return out
 
     def quant_f32(self, a):
         a = np.ascontiguousarray(a, dtype=np.float64)

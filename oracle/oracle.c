@@ -172,6 +172,110 @@ int oracle_cshift(const double *src, double *dst, const int32_t dims[4],
     return 0;
 }
 
+/* --------------------------------------------------------- Wilson hopping */
+
+/* Euclidean Dirac matrices in the chiral basis, gamma_mu for directions
+ * mu = 0..3 = x, y, z, t:
+ *   gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (k = 1, 2, 3),
+ *   gamma_4 = [[0, 1], [1, 0]],
+ * stored as [mu][row][col][re/im]. */
+static const double GAMMA[4][4][4][2] = {
+    /* gamma_1 */
+    {{{0, 0}, {0, 0}, {0, 0}, {0, -1}},
+     {{0, 0}, {0, 0}, {0, -1}, {0, 0}},
+     {{0, 0}, {0, 1}, {0, 0}, {0, 0}},
+     {{0, 1}, {0, 0}, {0, 0}, {0, 0}}},
+    /* gamma_2 */
+    {{{0, 0}, {0, 0}, {0, 0}, {-1, 0}},
+     {{0, 0}, {0, 0}, {1, 0}, {0, 0}},
+     {{0, 0}, {1, 0}, {0, 0}, {0, 0}},
+     {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},
+    /* gamma_3 */
+    {{{0, 0}, {0, 0}, {0, -1}, {0, 0}},
+     {{0, 0}, {0, 0}, {0, 0}, {0, 1}},
+     {{0, 1}, {0, 0}, {0, 0}, {0, 0}},
+     {{0, 0}, {0, -1}, {0, 0}, {0, 0}}},
+    /* gamma_4 */
+    {{{0, 0}, {0, 0}, {1, 0}, {0, 0}},
+     {{0, 0}, {0, 0}, {0, 0}, {1, 0}},
+     {{1, 0}, {0, 0}, {0, 0}, {0, 0}},
+     {{0, 0}, {1, 0}, {0, 0}, {0, 0}}},
+};
+
+/* Spinor fields: 4 spins x 3 colours complex per site, double at
+ * ((s*4 + spin)*3 + colour)*2 + c. */
+
+/* out = (1 + sign*gamma_mu) * (M v) for one site, where M is the link or
+ * its conjugate transpose (dagger = 1), v a 4x3 spinor; accumulated into
+ * acc.  Written as the full 4x4 spin matrix times the colour-rotated
+ * spinor, without spin projection. */
+static void hop_term(const double *m, int dagger, const double *v, int mu,
+                     double sign, double *acc)
+{
+    double w[4][3][2];
+    for (int sp = 0; sp < 4; ++sp)
+        for (int a = 0; a < 3; ++a) {
+            double re = 0.0, im = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                /* M_ab = m_ab, or conj(m_ba) for the dagger */
+                double mr = dagger ? re_(m, b, a) : re_(m, a, b);
+                double mi = dagger ? -im_(m, b, a) : im_(m, a, b);
+                double vr = v[(sp * 3 + b) * 2], vi = v[(sp * 3 + b) * 2 + 1];
+                re += mr * vr - mi * vi;
+                im += mr * vi + mi * vr;
+            }
+            w[sp][a][0] = re;
+            w[sp][a][1] = im;
+        }
+    for (int sp = 0; sp < 4; ++sp)
+        for (int a = 0; a < 3; ++a) {
+            double re = w[sp][a][0], im = w[sp][a][1]; /* identity part */
+            for (int q = 0; q < 4; ++q) {
+                double gr = sign * GAMMA[mu][sp][q][0];
+                double gi = sign * GAMMA[mu][sp][q][1];
+                re += gr * w[q][a][0] - gi * w[q][a][1];
+                im += gr * w[q][a][1] + gi * w[q][a][0];
+            }
+            acc[(sp * 3 + a) * 2] += re;
+            acc[(sp * 3 + a) * 2 + 1] += im;
+        }
+}
+
+/* Wilson hopping term (the "Dslash" whose port the paper's outlook names):
+ *   out(x) = sum_mu [ (1 - gamma_mu) U_mu(x) in(x + mu_hat)
+ *                   + (1 + gamma_mu) U_mu(x - mu_hat)^dagger in(x - mu_hat) ]
+ * periodic in every direction.  u[mu] are link fields (canonical 18
+ * doubles per site), in/out spinor fields (24 doubles per site). */
+int oracle_dslash(const double *const *u, const double *in, double *out,
+                  const int32_t dims[4])
+{
+    for (int d = 0; d < 4; ++d)
+        if (dims[d] <= 0)
+            return -1;
+    int64_t c[4];
+    for (c[3] = 0; c[3] < dims[3]; ++c[3])
+        for (c[2] = 0; c[2] < dims[2]; ++c[2])
+            for (c[1] = 0; c[1] < dims[1]; ++c[1])
+                for (c[0] = 0; c[0] < dims[0]; ++c[0]) {
+                    int64_t s = c[0] + dims[0] * (c[1] + dims[1] * (c[2] + dims[2] * c[3]));
+                    double acc[24];
+                    for (int t = 0; t < 24; ++t)
+                        acc[t] = 0.0;
+                    for (int mu = 0; mu < 4; ++mu) {
+                        int64_t f[4] = {c[0], c[1], c[2], c[3]};
+                        int64_t b[4] = {c[0], c[1], c[2], c[3]};
+                        f[mu] = (c[mu] + 1) % dims[mu];
+                        b[mu] = (c[mu] + dims[mu] - 1) % dims[mu];
+                        int64_t sf = f[0] + dims[0] * (f[1] + dims[1] * (f[2] + dims[2] * f[3]));
+                        int64_t sb = b[0] + dims[0] * (b[1] + dims[1] * (b[2] + dims[2] * b[3]));
+                        hop_term(u[mu] + 18 * s, 0, in + 24 * sf, mu, -1.0, acc);
+                        hop_term(u[mu] + 18 * sb, 1, in + 24 * sb, mu, +1.0, acc);
+                    }
+                    memcpy(out + 24 * s, acc, sizeof acc);
+                }
+    return 0;
+}
+
 /* ------------------------------------------------------ half precision */
 
 /* IEEE binary32 -> binary16, round to nearest, ties to even, subnormals

@@ -31,6 +31,17 @@ def from_complex(c):
     return np.stack([c.real, c.imag], axis=-1).astype(np.float64)
 
 
+def read_golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([int(x) if i < 2 else float(x)
+                             for i, x in enumerate(line.split())])
+    return rows
+
+
 def read_golden(name):
     vals = {}
     with open(os.path.join(GOLDEN, name)) as f:
@@ -379,9 +390,133 @@ def pin_cshift(orc):
         assert np.array_equal(orc.cshift(u, dims, mu, 1), want), mu
 
 
+# ---------------------------------------------------------- Wilson hopping
+
+def _plane_wave(dims, p, spin, colour=0):
+    """psi(x) = exp(i p.x) e_spin (x) e_colour, shape (V, 4, 3, 2)."""
+    V = int(np.prod(dims))
+    idx = np.arange(V)
+    c = [idx % dims[0], (idx // dims[0]) % dims[1],
+         (idx // (dims[0] * dims[1])) % dims[2], idx // (dims[0] * dims[1] * dims[2])]
+    ph = sum(p[m] * c[m] for m in range(4))
+    psi = np.zeros((V, 4, 3, 2))
+    psi[:, spin, colour, 0] = np.cos(ph)
+    psi[:, spin, colour, 1] = np.sin(ph)
+    return psi, ph
+
+
+def free_spin_matrix(orc, dims, p):
+    """M(p) with (D psi)(x) = exp(i p.x) M(p) chi for psi = exp(i p.x) chi
+    on the unit gauge field; also checks that D maps each plane wave to a
+    plane wave of the same momentum (translation invariance)."""
+    V = int(np.prod(dims))
+    unit = [testgen.identity(V) for _ in range(4)]
+    M = np.zeros((4, 4), dtype=complex)
+    for sp in range(4):
+        psi, ph = _plane_wave(dims, p, sp)
+        out = orc.dslash(unit, psi, dims)
+        outc = out[..., 0] + 1j * out[..., 1]           # (V, 4, 3)
+        col = outc * np.exp(-1j * ph)[:, None, None]    # remove the phase
+        assert np.max(np.abs(col - col[0])) < 1e-12     # same at every site
+        assert np.max(np.abs(col[0][:, 1:])) < 1e-14    # colour untouched
+        M[:, sp] = col[0][:, 0]
+    return M
+
+
+def oracle_gammas(orc, dims=(4, 4, 4, 4)):
+    """gamma_mu read off the oracle: with momentum pi/2 along mu only,
+    M = 2 cos(pi/2) + 6 - 2i sin(pi/2) gamma_mu = 6 - 2i gamma_mu."""
+    g = []
+    for mu in range(4):
+        p = [0.0] * 4
+        p[mu] = 2 * np.pi / dims[mu]  # = pi/2 on an extent of 4
+        M = free_spin_matrix(orc, dims, p)
+        g.append((6 * np.eye(4) - M) / 2j)
+    return g
+
+
+def pin_dslash_free_field(orc):
+    """Clifford algebra {g_mu, g_nu} = 2 delta, hermiticity, and the free
+    spin matrix M(p) = sum_mu (2 cos p_mu - 2i sin p_mu g_mu) at generic
+    momenta on a 4x6x3x5 lattice; the basis is the declared one."""
+    g = oracle_gammas(orc)
+    for a in range(4):
+        assert np.allclose(g[a], g[a].conj().T, atol=1e-12)
+        for b in range(4):
+            anti = g[a] @ g[b] + g[b] @ g[a]
+            assert np.allclose(anti, 2 * np.eye(4) * (a == b), atol=1e-12), (a, b)
+    vals = read_golden_rows("chiral_gamma.txt")
+    for mu in range(4):
+        want = np.array([[complex(r[2 + 2 * c], r[3 + 2 * c]) for c in range(4)]
+                         for r in vals if r[0] == mu])
+        assert np.allclose(g[mu], want, atol=1e-12), mu
+    dims = (4, 6, 3, 5)
+    n = (1, 2, 1, 3)
+    p = [2 * np.pi * n[m] / dims[m] for m in range(4)]
+    M = free_spin_matrix(orc, dims, p)
+    c = sum(2 * np.cos(q) for q in p)
+    S = M - c * np.eye(4)
+    # -2i sum sin(p) gamma: anti-Hermitian, and S S^dagger = 4 sum sin^2 p
+    assert np.allclose(S, -S.conj().T, atol=1e-12)
+    assert np.allclose(S @ S.conj().T, 4 * sum(np.sin(q) ** 2 for q in p) * np.eye(4), atol=1e-11)
+
+
+def _random_spinor(V, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((V, 4, 3, 2))
+
+
+def _spin_apply(mat, psi):
+    pc = psi[..., 0] + 1j * psi[..., 1]
+    out = np.einsum('ab,vbc->vac', mat, pc)
+    return np.stack([out.real, out.imag], -1)
+
+
+def pin_dslash_gamma5_hermitian(orc):
+    """<phi, D psi> = <g5 D g5 phi, psi> on random SU(3) links (g5 =
+    g1 g2 g3 g4 from the oracle's own matrices)."""
+    g = oracle_gammas(orc)
+    g5 = g[0] @ g[1] @ g[2] @ g[3]
+    dims = (3, 4, 2, 5)
+    V = int(np.prod(dims))
+    links = [testgen.su3_field(V, field_id=70 + m) for m in range(4)]
+    phi, psi = _random_spinor(V, 1), _random_spinor(V, 2)
+    cdot = lambda a, b: np.sum((a[..., 0] - 1j * a[..., 1]) * (b[..., 0] + 1j * b[..., 1]))
+    lhs = cdot(phi, orc.dslash(links, psi, dims))
+    rhs = cdot(_spin_apply(g5, orc.dslash(links, _spin_apply(g5, phi), dims)), psi)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+def pin_dslash_gauge_covariant(orc):
+    """U'_mu(x) = g(x) U_mu(x) g(x + mu)^dagger, psi'(x) = g(x) psi(x)
+    give (D' psi')(x) = g(x) (D psi)(x) for random SU(3) g."""
+    dims = (3, 4, 2, 5)
+    V = int(np.prod(dims))
+    links = [testgen.su3_field(V, field_id=74 + m) for m in range(4)]
+    g = to_complex(testgen.su3_field(V, field_id=78))
+    psi = _random_spinor(V, 3)
+    arr = lambda f: f.reshape(dims[3], dims[2], dims[1], dims[0], *f.shape[1:])
+    def shift(f, mu):  # f(x + mu)
+        return np.roll(arr(f), -1, axis=3 - mu).reshape(f.shape)
+    newl = []
+    for mu in range(4):
+        u = to_complex(links[mu])
+        gn = shift(g, mu)
+        newl.append(from_complex(g @ u @ np.conj(np.transpose(gn, (0, 2, 1)))))
+    pc = psi[..., 0] + 1j * psi[..., 1]
+    psi2 = np.einsum('vab,vsb->vsa', g, pc)
+    psi2 = np.stack([psi2.real, psi2.imag], -1)
+    lhs = orc.dslash(newl, psi2, dims)
+    d = orc.dslash(links, psi, dims)
+    dc = d[..., 0] + 1j * d[..., 1]
+    rhs = np.einsum('vab,vsb->vsa', g, dc)
+    assert np.max(np.abs((lhs[..., 0] + 1j * lhs[..., 1]) - rhs)) < 1e-12
+
+
 ALL_PINS = [pin_identity, pin_phase_diag, pin_signed_permutations,
             pin_unitary_inverse, pin_numpy_matmul, pin_nonsymmetric,
             pin_product_invariants, pin_associative, pin_listing2,
             pin_fused_reductions, pin_fused_numpy, pin_fused_unitary,
             pin_quantisers, pin_c12_rebuild, pin_layouts, pin_roundtrip,
-            pin_metrics, pin_cshift]
+            pin_metrics, pin_cshift, pin_dslash_free_field,
+            pin_dslash_gamma5_hermitian, pin_dslash_gauge_covariant]

@@ -34,6 +34,14 @@ MUTANTS = [
      "n[mu] = ((c[mu] - shift) % dims[mu] + dims[mu]) % dims[mu];"),
     ("cshift_no_wrap", "n[mu] = ((c[mu] + shift) % dims[mu] + dims[mu]) % dims[mu];",
      "n[mu] = (c[mu] + shift < dims[mu] && c[mu] + shift >= 0) ? c[mu] + shift : c[mu];"),
+    ("dslash_sign_swap", "hop_term(u[mu] + 18 * s, 0, in + 24 * sf, mu, -1.0, acc);",
+     "hop_term(u[mu] + 18 * s, 0, in + 24 * sf, mu, +1.0, acc);"),
+    ("dslash_no_dagger", "double mi = dagger ? -im_(m, b, a) : im_(m, a, b);",
+     "double mi = dagger ? im_(m, b, a) : im_(m, a, b);"),
+    ("dslash_backward_link_local", "hop_term(u[mu] + 18 * sb, 1, in + 24 * sb, mu, +1.0, acc);",
+     "hop_term(u[mu] + 18 * s, 1, in + 24 * sb, mu, +1.0, acc);"),
+    ("dslash_gamma_entry", "     {{0, 0}, {1, 0}, {0, 0}, {0, 0}},\n     {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},\n    /* gamma_3 */",
+     "     {{0, 0}, {-1, 0}, {0, 0}, {0, 0}},\n     {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},\n    /* gamma_3 */"),
     ("det_sign", "r += re_(m, 0, j) * cr - im_(m, 0, j) * ci;",
      "r += re_(m, 0, j) * cr + im_(m, 0, j) * ci;"),
 ]
