@@ -252,8 +252,10 @@ int oracle_dslash(const double *const *u, const double *in, double *out,
     for (int d = 0; d < 4; ++d)
         if (dims[d] <= 0)
             return -1;
-    int64_t c[4];
-    for (c[3] = 0; c[3] < dims[3]; ++c[3])
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < dims[3]; ++t) {
+        int64_t c[4];
+        c[3] = t;
         for (c[2] = 0; c[2] < dims[2]; ++c[2])
             for (c[1] = 0; c[1] < dims[1]; ++c[1])
                 for (c[0] = 0; c[0] < dims[0]; ++c[0]) {
@@ -273,6 +275,7 @@ int oracle_dslash(const double *const *u, const double *in, double *out,
                     }
                     memcpy(out + 24 * s, acc, sizeof acc);
                 }
+    }
     return 0;
 }
 

@@ -55,6 +55,10 @@ def _load():
                                      ctypes.c_int64, ctypes.c_int64,
                                      ctypes.c_void_p]
         lib.su3gen_sites.restype = None
+        lib.su3gen_spinor.argtypes = [ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_void_p]
+        lib.su3gen_spinor.restype = None
         lib.su3gen_sites.argtypes = [ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p]
@@ -94,6 +98,16 @@ def su3_sites(sites, seed: int = DEFAULT_SEED,
         _load().su3gen_sites(seed, field_id,
                              s.ctypes.data_as(ctypes.c_void_p), s.size,
                              out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def spinor_field(V: int, seed: int = DEFAULT_SEED, field_id: int = 200,
+                 s_begin: int = 0) -> np.ndarray:
+    """Gaussian spinor field, shape (V, 4, 3, 2): spin, colour, re/im."""
+    out = np.empty((V, 4, 3, 2), dtype=np.float64)
+    if V:
+        _load().su3gen_spinor(seed, field_id, s_begin, V,
+                              out.ctypes.data_as(ctypes.c_void_p))
     return out
 
 

@@ -175,3 +175,24 @@ void su3gen_sites(uint64_t seed, uint64_t field_id, const int64_t *sites,
         }
     }
 }
+
+/* Gaussian spinor field: 4 spins x 3 colours, each component a complex
+ * Gaussian (re, im independent standard normals), site s drawing
+ * n = 24*s + m from the same counter stream; out[count*24] in the layout
+ * ((s*4 + spin)*3 + colour)*2 + c. */
+void su3gen_spinor(uint64_t seed, uint64_t field_id, int64_t s_begin,
+                   int64_t count, double *out)
+{
+    const uint64_t key = su3gen_key(seed, field_id);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) {
+        const uint64_t n0 = 24 * (uint64_t)(s_begin + t);
+        for (int p = 0; p < 12; ++p) {
+            double ua = unit_open0(mix64(key + (n0 + 2 * p + 1) * GOLDEN));
+            double ub = unit_open0(mix64(key + (n0 + 2 * p + 2) * GOLDEN));
+            double rho = sqrt(-2.0 * log(ua));
+            out[24 * t + 2 * p] = rho * cos(2.0 * M_PI * ub);
+            out[24 * t + 2 * p + 1] = rho * sin(2.0 * M_PI * ub);
+        }
+    }
+}
