@@ -15,7 +15,8 @@ Prints ONE JSON line on stdout (progress goes to stderr):
   cpu_baseline the FP64 oracle on the host cores, on a bounded sample
   variants     the precision forms (F32, F16 with F32 arithmetic, two-row
                compressed F32) at 48^4, the layouts (AoS, AoS+LDS, AoSoA),
-               the volume sweep, fused vs chained expressions at 32^4, the
+               the volume sweep, the shifted operands, the Wilson hopping
+               term at 48^4, fused vs chained expressions at 32^4, the
                64-lattice batch replayed from a HIP graph, and the triad
                ceiling -- each in GB/s of its own algorithmic bytes
 """
@@ -40,6 +41,12 @@ METRIC = ("SU(3)×SU(3) achieved HBM GB/s (% of peak) at 48^4, "
 BYTES_PER_SITE = {0: 432, 1: 216, 2: 108, 3: 144}   # MUL by precision
 FLOPS_PER_SITE = {0: 198, 1: 396, 2: 414, 3: 18, 4: 234}
 REAL_BYTES = {0: 8, 1: 4, 2: 2, 3: 4}
+# Wilson hopping term, keyed (spinor precision, link precision): four link
+# matrices + input and output spinors once each; the customary 1320 flops
+# per site (8 hops of 12 projection + 132 colour + 24 accumulation flops,
+# less the first accumulation)
+DSLASH_BYTES_PER_SITE = {(0, 0): 960, (1, 1): 480, (1, 3): 384}
+DSLASH_FLOPS_PER_SITE = 1320
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16_f32acc", 3: "c12_f32"}
 
 
@@ -348,6 +355,34 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
             "mult_shifted_gbps": round(432 * V / (ms_m * 1e-3) / 1e9, 1)}
         log(f"shift mu {mu}: {shift[f'mu{mu}']}")
     out["shift_f64_48^4"] = shift
+
+    # Wilson hopping term at 48^4: algorithmic bytes per site = four link
+    # matrices + one input spinor + one output spinor, each moved once
+    # (F64: 4*144 + 192 + 192 = 960; F32: 480; F32 with compressed links:
+    # 4*48 + 96 + 96 = 384); 1320 flops per site
+    dsl = {}
+    host_psi = testgen.spinor_field(V, seed=args.seed, field_id=200)
+    for sp, lp, name in ((su3.SU3_F64, su3.SU3_F64, "f64"), (su3.SU3_F32, su3.SU3_F32, "f32"),
+                         (su3.SU3_F32, su3.SU3_C12_F32, "f32_c12")):
+        for lname, lay, lanes in (("soa", SOA, 0), ("aosoa64", AOSOA, 64)):
+            U = [make(dims, lp, lay, lanes, testgen.FID_U0 + mu) for mu in range(4)]
+            fin = su3.spinor_tensor(dims, sp, lay, lanes)
+            su3.su3_field_upload(fin, host_psi, stream)
+            fout = su3.spinor_tensor(dims, sp, lay, lanes)
+            cfg = tune(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims)
+            ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+            b = DSLASH_BYTES_PER_SITE[(sp, lp)] * V
+            key = f"{name}_{lname}"
+            dsl[key] = {"us": round(ms * 1e3, 2),
+                        "gbps": round(b / (ms * 1e-3) / 1e9, 1),
+                        "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "gflops": round(DSLASH_FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
+                        "bytes_per_site": DSLASH_BYTES_PER_SITE[(sp, lp)],
+                        "launch": cfg}
+            log(f"dslash {key}: {dsl[key]}")
+            del U, fin, fout
+    del host_psi
+    out["dslash_48^4"] = dsl
 
     # fused vs chained at 32^4 with four link fields
     d = (32, 32, 32, 32)

@@ -97,7 +97,10 @@ typedef enum su3_expr {
     /* launch-tuning keys of su3_cshift and su3_mult_shifted (accepted by
      * su3_autotune / su3_launch_get / su3_launch_set only) */
     SU3_EXPR_CSHIFT = 5,
-    SU3_EXPR_MUL_SHIFTED = 6
+    SU3_EXPR_MUL_SHIFTED = 6,
+    /* launch-tuning key of su3_dslash; its precision is the links' one
+     * (SU3_F64, SU3_F32 or SU3_C12_F32) */
+    SU3_EXPR_DSLASH = 7
 } su3_expr;
 
 typedef struct su3_field su3_field;
@@ -164,12 +167,13 @@ su3_status su3_field_free(su3_field *f);
 /* Device address and size of a field's storage. */
 su3_status su3_field_data(const su3_field *f, void **dev_ptr, size_t *bytes);
 
-/* Quantise and pack V*18 canonical doubles into the field (padding sites
- * written as zero).  Completes before returning. */
+/* Quantise and pack V*18 canonical doubles (V*24 for a spinor field) into
+ * the field (padding sites written as zero).  Completes before returning. */
 su3_status su3_field_upload(su3_field *f, const double *host_aos,
                             void *stream);
 
-/* Unpack the field into V*18 canonical doubles (exact widening).  For
+/* Unpack the field into V*18 canonical doubles (V*24 for a spinor field;
+ * exact widening).  For
  * SU3_C12_F32, rows 0-1 are the stored values and row 2 is rebuilt in
  * double as conj(row0 x row1).  Completes before returning. */
 su3_status su3_field_download(const su3_field *f, double *host_aos,
@@ -215,6 +219,42 @@ su3_status su3_cshift(su3_field *dst, const su3_field *src, int32_t mu,
 su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
                             const su3_field *y, int32_t mu, int32_t shift,
                             void *stream);
+
+/* ------------------------------------------------------ spinor fields */
+
+/* A spinor field holds 4 spins x 3 colours of complex numbers per site
+ * (12 complex entries, entry 3 * spin + colour, stored like a matrix
+ * field's entries in the same layouts).  Precisions SU3_F64 and SU3_F32
+ * (SU3_ERR_UNSUPPORTED otherwise).  The handles are su3_field handles:
+ * su3_field_free, su3_field_data, su3_field_upload / su3_field_download
+ * (V*24 canonical doubles: site, spin, colour, re/im) and
+ * su3_field_download_raw apply to them; every matrix routine rejects them
+ * (SU3_ERR_MISMATCH).  Arguments and errors as for the su3_field_* calls. */
+su3_status su3_spinor_bytes(const int32_t dims[4], su3_precision prec,
+                            su3_layout layout, int32_t lanes, size_t *bytes);
+su3_status su3_spinor_alloc(su3_field **out, const int32_t dims[4],
+                            su3_precision prec, su3_layout layout,
+                            int32_t lanes);
+su3_status su3_spinor_wrap(su3_field **out, void *dev_ptr, size_t bytes,
+                           const int32_t dims[4], su3_precision prec,
+                           su3_layout layout, int32_t lanes);
+
+/* Wilson hopping term, the stencil of the Dslash operator that the
+ * conclusions (Section 6) name as the next port, periodic in all four
+ * directions (0..3 = x, y, z, t, x fastest):
+ *   out(x) = sum_mu [ (1 - g_mu) U_mu(x) in(x + mu_hat)
+ *                   + (1 + g_mu) U_mu(x - mu_hat)^dagger in(x - mu_hat) ]
+ * with Euclidean chiral-basis gamma matrices g_k = [[0, -i s_k],
+ * [i s_k, 0]] (s_k the Pauli matrices), g_4 = [[0, 1], [1, 0]].
+ * `links[mu]` are four matrix fields (one per direction) and `in` / `out`
+ * spinor fields, all of one lattice, layout and lanes on one device
+ * (SU3_ERR_MISMATCH otherwise).  Precisions: SU3_F64 spinors with SU3_F64
+ * links (double arithmetic), SU3_F32 spinors with SU3_F32 or SU3_C12_F32
+ * links (single arithmetic; the compressed third row is rebuilt in
+ * registers); other pairs SU3_ERR_UNSUPPORTED.  `out` must not overlap
+ * `in` or a link field (SU3_ERR_ALIAS).  Asynchronous on `stream`. */
+su3_status su3_dslash(su3_field *out, su3_field *const links[4],
+                      const su3_field *in, void *stream);
 
 /* ------------------------------------------------------------ batches */
 

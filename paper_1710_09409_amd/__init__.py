@@ -37,6 +37,7 @@ SU3_F64, SU3_F32, SU3_F16_F32ACC, SU3_C12_F32 = 0, 1, 2, 3
 SU3_LAYOUT_AOS, SU3_LAYOUT_SOA, SU3_LAYOUT_AOSOA = 0, 1, 2
 SU3_EXPR_MUL, SU3_EXPR_MUL3, SU3_EXPR_MULADD, SU3_EXPR_ADD, SU3_EXPR_APB_AB = range(5)
 SU3_EXPR_CSHIFT, SU3_EXPR_MUL_SHIFTED = 5, 6  # launch-tuning keys only
+SU3_EXPR_DSLASH = 7  # launch-tuning key of su3_dslash (precision = links')
 N_OPERANDS = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}
 
 # exported symbols of su3.h, in declaration order
@@ -44,7 +45,8 @@ SYMBOLS = (
     "su3_field_bytes", "su3_field_alloc", "su3_field_wrap", "su3_field_free",
     "su3_field_data", "su3_field_upload", "su3_field_download",
     "su3_field_download_raw", "su3_mult", "su3_fused_eval", "su3_cshift",
-    "su3_mult_shifted",
+    "su3_mult_shifted", "su3_spinor_bytes", "su3_spinor_alloc",
+    "su3_spinor_wrap", "su3_dslash",
     "su3_batch_create", "su3_batch_launch", "su3_batch_destroy",
     "su3_batch_tiles", "su3_autotune", "su3_batch_autotune", "su3_launch_get",
     "su3_launch_set",
@@ -115,6 +117,10 @@ def load():
         "su3_fused_eval": [vp, i32, vp, i32, vp],
         "su3_cshift": [vp, vp, i32, i32, vp],
         "su3_mult_shifted": [vp, vp, vp, i32, i32, vp],
+        "su3_spinor_bytes": [dims_t, i32, i32, i32, ctypes.POINTER(sz)],
+        "su3_spinor_alloc": [pp, dims_t, i32, i32, i32],
+        "su3_spinor_wrap": [pp, vp, sz, dims_t, i32, i32, i32],
+        "su3_dslash": [vp, vp, vp, vp],
         "su3_batch_create": [pp, vp, vp, vp, i32, vp],
         "su3_batch_launch": [vp, vp],
         "su3_batch_destroy": [vp],
@@ -189,10 +195,16 @@ class Field:
     layout: int
     lanes: int
     owner: object = None  # torch tensor for wrapped fields
+    spinor: bool = False
 
     @property
     def V(self):
         return volume(self.dims)
+
+    @property
+    def site_shape(self):
+        """Canonical host shape of one site: (3, 3, 2) or (4, 3, 2)."""
+        return (4, 3, 2) if self.spinor else (3, 3, 2)
 
     def __del__(self):
         if self.handle and _lib is not None:
@@ -248,14 +260,15 @@ def su3_field_data(f: Field):
 
 def su3_field_upload(f: Field, host, stream=None):
     a = np.ascontiguousarray(host, dtype=np.float64)
-    if a.size != 18 * f.V:
-        raise ValueError(f"expected {18 * f.V} doubles, got {a.size}")
+    n = f.V * int(np.prod(f.site_shape))
+    if a.size != n:
+        raise ValueError(f"expected {n} doubles, got {a.size}")
     _check("su3_field_upload",
            load().su3_field_upload(f.handle, a.ctypes.data, _stream(stream)))
 
 
 def su3_field_download(f: Field, stream=None):
-    out = np.empty((f.V, 3, 3, 2), dtype=np.float64)
+    out = np.empty((f.V,) + f.site_shape, dtype=np.float64)
     _check("su3_field_download",
            load().su3_field_download(f.handle, out.ctypes.data, _stream(stream)))
     return out
@@ -294,6 +307,59 @@ def su3_mult_shifted(z: Field, x: Field, y: Field, mu, shift, stream=None):
     _check("su3_mult_shifted",
            load().su3_mult_shifted(z.handle, x.handle, y.handle, int(mu),
                                    int(shift), _stream(stream)))
+
+
+# ---------------------------------------------------------- spinor fields
+
+def su3_spinor_bytes(dims, prec, layout, lanes=0):
+    n = ctypes.c_size_t()
+    _check("su3_spinor_bytes",
+           load().su3_spinor_bytes(_dims(dims), prec, layout, lanes, ctypes.byref(n)))
+    return n.value
+
+
+def su3_spinor_alloc(dims, prec, layout, lanes=0):
+    h = ctypes.c_void_p()
+    _check("su3_spinor_alloc",
+           load().su3_spinor_alloc(ctypes.byref(h), _dims(dims), prec, layout, lanes))
+    return Field(h.value, tuple(dims), prec, layout, lanes, spinor=True)
+
+
+def su3_spinor_wrap(tensor_or_ptr, dims, prec, layout, lanes=0, nbytes=None):
+    """Describe device memory as a spinor field (as su3_field_wrap)."""
+    if isinstance(tensor_or_ptr, torch.Tensor):
+        t = tensor_or_ptr
+        ptr = t.data_ptr()
+        nbytes = t.numel() * t.element_size() if nbytes is None else nbytes
+        owner = t
+    else:
+        ptr, owner = int(tensor_or_ptr), None
+        if nbytes is None:
+            raise ValueError("nbytes is required with a raw pointer")
+    h = ctypes.c_void_p()
+    _check("su3_spinor_wrap",
+           load().su3_spinor_wrap(ctypes.byref(h), ptr, nbytes, _dims(dims),
+                                  prec, layout, lanes))
+    return Field(h.value, tuple(dims), prec, layout, lanes, owner, spinor=True)
+
+
+def spinor_tensor(dims, prec, layout, lanes=0, device="cuda"):
+    """A torch byte tensor sized for a spinor field, wrapped as a Field."""
+    n = su3_spinor_bytes(dims, prec, layout, lanes)
+    t = torch.zeros(n, dtype=torch.uint8, device=device)
+    return su3_spinor_wrap(t, dims, prec, layout, lanes)
+
+
+def su3_dslash(out: Field, links, inp: Field, stream=None):
+    """Wilson hopping term out = D in with links[mu], mu = 0..3."""
+    if len(links) != 4:
+        raise ValueError("links must hold 4 fields")
+    arr = (ctypes.c_void_p * 4)(*[u.handle if u is not None else None
+                                  for u in links])
+    _check("su3_dslash",
+           load().su3_dslash(out.handle if out is not None else None, arr,
+                             inp.handle if inp is not None else None,
+                             _stream(stream)))
 
 
 # --------------------------------------------------------------- batches

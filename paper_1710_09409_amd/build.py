@@ -1,8 +1,8 @@
 """Build libsu3.so in-tree for gfx950 with hipcc.
 
 The kernel unit su3_kprec.hip is compiled once per storage precision
-(-DSU3_PREC=0..3) in parallel, then linked with the batch/yardstick unit and
-the host C-ABI unit.  Always recompiles.
+(-DSU3_PREC=0..3) in parallel, then linked with the batch/yardstick unit,
+the Wilson hopping unit and the host C-ABI unit.  Always recompiles.
 """
 from __future__ import annotations
 
@@ -36,6 +36,8 @@ def _units():
                       os.path.join(OBJ, f"su3_kprec_p{p}.o")))
     units.append((["-x", "hip", os.path.join(CSRC, "su3_kmisc.hip")],
                   os.path.join(OBJ, "su3_kmisc.o")))
+    units.append((["-x", "hip", os.path.join(CSRC, "su3_kdslash.hip")],
+                  os.path.join(OBJ, "su3_kdslash.o")))
     units.append((["-x", "hip", os.path.join(CSRC, "su3_api.cpp")],
                   os.path.join(OBJ, "su3_api.o")))
     return units

@@ -35,7 +35,12 @@ struct su3_field {
     int32_t rbytes;
     int32_t owns;
     int32_t device;
+    int32_t kind;   // 0: SU(3) matrices, 1: spinors
+    int32_t canon;  // complex entries per site on the host (9 or 12)
 };
+
+enum { KIND_MATRIX = 0, KIND_SPINOR = 1 };
+static const int kSpinorEntries = 12;
 
 struct su3_batch {
     BatchItem *d_items;
@@ -85,12 +90,16 @@ struct Shape {
 };
 
 static su3_status make_shape(const int32_t dims[4], int prec, int layout,
-                             int32_t lanes, Shape *out)
+                             int32_t lanes, Shape *out,
+                             int kind = KIND_MATRIX)
 {
     if (!dims)
         return fail(SU3_ERR_INVALID_ARG, "dims is NULL");
     if (prec < SU3_F64 || prec > SU3_C12_F32)
         return fail(SU3_ERR_INVALID_ARG, "unknown precision %d", prec);
+    if (kind == KIND_SPINOR && prec != SU3_F64 && prec != SU3_F32)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "spinor fields are stored in SU3_F64 or SU3_F32");
     if (layout < SU3_LAYOUT_AOS || layout > SU3_LAYOUT_AOSOA)
         return fail(SU3_ERR_INVALID_ARG, "unknown layout %d", layout);
     int64_t V = 1;
@@ -104,7 +113,7 @@ static su3_status make_shape(const int32_t dims[4], int prec, int layout,
     }
     Shape s;
     s.V = V;
-    s.E = entries_of(prec);
+    s.E = kind == KIND_SPINOR ? kSpinorEntries : entries_of(prec);
     s.rbytes = real_bytes(prec);
     if (layout == SU3_LAYOUT_AOS) {
         s.L = 1;
@@ -163,22 +172,35 @@ static inline int64_t stored_index(const su3_field *f, int64_t s, int e, int c)
 
 // ------------------------------------------------------------ fields
 
-extern "C" su3_status su3_field_bytes(const int32_t dims[4],
-                                      su3_precision prec, su3_layout layout,
-                                      int32_t lanes, size_t *bytes)
+static su3_status bytes_of_kind(const int32_t dims[4], int prec, int layout,
+                                int32_t lanes, size_t *bytes, int kind)
 {
     if (!bytes)
         return fail(SU3_ERR_INVALID_ARG, "bytes is NULL");
     Shape s;
-    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    su3_status st = make_shape(dims, prec, layout, lanes, &s, kind);
     if (st != SU3_OK)
         return st;
     *bytes = s.bytes;
     return SU3_OK;
 }
 
+extern "C" su3_status su3_field_bytes(const int32_t dims[4],
+                                      su3_precision prec, su3_layout layout,
+                                      int32_t lanes, size_t *bytes)
+{
+    return bytes_of_kind(dims, prec, layout, lanes, bytes, KIND_MATRIX);
+}
+
+extern "C" su3_status su3_spinor_bytes(const int32_t dims[4],
+                                       su3_precision prec, su3_layout layout,
+                                       int32_t lanes, size_t *bytes)
+{
+    return bytes_of_kind(dims, prec, layout, lanes, bytes, KIND_SPINOR);
+}
+
 static su3_field *new_handle(const int32_t dims[4], int prec, int layout,
-                             int32_t lanes, const Shape &s)
+                             int32_t lanes, const Shape &s, int kind)
 {
     su3_field *f = new su3_field();
     f->ptr = nullptr;
@@ -194,17 +216,18 @@ static su3_field *new_handle(const int32_t dims[4], int prec, int layout,
     f->rbytes = s.rbytes;
     f->owns = 0;
     f->device = -1;
+    f->kind = kind;
+    f->canon = kind == KIND_SPINOR ? kSpinorEntries : 9;
     return f;
 }
 
-extern "C" su3_status su3_field_alloc(su3_field **out, const int32_t dims[4],
-                                      su3_precision prec, su3_layout layout,
-                                      int32_t lanes)
+static su3_status alloc_of_kind(su3_field **out, const int32_t dims[4],
+                                int prec, int layout, int32_t lanes, int kind)
 {
     if (!out)
         return fail(SU3_ERR_INVALID_ARG, "out is NULL");
     Shape s;
-    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    su3_status st = make_shape(dims, prec, layout, lanes, &s, kind);
     if (st != SU3_OK)
         return st;
     int dev = 0;
@@ -221,7 +244,7 @@ extern "C" su3_status su3_field_alloc(su3_field **out, const int32_t dims[4],
         (void)hipFree(p);
         return hip_fail(e, "hipMemset");
     }
-    su3_field *f = new_handle(dims, prec, layout, lanes, s);
+    su3_field *f = new_handle(dims, prec, layout, lanes, s, kind);
     f->ptr = p;
     f->owns = 1;
     f->device = dev;
@@ -229,10 +252,23 @@ extern "C" su3_status su3_field_alloc(su3_field **out, const int32_t dims[4],
     return SU3_OK;
 }
 
-extern "C" su3_status su3_field_wrap(su3_field **out, void *dev_ptr,
-                                     size_t bytes, const int32_t dims[4],
-                                     su3_precision prec, su3_layout layout,
-                                     int32_t lanes)
+extern "C" su3_status su3_field_alloc(su3_field **out, const int32_t dims[4],
+                                      su3_precision prec, su3_layout layout,
+                                      int32_t lanes)
+{
+    return alloc_of_kind(out, dims, prec, layout, lanes, KIND_MATRIX);
+}
+
+extern "C" su3_status su3_spinor_alloc(su3_field **out, const int32_t dims[4],
+                                       su3_precision prec, su3_layout layout,
+                                       int32_t lanes)
+{
+    return alloc_of_kind(out, dims, prec, layout, lanes, KIND_SPINOR);
+}
+
+static su3_status wrap_of_kind(su3_field **out, void *dev_ptr, size_t bytes,
+                               const int32_t dims[4], int prec, int layout,
+                               int32_t lanes, int kind)
 {
     if (!out)
         return fail(SU3_ERR_INVALID_ARG, "out is NULL");
@@ -241,7 +277,7 @@ extern "C" su3_status su3_field_wrap(su3_field **out, void *dev_ptr,
     if (((uintptr_t)dev_ptr & 15) != 0)
         return fail(SU3_ERR_INVALID_ARG, "dev_ptr is not 16-byte aligned");
     Shape s;
-    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    su3_status st = make_shape(dims, prec, layout, lanes, &s, kind);
     if (st != SU3_OK)
         return st;
     if (bytes < s.bytes)
@@ -263,12 +299,30 @@ extern "C" su3_status su3_field_wrap(su3_field **out, void *dev_ptr,
         return fail(SU3_ERR_INVALID_ARG,
                     "dev_ptr is not device memory of the current device %d",
                     dev);
-    su3_field *f = new_handle(dims, prec, layout, lanes, s);
+    su3_field *f = new_handle(dims, prec, layout, lanes, s, kind);
     f->ptr = dev_ptr;
     f->owns = 0;
     f->device = dev;
     *out = f;
     return SU3_OK;
+}
+
+extern "C" su3_status su3_field_wrap(su3_field **out, void *dev_ptr,
+                                     size_t bytes, const int32_t dims[4],
+                                     su3_precision prec, su3_layout layout,
+                                     int32_t lanes)
+{
+    return wrap_of_kind(out, dev_ptr, bytes, dims, prec, layout, lanes,
+                        KIND_MATRIX);
+}
+
+extern "C" su3_status su3_spinor_wrap(su3_field **out, void *dev_ptr,
+                                      size_t bytes, const int32_t dims[4],
+                                      su3_precision prec, su3_layout layout,
+                                      int32_t lanes)
+{
+    return wrap_of_kind(out, dev_ptr, bytes, dims, prec, layout, lanes,
+                        KIND_SPINOR);
 }
 
 extern "C" su3_status su3_field_free(su3_field *f)
@@ -338,7 +392,7 @@ extern "C" su3_status su3_field_upload(su3_field *f, const double *host,
         for (int e = 0; e < f->E; ++e)
             for (int c = 0; c < 2; ++c)
                 put_real(img.data(), f->prec, stored_index(f, s, e, c),
-                         host[18 * s + 2 * e + c]);
+                         host[2 * f->canon * s + 2 * e + c]);
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(f->ptr, img.data(), f->bytes,
                            hipMemcpyHostToDevice, st),
@@ -372,12 +426,12 @@ extern "C" su3_status su3_field_download(const su3_field *f, double *host,
     if (st != SU3_OK)
         return st;
     for (int64_t s = 0; s < f->V; ++s) {
-        double *m = host + 18 * s;
+        double *m = host + 2 * f->canon * s;
         for (int e = 0; e < f->E; ++e)
             for (int c = 0; c < 2; ++c)
                 m[2 * e + c] = get_real(img.data(), f->prec,
                                         stored_index(f, s, e, c));
-        if (f->prec == SU3_C12_F32) {
+        if (f->kind == KIND_MATRIX && f->prec == SU3_C12_F32) {
             // row 2 = conj(row0 x row1), in double
             for (int k = 0; k < 3; ++k) {
                 const int p = (k + 1) % 3, q = (k + 2) % 3;
@@ -457,7 +511,6 @@ static bool g_cache_loaded = false;
 
 static su3_launch default_launch(int expr, int prec, int layout)
 {
-    (void)expr;
     (void)prec;
     su3_launch c;
     c.block = 64;
@@ -468,6 +521,13 @@ static su3_launch default_launch(int expr, int prec, int layout)
     c.tile_sites = 4096;
     c.occupancy = layout == SU3_LAYOUT_AOS ? 0 : 5;
     c.schedule = layout == SU3_LAYOUT_AOS ? 0 : 1;
+    if (expr == SU3_EXPR_DSLASH) {
+        // neighbours re-read each spinor eight times: keep loads cached
+        c.block = 128;
+        c.nontemporal = 2;
+        c.occupancy = 0;
+        c.schedule = 0;
+    }
     return c;
 }
 
@@ -599,7 +659,7 @@ static void append_cache(const Key &k, const su3_launch &c, double us)
 
 static bool same_shape(const su3_field *a, const su3_field *b)
 {
-    return a->prec == b->prec && a->layout == b->layout &&
+    return a->kind == b->kind && a->prec == b->prec && a->layout == b->layout &&
            a->lanes == b->lanes && a->dims[0] == b->dims[0] &&
            a->dims[1] == b->dims[1] && a->dims[2] == b->dims[2] &&
            a->dims[3] == b->dims[3] && a->device == b->device;
@@ -617,6 +677,9 @@ static su3_status validate_item(const su3_field *z, int expr,
 {
     if (!z)
         return fail(SU3_ERR_INVALID_ARG, "output field is NULL");
+    if (z->kind != KIND_MATRIX)
+        return fail(SU3_ERR_MISMATCH,
+                    "a spinor field where an SU(3) matrix field is expected");
     if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_APB_AB)
         return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
     if (!ops)
@@ -760,6 +823,9 @@ extern "C" su3_status su3_cshift(su3_field *dst, const su3_field *src,
         return fail(SU3_ERR_INVALID_ARG, "field is NULL");
     if (mu < 0 || mu > 3)
         return fail(SU3_ERR_INVALID_ARG, "direction %d not in [0, 3]", mu);
+    if (dst->kind != KIND_MATRIX || src->kind != KIND_MATRIX)
+        return fail(SU3_ERR_MISMATCH,
+                    "a spinor field where an SU(3) matrix field is expected");
     if (!same_shape(dst, src))
         return fail(SU3_ERR_MISMATCH, "dst and src differ in dims, precision, "
                                       "layout, lanes or device");
@@ -777,6 +843,9 @@ extern "C" su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
         return fail(SU3_ERR_INVALID_ARG, "field is NULL");
     if (mu < 0 || mu > 3)
         return fail(SU3_ERR_INVALID_ARG, "direction %d not in [0, 3]", mu);
+    if (z->kind != KIND_MATRIX)
+        return fail(SU3_ERR_MISMATCH,
+                    "a spinor field where an SU(3) matrix field is expected");
     if (!same_shape(z, x) || !same_shape(z, y))
         return fail(SU3_ERR_MISMATCH, "operands differ in dims, precision, "
                                       "layout, lanes or device");
@@ -787,14 +856,104 @@ extern "C" su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
     return launch_shift_op(1, z, x, y, mu, shift, stream);
 }
 
+// ------------------------------------------------------ Wilson hopping
+
+static int spinor_prec_of_links(int link_prec)
+{
+    return link_prec == SU3_F64 ? SU3_F64 : SU3_F32;
+}
+
+// One site per lane, one-shot grid, the tuned (or default) block and
+// occupancy of the key (SU3_EXPR_DSLASH, link precision, layout, lanes,
+// volume).
+static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
+                                   const su3_field *in, void *stream,
+                                   const su3_launch *forced = nullptr)
+{
+    const su3_field *u0 = links[0];
+    const su3_launch c =
+        forced ? *forced
+               : lookup_launch(SU3_EXPR_DSLASH, u0->prec, u0->layout,
+                               u0->lanes, u0->V);
+    DslashArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.out = out->ptr;
+    a.in = in->ptr;
+    for (int mu = 0; mu < 4; ++mu)
+        a.u[mu] = links[mu]->ptr;
+    a.gs = geom_of(out);
+    a.gl = geom_of(u0);
+    a.nsites = (int32_t)out->V;
+    int64_t stride = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        a.dims[mu] = (uint32_t)out->dims[mu];
+        a.stride[mu] = (uint32_t)stride;
+        stride *= out->dims[mu];
+    }
+    const int64_t grid = (out->V + c.block - 1) / c.block;
+    hipError_t e = launch_dslash(out->prec, u0->prec, c.nontemporal, c.block,
+                                 (int)grid,
+                                 occupancy_reserve(out->device, c.occupancy),
+                                 a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "Dslash kernel launch");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_dslash(su3_field *out, su3_field *const links[4],
+                                 const su3_field *in, void *stream)
+{
+    if (!out || !in || !links)
+        return fail(SU3_ERR_INVALID_ARG, "field or link list is NULL");
+    for (int mu = 0; mu < 4; ++mu)
+        if (!links[mu])
+            return fail(SU3_ERR_INVALID_ARG, "links[%d] is NULL", mu);
+    if (out->kind != KIND_SPINOR || in->kind != KIND_SPINOR)
+        return fail(SU3_ERR_MISMATCH, "in and out must be spinor fields");
+    if (!same_shape(out, in))
+        return fail(SU3_ERR_MISMATCH, "in and out differ in dims, precision, "
+                                      "layout, lanes or device");
+    for (int mu = 0; mu < 4; ++mu) {
+        const su3_field *u = links[mu];
+        if (u->kind != KIND_MATRIX)
+            return fail(SU3_ERR_MISMATCH, "links[%d] is not a matrix field", mu);
+        if (!same_shape(u, links[0]))
+            return fail(SU3_ERR_MISMATCH,
+                        "links[%d] differs from links[0] in dims, precision, "
+                        "layout, lanes or device", mu);
+        if (std::memcmp(u->dims, out->dims, sizeof u->dims) != 0 ||
+            u->layout != out->layout || u->lanes != out->lanes ||
+            u->device != out->device)
+            return fail(SU3_ERR_MISMATCH,
+                        "links[%d] differs from the spinors in dims, layout, "
+                        "lanes or device", mu);
+    }
+    const int lp = links[0]->prec;
+    if (lp == SU3_F16_F32ACC || spinor_prec_of_links(lp) != out->prec)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "precision pair (spinor %d, links %d) not supported: "
+                    "F64 spinors take F64 links, F32 spinors F32 or C12 links",
+                    out->prec, lp);
+    if (overlaps(out, in))
+        return fail(SU3_ERR_ALIAS, "out overlaps in (a stencil gathers "
+                                   "neighbours: it cannot run in place)");
+    for (int mu = 0; mu < 4; ++mu)
+        if (overlaps(out, links[mu]))
+            return fail(SU3_ERR_ALIAS, "out overlaps links[%d]", mu);
+    return launch_dslash_op(out, links, in, stream);
+}
+
 // ------------------------------------------------------- launch tuning
 
 static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
                          int32_t lanes, const int32_t dims[4], Key *k,
                          Shape *shape)
 {
-    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_MUL_SHIFTED)
+    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_DSLASH)
         return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
+    if (expr == SU3_EXPR_DSLASH && prec == SU3_F16_F32ACC)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "Dslash links are stored in F64, F32 or C12");
     Shape s;
     su3_status st = make_shape(dims, prec, layout, lanes, &s);
     if (st != SU3_OK)
@@ -906,6 +1065,23 @@ static std::vector<su3_launch> candidates(int layout)
     return out;
 }
 
+// Candidates for the Wilson hopping kernel: one site per lane, one-shot
+// grid; block, occupancy cap and nontemporal bits.
+static std::vector<su3_launch> dslash_candidates()
+{
+    std::vector<su3_launch> out;
+    su3_launch c = default_launch(SU3_EXPR_DSLASH, SU3_F64, SU3_LAYOUT_SOA);
+    for (int b : {64, 128, 256})
+        for (int occ : {0, 2, 4, 6, 8})
+            for (int nt : {0, 1, 2, 3}) {
+                c.block = b;
+                c.occupancy = occ;
+                c.nontemporal = nt;
+                out.push_back(c);
+            }
+    return out;
+}
+
 // Median time (microseconds) of `reps` launches after `warm` warm-ups, each
 // launch bracketed by its own events.
 template <class F>
@@ -957,10 +1133,19 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     if (st != SU3_OK)
         return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const int nops = expr == SU3_EXPR_CSHIFT ? 1 : operands_of(expr);
-    su3_field *f[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const bool dslash = expr == SU3_EXPR_DSLASH;
+    // Dslash: f[0] out, f[1] in (spinors), f[2..5] links
+    const int nops = expr == SU3_EXPR_CSHIFT ? 1
+                     : dslash              ? 5
+                                           : operands_of(expr);
+    su3_field *f[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (int i = 0; i <= nops && st == SU3_OK; ++i) {
-        st = su3_field_alloc(&f[i], dims, prec, layout, lanes);
+        if (dslash && i < 2)
+            st = su3_spinor_alloc(&f[i], dims,
+                                  (su3_precision)spinor_prec_of_links(prec),
+                                  layout, lanes);
+        else
+            st = su3_field_alloc(&f[i], dims, prec, layout, lanes);
         if (st == SU3_OK) {
             // a non-zero bit pattern (finite in every precision)
             hipError_t e = hipMemsetD32Async((hipDeviceptr_t)f[i]->ptr,
@@ -973,12 +1158,16 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     double win_us = 1e300;
     if (st == SU3_OK) {
         const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
-        for (const su3_launch &c : candidates(layout)) {
+        su3_field *links[4] = {f[2], f[3], f[4], f[5]};
+        for (const su3_launch &c : dslash ? dslash_candidates()
+                                          : candidates(layout)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)
                 continue;  // a copy has no row phases
             double us = 0;
             su3_status r = time_launch(
                 [&]() {
+                    if (dslash)
+                        return launch_dslash_op(f[0], links, f[1], stream, &c);
                     if (expr == SU3_EXPR_CSHIFT)
                         return launch_shift_op(0, f[0], nullptr, f[1], 1, 1,
                                                stream, &c);
@@ -1000,7 +1189,7 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
         if (win_us >= 1e300)
             st = fail(SU3_ERR_HIP, "no candidate launch ran");
     }
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 6; ++i)
         su3_field_free(f[i]);
     if (st != SU3_OK)
         return st;

@@ -79,6 +79,22 @@ struct BatchItem {
     int32_t tile_start;
 };
 
+// Arguments of the Wilson hopping kernel.  Spinor fields store 12 complex
+// entries per site (spin-major: entry 3 * spin + colour), link fields 9 (or
+// 6 for the two-row form); both share dims, layout and lanes, so one site
+// index addresses either through its own Geom.  Direction mu has extent
+// dims[mu] and neighbour stride stride[mu] (x fastest).
+struct DslashArgs {
+    void *out;
+    const void *in;
+    const void *u[4];
+    Geom gs;          // spinor geometry
+    Geom gl;          // link geometry
+    int32_t nsites;
+    uint32_t dims[4];
+    uint32_t stride[4];
+};
+
 // Kernel-unit entry points.  Each returns the launch's hipError_t.
 // `sites_per_lane` must be natural_sites(prec, expr) for blocked layouts or
 // 1; `sched` 0 = all loads then all stores, 1 = row-phased; `shm` is LDS
@@ -100,6 +116,11 @@ hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
 hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
                         int grid, size_t shm, const ShiftArgs &a,
                         hipStream_t stream);
+// Wilson hopping term: spinor precision F64 with F64 links, F32 with F32
+// or C12 links.  One site per lane, `grid` * `block` >= nsites.
+hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
+                         int grid, size_t shm, const DslashArgs &a,
+                         hipStream_t stream);
 hipError_t launch_triad(double *a, const double *b, const double *c,
                         double s, int64_t n, hipStream_t stream);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,

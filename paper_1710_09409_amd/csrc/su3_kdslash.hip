@@ -1,0 +1,248 @@
+// Wilson hopping term on one GPU:
+//   out(x) = sum_mu [ (1 - gamma_mu) U_mu(x) psi(x + mu_hat)
+//                   + (1 + gamma_mu) U_mu(x - mu_hat)^dagger psi(x - mu_hat) ]
+// periodic, in the chiral basis gamma_mu = [[0, A_mu], [A_mu^dagger, 0]]
+// with A_1 = -i sigma_1, A_2 = -i sigma_2, A_3 = -i sigma_3, A_4 = 1.
+//
+// Each hop uses the spin projection: with h = psi_up + s A psi_dn,
+// (1 + s gamma) psi = (h, s A^dagger h), so only the two spin components of
+// h are colour-rotated (two 3x3 matrix-vector products instead of four).
+// One lane per site; neighbours from the site index (x fastest), periodic.
+#include "su3_device.h"
+
+namespace su3k {
+namespace dslash {
+
+template <class T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+// i a and -i a
+template <class T>
+__device__ __forceinline__ Cx<T> ci(Cx<T> a) { return {-a.im, a.re}; }
+template <class T>
+__device__ __forceinline__ Cx<T> cmi(Cx<T> a) { return {a.im, -a.re}; }
+template <class T>
+__device__ __forceinline__ Cx<T> cscale(T s, Cx<T> a) { return {s * a.re, s * a.im}; }
+
+// h = psi_up + s A_mu psi_dn  (psi[spin][colour])
+template <int MU, int SGN, class T>
+__device__ __forceinline__ void project(const Cx<T> (&p)[4][3], Cx<T> (&h)[2][3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if constexpr (MU == 0) {        // A = [[0, -i], [-i, 0]]
+            h[0][c] = SGN > 0 ? cadd(p[0][c], cmi(p[3][c])) : csub(p[0][c], cmi(p[3][c]));
+            h[1][c] = SGN > 0 ? cadd(p[1][c], cmi(p[2][c])) : csub(p[1][c], cmi(p[2][c]));
+        } else if constexpr (MU == 1) { // A = [[0, -1], [1, 0]]
+            h[0][c] = SGN > 0 ? csub(p[0][c], p[3][c]) : cadd(p[0][c], p[3][c]);
+            h[1][c] = SGN > 0 ? cadd(p[1][c], p[2][c]) : csub(p[1][c], p[2][c]);
+        } else if constexpr (MU == 2) { // A = diag(-i, i)
+            h[0][c] = SGN > 0 ? cadd(p[0][c], cmi(p[2][c])) : csub(p[0][c], cmi(p[2][c]));
+            h[1][c] = SGN > 0 ? cadd(p[1][c], ci(p[3][c])) : csub(p[1][c], ci(p[3][c]));
+        } else {                        // A = 1
+            h[0][c] = SGN > 0 ? cadd(p[0][c], p[2][c]) : csub(p[0][c], p[2][c]);
+            h[1][c] = SGN > 0 ? cadd(p[1][c], p[3][c]) : csub(p[1][c], p[3][c]);
+        }
+    }
+}
+
+// acc_up += w, acc_dn += s A_mu^dagger w
+template <int MU, int SGN, class T>
+__device__ __forceinline__ void reconstruct(const Cx<T> (&w)[2][3], Cx<T> (&acc)[4][3])
+{
+    const T s = SGN > 0 ? T(1) : T(-1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[0][c] = cadd(acc[0][c], w[0][c]);
+        acc[1][c] = cadd(acc[1][c], w[1][c]);
+        if constexpr (MU == 0) {        // A^dagger = [[0, i], [i, 0]]
+            acc[2][c] = cadd(acc[2][c], cscale(s, ci(w[1][c])));
+            acc[3][c] = cadd(acc[3][c], cscale(s, ci(w[0][c])));
+        } else if constexpr (MU == 1) { // A^dagger = [[0, 1], [-1, 0]]
+            acc[2][c] = cadd(acc[2][c], cscale(s, w[1][c]));
+            acc[3][c] = csub(acc[3][c], cscale(s, w[0][c]));
+        } else if constexpr (MU == 2) { // A^dagger = diag(i, -i)
+            acc[2][c] = cadd(acc[2][c], cscale(s, ci(w[0][c])));
+            acc[3][c] = cadd(acc[3][c], cscale(s, cmi(w[1][c])));
+        } else {                        // A^dagger = 1
+            acc[2][c] = cadd(acc[2][c], cscale(s, w[0][c]));
+            acc[3][c] = cadd(acc[3][c], cscale(s, w[1][c]));
+        }
+    }
+}
+
+// w_k = M h_k (DAG = 0) or M^dagger h_k (DAG = 1) for both spin components
+template <int DAG, class T>
+__device__ __forceinline__ void color_mul(const Cx<T> (&m)[9], const Cx<T> (&h)[2][3],
+                                          Cx<T> (&w)[2][3])
+{
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            T re = T(0), im = T(0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const Cx<T> u = DAG ? m[3 * b + a] : m[3 * a + b];
+                const T ui = DAG ? -u.im : u.im;
+                re = fma_t(u.re, h[k][b].re, re);
+                re = fma_t(-ui, h[k][b].im, re);
+                im = fma_t(u.re, h[k][b].im, im);
+                im = fma_t(ui, h[k][b].re, im);
+            }
+            w[k][a].re = re;
+            w[k][a].im = im;
+        }
+}
+
+template <int SP, int NT>
+__device__ __forceinline__ void load_spinor(const void *base, uint32_t off, uint32_t plane,
+                                            Cx<typename PrecT<SP>::T> (&p)[4][3])
+{
+    RawVec<SP, 1> raw[12];
+    load_entries<SP, 1, NT, true, 0, 12>(static_cast<const typename PrecT<SP>::R *>(base),
+                                         off, plane, 1, raw);
+#pragma unroll
+    for (int e = 0; e < 12; ++e)
+        p[e / 3][e % 3] = widen<SP, 1>(raw[e], 0);
+}
+
+template <int LP, int NT>
+__device__ __forceinline__ void load_link(const void *base, uint32_t off, uint32_t plane,
+                                          Cx<typename PrecT<LP>::T> (&m)[9])
+{
+    constexpr int E = PrecT<LP>::E;
+    RawVec<LP, 1> raw[E];
+    load_entries<LP, 1, NT, true, 0, E>(static_cast<const typename PrecT<LP>::R *>(base),
+                                        off, plane, 1, raw);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        m[e] = widen<LP, 1>(raw[e], 0);
+    if constexpr (LP == su3i::C12)
+        rebuild_row2(m);
+}
+
+// Pin the accumulators at this point of the instruction stream: every
+// operation of the hop before must finish first, and (the asm being
+// volatile) no load after it moves above it, so only one hop's operands
+// are live at a time.
+template <class T>
+__device__ __forceinline__ void fence_acc(Cx<T> (&acc)[4][3])
+{
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            __asm__ volatile("" : "+v"(acc[sp][c].re), "+v"(acc[sp][c].im));
+}
+
+template <int MU, int SP, int LP, int NT>
+__device__ __forceinline__ void hop(const su3i::DslashArgs &a, uint32_t s,
+                                    uint32_t c, Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    using T = typename PrecT<SP>::T;
+    const uint32_t stride = a.stride[MU], L = a.dims[MU];
+    // periodic neighbours, branch-free
+    const uint32_t sf = s + stride - (c + 1 == L ? L * stride : 0u);
+    const uint32_t sb = s - stride + (c == 0 ? L * stride : 0u);
+    {   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
+        Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+        load_spinor<SP, NT>(a.in, site_offset(a.gs, sf), a.gs.plane, p);
+        load_link<LP, NT>(a.u[MU], site_offset(a.gl, s), a.gl.plane, m);
+        project<MU, -1>(p, h);
+        color_mul<0>(m, h, w);
+        reconstruct<MU, -1>(w, acc);
+    }
+    fence_acc(acc);
+    {   // backward: (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu)
+        Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+        load_spinor<SP, NT>(a.in, site_offset(a.gs, sb), a.gs.plane, p);
+        load_link<LP, NT>(a.u[MU], site_offset(a.gl, sb), a.gl.plane, m);
+        project<MU, +1>(p, h);
+        color_mul<1>(m, h, w);
+        reconstruct<MU, +1>(w, acc);
+    }
+    fence_acc(acc);
+}
+
+template <int SP, int LP, int NT, int WPE = SP == su3i::F64 ? 3 : 4>
+// WPE: at least this many waves per SIMD (caps the register budget)
+__global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
+{
+    extern __shared__ char occupancy_reserve[];
+    using T = typename PrecT<SP>::T;
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < (uint32_t)a.nsites) {
+        Cx<T> acc[4][3];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[sp][c] = {T(0), T(0)};
+        // lattice coordinates (x fastest)
+        uint32_t c[4], r = s;
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            c[mu] = r % a.dims[mu];
+            r /= a.dims[mu];
+        }
+        c[3] = r;
+        hop<0, SP, LP, NT>(a, s, c[0], acc);
+        hop<1, SP, LP, NT>(a, s, c[1], acc);
+        hop<2, SP, LP, NT>(a, s, c[2], acc);
+        hop<3, SP, LP, NT>(a, s, c[3], acc);
+        RawVec<SP, 1> raw[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e)
+            narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
+        store_entries<SP, 1, NT, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
+                                              site_offset(a.gs, s), a.gs.plane, 1, raw);
+    }
+    if (a.nsites < 0)
+        occupancy_reserve[threadIdx.x] = 0;
+}
+
+template <int SP, int LP>
+static hipError_t go(int nt, int block, int grid, size_t shm, const su3i::DslashArgs &a,
+                     hipStream_t st)
+{
+    switch (nt & 3) {
+    case 0:
+        hipLaunchKernelGGL((k_dslash<SP, LP, 0>), dim3(grid), dim3(block), shm, st, a);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_dslash<SP, LP, 1>), dim3(grid), dim3(block), shm, st, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_dslash<SP, LP, 2>), dim3(grid), dim3(block), shm, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_dslash<SP, LP, 3>), dim3(grid), dim3(block), shm, st, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dslash
+}  // namespace su3k
+
+namespace su3i {
+
+hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
+                         int grid, size_t shm, const DslashArgs &a,
+                         hipStream_t st)
+{
+    using namespace su3k::dslash;
+    if (block > 256)
+        return hipErrorInvalidValue;
+    if (spinor_prec == F64 && link_prec == F64)
+        return go<F64, F64>(nt, block, grid, shm, a, st);
+    if (spinor_prec == F32 && link_prec == F32)
+        return go<F32, F32>(nt, block, grid, shm, a, st);
+    if (spinor_prec == F32 && link_prec == C12)
+        return go<F32, C12>(nt, block, grid, shm, a, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace su3i

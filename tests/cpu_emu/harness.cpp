@@ -2,7 +2,9 @@
 // hip/hip_runtime.h) against the FP64 oracle, under AddressSanitizer and
 // UBSan: every precision x layout x expression on ragged lattices with two
 // launch settings (which must agree), persistent grids, LDS staging, the
-// batch (tile rows, replays, autotuner) and the shifted operands.  Any
+// batch (tile rows, replays, autotuner), the shifted operands and the
+// Wilson hopping term (every precision pair and layout, two launch
+// settings, argument validation).  Any
 // out-of-bounds access in a kernel's indexing aborts the run.  Prints
 // "fails 0" on success.
 #include "su3.h"
@@ -17,6 +19,8 @@ int oracle_fused(int expr, const double *a, const double *b, const double *c, co
 int oracle_roundtrip(int prec, const double *in, double *out, int64_t V);
 int oracle_cshift(const double *src, double *dst, const int32_t dims[4], int mu, int64_t shift);
 void oracle_mult(const double *x, const double *y, double *z, int64_t V);
+int oracle_dslash(const double *const *u, const double *in, double *out, const int32_t dims[4]);
+void su3gen_spinor(uint64_t seed, uint64_t field_id, int64_t s_begin, int64_t count, double *out);
 }
 static int nops_of(int e) { return e == 1 ? 3 : (e == 2 ? 4 : 2); }
 static int fails = 0;
@@ -202,6 +206,83 @@ int main(int argc, char **argv)
                             su3_field_free(fx); su3_field_free(fy); su3_field_free(fz);
                         }
         printf("shift cases done\n");
+    }
+    // Wilson hopping term
+    {
+        int dd[][4] = {{3, 5, 7, 11}, {1, 2, 1, 3}, {4, 4, 4, 4}, {2, 6, 3, 4}};
+        int pairs[][2] = {{0, 0}, {1, 1}, {1, 3}};  // (spinor, links)
+        for (auto &d : dd)
+            for (auto &pr : pairs)
+                for (auto &l : lays) {
+                    const int sp = pr[0], lp = pr[1];
+                    int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
+                    std::vector<double> hu[4], qu[4], hin(24 * V), qin(24 * V), want(24 * V), got(24 * V), got1(24 * V);
+                    const double *up[4];
+                    su3_field *fu[4], *fin, *fout;
+                    for (int mu = 0; mu < 4; ++mu) {
+                        hu[mu].resize(18 * V);
+                        qu[mu].resize(18 * V);
+                        su3gen_field(9, 2 + mu, 0, V, hu[mu].data());
+                        oracle_roundtrip(lp, hu[mu].data(), qu[mu].data(), V);
+                        up[mu] = qu[mu].data();
+                        su3_field_alloc(&fu[mu], d, (su3_precision)lp, (su3_layout)l[0], l[1]);
+                        su3_field_upload(fu[mu], hu[mu].data(), nullptr);
+                    }
+                    su3gen_spinor(9, 200, 0, V, hin.data());
+                    for (int64_t i = 0; i < 24 * V; ++i)
+                        qin[i] = sp == 0 ? hin[i] : (double)(float)hin[i];
+                    oracle_dslash(up, qin.data(), want.data(), d);
+                    su3_spinor_alloc(&fin, d, (su3_precision)sp, (su3_layout)l[0], l[1]);
+                    su3_spinor_alloc(&fout, d, (su3_precision)sp, (su3_layout)l[0], l[1]);
+                    su3_field_upload(fin, hin.data(), nullptr);
+                    su3_launch c0 = {64, 0, 0, 0, 0, 4096, 0, 0};
+                    su3_launch c1 = {256, 0, 3, 0, 0, 4096, 4, 0};
+                    su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &c0);
+                    if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
+                    su3_field_download(fout, got.data(), nullptr);
+                    su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &c1);
+                    if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
+                    su3_field_download(fout, got1.data(), nullptr);
+                    su3_launch_reset();
+                    if (memcmp(got.data(), got1.data(), 8 * 24 * V) != 0) { printf("dslash launch settings differ\n"); fails++; }
+                    double err = 0;
+                    for (int64_t i = 0; i < 24 * V; ++i) err = std::max(err, std::fabs(got[i] - want[i]));
+                    if (err > (sp == 0 ? 1e-13 : 2e-5)) { printf("dslash err %.3e sp %d lp %d lay %d/%d dims %dx%dx%dx%d\n", err, sp, lp, l[0], l[1], d[0], d[1], d[2], d[3]); fails++; }
+                    su3_field_free(fin); su3_field_free(fout);
+                    for (int mu = 0; mu < 4; ++mu) su3_field_free(fu[mu]);
+                }
+        // validation
+        int d[4] = {2, 3, 2, 3};
+        su3_field *u64[4], *u16, *s64a, *s64b, *s32, *m64;
+        for (int mu = 0; mu < 4; ++mu) su3_field_alloc(&u64[mu], d, SU3_F64, SU3_LAYOUT_SOA, 0);
+        su3_field_alloc(&u16, d, SU3_F16_F32ACC, SU3_LAYOUT_SOA, 0);
+        su3_field_alloc(&m64, d, SU3_F64, SU3_LAYOUT_SOA, 0);
+        su3_spinor_alloc(&s64a, d, SU3_F64, SU3_LAYOUT_SOA, 0);
+        su3_spinor_alloc(&s64b, d, SU3_F64, SU3_LAYOUT_SOA, 0);
+        su3_spinor_alloc(&s32, d, SU3_F32, SU3_LAYOUT_SOA, 0);
+        su3_field *bad16[4] = {u16, u16, u16, u16};
+        su3_field *mixed[4] = {u64[0], u64[1], u16, u64[3]};
+        const su3_field *mops[2] = {s64a, s64b};
+        struct { su3_status got, want; const char *what; } v[] = {
+            {su3_dslash(s64a, u64, s64a, nullptr), SU3_ERR_ALIAS, "in place"},
+            {su3_dslash(s64a, u64, s32, nullptr), SU3_ERR_MISMATCH, "spinor precisions"},
+            {su3_dslash(s32, u64, s32, nullptr), SU3_ERR_UNSUPPORTED, "f32 spinors with f64 links"},
+            {su3_dslash(s64a, mixed, s64b, nullptr), SU3_ERR_MISMATCH, "mixed links"},
+            {su3_dslash(s64a, u64, m64, nullptr), SU3_ERR_MISMATCH, "matrix as spinor"},
+            {su3_dslash(s64a, bad16, s64b, nullptr), SU3_ERR_UNSUPPORTED, "f16 links"},
+            {su3_dslash(s64a, nullptr, s64b, nullptr), SU3_ERR_INVALID_ARG, "null links"},
+            {su3_fused_eval(m64, SU3_EXPR_MUL, mops, 2, nullptr), SU3_ERR_MISMATCH, "spinors in mult"},
+            {su3_cshift(s64a, s64b, 0, 1, nullptr), SU3_ERR_MISMATCH, "spinor cshift"},
+            {su3_dslash(s64a, u64, s64b, nullptr), SU3_OK, "valid"},
+        };
+        for (auto &x : v)
+            if (x.got != x.want) { printf("dslash validation %s: got %d want %d\n", x.what, x.got, x.want); fails++; }
+        su3_field *links_c12[4];
+        for (int mu = 0; mu < 4; ++mu) su3_field_alloc(&links_c12[mu], d, SU3_C12_F32, SU3_LAYOUT_SOA, 0);
+        if (su3_dslash(s64a, links_c12, s64b, nullptr) != SU3_ERR_UNSUPPORTED) { printf("f64 spinor with c12 links accepted\n"); fails++; }
+        for (int mu = 0; mu < 4; ++mu) { su3_field_free(u64[mu]); su3_field_free(links_c12[mu]); }
+        su3_field_free(u16); su3_field_free(m64); su3_field_free(s64a); su3_field_free(s64b); su3_field_free(s32);
+        printf("dslash cases done\n");
     }
     printf("fails %d\n", fails);
     return fails != 0;

@@ -25,7 +25,7 @@ def header_functions():
 def test_every_declared_symbol_is_exported():
     lib = su3.load()
     names = header_functions()
-    assert len(names) == 26
+    assert len(names) == 30
     assert set(names) == set(su3.SYMBOLS)
     for n in names:
         assert hasattr(lib, n), n
@@ -56,6 +56,24 @@ def test_field_bytes_match_oracle(dims):
         for lay, lanes in ((0, 0), (1, 0), (2, 8), (2, 16), (2, 32), (2, 64)):
             assert su3.su3_field_bytes(dims, prec, lay, lanes) == \
                 O.get().field_bytes(prec, lay, lanes, V)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1, 1), (3, 5, 7, 11), (48, 48, 48, 48)])
+def test_spinor_bytes(dims):
+    """12 complex entries per site, padded like matrix fields."""
+    V = int(np.prod(dims))
+    for prec, rb in ((0, 8), (1, 4)):
+        for lay, lanes in ((0, 0), (1, 0), (2, 8), (2, 64)):
+            pad = {0: 1, 1: 64, 2: lanes}[lay]
+            Vpad = -(-V // pad) * pad
+            assert su3.su3_spinor_bytes(dims, prec, lay, lanes) == Vpad * 12 * 2 * rb
+    for prec in (2, 3):
+        assert _status(su3.su3_spinor_bytes, dims, prec, 1, 0) == su3.SU3_ERR_UNSUPPORTED
+    # 128^3 x 48 sites: 1.81e9 matrix reals fit below 2^31, 2.42e9 spinor
+    # reals do not
+    big = (128, 128, 128, 48)
+    assert su3.su3_field_bytes(big, 1, 1, 0) > 0
+    assert _status(su3.su3_spinor_bytes, big, 1, 1, 0) == su3.SU3_ERR_INVALID_ARG
 
 
 def _status(fn, *a):
@@ -119,11 +137,17 @@ def test_launch_table():
                    dict(cfg, lds_stage=1, block=128)) == 0
     assert _status(su3.su3_launch_set, 3, 3, 1, 0, dims, cfg) == \
         su3.SU3_ERR_UNSUPPORTED
-    # the shifted operations' tuning keys are accepted, unknown ones not
-    for key in (su3.SU3_EXPR_CSHIFT, su3.SU3_EXPR_MUL_SHIFTED):
+    # the shifted operations' and Dslash's tuning keys are accepted,
+    # unknown ones not
+    for key in (su3.SU3_EXPR_CSHIFT, su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_EXPR_DSLASH):
         su3.su3_launch_set(key, 0, 1, 0, dims, cfg)
         assert su3.su3_launch_get(key, 0, 1, 0, dims).as_dict() == cfg
-    assert _status(su3.su3_launch_set, 7, 0, 1, 0, dims, cfg) == su3.SU3_ERR_INVALID_ARG
+    assert _status(su3.su3_launch_set, 8, 0, 1, 0, dims, cfg) == su3.SU3_ERR_INVALID_ARG
+    # Dslash links are never half precision
+    assert _status(su3.su3_launch_set, su3.SU3_EXPR_DSLASH, 2, 1, 0, dims, cfg) == \
+        su3.SU3_ERR_UNSUPPORTED
+    # the default Dslash launch keeps loads cached (neighbours re-read them)
+    assert su3.su3_launch_get(su3.SU3_EXPR_DSLASH, 0, 1, 0, (8, 8, 8, 8)).nontemporal & 1 == 0
     su3.su3_launch_reset()
     assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == d.as_dict()
 

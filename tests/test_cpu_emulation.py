@@ -22,6 +22,7 @@ def test_kernels_under_asan(tmp_path):
     units = [([f"-DSU3_PREC={p}", "-x", "c++", os.path.join(CSRC, "su3_kprec.hip")], f"kp{p}.o")
              for p in range(4)]
     units += [(["-x", "c++", os.path.join(CSRC, "su3_kmisc.hip")], "km.o"),
+              (["-x", "c++", os.path.join(CSRC, "su3_kdslash.hip")], "kd.o"),
               ([os.path.join(CSRC, "su3_api.cpp")], "api.o"),
               ([os.path.join(EMU, "emu_globals.cpp")], "g.o"),
               ([os.path.join(EMU, "harness.cpp")], "h.o")]
@@ -36,7 +37,7 @@ def test_kernels_under_asan(tmp_path):
     for p in procs:
         _, err = p.communicate()
         assert p.returncode == 0, err
-    objs = [str(tmp_path / o) for o in ("kp0.o", "kp1.o", "kp2.o", "kp3.o", "km.o", "api.o",
+    objs = [str(tmp_path / o) for o in ("kp0.o", "kp1.o", "kp2.o", "kp3.o", "km.o", "kd.o", "api.o",
                                         "g.o", "h.o", "gen.o", "or.o")]
     subprocess.check_call([CLANG, "-fsanitize=address,undefined"] + objs +
                           ["-o", str(tmp_path / "harness"), "-lm"])
@@ -46,3 +47,4 @@ def test_kernels_under_asan(tmp_path):
     assert r.returncode == 0, tail
     assert "fails 0" in r.stdout, tail
     assert "shift cases done" in r.stdout, tail
+    assert "dslash cases done" in r.stdout, tail
