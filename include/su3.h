@@ -117,7 +117,9 @@ typedef struct su3_batch su3_batch;
  *               workgroups instead of the hardware's round-robin
  *   lds_stage   AOS only: 1 stages each workgroup's sites through LDS with
  *               coalesced 16-byte copies (block <= 128)
- *   tile_sites  batched launch only: sites per tile (multiple of 64)
+ *   tile_sites  batched launch: sites per tile (multiple of 64).
+ *               su3_dslash: t-slices each lane walks (1..4096, clipped to
+ *               the t extent; 1 = one site per lane)
  *   occupancy   0: no cap; k > 0: at most k workgroups per compute unit
  *               (enforced by reserving LDS): fewer waves with their loads
  *               in flight keep HBM streaming efficiently

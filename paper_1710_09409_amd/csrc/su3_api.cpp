@@ -522,16 +522,19 @@ static su3_launch default_launch(int expr, int prec, int layout)
     c.occupancy = layout == SU3_LAYOUT_AOS ? 0 : 5;
     c.schedule = layout == SU3_LAYOUT_AOS ? 0 : 1;
     if (expr == SU3_EXPR_DSLASH) {
-        // neighbours re-read each spinor eight times: keep loads cached
+        // neighbours re-read each spinor eight times: keep loads cached;
+        // each lane walks 8 t-slices
         c.block = 128;
         c.nontemporal = 2;
         c.occupancy = 0;
         c.schedule = 0;
+        c.tile_sites = 8;
+        c.xcd_remap = 1;
     }
     return c;
 }
 
-static su3_status check_launch(const su3_launch &c, int layout)
+static su3_status check_launch(const su3_launch &c, int layout, int expr)
 {
     if (c.block != 64 && c.block != 128 && c.block != 256)
         return fail(SU3_ERR_INVALID_ARG, "block %d not in {64, 128, 256}",
@@ -549,9 +552,16 @@ static su3_status check_launch(const su3_launch &c, int layout)
         return fail(SU3_ERR_INVALID_ARG, "lds_stage is for the AoS layout only");
     if (c.lds_stage && c.block > 128)
         return fail(SU3_ERR_INVALID_ARG, "lds_stage needs block <= 128");
-    if (c.tile_sites < 64 || c.tile_sites % 64 != 0 || c.tile_sites > (1 << 24))
+    if (expr == SU3_EXPR_DSLASH) {
+        if (c.tile_sites < 1 || c.tile_sites > 4096)
+            return fail(SU3_ERR_INVALID_ARG,
+                        "Dslash tile_sites (t-slices per lane) must be in "
+                        "[1, 4096]");
+    } else if (c.tile_sites < 64 || c.tile_sites % 64 != 0 ||
+               c.tile_sites > (1 << 24)) {
         return fail(SU3_ERR_INVALID_ARG,
                     "tile_sites must be a positive multiple of 64");
+    }
     if (c.occupancy < 0 || c.occupancy > 64)
         return fail(SU3_ERR_INVALID_ARG, "occupancy %d not in [0, 64]",
                     c.occupancy);
@@ -627,7 +637,7 @@ static void load_cache_locked()
             !parse_int(line, "occupancy", &c.occupancy) ||
             !parse_int(line, "schedule", &c.schedule))
             continue;
-        if (check_launch(c, la) != SU3_OK)
+        if (check_launch(c, la, ex) != SU3_OK)
             continue;
         g_tuned[Key(ex, pr, la, ln, vb)] = c;
     }
@@ -884,13 +894,20 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     a.gs = geom_of(out);
     a.gl = geom_of(u0);
     a.nsites = (int32_t)out->V;
+    a.xcd_remap = c.xcd_remap;
     int64_t stride = 1;
     for (int mu = 0; mu < 4; ++mu) {
         a.dims[mu] = (uint32_t)out->dims[mu];
         a.stride[mu] = (uint32_t)stride;
         stride *= out->dims[mu];
     }
-    const int64_t grid = (out->V + c.block - 1) / c.block;
+    // lanes: one per site, or one per (x, y, z) site and chunk of `walk`
+    // t-slices
+    const int64_t Lt = out->dims[3];
+    a.walk = (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
+    const int64_t lanes = a.walk <= 1 ? out->V
+                                      : a.stride[3] * ((Lt + a.walk - 1) / a.walk);
+    const int64_t grid = (lanes + c.block - 1) / c.block;
     hipError_t e = launch_dslash(out->prec, u0->prec, c.nontemporal, c.block,
                                  (int)grid,
                                  occupancy_reserve(out->device, c.occupancy),
@@ -996,7 +1013,7 @@ extern "C" su3_status su3_launch_set(su3_expr expr, su3_precision prec,
     su3_status st = key_of(expr, prec, layout, lanes, dims, &k, nullptr);
     if (st != SU3_OK)
         return st;
-    st = check_launch(*cfg, layout);
+    st = check_launch(*cfg, layout, expr);
     if (st != SU3_OK)
         return st;
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1065,20 +1082,24 @@ static std::vector<su3_launch> candidates(int layout)
     return out;
 }
 
-// Candidates for the Wilson hopping kernel: one site per lane, one-shot
-// grid; block, occupancy cap and nontemporal bits.
+// Candidates for the Wilson hopping kernel: t-slices per lane (1: one
+// site per lane), block, occupancy cap, nontemporal bits, XCD remapping.
 static std::vector<su3_launch> dslash_candidates()
 {
     std::vector<su3_launch> out;
     su3_launch c = default_launch(SU3_EXPR_DSLASH, SU3_F64, SU3_LAYOUT_SOA);
-    for (int b : {64, 128, 256})
-        for (int occ : {0, 2, 4, 6, 8})
-            for (int nt : {0, 1, 2, 3}) {
-                c.block = b;
-                c.occupancy = occ;
-                c.nontemporal = nt;
-                out.push_back(c);
-            }
+    for (int walk : {1, 4, 8, 16})
+        for (int b : {64, 128, 256})
+            for (int occ : {0, 2, 3, 4, 6})
+                for (int nt : {0, 2})
+                    for (int x : {0, 1}) {
+                        c.tile_sites = walk;
+                        c.block = b;
+                        c.occupancy = occ;
+                        c.nontemporal = nt;
+                        c.xcd_remap = x;
+                        out.push_back(c);
+                    }
     return out;
 }
 

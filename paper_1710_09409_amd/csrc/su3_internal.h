@@ -91,6 +91,8 @@ struct DslashArgs {
     Geom gs;          // spinor geometry
     Geom gl;          // link geometry
     int32_t nsites;
+    int32_t xcd_remap;  // 1: contiguous workgroup ranges per XCD
+    uint32_t walk;      // t-slices per lane (1: one site per lane)
     uint32_t dims[4];
     uint32_t stride[4];
 };
@@ -117,7 +119,9 @@ hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
                         int grid, size_t shm, const ShiftArgs &a,
                         hipStream_t stream);
 // Wilson hopping term: spinor precision F64 with F64 links, F32 with F32
-// or C12 links.  One site per lane, `grid` * `block` >= nsites.
+// or C12 links.  walk == 1: one site per lane, grid * block >= nsites;
+// walk > 1: one lane per (x, y, z) site and chunk of `walk` t-slices,
+// grid * block >= stride[3] * ceil(dims[3] / walk).
 hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
                          int grid, size_t shm, const DslashArgs &a,
                          hipStream_t stream);

@@ -127,42 +127,57 @@ __device__ __forceinline__ void load_link(const void *base, uint32_t off, uint32
 // operation of the hop before must finish first, and (the asm being
 // volatile) no load after it moves above it, so only one hop's operands
 // are live at a time.
-template <class T>
-__device__ __forceinline__ void fence_acc(Cx<T> (&acc)[4][3])
+template <class T, int N>
+__device__ __forceinline__ void fence_acc(Cx<T> (&acc)[N][3])
 {
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
+    for (int sp = 0; sp < N; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             __asm__ volatile("" : "+v"(acc[sp][c].re), "+v"(acc[sp][c].im));
 }
 
+// Forward hop (1 - gamma_mu) U_mu(x) psi(x + mu) from site sf.
+template <int MU, int SP, int LP, int NT>
+__device__ __forceinline__ void hop_fwd(const su3i::DslashArgs &a, uint32_t s,
+                                        uint32_t sf,
+                                        Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    using T = typename PrecT<SP>::T;
+    Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+    load_spinor<SP, NT>(a.in, site_offset(a.gs, sf), a.gs.plane, p);
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, s), a.gl.plane, m);
+    project<MU, -1>(p, h);
+    color_mul<0>(m, h, w);
+    reconstruct<MU, -1>(w, acc);
+}
+
+// Backward hop (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu) from site sb.
+template <int MU, int SP, int LP, int NT>
+__device__ __forceinline__ void hop_bwd(const su3i::DslashArgs &a, uint32_t sb,
+                                        Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    using T = typename PrecT<SP>::T;
+    Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+    load_spinor<SP, NT>(a.in, site_offset(a.gs, sb), a.gs.plane, p);
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, sb), a.gl.plane, m);
+    project<MU, +1>(p, h);
+    color_mul<1>(m, h, w);
+    reconstruct<MU, +1>(w, acc);
+}
+
+// Both hops of direction MU (forward first), c = the site's coordinate.
 template <int MU, int SP, int LP, int NT>
 __device__ __forceinline__ void hop(const su3i::DslashArgs &a, uint32_t s,
                                     uint32_t c, Cx<typename PrecT<SP>::T> (&acc)[4][3])
 {
-    using T = typename PrecT<SP>::T;
     const uint32_t stride = a.stride[MU], L = a.dims[MU];
     // periodic neighbours, branch-free
     const uint32_t sf = s + stride - (c + 1 == L ? L * stride : 0u);
     const uint32_t sb = s - stride + (c == 0 ? L * stride : 0u);
-    {   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
-        Cx<T> p[4][3], m[9], h[2][3], w[2][3];
-        load_spinor<SP, NT>(a.in, site_offset(a.gs, sf), a.gs.plane, p);
-        load_link<LP, NT>(a.u[MU], site_offset(a.gl, s), a.gl.plane, m);
-        project<MU, -1>(p, h);
-        color_mul<0>(m, h, w);
-        reconstruct<MU, -1>(w, acc);
-    }
+    hop_fwd<MU, SP, LP, NT>(a, s, sf, acc);
     fence_acc(acc);
-    {   // backward: (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu)
-        Cx<T> p[4][3], m[9], h[2][3], w[2][3];
-        load_spinor<SP, NT>(a.in, site_offset(a.gs, sb), a.gs.plane, p);
-        load_link<LP, NT>(a.u[MU], site_offset(a.gl, sb), a.gl.plane, m);
-        project<MU, +1>(p, h);
-        color_mul<1>(m, h, w);
-        reconstruct<MU, +1>(w, acc);
-    }
+    hop_bwd<MU, SP, LP, NT>(a, sb, acc);
     fence_acc(acc);
 }
 
@@ -172,7 +187,9 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
 {
     extern __shared__ char occupancy_reserve[];
     using T = typename PrecT<SP>::T;
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
+                                     : blockIdx.x;
+    const uint32_t s = blk * blockDim.x + threadIdx.x;
     if (s < (uint32_t)a.nsites) {
         Cx<T> acc[4][3];
 #pragma unroll
@@ -188,10 +205,19 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
             r /= a.dims[mu];
         }
         c[3] = r;
+        // accumulation order shared with the walk kernel (results are
+        // bitwise independent of the launch): t backward, t forward,
+        // then x, y, z (forward, backward)
+        {
+            const uint32_t st = a.stride[3], Lt = a.dims[3];
+            hop_bwd<3, SP, LP, NT>(a, s - st + (c[3] == 0 ? Lt * st : 0u), acc);
+            fence_acc(acc);
+            hop_fwd<3, SP, LP, NT>(a, s, s + st - (c[3] + 1 == Lt ? Lt * st : 0u), acc);
+            fence_acc(acc);
+        }
         hop<0, SP, LP, NT>(a, s, c[0], acc);
         hop<1, SP, LP, NT>(a, s, c[1], acc);
         hop<2, SP, LP, NT>(a, s, c[2], acc);
-        hop<3, SP, LP, NT>(a, s, c[3], acc);
         RawVec<SP, 1> raw[12];
 #pragma unroll
         for (int e = 0; e < 12; ++e)
@@ -203,22 +229,114 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
         occupancy_reserve[threadIdx.x] = 0;
 }
 
+// t-walk: a lane owns one (x, y, z) site and walks t-slices t0 .. t1-1.
+// Along t each spinor and each t-link is loaded once per walk: at slice t
+// the lane loads psi(t+1) and U_t(t) for the forward t-hop, and from the
+// same registers prepares the next slice's backward t-hop,
+//   wb(t+1) = U_t(t)^dagger (P+ psi(t)),  hc = P+ psi(t+1),
+// carrying two half spinors (wb, hc) between slices.  The x, y, z hops
+// are the one-site hops; their neighbours are loaded by adjacent lanes at
+// about the same time and come from cache.
+template <int SP, int LP, int NT, int WPE = (SP == su3i::F64 || LP == su3i::C12) ? 3 : 4>
+__global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
+{
+    extern __shared__ char occupancy_reserve[];
+    using T = typename PrecT<SP>::T;
+    const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
+                                     : blockIdx.x;
+    const uint32_t tid = blk * blockDim.x + threadIdx.x;
+    const uint32_t V3 = a.stride[3], Lt = a.dims[3];
+    const uint32_t chunk = tid / V3, r = tid - chunk * V3;
+    const uint32_t t0 = chunk * a.walk;
+    if (t0 < Lt) {
+        const uint32_t t1 = t0 + a.walk < Lt ? t0 + a.walk : Lt;
+        uint32_t c[3], q = r;
+#pragma unroll
+        for (int mu = 0; mu < 2; ++mu) {
+            c[mu] = q % a.dims[mu];
+            q /= a.dims[mu];
+        }
+        c[2] = q;
+        Cx<T> wb[2][3], hc[2][3];
+        {   // backward t-hop of slice t0 and P+ psi(t0)
+            const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
+            Cx<T> p[4][3], m[9], h[2][3];
+            load_spinor<SP, NT>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
+            load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
+            project<3, +1>(p, h);
+            color_mul<1>(m, h, wb);
+        }
+        fence_acc(wb);
+        {
+            Cx<T> p[4][3];
+            load_spinor<SP, NT>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
+            project<3, +1>(p, hc);
+        }
+        fence_acc(hc);
+        for (uint32_t t = t0; t < t1; ++t) {
+            const uint32_t s = r + V3 * t;
+            Cx<T> acc[4][3];
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    acc[sp][cc] = {T(0), T(0)};
+            reconstruct<3, +1>(wb, acc);
+            {   // forward t-hop; next slice's backward t-hop and P+ psi
+                const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
+                Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+                load_spinor<SP, NT>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
+                load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
+                project<3, -1>(p, h);
+                color_mul<0>(m, h, w);
+                reconstruct<3, -1>(w, acc);
+                color_mul<1>(m, hc, wb);
+                project<3, +1>(p, hc);
+            }
+            fence_acc(acc);
+            fence_acc(wb);
+            fence_acc(hc);
+            hop<0, SP, LP, NT>(a, s, c[0], acc);
+            hop<1, SP, LP, NT>(a, s, c[1], acc);
+            hop<2, SP, LP, NT>(a, s, c[2], acc);
+            RawVec<SP, 1> raw[12];
+#pragma unroll
+            for (int e = 0; e < 12; ++e)
+                narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
+            store_entries<SP, 1, NT, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
+                                                  site_offset(a.gs, s), a.gs.plane, 1, raw);
+        }
+    }
+    if (a.nsites < 0)
+        occupancy_reserve[threadIdx.x] = 0;
+}
+
+template <int SP, int LP, int NT>
+static void go_nt(int block, int grid, size_t shm, const su3i::DslashArgs &a,
+                  hipStream_t st)
+{
+    if (a.walk > 1)
+        hipLaunchKernelGGL((k_dslash_walk<SP, LP, NT>), dim3(grid), dim3(block), shm, st, a);
+    else
+        hipLaunchKernelGGL((k_dslash<SP, LP, NT>), dim3(grid), dim3(block), shm, st, a);
+}
+
 template <int SP, int LP>
 static hipError_t go(int nt, int block, int grid, size_t shm, const su3i::DslashArgs &a,
                      hipStream_t st)
 {
     switch (nt & 3) {
     case 0:
-        hipLaunchKernelGGL((k_dslash<SP, LP, 0>), dim3(grid), dim3(block), shm, st, a);
+        go_nt<SP, LP, 0>(block, grid, shm, a, st);
         break;
     case 1:
-        hipLaunchKernelGGL((k_dslash<SP, LP, 1>), dim3(grid), dim3(block), shm, st, a);
+        go_nt<SP, LP, 1>(block, grid, shm, a, st);
         break;
     case 2:
-        hipLaunchKernelGGL((k_dslash<SP, LP, 2>), dim3(grid), dim3(block), shm, st, a);
+        go_nt<SP, LP, 2>(block, grid, shm, a, st);
         break;
     default:
-        hipLaunchKernelGGL((k_dslash<SP, LP, 3>), dim3(grid), dim3(block), shm, st, a);
+        go_nt<SP, LP, 3>(block, grid, shm, a, st);
         break;
     }
     return hipGetLastError();

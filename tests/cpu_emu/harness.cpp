@@ -235,16 +235,16 @@ int main(int argc, char **argv)
                     su3_spinor_alloc(&fin, d, (su3_precision)sp, (su3_layout)l[0], l[1]);
                     su3_spinor_alloc(&fout, d, (su3_precision)sp, (su3_layout)l[0], l[1]);
                     su3_field_upload(fin, hin.data(), nullptr);
-                    su3_launch c0 = {64, 0, 0, 0, 0, 4096, 0, 0};
-                    su3_launch c1 = {256, 0, 3, 0, 0, 4096, 4, 0};
-                    su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &c0);
-                    if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
-                    su3_field_download(fout, got.data(), nullptr);
-                    su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &c1);
-                    if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
-                    su3_field_download(fout, got1.data(), nullptr);
+                    // one site per lane; walks of 3 t-slices; one walk over all of t
+                    su3_launch cs[3] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
+                                        {128, 0, 2, 0, 0, 4096, 0, 0}};
+                    for (int k = 0; k < 3; ++k) {
+                        su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &cs[k]);
+                        if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
+                        su3_field_download(fout, k ? got1.data() : got.data(), nullptr);
+                        if (k && memcmp(got.data(), got1.data(), 8 * 24 * V) != 0) { printf("dslash launch settings differ (%d)\n", k); fails++; }
+                    }
                     su3_launch_reset();
-                    if (memcmp(got.data(), got1.data(), 8 * 24 * V) != 0) { printf("dslash launch settings differ\n"); fails++; }
                     double err = 0;
                     for (int64_t i = 0; i < 24 * V; ++i) err = std::max(err, std::fabs(got[i] - want[i]));
                     if (err > (sp == 0 ? 1e-13 : 2e-5)) { printf("dslash err %.3e sp %d lp %d lay %d/%d dims %dx%dx%dx%d\n", err, sp, lp, l[0], l[1], d[0], d[1], d[2], d[3]); fails++; }

@@ -148,6 +148,10 @@ def test_launch_table():
         su3.SU3_ERR_UNSUPPORTED
     # the default Dslash launch keeps loads cached (neighbours re-read them)
     assert su3.su3_launch_get(su3.SU3_EXPR_DSLASH, 0, 1, 0, (8, 8, 8, 8)).nontemporal & 1 == 0
+    # Dslash tile_sites counts t-slices per lane
+    su3.su3_launch_set(su3.SU3_EXPR_DSLASH, 0, 1, 0, dims, dict(cfg, tile_sites=3))
+    assert _status(su3.su3_launch_set, su3.SU3_EXPR_DSLASH, 0, 1, 0, dims,
+                   dict(cfg, tile_sites=0)) == su3.SU3_ERR_INVALID_ARG
     su3.su3_launch_reset()
     assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == d.as_dict()
 

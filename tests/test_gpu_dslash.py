@@ -1,8 +1,9 @@
 """Wilson hopping term on the GPU against the oracle: every precision pair
 (F64/F64, F32/F32, F32 spinors with compressed links) in every layout on
 ragged lattices (extents 1 and 2 included, where forward and backward
-neighbours coincide), bitwise agreement across launch settings, argument
-rules, and the full 48^4 lattice in the tuned launch.
+neighbours coincide), bitwise agreement across launch settings (one site
+per lane and t-walks of several lengths, ragged last walk included),
+argument rules, and the full 48^4 lattice in the tuned launch.
 
 Tolerance (absolute, per real entry).  Each output entry is a sum over 8
 hops of +-1 or +-i times an entry of U h (or U^dagger h), h a sum of two
@@ -101,11 +102,12 @@ def test_dslash_parity(pair, dims):
         fu, fin = device_inputs(dims, sp, lp, lay, lanes, links, psi, s)
         fout = su3.spinor_tensor(dims, sp, lay, lanes)
         prev = None
-        for cfg in (dict(block=64, nontemporal=0, occupancy=0),
-                    dict(block=256, nontemporal=3, occupancy=4),
-                    dict(block=128, nontemporal=2, occupancy=2)):
-            full = dict(persistent=0, xcd_remap=0, lds_stage=0, tile_sites=4096,
-                        schedule=0, **cfg)
+        # one site per lane; walks of 3 t-slices; one walk over all of t
+        for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1),
+                    dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3),
+                    dict(block=128, nontemporal=2, occupancy=2, xcd_remap=0,
+                         tile_sites=4096)):
+            full = dict(persistent=0, lds_stage=0, schedule=0, **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
                 su3.su3_dslash(fout, fu, fin, s)
