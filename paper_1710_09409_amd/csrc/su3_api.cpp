@@ -1083,23 +1083,23 @@ static std::vector<su3_launch> candidates(int layout)
 }
 
 // Candidates for the Wilson hopping kernel: t-slices per lane (1: one
-// site per lane), block, occupancy cap, nontemporal bits, XCD remapping.
+// site per lane), block, occupancy cap, XCD remapping (nontemporal
+// stores, cached loads).
 static std::vector<su3_launch> dslash_candidates()
 {
     std::vector<su3_launch> out;
     su3_launch c = default_launch(SU3_EXPR_DSLASH, SU3_F64, SU3_LAYOUT_SOA);
+    c.nontemporal = 2;
     for (int walk : {1, 4, 8, 16})
         for (int b : {64, 128, 256})
             for (int occ : {0, 2, 3, 4, 6})
-                for (int nt : {0, 2})
-                    for (int x : {0, 1}) {
-                        c.tile_sites = walk;
-                        c.block = b;
-                        c.occupancy = occ;
-                        c.nontemporal = nt;
-                        c.xcd_remap = x;
-                        out.push_back(c);
-                    }
+                for (int x : {0, 1}) {
+                    c.tile_sites = walk;
+                    c.block = b;
+                    c.occupancy = occ;
+                    c.xcd_remap = x;
+                    out.push_back(c);
+                }
     return out;
 }
 

@@ -244,12 +244,12 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
     using T = typename PrecT<SP>::T;
     const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
                                      : blockIdx.x;
+    // lanes in site order over the (x, y, z) volume, then t-chunks
     const uint32_t tid = blk * blockDim.x + threadIdx.x;
     const uint32_t V3 = a.stride[3], Lt = a.dims[3];
     const uint32_t chunk = tid / V3, r = tid - chunk * V3;
     const uint32_t t0 = chunk * a.walk;
     if (t0 < Lt) {
-        const uint32_t t1 = t0 + a.walk < Lt ? t0 + a.walk : Lt;
         uint32_t c[3], q = r;
 #pragma unroll
         for (int mu = 0; mu < 2; ++mu) {
@@ -257,6 +257,7 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
             q /= a.dims[mu];
         }
         c[2] = q;
+        const uint32_t t1 = t0 + a.walk < Lt ? t0 + a.walk : Lt;
         Cx<T> wb[2][3], hc[2][3];
         {   // backward t-hop of slice t0 and P+ psi(t0)
             const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);

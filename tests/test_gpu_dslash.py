@@ -102,12 +102,19 @@ def test_dslash_parity(pair, dims):
         fu, fin = device_inputs(dims, sp, lp, lay, lanes, links, psi, s)
         fout = su3.spinor_tensor(dims, sp, lay, lanes)
         prev = None
-        # one site per lane; walks of 3 t-slices; one walk over all of t
-        for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1),
-                    dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3),
+        # one site per lane; walks of 3 t-slices; one walk over all of t;
+        # walks of 4 and 2
+        for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1,
+                         schedule=0),
+                    dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3,
+                         schedule=0),
                     dict(block=128, nontemporal=2, occupancy=2, xcd_remap=0,
-                         tile_sites=4096)):
-            full = dict(persistent=0, lds_stage=0, schedule=0, **cfg)
+                         tile_sites=4096, schedule=0),
+                    dict(block=128, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=4,
+                         schedule=0),
+                    dict(block=64, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=2,
+                         schedule=0)):
+            full = dict(persistent=0, lds_stage=0, **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
                 su3.su3_dslash(fout, fu, fin, s)
