@@ -71,7 +71,11 @@ def parse():
                     help="headline only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
-                    help="use the library's default launch")
+                    help="no autotuning: the library's default launch, or the "
+                         "one cached in the file SU3_TUNE_CACHE names")
+    ap.add_argument("--only-dslash", action="store_true",
+                    help="time only the Wilson hopping term (48^4, FP64, "
+                         "SoA) and print its line (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain copies of known size (PMC scaling)")
     return ap.parse_args()
@@ -175,6 +179,10 @@ def main():
             return su3.su3_launch_get(expr, prec, layout, lanes, dims).as_dict()
         return su3.su3_autotune(expr, prec, layout, lanes, dims, stream).as_dict()
 
+    if args.only_dslash:
+        dslash_only(args, su3, torch, testgen, stream, timer, make, tune)
+        return
+
     # ------------------------------------------------------------ headline
     dims = (48, 48, 48, 48)
     V = testgen.volume(dims)
@@ -266,6 +274,23 @@ def main():
         "variants": variants,
     }
     print(json.dumps(out), flush=True)
+
+
+def dslash_only(args, su3, torch, testgen, stream, timer, make, tune):
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    F64, SOA = su3.SU3_F64, su3.SU3_LAYOUT_SOA
+    log(f"Dslash: {V} sites, FP64 SoA; generating inputs")
+    U = [make(dims, F64, SOA, 0, testgen.FID_U0 + mu) for mu in range(4)]
+    fin = su3.spinor_tensor(dims, F64, SOA)
+    su3.su3_field_upload(fin, testgen.spinor_field(V, seed=args.seed, field_id=200), stream)
+    fout = su3.spinor_tensor(dims, F64, SOA)
+    cfg = tune(su3.SU3_EXPR_DSLASH, F64, SOA, 0, dims)
+    ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), args.steps, args.warmup)
+    b = DSLASH_BYTES_PER_SITE[(0, 0)] * V
+    print(json.dumps({"kernel": "k_dslash (FP64 SoA 48^4)", "us": round(ms * 1e3, 2),
+                      "gbps": round(b / (ms * 1e-3) / 1e9, 1),
+                      "bytes_per_launch": b, "launch": cfg}), flush=True)
 
 
 def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
