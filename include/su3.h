@@ -40,6 +40,16 @@
  * field occupies V_pad * E * 2 * sizeof(real) bytes.  Padding sites are
  * zero after su3_field_alloc/su3_field_upload and are never written by a
  * compute call.
+ *     VNODE  Grid's virtual-node layout (Section 5), made by su3_vnode_*:
+ *            the lattice is split into N_sub = simd[0]*simd[1]*simd[2]*
+ *            simd[3] virtual nodes, one per SIMD lane, each a sub-lattice
+ *            of extents r[mu] = dims[mu] / simd[mu].  Site x has lane
+ *            coordinates l[mu] = x[mu] / r[mu] and outer coordinates
+ *            o[mu] = x[mu] % r[mu]; lane = l0 + simd0*(l1 + simd1*(l2 +
+ *            simd2*l3)), osite = o0 + r0*(o1 + r1*(o2 + r2*o3)).  It is
+ *            stored as AOSOA with L = N_sub at s = osite * N_sub + lane
+ *            (each scalar leaf is a vector of N_sub lanes, (re, im)
+ *            interleaved per lane), V_pad = V.
  */
 #ifndef SU3_H
 #define SU3_H
@@ -76,8 +86,18 @@ typedef enum su3_precision {
 typedef enum su3_layout {
     SU3_LAYOUT_AOS = 0,
     SU3_LAYOUT_SOA = 1,
-    SU3_LAYOUT_AOSOA = 2
+    SU3_LAYOUT_AOSOA = 2,
+    /* made by su3_vnode_alloc / su3_vnode_wrap only; as a launch-tuning
+     * key its `lanes` is N_sub */
+    SU3_LAYOUT_VNODE = 3
 } su3_layout;
+
+/* What a field holds per site: a 3x3 complex matrix or a spinor (4 spins x
+ * 3 colours). */
+typedef enum su3_kind {
+    SU3_KIND_MATRIX = 0,
+    SU3_KIND_SPINOR = 1
+} su3_kind;
 
 /* Fixed site-local expressions (Section 3, Listings 1-2; left-to-right
  * association as in v1+v2+v1*v2):
@@ -257,6 +277,29 @@ su3_status su3_spinor_wrap(su3_field **out, void *dev_ptr, size_t bytes,
  * `in` or a link field (SU3_ERR_ALIAS).  Asynchronous on `stream`. */
 su3_status su3_dslash(su3_field *out, su3_field *const links[4],
                       const su3_field *in, void *stream);
+
+/* --------------------------------------------- Grid virtual-node layout */
+
+/* Fields in Grid's virtual-node layout (SU3_LAYOUT_VNODE above; Section 5):
+ * Grid-layout data on the device is used as it is, with no repacking.
+ * `simd[mu]` (each >= 1, N_sub = their product a power of two <= 256)
+ * must divide dims[mu] (SU3_ERR_INVALID_ARG otherwise).  Every call that
+ * takes fields accepts these handles: site-local expressions and batches
+ * run on the storage as AoSoA(N_sub) (batches need N_sub >= 4), shifts
+ * and Dslash follow the virtual-node neighbours, and upload/download
+ * convert from/to the canonical host order.  Fields are compatible only
+ * with fields of the same dims, precision, kind and simd.  Arguments and
+ * errors otherwise as su3_field_bytes / su3_field_alloc / su3_field_wrap
+ * (matrix kind) and su3_spinor_* (spinor kind). */
+su3_status su3_vnode_bytes(const int32_t dims[4], su3_precision prec,
+                           su3_kind kind, const int32_t simd[4],
+                           size_t *bytes);
+su3_status su3_vnode_alloc(su3_field **out, const int32_t dims[4],
+                           su3_precision prec, su3_kind kind,
+                           const int32_t simd[4]);
+su3_status su3_vnode_wrap(su3_field **out, void *dev_ptr, size_t bytes,
+                          const int32_t dims[4], su3_precision prec,
+                          su3_kind kind, const int32_t simd[4]);
 
 /* ------------------------------------------------------------ batches */
 

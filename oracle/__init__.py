@@ -73,6 +73,10 @@ def _bind(lib):
     lib.oracle_dslash.restype = i32
     lib.oracle_set_threads.argtypes = [i32]
     lib.oracle_set_threads.restype = None
+    lib.oracle_vnode_pack.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+    lib.oracle_vnode_pack.restype = i32
+    lib.oracle_vnode_unpack.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+    lib.oracle_vnode_unpack.restype = i32
     return lib
 
 
@@ -207,6 +211,36 @@ class Oracle:
         out = np.zeros((V, 3, 3, 2), dtype=np.float64)
         rc = self.lib.oracle_unpack(self._p(raw), V, prec, layout, lanes,
                                     self._p(out))
+        assert rc == 0
+        return out
+
+    def vnode_pack(self, a, dims, simd, prec):
+        """Stored image (uint8) of a canonical matrix field (V, 3, 3, 2) or
+        spinor field (V, 4, 3, 2) in Grid's virtual-node layout."""
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        canon = 12 if a.shape[1:] == (4, 3, 2) else 9
+        entries = 6 if (canon == 9 and prec == 3) else canon
+        rb = {0: 8, 1: 4, 2: 2, 3: 4}[prec]
+        out = np.zeros(a.shape[0] * entries * 2 * rb, dtype=np.uint8)
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+        sm = np.ascontiguousarray(np.asarray(simd, dtype=np.int32))
+        rc = self.lib.oracle_vnode_pack(self._p(a), self._p(d), self._p(sm), prec,
+                                        entries, canon, self._p(out))
+        assert rc == 0
+        return out
+
+    def vnode_unpack(self, raw, dims, simd, prec, spinor=False):
+        """Canonical field from a virtual-node image (compressed rows 0-1
+        only: row 2 is left zero)."""
+        raw = np.ascontiguousarray(raw).view(np.uint8)
+        V = int(np.prod(dims))
+        canon = 12 if spinor else 9
+        entries = 6 if (not spinor and prec == 3) else canon
+        out = np.zeros((V, 4 if spinor else 3, 3, 2), dtype=np.float64)
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+        sm = np.ascontiguousarray(np.asarray(simd, dtype=np.int32))
+        rc = self.lib.oracle_vnode_unpack(self._p(raw), self._p(d), self._p(sm), prec,
+                                          entries, canon, self._p(out))
         assert rc == 0
         return out
 

@@ -23,7 +23,8 @@
  *     (Section 3, Listing 1), and composite expressions such as v1+v2 and
  *     v1+v2+v1*v2 associate left to right (Section 3, Listing 2);
  *   - the scalar (AoS) layout and the vector (AoSoV) layout whose scalar
- *     leaves hold several lanes (Sections 4 and 5).
+ *     leaves hold several lanes (Sections 4 and 5), including Grid's split
+ *     of the lattice into virtual nodes, one per SIMD lane (Section 5).
  * The reduced-precision storage forms (single, half with single-precision
  * arithmetic, two-row compressed) are not in the paper; their steps follow
  * the stated convention: quantise with round-to-nearest-even, widen
@@ -476,6 +477,98 @@ int oracle_pack(const double *canon, int64_t V, int prec, int layout,
             }
         }
     }
+    return 0;
+}
+
+/* Grid's virtual-node layout (Section 5): the lattice is split into
+ * N_sub virtual nodes, simd[mu] of them along direction mu; each holds a
+ * sub-lattice of extents r[mu] = dims[mu] / simd[mu] and occupies one SIMD
+ * lane, so every scalar leaf of a site object is a vector of N_sub lanes.
+ * The walk: outer site o (sub-lattice coordinates, x fastest), then entry
+ * e, then virtual node n (node coordinates, x fastest), then re/im; the
+ * lattice site is x[mu] = n[mu] * r[mu] + o[mu].  `entries` is the number
+ * of stored complex entries per site and `canon_entries` the number per
+ * canonical site (9 for matrices, 12 for spinors); the stored entries are
+ * canonical entries 0 .. entries-1.  Returns -1 for an invalid split. */
+static int vnode_walk_setup(const int32_t dims[4], const int32_t simd[4],
+                            int64_t r[4], int64_t *nsub, int64_t *nouter)
+{
+    *nsub = 1;
+    *nouter = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (dims[mu] <= 0 || simd[mu] <= 0 || dims[mu] % simd[mu] != 0)
+            return -1;
+        r[mu] = dims[mu] / simd[mu];
+        *nsub *= simd[mu];
+        *nouter *= r[mu];
+    }
+    return 0;
+}
+
+static int64_t vnode_site(const int32_t dims[4], const int64_t r[4],
+                          const int32_t simd[4], int64_t o, int64_t n)
+{
+    int64_t site = 0, stride = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int64_t om = o % r[mu], nm = n % simd[mu];
+        o /= r[mu];
+        n /= simd[mu];
+        site += (nm * r[mu] + om) * stride;
+        stride *= dims[mu];
+    }
+    return site;
+}
+
+int oracle_vnode_pack(const double *canon, const int32_t dims[4],
+                      const int32_t simd[4], int prec, int entries,
+                      int canon_entries, void *out)
+{
+    int64_t r[4], nsub, nouter;
+    if (vnode_walk_setup(dims, simd, r, &nsub, &nouter))
+        return -1;
+    int64_t w = 0;
+    for (int64_t o = 0; o < nouter; ++o)
+        for (int e = 0; e < entries; ++e)
+            for (int64_t n = 0; n < nsub; ++n) {
+                const int64_t site = vnode_site(dims, r, simd, o, n);
+                for (int c = 0; c < 2; ++c, ++w) {
+                    const double v = canon[2 * canon_entries * site + 2 * e + c];
+                    if (prec == P_F64)
+                        ((double *)out)[w] = v;
+                    else if (prec == P_F16)
+                        ((uint16_t *)out)[w] = half_from_float((float)v);
+                    else
+                        ((float *)out)[w] = (float)v;
+                }
+            }
+    return 0;
+}
+
+/* Inverse of oracle_vnode_pack (exact widening; entries beyond `entries`
+ * are left untouched). */
+int oracle_vnode_unpack(const void *in, const int32_t dims[4],
+                        const int32_t simd[4], int prec, int entries,
+                        int canon_entries, double *canon)
+{
+    int64_t r[4], nsub, nouter;
+    if (vnode_walk_setup(dims, simd, r, &nsub, &nouter))
+        return -1;
+    int64_t w = 0;
+    for (int64_t o = 0; o < nouter; ++o)
+        for (int e = 0; e < entries; ++e)
+            for (int64_t n = 0; n < nsub; ++n) {
+                const int64_t site = vnode_site(dims, r, simd, o, n);
+                for (int c = 0; c < 2; ++c, ++w) {
+                    double v;
+                    if (prec == P_F64)
+                        v = ((const double *)in)[w];
+                    else if (prec == P_F16)
+                        v = double_from_half(((const uint16_t *)in)[w]);
+                    else
+                        v = (double)((const float *)in)[w];
+                    canon[2 * canon_entries * site + 2 * e + c] = v;
+                }
+            }
     return 0;
 }
 

@@ -34,7 +34,8 @@ SU3_ERR_ALIAS = -5
 SU3_ERR_HIP = -6
 
 SU3_F64, SU3_F32, SU3_F16_F32ACC, SU3_C12_F32 = 0, 1, 2, 3
-SU3_LAYOUT_AOS, SU3_LAYOUT_SOA, SU3_LAYOUT_AOSOA = 0, 1, 2
+SU3_LAYOUT_AOS, SU3_LAYOUT_SOA, SU3_LAYOUT_AOSOA, SU3_LAYOUT_VNODE = 0, 1, 2, 3
+SU3_KIND_MATRIX, SU3_KIND_SPINOR = 0, 1
 SU3_EXPR_MUL, SU3_EXPR_MUL3, SU3_EXPR_MULADD, SU3_EXPR_ADD, SU3_EXPR_APB_AB = range(5)
 SU3_EXPR_CSHIFT, SU3_EXPR_MUL_SHIFTED = 5, 6  # launch-tuning keys only
 SU3_EXPR_DSLASH = 7  # launch-tuning key of su3_dslash (precision = links')
@@ -46,7 +47,8 @@ SYMBOLS = (
     "su3_field_data", "su3_field_upload", "su3_field_download",
     "su3_field_download_raw", "su3_mult", "su3_fused_eval", "su3_cshift",
     "su3_mult_shifted", "su3_spinor_bytes", "su3_spinor_alloc",
-    "su3_spinor_wrap", "su3_dslash",
+    "su3_spinor_wrap", "su3_dslash", "su3_vnode_bytes", "su3_vnode_alloc",
+    "su3_vnode_wrap",
     "su3_batch_create", "su3_batch_launch", "su3_batch_destroy",
     "su3_batch_tiles", "su3_autotune", "su3_batch_autotune", "su3_launch_get",
     "su3_launch_set",
@@ -121,6 +123,9 @@ def load():
         "su3_spinor_alloc": [pp, dims_t, i32, i32, i32],
         "su3_spinor_wrap": [pp, vp, sz, dims_t, i32, i32, i32],
         "su3_dslash": [vp, vp, vp, vp],
+        "su3_vnode_bytes": [dims_t, i32, i32, dims_t, ctypes.POINTER(sz)],
+        "su3_vnode_alloc": [pp, dims_t, i32, i32, dims_t],
+        "su3_vnode_wrap": [pp, vp, sz, dims_t, i32, i32, dims_t],
         "su3_batch_create": [pp, vp, vp, vp, i32, vp],
         "su3_batch_launch": [vp, vp],
         "su3_batch_destroy": [vp],
@@ -196,6 +201,7 @@ class Field:
     lanes: int
     owner: object = None  # torch tensor for wrapped fields
     spinor: bool = False
+    simd: tuple = None    # virtual nodes per direction (VNODE layout)
 
     @property
     def V(self):
@@ -360,6 +366,49 @@ def su3_dslash(out: Field, links, inp: Field, stream=None):
            load().su3_dslash(out.handle if out is not None else None, arr,
                              inp.handle if inp is not None else None,
                              _stream(stream)))
+
+
+# ------------------------------------------------- virtual-node layout
+
+def su3_vnode_bytes(dims, prec, kind, simd):
+    n = ctypes.c_size_t()
+    _check("su3_vnode_bytes",
+           load().su3_vnode_bytes(_dims(dims), prec, kind, _dims(simd), ctypes.byref(n)))
+    return n.value
+
+
+def su3_vnode_alloc(dims, prec, kind, simd):
+    h = ctypes.c_void_p()
+    _check("su3_vnode_alloc",
+           load().su3_vnode_alloc(ctypes.byref(h), _dims(dims), prec, kind, _dims(simd)))
+    return Field(h.value, tuple(dims), prec, SU3_LAYOUT_VNODE, volume(simd),
+                 spinor=kind == SU3_KIND_SPINOR, simd=tuple(simd))
+
+
+def su3_vnode_wrap(tensor_or_ptr, dims, prec, kind, simd, nbytes=None):
+    """Describe Grid-layout device memory as a field (as su3_field_wrap)."""
+    if isinstance(tensor_or_ptr, torch.Tensor):
+        t = tensor_or_ptr
+        ptr = t.data_ptr()
+        nbytes = t.numel() * t.element_size() if nbytes is None else nbytes
+        owner = t
+    else:
+        ptr, owner = int(tensor_or_ptr), None
+        if nbytes is None:
+            raise ValueError("nbytes is required with a raw pointer")
+    h = ctypes.c_void_p()
+    _check("su3_vnode_wrap",
+           load().su3_vnode_wrap(ctypes.byref(h), ptr, nbytes, _dims(dims), prec, kind,
+                                 _dims(simd)))
+    return Field(h.value, tuple(dims), prec, SU3_LAYOUT_VNODE, volume(simd), owner,
+                 spinor=kind == SU3_KIND_SPINOR, simd=tuple(simd))
+
+
+def vnode_tensor(dims, prec, simd, kind=SU3_KIND_MATRIX, device="cuda"):
+    """A torch byte tensor sized for a virtual-node field, wrapped."""
+    n = su3_vnode_bytes(dims, prec, kind, simd)
+    t = torch.zeros(n, dtype=torch.uint8, device=device)
+    return su3_vnode_wrap(t, dims, prec, kind, simd)
 
 
 # --------------------------------------------------------------- batches

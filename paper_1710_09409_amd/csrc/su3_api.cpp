@@ -37,6 +37,7 @@ struct su3_field {
     int32_t device;
     int32_t kind;   // 0: SU(3) matrices, 1: spinors
     int32_t canon;  // complex entries per site on the host (9 or 12)
+    int32_t simd[4];  // virtual nodes per direction (all 1 unless VNODE)
 };
 
 enum { KIND_MATRIX = 0, KIND_SPINOR = 1 };
@@ -91,17 +92,24 @@ struct Shape {
 
 static su3_status make_shape(const int32_t dims[4], int prec, int layout,
                              int32_t lanes, Shape *out,
-                             int kind = KIND_MATRIX)
+                             int kind = KIND_MATRIX,
+                             const int32_t *simd = nullptr)
 {
     if (!dims)
         return fail(SU3_ERR_INVALID_ARG, "dims is NULL");
     if (prec < SU3_F64 || prec > SU3_C12_F32)
         return fail(SU3_ERR_INVALID_ARG, "unknown precision %d", prec);
+    if (kind != KIND_MATRIX && kind != KIND_SPINOR)
+        return fail(SU3_ERR_INVALID_ARG, "unknown field kind %d", kind);
     if (kind == KIND_SPINOR && prec != SU3_F64 && prec != SU3_F32)
         return fail(SU3_ERR_UNSUPPORTED,
                     "spinor fields are stored in SU3_F64 or SU3_F32");
-    if (layout < SU3_LAYOUT_AOS || layout > SU3_LAYOUT_AOSOA)
+    if (layout < SU3_LAYOUT_AOS || layout > SU3_LAYOUT_VNODE)
         return fail(SU3_ERR_INVALID_ARG, "unknown layout %d", layout);
+    if (layout == SU3_LAYOUT_VNODE && !simd)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "virtual-node fields are made by su3_vnode_alloc / "
+                    "su3_vnode_wrap");
     int64_t V = 1;
     for (int d = 0; d < 4; ++d) {
         if (dims[d] <= 0)
@@ -117,6 +125,21 @@ static su3_status make_shape(const int32_t dims[4], int prec, int layout,
     s.rbytes = real_bytes(prec);
     if (layout == SU3_LAYOUT_AOS) {
         s.L = 1;
+        s.Vpad = V;
+    } else if (layout == SU3_LAYOUT_VNODE) {
+        int64_t n = 1;
+        for (int d = 0; d < 4; ++d) {
+            if (simd[d] < 1 || dims[d] % simd[d] != 0)
+                return fail(SU3_ERR_INVALID_ARG,
+                            "simd[%d] = %d must be >= 1 and divide dims[%d] = %d",
+                            d, simd[d], d, dims[d]);
+            n *= simd[d];
+        }
+        if (n > 256 || (n & (n - 1)) != 0)
+            return fail(SU3_ERR_INVALID_ARG,
+                        "N_sub = %lld virtual nodes must be a power of two <= 256",
+                        (long long)n);
+        s.L = n;
         s.Vpad = V;
     } else if (layout == SU3_LAYOUT_SOA) {
         s.Vpad = (V + 63) / 64 * 64;
@@ -136,6 +159,25 @@ static su3_status make_shape(const int32_t dims[4], int prec, int layout,
     s.bytes = (size_t)reals * s.rbytes;
     *out = s;
     return SU3_OK;
+}
+
+// Storage site of lattice site s: s itself, or osite * N_sub + lane in the
+// virtual-node layout.
+static int64_t storage_site(const su3_field *f, int64_t s)
+{
+    if (f->layout != SU3_LAYOUT_VNODE)
+        return s;
+    int64_t osite = 0, lane = 0, ostride = 1, lstride = 1;
+    for (int d = 0; d < 4; ++d) {
+        const int64_t x = s % f->dims[d];
+        s /= f->dims[d];
+        const int64_t r = f->dims[d] / f->simd[d];
+        osite += (x % r) * ostride;
+        lane += (x / r) * lstride;
+        ostride *= r;
+        lstride *= f->simd[d];
+    }
+    return osite * f->L + lane;
 }
 
 static Geom geom_of(const su3_field *f)
@@ -167,6 +209,7 @@ static Geom geom_of(const su3_field *f)
 // kernels' addressing.
 static inline int64_t stored_index(const su3_field *f, int64_t s, int e, int c)
 {
+    s = storage_site(f, s);
     return ((s / f->L) * f->E + e) * 2 * f->L + (s % f->L) * 2 + c;
 }
 
@@ -200,7 +243,8 @@ extern "C" su3_status su3_spinor_bytes(const int32_t dims[4],
 }
 
 static su3_field *new_handle(const int32_t dims[4], int prec, int layout,
-                             int32_t lanes, const Shape &s, int kind)
+                             int32_t lanes, const Shape &s, int kind,
+                             const int32_t *simd = nullptr)
 {
     su3_field *f = new su3_field();
     f->ptr = nullptr;
@@ -211,23 +255,28 @@ static su3_field *new_handle(const int32_t dims[4], int prec, int layout,
     f->L = s.L;
     f->prec = prec;
     f->layout = layout;
-    f->lanes = layout == SU3_LAYOUT_AOSOA ? lanes : 0;
+    f->lanes = layout == SU3_LAYOUT_AOSOA ? lanes
+               : layout == SU3_LAYOUT_VNODE ? (int32_t)s.L
+                                            : 0;
     f->E = s.E;
     f->rbytes = s.rbytes;
     f->owns = 0;
     f->device = -1;
     f->kind = kind;
     f->canon = kind == KIND_SPINOR ? kSpinorEntries : 9;
+    for (int d = 0; d < 4; ++d)
+        f->simd[d] = simd ? simd[d] : 1;
     return f;
 }
 
 static su3_status alloc_of_kind(su3_field **out, const int32_t dims[4],
-                                int prec, int layout, int32_t lanes, int kind)
+                                int prec, int layout, int32_t lanes, int kind,
+                                const int32_t *simd = nullptr)
 {
     if (!out)
         return fail(SU3_ERR_INVALID_ARG, "out is NULL");
     Shape s;
-    su3_status st = make_shape(dims, prec, layout, lanes, &s, kind);
+    su3_status st = make_shape(dims, prec, layout, lanes, &s, kind, simd);
     if (st != SU3_OK)
         return st;
     int dev = 0;
@@ -244,7 +293,7 @@ static su3_status alloc_of_kind(su3_field **out, const int32_t dims[4],
         (void)hipFree(p);
         return hip_fail(e, "hipMemset");
     }
-    su3_field *f = new_handle(dims, prec, layout, lanes, s, kind);
+    su3_field *f = new_handle(dims, prec, layout, lanes, s, kind, simd);
     f->ptr = p;
     f->owns = 1;
     f->device = dev;
@@ -268,7 +317,8 @@ extern "C" su3_status su3_spinor_alloc(su3_field **out, const int32_t dims[4],
 
 static su3_status wrap_of_kind(su3_field **out, void *dev_ptr, size_t bytes,
                                const int32_t dims[4], int prec, int layout,
-                               int32_t lanes, int kind)
+                               int32_t lanes, int kind,
+                               const int32_t *simd = nullptr)
 {
     if (!out)
         return fail(SU3_ERR_INVALID_ARG, "out is NULL");
@@ -277,7 +327,7 @@ static su3_status wrap_of_kind(su3_field **out, void *dev_ptr, size_t bytes,
     if (((uintptr_t)dev_ptr & 15) != 0)
         return fail(SU3_ERR_INVALID_ARG, "dev_ptr is not 16-byte aligned");
     Shape s;
-    su3_status st = make_shape(dims, prec, layout, lanes, &s, kind);
+    su3_status st = make_shape(dims, prec, layout, lanes, &s, kind, simd);
     if (st != SU3_OK)
         return st;
     if (bytes < s.bytes)
@@ -299,7 +349,7 @@ static su3_status wrap_of_kind(su3_field **out, void *dev_ptr, size_t bytes,
         return fail(SU3_ERR_INVALID_ARG,
                     "dev_ptr is not device memory of the current device %d",
                     dev);
-    su3_field *f = new_handle(dims, prec, layout, lanes, s, kind);
+    su3_field *f = new_handle(dims, prec, layout, lanes, s, kind, simd);
     f->ptr = dev_ptr;
     f->owns = 0;
     f->device = dev;
@@ -323,6 +373,54 @@ extern "C" su3_status su3_spinor_wrap(su3_field **out, void *dev_ptr,
 {
     return wrap_of_kind(out, dev_ptr, bytes, dims, prec, layout, lanes,
                         KIND_SPINOR);
+}
+
+// --------------------------------------------- virtual-node fields
+
+static su3_status check_simd(const int32_t *simd)
+{
+    if (!simd)
+        return fail(SU3_ERR_INVALID_ARG, "simd is NULL");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_vnode_bytes(const int32_t dims[4],
+                                      su3_precision prec, su3_kind kind,
+                                      const int32_t simd[4], size_t *bytes)
+{
+    su3_status st = check_simd(simd);
+    if (st != SU3_OK)
+        return st;
+    if (!bytes)
+        return fail(SU3_ERR_INVALID_ARG, "bytes is NULL");
+    Shape s;
+    st = make_shape(dims, prec, SU3_LAYOUT_VNODE, 0, &s, kind, simd);
+    if (st != SU3_OK)
+        return st;
+    *bytes = s.bytes;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_vnode_alloc(su3_field **out, const int32_t dims[4],
+                                      su3_precision prec, su3_kind kind,
+                                      const int32_t simd[4])
+{
+    su3_status st = check_simd(simd);
+    if (st != SU3_OK)
+        return st;
+    return alloc_of_kind(out, dims, prec, SU3_LAYOUT_VNODE, 0, kind, simd);
+}
+
+extern "C" su3_status su3_vnode_wrap(su3_field **out, void *dev_ptr,
+                                     size_t bytes, const int32_t dims[4],
+                                     su3_precision prec, su3_kind kind,
+                                     const int32_t simd[4])
+{
+    su3_status st = check_simd(simd);
+    if (st != SU3_OK)
+        return st;
+    return wrap_of_kind(out, dev_ptr, bytes, dims, prec, SU3_LAYOUT_VNODE, 0,
+                        kind, simd);
 }
 
 extern "C" su3_status su3_field_free(su3_field *f)
@@ -667,12 +765,17 @@ static void append_cache(const Key &k, const su3_launch &c, double us)
 
 // --------------------------------------------------------- validation
 
+static bool same_geometry(const su3_field *a, const su3_field *b)
+{
+    return a->layout == b->layout && a->lanes == b->lanes &&
+           std::memcmp(a->dims, b->dims, sizeof a->dims) == 0 &&
+           std::memcmp(a->simd, b->simd, sizeof a->simd) == 0 &&
+           a->device == b->device;
+}
+
 static bool same_shape(const su3_field *a, const su3_field *b)
 {
-    return a->kind == b->kind && a->prec == b->prec && a->layout == b->layout &&
-           a->lanes == b->lanes && a->dims[0] == b->dims[0] &&
-           a->dims[1] == b->dims[1] && a->dims[2] == b->dims[2] &&
-           a->dims[3] == b->dims[3] && a->device == b->device;
+    return a->kind == b->kind && a->prec == b->prec && same_geometry(a, b);
 }
 
 static bool overlaps(const su3_field *a, const su3_field *b)
@@ -752,8 +855,10 @@ static su3_status launch_item(su3_field *z, int expr,
         e = launch_site_lds(z->prec, expr, c.nontemporal, c.block, (int)grid,
                             a, st);
     } else {
-        const int S = z->layout == SU3_LAYOUT_AOS ? 1
-                                                  : natural_sites(z->prec, expr);
+        // S sites per lane must sit in one lane-block
+        int S = natural_sites(z->prec, expr);
+        if (z->layout == SU3_LAYOUT_AOS || z->L % S != 0)
+            S = 1;
         a.ngroups = (int32_t)((z->V + S - 1) / S);
         int64_t grid = (a.ngroups + c.block - 1) / c.block;
         if (c.persistent)
@@ -809,12 +914,20 @@ static su3_status launch_shift_op(int mode, su3_field *z, const su3_field *x,
     a.y = y->ptr;
     a.g = geom_of(z);
     a.nsites = (int32_t)z->V;
-    int64_t stride = 1;
-    for (int d = 0; d < mu; ++d)
-        stride *= z->dims[d];
+    // outer stride (storage sites) and extent along mu; lane stride and
+    // count along mu (1 lane outside the virtual-node layout)
+    int64_t ostride = z->layout == SU3_LAYOUT_VNODE ? z->L : 1;
+    int64_t lstride = 1;
+    for (int d = 0; d < mu; ++d) {
+        ostride *= z->dims[d] / z->simd[d];
+        lstride *= z->simd[d];
+    }
     const int64_t L = z->dims[mu];
-    a.stride = (uint32_t)stride;
-    a.extent = (uint32_t)L;
+    a.stride = (uint32_t)ostride;
+    a.extent = (uint32_t)(L / z->simd[mu]);
+    a.nlanes = (uint32_t)z->simd[mu];
+    a.lstride = (uint32_t)lstride;
+    a.lmask = z->layout == SU3_LAYOUT_VNODE ? (uint32_t)(z->L - 1) : 0u;
     a.shift = (uint32_t)(((int64_t)shift % L + L) % L);
     const int64_t grid = (z->V + c.block - 1) / c.block;
     hipError_t e = launch_shift(z->prec, mode, c.nontemporal, c.schedule,
@@ -895,16 +1008,26 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     a.gl = geom_of(u0);
     a.nsites = (int32_t)out->V;
     a.xcd_remap = c.xcd_remap;
-    int64_t stride = 1;
+    // outer extents and strides (storage sites), lane counts and strides
+    const bool vn = out->layout == SU3_LAYOUT_VNODE;
+    int64_t ostride = vn ? out->L : 1, lstride = 1;
+    uint32_t lg = 0;
+    while (vn && ((int64_t)1 << lg) < out->L)
+        ++lg;
+    a.lg = lg;
+    a.lmask = vn ? (uint32_t)(out->L - 1) : 0u;
     for (int mu = 0; mu < 4; ++mu) {
-        a.dims[mu] = (uint32_t)out->dims[mu];
-        a.stride[mu] = (uint32_t)stride;
-        stride *= out->dims[mu];
+        a.dims[mu] = (uint32_t)(out->dims[mu] / out->simd[mu]);
+        a.stride[mu] = (uint32_t)ostride;
+        a.nlanes[mu] = (uint32_t)out->simd[mu];
+        a.lstride[mu] = (uint32_t)lstride;
+        ostride *= a.dims[mu];
+        lstride *= out->simd[mu];
     }
-    // lanes: one per site, or one per (x, y, z) site and chunk of `walk`
-    // t-slices
+    // lanes: one per site, or (lexicographic site order only) one per
+    // (x, y, z) site and chunk of `walk` t-slices
     const int64_t Lt = out->dims[3];
-    a.walk = (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
+    a.walk = vn ? 1u : (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
     const int64_t lanes = a.walk <= 1 ? out->V
                                       : a.stride[3] * ((Lt + a.walk - 1) / a.walk);
     const int64_t grid = (lanes + c.block - 1) / c.block;
@@ -938,12 +1061,10 @@ extern "C" su3_status su3_dslash(su3_field *out, su3_field *const links[4],
             return fail(SU3_ERR_MISMATCH,
                         "links[%d] differs from links[0] in dims, precision, "
                         "layout, lanes or device", mu);
-        if (std::memcmp(u->dims, out->dims, sizeof u->dims) != 0 ||
-            u->layout != out->layout || u->lanes != out->lanes ||
-            u->device != out->device)
+        if (!same_geometry(u, out))
             return fail(SU3_ERR_MISMATCH,
                         "links[%d] differs from the spinors in dims, layout, "
-                        "lanes or device", mu);
+                        "lanes, virtual nodes or device", mu);
     }
     const int lp = links[0]->prec;
     if (lp == SU3_F16_F32ACC || spinor_prec_of_links(lp) != out->prec)
@@ -962,6 +1083,32 @@ extern "C" su3_status su3_dslash(su3_field *out, su3_field *const links[4],
 
 // ------------------------------------------------------- launch tuning
 
+// The virtual-node split a tuning key of N_sub = lanes stands for: factors
+// of two handed to t, z, y, x in turn where the extent allows.
+static su3_status default_simd(const int32_t dims[4], int32_t lanes,
+                               int32_t simd[4])
+{
+    if (!dims)
+        return fail(SU3_ERR_INVALID_ARG, "dims is NULL");
+    if (lanes < 1 || lanes > 256 || (lanes & (lanes - 1)) != 0)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "virtual-node lanes %d must be a power of two <= 256",
+                    lanes);
+    for (int d = 0; d < 4; ++d)
+        simd[d] = 1;
+    int left = lanes;
+    for (int round = 0; left > 1 && round < 64; ++round)
+        for (int d = 3; d >= 0 && left > 1; --d)
+            if (dims[d] > 0 && dims[d] % (2 * simd[d]) == 0) {
+                simd[d] *= 2;
+                left /= 2;
+            }
+    if (left > 1)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "dims cannot be split into %d virtual nodes", lanes);
+    return SU3_OK;
+}
+
 static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
                          int32_t lanes, const int32_t dims[4], Key *k,
                          Shape *shape)
@@ -971,8 +1118,15 @@ static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
     if (expr == SU3_EXPR_DSLASH && prec == SU3_F16_F32ACC)
         return fail(SU3_ERR_UNSUPPORTED,
                     "Dslash links are stored in F64, F32 or C12");
+    int32_t simd[4] = {1, 1, 1, 1};
+    if (layout == SU3_LAYOUT_VNODE) {
+        su3_status st = default_simd(dims, lanes, simd);
+        if (st != SU3_OK)
+            return st;
+    }
     Shape s;
-    su3_status st = make_shape(dims, prec, layout, lanes, &s);
+    su3_status st = make_shape(dims, prec, layout, lanes, &s, KIND_MATRIX,
+                               layout == SU3_LAYOUT_VNODE ? simd : nullptr);
     if (st != SU3_OK)
         return st;
     if (prec == SU3_C12_F32 &&
@@ -980,7 +1134,8 @@ static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
          expr == SU3_EXPR_APB_AB))
         return fail(SU3_ERR_UNSUPPORTED,
                     "the two-row compressed form supports MUL and MUL3 only");
-    *k = Key(expr, prec, layout, layout == SU3_LAYOUT_AOSOA ? lanes : 0,
+    *k = Key(expr, prec, layout,
+             layout == SU3_LAYOUT_AOSOA || layout == SU3_LAYOUT_VNODE ? lanes : 0,
              vbucket(s.V));
     if (shape)
         *shape = s;
@@ -1160,13 +1315,17 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
                      : dslash              ? 5
                                            : operands_of(expr);
     su3_field *f[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t simd[4] = {1, 1, 1, 1};
+    if (layout == SU3_LAYOUT_VNODE)
+        (void)default_simd(dims, lanes, simd);  // checked by key_of
     for (int i = 0; i <= nops && st == SU3_OK; ++i) {
-        if (dslash && i < 2)
-            st = su3_spinor_alloc(&f[i], dims,
-                                  (su3_precision)spinor_prec_of_links(prec),
-                                  layout, lanes);
+        const bool spinor = dslash && i < 2;
+        const int fp = spinor ? spinor_prec_of_links(prec) : prec;
+        const int kind = spinor ? KIND_SPINOR : KIND_MATRIX;
+        if (layout == SU3_LAYOUT_VNODE)
+            st = alloc_of_kind(&f[i], dims, fp, layout, 0, kind, simd);
         else
-            st = su3_field_alloc(&f[i], dims, prec, layout, lanes);
+            st = alloc_of_kind(&f[i], dims, fp, layout, lanes, kind);
         if (st == SU3_OK) {
             // a non-zero bit pattern (finite in every precision)
             hipError_t e = hipMemsetD32Async((hipDeviceptr_t)f[i]->ptr,
@@ -1255,9 +1414,11 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
             dev = z[i]->device;
         else if (z[i]->device != dev)
             return fail(SU3_ERR_MISMATCH, "batch items on different devices");
-        if (z[i]->layout == SU3_LAYOUT_AOS)
+        if (z[i]->layout == SU3_LAYOUT_AOS ||
+            (z[i]->layout == SU3_LAYOUT_VNODE && z[i]->L < 4))
             return fail(SU3_ERR_UNSUPPORTED,
-                        "batch item %d: batches take SoA or AoSoA fields", i);
+                        "batch item %d: batches take SoA, AoSoA or "
+                        "virtual-node fields with N_sub >= 4", i);
         BatchItem &it = items[i];
         std::memset(&it, 0, sizeof it);
         it.z = z[i]->ptr;

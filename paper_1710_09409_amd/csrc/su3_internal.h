@@ -53,17 +53,24 @@ struct SiteArgs {
 };
 
 // Arguments of the shifted-operand kernels: the operand y is read at the
-// neighbour s' of site s along one direction, s' = s + (c' - c) * stride
-// with c = (s / stride) % extent and c' = (c + shift) % extent.
+// neighbour s' of storage site s along one direction.  The coordinate
+// along the direction is x = l * extent + o with the outer coordinate
+// o = (s / stride) % extent and (virtual-node layout only, else l = 0)
+// the lane coordinate l = ((s & lmask) / lstride) % nlanes;
+// x' = (x + shift) mod (extent * nlanes) and
+// s' = s + (o' - o) * stride + (l' - l) * lstride.
 struct ShiftArgs {
     void *z;
     const void *x;   // unshifted left operand (product only)
     const void *y;   // shifted operand
     Geom g;
     int32_t nsites;
-    uint32_t stride;  // sites between neighbours along the direction
-    uint32_t extent;  // lattice extent along the direction
-    uint32_t shift;   // in [0, extent)
+    uint32_t stride;  // storage sites between outer neighbours
+    uint32_t extent;  // outer extent along the direction
+    uint32_t shift;   // in [0, extent * nlanes)
+    uint32_t nlanes;  // virtual nodes along the direction (1: none)
+    uint32_t lstride; // lanes between virtual-node neighbours
+    uint32_t lmask;   // N_sub - 1 (0 outside the virtual-node layout)
 };
 
 // One item of a batched launch (device-resident table).  The item owns
@@ -84,6 +91,9 @@ struct BatchItem {
 // 6 for the two-row form); both share dims, layout and lanes, so one site
 // index addresses either through its own Geom.  Direction mu has extent
 // dims[mu] and neighbour stride stride[mu] (x fastest).
+// In the virtual-node layout dims/stride describe the outer sub-lattice
+// (storage site s = osite * N_sub + lane, stride in storage sites) and
+// nlanes/lstride the lanes; elsewhere nlanes = 1, lg = lmask = 0.
 struct DslashArgs {
     void *out;
     const void *in;
@@ -93,8 +103,12 @@ struct DslashArgs {
     int32_t nsites;
     int32_t xcd_remap;  // 1: contiguous workgroup ranges per XCD
     uint32_t walk;      // t-slices per lane (1: one site per lane)
-    uint32_t dims[4];
-    uint32_t stride[4];
+    uint32_t dims[4];   // outer extents
+    uint32_t stride[4]; // outer strides (storage sites)
+    uint32_t nlanes[4]; // virtual nodes per direction
+    uint32_t lstride[4];
+    uint32_t lg;        // log2 N_sub
+    uint32_t lmask;     // N_sub - 1
 };
 
 // Kernel-unit entry points.  Each returns the launch's hipError_t.
@@ -120,7 +134,8 @@ hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
                         hipStream_t stream);
 // Wilson hopping term: spinor precision F64 with F64 links, F32 with F32
 // or C12 links.  walk == 1: one site per lane, grid * block >= nsites;
-// walk > 1: one lane per (x, y, z) site and chunk of `walk` t-slices,
+// walk > 1 (lexicographic site order only): one lane per (x, y, z) site
+// and chunk of `walk` t-slices,
 // grid * block >= stride[3] * ceil(dims[3] / walk).
 hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
                          int grid, size_t shm, const DslashArgs &a,

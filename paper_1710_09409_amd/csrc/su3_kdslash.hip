@@ -166,19 +166,67 @@ __device__ __forceinline__ void hop_bwd(const su3i::DslashArgs &a, uint32_t sb,
     reconstruct<MU, +1>(w, acc);
 }
 
-// Both hops of direction MU (forward first), c = the site's coordinate.
-template <int MU, int SP, int LP, int NT>
-__device__ __forceinline__ void hop(const su3i::DslashArgs &a, uint32_t s,
-                                    uint32_t c, Cx<typename PrecT<SP>::T> (&acc)[4][3])
+// Periodic neighbours of storage site s along MU (modulo 2^32, in range).
+// c: outer coordinate, l: lane coordinate (0 outside the virtual-node
+// layout).  Within the outer sub-lattice a step is +-stride; across its
+// edge the outer coordinate wraps and the lane coordinate steps (wrapping
+// over the lattice when there is one lane).
+template <int MU>
+__device__ __forceinline__ uint32_t fwd_site(const su3i::DslashArgs &a, uint32_t s,
+                                             uint32_t c, uint32_t l)
 {
     const uint32_t stride = a.stride[MU], L = a.dims[MU];
-    // periodic neighbours, branch-free
-    const uint32_t sf = s + stride - (c + 1 == L ? L * stride : 0u);
-    const uint32_t sb = s - stride + (c == 0 ? L * stride : 0u);
-    hop_fwd<MU, SP, LP, NT>(a, s, sf, acc);
+    const uint32_t n = a.nlanes[MU], ls = a.lstride[MU];
+    const uint32_t wrap = s - (L - 1) * stride + (l + 1 == n ? 0u - (n - 1) * ls : ls);
+    return c + 1 == L ? wrap : s + stride;
+}
+
+template <int MU>
+__device__ __forceinline__ uint32_t bwd_site(const su3i::DslashArgs &a, uint32_t s,
+                                             uint32_t c, uint32_t l)
+{
+    const uint32_t stride = a.stride[MU], L = a.dims[MU];
+    const uint32_t n = a.nlanes[MU], ls = a.lstride[MU];
+    const uint32_t wrap = s + (L - 1) * stride + (l == 0 ? (n - 1) * ls : 0u - ls);
+    return c == 0 ? wrap : s - stride;
+}
+
+// Both hops of direction MU (forward first).
+template <int MU, int SP, int LP, int NT>
+__device__ __forceinline__ void hop(const su3i::DslashArgs &a, uint32_t s,
+                                    uint32_t c, uint32_t l,
+                                    Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    hop_fwd<MU, SP, LP, NT>(a, s, fwd_site<MU>(a, s, c, l), acc);
     fence_acc(acc);
-    hop_bwd<MU, SP, LP, NT>(a, sb, acc);
+    hop_bwd<MU, SP, LP, NT>(a, bwd_site<MU>(a, s, c, l), acc);
     fence_acc(acc);
+}
+
+// Outer and lane coordinates of storage site s.
+__device__ __forceinline__ void coords(const su3i::DslashArgs &a, uint32_t s,
+                                       uint32_t (&c)[4], uint32_t (&l)[4])
+{
+    uint32_t r = s >> a.lg;
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+        c[mu] = r % a.dims[mu];
+        r /= a.dims[mu];
+    }
+    c[3] = r;
+    if (a.lmask) {
+        uint32_t q = s & a.lmask;
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            l[mu] = q % a.nlanes[mu];
+            q /= a.nlanes[mu];
+        }
+        l[3] = q;
+    } else {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+            l[mu] = 0;
+    }
 }
 
 template <int SP, int LP, int NT, int WPE = SP == su3i::F64 ? 3 : 4>
@@ -197,27 +245,18 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 acc[sp][c] = {T(0), T(0)};
-        // lattice coordinates (x fastest)
-        uint32_t c[4], r = s;
-#pragma unroll
-        for (int mu = 0; mu < 3; ++mu) {
-            c[mu] = r % a.dims[mu];
-            r /= a.dims[mu];
-        }
-        c[3] = r;
+        uint32_t c[4], l[4];
+        coords(a, s, c, l);
         // accumulation order shared with the walk kernel (results are
         // bitwise independent of the launch): t backward, t forward,
         // then x, y, z (forward, backward)
-        {
-            const uint32_t st = a.stride[3], Lt = a.dims[3];
-            hop_bwd<3, SP, LP, NT>(a, s - st + (c[3] == 0 ? Lt * st : 0u), acc);
-            fence_acc(acc);
-            hop_fwd<3, SP, LP, NT>(a, s, s + st - (c[3] + 1 == Lt ? Lt * st : 0u), acc);
-            fence_acc(acc);
-        }
-        hop<0, SP, LP, NT>(a, s, c[0], acc);
-        hop<1, SP, LP, NT>(a, s, c[1], acc);
-        hop<2, SP, LP, NT>(a, s, c[2], acc);
+        hop_bwd<3, SP, LP, NT>(a, bwd_site<3>(a, s, c[3], l[3]), acc);
+        fence_acc(acc);
+        hop_fwd<3, SP, LP, NT>(a, s, fwd_site<3>(a, s, c[3], l[3]), acc);
+        fence_acc(acc);
+        hop<0, SP, LP, NT>(a, s, c[0], l[0], acc);
+        hop<1, SP, LP, NT>(a, s, c[1], l[1], acc);
+        hop<2, SP, LP, NT>(a, s, c[2], l[2], acc);
         RawVec<SP, 1> raw[12];
 #pragma unroll
         for (int e = 0; e < 12; ++e)
@@ -229,7 +268,8 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
         occupancy_reserve[threadIdx.x] = 0;
 }
 
-// t-walk: a lane owns one (x, y, z) site and walks t-slices t0 .. t1-1.
+// t-walk (lexicographic site order): a lane owns one (x, y, z) site and
+// walks t-slices t0 .. t1-1.
 // Along t each spinor and each t-link is loaded once per walk: at slice t
 // the lane loads psi(t+1) and U_t(t) for the forward t-hop, and from the
 // same registers prepares the next slice's backward t-hop,
@@ -297,9 +337,9 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
             fence_acc(acc);
             fence_acc(wb);
             fence_acc(hc);
-            hop<0, SP, LP, NT>(a, s, c[0], acc);
-            hop<1, SP, LP, NT>(a, s, c[1], acc);
-            hop<2, SP, LP, NT>(a, s, c[2], acc);
+            hop<0, SP, LP, NT>(a, s, c[0], 0u, acc);
+            hop<1, SP, LP, NT>(a, s, c[1], 0u, acc);
+            hop<2, SP, LP, NT>(a, s, c[2], 0u, acc);
             RawVec<SP, 1> raw[12];
 #pragma unroll
             for (int e = 0; e < 12; ++e)

@@ -62,11 +62,24 @@ __global__ __launch_bounds__(kMaxSiteBlock) void k_shift(su3i::ShiftArgs a)
     constexpr int E = PrecT<P>::E;
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < (uint32_t)a.nsites) {
-        const uint32_t c = (s / a.stride) % a.extent;
-        uint32_t cn = c + a.shift;
-        if (cn >= a.extent)
-            cn -= a.extent;
-        const uint32_t sn = s + (cn - c) * a.stride;  // modulo 2^32, in range
+        // coordinate along the direction: outer part o, lane part l
+        const uint32_t o = (s / a.stride) % a.extent;
+        uint32_t l = 0, x = o;
+        if (a.nlanes > 1) {
+            l = ((s & a.lmask) / a.lstride) % a.nlanes;
+            x = l * a.extent + o;
+        }
+        const uint32_t ext = a.extent * a.nlanes;
+        uint32_t xn = x + a.shift;
+        if (xn >= ext)
+            xn -= ext;
+        uint32_t on = xn, ln = 0;
+        if (a.nlanes > 1) {
+            ln = xn / a.extent;
+            on = xn - ln * a.extent;
+        }
+        // modulo 2^32, in range
+        const uint32_t sn = s + (on - o) * a.stride + (ln - l) * a.lstride;
         const uint32_t off = site_offset(a.g, s);
         const uint32_t offn = site_offset(a.g, sn);
         if constexpr (MODE == 0) {

@@ -4,7 +4,8 @@
 // launch settings (which must agree), persistent grids, LDS staging, the
 // batch (tile rows, replays, autotuner), the shifted operands and the
 // Wilson hopping term (every precision pair and layout, two launch
-// settings, argument validation).  Any
+// settings, argument validation), and Grid's virtual-node layout (stored
+// image, products, shifts, Dslash).  Any
 // out-of-bounds access in a kernel's indexing aborts the run.  Prints
 // "fails 0" on success.
 #include "su3.h"
@@ -21,6 +22,7 @@ int oracle_cshift(const double *src, double *dst, const int32_t dims[4], int mu,
 void oracle_mult(const double *x, const double *y, double *z, int64_t V);
 int oracle_dslash(const double *const *u, const double *in, double *out, const int32_t dims[4]);
 void su3gen_spinor(uint64_t seed, uint64_t field_id, int64_t s_begin, int64_t count, double *out);
+int oracle_vnode_pack(const double *canon, const int32_t dims[4], const int32_t simd[4], int prec, int entries, int canon_entries, void *out);
 }
 static int nops_of(int e) { return e == 1 ? 3 : (e == 2 ? 4 : 2); }
 static int fails = 0;
@@ -285,6 +287,113 @@ int main(int argc, char **argv)
         for (int mu = 0; mu < 4; ++mu) { su3_field_free(u64[mu]); su3_field_free(links_c12[mu]); }
         su3_field_free(u16); su3_field_free(m64); su3_field_free(s64a); su3_field_free(s64b); su3_field_free(s32);
         printf("dslash cases done\n");
+    }
+    // virtual-node layout
+    {
+        struct Vn { int d[4]; int simd[4]; };
+        Vn cases[] = {{{4, 2, 6, 4}, {2, 1, 2, 2}}, {{3, 5, 7, 2}, {1, 1, 1, 2}}, {{2, 4, 4, 8}, {1, 1, 2, 4}},
+                      {{4, 4, 4, 4}, {2, 2, 2, 2}}, {{8, 3, 2, 2}, {8, 1, 1, 1}}, {{2, 2, 2, 2}, {1, 1, 1, 1}},
+                      {{4, 4, 8, 8}, {2, 2, 4, 2}}};
+        for (auto &c : cases) {
+            const int *d = c.d;
+            int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
+            for (int prec = 0; prec < 4; ++prec) {
+                std::vector<double> hx(18 * V), hy(18 * V), qx(18 * V), qy(18 * V), want(18 * V), got(18 * V), sy(18 * V);
+                su3gen_field(11, 1, 0, V, hx.data()); su3gen_field(11, 2, 0, V, hy.data());
+                oracle_roundtrip(prec, hx.data(), qx.data(), V); oracle_roundtrip(prec, hy.data(), qy.data(), V);
+                su3_field *fx, *fy, *fz;
+                if (su3_vnode_alloc(&fx, d, (su3_precision)prec, SU3_KIND_MATRIX, c.simd) != SU3_OK) { printf("vnode alloc %s\n", su3_last_error()); fails++; continue; }
+                su3_vnode_alloc(&fy, d, (su3_precision)prec, SU3_KIND_MATRIX, c.simd);
+                su3_vnode_alloc(&fz, d, (su3_precision)prec, SU3_KIND_MATRIX, c.simd);
+                su3_field_upload(fx, hx.data(), nullptr); su3_field_upload(fy, hy.data(), nullptr);
+                // stored image
+                {
+                    void *p; size_t n;
+                    su3_field_data(fx, &p, &n);
+                    std::vector<unsigned char> img(n);
+                    oracle_vnode_pack(hx.data(), d, c.simd, prec, prec == 3 ? 6 : 9, 9, img.data());
+                    if (memcmp(p, img.data(), n) != 0) { printf("vnode image differs prec %d\n", prec); fails++; }
+                }
+                for (int expr = 0; expr < (prec == 3 ? 2 : 5); ++expr) {
+                    int n = nops_of(expr);
+                    const su3_field *ops[4] = {fx, fy, fx, fy};
+                    const double *qo[4] = {qx.data(), qy.data(), qx.data(), qy.data()};
+                    oracle_fused(expr, qo[0], qo[1], n > 2 ? qo[2] : nullptr, n > 3 ? qo[3] : nullptr, want.data(), V);
+                    if (su3_fused_eval(fz, (su3_expr)expr, ops, n, nullptr) != SU3_OK) { printf("vnode eval %s\n", su3_last_error()); fails++; }
+                    su3_field_download(fz, got.data(), nullptr);
+                    double err = 0; int rows = prec == 3 ? 2 : 3;
+                    for (int64_t s = 0; s < V; ++s) for (int t = 0; t < rows * 6; ++t) err = std::max(err, std::fabs(got[18 * s + t] - want[18 * s + t]));
+                    if (err > (prec == 0 ? 1e-13 : (prec == 2 ? 5e-3 : 1e-5))) { printf("vnode expr %d prec %d err %.3e\n", expr, prec, err); fails++; }
+                }
+                for (int mu = 0; mu < 4; ++mu)
+                    for (int sh : {1, -1, 3, -5}) {
+                        oracle_cshift(qy.data(), sy.data(), d, mu, sh);
+                        if (su3_cshift(fz, fy, mu, sh, nullptr) != SU3_OK) { printf("vnode cshift %s\n", su3_last_error()); fails++; }
+                        su3_field_download(fz, got.data(), nullptr);
+                        if (memcmp(got.data(), sy.data(), 8 * 18 * V) != 0) { printf("vnode cshift mismatch prec %d mu %d sh %d simd %d%d%d%d\n", prec, mu, sh, c.simd[0], c.simd[1], c.simd[2], c.simd[3]); fails++; }
+                        if (su3_mult_shifted(fz, fx, fy, mu, sh, nullptr) != SU3_OK) { printf("vnode mult_shifted %s\n", su3_last_error()); fails++; }
+                        su3_field_download(fz, got.data(), nullptr);
+                        oracle_mult(qx.data(), sy.data(), want.data(), V);
+                        double err = 0; int rows = prec == 3 ? 2 : 3;
+                        for (int64_t s = 0; s < V; ++s) for (int t = 0; t < rows * 6; ++t) err = std::max(err, std::fabs(got[18 * s + t] - want[18 * s + t]));
+                        if (err > (prec == 0 ? 1e-14 : (prec == 2 ? 2e-3 : 2e-6))) { printf("vnode mult_shifted err %.3e\n", err); fails++; }
+                    }
+                su3_field_free(fx); su3_field_free(fy); su3_field_free(fz);
+            }
+            // Dslash
+            int pairs[][2] = {{0, 0}, {1, 1}, {1, 3}};
+            for (auto &pr : pairs) {
+                const int sp = pr[0], lp = pr[1];
+                std::vector<double> hu[4], qu[4], hin(24 * V), qin(24 * V), want(24 * V), got(24 * V);
+                const double *up[4];
+                su3_field *fu[4], *fin, *fout;
+                for (int mu = 0; mu < 4; ++mu) {
+                    hu[mu].resize(18 * V); qu[mu].resize(18 * V);
+                    su3gen_field(12, 2 + mu, 0, V, hu[mu].data());
+                    oracle_roundtrip(lp, hu[mu].data(), qu[mu].data(), V);
+                    up[mu] = qu[mu].data();
+                    su3_vnode_alloc(&fu[mu], d, (su3_precision)lp, SU3_KIND_MATRIX, c.simd);
+                    su3_field_upload(fu[mu], hu[mu].data(), nullptr);
+                }
+                su3gen_spinor(12, 200, 0, V, hin.data());
+                for (int64_t i = 0; i < 24 * V; ++i) qin[i] = sp == 0 ? hin[i] : (double)(float)hin[i];
+                oracle_dslash(up, qin.data(), want.data(), d);
+                su3_vnode_alloc(&fin, d, (su3_precision)sp, SU3_KIND_SPINOR, c.simd);
+                su3_vnode_alloc(&fout, d, (su3_precision)sp, SU3_KIND_SPINOR, c.simd);
+                su3_field_upload(fin, hin.data(), nullptr);
+                {
+                    void *p; size_t n;
+                    su3_field_data(fin, &p, &n);
+                    std::vector<unsigned char> img(n);
+                    oracle_vnode_pack(hin.data(), d, c.simd, sp, 12, 12, img.data());
+                    if (memcmp(p, img.data(), n) != 0) { printf("vnode spinor image differs\n"); fails++; }
+                }
+                if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("vnode dslash %s\n", su3_last_error()); fails++; }
+                su3_field_download(fout, got.data(), nullptr);
+                double err = 0;
+                for (int64_t i = 0; i < 24 * V; ++i) err = std::max(err, std::fabs(got[i] - want[i]));
+                if (err > (sp == 0 ? 1e-13 : 2e-5)) { printf("vnode dslash err %.3e sp %d lp %d simd %d%d%d%d\n", err, sp, lp, c.simd[0], c.simd[1], c.simd[2], c.simd[3]); fails++; }
+                su3_field_free(fin); su3_field_free(fout);
+                for (int mu = 0; mu < 4; ++mu) su3_field_free(fu[mu]);
+            }
+        }
+        // rules
+        int d[4] = {4, 4, 4, 4}, s1[4] = {2, 2, 1, 1}, s2[4] = {1, 1, 2, 2}, bad[4] = {3, 1, 1, 1}, odd[4] = {1, 1, 1, 3};
+        su3_field *a, *b, *z;
+        su3_vnode_alloc(&a, d, SU3_F64, SU3_KIND_MATRIX, s1);
+        su3_vnode_alloc(&b, d, SU3_F64, SU3_KIND_MATRIX, s2);
+        su3_vnode_alloc(&z, d, SU3_F64, SU3_KIND_MATRIX, s1);
+        if (su3_mult(z, a, b, nullptr) != SU3_ERR_MISMATCH) { printf("vnode simd mismatch accepted\n"); fails++; }
+        if (su3_mult(z, a, a, nullptr) != SU3_OK) { printf("vnode mult %s\n", su3_last_error()); fails++; }
+        su3_field *t;
+        size_t nb;
+        if (su3_vnode_alloc(&t, d, SU3_F64, SU3_KIND_MATRIX, bad) != SU3_ERR_INVALID_ARG) { printf("vnode non-dividing simd accepted\n"); fails++; }
+        int d12[4] = {4, 4, 4, 12};
+        if (su3_vnode_bytes(d12, SU3_F64, SU3_KIND_MATRIX, odd, &nb) != SU3_ERR_INVALID_ARG) { printf("vnode N_sub 3 accepted\n"); fails++; }
+        if (su3_field_alloc(&t, d, SU3_F64, SU3_LAYOUT_VNODE, 4) != SU3_ERR_INVALID_ARG) { printf("vnode via field_alloc accepted\n"); fails++; }
+        if (su3_vnode_bytes(d, SU3_F16_F32ACC, SU3_KIND_SPINOR, s1, &nb) != SU3_ERR_UNSUPPORTED) { printf("f16 vnode spinor accepted\n"); fails++; }
+        su3_field_free(a); su3_field_free(b); su3_field_free(z);
+        printf("vnode cases done\n");
     }
     printf("fails %d\n", fails);
     return fails != 0;

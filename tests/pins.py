@@ -513,10 +513,64 @@ def pin_dslash_gauge_covariant(orc):
     assert np.max(np.abs((lhs[..., 0] + 1j * lhs[..., 1]) - rhs)) < 1e-12
 
 
+def _vnode_numpy(a, dims, simd, prec):
+    """Virtual-node image built with numpy: each lattice axis split into
+    (node, outer) coordinates, then the outer axes moved outside the entry
+    axis and the node axes inside it."""
+    V = a.shape[0]
+    canon = a.shape[1] * a.shape[2]  # 9 or 12 complex entries
+    E = 6 if (canon == 9 and prec == O.C12) else canon
+    Lx, Ly, Lz, Lt = dims
+    sx, sy, sz, st = simd
+    ent = a.reshape(V, canon, 2)[:, :E, :]
+    g = ent.reshape(st, Lt // st, sz, Lz // sz, sy, Ly // sy, sx, Lx // sx, E, 2)
+    # axes: 0 nt 1 ot 2 nz 3 oz 4 ny 5 oy 6 nx 7 ox 8 e 9 c
+    img = g.transpose(1, 3, 5, 7, 8, 0, 2, 4, 6, 9).reshape(-1)
+    if prec == O.F64:
+        return img.view(np.uint8)
+    if prec == O.F16:
+        return img.astype(np.float32).astype(np.float16).view(np.uint8)
+    return img.astype(np.float32).view(np.uint8)
+
+
+VNODE_CASES = [((4, 2, 6, 4), (2, 1, 2, 2)), ((2, 4, 4, 8), (1, 1, 2, 4)),
+               ((8, 3, 2, 2), (8, 1, 1, 1)), ((3, 5, 7, 2), (1, 1, 1, 2)),
+               ((4, 4, 4, 4), (2, 2, 2, 2)), ((2, 2, 2, 2), (1, 1, 1, 1))]
+
+
+def pin_vnode_layout(orc):
+    """Grid's virtual-node images equal numpy's split/transpose
+    construction (matrices in every precision, spinors in F64/F32); with
+    one virtual node the image is the AoS one, with the x extent split
+    into single-site nodes it is AoSoA(Lx); unpack inverts pack."""
+    for dims, simd in VNODE_CASES:
+        V = int(np.prod(dims))
+        x = testgen.su3_field(V, field_id=32)
+        for prec in (O.F64, O.F32, O.F16, O.C12):
+            img = orc.vnode_pack(x, dims, simd, prec)
+            assert np.array_equal(img, _vnode_numpy(x, dims, simd, prec)), (dims, simd, prec)
+        psi = testgen.spinor_field(V, field_id=33)
+        for prec in (O.F64, O.F32):
+            img = orc.vnode_pack(psi, dims, simd, prec)
+            assert np.array_equal(img, _vnode_numpy(psi, dims, simd, prec)), (dims, simd)
+        back = orc.vnode_unpack(orc.vnode_pack(psi, dims, simd, O.F64), dims, simd, O.F64,
+                                spinor=True)
+        assert np.array_equal(back, psi)
+        if simd == (1, 1, 1, 1):
+            assert np.array_equal(orc.vnode_pack(x, dims, simd, O.F64),
+                                  orc.pack(x, O.F64, O.AOS))
+    dims = (8, 3, 2, 2)
+    x = testgen.su3_field(96, field_id=34)
+    for prec in (O.F64, O.F16, O.C12):
+        assert np.array_equal(orc.vnode_pack(x, dims, (8, 1, 1, 1), prec),
+                              orc.pack(x, prec, O.AOSOA, 8))
+
+
 ALL_PINS = [pin_identity, pin_phase_diag, pin_signed_permutations,
             pin_unitary_inverse, pin_numpy_matmul, pin_nonsymmetric,
             pin_product_invariants, pin_associative, pin_listing2,
             pin_fused_reductions, pin_fused_numpy, pin_fused_unitary,
             pin_quantisers, pin_c12_rebuild, pin_layouts, pin_roundtrip,
             pin_metrics, pin_cshift, pin_dslash_free_field,
-            pin_dslash_gamma5_hermitian, pin_dslash_gauge_covariant]
+            pin_dslash_gamma5_hermitian, pin_dslash_gauge_covariant,
+            pin_vnode_layout]

@@ -48,3 +48,4 @@ def test_kernels_under_asan(tmp_path):
     assert "fails 0" in r.stdout, tail
     assert "shift cases done" in r.stdout, tail
     assert "dslash cases done" in r.stdout, tail
+    assert "vnode cases done" in r.stdout, tail

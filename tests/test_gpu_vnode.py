@@ -1,0 +1,168 @@
+"""Grid's virtual-node layout on the GPU: the stored image equals the
+oracle's virtual-node walk byte for byte (matrices in every precision,
+spinors), Grid-layout data written by the host is used in place with no
+repacking, and products, fused expressions, shifts, Dslash and batches on
+virtual-node fields agree with the oracle (shifts bit-exact)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import testgen
+import paper_1710_09409_amd as su3
+from gpu_util import PREC_NAMES, PRECS, assert_parity, exprs_for
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((4, 2, 6, 4), (2, 1, 2, 2)), ((3, 5, 7, 2), (1, 1, 1, 2)),
+         ((8, 8, 8, 8), (2, 2, 2, 2)), ((8, 4, 8, 16), (1, 1, 4, 4)),
+         ((16, 8, 8, 8), (4, 2, 2, 4)), ((2, 2, 2, 2), (1, 1, 1, 1))]
+IDS = ["%s_%s" % ("x".join(map(str, d)), "".join(map(str, s))) for d, s in CASES]
+M, SP = su3.SU3_KIND_MATRIX, su3.SU3_KIND_SPINOR
+
+
+def vfield(dims, prec, simd, host, s, kind=M):
+    f = su3.vnode_tensor(dims, prec, simd, kind)
+    su3.su3_field_upload(f, host, s)
+    return f
+
+
+@pytest.mark.parametrize("dims,simd", CASES, ids=IDS)
+@pytest.mark.parametrize("prec", PRECS, ids=[PREC_NAMES[p] for p in PRECS])
+def test_vnode_image_and_expressions(dims, simd, prec):
+    s = torch.cuda.current_stream()
+    V = testgen.volume(dims)
+    ops = [testgen.su3_field(V, field_id=70 + k) for k in range(4)]
+    fs = [vfield(dims, prec, simd, h, s) for h in ops]
+    for f, h in zip(fs, ops):
+        assert np.array_equal(su3.su3_field_download_raw(f, s),
+                              O.get().vnode_pack(h, dims, simd, prec))
+    z = su3.vnode_tensor(dims, prec, simd)
+    for expr in exprs_for(prec):
+        n = su3.N_OPERANDS[expr]
+        su3.su3_fused_eval(z, expr, fs[:n], s)
+        su3.su3_sync(s)
+        got = su3.su3_field_download(z, s)
+        want = O.get().reference(expr, prec, ops[:n])
+        assert_parity(prec, expr, got, want, f"vnode {dims} {simd} expr {expr}")
+
+
+@pytest.mark.parametrize("dims,simd", CASES, ids=IDS)
+def test_vnode_no_repack(dims, simd):
+    """Grid-layout bytes built on the host (the oracle's walk) are wrapped
+    in place; the product's stored result is the oracle's walk of the
+    expected product."""
+    s = torch.cuda.current_stream()
+    V = testgen.volume(dims)
+    x, y = testgen.su3_field(V, field_id=80), testgen.su3_field(V, field_id=81)
+    tx = torch.from_numpy(O.get().vnode_pack(x, dims, simd, su3.SU3_F64)).cuda()
+    ty = torch.from_numpy(O.get().vnode_pack(y, dims, simd, su3.SU3_F64)).cuda()
+    tz = torch.zeros_like(tx)
+    fx = su3.su3_vnode_wrap(tx, dims, su3.SU3_F64, M, simd)
+    fy = su3.su3_vnode_wrap(ty, dims, su3.SU3_F64, M, simd)
+    fz = su3.su3_vnode_wrap(tz, dims, su3.SU3_F64, M, simd)
+    su3.su3_mult(fz, fx, fy, s)
+    su3.su3_sync(s)
+    got = O.get().vnode_unpack(tz.cpu().numpy(), dims, simd, su3.SU3_F64)
+    assert_parity(su3.SU3_F64, su3.SU3_EXPR_MUL, got, O.get().mult(x, y), "no repack")
+
+
+@pytest.mark.parametrize("dims,simd", CASES, ids=IDS)
+@pytest.mark.parametrize("prec", PRECS, ids=[PREC_NAMES[p] for p in PRECS])
+def test_vnode_shifts(dims, simd, prec):
+    s = torch.cuda.current_stream()
+    V = testgen.volume(dims)
+    x, y = testgen.su3_field(V, field_id=82), testgen.su3_field(V, field_id=83)
+    qx, qy = O.get().roundtrip(prec, x), O.get().roundtrip(prec, y)
+    fx, fy = vfield(dims, prec, simd, x, s), vfield(dims, prec, simd, y, s)
+    fz = su3.vnode_tensor(dims, prec, simd)
+    for mu in range(4):
+        for k in (1, -1, 2, -3, dims[mu] + 1):
+            want = O.get().cshift(qy, dims, mu, k)
+            su3.su3_cshift(fz, fy, mu, k, s)
+            assert np.array_equal(su3.su3_field_download(fz, s), want), (mu, k)
+            su3.su3_mult_shifted(fz, fx, fy, mu, k, s)
+            assert_parity(prec, su3.SU3_EXPR_MUL, su3.su3_field_download(fz, s),
+                          O.get().mult(qx, want), f"vnode shifted mu {mu} k {k}")
+
+
+@pytest.mark.parametrize("dims,simd", CASES, ids=IDS)
+def test_vnode_dslash(dims, simd):
+    from test_gpu_dslash import PAIRS, assert_dslash, reference
+    s = torch.cuda.current_stream()
+    V = testgen.volume(dims)
+    links = [testgen.su3_field(V, field_id=testgen.FID_U0 + mu) for mu in range(4)]
+    psi = testgen.spinor_field(V, field_id=201)
+    for sp, lp in PAIRS:
+        fu = [vfield(dims, lp, simd, u, s) for u in links]
+        fin = vfield(dims, sp, simd, psi, s, SP)
+        assert np.array_equal(su3.su3_field_download_raw(fin, s),
+                              O.get().vnode_pack(psi, dims, simd, sp))
+        fout = su3.vnode_tensor(dims, sp, simd, SP)
+        su3.su3_dslash(fout, fu, fin, s)
+        su3.su3_sync(s)
+        want, mag = reference(sp, lp, links, psi, dims)
+        assert_dslash(sp, lp, su3.su3_field_download(fout, s), want, mag,
+                      f"vnode {dims} {simd} {sp}/{lp}")
+
+
+def test_vnode_batch():
+    """Virtual-node items (N_sub >= 4) mixed with AoSoA and SoA items in
+    one batch, each equal to its own unbatched evaluation."""
+    s = torch.cuda.current_stream()
+    items = [((8, 8, 8, 8), su3.SU3_F64, (2, 2, 2, 2)),
+             ((8, 4, 8, 16), su3.SU3_C12_F32, (1, 1, 4, 4)),
+             ((16, 8, 8, 8), su3.SU3_F64, (4, 2, 2, 4)),
+             ((4, 4, 4, 4), su3.SU3_F32, None)]
+    zs, refs, ops = [], [], []
+    for i, (d, prec, simd) in enumerate(items):
+        V = testgen.volume(d)
+        hs = [testgen.su3_field(V, field_id=90 + 2 * i + k) for k in range(2)]
+        if simd:
+            fo = [vfield(d, prec, simd, h, s) for h in hs]
+            zs.append(su3.vnode_tensor(d, prec, simd))
+            refs.append(su3.vnode_tensor(d, prec, simd))
+        else:
+            fo = []
+            for h in hs:
+                f = su3.field_tensor(d, prec, su3.SU3_LAYOUT_AOSOA, 16)
+                su3.su3_field_upload(f, h, s)
+                fo.append(f)
+            zs.append(su3.field_tensor(d, prec, su3.SU3_LAYOUT_AOSOA, 16))
+            refs.append(su3.field_tensor(d, prec, su3.SU3_LAYOUT_AOSOA, 16))
+        ops.append(fo)
+        su3.su3_mult(refs[-1], fo[0], fo[1], s)
+    b = su3.su3_batch_create([su3.SU3_EXPR_MUL] * len(items), zs, ops, s)
+    for _ in range(2):
+        su3.su3_batch_launch(b, s)
+        su3.su3_sync(s)
+        for z, r in zip(zs, refs):
+            assert np.array_equal(su3.su3_field_download_raw(z, s),
+                                  su3.su3_field_download_raw(r, s))
+    su3.su3_batch_destroy(b)
+
+
+def test_vnode_rules():
+    s = torch.cuda.current_stream()
+    d = (4, 4, 4, 4)
+    a = su3.vnode_tensor(d, su3.SU3_F64, (2, 2, 1, 1))
+    b = su3.vnode_tensor(d, su3.SU3_F64, (1, 1, 2, 2))
+    c = su3.field_tensor(d, su3.SU3_F64, su3.SU3_LAYOUT_AOSOA, 8)
+    for x, y in ((a, b), (a, c)):
+        with pytest.raises(su3.Su3Error) as e:
+            su3.su3_mult(a, x, y, s)
+        assert e.value.status == su3.SU3_ERR_MISMATCH
+    for simd in ((3, 1, 1, 1), (1, 1, 1, 0)):
+        with pytest.raises(su3.Su3Error) as e:
+            su3.su3_vnode_bytes(d, su3.SU3_F64, M, simd)
+        assert e.value.status == su3.SU3_ERR_INVALID_ARG
+    two = [su3.vnode_tensor(d, su3.SU3_F64, (2, 1, 1, 1)) for _ in range(3)]
+    with pytest.raises(su3.Su3Error) as e:
+        su3.su3_batch_create([su3.SU3_EXPR_MUL], [two[0]], [two[1:]], s)
+    assert e.value.status == su3.SU3_ERR_UNSUPPORTED
+    # tuning keys of the layout are N_sub
+    cfg = su3.su3_autotune(su3.SU3_EXPR_MUL, su3.SU3_F64, su3.SU3_LAYOUT_VNODE, 16,
+                           (8, 8, 8, 8), s)
+    assert su3.su3_launch_get(su3.SU3_EXPR_MUL, su3.SU3_F64, su3.SU3_LAYOUT_VNODE, 16,
+                              (8, 8, 8, 8)).as_dict() == cfg.as_dict()
+    su3.su3_launch_reset()

@@ -42,6 +42,10 @@ MUTANTS = [
      "hop_term(u[mu] + 18 * s, 1, in + 24 * sb, mu, +1.0, acc);"),
     ("dslash_gamma_entry", "     {{0, 0}, {1, 0}, {0, 0}, {0, 0}},\n     {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},\n    /* gamma_3 */",
      "     {{0, 0}, {-1, 0}, {0, 0}, {0, 0}},\n     {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},\n    /* gamma_3 */"),
+    ("vnode_node_outer_swap", "site += (nm * r[mu] + om) * stride;",
+     "site += (om * simd[mu] + nm) * stride;"),
+    ("vnode_lane_order", "            for (int64_t n = 0; n < nsub; ++n) {\n                const int64_t site = vnode_site(dims, r, simd, o, n);\n                for (int c = 0; c < 2; ++c, ++w) {\n                    const double v",
+     "            for (int64_t n = 0; n < nsub; ++n) {\n                const int64_t site = vnode_site(dims, r, simd, o, (n % 2) * (nsub / 2) + n / 2);\n                for (int c = 0; c < 2; ++c, ++w) {\n                    const double v"),
     ("det_sign", "r += re_(m, 0, j) * cr - im_(m, 0, j) * ci;",
      "r += re_(m, 0, j) * cr + im_(m, 0, j) * ci;"),
 ]
