@@ -96,7 +96,9 @@ typedef enum su3_layout {
  * 3 colours). */
 typedef enum su3_kind {
     SU3_KIND_MATRIX = 0,
-    SU3_KIND_SPINOR = 1
+    SU3_KIND_SPINOR = 1,
+    SU3_KIND_REAL = 2,    /* one real per site */
+    SU3_KIND_COMPLEX = 3  /* one complex number per site */
 } su3_kind;
 
 /* Fixed site-local expressions (Section 3, Listings 1-2; left-to-right
@@ -120,11 +122,15 @@ typedef enum su3_expr {
     SU3_EXPR_MUL_SHIFTED = 6,
     /* launch-tuning key of su3_dslash; its precision is the links' one
      * (SU3_F64, SU3_F32 or SU3_C12_F32) */
-    SU3_EXPR_DSLASH = 7
+    SU3_EXPR_DSLASH = 7,
+    /* launch-tuning key of su3_program_eval; its precision is the
+     * arithmetic one (SU3_F64 or SU3_F32) */
+    SU3_EXPR_PROGRAM = 8
 } su3_expr;
 
 typedef struct su3_field su3_field;
 typedef struct su3_batch su3_batch;
+typedef struct su3_program su3_program;
 
 /* How a compute call is launched.  Any valid setting gives bit-identical
  * results; only speed differs.
@@ -277,6 +283,69 @@ su3_status su3_spinor_wrap(su3_field **out, void *dev_ptr, size_t bytes,
  * `in` or a link field (SU3_ERR_ALIAS).  Asynchronous on `stream`. */
 su3_status su3_dslash(su3_field *out, su3_field *const links[4],
                       const su3_field *in, void *stream);
+
+/* ------------------------------------------------------ scalar fields */
+
+/* Real or complex scalar fields (kind SU3_KIND_REAL / SU3_KIND_COMPLEX),
+ * like the Lattice<double> fields of Section 3, Listing 2: one entry per
+ * site, stored with E = 1 (real: V_pad reals; complex: V_pad (re, im)
+ * pairs), so the layout changes only the padding.  Precisions SU3_F64 and
+ * SU3_F32.  Host canonical data for upload/download: V doubles (real) or
+ * V (re, im) pairs (complex).  Only expression programs (below) compute on
+ * them.  Arguments and errors as su3_field_bytes / alloc / wrap;
+ * SU3_ERR_INVALID_ARG for another kind. */
+su3_status su3_scalar_bytes(const int32_t dims[4], su3_precision prec,
+                            su3_layout layout, int32_t lanes, su3_kind kind,
+                            size_t *bytes);
+su3_status su3_scalar_alloc(su3_field **out, const int32_t dims[4],
+                            su3_precision prec, su3_layout layout,
+                            int32_t lanes, su3_kind kind);
+su3_status su3_scalar_wrap(su3_field **out, void *dev_ptr, size_t bytes,
+                           const int32_t dims[4], su3_precision prec,
+                           su3_layout layout, int32_t lanes, su3_kind kind);
+
+/* ------------------------------------------------ expression programs */
+
+/* General site-local expressions (Section 3: the expression template
+ * engine evaluates arbitrary expressions such as v1+v2+v1*v2, Listing 2,
+ * site by site, Listing 1), compiled on the host into a register program
+ * that one precompiled kernel evaluates at every site.  Grammar:
+ *   expr    := term (('+' | '-') term)*
+ *   term    := unary ('*' unary)*
+ *   unary   := '-' unary | primary
+ *   primary := number | 'i' | operand | func '(' expr ')' | '(' expr ')'
+ *   operand := 'a' .. 'h'   (operand fields 0 .. 7, kinds[k] their kinds)
+ *   func    := adj | conj | transpose | trace | real | imag
+ * Values are real scalars, complex scalars or 3x3 complex matrices
+ * (SU3_KIND_MATRIX operands); a scalar meets a matrix as a multiple of
+ * the identity (s + M adds s to the diagonal, s * M scales), trace maps a
+ * matrix to a complex scalar, real/imag map scalars to real scalars.
+ * Products associate left to right: a*b*c = (a*b)*c.  A constant alone
+ * ("1.0") assigns it to every site.  Spinor operands are unsupported.
+ * SU3_ERR_INVALID_ARG for a syntax or type error, or an expression needing
+ * more than 8 registers or 48 instructions (text in su3_last_error). */
+su3_status su3_program_create(su3_program **out, const char *expr,
+                              int32_t n_ops, const su3_kind *kinds);
+
+/* Result kind (matrix, real or complex), instruction and register count. */
+su3_status su3_program_info(const su3_program *p, su3_kind *result_kind,
+                            int32_t *n_instr, int32_t *n_regs);
+
+/* z = expr(ops[0..n_ops-1]) at every site, in one kernel.  Every field
+ * shares dims, layout, lanes (and virtual-node split) with z; ops[k] has
+ * kind kinds[k] and z the result kind (SU3_ERR_MISMATCH otherwise).
+ * Arithmetic is double when every field is SU3_F64 and single when every
+ * field is SU3_F32 or SU3_C12_F32 (mixed: SU3_ERR_MISMATCH; half:
+ * SU3_ERR_UNSUPPORTED).  A compressed output needs an SU(3)-valued
+ * expression (products, adj, transpose, conj of matrices), and double
+ * arithmetic at most 4 registers (SU3_ERR_UNSUPPORTED otherwise).  z may
+ * be an operand exactly; a partial overlap is SU3_ERR_ALIAS. */
+su3_status su3_program_eval(const su3_program *p, su3_field *z,
+                            const su3_field *const *ops, int32_t n_ops,
+                            void *stream);
+
+/* Release a program.  NULL is accepted. */
+su3_status su3_program_destroy(su3_program *p);
 
 /* --------------------------------------------- Grid virtual-node layout */
 

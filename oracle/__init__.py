@@ -77,6 +77,8 @@ def _bind(lib):
     lib.oracle_vnode_pack.restype = i32
     lib.oracle_vnode_unpack.argtypes = [vp, vp, vp, i32, i32, i32, vp]
     lib.oracle_vnode_unpack.restype = i32
+    lib.oracle_eval_expr.argtypes = [ctypes.c_char_p, i32, vp, vp, vp, i64]
+    lib.oracle_eval_expr.restype = i32
     return lib
 
 
@@ -243,6 +245,27 @@ class Oracle:
                                           entries, canon, self._p(out))
         assert rc == 0
         return out
+
+    def eval_expr(self, text, fields, kinds, V=None):
+        """Evaluate a site-local expression over operand fields a, b, ...
+        (canonical arrays: matrices (V, 3, 3, 2), real (V,), complex (V, 2));
+        kinds 0 matrix, 2 real, 3 complex.  Returns the result in the same
+        forms; raises ValueError for a malformed or ill-typed expression."""
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in fields]
+        if V is None:
+            V = fs[0].shape[0]
+        out = np.zeros(V * 18, dtype=np.float64)
+        kk = np.ascontiguousarray(np.asarray(kinds, dtype=np.int32))
+        arr = (ctypes.c_void_p * max(1, len(fs)))(*[f.ctypes.data for f in fs])
+        rk = self.lib.oracle_eval_expr(text.encode(), len(fs), self._p(kk),
+                                       ctypes.cast(arr, ctypes.c_void_p), self._p(out), V)
+        if rk < 0:
+            raise ValueError(f"expression {text!r} rejected")
+        if rk == 0:
+            return out.reshape(V, 3, 3, 2)
+        if rk == 3:
+            return out[:2 * V].reshape(V, 2).copy()
+        return out[:V].copy()
 
     def metrics(self, zh, z=None):
         """dict(e_max, r_max, d_u, d_det) of zh (against z where given)."""

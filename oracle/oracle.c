@@ -32,6 +32,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
@@ -682,4 +683,369 @@ void oracle_metrics(const double *zh, const double *z, int64_t V, double *out)
     out[1] = rmax;
     out[2] = du;
     out[3] = dd;
+}
+
+/* ------------------------------------------------------------------------
+ * General site-local expressions (Section 3: the expression template
+ * engine evaluates arbitrary expressions site by site, e.g. v1+v2+v1*v2 on
+ * Lattice<double> fields, Listing 2).  The text is parsed into a tree once
+ * and the tree is evaluated at every site with plain double arithmetic.
+ * Grammar: sums and differences of products of unary terms; a unary term
+ * is an optional minus sign and a number, the imaginary unit i, an operand
+ * a..h, a parenthesised expression, or adj / conj / transpose / trace /
+ * real / imag of one.  Values are real scalars, complex scalars or 3x3
+ * complex matrices; a scalar meets a matrix as that multiple of the
+ * identity (added to the diagonal, or scaling every entry).
+ * Operand kinds: 0 matrix (18 doubles per site), 2 real (1 double),
+ * 3 complex (2 doubles).  Result written in the same forms.  Returns the
+ * result kind, or -1 for a malformed or ill-typed expression.
+ * ---------------------------------------------------------------------- */
+
+enum { EN_OPND, EN_NUM, EN_NEG, EN_ADD, EN_SUB, EN_MUL, EN_FN };
+enum { EF_ADJ, EF_CONJ, EF_TRANS, EF_TRACE, EF_REAL, EF_IMAG };
+enum { ET_REAL = 0, ET_CPLX = 1, ET_MAT = 2 };
+
+typedef struct {
+    int kind, operand, fn, l, r, type;
+    double re, im;
+} enode;
+
+typedef struct {
+    const char *p;
+    enode n[256];
+    int count;
+    int bad;
+} eparse;
+
+static int e_new(eparse *ps, int kind)
+{
+    if (ps->count >= 256) {
+        ps->bad = 1;
+        return 0;
+    }
+    enode *x = &ps->n[ps->count];
+    memset(x, 0, sizeof *x);
+    x->kind = kind;
+    x->l = x->r = -1;
+    return ps->count++;
+}
+
+static void e_space(eparse *ps)
+{
+    while (*ps->p == ' ' || *ps->p == '\t' || *ps->p == '\n')
+        ps->p++;
+}
+
+static int e_sum(eparse *ps);
+
+static int e_unary(eparse *ps)
+{
+    e_space(ps);
+    if (ps->bad)
+        return 0;
+    const char c = *ps->p;
+    if (c == '-') {
+        ps->p++;
+        int k = e_new(ps, EN_NEG);
+        int child = e_unary(ps);
+        ps->n[k].l = child;
+        return k;
+    }
+    if ((c >= '0' && c <= '9') || c == '.') {
+        char *end;
+        double v = strtod(ps->p, &end);
+        if (end == ps->p) {
+            ps->bad = 1;
+            return 0;
+        }
+        ps->p = end;
+        int k = e_new(ps, EN_NUM);
+        ps->n[k].re = v;
+        return k;
+    }
+    if (c == '(') {
+        ps->p++;
+        int k = e_sum(ps);
+        e_space(ps);
+        if (*ps->p != ')')
+            ps->bad = 1;
+        else
+            ps->p++;
+        return k;
+    }
+    /* a name */
+    char name[16];
+    int len = 0;
+    while (((*ps->p >= 'a' && *ps->p <= 'z') || (*ps->p >= 'A' && *ps->p <= 'Z')) &&
+           len < 15)
+        name[len++] = *ps->p++;
+    name[len] = 0;
+    if (len == 0) {
+        ps->bad = 1;
+        return 0;
+    }
+    if (len == 1 && name[0] == 'i') {
+        int k = e_new(ps, EN_NUM);
+        ps->n[k].im = 1.0;
+        return k;
+    }
+    if (len == 1 && name[0] >= 'a' && name[0] <= 'h') {
+        int k = e_new(ps, EN_OPND);
+        ps->n[k].operand = name[0] - 'a';
+        return k;
+    }
+    static const char *fns[] = {"adj", "conj", "transpose", "trace", "real", "imag"};
+    for (int f = 0; f < 6; ++f)
+        if (strcmp(name, fns[f]) == 0) {
+            e_space(ps);
+            if (*ps->p != '(') {
+                ps->bad = 1;
+                return 0;
+            }
+            ps->p++;
+            int k = e_new(ps, EN_FN);
+            ps->n[k].fn = f;
+            int child = e_sum(ps);
+            ps->n[k].l = child;
+            e_space(ps);
+            if (*ps->p != ')')
+                ps->bad = 1;
+            else
+                ps->p++;
+            return k;
+        }
+    ps->bad = 1;
+    return 0;
+}
+
+static int e_product(eparse *ps)
+{
+    int k = e_unary(ps);
+    for (;;) {
+        e_space(ps);
+        if (ps->bad || *ps->p != '*')
+            return k;
+        ps->p++;
+        int m = e_new(ps, EN_MUL);
+        int r = e_unary(ps);
+        ps->n[m].l = k;
+        ps->n[m].r = r;
+        k = m;
+    }
+}
+
+static int e_sum(eparse *ps)
+{
+    int k = e_product(ps);
+    for (;;) {
+        e_space(ps);
+        if (ps->bad || (*ps->p != '+' && *ps->p != '-'))
+            return k;
+        int m = e_new(ps, *ps->p == '+' ? EN_ADD : EN_SUB);
+        ps->p++;
+        int r = e_product(ps);
+        ps->n[m].l = k;
+        ps->n[m].r = r;
+        k = m;
+    }
+}
+
+/* static types; -1 on a type error */
+static int e_type(eparse *ps, int k, int nops, const int *kinds)
+{
+    enode *x = &ps->n[k];
+    int a, b;
+    switch (x->kind) {
+    case EN_OPND:
+        if (x->operand >= nops)
+            return -1;
+        x->type = kinds[x->operand] == 0 ? ET_MAT
+                  : kinds[x->operand] == 2 ? ET_REAL
+                  : kinds[x->operand] == 3 ? ET_CPLX
+                                           : -1;
+        return x->type;
+    case EN_NUM:
+        return x->type = x->im != 0.0 ? ET_CPLX : ET_REAL;
+    case EN_NEG:
+        return x->type = e_type(ps, x->l, nops, kinds);
+    case EN_FN:
+        a = e_type(ps, x->l, nops, kinds);
+        if (a < 0)
+            return -1;
+        if (x->fn == EF_TRACE)
+            return x->type = a == ET_MAT ? ET_CPLX : a;
+        if (x->fn == EF_REAL || x->fn == EF_IMAG)
+            return x->type = a == ET_MAT ? -1 : ET_REAL;
+        return x->type = a;
+    default:
+        a = e_type(ps, x->l, nops, kinds);
+        b = e_type(ps, x->r, nops, kinds);
+        if (a < 0 || b < 0)
+            return -1;
+        if (a == ET_MAT || b == ET_MAT)
+            return x->type = ET_MAT;
+        return x->type = (a == ET_CPLX || b == ET_CPLX) ? ET_CPLX : ET_REAL;
+    }
+}
+
+/* A value: 3x3 complex matrix m (row-major, re/im), or a scalar in m[0..1]. */
+typedef struct {
+    int mat;
+    double m[18];
+} evalue;
+
+static void e_scalar_times(double sr, double si, const double *in, double *out)
+{
+    for (int e = 0; e < 9; ++e) {
+        const double r = in[2 * e], i = in[2 * e + 1];
+        out[2 * e] = sr * r - si * i;
+        out[2 * e + 1] = sr * i + si * r;
+    }
+}
+
+static evalue e_eval(const eparse *ps, int k, const double *const *fields,
+                     const int *kinds, int64_t s)
+{
+    const enode *x = &ps->n[k];
+    evalue v, a, b;
+    memset(&v, 0, sizeof v);
+    switch (x->kind) {
+    case EN_OPND: {
+        const double *f = fields[x->operand];
+        if (kinds[x->operand] == 0) {
+            v.mat = 1;
+            memcpy(v.m, f + 18 * s, sizeof v.m);
+        } else if (kinds[x->operand] == 2) {
+            v.m[0] = f[s];
+        } else {
+            v.m[0] = f[2 * s];
+            v.m[1] = f[2 * s + 1];
+        }
+        return v;
+    }
+    case EN_NUM:
+        v.m[0] = x->re;
+        v.m[1] = x->im;
+        return v;
+    case EN_NEG:
+        a = e_eval(ps, x->l, fields, kinds, s);
+        v.mat = a.mat;
+        for (int t = 0; t < 18; ++t)
+            v.m[t] = -a.m[t];
+        return v;
+    case EN_FN:
+        a = e_eval(ps, x->l, fields, kinds, s);
+        v.mat = a.mat;
+        switch (x->fn) {
+        case EF_ADJ:
+        case EF_TRANS:
+            if (!a.mat) {
+                v = a;
+                if (x->fn == EF_ADJ)
+                    v.m[1] = -a.m[1];
+                return v;
+            }
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    v.m[2 * (3 * i + j)] = a.m[2 * (3 * j + i)];
+                    v.m[2 * (3 * i + j) + 1] =
+                        x->fn == EF_ADJ ? -a.m[2 * (3 * j + i) + 1] : a.m[2 * (3 * j + i) + 1];
+                }
+            return v;
+        case EF_CONJ:
+            v = a;
+            for (int e = 0; e < 9; ++e)
+                v.m[2 * e + 1] = -a.m[2 * e + 1];
+            return v;
+        case EF_TRACE:
+            if (!a.mat)
+                return a;
+            v.mat = 0;
+            v.m[0] = (a.m[0] + a.m[8]) + a.m[16];
+            v.m[1] = (a.m[1] + a.m[9]) + a.m[17];
+            return v;
+        case EF_REAL:
+            v.m[0] = a.m[0];
+            return v;
+        default:  /* imag */
+            v.m[0] = a.m[1];
+            return v;
+        }
+    default:
+        break;
+    }
+    a = e_eval(ps, x->l, fields, kinds, s);
+    b = e_eval(ps, x->r, fields, kinds, s);
+    if (x->kind == EN_MUL) {
+        if (a.mat && b.mat) {
+            v.mat = 1;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double re = 0.0, im = 0.0;
+                    for (int q = 0; q < 3; ++q) {
+                        const double ar = a.m[2 * (3 * i + q)], ai = a.m[2 * (3 * i + q) + 1];
+                        const double br = b.m[2 * (3 * q + j)], bi = b.m[2 * (3 * q + j) + 1];
+                        re += ar * br - ai * bi;
+                        im += ar * bi + ai * br;
+                    }
+                    v.m[2 * (3 * i + j)] = re;
+                    v.m[2 * (3 * i + j) + 1] = im;
+                }
+        } else if (a.mat) {
+            v.mat = 1;
+            e_scalar_times(b.m[0], b.m[1], a.m, v.m);
+        } else if (b.mat) {
+            v.mat = 1;
+            e_scalar_times(a.m[0], a.m[1], b.m, v.m);
+        } else {
+            v.m[0] = a.m[0] * b.m[0] - a.m[1] * b.m[1];
+            v.m[1] = a.m[0] * b.m[1] + a.m[1] * b.m[0];
+        }
+        return v;
+    }
+    /* sum or difference; a scalar is added to (subtracted from) the diagonal */
+    const double sg = x->kind == EN_ADD ? 1.0 : -1.0;
+    if (!a.mat && !b.mat) {
+        v.m[0] = a.m[0] + sg * b.m[0];
+        v.m[1] = a.m[1] + sg * b.m[1];
+        return v;
+    }
+    v.mat = 1;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int c = 0; c < 2; ++c) {
+                const int t = 2 * (3 * i + j) + c;
+                const double av = a.mat ? a.m[t] : (i == j ? a.m[c] : 0.0);
+                const double bv = b.mat ? b.m[t] : (i == j ? b.m[c] : 0.0);
+                v.m[t] = av + sg * bv;
+            }
+    return v;
+}
+
+int oracle_eval_expr(const char *text, int nops, const int *kinds,
+                     const double *const *fields, double *out, int64_t V)
+{
+    eparse ps;
+    memset(&ps, 0, sizeof ps);
+    ps.p = text;
+    int root = e_sum(&ps);
+    e_space(&ps);
+    if (ps.bad || *ps.p)
+        return -1;
+    int ty = e_type(&ps, root, nops, kinds);
+    if (ty < 0)
+        return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < V; ++s) {
+        evalue v = e_eval(&ps, root, fields, kinds, s);
+        if (ty == ET_MAT)
+            memcpy(out + 18 * s, v.m, sizeof v.m);
+        else if (ty == ET_CPLX) {
+            out[2 * s] = v.m[0];
+            out[2 * s + 1] = v.m[1];
+        } else {
+            out[s] = v.m[0];
+        }
+    }
+    return ty == ET_MAT ? 0 : (ty == ET_CPLX ? 3 : 2);
 }

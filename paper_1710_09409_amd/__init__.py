@@ -35,10 +35,11 @@ SU3_ERR_HIP = -6
 
 SU3_F64, SU3_F32, SU3_F16_F32ACC, SU3_C12_F32 = 0, 1, 2, 3
 SU3_LAYOUT_AOS, SU3_LAYOUT_SOA, SU3_LAYOUT_AOSOA, SU3_LAYOUT_VNODE = 0, 1, 2, 3
-SU3_KIND_MATRIX, SU3_KIND_SPINOR = 0, 1
+SU3_KIND_MATRIX, SU3_KIND_SPINOR, SU3_KIND_REAL, SU3_KIND_COMPLEX = 0, 1, 2, 3
 SU3_EXPR_MUL, SU3_EXPR_MUL3, SU3_EXPR_MULADD, SU3_EXPR_ADD, SU3_EXPR_APB_AB = range(5)
 SU3_EXPR_CSHIFT, SU3_EXPR_MUL_SHIFTED = 5, 6  # launch-tuning keys only
 SU3_EXPR_DSLASH = 7  # launch-tuning key of su3_dslash (precision = links')
+SU3_EXPR_PROGRAM = 8  # launch-tuning key of su3_program_eval (arithmetic precision)
 N_OPERANDS = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}
 
 # exported symbols of su3.h, in declaration order
@@ -48,7 +49,9 @@ SYMBOLS = (
     "su3_field_download_raw", "su3_mult", "su3_fused_eval", "su3_cshift",
     "su3_mult_shifted", "su3_spinor_bytes", "su3_spinor_alloc",
     "su3_spinor_wrap", "su3_dslash", "su3_vnode_bytes", "su3_vnode_alloc",
-    "su3_vnode_wrap",
+    "su3_scalar_bytes", "su3_scalar_alloc", "su3_scalar_wrap",
+    "su3_program_create", "su3_program_info", "su3_program_eval",
+    "su3_program_destroy", "su3_vnode_wrap",
     "su3_batch_create", "su3_batch_launch", "su3_batch_destroy",
     "su3_batch_tiles", "su3_autotune", "su3_batch_autotune", "su3_launch_get",
     "su3_launch_set",
@@ -123,6 +126,14 @@ def load():
         "su3_spinor_alloc": [pp, dims_t, i32, i32, i32],
         "su3_spinor_wrap": [pp, vp, sz, dims_t, i32, i32, i32],
         "su3_dslash": [vp, vp, vp, vp],
+        "su3_scalar_bytes": [dims_t, i32, i32, i32, i32, ctypes.POINTER(sz)],
+        "su3_scalar_alloc": [pp, dims_t, i32, i32, i32, i32],
+        "su3_scalar_wrap": [pp, vp, sz, dims_t, i32, i32, i32, i32],
+        "su3_program_create": [pp, ctypes.c_char_p, i32, vp],
+        "su3_program_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                             ctypes.POINTER(i32)],
+        "su3_program_eval": [vp, vp, vp, i32, vp],
+        "su3_program_destroy": [vp],
         "su3_vnode_bytes": [dims_t, i32, i32, dims_t, ctypes.POINTER(sz)],
         "su3_vnode_alloc": [pp, dims_t, i32, i32, dims_t],
         "su3_vnode_wrap": [pp, vp, sz, dims_t, i32, i32, dims_t],
@@ -202,6 +213,12 @@ class Field:
     owner: object = None  # torch tensor for wrapped fields
     spinor: bool = False
     simd: tuple = None    # virtual nodes per direction (VNODE layout)
+    kind: int = None      # su3_kind (matrix unless set)
+
+    def __post_init__(self):
+        if self.kind is None:
+            self.kind = SU3_KIND_SPINOR if self.spinor else SU3_KIND_MATRIX
+        self.spinor = self.kind == SU3_KIND_SPINOR
 
     @property
     def V(self):
@@ -209,8 +226,9 @@ class Field:
 
     @property
     def site_shape(self):
-        """Canonical host shape of one site: (3, 3, 2) or (4, 3, 2)."""
-        return (4, 3, 2) if self.spinor else (3, 3, 2)
+        """Canonical host shape of one site."""
+        return {SU3_KIND_MATRIX: (3, 3, 2), SU3_KIND_SPINOR: (4, 3, 2),
+                SU3_KIND_REAL: (), SU3_KIND_COMPLEX: (2,)}[self.kind]
 
     def __del__(self):
         if self.handle and _lib is not None:
@@ -368,6 +386,96 @@ def su3_dslash(out: Field, links, inp: Field, stream=None):
                              _stream(stream)))
 
 
+# ------------------------------------------------------- scalar fields
+
+def su3_scalar_bytes(dims, prec, layout, lanes, kind):
+    n = ctypes.c_size_t()
+    _check("su3_scalar_bytes",
+           load().su3_scalar_bytes(_dims(dims), prec, layout, lanes, kind, ctypes.byref(n)))
+    return n.value
+
+
+def su3_scalar_alloc(dims, prec, layout, lanes, kind):
+    h = ctypes.c_void_p()
+    _check("su3_scalar_alloc",
+           load().su3_scalar_alloc(ctypes.byref(h), _dims(dims), prec, layout, lanes, kind))
+    return Field(h.value, tuple(dims), prec, layout, lanes, kind=kind)
+
+
+def su3_scalar_wrap(tensor_or_ptr, dims, prec, layout, lanes, kind, nbytes=None):
+    """Describe device memory as a real or complex scalar field."""
+    if isinstance(tensor_or_ptr, torch.Tensor):
+        t = tensor_or_ptr
+        ptr = t.data_ptr()
+        nbytes = t.numel() * t.element_size() if nbytes is None else nbytes
+        owner = t
+    else:
+        ptr, owner = int(tensor_or_ptr), None
+        if nbytes is None:
+            raise ValueError("nbytes is required with a raw pointer")
+    h = ctypes.c_void_p()
+    _check("su3_scalar_wrap",
+           load().su3_scalar_wrap(ctypes.byref(h), ptr, nbytes, _dims(dims), prec, layout,
+                                  lanes, kind))
+    return Field(h.value, tuple(dims), prec, layout, lanes, owner, kind=kind)
+
+
+def scalar_tensor(dims, prec, layout, kind, lanes=0, device="cuda"):
+    """A torch byte tensor sized for a scalar field, wrapped."""
+    n = su3_scalar_bytes(dims, prec, layout, lanes, kind)
+    t = torch.zeros(n, dtype=torch.uint8, device=device)
+    return su3_scalar_wrap(t, dims, prec, layout, lanes, kind)
+
+
+# ---------------------------------------------------- expression programs
+
+class Program:
+    """A compiled site-local expression (su3_program_create)."""
+
+    def __init__(self, expr, kinds):
+        arr = (ctypes.c_int32 * max(1, len(kinds)))(*[int(k) for k in kinds])
+        h = ctypes.c_void_p()
+        _check("su3_program_create",
+               load().su3_program_create(ctypes.byref(h), expr.encode(), len(kinds),
+                                         ctypes.cast(arr, ctypes.c_void_p)))
+        self.handle = h.value
+        self.expr = expr
+        self.kinds = tuple(kinds)
+
+    def info(self):
+        k, n, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("su3_program_info", load().su3_program_info(self.handle, ctypes.byref(k),
+                                                             ctypes.byref(n), ctypes.byref(r)))
+        return {"result_kind": k.value, "n_instr": n.value, "n_regs": r.value}
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.su3_program_destroy(self.handle)
+            self.handle = None
+
+
+def su3_program_create(expr, kinds):
+    return Program(expr, kinds)
+
+
+def su3_program_info(p: Program):
+    return p.info()
+
+
+def su3_program_eval(p: Program, z: Field, ops, stream=None):
+    arr = (ctypes.c_void_p * max(1, len(ops)))(*[o.handle if o is not None else None
+                                                 for o in ops])
+    _check("su3_program_eval",
+           load().su3_program_eval(p.handle, z.handle if z is not None else None, arr,
+                                   len(ops), _stream(stream)))
+
+
+def su3_program_destroy(p: Program):
+    if p.handle:
+        _check("su3_program_destroy", load().su3_program_destroy(p.handle))
+        p.handle = None
+
+
 # ------------------------------------------------- virtual-node layout
 
 def su3_vnode_bytes(dims, prec, kind, simd):
@@ -382,7 +490,7 @@ def su3_vnode_alloc(dims, prec, kind, simd):
     _check("su3_vnode_alloc",
            load().su3_vnode_alloc(ctypes.byref(h), _dims(dims), prec, kind, _dims(simd)))
     return Field(h.value, tuple(dims), prec, SU3_LAYOUT_VNODE, volume(simd),
-                 spinor=kind == SU3_KIND_SPINOR, simd=tuple(simd))
+                 simd=tuple(simd), kind=kind)
 
 
 def su3_vnode_wrap(tensor_or_ptr, dims, prec, kind, simd, nbytes=None):
@@ -401,7 +509,7 @@ def su3_vnode_wrap(tensor_or_ptr, dims, prec, kind, simd, nbytes=None):
            load().su3_vnode_wrap(ctypes.byref(h), ptr, nbytes, _dims(dims), prec, kind,
                                  _dims(simd)))
     return Field(h.value, tuple(dims), prec, SU3_LAYOUT_VNODE, volume(simd), owner,
-                 spinor=kind == SU3_KIND_SPINOR, simd=tuple(simd))
+                 simd=tuple(simd), kind=kind)
 
 
 def vnode_tensor(dims, prec, simd, kind=SU3_KIND_MATRIX, device="cuda"):

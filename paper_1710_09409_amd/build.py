@@ -2,7 +2,8 @@
 
 The kernel unit su3_kprec.hip is compiled once per storage precision
 (-DSU3_PREC=0..3) in parallel, then linked with the batch/yardstick unit,
-the Wilson hopping unit and the host C-ABI unit.  Always recompiles.
+the Wilson hopping unit, the expression-program unit, the host expression
+compiler and the host C-ABI unit.  Always recompiles.
 """
 from __future__ import annotations
 
@@ -38,6 +39,10 @@ def _units():
                   os.path.join(OBJ, "su3_kmisc.o")))
     units.append((["-x", "hip", os.path.join(CSRC, "su3_kdslash.hip")],
                   os.path.join(OBJ, "su3_kdslash.o")))
+    units.append((["-x", "hip", os.path.join(CSRC, "su3_kprog.hip")],
+                  os.path.join(OBJ, "su3_kprog.o")))
+    units.append((["-x", "hip", os.path.join(CSRC, "su3_program.cpp")],
+                  os.path.join(OBJ, "su3_program.o")))
     units.append((["-x", "hip", os.path.join(CSRC, "su3_api.cpp")],
                   os.path.join(OBJ, "su3_api.o")))
     return units

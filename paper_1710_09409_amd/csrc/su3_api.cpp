@@ -35,12 +35,13 @@ struct su3_field {
     int32_t rbytes;
     int32_t owns;
     int32_t device;
-    int32_t kind;   // 0: SU(3) matrices, 1: spinors
-    int32_t canon;  // complex entries per site on the host (9 or 12)
+    int32_t kind;   // su3_kind
+    int32_t canon;  // entries per site on the host (9, 12 or 1)
+    int32_t ncomp;  // reals per entry (2 complex, 1 real)
     int32_t simd[4];  // virtual nodes per direction (all 1 unless VNODE)
 };
 
-enum { KIND_MATRIX = 0, KIND_SPINOR = 1 };
+enum { KIND_MATRIX = 0, KIND_SPINOR = 1, KIND_REAL = 2, KIND_COMPLEX = 3 };
 static const int kSpinorEntries = 12;
 
 struct su3_batch {
@@ -86,7 +87,7 @@ static su3_status hip_fail(hipError_t e, const char *what)
 
 struct Shape {
     int64_t V, Vpad, L;
-    int32_t E, rbytes;
+    int32_t E, ncomp, rbytes;
     size_t bytes;
 };
 
@@ -99,11 +100,11 @@ static su3_status make_shape(const int32_t dims[4], int prec, int layout,
         return fail(SU3_ERR_INVALID_ARG, "dims is NULL");
     if (prec < SU3_F64 || prec > SU3_C12_F32)
         return fail(SU3_ERR_INVALID_ARG, "unknown precision %d", prec);
-    if (kind != KIND_MATRIX && kind != KIND_SPINOR)
+    if (kind < KIND_MATRIX || kind > KIND_COMPLEX)
         return fail(SU3_ERR_INVALID_ARG, "unknown field kind %d", kind);
-    if (kind == KIND_SPINOR && prec != SU3_F64 && prec != SU3_F32)
+    if (kind != KIND_MATRIX && prec != SU3_F64 && prec != SU3_F32)
         return fail(SU3_ERR_UNSUPPORTED,
-                    "spinor fields are stored in SU3_F64 or SU3_F32");
+                    "spinor and scalar fields are stored in SU3_F64 or SU3_F32");
     if (layout < SU3_LAYOUT_AOS || layout > SU3_LAYOUT_VNODE)
         return fail(SU3_ERR_INVALID_ARG, "unknown layout %d", layout);
     if (layout == SU3_LAYOUT_VNODE && !simd)
@@ -121,7 +122,10 @@ static su3_status make_shape(const int32_t dims[4], int prec, int layout,
     }
     Shape s;
     s.V = V;
-    s.E = kind == KIND_SPINOR ? kSpinorEntries : entries_of(prec);
+    s.E = kind == KIND_SPINOR ? kSpinorEntries
+          : kind == KIND_MATRIX ? entries_of(prec)
+                                : 1;
+    s.ncomp = kind == KIND_REAL ? 1 : 2;
     s.rbytes = real_bytes(prec);
     if (layout == SU3_LAYOUT_AOS) {
         s.L = 1;
@@ -151,7 +155,7 @@ static su3_status make_shape(const int32_t dims[4], int prec, int layout,
         s.L = lanes;
         s.Vpad = (V + lanes - 1) / lanes * lanes;
     }
-    const int64_t reals = s.Vpad * s.E * 2;
+    const int64_t reals = s.Vpad * s.E * s.ncomp;
     if (reals >= ((int64_t)1 << 31))
         return fail(SU3_ERR_INVALID_ARG,
                     "field holds %lld reals; the limit is 2^31 - 1",
@@ -210,7 +214,7 @@ static Geom geom_of(const su3_field *f)
 static inline int64_t stored_index(const su3_field *f, int64_t s, int e, int c)
 {
     s = storage_site(f, s);
-    return ((s / f->L) * f->E + e) * 2 * f->L + (s % f->L) * 2 + c;
+    return ((s / f->L) * f->E + e) * f->ncomp * f->L + (s % f->L) * f->ncomp + c;
 }
 
 // ------------------------------------------------------------ fields
@@ -263,7 +267,8 @@ static su3_field *new_handle(const int32_t dims[4], int prec, int layout,
     f->owns = 0;
     f->device = -1;
     f->kind = kind;
-    f->canon = kind == KIND_SPINOR ? kSpinorEntries : 9;
+    f->canon = kind == KIND_SPINOR ? kSpinorEntries : kind == KIND_MATRIX ? 9 : 1;
+    f->ncomp = s.ncomp;
     for (int d = 0; d < 4; ++d)
         f->simd[d] = simd ? simd[d] : 1;
     return f;
@@ -373,6 +378,46 @@ extern "C" su3_status su3_spinor_wrap(su3_field **out, void *dev_ptr,
 {
     return wrap_of_kind(out, dev_ptr, bytes, dims, prec, layout, lanes,
                         KIND_SPINOR);
+}
+
+// ---------------------------------------------------- scalar fields
+
+static su3_status check_scalar_kind(int kind)
+{
+    if (kind != KIND_REAL && kind != KIND_COMPLEX)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "scalar fields are SU3_KIND_REAL or SU3_KIND_COMPLEX");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_scalar_bytes(const int32_t dims[4],
+                                       su3_precision prec, su3_layout layout,
+                                       int32_t lanes, su3_kind kind,
+                                       size_t *bytes)
+{
+    su3_status st = check_scalar_kind(kind);
+    return st != SU3_OK ? st
+                        : bytes_of_kind(dims, prec, layout, lanes, bytes, kind);
+}
+
+extern "C" su3_status su3_scalar_alloc(su3_field **out, const int32_t dims[4],
+                                       su3_precision prec, su3_layout layout,
+                                       int32_t lanes, su3_kind kind)
+{
+    su3_status st = check_scalar_kind(kind);
+    return st != SU3_OK ? st
+                        : alloc_of_kind(out, dims, prec, layout, lanes, kind);
+}
+
+extern "C" su3_status su3_scalar_wrap(su3_field **out, void *dev_ptr,
+                                      size_t bytes, const int32_t dims[4],
+                                      su3_precision prec, su3_layout layout,
+                                      int32_t lanes, su3_kind kind)
+{
+    su3_status st = check_scalar_kind(kind);
+    return st != SU3_OK ? st
+                        : wrap_of_kind(out, dev_ptr, bytes, dims, prec, layout,
+                                       lanes, kind);
 }
 
 // --------------------------------------------- virtual-node fields
@@ -488,9 +533,9 @@ extern "C" su3_status su3_field_upload(su3_field *f, const double *host,
     std::vector<unsigned char> img(f->bytes, 0);
     for (int64_t s = 0; s < f->V; ++s)
         for (int e = 0; e < f->E; ++e)
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < f->ncomp; ++c)
                 put_real(img.data(), f->prec, stored_index(f, s, e, c),
-                         host[2 * f->canon * s + 2 * e + c]);
+                         host[f->ncomp * (f->canon * s + e) + c]);
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(f->ptr, img.data(), f->bytes,
                            hipMemcpyHostToDevice, st),
@@ -524,11 +569,11 @@ extern "C" su3_status su3_field_download(const su3_field *f, double *host,
     if (st != SU3_OK)
         return st;
     for (int64_t s = 0; s < f->V; ++s) {
-        double *m = host + 2 * f->canon * s;
+        double *m = host + f->ncomp * f->canon * s;
         for (int e = 0; e < f->E; ++e)
-            for (int c = 0; c < 2; ++c)
-                m[2 * e + c] = get_real(img.data(), f->prec,
-                                        stored_index(f, s, e, c));
+            for (int c = 0; c < f->ncomp; ++c)
+                m[f->ncomp * e + c] = get_real(img.data(), f->prec,
+                                               stored_index(f, s, e, c));
         if (f->kind == KIND_MATRIX && f->prec == SU3_C12_F32) {
             // row 2 = conj(row0 x row1), in double
             for (int k = 0; k < 3; ++k) {
@@ -619,6 +664,11 @@ static su3_launch default_launch(int expr, int prec, int layout)
     c.tile_sites = 4096;
     c.occupancy = layout == SU3_LAYOUT_AOS ? 0 : 5;
     c.schedule = layout == SU3_LAYOUT_AOS ? 0 : 1;
+    if (expr == SU3_EXPR_PROGRAM) {
+        c.block = 128;
+        c.occupancy = 0;
+        c.schedule = 0;
+    }
     if (expr == SU3_EXPR_DSLASH) {
         // neighbours re-read each spinor eight times: keep loads cached;
         // each lane walks 8 t-slices
@@ -1081,6 +1131,170 @@ extern "C" su3_status su3_dslash(su3_field *out, su3_field *const links[4],
     return launch_dslash_op(out, links, in, stream);
 }
 
+// ------------------------------------------------ expression programs
+
+struct su3_program {
+    ProgCode code;
+    int32_t kinds[kProgMaxOps];
+};
+
+static const char *kind_name(int k)
+{
+    switch (k) {
+    case KIND_MATRIX: return "matrix";
+    case KIND_SPINOR: return "spinor";
+    case KIND_REAL: return "real";
+    case KIND_COMPLEX: return "complex";
+    }
+    return "unknown";
+}
+
+extern "C" su3_status su3_program_create(su3_program **out, const char *expr,
+                                         int32_t n_ops, const su3_kind *kinds)
+{
+    if (!out || !expr)
+        return fail(SU3_ERR_INVALID_ARG, "out or expression is NULL");
+    if (n_ops < 0 || n_ops > kProgMaxOps)
+        return fail(SU3_ERR_INVALID_ARG, "n_ops %d not in [0, %d]", n_ops,
+                    kProgMaxOps);
+    if (n_ops > 0 && !kinds)
+        return fail(SU3_ERR_INVALID_ARG, "kinds is NULL");
+    int k32[kProgMaxOps] = {0};
+    for (int k = 0; k < n_ops; ++k) {
+        if (kinds[k] < KIND_MATRIX || kinds[k] > KIND_COMPLEX)
+            return fail(SU3_ERR_INVALID_ARG, "unknown kind %d of operand %d",
+                        (int)kinds[k], k);
+        if (kinds[k] == KIND_SPINOR)
+            return fail(SU3_ERR_UNSUPPORTED,
+                        "expressions take matrix, real and complex fields");
+        k32[k] = kinds[k];
+    }
+    su3_program *p = new su3_program();
+    char err[256];
+    if (!compile_program(expr, n_ops, k32, &p->code, err, sizeof err)) {
+        delete p;
+        return fail(SU3_ERR_INVALID_ARG, "expression \"%s\": %s", expr, err);
+    }
+    for (int k = 0; k < kProgMaxOps; ++k)
+        p->kinds[k] = k < n_ops ? k32[k] : -1;
+    *out = p;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_program_info(const su3_program *p,
+                                       su3_kind *result_kind,
+                                       int32_t *n_instr, int32_t *n_regs)
+{
+    if (!p)
+        return fail(SU3_ERR_INVALID_ARG, "program is NULL");
+    if (result_kind)
+        *result_kind = (su3_kind)p->code.result_kind;
+    if (n_instr)
+        *n_instr = p->code.ninstr;
+    if (n_regs)
+        *n_regs = p->code.nregs;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_program_destroy(su3_program *p)
+{
+    delete p;
+    return SU3_OK;
+}
+
+static su3_status launch_program_op(const su3_program *p, su3_field *z,
+                                    const su3_field *const *ops, int arith,
+                                    hipStream_t st,
+                                    const su3_launch *forced = nullptr)
+{
+    const su3_launch c =
+        forced ? *forced
+               : lookup_launch(SU3_EXPR_PROGRAM, arith, z->layout, z->lanes,
+                               z->V);
+    ProgArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.z = z->ptr;
+    a.gz = geom_of(z);
+    a.zkind = (uint8_t)z->kind;
+    a.zprec = (uint8_t)z->prec;
+    for (int k = 0; k < p->code.nops; ++k) {
+        a.op[k] = ops[k]->ptr;
+        a.g[k] = geom_of(ops[k]);
+        a.kind[k] = (uint8_t)ops[k]->kind;
+        a.prec[k] = (uint8_t)ops[k]->prec;
+    }
+    a.nops = (uint8_t)p->code.nops;
+    a.ninstr = (uint8_t)p->code.ninstr;
+    a.result = (uint8_t)p->code.result;
+    a.used = (uint8_t)p->code.used;
+    a.nsites = (int32_t)z->V;
+    for (int t = 0; t < p->code.ninstr; ++t)
+        a.ins[t] = p->code.ins[t];
+    for (int k = 0; k < p->code.nimm; ++k) {
+        a.imm[k][0] = p->code.imm[k][0];
+        a.imm[k][1] = p->code.imm[k][1];
+    }
+    const int64_t grid = (z->V + c.block - 1) / c.block;
+    hipError_t e = launch_program(arith, p->code.nregs, c.nontemporal, c.block,
+                                  (int)grid,
+                                  occupancy_reserve(z->device, c.occupancy), a,
+                                  st);
+    if (e != hipSuccess)
+        return hip_fail(e, "program kernel launch");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_program_eval(const su3_program *p, su3_field *z,
+                                       const su3_field *const *ops,
+                                       int32_t n_ops, void *stream)
+{
+    if (!p || !z)
+        return fail(SU3_ERR_INVALID_ARG, "program or output is NULL");
+    if (n_ops != p->code.nops)
+        return fail(SU3_ERR_INVALID_ARG, "the program takes %d operands, got %d",
+                    p->code.nops, n_ops);
+    if (n_ops > 0 && !ops)
+        return fail(SU3_ERR_INVALID_ARG, "operand list is NULL");
+    if (z->kind != p->code.result_kind)
+        return fail(SU3_ERR_MISMATCH,
+                    "the expression is %s-valued, the output a %s field",
+                    kind_name(p->code.result_kind), kind_name(z->kind));
+    if (z->prec == SU3_F16_F32ACC)
+        return fail(SU3_ERR_UNSUPPORTED, "expressions take F64, F32 or C12 fields");
+    const int arith = z->prec == SU3_F64 ? SU3_F64 : SU3_F32;
+    for (int k = 0; k < n_ops; ++k) {
+        const su3_field *o = ops[k];
+        if (!o)
+            return fail(SU3_ERR_INVALID_ARG, "operand %d is NULL", k);
+        if (o->kind != p->kinds[k])
+            return fail(SU3_ERR_MISMATCH,
+                        "operand %d is a %s field, the program declared %s", k,
+                        kind_name(o->kind), kind_name(p->kinds[k]));
+        if (!same_geometry(o, z))
+            return fail(SU3_ERR_MISMATCH,
+                        "operand %d differs from the output in dims, layout, "
+                        "lanes, virtual nodes or device", k);
+        if (o->prec == SU3_F16_F32ACC)
+            return fail(SU3_ERR_UNSUPPORTED,
+                        "expressions take F64, F32 or C12 fields");
+        if ((o->prec == SU3_F64) != (arith == SU3_F64))
+            return fail(SU3_ERR_MISMATCH,
+                        "operand %d: an expression is evaluated in one precision "
+                        "(all fields F64, or all F32/C12)", k);
+        if (overlaps(z, o) && !(z->ptr == o->ptr && z->bytes == o->bytes))
+            return fail(SU3_ERR_ALIAS, "output partially overlaps operand %d", k);
+    }
+    if (z->prec == SU3_C12_F32 && !p->code.su3_closed)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "a compressed output needs an SU(3)-valued expression "
+                    "(products, adjoints, transposes, conjugates of matrices)");
+    if (arith == SU3_F64 && p->code.nregs > 4)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "the expression needs %d registers; double precision "
+                    "evaluates with at most 4", p->code.nregs);
+    return launch_program_op(p, z, ops, arith, static_cast<hipStream_t>(stream));
+}
+
 // ------------------------------------------------------- launch tuning
 
 // The virtual-node split a tuning key of N_sub = lanes stands for: factors
@@ -1113,8 +1327,11 @@ static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
                          int32_t lanes, const int32_t dims[4], Key *k,
                          Shape *shape)
 {
-    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_DSLASH)
+    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_PROGRAM)
         return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
+    if (expr == SU3_EXPR_PROGRAM && prec != SU3_F64 && prec != SU3_F32)
+        return fail(SU3_ERR_UNSUPPORTED,
+                    "expression programs evaluate in F64 or F32");
     if (expr == SU3_EXPR_DSLASH && prec == SU3_F16_F32ACC)
         return fail(SU3_ERR_UNSUPPORTED,
                     "Dslash links are stored in F64, F32 or C12");
@@ -1258,6 +1475,23 @@ static std::vector<su3_launch> dslash_candidates()
     return out;
 }
 
+// Candidates for the program kernel: one site per lane, one-shot grid;
+// block, occupancy cap, nontemporal bits.
+static std::vector<su3_launch> program_candidates()
+{
+    std::vector<su3_launch> out;
+    su3_launch c = default_launch(SU3_EXPR_PROGRAM, SU3_F64, SU3_LAYOUT_SOA);
+    for (int b : {64, 128, 256})
+        for (int occ : {0, 2, 3, 4, 6, 8})
+            for (int nt : {0, 2, 3}) {
+                c.block = b;
+                c.occupancy = occ;
+                c.nontemporal = nt;
+                out.push_back(c);
+            }
+    return out;
+}
+
 // Median time (microseconds) of `reps` launches after `warm` warm-ups, each
 // launch bracketed by its own events.
 template <class F>
@@ -1336,11 +1570,20 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     }
     su3_launch win = default_launch(expr, prec, layout);
     double win_us = 1e300;
+    // expression programs are timed on the streaming product a*b
+    su3_program prog;
+    if (st == SU3_OK && expr == SU3_EXPR_PROGRAM) {
+        const int kinds[2] = {KIND_MATRIX, KIND_MATRIX};
+        char err[128];
+        if (!compile_program("a*b", 2, kinds, &prog.code, err, sizeof err))
+            st = fail(SU3_ERR_HIP, "internal program: %s", err);
+    }
     if (st == SU3_OK) {
         const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
         su3_field *links[4] = {f[2], f[3], f[4], f[5]};
         for (const su3_launch &c : dslash ? dslash_candidates()
-                                          : candidates(layout)) {
+                                   : expr == SU3_EXPR_PROGRAM ? program_candidates()
+                                                              : candidates(layout)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)
                 continue;  // a copy has no row phases
             double us = 0;
@@ -1348,6 +1591,8 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
                 [&]() {
                     if (dslash)
                         return launch_dslash_op(f[0], links, f[1], stream, &c);
+                    if (expr == SU3_EXPR_PROGRAM)
+                        return launch_program_op(&prog, f[0], ops, prec, hs, &c);
                     if (expr == SU3_EXPR_CSHIFT)
                         return launch_shift_op(0, f[0], nullptr, f[1], 1, 1,
                                                stream, &c);

@@ -4,8 +4,8 @@
 // launch settings (which must agree), persistent grids, LDS staging, the
 // batch (tile rows, replays, autotuner), the shifted operands and the
 // Wilson hopping term (every precision pair and layout, two launch
-// settings, argument validation), and Grid's virtual-node layout (stored
-// image, products, shifts, Dslash).  Any
+// settings, argument validation), Grid's virtual-node layout (stored
+// image, products, shifts, Dslash) and expression programs.  Any
 // out-of-bounds access in a kernel's indexing aborts the run.  Prints
 // "fails 0" on success.
 #include "su3.h"
@@ -23,6 +23,7 @@ void oracle_mult(const double *x, const double *y, double *z, int64_t V);
 int oracle_dslash(const double *const *u, const double *in, double *out, const int32_t dims[4]);
 void su3gen_spinor(uint64_t seed, uint64_t field_id, int64_t s_begin, int64_t count, double *out);
 int oracle_vnode_pack(const double *canon, const int32_t dims[4], const int32_t simd[4], int prec, int entries, int canon_entries, void *out);
+int oracle_eval_expr(const char *text, int nops, const int *kinds, const double *const *fields, double *out, int64_t V);
 }
 static int nops_of(int e) { return e == 1 ? 3 : (e == 2 ? 4 : 2); }
 static int fails = 0;
@@ -394,6 +395,129 @@ int main(int argc, char **argv)
         if (su3_vnode_bytes(d, SU3_F16_F32ACC, SU3_KIND_SPINOR, s1, &nb) != SU3_ERR_UNSUPPORTED) { printf("f16 vnode spinor accepted\n"); fails++; }
         su3_field_free(a); su3_field_free(b); su3_field_free(z);
         printf("vnode cases done\n");
+    }
+    // expression programs
+    {
+        struct Ex { const char *text; int n; int kinds[4]; };
+        Ex exs[] = {{"a+b+a*b", 2, {2, 2}}, {"1.0", 0, {}}, {"a*b", 2, {0, 0}},
+                    {"trace(a*adj(b)) * c + d", 4, {0, 0, 3, 3}}, {"2*i*a - b*c", 3, {0, 0, 3}},
+                    {"(a*b)*(c*d) + a - d", 4, {0, 0, 0, 0}}, {"real(trace(a)) * b + c", 3, {0, 0, 2}},
+                    {"adj(a)*transpose(b) - conj(a)", 2, {0, 0}}, {"a", 1, {3}},
+                    {"((a*b)*(c*d))*((a*c)*(b*d))", 4, {0, 0, 0, 0}}};
+        int dims_list[][4] = {{3, 5, 7, 11}, {4, 4, 4, 4}};
+        int lays[][2] = {{0, 0}, {1, 0}, {2, 16}, {3, 0}};
+        int simd[4] = {2, 1, 1, 2};
+        for (auto &d : dims_list)
+            for (auto &l : lays) {
+                if (l[0] == 3 && d[0] % 2) continue;  // virtual nodes need even x, t
+                int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
+                for (int arith : {0, 1, 3}) {  // F64; F32; F32 with compressed matrices
+                    for (auto &ex : exs) {
+                        std::vector<std::vector<double>> host(4), q(4);
+                        std::vector<su3_field *> fs(4, nullptr);
+                        const double *qp[4] = {nullptr, nullptr, nullptr, nullptr};
+                        bool ok = true;
+                        for (int k = 0; k < ex.n; ++k) {
+                            const int kind = ex.kinds[k];
+                            const int prec = kind == 0 ? arith : (arith == 0 ? 0 : 1);
+                            const int64_t per = kind == 0 ? 18 : (kind == 3 ? 2 : 1);
+                            host[k].resize(per * V);
+                            q[k].resize(per * V);
+                            if (kind == 0) {
+                                su3gen_field(13, 50 + k, 0, V, host[k].data());
+                                oracle_roundtrip(prec, host[k].data(), q[k].data(), V);
+                            } else {
+                                std::vector<double> tmp(18 * V);
+                                su3gen_field(13, 60 + k, 0, V, tmp.data());
+                                for (int64_t i = 0; i < per * V; ++i) {
+                                    host[k][i] = tmp[i] * 3.0;
+                                    q[k][i] = prec == 0 ? host[k][i] : (double)(float)host[k][i];
+                                }
+                            }
+                            qp[k] = q[k].data();
+                            su3_status st;
+                            if (l[0] == 3)
+                                st = su3_vnode_alloc(&fs[k], d, (su3_precision)prec, (su3_kind)kind, simd);
+                            else if (kind == 0)
+                                st = su3_field_alloc(&fs[k], d, (su3_precision)prec, (su3_layout)l[0], l[1]);
+                            else
+                                st = su3_scalar_alloc(&fs[k], d, (su3_precision)prec, (su3_layout)l[0], l[1], (su3_kind)kind);
+                            if (st != SU3_OK) { printf("program operand alloc %s\n", su3_last_error()); fails++; ok = false; break; }
+                            su3_field_upload(fs[k], host[k].data(), nullptr);
+                        }
+                        if (!ok) continue;
+                        su3_program *p;
+                        su3_kind kinds[4];
+                        for (int k = 0; k < 4; ++k) kinds[k] = (su3_kind)ex.kinds[k];
+                        if (su3_program_create(&p, ex.text, ex.n, kinds) != SU3_OK) { printf("program %s: %s\n", ex.text, su3_last_error()); fails++; continue; }
+                        su3_kind rk; int32_t ni, nr;
+                        su3_program_info(p, &rk, &ni, &nr);
+                        const int zprec = rk == SU3_KIND_MATRIX ? (arith == 3 ? 1 : arith) : (arith == 0 ? 0 : 1);
+                        su3_field *z;
+                        if (l[0] == 3)
+                            su3_vnode_alloc(&z, d, (su3_precision)zprec, rk, simd);
+                        else if (rk == SU3_KIND_MATRIX)
+                            su3_field_alloc(&z, d, (su3_precision)zprec, (su3_layout)l[0], l[1]);
+                        else
+                            su3_scalar_alloc(&z, d, (su3_precision)zprec, (su3_layout)l[0], l[1], rk);
+                        const int64_t per = rk == SU3_KIND_MATRIX ? 18 : (rk == SU3_KIND_COMPLEX ? 2 : 1);
+                        std::vector<double> want(18 * V), got(per * V);
+                        int okinds[4];
+                        for (int k = 0; k < 4; ++k) okinds[k] = ex.kinds[k];
+                        const int ork = oracle_eval_expr(ex.text, ex.n, okinds, qp, want.data(), V);
+                        if (ork != (int)rk) { printf("program %s: oracle kind %d vs %d\n", ex.text, ork, (int)rk); fails++; }
+                        su3_status st = su3_program_eval(p, z, fs.data(), ex.n, nullptr);
+                        if (arith == 0 && nr > 4) {
+                            if (st != SU3_ERR_UNSUPPORTED) { printf("program %s: 5+ double registers accepted\n", ex.text); fails++; }
+                        } else if (st != SU3_OK) {
+                            printf("program eval %s: %s\n", ex.text, su3_last_error()); fails++;
+                        } else {
+                            su3_field_download(z, got.data(), nullptr);
+                            double err = 0, mag = 0;
+                            for (int64_t i = 0; i < per * V; ++i) { err = std::max(err, std::fabs(got[i] - want[i])); mag = std::max(mag, std::fabs(want[i])); }
+                            if (err > (arith == 0 ? 1e-13 : 2e-6) * (1 + mag)) { printf("program %s arith %d layout %d err %.3e\n", ex.text, arith, l[0], err); fails++; }
+                        }
+                        su3_field_free(z);
+                        su3_program_destroy(p);
+                        for (auto *f : fs) su3_field_free(f);
+                    }
+                }
+            }
+        // rules
+        int d[4] = {2, 2, 2, 2};
+        su3_field *m64, *m32, *r64, *c64;
+        su3_field_alloc(&m64, d, SU3_F64, SU3_LAYOUT_SOA, 0);
+        su3_field_alloc(&m32, d, SU3_F32, SU3_LAYOUT_SOA, 0);
+        su3_scalar_alloc(&r64, d, SU3_F64, SU3_LAYOUT_SOA, 0, SU3_KIND_REAL);
+        su3_scalar_alloc(&c64, d, SU3_F64, SU3_LAYOUT_SOA, 0, SU3_KIND_COMPLEX);
+        su3_program *p;
+        su3_kind mm[2] = {SU3_KIND_MATRIX, SU3_KIND_MATRIX};
+        su3_program_create(&p, "a*b", 2, mm);
+        const su3_field *mixed[2] = {m64, m32}, *wrongkind[2] = {m64, r64}, *good[2] = {m64, m64};
+        if (su3_program_eval(p, m64, mixed, 2, nullptr) != SU3_ERR_MISMATCH) { printf("mixed precision accepted\n"); fails++; }
+        if (su3_program_eval(p, m64, wrongkind, 2, nullptr) != SU3_ERR_MISMATCH) { printf("wrong kind accepted\n"); fails++; }
+        if (su3_program_eval(p, c64, good, 2, nullptr) != SU3_ERR_MISMATCH) { printf("wrong result kind accepted\n"); fails++; }
+        if (su3_program_eval(p, m64, good, 1, nullptr) != SU3_ERR_INVALID_ARG) { printf("operand count accepted\n"); fails++; }
+        if (su3_program_eval(p, m64, good, 2, nullptr) != SU3_OK) { printf("in-place program: %s\n", su3_last_error()); fails++; }
+        su3_program_destroy(p);
+        su3_program *q;
+        if (su3_program_create(&q, "a+*b", 2, mm) != SU3_ERR_INVALID_ARG) { printf("syntax error accepted\n"); fails++; }
+        su3_kind sp[1] = {SU3_KIND_SPINOR};
+        if (su3_program_create(&q, "a", 1, sp) != SU3_ERR_UNSUPPORTED) { printf("spinor operand accepted\n"); fails++; }
+        su3_field *c12a, *c12z;
+        su3_field_alloc(&c12a, d, SU3_C12_F32, SU3_LAYOUT_SOA, 0);
+        su3_field_alloc(&c12z, d, SU3_C12_F32, SU3_LAYOUT_SOA, 0);
+        su3_kind m1[1] = {SU3_KIND_MATRIX};
+        su3_program_create(&q, "a + a", 1, m1);
+        const su3_field *one[1] = {c12a};
+        if (su3_program_eval(q, c12z, one, 1, nullptr) != SU3_ERR_UNSUPPORTED) { printf("non-SU(3) compressed output accepted\n"); fails++; }
+        su3_program_destroy(q);
+        su3_program_create(&q, "adj(a)*a", 1, m1);
+        if (su3_program_eval(q, c12z, one, 1, nullptr) != SU3_OK) { printf("SU(3) compressed output refused: %s\n", su3_last_error()); fails++; }
+        su3_program_destroy(q);
+        su3_field_free(m64); su3_field_free(m32); su3_field_free(r64); su3_field_free(c64);
+        su3_field_free(c12a); su3_field_free(c12z);
+        printf("program cases done\n");
     }
     printf("fails %d\n", fails);
     return fails != 0;

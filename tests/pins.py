@@ -566,6 +566,90 @@ def pin_vnode_layout(orc):
                               orc.pack(x, prec, O.AOSOA, 8))
 
 
+def pin_expr_listing2(orc):
+    """Listing 2 on real (double) fields through the expression evaluator:
+    v1 = 1.0, v2 = 2.0 assigned as constants, v3 = v1+v2 and
+    v3 = v1+v2+v1*v2 (exact), and the SU(3)-typed counterparts equal the
+    fixed expressions."""
+    g = read_golden("listing2_composite.txt")
+    V = 12
+    v1 = orc.eval_expr(repr(g["v1"]), [], [], V=V)
+    v2 = orc.eval_expr(repr(g["v2"]), [], [], V=V)
+    assert np.array_equal(v1, np.full(V, g["v1"])) and np.array_equal(v2, np.full(V, g["v2"]))
+    assert np.array_equal(orc.eval_expr("a+b", [v1, v2], [2, 2]), np.full(V, g["real_ADD"]))
+    assert np.array_equal(orc.eval_expr("a+b+a*b", [v1, v2], [2, 2]),
+                          np.full(V, g["real_APB_AB"]))
+    x = testgen.identity(V, g["v1"])
+    y = testgen.identity(V, g["v2"])
+    assert np.array_equal(orc.eval_expr("a+b+a*b", [x, y], [0, 0]),
+                          testgen.identity(V, g["APB_AB"]))
+
+
+def pin_expr_matches_fixed(orc):
+    """Matrix expressions equal the (separately pinned) fixed expressions
+    bit for bit: same association, same textbook sums."""
+    V = 40
+    ops = [testgen.su3_field(V, field_id=40 + k) for k in range(4)]
+    for text, expr in (("a*b", O.MUL), ("a*b*c", O.MUL3), ("a*b+c*d", O.MULADD),
+                       ("a+b", O.ADD), ("a+b+a*b", O.APB_AB)):
+        n = {O.MUL: 2, O.MUL3: 3, O.MULADD: 4, O.ADD: 2, O.APB_AB: 2}[expr]
+        got = orc.eval_expr(text, ops[:n], [0] * n)
+        assert np.array_equal(got, orc.fused(expr, ops[:n])), text
+
+
+def _cx_mat(a):
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def pin_expr_numpy(orc):
+    """Functions, scalar-matrix mixing and complex constants against numpy
+    on random complex inputs (not unitary, so no identity hides an error)."""
+    rng = np.random.default_rng(5)
+    V = 30
+    a = rng.standard_normal((V, 3, 3, 2))
+    b = rng.standard_normal((V, 3, 3, 2))
+    c = rng.standard_normal((V, 2))
+    r = rng.standard_normal(V)
+    A, B, C = _cx_mat(a), _cx_mat(b), c[:, 0] + 1j * c[:, 1]
+    eye = np.eye(3)[None]
+    fields, kinds = [a, b, c, r], [0, 0, 3, 2]
+    cases = [
+        ("adj(a)", np.conj(np.transpose(A, (0, 2, 1)))),
+        ("transpose(a)", np.transpose(A, (0, 2, 1))),
+        ("conj(a)", np.conj(A)),
+        ("trace(a*b)", np.einsum("sij,sji->s", A, B)),
+        ("2*i*a - b", 2j * A - B),
+        ("c*a + b", C[:, None, None] * A + B),
+        ("a - c", A - C[:, None, None] * eye),
+        ("c - a", C[:, None, None] * eye - A),
+        ("d*a*c", (r * C)[:, None, None] * A),
+        ("-a*b", -(A @ B)),
+        ("real(trace(a)) + imag(c)", np.trace(A, axis1=1, axis2=2).real + C.imag),
+        ("a*transpose(b)", A @ np.transpose(B, (0, 2, 1))),
+        ("conj(c)*d", np.conj(C) * r),
+    ]
+    for text, want in cases:
+        got = orc.eval_expr(text, fields, kinds)
+        if got.ndim == 4:
+            got = _cx_mat(got)
+        elif got.ndim == 2:
+            got = got[:, 0] + 1j * got[:, 1]
+        assert got.shape == want.shape, text
+        assert np.max(np.abs(got - want)) <= 1e-13 * (1 + np.max(np.abs(want))), text
+
+
+def pin_expr_rejects(orc):
+    """Malformed and ill-typed expressions are refused."""
+    V = 4
+    x = testgen.su3_field(V)
+    for bad in ("a+", "a*(b", "x", "real(a)", "b", "adj a", "1..2"):
+        try:
+            orc.eval_expr(bad, [x], [0])
+        except ValueError:
+            continue
+        raise AssertionError(f"{bad!r} accepted")
+
+
 ALL_PINS = [pin_identity, pin_phase_diag, pin_signed_permutations,
             pin_unitary_inverse, pin_numpy_matmul, pin_nonsymmetric,
             pin_product_invariants, pin_associative, pin_listing2,
@@ -573,4 +657,5 @@ ALL_PINS = [pin_identity, pin_phase_diag, pin_signed_permutations,
             pin_quantisers, pin_c12_rebuild, pin_layouts, pin_roundtrip,
             pin_metrics, pin_cshift, pin_dslash_free_field,
             pin_dslash_gamma5_hermitian, pin_dslash_gauge_covariant,
-            pin_vnode_layout]
+            pin_vnode_layout, pin_expr_listing2, pin_expr_matches_fixed,
+            pin_expr_numpy, pin_expr_rejects]

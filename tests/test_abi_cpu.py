@@ -25,7 +25,7 @@ def header_functions():
 def test_every_declared_symbol_is_exported():
     lib = su3.load()
     names = header_functions()
-    assert len(names) == 33
+    assert len(names) == 40
     assert set(names) == set(su3.SYMBOLS)
     for n in names:
         assert hasattr(lib, n), n
@@ -74,6 +74,52 @@ def test_spinor_bytes(dims):
     big = (128, 128, 128, 48)
     assert su3.su3_field_bytes(big, 1, 1, 0) > 0
     assert _status(su3.su3_spinor_bytes, big, 1, 1, 0) == su3.SU3_ERR_INVALID_ARG
+
+
+def test_scalar_and_vnode_bytes():
+    """Scalar fields hold one real or complex number per site (padded like
+    the layout); virtual-node fields hold V sites of E entries."""
+    for dims in ((3, 5, 7, 11), (8, 8, 8, 8)):
+        V = int(np.prod(dims))
+        for prec, rb in ((0, 8), (1, 4)):
+            for lay, lanes, pad in ((0, 0, 1), (1, 0, 64), (2, 16, 16)):
+                Vpad = -(-V // pad) * pad
+                assert su3.su3_scalar_bytes(dims, prec, lay, lanes, su3.SU3_KIND_REAL) == Vpad * rb
+                assert su3.su3_scalar_bytes(dims, prec, lay, lanes, su3.SU3_KIND_COMPLEX) == \
+                    2 * Vpad * rb
+        for kind in (su3.SU3_KIND_MATRIX, su3.SU3_KIND_SPINOR):
+            assert _status(su3.su3_scalar_bytes, dims, 0, 1, 0, kind) == su3.SU3_ERR_INVALID_ARG
+        assert _status(su3.su3_scalar_bytes, dims, 2, 1, 0, su3.SU3_KIND_REAL) == \
+            su3.SU3_ERR_UNSUPPORTED
+    d = (4, 6, 8, 10)
+    V = int(np.prod(d))
+    assert su3.su3_vnode_bytes(d, 0, su3.SU3_KIND_MATRIX, (2, 1, 2, 2)) == V * 144
+    assert su3.su3_vnode_bytes(d, 3, su3.SU3_KIND_MATRIX, (2, 1, 2, 2)) == V * 48
+    assert su3.su3_vnode_bytes(d, 1, su3.SU3_KIND_SPINOR, (1, 1, 1, 2)) == V * 96
+    assert su3.su3_vnode_bytes(d, 0, su3.SU3_KIND_REAL, (2, 2, 2, 2)) == V * 8
+    assert _status(su3.su3_vnode_bytes, d, 0, su3.SU3_KIND_MATRIX, (3, 1, 1, 1)) == \
+        su3.SU3_ERR_INVALID_ARG
+    assert _status(su3.su3_field_bytes, d, 0, su3.SU3_LAYOUT_VNODE, 4) == \
+        su3.SU3_ERR_INVALID_ARG
+
+
+def test_program_compiler():
+    """Expressions compile to register programs of the stated kind;
+    malformed, ill-typed and over-long ones are refused.  Pure host."""
+    M, R, C = su3.SU3_KIND_MATRIX, su3.SU3_KIND_REAL, su3.SU3_KIND_COMPLEX
+    for text, kinds, rk in (("a+b+a*b", [R, R], R), ("a*b", [M, M], M),
+                            ("trace(a)", [M], C), ("real(trace(a))", [M], R),
+                            ("1.0", [], R), ("2*i", [], C), ("a*b", [C, M], M),
+                            ("-(a - 1) * adj(b)", [M, M], M)):
+        assert su3.Program(text, kinds).info()["result_kind"] == rk, text
+    info = su3.Program("((a*b)*(c*d))*((e*f)*(g*h))", [M] * 8).info()
+    assert info["n_instr"] == 7 and 4 < info["n_regs"] <= 8
+    for bad, kinds in (("a+", [M]), ("(a", [M]), ("a b", [M, M]), ("z", [M]),
+                       ("b", [M]), ("real(a)", [M]), ("adj(", [M]), ("", [])):
+        assert _status(su3.Program, bad, kinds) == su3.SU3_ERR_INVALID_ARG, bad
+    deep = "a" + "".join(f"*(a+{k}.0)" for k in range(30))
+    assert _status(su3.Program, deep, [M]) == su3.SU3_ERR_INVALID_ARG
+    assert _status(su3.Program, "a", [su3.SU3_KIND_SPINOR]) == su3.SU3_ERR_UNSUPPORTED
 
 
 def _status(fn, *a):
@@ -139,10 +185,19 @@ def test_launch_table():
         su3.SU3_ERR_UNSUPPORTED
     # the shifted operations' and Dslash's tuning keys are accepted,
     # unknown ones not
-    for key in (su3.SU3_EXPR_CSHIFT, su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_EXPR_DSLASH):
+    for key in (su3.SU3_EXPR_CSHIFT, su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_EXPR_DSLASH,
+                su3.SU3_EXPR_PROGRAM):
         su3.su3_launch_set(key, 0, 1, 0, dims, cfg)
         assert su3.su3_launch_get(key, 0, 1, 0, dims).as_dict() == cfg
-    assert _status(su3.su3_launch_set, 8, 0, 1, 0, dims, cfg) == su3.SU3_ERR_INVALID_ARG
+    assert _status(su3.su3_launch_set, 9, 0, 1, 0, dims, cfg) == su3.SU3_ERR_INVALID_ARG
+    # programs evaluate in double or single
+    assert _status(su3.su3_launch_set, su3.SU3_EXPR_PROGRAM, 3, 1, 0, dims, cfg) == \
+        su3.SU3_ERR_UNSUPPORTED
+    # virtual-node keys: N_sub lanes
+    su3.su3_launch_set(0, 0, su3.SU3_LAYOUT_VNODE, 16, dims, cfg)
+    assert su3.su3_launch_get(0, 0, su3.SU3_LAYOUT_VNODE, 16, dims).as_dict() == cfg
+    assert _status(su3.su3_launch_set, 0, 0, su3.SU3_LAYOUT_VNODE, 3, dims, cfg) == \
+        su3.SU3_ERR_INVALID_ARG
     # Dslash links are never half precision
     assert _status(su3.su3_launch_set, su3.SU3_EXPR_DSLASH, 2, 1, 0, dims, cfg) == \
         su3.SU3_ERR_UNSUPPORTED

@@ -23,6 +23,8 @@ def test_kernels_under_asan(tmp_path):
              for p in range(4)]
     units += [(["-x", "c++", os.path.join(CSRC, "su3_kmisc.hip")], "km.o"),
               (["-x", "c++", os.path.join(CSRC, "su3_kdslash.hip")], "kd.o"),
+              (["-x", "c++", os.path.join(CSRC, "su3_kprog.hip")], "kg.o"),
+              ([os.path.join(CSRC, "su3_program.cpp")], "pg.o"),
               ([os.path.join(CSRC, "su3_api.cpp")], "api.o"),
               ([os.path.join(EMU, "emu_globals.cpp")], "g.o"),
               ([os.path.join(EMU, "harness.cpp")], "h.o")]
@@ -37,7 +39,7 @@ def test_kernels_under_asan(tmp_path):
     for p in procs:
         _, err = p.communicate()
         assert p.returncode == 0, err
-    objs = [str(tmp_path / o) for o in ("kp0.o", "kp1.o", "kp2.o", "kp3.o", "km.o", "kd.o", "api.o",
+    objs = [str(tmp_path / o) for o in ("kp0.o", "kp1.o", "kp2.o", "kp3.o", "km.o", "kd.o", "kg.o", "pg.o", "api.o",
                                         "g.o", "h.o", "gen.o", "or.o")]
     subprocess.check_call([CLANG, "-fsanitize=address,undefined"] + objs +
                           ["-o", str(tmp_path / "harness"), "-lm"])
@@ -49,3 +51,4 @@ def test_kernels_under_asan(tmp_path):
     assert "shift cases done" in r.stdout, tail
     assert "dslash cases done" in r.stdout, tail
     assert "vnode cases done" in r.stdout, tail
+    assert "program cases done" in r.stdout, tail

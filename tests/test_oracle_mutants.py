@@ -46,6 +46,17 @@ MUTANTS = [
      "site += (om * simd[mu] + nm) * stride;"),
     ("vnode_lane_order", "            for (int64_t n = 0; n < nsub; ++n) {\n                const int64_t site = vnode_site(dims, r, simd, o, n);\n                for (int c = 0; c < 2; ++c, ++w) {\n                    const double v",
      "            for (int64_t n = 0; n < nsub; ++n) {\n                const int64_t site = vnode_site(dims, r, simd, o, (n % 2) * (nsub / 2) + n / 2);\n                for (int c = 0; c < 2; ++c, ++w) {\n                    const double v"),
+    ("expr_scalar_on_all_entries",
+     "const double av = a.mat ? a.m[t] : (i == j ? a.m[c] : 0.0);",
+     "const double av = a.mat ? a.m[t] : a.m[c];"),
+    ("expr_adj_no_conj", "x->fn == EF_ADJ ? -a.m[2 * (3 * j + i) + 1] : a.m[2 * (3 * j + i) + 1];",
+     "a.m[2 * (3 * j + i) + 1];"),
+    ("expr_trace_index", "v.m[0] = (a.m[0] + a.m[8]) + a.m[16];",
+     "v.m[0] = (a.m[0] + a.m[8]) + a.m[12];"),
+    ("expr_product_order", "const double br = b.m[2 * (3 * q + j)], bi = b.m[2 * (3 * q + j) + 1];",
+     "const double br = b.m[2 * (3 * j + q)], bi = b.m[2 * (3 * j + q) + 1];"),
+    ("expr_sub_sign", "const double sg = x->kind == EN_ADD ? 1.0 : -1.0;",
+     "const double sg = 1.0;"),
     ("det_sign", "r += re_(m, 0, j) * cr - im_(m, 0, j) * ci;",
      "r += re_(m, 0, j) * cr + im_(m, 0, j) * ci;"),
 ]
