@@ -16,7 +16,8 @@ Prints ONE JSON line on stdout (progress goes to stderr):
   variants     the precision forms (F32, F16 with F32 arithmetic, two-row
                compressed F32) at 48^4, the layouts (AoS, AoS+LDS, AoSoA),
                the volume sweep, the shifted operands, the Wilson hopping
-               term at 48^4, fused vs chained expressions at 32^4, the
+               term at 48^4, expression programs at 48^4, fused vs
+               chained expressions at 32^4, the
                64-lattice batch replayed from a HIP graph, and the triad
                ceiling -- each in GB/s of its own algorithmic bytes
 """
@@ -408,6 +409,46 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
             del U, fin, fout
     del host_psi
     out["dslash_48^4"] = dsl
+
+    # expression programs at 48^4 (one precompiled kernel interpreting the
+    # host-compiled expression): Listing 2 on double fields (two real
+    # inputs, one real output: 24 B/site), the streaming product, the
+    # MULADD shape and a trace into a complex field, each against its
+    # algorithmic bytes; the fixed-expression kernels beside them
+    progs = {}
+    M, R, C = su3.SU3_KIND_MATRIX, su3.SU3_KIND_REAL, su3.SU3_KIND_COMPLEX
+    for prec, pname in ((su3.SU3_F64, "f64"), (su3.SU3_F32, "f32")):
+        tune(su3.SU3_EXPR_PROGRAM, prec, SOA, 0, dims)
+        rb = REAL_BYTES[prec]
+        v1 = su3.scalar_tensor(dims, prec, SOA, R)
+        v2 = su3.scalar_tensor(dims, prec, SOA, R)
+        v3 = su3.scalar_tensor(dims, prec, SOA, R)
+        su3.su3_program_eval(su3.Program("1.0", []), v1, [], stream)
+        su3.su3_program_eval(su3.Program("2.0", []), v2, [], stream)
+        mats = [make(dims, prec, SOA, 0, testgen.FID_U0 + k) for k in range(4)]
+        zm = su3.field_tensor(dims, prec, SOA, 0)
+        zc = su3.scalar_tensor(dims, prec, SOA, C)
+        cases = [("listing2", "a+b+a*b", [R, R], v3, [v1, v2], 3 * rb),
+                 ("mul", "a*b", [M, M], zm, mats[:2], 54 * rb),
+                 ("muladd", "a*b+c*d", [M, M, M, M], zm, mats, 90 * rb),
+                 ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb)]
+        for name, text, kinds, z, ops, bps in cases:
+            prog = su3.Program(text, kinds)
+            ms, _ = timer.run(lambda: su3.su3_program_eval(prog, z, ops, stream), steps, 3)
+            key = f"{pname}_{name}"
+            progs[key] = {"expr": text, "us": round(ms * 1e3, 2),
+                          "gbps": round(bps * V / (ms * 1e-3) / 1e9, 1),
+                          "bytes_per_site": bps}
+            if name == "mul":
+                mf, _ = timer.run(lambda: su3.su3_mult(zm, mats[0], mats[1], stream), steps, 3)
+                progs[key]["fixed_kernel_us"] = round(mf * 1e3, 2)
+            if name == "muladd":
+                mf, _ = timer.run(lambda: su3.su3_fused_eval(zm, su3.SU3_EXPR_MULADD, mats,
+                                                             stream), steps, 3)
+                progs[key]["fixed_kernel_us"] = round(mf * 1e3, 2)
+            log(f"program {key}: {progs[key]}")
+        del v1, v2, v3, mats, zm, zc
+    out["programs_48^4"] = progs
 
     # fused vs chained at 32^4 with four link fields
     d = (32, 32, 32, 32)

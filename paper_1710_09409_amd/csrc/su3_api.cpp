@@ -17,7 +17,9 @@
 #include <tuple>
 #include <vector>
 
+#include "su3_dslash.h"
 #include "su3_internal.h"
+#include "su3_program.h"
 
 using namespace su3i;
 

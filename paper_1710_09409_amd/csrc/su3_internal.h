@@ -1,5 +1,8 @@
 // Internal interface between the host C-ABI unit (su3_api.cpp) and the
-// kernel unit (su3_kernels.hip).  Not installed, not part of the ABI.
+// site, shift, batch and yardstick kernel units (su3_kprec.hip,
+// su3_kmisc.hip); shared definitions (precisions, expressions, layouts,
+// index geometry) of every kernel unit.  Not installed, not part of the
+// ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -86,110 +89,6 @@ struct BatchItem {
     int32_t tile_start;
 };
 
-// Arguments of the Wilson hopping kernel.  Spinor fields store 12 complex
-// entries per site (spin-major: entry 3 * spin + colour), link fields 9 (or
-// 6 for the two-row form); both share dims, layout and lanes, so one site
-// index addresses either through its own Geom.  Direction mu has extent
-// dims[mu] and neighbour stride stride[mu] (x fastest).
-// In the virtual-node layout dims/stride describe the outer sub-lattice
-// (storage site s = osite * N_sub + lane, stride in storage sites) and
-// nlanes/lstride the lanes; elsewhere nlanes = 1, lg = lmask = 0.
-struct DslashArgs {
-    void *out;
-    const void *in;
-    const void *u[4];
-    Geom gs;          // spinor geometry
-    Geom gl;          // link geometry
-    int32_t nsites;
-    int32_t xcd_remap;  // 1: contiguous workgroup ranges per XCD
-    uint32_t walk;      // t-slices per lane (1: one site per lane)
-    uint32_t dims[4];   // outer extents
-    uint32_t stride[4]; // outer strides (storage sites)
-    uint32_t nlanes[4]; // virtual nodes per direction
-    uint32_t lstride[4];
-    uint32_t lg;        // log2 N_sub
-    uint32_t lmask;     // N_sub - 1
-};
-
-// ------------------------------------------------ expression programs
-//
-// A site-local expression compiled on the host into a register program.
-// Registers hold a 3x3 complex matrix; a scalar occupies entry 0 (real
-// scalars keep a zero imaginary part).  Operand k is loaded into register
-// k before the first instruction; instructions read registers a, b and
-// write register d; the result is register `result`.
-enum ProgOp : uint8_t {
-    OP_CONST = 0,  // r[d] = imm[a] (scalar)
-    OP_ADD_MM, OP_SUB_MM, OP_MUL_MM,
-    OP_ADD_SS, OP_SUB_SS, OP_MUL_SS,
-    OP_MUL_SM,     // r[d] = r[a] (scalar) * r[b] (matrix)
-    OP_MUL_MS,     // r[d] = r[a] (matrix) * r[b] (scalar)
-    OP_ADD_SM,     // r[d] = r[a] I + r[b]
-    OP_ADD_MS,     // r[d] = r[a] + r[b] I
-    OP_SUB_SM,     // r[d] = r[a] I - r[b]
-    OP_SUB_MS,     // r[d] = r[a] - r[b] I
-    OP_NEG_M, OP_NEG_S,
-    OP_ADJ_M,      // conjugate transpose
-    OP_CONJ_M,     // elementwise conjugate
-    OP_CONJ_S,
-    OP_TRACE,      // matrix -> complex scalar
-    OP_REAL, OP_IMAG,  // scalar -> real scalar
-    OP_TRANS_M,    // transpose
-    NPROGOP
-};
-
-constexpr int kProgMaxOps = 8;     // operand fields
-constexpr int kProgMaxInstr = 48;
-constexpr int kProgMaxImm = 8;
-constexpr int kProgMaxRegs = 8;
-
-struct ProgInstr {
-    uint8_t op, d, a, b;
-};
-
-// Field kinds of program operands and results.
-enum FieldKind { FK_MATRIX = 0, FK_SPINOR = 1, FK_REAL = 2, FK_COMPLEX = 3 };
-
-struct ProgArgs {
-    void *z;
-    const void *op[kProgMaxOps];
-    Geom g[kProgMaxOps];      // per operand (entry counts differ by kind)
-    Geom gz;
-    uint8_t kind[kProgMaxOps];   // FieldKind
-    uint8_t prec[kProgMaxOps];   // storage precision (F64, F32, C12)
-    uint8_t zkind, zprec;
-    uint8_t nops, ninstr, result;
-    uint8_t used;                // bit k: operand k is read
-    int32_t nsites;
-    double imm[kProgMaxImm][2];
-    ProgInstr ins[kProgMaxInstr];
-};
-
-// Arithmetic precision F64 (all fields F64; at most 4 registers) or F32
-// (F32 / C12 fields; at most 8).  One site per lane; grid * block >=
-// nsites.
-hipError_t launch_program(int arith, int nregs, int nt, int block, int grid,
-                          size_t shm, const ProgArgs &a, hipStream_t stream);
-
-// Host compiler (su3_program.cpp): parse `text` over n operands of the
-// given kinds (FieldKind), type-check and allocate registers.  Fills
-// ins/ninstr/imm/result/nops of `out`, the result kind and the number of
-// registers used; returns false with a message in *err.
-struct ProgCode {
-    ProgInstr ins[kProgMaxInstr];
-    int ninstr;
-    double imm[kProgMaxImm][2];
-    int nimm;
-    int result;
-    int result_kind;
-    int nregs;
-    int nops;
-    bool su3_closed;  // only products, adjoints and transposes of matrices
-    unsigned used;    // bit k: operand k is read
-};
-bool compile_program(const char *text, int nops, const int *kinds,
-                     ProgCode *out, char *err, size_t errlen);
-
 // Kernel-unit entry points.  Each returns the launch's hipError_t.
 // `sites_per_lane` must be natural_sites(prec, expr) for blocked layouts or
 // 1; `sched` 0 = all loads then all stores, 1 = row-phased; `shm` is LDS
@@ -211,14 +110,6 @@ hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
 hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
                         int grid, size_t shm, const ShiftArgs &a,
                         hipStream_t stream);
-// Wilson hopping term: spinor precision F64 with F64 links, F32 with F32
-// or C12 links.  walk == 1: one site per lane, grid * block >= nsites;
-// walk > 1 (lexicographic site order only): one lane per (x, y, z) site
-// and chunk of `walk` t-slices,
-// grid * block >= stride[3] * ceil(dims[3] / walk).
-hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
-                         int grid, size_t shm, const DslashArgs &a,
-                         hipStream_t stream);
 hipError_t launch_triad(double *a, const double *b, const double *c,
                         double s, int64_t n, hipStream_t stream);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,

@@ -9,6 +9,7 @@
 // h are colour-rotated (two 3x3 matrix-vector products instead of four).
 // One lane per site; neighbours from the site index (x fastest), periodic.
 #include "su3_device.h"
+#include "su3_dslash.h"
 
 namespace su3k {
 namespace dslash {

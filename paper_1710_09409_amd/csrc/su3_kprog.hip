@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "su3_device.h"
+#include "su3_program.h"
 
 namespace su3k {
 namespace prog {

@@ -21,7 +21,7 @@
 #include <string>
 #include <vector>
 
-#include "su3_internal.h"
+#include "su3_program.h"
 
 namespace su3i {
 namespace {
