@@ -152,7 +152,11 @@ typedef struct su3_program su3_program;
  *   schedule    0: each lane loads every operand entry, then stores every
  *               result entry; 1: row-phased -- right-hand operands in
  *               full, then per result row the left operands' row, the
- *               row's evaluation and its stores                          */
+ *               row's evaluation and its stores.
+ *               su3_dslash with one site per lane (lexicographic layouts):
+ *               0 sites in index order; 1..3 each workgroup covers a 4D
+ *               tile of sites, 8x4x2x(B/64), 4x4x4x(B/64), 8x2x2x(B/32)
+ *               for block B                                              */
 typedef struct su3_launch {
     int32_t block;
     int32_t persistent;

@@ -715,8 +715,13 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
     if (c.occupancy < 0 || c.occupancy > 64)
         return fail(SU3_ERR_INVALID_ARG, "occupancy %d not in [0, 64]",
                     c.occupancy);
-    if (c.schedule < 0 || c.schedule > 1)
+    if (expr == SU3_EXPR_DSLASH) {
+        if (c.schedule < 0 || c.schedule > 3)
+            return fail(SU3_ERR_INVALID_ARG,
+                        "Dslash schedule (site tile) must be in [0, 3]");
+    } else if (c.schedule < 0 || c.schedule > 1) {
         return fail(SU3_ERR_INVALID_ARG, "schedule must be 0 or 1");
+    }
     return SU3_OK;
 }
 
@@ -1033,6 +1038,18 @@ extern "C" su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
 
 // ------------------------------------------------------ Wilson hopping
 
+// Site tiles of the one-site Dslash kernel by `schedule` (1..3) and block
+// B: 8 x 4 x 2 x B/64, 4 x 4 x 4 x B/64, 8 x 2 x 2 x B/32.
+static void dslash_tile(int schedule, int block, uint32_t t[4])
+{
+    static const uint32_t shape[3][3] = {{8, 4, 2}, {4, 4, 4}, {8, 2, 2}};
+    const uint32_t *sh = shape[(schedule - 1) % 3];
+    t[0] = sh[0];
+    t[1] = sh[1];
+    t[2] = sh[2];
+    t[3] = (uint32_t)block / (sh[0] * sh[1] * sh[2]);
+}
+
 static int spinor_prec_of_links(int link_prec)
 {
     return link_prec == SU3_F64 ? SU3_F64 : SU3_F32;
@@ -1082,7 +1099,15 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     a.walk = vn ? 1u : (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
     const int64_t lanes = a.walk <= 1 ? out->V
                                       : a.stride[3] * ((Lt + a.walk - 1) / a.walk);
-    const int64_t grid = (lanes + c.block - 1) / c.block;
+    int64_t grid = (lanes + c.block - 1) / c.block;
+    if (a.walk <= 1 && !vn && c.schedule > 0) {
+        dslash_tile(c.schedule, c.block, a.tile);
+        grid = 1;
+        for (int mu = 0; mu < 4; ++mu) {
+            a.ntile[mu] = (uint32_t)((out->dims[mu] + a.tile[mu] - 1) / a.tile[mu]);
+            grid *= a.ntile[mu];
+        }
+    }
     hipError_t e = launch_dslash(out->prec, u0->prec, c.nontemporal, c.block,
                                  (int)grid,
                                  occupancy_reserve(out->device, c.occupancy),
@@ -1457,23 +1482,25 @@ static std::vector<su3_launch> candidates(int layout)
 }
 
 // Candidates for the Wilson hopping kernel: t-slices per lane (1: one
-// site per lane), block, occupancy cap, XCD remapping (nontemporal
-// stores, cached loads).
+// site per lane, in index order or in site tiles), block, occupancy cap,
+// XCD remapping (nontemporal stores, cached loads).
 static std::vector<su3_launch> dslash_candidates()
 {
     std::vector<su3_launch> out;
     su3_launch c = default_launch(SU3_EXPR_DSLASH, SU3_F64, SU3_LAYOUT_SOA);
     c.nontemporal = 2;
-    for (int walk : {1, 4, 8, 16})
-        for (int b : {64, 128, 256})
-            for (int occ : {0, 2, 3, 4, 6})
-                for (int x : {0, 1}) {
-                    c.tile_sites = walk;
-                    c.block = b;
-                    c.occupancy = occ;
-                    c.xcd_remap = x;
-                    out.push_back(c);
-                }
+    for (int walk : {1, 4, 8})
+        for (int sched = 0; sched <= (walk == 1 ? 3 : 0); ++sched)
+            for (int b : {64, 128, 256})
+                for (int occ : {0, 2, 3, 4, 6})
+                    for (int x : {0, 1}) {
+                        c.tile_sites = walk;
+                        c.schedule = sched;
+                        c.block = b;
+                        c.occupancy = occ;
+                        c.xcd_remap = x;
+                        out.push_back(c);
+                    }
     return out;
 }
 

@@ -29,13 +29,20 @@ struct DslashArgs {
     uint32_t lstride[4];
     uint32_t lg;        // log2 N_sub
     uint32_t lmask;     // N_sub - 1
+    // one site per lane (walk == 1), lexicographic fields: tile[0] > 0
+    // gives each workgroup a tile[0] x tile[1] x tile[2] x tile[3] block of
+    // sites (product = block), tiles x-fastest over ntile[0..2] per
+    // direction; tile[0] == 0 takes sites in index order
+    uint32_t tile[4];
+    uint32_t ntile[4];
 };
 
 // Wilson hopping term: spinor precision F64 with F64 links, F32 with F32
 // or C12 links.  walk == 1: one site per lane, grid * block >= nsites;
 // walk > 1 (lexicographic site order only): one lane per (x, y, z) site
 // and chunk of `walk` t-slices,
-// grid * block >= stride[3] * ceil(dims[3] / walk).
+// grid * block >= stride[3] * ceil(dims[3] / walk).  With a tile:
+// grid = ntile[0] * ntile[1] * ntile[2] * ntile[3].
 hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
                          int grid, size_t shm, const DslashArgs &a,
                          hipStream_t stream);

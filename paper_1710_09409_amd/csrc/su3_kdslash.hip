@@ -238,16 +238,37 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
     using T = typename PrecT<SP>::T;
     const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
                                      : blockIdx.x;
-    const uint32_t s = blk * blockDim.x + threadIdx.x;
-    if (s < (uint32_t)a.nsites) {
+    uint32_t s, c[4], l[4];
+    bool inside;
+    if (a.tile[0] == 0) {
+        s = blk * blockDim.x + threadIdx.x;
+        inside = s < (uint32_t)a.nsites;
+        if (inside)
+            coords(a, s, c, l);
+    } else {
+        // a workgroup covers a tile[0] x .. x tile[3] block of sites
+        // (lexicographic fields only); tiles in x-fastest order
+        uint32_t q = blk, r = threadIdx.x;
+        inside = true;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const uint32_t tq = mu < 3 ? q % a.ntile[mu] : q;
+            q = mu < 3 ? q / a.ntile[mu] : 0;
+            const uint32_t tr = mu < 3 ? r % a.tile[mu] : r;
+            r = mu < 3 ? r / a.tile[mu] : 0;
+            c[mu] = tq * a.tile[mu] + tr;
+            l[mu] = 0;
+            inside = inside && c[mu] < a.dims[mu];
+        }
+        s = c[0] + a.dims[0] * (c[1] + a.dims[1] * (c[2] + a.dims[2] * c[3]));
+    }
+    if (inside) {
         Cx<T> acc[4][3];
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                acc[sp][c] = {T(0), T(0)};
-        uint32_t c[4], l[4];
-        coords(a, s, c, l);
+            for (int cc = 0; cc < 3; ++cc)
+                acc[sp][cc] = {T(0), T(0)};
         // accumulation order shared with the walk kernel (results are
         // bitwise independent of the launch): t backward, t forward,
         // then x, y, z (forward, backward)

@@ -240,10 +240,12 @@ int main(int argc, char **argv)
                     su3_field_upload(fin, hin.data(), nullptr);
                     // one site per lane; walks of 3 t-slices; one walk over all of t;
                     // walks of 4 and 2 (ragged last walks)
-                    su3_launch cs[5] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
+                    // site tiles 8x4x2x2, 4x4x4x1, 8x2x2x8 (ragged against these lattices)
+                    su3_launch cs[8] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
                                         {128, 0, 2, 0, 0, 4096, 0, 0}, {128, 0, 2, 1, 0, 4, 0, 0},
-                                        {64, 0, 2, 0, 0, 2, 0, 0}};
-                    for (int k = 0; k < 5; ++k) {
+                                        {64, 0, 2, 0, 0, 2, 0, 0}, {128, 0, 2, 1, 0, 1, 0, 1},
+                                        {64, 0, 2, 0, 0, 1, 0, 2}, {256, 0, 2, 1, 0, 1, 0, 3}};
+                    for (int k = 0; k < 8; ++k) {
                         su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &cs[k]);
                         if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
                         su3_field_download(fout, k ? got1.data() : got.data(), nullptr);
