@@ -1262,8 +1262,8 @@ static su3_status launch_program_op(const su3_program *p, su3_field *z,
         a.imm[k][1] = p->code.imm[k][1];
     }
     const int64_t grid = (z->V + c.block - 1) / c.block;
-    hipError_t e = launch_program(arith, p->code.nregs, c.nontemporal, c.block,
-                                  (int)grid,
+    hipError_t e = launch_program(arith, p->code.scalar_only, p->code.nregs,
+                                  c.nontemporal, c.block, (int)grid,
                                   occupancy_reserve(z->device, c.occupancy), a,
                                   st);
     if (e != hipSuccess)
@@ -1315,10 +1315,10 @@ extern "C" su3_status su3_program_eval(const su3_program *p, su3_field *z,
         return fail(SU3_ERR_UNSUPPORTED,
                     "a compressed output needs an SU(3)-valued expression "
                     "(products, adjoints, transposes, conjugates of matrices)");
-    if (arith == SU3_F64 && p->code.nregs > 4)
+    if (arith == SU3_F64 && p->code.nregs > 4 && !p->code.scalar_only)
         return fail(SU3_ERR_UNSUPPORTED,
-                    "the expression needs %d registers; double precision "
-                    "evaluates with at most 4", p->code.nregs);
+                    "the expression needs %d matrix registers; double "
+                    "precision evaluates with at most 4", p->code.nregs);
     return launch_program_op(p, z, ops, arith, static_cast<hipStream_t>(stream));
 }
 

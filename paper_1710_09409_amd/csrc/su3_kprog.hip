@@ -5,7 +5,9 @@
 // registers, each a uniform branch on the opcode, and the result register
 // is stored.
 //
-// A register is a 3x3 complex matrix; scalars use entry 0.  Register
+// A register holds a 3x3 complex matrix (NE = 9; a scalar uses entry 0),
+// or, for programs without matrix values, one complex number (NE = 1,
+// which keeps the register file small and the occupancy high).  Register
 // indices are uniform across the wave and are resolved by a chain of
 // compare-and-copy branches, so the register file stays in VGPRs.
 #include <type_traits>
@@ -19,18 +21,15 @@ namespace prog {
 using su3i::ProgArgs;
 using su3i::ProgInstr;
 
-template <class T>
+template <class T, int NE>
 struct Reg {
-    Cx<T> m[9];
+    Cx<T> m[NE];
 };
 
-// The register file as separate members, each selected in its own branch
-// that ends in an empty asm statement with a distinct immediate: the
-// branches cannot be merged into one copy from a selected address, which
-// would move the registers to scratch memory.
 // End of a branch that wrote registers: an empty asm statement with an
 // immediate unique to the branch, so that no two branches are merged into
-// one store through a selected address.
+// one copy through a selected address (which would move the register file
+// to scratch memory).
 template <int N>
 __device__ __forceinline__ void branch_end()
 {
@@ -39,22 +38,23 @@ __device__ __forceinline__ void branch_end()
 
 struct NoReg {};
 
-template <class T, int NR, int K>
-using RegIf = typename std::conditional<(K < NR), Reg<T>, NoReg>::type;
+template <class T, int NE, int NR, int K>
+using RegIf = typename std::conditional<(K < NR), Reg<T, NE>, NoReg>::type;
 
-template <class T, int NR>
+// The register file as separate members (never an indexable array).
+template <class T, int NE, int NR>
 struct RegFile {
-    RegIf<T, NR, 0> r0;
-    RegIf<T, NR, 1> r1;
-    RegIf<T, NR, 2> r2;
-    RegIf<T, NR, 3> r3;
-    RegIf<T, NR, 4> r4;
-    RegIf<T, NR, 5> r5;
-    RegIf<T, NR, 6> r6;
-    RegIf<T, NR, 7> r7;
+    RegIf<T, NE, NR, 0> r0;
+    RegIf<T, NE, NR, 1> r1;
+    RegIf<T, NE, NR, 2> r2;
+    RegIf<T, NE, NR, 3> r3;
+    RegIf<T, NE, NR, 4> r4;
+    RegIf<T, NE, NR, 5> r5;
+    RegIf<T, NE, NR, 6> r6;
+    RegIf<T, NE, NR, 7> r7;
 
     template <int K>
-    __device__ __forceinline__ RegIf<T, NR, K> &at()
+    __device__ __forceinline__ RegIf<T, NE, NR, K> &at()
     {
         if constexpr (K == 0) return r0;
         else if constexpr (K == 1) return r1;
@@ -67,34 +67,31 @@ struct RegFile {
     }
 };
 
-template <class T, int NR, int K = 0>
-__device__ __forceinline__ void get(RegFile<T, NR> &R, int i, Reg<T> &out)
+template <class T, int NE, int NR, int K = 0>
+__device__ __forceinline__ void get(RegFile<T, NE, NR> &R, int i, Reg<T, NE> &out)
 {
     if constexpr (K < NR) {
         if (i == K) {
             out = R.template at<K>();
             branch_end<K>();
         } else {
-            get<T, NR, K + 1>(R, i, out);
+            get<T, NE, NR, K + 1>(R, i, out);
         }
     }
 }
 
-template <class T, int NR, int K = 0>
-__device__ __forceinline__ void put(RegFile<T, NR> &R, int i, const Reg<T> &v)
+template <class T, int NE, int NR, int K = 0>
+__device__ __forceinline__ void put(RegFile<T, NE, NR> &R, int i, const Reg<T, NE> &v)
 {
     if constexpr (K < NR) {
         if (i == K) {
             R.template at<K>() = v;
             branch_end<K + 16>();
         } else {
-            put<T, NR, K + 1>(R, i, v);
+            put<T, NE, NR, K + 1>(R, i, v);
         }
     }
 }
-
-template <class T, int NR, int NT, int K = 0>
-__device__ __forceinline__ void load_all(const ProgArgs &a, uint32_t s, RegFile<T, NR> &R);
 
 template <class T>
 __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
@@ -106,7 +103,7 @@ __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
 // F32 and the compressed form, whose third row is rebuilt).
 template <int P, int NT>
 __device__ __forceinline__ void load_matrix(const void *base, const su3i::Geom &g,
-                                            uint32_t s, Reg<typename PrecT<P>::T> &r)
+                                            uint32_t s, Reg<typename PrecT<P>::T, 9> &r)
 {
     constexpr int E = PrecT<P>::E;
     RawVec<P, 1> raw[E];
@@ -119,23 +116,25 @@ __device__ __forceinline__ void load_matrix(const void *base, const su3i::Geom &
         rebuild_row2(r.m);
 }
 
-template <class T, int NT>
+template <class T, int NE, int NT>
 __device__ __forceinline__ void load_operand(const ProgArgs &a, int k, uint32_t s,
-                                             Reg<T> &r)
+                                             Reg<T, NE> &r)
 {
     const void *base = a.op[k];
     switch (a.kind[k]) {
     case su3i::FK_MATRIX:
-        if constexpr (sizeof(T) == 8) {
-            load_matrix<su3i::F64, NT>(base, a.g[k], s, r);
-            branch_end<32>();
-        } else {
-            if (a.prec[k] == su3i::C12) {
-                load_matrix<su3i::C12, NT>(base, a.g[k], s, r);
-                branch_end<33>();
+        if constexpr (NE == 9) {
+            if constexpr (sizeof(T) == 8) {
+                load_matrix<su3i::F64, NT>(base, a.g[k], s, r);
+                branch_end<32>();
             } else {
-                load_matrix<su3i::F32, NT>(base, a.g[k], s, r);
-                branch_end<34>();
+                if (a.prec[k] == su3i::C12) {
+                    load_matrix<su3i::C12, NT>(base, a.g[k], s, r);
+                    branch_end<33>();
+                } else {
+                    load_matrix<su3i::F32, NT>(base, a.g[k], s, r);
+                    branch_end<34>();
+                }
             }
         }
         break;
@@ -153,92 +152,73 @@ __device__ __forceinline__ void load_operand(const ProgArgs &a, int k, uint32_t 
     }
 }
 
+// Matrix instructions (NE = 9 only).
 template <class T>
-__device__ __forceinline__ void exec(const ProgInstr in, const ProgArgs &a,
-                                     const Reg<T> &A, const Reg<T> &B, Reg<T> &C)
+__device__ __forceinline__ void exec_matrix(const ProgInstr in, const Reg<T, 9> &A,
+                                            const Reg<T, 9> &B, Reg<T, 9> &C)
 {
     switch (in.op) {
-    case su3i::OP_CONST:
-        C.m[0] = {T(a.imm[in.a][0]), T(a.imm[in.a][1])};
-        branch_end<65>();
-        break;
     case su3i::OP_ADD_MM:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = {A.m[e].re + B.m[e].re, A.m[e].im + B.m[e].im};
-        branch_end<66>();
+        branch_end<64>();
         break;
     case su3i::OP_SUB_MM:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = {A.m[e].re - B.m[e].re, A.m[e].im - B.m[e].im};
-        branch_end<67>();
+        branch_end<65>();
         break;
     case su3i::OP_MUL_MM:
         mat_mul<3>(A.m, B.m, C.m);
-        branch_end<68>();
-        break;
-    case su3i::OP_ADD_SS:
-        C.m[0] = {A.m[0].re + B.m[0].re, A.m[0].im + B.m[0].im};
-        branch_end<69>();
-        break;
-    case su3i::OP_SUB_SS:
-        C.m[0] = {A.m[0].re - B.m[0].re, A.m[0].im - B.m[0].im};
-        branch_end<70>();
-        break;
-    case su3i::OP_MUL_SS:
-        C.m[0] = cmul(A.m[0], B.m[0]);
-        branch_end<71>();
+        branch_end<66>();
         break;
     case su3i::OP_MUL_SM:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = cmul(A.m[0], B.m[e]);
-        branch_end<72>();
+        branch_end<67>();
         break;
     case su3i::OP_MUL_MS:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = cmul(A.m[e], B.m[0]);
-        branch_end<73>();
+        branch_end<68>();
         break;
     case su3i::OP_ADD_SM:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = e % 4 == 0 ? Cx<T>{A.m[0].re + B.m[e].re, A.m[0].im + B.m[e].im}
                                 : B.m[e];
-        branch_end<74>();
+        branch_end<69>();
         break;
     case su3i::OP_ADD_MS:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = e % 4 == 0 ? Cx<T>{A.m[e].re + B.m[0].re, A.m[e].im + B.m[0].im}
                                 : A.m[e];
-        branch_end<75>();
+        branch_end<70>();
         break;
     case su3i::OP_SUB_SM:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = e % 4 == 0 ? Cx<T>{A.m[0].re - B.m[e].re, A.m[0].im - B.m[e].im}
                                 : Cx<T>{-B.m[e].re, -B.m[e].im};
-        branch_end<76>();
+        branch_end<71>();
         break;
     case su3i::OP_SUB_MS:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = e % 4 == 0 ? Cx<T>{A.m[e].re - B.m[0].re, A.m[e].im - B.m[0].im}
                                 : A.m[e];
-        branch_end<77>();
+        branch_end<72>();
         break;
     case su3i::OP_NEG_M:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = {-A.m[e].re, -A.m[e].im};
-        branch_end<78>();
-        break;
-    case su3i::OP_NEG_S:
-        C.m[0] = {-A.m[0].re, -A.m[0].im};
-        branch_end<79>();
+        branch_end<73>();
         break;
     case su3i::OP_ADJ_M:
 #pragma unroll
@@ -246,29 +226,17 @@ __device__ __forceinline__ void exec(const ProgInstr in, const ProgArgs &a,
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 C.m[3 * i + j] = {A.m[3 * j + i].re, -A.m[3 * j + i].im};
-        branch_end<80>();
+        branch_end<74>();
         break;
     case su3i::OP_CONJ_M:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
             C.m[e] = {A.m[e].re, -A.m[e].im};
-        branch_end<81>();
-        break;
-    case su3i::OP_CONJ_S:
-        C.m[0] = {A.m[0].re, -A.m[0].im};
-        branch_end<82>();
+        branch_end<75>();
         break;
     case su3i::OP_TRACE:
         C.m[0] = {(A.m[0].re + A.m[4].re) + A.m[8].re, (A.m[0].im + A.m[4].im) + A.m[8].im};
-        branch_end<83>();
-        break;
-    case su3i::OP_REAL:
-        C.m[0] = {A.m[0].re, T(0)};
-        branch_end<84>();
-        break;
-    case su3i::OP_IMAG:
-        C.m[0] = {A.m[0].im, T(0)};
-        branch_end<85>();
+        branch_end<76>();
         break;
     case su3i::OP_TRANS_M:
 #pragma unroll
@@ -276,70 +244,116 @@ __device__ __forceinline__ void exec(const ProgInstr in, const ProgArgs &a,
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 C.m[3 * i + j] = A.m[3 * j + i];
-        branch_end<86>();
+        branch_end<77>();
         break;
     default:
-        branch_end<87>();
+        branch_end<78>();
         break;
     }
 }
 
-template <class T, int NR, int NT, int K>
-__device__ __forceinline__ void load_all(const ProgArgs &a, uint32_t s, RegFile<T, NR> &R)
+template <class T, int NE>
+__device__ __forceinline__ void exec(const ProgInstr in, const ProgArgs &a,
+                                     const Reg<T, NE> &A, const Reg<T, NE> &B,
+                                     Reg<T, NE> &C)
+{
+    switch (in.op) {
+    case su3i::OP_CONST:
+        C.m[0] = {T(a.imm[in.a][0]), T(a.imm[in.a][1])};
+        branch_end<96>();
+        break;
+    case su3i::OP_ADD_SS:
+        C.m[0] = {A.m[0].re + B.m[0].re, A.m[0].im + B.m[0].im};
+        branch_end<97>();
+        break;
+    case su3i::OP_SUB_SS:
+        C.m[0] = {A.m[0].re - B.m[0].re, A.m[0].im - B.m[0].im};
+        branch_end<98>();
+        break;
+    case su3i::OP_MUL_SS:
+        C.m[0] = cmul(A.m[0], B.m[0]);
+        branch_end<99>();
+        break;
+    case su3i::OP_NEG_S:
+        C.m[0] = {-A.m[0].re, -A.m[0].im};
+        branch_end<100>();
+        break;
+    case su3i::OP_CONJ_S:
+        C.m[0] = {A.m[0].re, -A.m[0].im};
+        branch_end<101>();
+        break;
+    case su3i::OP_REAL:
+        C.m[0] = {A.m[0].re, T(0)};
+        branch_end<102>();
+        break;
+    case su3i::OP_IMAG:
+        C.m[0] = {A.m[0].im, T(0)};
+        branch_end<103>();
+        break;
+    default:
+        if constexpr (NE == 9)
+            exec_matrix<T>(in, A, B, C);
+        branch_end<104>();
+        break;
+    }
+}
+
+template <class T, int NE, int NR, int NT, int K = 0>
+__device__ __forceinline__ void load_all(const ProgArgs &a, uint32_t s,
+                                         RegFile<T, NE, NR> &R)
 {
     if constexpr (K < NR) {
         if (K < a.nops) {
             if ((a.used >> K) & 1)
-                load_operand<T, NT>(a, K, s, R.template at<K>());
-            load_all<T, NR, NT, K + 1>(a, s, R);
+                load_operand<T, NE, NT>(a, K, s, R.template at<K>());
+            load_all<T, NE, NR, NT, K + 1>(a, s, R);
         }
     }
 }
 
-template <class T, int NR, int NT>
+template <class T, int NE, int NR, int NT>
 __global__ __launch_bounds__(256) void k_program(ProgArgs a)
 {
     extern __shared__ char occupancy_reserve[];
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < (uint32_t)a.nsites) {
-        RegFile<T, NR> R;
-        load_all<T, NR, NT>(a, s, R);
+        RegFile<T, NE, NR> R;
+        load_all<T, NE, NR, NT>(a, s, R);
         for (int pc = 0; pc < a.ninstr; ++pc) {
             const ProgInstr in = a.ins[pc];
-            Reg<T> A, B, C;
+            Reg<T, NE> A, B, C;
             get(R, in.a, A);
             get(R, in.b, B);
-            exec<T>(in, a, A, B, C);
+            exec<T, NE>(in, a, A, B, C);
             put(R, in.d, C);
         }
-        Reg<T> Z;
+        Reg<T, NE> Z;
         get(R, a.result, Z);
         switch (a.zkind) {
         case su3i::FK_MATRIX:
-            if constexpr (sizeof(T) == 8) {
-                RawVec<su3i::F64, 1> raw[9];
+            if constexpr (NE == 9) {
+                if constexpr (sizeof(T) == 8) {
+                    RawVec<su3i::F64, 1> raw[9];
 #pragma unroll
-                for (int e = 0; e < 9; ++e)
-                    narrow<su3i::F64, 1>(raw[e], 0, Z.m[e]);
-                store_entries<su3i::F64, 1, NT, true, 0, 9>(static_cast<double *>(a.z),
-                                                            site_offset(a.gz, s),
-                                                            a.gz.plane, 1, raw);
-            } else if (a.zprec == su3i::C12) {
-                RawVec<su3i::C12, 1> raw[6];
+                    for (int e = 0; e < 9; ++e)
+                        narrow<su3i::F64, 1>(raw[e], 0, Z.m[e]);
+                    store_entries<su3i::F64, 1, NT, true, 0, 9>(
+                        static_cast<double *>(a.z), site_offset(a.gz, s), a.gz.plane, 1, raw);
+                } else if (a.zprec == su3i::C12) {
+                    RawVec<su3i::C12, 1> raw[6];
 #pragma unroll
-                for (int e = 0; e < 6; ++e)
-                    narrow<su3i::C12, 1>(raw[e], 0, Z.m[e]);
-                store_entries<su3i::C12, 1, NT, true, 0, 6>(static_cast<float *>(a.z),
-                                                            site_offset(a.gz, s),
-                                                            a.gz.plane, 1, raw);
-            } else {
-                RawVec<su3i::F32, 1> raw[9];
+                    for (int e = 0; e < 6; ++e)
+                        narrow<su3i::C12, 1>(raw[e], 0, Z.m[e]);
+                    store_entries<su3i::C12, 1, NT, true, 0, 6>(
+                        static_cast<float *>(a.z), site_offset(a.gz, s), a.gz.plane, 1, raw);
+                } else {
+                    RawVec<su3i::F32, 1> raw[9];
 #pragma unroll
-                for (int e = 0; e < 9; ++e)
-                    narrow<su3i::F32, 1>(raw[e], 0, Z.m[e]);
-                store_entries<su3i::F32, 1, NT, true, 0, 9>(static_cast<float *>(a.z),
-                                                            site_offset(a.gz, s),
-                                                            a.gz.plane, 1, raw);
+                    for (int e = 0; e < 9; ++e)
+                        narrow<su3i::F32, 1>(raw[e], 0, Z.m[e]);
+                    store_entries<su3i::F32, 1, NT, true, 0, 9>(
+                        static_cast<float *>(a.z), site_offset(a.gz, s), a.gz.plane, 1, raw);
+                }
             }
             break;
         case su3i::FK_REAL:
@@ -359,17 +373,30 @@ __global__ __launch_bounds__(256) void k_program(ProgArgs a)
         occupancy_reserve[threadIdx.x] = 0;
 }
 
-template <class T, int NR>
+template <class T, int NE, int NR>
 static hipError_t go(int nt, int block, int grid, size_t shm, const ProgArgs &a,
                      hipStream_t st)
 {
     if ((nt & 3) == 3)
-        hipLaunchKernelGGL((k_program<T, NR, 3>), dim3(grid), dim3(block), shm, st, a);
+        hipLaunchKernelGGL((k_program<T, NE, NR, 3>), dim3(grid), dim3(block), shm, st, a);
     else if ((nt & 3) == 2)
-        hipLaunchKernelGGL((k_program<T, NR, 2>), dim3(grid), dim3(block), shm, st, a);
+        hipLaunchKernelGGL((k_program<T, NE, NR, 2>), dim3(grid), dim3(block), shm, st, a);
     else
-        hipLaunchKernelGGL((k_program<T, NR, 0>), dim3(grid), dim3(block), shm, st, a);
+        hipLaunchKernelGGL((k_program<T, NE, NR, 0>), dim3(grid), dim3(block), shm, st, a);
     return hipGetLastError();
+}
+
+template <class T>
+static hipError_t go_t(bool scalar_only, int nregs, int nt, int block, int grid,
+                       size_t shm, const ProgArgs &a, hipStream_t st)
+{
+    if (scalar_only)
+        return go<T, 1, 8>(nt, block, grid, shm, a, st);
+    if (nregs <= 4)
+        return go<T, 9, 4>(nt, block, grid, shm, a, st);
+    if constexpr (sizeof(T) == 4)
+        return go<T, 9, 8>(nt, block, grid, shm, a, st);
+    return hipErrorInvalidValue;  // four double matrices fill the register file
 }
 
 }  // namespace prog
@@ -377,18 +404,17 @@ static hipError_t go(int nt, int block, int grid, size_t shm, const ProgArgs &a,
 
 namespace su3i {
 
-hipError_t launch_program(int arith, int nregs, int nt, int block, int grid,
-                          size_t shm, const ProgArgs &a, hipStream_t st)
+hipError_t launch_program(int arith, bool scalar_only, int nregs, int nt,
+                          int block, int grid, size_t shm, const ProgArgs &a,
+                          hipStream_t st)
 {
     using namespace su3k::prog;
     if (block > 256 || nregs < 1 || nregs > kProgMaxRegs)
         return hipErrorInvalidValue;
-    if (arith == F64)  // four double registers fill the register file
-        return nregs <= 4 ? go<double, 4>(nt, block, grid, shm, a, st)
-                          : hipErrorInvalidValue;
+    if (arith == F64)
+        return go_t<double>(scalar_only, nregs, nt, block, grid, shm, a, st);
     if (arith == F32)
-        return nregs <= 4 ? go<float, 4>(nt, block, grid, shm, a, st)
-                          : go<float, 8>(nt, block, grid, shm, a, st);
+        return go_t<float>(scalar_only, nregs, nt, block, grid, shm, a, st);
     return hipErrorInvalidValue;
 }
 

@@ -448,6 +448,14 @@ bool compile_program(const char *text, int nops, const int *kinds,
     out->nregs = maxreg < 1 ? 1 : maxreg;
     out->nops = nops;
     out->su3_closed = closed && root->ty == T_MATRIX;
+    struct Walk {
+        static bool any_matrix(const Node *n)
+        {
+            return n && (n->ty == T_MATRIX || any_matrix(n->l.get()) ||
+                         any_matrix(n->r.get()));
+        }
+    };
+    out->scalar_only = !Walk::any_matrix(root.get());
     out->used = 0;
     for (int k = 0; k < nops; ++k)
         if (last[k] >= 0)

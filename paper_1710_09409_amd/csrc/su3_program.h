@@ -61,11 +61,13 @@ struct ProgArgs {
     ProgInstr ins[kProgMaxInstr];
 };
 
-// Arithmetic precision F64 (all fields F64; at most 4 registers) or F32
-// (F32 / C12 fields; at most 8).  One site per lane; grid * block >=
-// nsites.
-hipError_t launch_program(int arith, int nregs, int nt, int block, int grid,
-                          size_t shm, const ProgArgs &a, hipStream_t stream);
+// Arithmetic precision F64 (all fields F64) or F32 (F32 / C12 fields).
+// Programs with matrix values use at most 4 registers in F64 and 8 in F32;
+// scalar_only programs (no matrix value anywhere) at most 8 in either.
+// One site per lane; grid * block >= nsites.
+hipError_t launch_program(int arith, bool scalar_only, int nregs, int nt,
+                          int block, int grid, size_t shm, const ProgArgs &a,
+                          hipStream_t stream);
 
 // Host compiler (su3_program.cpp): parse `text` over n operands of the
 // given kinds (FieldKind), type-check and allocate registers.  Fills
@@ -81,6 +83,7 @@ struct ProgCode {
     int nregs;
     int nops;
     bool su3_closed;  // only products, adjoints and transposes of matrices
+    bool scalar_only; // no matrix-valued operand or intermediate
     unsigned used;    // bit k: operand k is read
 };
 bool compile_program(const char *text, int nops, const int *kinds,
