@@ -1261,7 +1261,9 @@ static su3_status launch_program_op(const su3_program *p, su3_field *z,
         a.imm[k][0] = p->code.imm[k][0];
         a.imm[k][1] = p->code.imm[k][1];
     }
-    const int64_t grid = (z->V + c.block - 1) / c.block;
+    const int64_t per = program_sites_per_lane(arith, p->code.scalar_only);
+    const int64_t lanes = (z->V + per - 1) / per;
+    const int64_t grid = (lanes + c.block - 1) / c.block;
     hipError_t e = launch_program(arith, p->code.scalar_only, p->code.nregs,
                                   c.nontemporal, c.block, (int)grid,
                                   occupancy_reserve(z->device, c.occupancy), a,

@@ -5,10 +5,10 @@
 // registers, each a uniform branch on the opcode, and the result register
 // is stored.
 //
-// A register holds a 3x3 complex matrix (NE = 9; a scalar uses entry 0),
-// or, for programs without matrix values, one complex number (NE = 1,
-// which keeps the register file small and the occupancy high).  Register
-// indices are uniform across the wave and are resolved by a chain of
+// A register holds a 3x3 complex matrix (NE = 9; a scalar uses entry 0).
+// Programs without matrix values run in their own kernel, whose registers
+// hold one complex value for each of the lane's S sites.  Register indices
+// are uniform across the wave and are resolved by a chain of
 // compare-and-copy branches, so the register file stays in VGPRs.
 #include <type_traits>
 
@@ -373,6 +373,165 @@ __global__ __launch_bounds__(256) void k_program(ProgArgs a)
         occupancy_reserve[threadIdx.x] = 0;
 }
 
+// Scalar-only programs: each lane evaluates S consecutive sites (one
+// complex value per site in each register), so a site costs 1/S of the
+// instruction dispatch and operands move in S-wide vector accesses.
+template <class T, int S>
+struct SReg {
+    Cx<T> v[S];
+};
+
+template <class T, int S, int NT>
+__device__ __forceinline__ void load_scalars(const ProgArgs &a, int k, uint32_t s0,
+                                             int cnt, SReg<T, S> &r)
+{
+    if (a.kind[k] == su3i::FK_REAL) {
+        const T *p = static_cast<const T *>(a.op[k]) + s0;
+        if (cnt == S) {
+            using V = typename VecOf<T, S>::type;
+            const V w = vload<NT & 1>(reinterpret_cast<const V *>(p));
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                r.v[j] = {w[j], T(0)};
+        } else {
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                r.v[j] = {j < cnt ? p[j] : T(0), T(0)};
+        }
+        branch_end<40>();
+    } else {
+        using V2 = typename VecOf<T, 2>::type;
+        const V2 *p = static_cast<const V2 *>(a.op[k]) + s0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            V2 w;
+            if (cnt == S || j < cnt) {
+                w = vload<NT & 1>(p + j);
+            } else {
+                w[0] = T(0);
+                w[1] = T(0);
+            }
+            r.v[j] = {w[0], w[1]};
+        }
+        branch_end<41>();
+    }
+}
+
+template <class T, int S>
+__device__ __forceinline__ void exec_scalars(const ProgInstr in, const ProgArgs &a,
+                                             const SReg<T, S> &A, const SReg<T, S> &B,
+                                             SReg<T, S> &C)
+{
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        Reg<T, 1> x, y, z;
+        x.m[0] = A.v[j];
+        y.m[0] = B.v[j];
+        exec<T, 1>(in, a, x, y, z);
+        C.v[j] = z.m[0];
+    }
+}
+
+template <class T, int S, int NR, int K = 0>
+__device__ __forceinline__ void sget(RegFile<T, S, NR> &R, int i, SReg<T, S> &out)
+{
+    if constexpr (K < NR) {
+        if (i == K) {
+            const Reg<T, S> &r = R.template at<K>();
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                out.v[j] = r.m[j];
+            branch_end<K + 48>();
+        } else {
+            sget<T, S, NR, K + 1>(R, i, out);
+        }
+    }
+}
+
+template <class T, int S, int NR, int K = 0>
+__device__ __forceinline__ void sput(RegFile<T, S, NR> &R, int i, const SReg<T, S> &v)
+{
+    if constexpr (K < NR) {
+        if (i == K) {
+            Reg<T, S> &r = R.template at<K>();
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                r.m[j] = v.v[j];
+            branch_end<K + 56>();
+        } else {
+            sput<T, S, NR, K + 1>(R, i, v);
+        }
+    }
+}
+
+template <class T, int S, int NT, int K = 0>
+__device__ __forceinline__ void sload_all(const ProgArgs &a, uint32_t s0, int cnt,
+                                          RegFile<T, S, 8> &R)
+{
+    if constexpr (K < 8) {
+        if (K < a.nops) {
+            if ((a.used >> K) & 1) {
+                SReg<T, S> t;
+                load_scalars<T, S, NT>(a, K, s0, cnt, t);
+                sput<T, S, 8>(R, K, t);
+            }
+            sload_all<T, S, NT, K + 1>(a, s0, cnt, R);
+        }
+    }
+}
+
+// Registers here hold S sites' values (RegFile entries reused as S-wide).
+template <class T, int S, int NT>
+__global__ __launch_bounds__(256) void k_program_scalar(ProgArgs a)
+{
+    extern __shared__ char occupancy_reserve[];
+    const uint32_t s0 = (blockIdx.x * blockDim.x + threadIdx.x) * S;
+    if (s0 < (uint32_t)a.nsites) {
+        const int cnt = (uint32_t)a.nsites - s0 < (uint32_t)S ? int(a.nsites - s0) : S;
+        RegFile<T, S, 8> R;
+        sload_all<T, S, NT>(a, s0, cnt, R);
+        for (int pc = 0; pc < a.ninstr; ++pc) {
+            const ProgInstr in = a.ins[pc];
+            SReg<T, S> A, B, C;
+            sget(R, in.a, A);
+            sget(R, in.b, B);
+            exec_scalars<T, S>(in, a, A, B, C);
+            sput(R, in.d, C);
+        }
+        SReg<T, S> Z;
+        sget(R, a.result, Z);
+        if (a.zkind == su3i::FK_REAL) {
+            T *p = static_cast<T *>(a.z) + s0;
+            if (cnt == S) {
+                using V = typename VecOf<T, S>::type;
+                V w;
+#pragma unroll
+                for (int j = 0; j < S; ++j)
+                    w[j] = Z.v[j].re;
+                vstore<NT & 2>(reinterpret_cast<V *>(p), w);
+            } else {
+#pragma unroll
+                for (int j = 0; j < S; ++j)
+                    if (j < cnt)
+                        p[j] = Z.v[j].re;
+            }
+        } else {
+            using V2 = typename VecOf<T, 2>::type;
+            V2 *p = static_cast<V2 *>(a.z) + s0;
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                if (cnt == S || j < cnt) {
+                    V2 w;
+                    w[0] = Z.v[j].re;
+                    w[1] = Z.v[j].im;
+                    vstore<NT & 2>(p + j, w);
+                }
+        }
+    }
+    if (a.nsites < 0)
+        occupancy_reserve[threadIdx.x] = 0;
+}
+
 template <class T, int NE, int NR>
 static hipError_t go(int nt, int block, int grid, size_t shm, const ProgArgs &a,
                      hipStream_t st)
@@ -386,12 +545,30 @@ static hipError_t go(int nt, int block, int grid, size_t shm, const ProgArgs &a,
     return hipGetLastError();
 }
 
+// Sites per lane of scalar-only programs: 16-byte real accesses.
+template <class T>
+constexpr int kScalarSites = 16 / sizeof(T);
+
+template <class T>
+static hipError_t go_scalar(int nt, int block, int grid, size_t shm,
+                            const ProgArgs &a, hipStream_t st)
+{
+    constexpr int S = kScalarSites<T>;
+    if ((nt & 3) == 3)
+        hipLaunchKernelGGL((k_program_scalar<T, S, 3>), dim3(grid), dim3(block), shm, st, a);
+    else if ((nt & 3) == 2)
+        hipLaunchKernelGGL((k_program_scalar<T, S, 2>), dim3(grid), dim3(block), shm, st, a);
+    else
+        hipLaunchKernelGGL((k_program_scalar<T, S, 0>), dim3(grid), dim3(block), shm, st, a);
+    return hipGetLastError();
+}
+
 template <class T>
 static hipError_t go_t(bool scalar_only, int nregs, int nt, int block, int grid,
                        size_t shm, const ProgArgs &a, hipStream_t st)
 {
     if (scalar_only)
-        return go<T, 1, 8>(nt, block, grid, shm, a, st);
+        return go_scalar<T>(nt, block, grid, shm, a, st);
     if (nregs <= 4)
         return go<T, 9, 4>(nt, block, grid, shm, a, st);
     if constexpr (sizeof(T) == 4)
@@ -403,6 +580,14 @@ static hipError_t go_t(bool scalar_only, int nregs, int nt, int block, int grid,
 }  // namespace su3k
 
 namespace su3i {
+
+int program_sites_per_lane(int arith, bool scalar_only)
+{
+    if (!scalar_only)
+        return 1;
+    return arith == F64 ? su3k::prog::kScalarSites<double>
+                        : su3k::prog::kScalarSites<float>;
+}
 
 hipError_t launch_program(int arith, bool scalar_only, int nregs, int nt,
                           int block, int grid, size_t shm, const ProgArgs &a,

@@ -62,9 +62,11 @@ struct ProgArgs {
 };
 
 // Arithmetic precision F64 (all fields F64) or F32 (F32 / C12 fields).
-// Programs with matrix values use at most 4 registers in F64 and 8 in F32;
-// scalar_only programs (no matrix value anywhere) at most 8 in either.
-// One site per lane; grid * block >= nsites.
+// Programs with matrix values use at most 4 registers in F64 and 8 in F32,
+// one site per lane; scalar_only programs (no matrix value anywhere) at
+// most 8 in either, program_sites_per_lane() sites per lane.  grid * block
+// * sites per lane >= nsites.
+int program_sites_per_lane(int arith, bool scalar_only);
 hipError_t launch_program(int arith, bool scalar_only, int nregs, int nt,
                           int block, int grid, size_t shm, const ProgArgs &a,
                           hipStream_t stream);
