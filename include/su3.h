@@ -153,10 +153,13 @@ typedef struct su3_program su3_program;
  *               result entry; 1: row-phased -- right-hand operands in
  *               full, then per result row the left operands' row, the
  *               row's evaluation and its stores.
- *               su3_dslash with one site per lane (lexicographic layouts):
- *               0 sites in index order; 1..3 each workgroup covers a 4D
- *               tile of sites, 8x4x2x(B/64), 4x4x4x(B/64), 8x2x2x(B/32)
- *               for block B                                              */
+ *               su3_dslash (lexicographic layouts): with one site per
+ *               lane, 0 takes sites in index order and 1..3 give each
+ *               workgroup a 4D tile of sites, 8x4x2x(B/64), 4x4x4x(B/64),
+ *               8x2x2x(B/32) for block B; 4 is the LDS-tiled walk: each
+ *               workgroup holds an 8x8x(B/64) tile of (x, y, z) sites and
+ *               walks tile_sites t-slices, sharing each slice's spinors
+ *               through LDS (B = 128 or 256; double spinors use 128)     */
 typedef struct su3_launch {
     int32_t block;
     int32_t persistent;

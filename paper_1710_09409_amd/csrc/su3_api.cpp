@@ -716,9 +716,12 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
         return fail(SU3_ERR_INVALID_ARG, "occupancy %d not in [0, 64]",
                     c.occupancy);
     if (expr == SU3_EXPR_DSLASH) {
-        if (c.schedule < 0 || c.schedule > 3)
+        if (c.schedule < 0 || c.schedule > 4)
             return fail(SU3_ERR_INVALID_ARG,
-                        "Dslash schedule (site tile) must be in [0, 3]");
+                        "Dslash schedule (site tile) must be in [0, 4]");
+        if (c.schedule == 4 && c.block != 128 && c.block != 256)
+            return fail(SU3_ERR_INVALID_ARG,
+                        "the LDS-tiled Dslash takes block 128 or 256");
     } else if (c.schedule < 0 || c.schedule > 1) {
         return fail(SU3_ERR_INVALID_ARG, "schedule must be 0 or 1");
     }
@@ -1063,10 +1066,12 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
                                    const su3_launch *forced = nullptr)
 {
     const su3_field *u0 = links[0];
-    const su3_launch c =
+    su3_launch c =
         forced ? *forced
                : lookup_launch(SU3_EXPR_DSLASH, u0->prec, u0->layout,
                                u0->lanes, u0->V);
+    if (c.schedule == 4 && out->prec == SU3_F64)
+        c.block = 128;  // double spinors: 8 x 8 x 2 tiles (48 KB of LDS)
     DslashArgs a;
     std::memset(&a, 0, sizeof a);
     a.out = out->ptr;
@@ -1100,7 +1105,18 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     const int64_t lanes = a.walk <= 1 ? out->V
                                       : a.stride[3] * ((Lt + a.walk - 1) / a.walk);
     int64_t grid = (lanes + c.block - 1) / c.block;
-    if (a.walk <= 1 && !vn && c.schedule > 0) {
+    if (!vn && c.schedule == 4) {
+        // LDS-tiled walk: 8 x 8 x (block / 64) tiles over (x, y, z)
+        a.lds_tile = 1;
+        a.walk = (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
+        const uint32_t tz = (uint32_t)c.block / 64u;
+        const uint32_t tdim[3] = {8u, 8u, tz};
+        grid = (Lt + a.walk - 1) / a.walk;
+        for (int mu = 0; mu < 3; ++mu) {
+            a.ntile[mu] = (uint32_t)((out->dims[mu] + tdim[mu] - 1) / tdim[mu]);
+            grid *= a.ntile[mu];
+        }
+    } else if (a.walk <= 1 && !vn && c.schedule > 0) {
         dslash_tile(c.schedule, c.block, a.tile);
         grid = 1;
         for (int mu = 0; mu < 4; ++mu) {
@@ -1108,10 +1124,12 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
             grid *= a.ntile[mu];
         }
     }
+    size_t shm = occupancy_reserve(out->device, c.occupancy);
+    if (a.lds_tile)  // the tile's two slice buffers (no occupancy cap)
+        shm = (size_t)2 * 12 * c.block * 2 * out->rbytes;
     hipError_t e = launch_dslash(out->prec, u0->prec, c.nontemporal, c.block,
-                                 (int)grid,
-                                 occupancy_reserve(out->device, c.occupancy),
-                                 a, static_cast<hipStream_t>(stream));
+                                 (int)grid, shm, a,
+                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(e, "Dslash kernel launch");
     return SU3_OK;
@@ -1503,6 +1521,17 @@ static std::vector<su3_launch> dslash_candidates()
                         c.xcd_remap = x;
                         out.push_back(c);
                     }
+    // LDS-tiled walks (block 256 is the 8 x 8 x 4 tile of single precision)
+    for (int walk : {4, 8, 16, 48})
+        for (int b : {128, 256})
+            for (int x : {0, 1}) {
+                c.tile_sites = walk;
+                c.schedule = 4;
+                c.block = b;
+                c.occupancy = 0;
+                c.xcd_remap = x;
+                out.push_back(c);
+            }
     return out;
 }
 

@@ -35,6 +35,9 @@ struct DslashArgs {
     // direction; tile[0] == 0 takes sites in index order
     uint32_t tile[4];
     uint32_t ntile[4];
+    // 1: LDS-tiled walk (8 x 8 x block/64 tiles of (x, y, z) sites, each
+    // workgroup walking `walk` t-slices; ntile[0..2] tiles per direction)
+    uint32_t lds_tile;
 };
 
 // Wilson hopping term: spinor precision F64 with F64 links, F32 with F32
@@ -42,7 +45,9 @@ struct DslashArgs {
 // walk > 1 (lexicographic site order only): one lane per (x, y, z) site
 // and chunk of `walk` t-slices,
 // grid * block >= stride[3] * ceil(dims[3] / walk).  With a tile:
-// grid = ntile[0] * ntile[1] * ntile[2] * ntile[3].
+// grid = ntile[0] * ntile[1] * ntile[2] * ntile[3].  LDS-tiled walk
+// (lds_tile = 1; block 128, or 256 for single-precision spinors): grid =
+// ntile[0] * ntile[1] * ntile[2] * ceil(dims[3] / walk).
 hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
                          int grid, size_t shm, const DslashArgs &a,
                          hipStream_t stream);

@@ -374,10 +374,186 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
         occupancy_reserve[threadIdx.x] = 0;
 }
 
+// ---------------------------------------------------------------------
+// LDS-tiled walk: a workgroup owns an 8 x 8 x TZ tile of (x, y, z) sites
+// (one lane each) and walks a chunk of t-slices.  Each step a lane loads
+// psi(x, t+1) for its forward t-hop and also writes it to an LDS buffer,
+// where it serves the tile's x, y and z hops of the next slice; only
+// neighbours across the tile's faces (and across the lattice's periodic
+// wrap) are read from global memory.  Two buffers and one barrier per
+// step: slice t is read from one while slice t+1 is written to the other.
+// Accumulation order and arithmetic as in the other Dslash kernels.
+
+template <int MU, int SP, int LP, int NT, int NS>
+__device__ __forceinline__ void hop_fwd_tile(const su3i::DslashArgs &a, uint32_t s,
+                                             uint32_t sf, bool in_tile, int lf,
+                                             const Cx<typename PrecT<SP>::T> (*tile)[NS],
+                                             Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    using T = typename PrecT<SP>::T;
+    Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+    if (in_tile) {
+#pragma unroll
+        for (int e = 0; e < 12; ++e)
+            p[e / 3][e % 3] = tile[e][lf];
+    } else {
+        load_spinor<SP, NT>(a.in, site_offset(a.gs, sf), a.gs.plane, p);
+    }
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, s), a.gl.plane, m);
+    project<MU, -1>(p, h);
+    color_mul<0>(m, h, w);
+    reconstruct<MU, -1>(w, acc);
+}
+
+template <int MU, int SP, int LP, int NT, int NS>
+__device__ __forceinline__ void hop_bwd_tile(const su3i::DslashArgs &a, uint32_t sb,
+                                             bool in_tile, int lb,
+                                             const Cx<typename PrecT<SP>::T> (*tile)[NS],
+                                             Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    using T = typename PrecT<SP>::T;
+    Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+    if (in_tile) {
+#pragma unroll
+        for (int e = 0; e < 12; ++e)
+            p[e / 3][e % 3] = tile[e][lb];
+    } else {
+        load_spinor<SP, NT>(a.in, site_offset(a.gs, sb), a.gs.plane, p);
+    }
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, sb), a.gl.plane, m);
+    project<MU, +1>(p, h);
+    color_mul<1>(m, h, w);
+    reconstruct<MU, +1>(w, acc);
+}
+
+template <int SP, int LP, int NT, int TZ>
+__global__ __launch_bounds__(64 * TZ) void k_dslash_lds(su3i::DslashArgs a)
+{
+    constexpr int TX = 8, TY = 8, NS = TX * TY * TZ;
+    using T = typename PrecT<SP>::T;
+    // the two slice buffers, [buffer][entry][site], in the dynamic LDS the
+    // host sizes to 2 * 12 * NS complex numbers
+    extern __shared__ char occupancy_reserve[];
+    Cx<T>(*tile)[12][NS] = reinterpret_cast<Cx<T>(*)[12][NS]>(occupancy_reserve);
+    const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
+                                     : blockIdx.x;
+    const uint32_t ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
+    const uint32_t chunk = blk / ntiles, tid = blk - chunk * ntiles;
+    const int l = threadIdx.x;
+    const int lx = l % TX, ly = (l / TX) % TY, lz = l / (TX * TY);
+    uint32_t c[3];
+    c[0] = (tid % a.ntile[0]) * TX + lx;
+    c[1] = (tid / a.ntile[0] % a.ntile[1]) * TY + ly;
+    c[2] = (tid / (a.ntile[0] * a.ntile[1])) * TZ + lz;
+    const bool valid = c[0] < a.dims[0] && c[1] < a.dims[1] && c[2] < a.dims[2];
+    const uint32_t V3 = a.stride[3], Lt = a.dims[3];
+    const uint32_t t0 = chunk * a.walk;
+    const uint32_t t1 = t0 + a.walk < Lt ? t0 + a.walk : Lt;
+    const uint32_t r = c[0] + a.dims[0] * (c[1] + a.dims[1] * c[2]);
+    // neighbours held by the tile (no periodic wrap, inside the lattice)
+    const bool xf = lx + 1 < TX && c[0] + 1 < a.dims[0], xb = lx > 0;
+    const bool yf = ly + 1 < TY && c[1] + 1 < a.dims[1], yb = ly > 0;
+    const bool zf = lz + 1 < TZ && c[2] + 1 < a.dims[2], zb = lz > 0;
+
+    Cx<T> wb[2][3], hc[2][3];
+    if (valid && t0 < Lt) {
+        {   // backward t-hop of slice t0
+            const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
+            Cx<T> p[4][3], m[9], h[2][3];
+            load_spinor<SP, NT>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
+            load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
+            project<3, +1>(p, h);
+            color_mul<1>(m, h, wb);
+        }
+        fence_acc(wb);
+        {   // psi(t0): P+ psi for the carry, and the tile's slice t0
+            Cx<T> p[4][3];
+            load_spinor<SP, NT>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
+            project<3, +1>(p, hc);
+#pragma unroll
+            for (int e = 0; e < 12; ++e)
+                tile[0][e][l] = p[e / 3][e % 3];
+        }
+        fence_acc(hc);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (uint32_t t = t0; t < t1; ++t) {
+        if (valid) {
+            const uint32_t s = r + V3 * t;
+            Cx<T> acc[4][3];
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    acc[sp][cc] = {T(0), T(0)};
+            reconstruct<3, +1>(wb, acc);
+            {   // forward t-hop; next slice's carry; next slice into LDS
+                const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
+                Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+                load_spinor<SP, NT>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
+                load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
+                project<3, -1>(p, h);
+                color_mul<0>(m, h, w);
+                reconstruct<3, -1>(w, acc);
+                color_mul<1>(m, hc, wb);
+                project<3, +1>(p, hc);
+#pragma unroll
+                for (int e = 0; e < 12; ++e)
+                    tile[cur ^ 1][e][l] = p[e / 3][e % 3];
+            }
+            fence_acc(acc);
+            fence_acc(wb);
+            fence_acc(hc);
+            const Cx<T>(*cur_tile)[NS] = tile[cur];
+            hop_fwd_tile<0, SP, LP, NT, NS>(a, s, fwd_site<0>(a, s, c[0], 0u), xf, l + 1,
+                                            cur_tile, acc);
+            fence_acc(acc);
+            hop_bwd_tile<0, SP, LP, NT, NS>(a, bwd_site<0>(a, s, c[0], 0u), xb, l - 1,
+                                            cur_tile, acc);
+            fence_acc(acc);
+            hop_fwd_tile<1, SP, LP, NT, NS>(a, s, fwd_site<1>(a, s, c[1], 0u), yf, l + TX,
+                                            cur_tile, acc);
+            fence_acc(acc);
+            hop_bwd_tile<1, SP, LP, NT, NS>(a, bwd_site<1>(a, s, c[1], 0u), yb, l - TX,
+                                            cur_tile, acc);
+            fence_acc(acc);
+            hop_fwd_tile<2, SP, LP, NT, NS>(a, s, fwd_site<2>(a, s, c[2], 0u), zf,
+                                            l + TX * TY, cur_tile, acc);
+            fence_acc(acc);
+            hop_bwd_tile<2, SP, LP, NT, NS>(a, bwd_site<2>(a, s, c[2], 0u), zb,
+                                            l - TX * TY, cur_tile, acc);
+            fence_acc(acc);
+            RawVec<SP, 1> raw[12];
+#pragma unroll
+            for (int e = 0; e < 12; ++e)
+                narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
+            store_entries<SP, 1, NT, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
+                                                  site_offset(a.gs, s), a.gs.plane, 1, raw);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
 template <int SP, int LP, int NT>
 static void go_nt(int block, int grid, size_t shm, const su3i::DslashArgs &a,
                   hipStream_t st)
 {
+    if (a.lds_tile) {
+        // block 64 * TZ: 128 (8 x 8 x 2), or 256 (8 x 8 x 4, single only)
+        if constexpr (SP != su3i::F64) {
+            if (block == 256) {
+                hipLaunchKernelGGL((k_dslash_lds<SP, LP, NT, 4>), dim3(grid), dim3(block),
+                                   shm, st, a);
+                return;
+            }
+        }
+        if (block == 128)
+            hipLaunchKernelGGL((k_dslash_lds<SP, LP, NT, 2>), dim3(grid), dim3(block), shm,
+                               st, a);
+        return;
+    }
     if (a.walk > 1)
         hipLaunchKernelGGL((k_dslash_walk<SP, LP, NT>), dim3(grid), dim3(block), shm, st, a);
     else
@@ -417,6 +593,8 @@ hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
     using namespace su3k::dslash;
     if (block > 256)
         return hipErrorInvalidValue;
+    if (a.lds_tile && !(block == 128 || (block == 256 && spinor_prec != F64)))
+        return hipErrorInvalidValue;  // the tile is 8 x 8 x (block / 64)
     if (spinor_prec == F64 && link_prec == F64)
         return go<F64, F64>(nt, block, grid, shm, a, st);
     if (spinor_prec == F32 && link_prec == F32)

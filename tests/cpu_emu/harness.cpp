@@ -241,13 +241,19 @@ int main(int argc, char **argv)
                     // one site per lane; walks of 3 t-slices; one walk over all of t;
                     // walks of 4 and 2 (ragged last walks)
                     // site tiles 8x4x2x2, 4x4x4x1, 8x2x2x8 (ragged against these lattices)
-                    su3_launch cs[8] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
-                                        {128, 0, 2, 0, 0, 4096, 0, 0}, {128, 0, 2, 1, 0, 4, 0, 0},
-                                        {64, 0, 2, 0, 0, 2, 0, 0}, {128, 0, 2, 1, 0, 1, 0, 1},
-                                        {64, 0, 2, 0, 0, 1, 0, 2}, {256, 0, 2, 1, 0, 1, 0, 3}};
-                    for (int k = 0; k < 8; ++k) {
+                    // LDS-tiled walks of 3 and of all of t, blocks 128 and 256
+                    // (run with one thread per lane: they synchronise)
+                    su3_launch cs[11] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
+                                         {128, 0, 2, 0, 0, 4096, 0, 0}, {128, 0, 2, 1, 0, 4, 0, 0},
+                                         {64, 0, 2, 0, 0, 2, 0, 0}, {128, 0, 2, 1, 0, 1, 0, 1},
+                                         {64, 0, 2, 0, 0, 1, 0, 2}, {256, 0, 2, 1, 0, 1, 0, 3},
+                                         {128, 0, 2, 0, 0, 3, 0, 4}, {256, 0, 2, 1, 0, 4096, 0, 4},
+                                         {128, 0, 3, 1, 0, 1, 0, 4}};
+                    for (int k = 0; k < 11; ++k) {
                         su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &cs[k]);
+                        emu_threaded = cs[k].schedule == 4;
                         if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
+                        emu_threaded = false;
                         su3_field_download(fout, k ? got1.data() : got.data(), nullptr);
                         if (k && memcmp(got.data(), got1.data(), 8 * 24 * V) != 0) { printf("dslash launch settings differ (%d)\n", k); fails++; }
                     }

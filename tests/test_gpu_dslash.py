@@ -104,7 +104,7 @@ def test_dslash_parity(pair, dims):
         prev = None
         # one site per lane; walks of 3 t-slices; one walk over all of t;
         # walks of 4 and 2; site tiles 8x4x2x2, 4x4x4x1, 8x2x2x8 (ragged
-        # against these lattices)
+        # against these lattices); LDS-tiled walks of 3 and of all of t
         for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1,
                          schedule=0),
                     dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3,
@@ -120,7 +120,11 @@ def test_dslash_parity(pair, dims):
                     dict(block=64, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=1,
                          schedule=2),
                     dict(block=256, nontemporal=2, occupancy=2, xcd_remap=1, tile_sites=1,
-                         schedule=3)):
+                         schedule=3),
+                    dict(block=128, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=3,
+                         schedule=4),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=4096,
+                         schedule=4)):
             full = dict(persistent=0, lds_stage=0, **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
