@@ -388,11 +388,16 @@ __device__ __forceinline__ void load_scalars(const ProgArgs &a, int k, uint32_t 
     if (a.kind[k] == su3i::FK_REAL) {
         const T *p = static_cast<const T *>(a.op[k]) + s0;
         if (cnt == S) {
-            using V = typename VecOf<T, S>::type;
-            const V w = vload<NT & 1>(reinterpret_cast<const V *>(p));
+            // 16-byte pieces
+            constexpr int W = 16 / sizeof(T);
+            using V = typename VecOf<T, W>::type;
 #pragma unroll
-            for (int j = 0; j < S; ++j)
-                r.v[j] = {w[j], T(0)};
+            for (int q = 0; q < S / W; ++q) {
+                const V w = vload<NT & 1>(reinterpret_cast<const V *>(p) + q);
+#pragma unroll
+                for (int j = 0; j < W; ++j)
+                    r.v[q * W + j] = {w[j], T(0)};
+            }
         } else {
 #pragma unroll
             for (int j = 0; j < S; ++j)
@@ -464,32 +469,32 @@ __device__ __forceinline__ void sput(RegFile<T, S, NR> &R, int i, const SReg<T, 
     }
 }
 
-template <class T, int S, int NT, int K = 0>
+template <class T, int S, int NR, int NT, int K = 0>
 __device__ __forceinline__ void sload_all(const ProgArgs &a, uint32_t s0, int cnt,
-                                          RegFile<T, S, 8> &R)
+                                          RegFile<T, S, NR> &R)
 {
-    if constexpr (K < 8) {
+    if constexpr (K < NR) {
         if (K < a.nops) {
             if ((a.used >> K) & 1) {
                 SReg<T, S> t;
                 load_scalars<T, S, NT>(a, K, s0, cnt, t);
-                sput<T, S, 8>(R, K, t);
+                sput<T, S, NR>(R, K, t);
             }
-            sload_all<T, S, NT, K + 1>(a, s0, cnt, R);
+            sload_all<T, S, NR, NT, K + 1>(a, s0, cnt, R);
         }
     }
 }
 
 // Registers here hold S sites' values (RegFile entries reused as S-wide).
-template <class T, int S, int NT>
+template <class T, int S, int NR, int NT>
 __global__ __launch_bounds__(256) void k_program_scalar(ProgArgs a)
 {
     extern __shared__ char occupancy_reserve[];
     const uint32_t s0 = (blockIdx.x * blockDim.x + threadIdx.x) * S;
     if (s0 < (uint32_t)a.nsites) {
         const int cnt = (uint32_t)a.nsites - s0 < (uint32_t)S ? int(a.nsites - s0) : S;
-        RegFile<T, S, 8> R;
-        sload_all<T, S, NT>(a, s0, cnt, R);
+        RegFile<T, S, NR> R;
+        sload_all<T, S, NR, NT>(a, s0, cnt, R);
         for (int pc = 0; pc < a.ninstr; ++pc) {
             const ProgInstr in = a.ins[pc];
             SReg<T, S> A, B, C;
@@ -503,12 +508,16 @@ __global__ __launch_bounds__(256) void k_program_scalar(ProgArgs a)
         if (a.zkind == su3i::FK_REAL) {
             T *p = static_cast<T *>(a.z) + s0;
             if (cnt == S) {
-                using V = typename VecOf<T, S>::type;
-                V w;
+                constexpr int W = 16 / sizeof(T);
+                using V = typename VecOf<T, W>::type;
 #pragma unroll
-                for (int j = 0; j < S; ++j)
-                    w[j] = Z.v[j].re;
-                vstore<NT & 2>(reinterpret_cast<V *>(p), w);
+                for (int q = 0; q < S / W; ++q) {
+                    V w;
+#pragma unroll
+                    for (int j = 0; j < W; ++j)
+                        w[j] = Z.v[q * W + j].re;
+                    vstore<NT & 2>(reinterpret_cast<V *>(p) + q, w);
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < S; ++j)
@@ -545,21 +554,22 @@ static hipError_t go(int nt, int block, int grid, size_t shm, const ProgArgs &a,
     return hipGetLastError();
 }
 
-// Sites per lane of scalar-only programs: 16-byte real accesses.
+// Sites per lane of scalar-only programs: 32 bytes of each real operand
+// (two 16-byte accesses).
 template <class T>
-constexpr int kScalarSites = 16 / sizeof(T);
+constexpr int kScalarSites = 32 / sizeof(T);
 
-template <class T>
+template <class T, int NR>
 static hipError_t go_scalar(int nt, int block, int grid, size_t shm,
                             const ProgArgs &a, hipStream_t st)
 {
     constexpr int S = kScalarSites<T>;
     if ((nt & 3) == 3)
-        hipLaunchKernelGGL((k_program_scalar<T, S, 3>), dim3(grid), dim3(block), shm, st, a);
+        hipLaunchKernelGGL((k_program_scalar<T, S, NR, 3>), dim3(grid), dim3(block), shm, st, a);
     else if ((nt & 3) == 2)
-        hipLaunchKernelGGL((k_program_scalar<T, S, 2>), dim3(grid), dim3(block), shm, st, a);
+        hipLaunchKernelGGL((k_program_scalar<T, S, NR, 2>), dim3(grid), dim3(block), shm, st, a);
     else
-        hipLaunchKernelGGL((k_program_scalar<T, S, 0>), dim3(grid), dim3(block), shm, st, a);
+        hipLaunchKernelGGL((k_program_scalar<T, S, NR, 0>), dim3(grid), dim3(block), shm, st, a);
     return hipGetLastError();
 }
 
@@ -568,7 +578,8 @@ static hipError_t go_t(bool scalar_only, int nregs, int nt, int block, int grid,
                        size_t shm, const ProgArgs &a, hipStream_t st)
 {
     if (scalar_only)
-        return go_scalar<T>(nt, block, grid, shm, a, st);
+        return nregs <= 4 ? go_scalar<T, 4>(nt, block, grid, shm, a, st)
+                          : go_scalar<T, 8>(nt, block, grid, shm, a, st);
     if (nregs <= 4)
         return go<T, 9, 4>(nt, block, grid, shm, a, st);
     if constexpr (sizeof(T) == 4)
