@@ -166,3 +166,53 @@ def test_vnode_rules():
     assert su3.su3_launch_get(su3.SU3_EXPR_MUL, su3.SU3_F64, su3.SU3_LAYOUT_VNODE, 16,
                               (8, 8, 8, 8)).as_dict() == cfg.as_dict()
     su3.su3_launch_reset()
+
+
+def test_vnode_full_size_matches_soa():
+    """48^4 in Grid's usual split of the two slowest directions (N_sub = 4):
+    the product and the Wilson hopping term on virtual-node fields equal,
+    bit for bit, the same operations on SoA fields (same arithmetic, other
+    storage order)."""
+    s = torch.cuda.current_stream()
+    dims, simd = (48, 48, 48, 48), (1, 1, 2, 2)
+    V = testgen.volume(dims)
+    x = testgen.su3_field(V, field_id=testgen.FID_X)
+    y = testgen.su3_field(V, field_id=testgen.FID_Y)
+    fx = vfield(dims, su3.SU3_F64, simd, x, s)
+    fy = vfield(dims, su3.SU3_F64, simd, y, s)
+    fz = su3.vnode_tensor(dims, su3.SU3_F64, simd)
+    su3.su3_mult(fz, fx, fy, s)
+    got = su3.su3_field_download(fz, s)
+    del fx, fy, fz
+    gx = su3.field_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+    gy = su3.field_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+    gz = su3.field_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+    su3.su3_field_upload(gx, x, s)
+    su3.su3_field_upload(gy, y, s)
+    su3.su3_mult(gz, gx, gy, s)
+    assert np.array_equal(got, su3.su3_field_download(gz, s))
+    del gx, gy, gz, x, y
+    torch.cuda.empty_cache()
+    # Dslash at 32^4 (the SoA launch may be any kernel variant)
+    dims = (32, 32, 32, 32)
+    V = testgen.volume(dims)
+    links = [testgen.su3_field(V, field_id=testgen.FID_U0 + mu) for mu in range(4)]
+    psi = testgen.spinor_field(V, field_id=200)
+    fu = [vfield(dims, su3.SU3_F64, simd, u, s) for u in links]
+    fin = vfield(dims, su3.SU3_F64, simd, psi, s, SP)
+    fout = su3.vnode_tensor(dims, su3.SU3_F64, simd, SP)
+    su3.su3_dslash(fout, fu, fin, s)
+    got = su3.su3_field_download(fout, s)
+    del fu, fin, fout
+    gu = []
+    for u in links:
+        f = su3.field_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+        su3.su3_field_upload(f, u, s)
+        gu.append(f)
+    gin = su3.spinor_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+    su3.su3_field_upload(gin, psi, s)
+    gout = su3.spinor_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+    su3.su3_autotune(su3.SU3_EXPR_DSLASH, su3.SU3_F64, su3.SU3_LAYOUT_SOA, 0, dims, s)
+    su3.su3_dslash(gout, gu, gin, s)
+    assert np.array_equal(got, su3.su3_field_download(gout, s))
+    su3.su3_launch_reset()
