@@ -134,11 +134,14 @@ typedef struct su3_program su3_program;
 
 /* How a compute call is launched.  Any valid setting gives bit-identical
  * results; only speed differs.
- *   block       lanes per workgroup: 64, 128 or 256
+ *   block       lanes per workgroup: 64, 128 or 256 (512: su3_dslash's
+ *               LDS-tiled walks)
  *   persistent  0: one lane per site group (one-shot grid); batches: one
  *               workgroup per tile.  k > 0: k workgroups per compute unit
  *               loop over the work (grid-stride over site groups or tiles)
  *   nontemporal bit 0: nontemporal loads, bit 1: nontemporal stores
+ *               (su3_dslash: bit 0 applies to link loads only; the
+ *               LDS-tiled walks always store nontemporal)
  *   xcd_remap   1: hand each of the 8 XCDs a contiguous range of
  *               workgroups instead of the hardware's round-robin
  *   lds_stage   AOS only: 1 stages each workgroup's sites through LDS with
@@ -156,10 +159,18 @@ typedef struct su3_program su3_program;
  *               su3_dslash (lexicographic layouts): with one site per
  *               lane, 0 takes sites in index order and 1..3 give each
  *               workgroup a 4D tile of sites, 8x4x2x(B/64), 4x4x4x(B/64),
- *               8x2x2x(B/32) for block B; 4 is the LDS-tiled walk: each
- *               workgroup holds an 8x8x(B/64) tile of (x, y, z) sites and
- *               walks tile_sites t-slices, sharing each slice's spinors
- *               through LDS (B = 128 or 256; double spinors use 128)     */
+ *               8x2x2x(B/32) for block B; 4..7 are LDS-tiled walks:
+ *               each workgroup holds a tile of (x, y, z) sites and walks
+ *               tile_sites t-slices, sharing each slice's spinors through
+ *               LDS: 4: 8x8x(B/64) with two slice buffers, 5: 8x8x(B/64),
+ *               6: 8x4x(B/32), 7: 16x8x(B/128), 8: 16x4x(B/64) with one
+ *               buffer; B = 128, 256 or 512 (6: 128 or 256, 7 and 8: 256
+ *               or 512), limited to 48 KiB of buffers (a larger tile falls
+ *               back to the schedule's smallest); 9..12 take whole x rows,
+ *               Lx x 2 x 2, Lx x 2 x 4, Lx x 4 x 2, Lx x 4 x 4, so that
+ *               every x hop comes from LDS (B is ignored: the workgroup
+ *               has one lane per tile site, at most 512 for double
+ *               spinors and 1024 for single, else 16x4x4 is used)       */
 typedef struct su3_launch {
     int32_t block;
     int32_t persistent;

@@ -686,9 +686,11 @@ static su3_launch default_launch(int expr, int prec, int layout)
 
 static su3_status check_launch(const su3_launch &c, int layout, int expr)
 {
-    if (c.block != 64 && c.block != 128 && c.block != 256)
-        return fail(SU3_ERR_INVALID_ARG, "block %d not in {64, 128, 256}",
-                    c.block);
+    const bool lds_walk = expr == SU3_EXPR_DSLASH && c.schedule >= 4;
+    if (c.block != 64 && c.block != 128 && c.block != 256 &&
+        !(lds_walk && c.block == 512))
+        return fail(SU3_ERR_INVALID_ARG, "block %d not in {64, 128, 256}%s",
+                    c.block, lds_walk ? " or 512" : "");
     if (c.persistent < 0 || c.persistent > 64)
         return fail(SU3_ERR_INVALID_ARG, "persistent %d not in [0, 64]",
                     c.persistent);
@@ -716,12 +718,14 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
         return fail(SU3_ERR_INVALID_ARG, "occupancy %d not in [0, 64]",
                     c.occupancy);
     if (expr == SU3_EXPR_DSLASH) {
-        if (c.schedule < 0 || c.schedule > 4)
+        LdsShape sh;
+        if (c.schedule < 0 || c.schedule > 12)
             return fail(SU3_ERR_INVALID_ARG,
-                        "Dslash schedule (site tile) must be in [0, 4]");
-        if (c.schedule == 4 && c.block != 128 && c.block != 256)
+                        "Dslash schedule (site tile) must be in [0, 12]");
+        if (lds_walk && c.schedule <= 8 && !lds_shape(c.schedule, c.block, 8, 0, sh))
             return fail(SU3_ERR_INVALID_ARG,
-                        "the LDS-tiled Dslash takes block 128 or 256");
+                        "the LDS-tiled Dslash (schedule %d) has no tile for "
+                        "block %d", c.schedule, c.block);
     } else if (c.schedule < 0 || c.schedule > 1) {
         return fail(SU3_ERR_INVALID_ARG, "schedule must be 0 or 1");
     }
@@ -1070,8 +1074,22 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
         forced ? *forced
                : lookup_launch(SU3_EXPR_DSLASH, u0->prec, u0->layout,
                                u0->lanes, u0->V);
-    if (c.schedule == 4 && out->prec == SU3_F64)
-        c.block = 128;  // double spinors: 8 x 8 x 2 tiles (48 KB of LDS)
+    const int cbytes = 2 * out->rbytes;  // one complex spinor entry
+    const bool vn = out->layout == SU3_LAYOUT_VNODE;
+    LdsShape sh = {0, 0, 0, 0};
+    const bool lds = !vn && c.schedule >= 4;
+    if (lds && !lds_shape(c.schedule, c.block, cbytes, (int)out->dims[0], sh)) {
+        // a tile too large for double spinors: the schedule's smallest;
+        // whole rows this lattice cannot take: 16 x 4 x 4
+        if (c.schedule >= 9)
+            c.schedule = 8;
+        c.block = c.schedule >= 7 ? 256 : 128;
+        lds_shape(c.schedule, c.block, cbytes, (int)out->dims[0], sh);
+    }
+    if (lds)
+        c.block = sh.tx * sh.ty * sh.tz;
+    else if (c.block > 256)
+        c.block = 256;  // the one-site and walk kernels take at most 256
     DslashArgs a;
     std::memset(&a, 0, sizeof a);
     a.out = out->ptr;
@@ -1083,7 +1101,6 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     a.nsites = (int32_t)out->V;
     a.xcd_remap = c.xcd_remap;
     // outer extents and strides (storage sites), lane counts and strides
-    const bool vn = out->layout == SU3_LAYOUT_VNODE;
     int64_t ostride = vn ? out->L : 1, lstride = 1;
     uint32_t lg = 0;
     while (vn && ((int64_t)1 << lg) < out->L)
@@ -1105,12 +1122,11 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     const int64_t lanes = a.walk <= 1 ? out->V
                                       : a.stride[3] * ((Lt + a.walk - 1) / a.walk);
     int64_t grid = (lanes + c.block - 1) / c.block;
-    if (!vn && c.schedule == 4) {
-        // LDS-tiled walk: 8 x 8 x (block / 64) tiles over (x, y, z)
-        a.lds_tile = 1;
+    if (lds) {
+        // LDS-tiled walk: tiles of (x, y, z) sites walking t
+        a.lds_tile = (uint32_t)c.schedule;
         a.walk = (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
-        const uint32_t tz = (uint32_t)c.block / 64u;
-        const uint32_t tdim[3] = {8u, 8u, tz};
+        const uint32_t tdim[3] = {(uint32_t)sh.tx, (uint32_t)sh.ty, (uint32_t)sh.tz};
         grid = (Lt + a.walk - 1) / a.walk;
         for (int mu = 0; mu < 3; ++mu) {
             a.ntile[mu] = (uint32_t)((out->dims[mu] + tdim[mu] - 1) / tdim[mu]);
@@ -1125,8 +1141,8 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
         }
     }
     size_t shm = occupancy_reserve(out->device, c.occupancy);
-    if (a.lds_tile)  // the tile's two slice buffers (no occupancy cap)
-        shm = (size_t)2 * 12 * c.block * 2 * out->rbytes;
+    if (a.lds_tile)  // the tile's slice buffers (no occupancy cap)
+        shm = lds_shape_bytes(sh, cbytes);
     hipError_t e = launch_dslash(out->prec, u0->prec, c.nontemporal, c.block,
                                  (int)grid, shm, a,
                                  static_cast<hipStream_t>(stream));
@@ -1503,8 +1519,10 @@ static std::vector<su3_launch> candidates(int layout)
 
 // Candidates for the Wilson hopping kernel: t-slices per lane (1: one
 // site per lane, in index order or in site tiles), block, occupancy cap,
-// XCD remapping (nontemporal stores, cached loads).
-static std::vector<su3_launch> dslash_candidates()
+// XCD remapping (nontemporal stores, cached spinor loads); LDS-tiled
+// walks of every tile that fits the precision (cbytes per complex entry)
+// and the lattice's x extent lx (whole-row tiles).
+static std::vector<su3_launch> dslash_candidates(int cbytes, int lx)
 {
     std::vector<su3_launch> out;
     su3_launch c = default_launch(SU3_EXPR_DSLASH, SU3_F64, SU3_LAYOUT_SOA);
@@ -1521,17 +1539,25 @@ static std::vector<su3_launch> dslash_candidates()
                         c.xcd_remap = x;
                         out.push_back(c);
                     }
-    // LDS-tiled walks (block 256 is the 8 x 8 x 4 tile of single precision)
-    for (int walk : {4, 8, 16, 48})
-        for (int b : {128, 256})
-            for (int x : {0, 1}) {
-                c.tile_sites = walk;
-                c.schedule = 4;
-                c.block = b;
-                c.occupancy = 0;
-                c.xcd_remap = x;
-                out.push_back(c);
-            }
+    // LDS-tiled walks: every tile shape that fits this spinor precision,
+    // with and without nontemporal link loads
+    for (int sched = 4; sched <= 12; ++sched)
+        for (int b : {128, 256, 512}) {
+            LdsShape sh;
+            if (!lds_shape(sched, b, cbytes, lx, sh) || (sched >= 9 && b != 256))
+                continue;
+            for (int walk : {4, 8, 16, 48})
+                for (int x : {0, 1})
+                    for (int nt : {2, 3}) {
+                        c.tile_sites = walk;
+                        c.schedule = sched;
+                        c.block = b;
+                        c.occupancy = 0;
+                        c.xcd_remap = x;
+                        c.nontemporal = nt;
+                        out.push_back(c);
+                    }
+        }
     return out;
 }
 
@@ -1641,7 +1667,7 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     if (st == SU3_OK) {
         const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
         su3_field *links[4] = {f[2], f[3], f[4], f[5]};
-        for (const su3_launch &c : dslash ? dslash_candidates()
+        for (const su3_launch &c : dslash ? dslash_candidates(2 * f[0]->rbytes, dims[0])
                                    : expr == SU3_EXPR_PROGRAM ? program_candidates()
                                                               : candidates(layout)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)

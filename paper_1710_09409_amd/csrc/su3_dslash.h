@@ -35,10 +35,68 @@ struct DslashArgs {
     // direction; tile[0] == 0 takes sites in index order
     uint32_t tile[4];
     uint32_t ntile[4];
-    // 1: LDS-tiled walk (8 x 8 x block/64 tiles of (x, y, z) sites, each
-    // workgroup walking `walk` t-slices; ntile[0..2] tiles per direction)
+    // LDS-tiled walk: the schedule (4..7) whose tile each workgroup holds
+    // (lds_shape), walking `walk` t-slices; ntile[0..2] tiles per
+    // direction.  0: no LDS tile
     uint32_t lds_tile;
 };
+
+// Tile of the LDS-tiled walk: tx x ty x tz (x, y, z) sites, one lane each,
+// and nb slice buffers in LDS (2: one barrier per slice, 1: two).
+struct LdsShape {
+    int tx, ty, tz, nb;
+};
+
+// Tile by schedule and block B:
+//   4: 8 x 8 x B/64, two buffers     5: 8 x 8 x B/64, one buffer
+//   6: 8 x 4 x B/32, one buffer      7: 16 x 8 x B/128, one buffer
+//   8: 16 x 4 x B/64, one buffer
+// A shape exists for block 128, 256 or 512 (schedule 6: 128 or 256,
+// schedules 7 and 8: 256 or 512) when its buffers, nb * 12 * B complex
+// numbers of cbytes bytes each, fit in 48 KiB of LDS.
+// Schedules 9..12 take whole x rows, lx x 2 x 2, lx x 2 x 4, lx x 4 x 2,
+// lx x 4 x 4 for the lattice's x extent lx, one buffer, B ignored (the
+// workgroup has lx * ty * tz lanes): they exist when that is at most 512
+// lanes for double spinors (1024 for single) and the buffer fits the
+// 160 KiB of LDS of a compute unit.
+inline bool lds_shape(int schedule, int block, int cbytes, int lx, LdsShape &s)
+{
+    if (schedule >= 9 && schedule <= 12) {
+        static const int rows[4][2] = {{2, 2}, {2, 4}, {4, 2}, {4, 4}};
+        s = {lx, rows[schedule - 9][0], rows[schedule - 9][1], 1};
+        const long lanes = (long)lx * s.ty * s.tz;
+        return lx > 0 && lanes <= (cbytes == 16 ? 512 : 1024) &&
+               lanes * 12 * cbytes <= 160 * 1024;
+    }
+    if (block != 128 && block != 256 && block != 512)
+        return false;
+    switch (schedule) {
+    case 4: s = {8, 8, block / 64, 2}; break;
+    case 5: s = {8, 8, block / 64, 1}; break;
+    case 6:
+        if (block > 256)
+            return false;
+        s = {8, 4, block / 32, 1};
+        break;
+    case 7:
+        if (block < 256)
+            return false;
+        s = {16, 8, block / 128, 1};
+        break;
+    case 8:
+        if (block < 256)
+            return false;
+        s = {16, 4, block / 64, 1};
+        break;
+    default: return false;
+    }
+    return (long)s.nb * 12 * block * cbytes <= 48 * 1024;
+}
+
+inline size_t lds_shape_bytes(const LdsShape &s, int cbytes)
+{
+    return (size_t)s.nb * 12 * s.tx * s.ty * s.tz * cbytes;
+}
 
 // Wilson hopping term: spinor precision F64 with F64 links, F32 with F32
 // or C12 links.  walk == 1: one site per lane, grid * block >= nsites;
@@ -46,8 +104,11 @@ struct DslashArgs {
 // and chunk of `walk` t-slices,
 // grid * block >= stride[3] * ceil(dims[3] / walk).  With a tile:
 // grid = ntile[0] * ntile[1] * ntile[2] * ntile[3].  LDS-tiled walk
-// (lds_tile = 1; block 128, or 256 for single-precision spinors): grid =
-// ntile[0] * ntile[1] * ntile[2] * ceil(dims[3] / walk).
+// (lds_tile = schedule with a shape for this block and spinor precision):
+// grid = ntile[0] * ntile[1] * ntile[2] * ceil(dims[3] / walk), shm =
+// lds_shape_bytes; its stores are always nontemporal.
+// Nontemporal bit 0 applies to link loads only: each spinor is read by
+// nine sites and stays cached.
 hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
                          int grid, size_t shm, const DslashArgs &a,
                          hipStream_t stream);

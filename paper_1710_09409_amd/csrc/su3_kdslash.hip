@@ -138,6 +138,15 @@ __device__ __forceinline__ void fence_acc(Cx<T> (&acc)[N][3])
             __asm__ volatile("" : "+v"(acc[sp][c].re), "+v"(acc[sp][c].im));
 }
 
+// Pass an index through an empty volatile asm: loads addressed by it stay
+// after the fences before it (the compiler cannot hoist them into an
+// earlier hop, where their registers would add to that hop's).
+__device__ __forceinline__ uint32_t pin(uint32_t x)
+{
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+
 // Forward hop (1 - gamma_mu) U_mu(x) psi(x + mu) from site sf.
 template <int MU, int SP, int LP, int NT>
 __device__ __forceinline__ void hop_fwd(const su3i::DslashArgs &a, uint32_t s,
@@ -146,8 +155,8 @@ __device__ __forceinline__ void hop_fwd(const su3i::DslashArgs &a, uint32_t s,
 {
     using T = typename PrecT<SP>::T;
     Cx<T> p[4][3], m[9], h[2][3], w[2][3];
-    load_spinor<SP, NT>(a.in, site_offset(a.gs, sf), a.gs.plane, p);
-    load_link<LP, NT>(a.u[MU], site_offset(a.gl, s), a.gl.plane, m);
+    load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, pin(sf)), a.gs.plane, p);
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, pin(s)), a.gl.plane, m);
     project<MU, -1>(p, h);
     color_mul<0>(m, h, w);
     reconstruct<MU, -1>(w, acc);
@@ -160,8 +169,9 @@ __device__ __forceinline__ void hop_bwd(const su3i::DslashArgs &a, uint32_t sb,
 {
     using T = typename PrecT<SP>::T;
     Cx<T> p[4][3], m[9], h[2][3], w[2][3];
-    load_spinor<SP, NT>(a.in, site_offset(a.gs, sb), a.gs.plane, p);
-    load_link<LP, NT>(a.u[MU], site_offset(a.gl, sb), a.gl.plane, m);
+    const uint32_t sbp = pin(sb);
+    load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sbp), a.gs.plane, p);
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, sbp), a.gl.plane, m);
     project<MU, +1>(p, h);
     color_mul<1>(m, h, w);
     reconstruct<MU, +1>(w, acc);
@@ -269,16 +279,15 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
                 acc[sp][cc] = {T(0), T(0)};
-        // accumulation order shared with the walk kernel (results are
-        // bitwise independent of the launch): t backward, t forward,
-        // then x, y, z (forward, backward)
+        // accumulation order shared with the walk kernels (results are
+        // bitwise independent of the launch): t backward, then x, y, z
+        // (forward, backward), then t forward
         hop_bwd<3, SP, LP, NT>(a, bwd_site<3>(a, s, c[3], l[3]), acc);
-        fence_acc(acc);
-        hop_fwd<3, SP, LP, NT>(a, s, fwd_site<3>(a, s, c[3], l[3]), acc);
         fence_acc(acc);
         hop<0, SP, LP, NT>(a, s, c[0], l[0], acc);
         hop<1, SP, LP, NT>(a, s, c[1], l[1], acc);
         hop<2, SP, LP, NT>(a, s, c[2], l[2], acc);
+        hop_fwd<3, SP, LP, NT>(a, s, fwd_site<3>(a, s, c[3], l[3]), acc);
         RawVec<SP, 1> raw[12];
 #pragma unroll
         for (int e = 0; e < 12; ++e)
@@ -298,8 +307,10 @@ __global__ __launch_bounds__(256, WPE) void k_dslash(su3i::DslashArgs a)
 //   wb(t+1) = U_t(t)^dagger (P+ psi(t)),  hc = P+ psi(t+1),
 // carrying two half spinors (wb, hc) between slices.  The x, y, z hops
 // are the one-site hops; their neighbours are loaded by adjacent lanes at
-// about the same time and come from cache.
-template <int SP, int LP, int NT, int WPE = (SP == su3i::F64 || LP == su3i::C12) ? 3 : 4>
+// about the same time and come from cache.  The result of slice t is
+// stored after its forward t-hop (x, y, z hops first: the accumulation
+// order of the one-site kernel).
+template <int SP, int LP, int NT, int WPE = SP == su3i::F64 ? 2 : LP == su3i::C12 ? 3 : 4>
 __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
 {
     extern __shared__ char occupancy_reserve[];
@@ -324,7 +335,7 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
         {   // backward t-hop of slice t0 and P+ psi(t0)
             const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
             Cx<T> p[4][3], m[9], h[2][3];
-            load_spinor<SP, NT>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
+            load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
             load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
             project<3, +1>(p, h);
             color_mul<1>(m, h, wb);
@@ -332,7 +343,7 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
         fence_acc(wb);
         {
             Cx<T> p[4][3];
-            load_spinor<SP, NT>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
+            load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
             project<3, +1>(p, hc);
         }
         fence_acc(hc);
@@ -345,29 +356,32 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
                 for (int cc = 0; cc < 3; ++cc)
                     acc[sp][cc] = {T(0), T(0)};
             reconstruct<3, +1>(wb, acc);
-            {   // forward t-hop; next slice's backward t-hop and P+ psi
+            fence_acc(acc);
+            hop<0, SP, LP, NT>(a, s, c[0], 0u, acc);
+            hop<1, SP, LP, NT>(a, s, c[1], 0u, acc);
+            hop<2, SP, LP, NT>(a, s, c[2], 0u, acc);
+            {   // forward t-hop and the result; then from the same
+                // registers the next slice's backward t-hop and P+ psi
                 const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
                 Cx<T> p[4][3], m[9], h[2][3], w[2][3];
-                load_spinor<SP, NT>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
+                load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
                 load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
                 project<3, -1>(p, h);
                 color_mul<0>(m, h, w);
                 reconstruct<3, -1>(w, acc);
+                fence_acc(acc);
+                RawVec<SP, 1> raw[12];
+#pragma unroll
+                for (int e = 0; e < 12; ++e)
+                    narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
+                store_entries<SP, 1, NT, true, 0, 12>(
+                    static_cast<typename PrecT<SP>::R *>(a.out), site_offset(a.gs, s),
+                    a.gs.plane, 1, raw);
                 color_mul<1>(m, hc, wb);
                 project<3, +1>(p, hc);
             }
-            fence_acc(acc);
             fence_acc(wb);
             fence_acc(hc);
-            hop<0, SP, LP, NT>(a, s, c[0], 0u, acc);
-            hop<1, SP, LP, NT>(a, s, c[1], 0u, acc);
-            hop<2, SP, LP, NT>(a, s, c[2], 0u, acc);
-            RawVec<SP, 1> raw[12];
-#pragma unroll
-            for (int e = 0; e < 12; ++e)
-                narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
-            store_entries<SP, 1, NT, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
-                                                  site_offset(a.gs, s), a.gs.plane, 1, raw);
         }
     }
     if (a.nsites < 0)
@@ -375,29 +389,35 @@ __global__ __launch_bounds__(256, WPE) void k_dslash_walk(su3i::DslashArgs a)
 }
 
 // ---------------------------------------------------------------------
-// LDS-tiled walk: a workgroup owns an 8 x 8 x TZ tile of (x, y, z) sites
+// LDS-tiled walk: a workgroup owns a TX x TY x TZ tile of (x, y, z) sites
 // (one lane each) and walks a chunk of t-slices.  Each step a lane loads
-// psi(x, t+1) for its forward t-hop and also writes it to an LDS buffer,
-// where it serves the tile's x, y and z hops of the next slice; only
-// neighbours across the tile's faces (and across the lattice's periodic
-// wrap) are read from global memory.  Two buffers and one barrier per
-// step: slice t is read from one while slice t+1 is written to the other.
-// Accumulation order and arithmetic as in the other Dslash kernels.
+// psi(x, t+1) for its forward t-hop and also writes it to LDS, where it
+// serves the tile's x, y and z hops of the next slice; only neighbours
+// across the tile's faces (and across the lattice's periodic wrap) are
+// read from global memory.  TX = 0: the tile spans whole x rows (TX is
+// the lattice's x extent) and the x hops, periodic wrap included, all
+// come from LDS.  NB = 2: two slice buffers and one barrier per step
+// (slice t is read from one while slice t+1 is written to the other);
+// NB = 1: one buffer, a barrier after the x, y, z hops and one after the
+// write.  Accumulation order and arithmetic as in the other Dslash kernels.
+// LDS layout: [buffer][entry][site of the tile], ns sites per entry.
 
-template <int MU, int SP, int LP, int NT, int NS>
+template <int MU, int SP, int LP, int NT>
 __device__ __forceinline__ void hop_fwd_tile(const su3i::DslashArgs &a, uint32_t s,
                                              uint32_t sf, bool in_tile, int lf,
-                                             const Cx<typename PrecT<SP>::T> (*tile)[NS],
+                                             const Cx<typename PrecT<SP>::T> *tile, int ns,
                                              Cx<typename PrecT<SP>::T> (&acc)[4][3])
 {
     using T = typename PrecT<SP>::T;
     Cx<T> p[4][3], m[9], h[2][3], w[2][3];
     if (in_tile) {
+        // the LDS address is formed here, not hoisted out of the walk
+        const Cx<T> *q = tile + pin((uint32_t)lf);
 #pragma unroll
         for (int e = 0; e < 12; ++e)
-            p[e / 3][e % 3] = tile[e][lf];
+            p[e / 3][e % 3] = q[e * ns];
     } else {
-        load_spinor<SP, NT>(a.in, site_offset(a.gs, sf), a.gs.plane, p);
+        load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sf), a.gs.plane, p);
     }
     load_link<LP, NT>(a.u[MU], site_offset(a.gl, s), a.gl.plane, m);
     project<MU, -1>(p, h);
@@ -405,20 +425,21 @@ __device__ __forceinline__ void hop_fwd_tile(const su3i::DslashArgs &a, uint32_t
     reconstruct<MU, -1>(w, acc);
 }
 
-template <int MU, int SP, int LP, int NT, int NS>
+template <int MU, int SP, int LP, int NT>
 __device__ __forceinline__ void hop_bwd_tile(const su3i::DslashArgs &a, uint32_t sb,
                                              bool in_tile, int lb,
-                                             const Cx<typename PrecT<SP>::T> (*tile)[NS],
+                                             const Cx<typename PrecT<SP>::T> *tile, int ns,
                                              Cx<typename PrecT<SP>::T> (&acc)[4][3])
 {
     using T = typename PrecT<SP>::T;
     Cx<T> p[4][3], m[9], h[2][3], w[2][3];
     if (in_tile) {
+        const Cx<T> *q = tile + pin((uint32_t)lb);
 #pragma unroll
         for (int e = 0; e < 12; ++e)
-            p[e / 3][e % 3] = tile[e][lb];
+            p[e / 3][e % 3] = q[e * ns];
     } else {
-        load_spinor<SP, NT>(a.in, site_offset(a.gs, sb), a.gs.plane, p);
+        load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sb), a.gs.plane, p);
     }
     load_link<LP, NT>(a.u[MU], site_offset(a.gl, sb), a.gl.plane, m);
     project<MU, +1>(p, h);
@@ -426,23 +447,34 @@ __device__ __forceinline__ void hop_bwd_tile(const su3i::DslashArgs &a, uint32_t
     reconstruct<MU, +1>(w, acc);
 }
 
-template <int SP, int LP, int NT, int TZ>
-__global__ __launch_bounds__(64 * TZ) void k_dslash_lds(su3i::DslashArgs a)
+// Most lanes a workgroup of the LDS-tiled walk has (whole-row tiles have
+// the lattice's x extent times TY * TZ).
+template <int SP, int TX, int TY, int TZ>
+constexpr int lds_max_lanes()
 {
-    constexpr int TX = 8, TY = 8, NS = TX * TY * TZ;
+    return TX ? TX * TY * TZ : (SP == su3i::F64 ? 512 : 1024);
+}
+
+template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB>
+__global__ __launch_bounds__(TX ? TX * TY * TZ : (SP == su3i::F64 ? 512 : 1024),
+                             SP == su3i::F64 ? 2 : 4)
+void k_dslash_lds(su3i::DslashArgs a)
+{
     using T = typename PrecT<SP>::T;
-    // the two slice buffers, [buffer][entry][site], in the dynamic LDS the
-    // host sizes to 2 * 12 * NS complex numbers
+    const int tx = TX ? TX : (int)a.dims[0];
+    const int ns = tx * TY * TZ;
+    // the slice buffers in the dynamic LDS the host sizes to NB * 12 * ns
+    // complex numbers
     extern __shared__ char occupancy_reserve[];
-    Cx<T>(*tile)[12][NS] = reinterpret_cast<Cx<T>(*)[12][NS]>(occupancy_reserve);
+    Cx<T> *tile = reinterpret_cast<Cx<T> *>(occupancy_reserve);
     const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
                                      : blockIdx.x;
     const uint32_t ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
     const uint32_t chunk = blk / ntiles, tid = blk - chunk * ntiles;
     const int l = threadIdx.x;
-    const int lx = l % TX, ly = (l / TX) % TY, lz = l / (TX * TY);
+    const int lx = l % tx, ly = (l / tx) % TY, lz = l / (tx * TY);
     uint32_t c[3];
-    c[0] = (tid % a.ntile[0]) * TX + lx;
+    c[0] = (tid % a.ntile[0]) * tx + lx;
     c[1] = (tid / a.ntile[0] % a.ntile[1]) * TY + ly;
     c[2] = (tid / (a.ntile[0] * a.ntile[1])) * TZ + lz;
     const bool valid = c[0] < a.dims[0] && c[1] < a.dims[1] && c[2] < a.dims[2];
@@ -450,8 +482,12 @@ __global__ __launch_bounds__(64 * TZ) void k_dslash_lds(su3i::DslashArgs a)
     const uint32_t t0 = chunk * a.walk;
     const uint32_t t1 = t0 + a.walk < Lt ? t0 + a.walk : Lt;
     const uint32_t r = c[0] + a.dims[0] * (c[1] + a.dims[1] * c[2]);
-    // neighbours held by the tile (no periodic wrap, inside the lattice)
-    const bool xf = lx + 1 < TX && c[0] + 1 < a.dims[0], xb = lx > 0;
+    // neighbours held by the tile (no periodic wrap, inside the lattice;
+    // whole rows hold both x neighbours, across the wrap too)
+    const bool xf = TX ? lx + 1 < TX && c[0] + 1 < a.dims[0] : true;
+    const bool xb = TX ? lx > 0 : true;
+    const int lxf = TX || lx + 1 < tx ? l + 1 : l - (tx - 1);
+    const int lxb = TX || lx > 0 ? l - 1 : l + (tx - 1);
     const bool yf = ly + 1 < TY && c[1] + 1 < a.dims[1], yb = ly > 0;
     const bool zf = lz + 1 < TZ && c[2] + 1 < a.dims[2], zb = lz > 0;
 
@@ -460,7 +496,7 @@ __global__ __launch_bounds__(64 * TZ) void k_dslash_lds(su3i::DslashArgs a)
         {   // backward t-hop of slice t0
             const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
             Cx<T> p[4][3], m[9], h[2][3];
-            load_spinor<SP, NT>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
+            load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
             load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
             project<3, +1>(p, h);
             color_mul<1>(m, h, wb);
@@ -468,92 +504,138 @@ __global__ __launch_bounds__(64 * TZ) void k_dslash_lds(su3i::DslashArgs a)
         fence_acc(wb);
         {   // psi(t0): P+ psi for the carry, and the tile's slice t0
             Cx<T> p[4][3];
-            load_spinor<SP, NT>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
+            load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
             project<3, +1>(p, hc);
 #pragma unroll
             for (int e = 0; e < 12; ++e)
-                tile[0][e][l] = p[e / 3][e % 3];
+                tile[e * ns + l] = p[e / 3][e % 3];
         }
         fence_acc(hc);
     }
     __syncthreads();
     int cur = 0;
     for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t s = r + V3 * t;
+        Cx<T> acc[4][3];
         if (valid) {
-            const uint32_t s = r + V3 * t;
-            Cx<T> acc[4][3];
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc)
                     acc[sp][cc] = {T(0), T(0)};
             reconstruct<3, +1>(wb, acc);
+            fence_acc(acc);
+            const Cx<T> *cur_tile = tile + cur * 12 * ns;
+            hop_fwd_tile<0, SP, LP, NT>(a, s, fwd_site<0>(a, s, c[0], 0u), xf, lxf,
+                                        cur_tile, ns, acc);
+            fence_acc(acc);
+            hop_bwd_tile<0, SP, LP, NT>(a, bwd_site<0>(a, s, c[0], 0u), xb, lxb, cur_tile,
+                                        ns, acc);
+            fence_acc(acc);
+            hop_fwd_tile<1, SP, LP, NT>(a, s, fwd_site<1>(a, s, c[1], 0u), yf, l + tx,
+                                        cur_tile, ns, acc);
+            fence_acc(acc);
+            hop_bwd_tile<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], 0u), yb, l - tx, cur_tile,
+                                        ns, acc);
+            fence_acc(acc);
+            hop_fwd_tile<2, SP, LP, NT>(a, s, fwd_site<2>(a, s, c[2], 0u), zf, l + tx * TY,
+                                        cur_tile, ns, acc);
+            fence_acc(acc);
+            hop_bwd_tile<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], 0u), zb, l - tx * TY,
+                                        cur_tile, ns, acc);
+            fence_acc(acc);
+        }
+        if constexpr (NB == 1)
+            __syncthreads();  // slice t read by the whole tile
+        if (valid) {
             {   // forward t-hop; next slice's carry; next slice into LDS
                 const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
                 Cx<T> p[4][3], m[9], h[2][3], w[2][3];
-                load_spinor<SP, NT>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
+                load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
                 load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
                 project<3, -1>(p, h);
                 color_mul<0>(m, h, w);
                 reconstruct<3, -1>(w, acc);
                 color_mul<1>(m, hc, wb);
                 project<3, +1>(p, hc);
+                Cx<T> *next = tile + (NB == 1 ? 0 : (cur ^ 1) * 12 * ns);
 #pragma unroll
                 for (int e = 0; e < 12; ++e)
-                    tile[cur ^ 1][e][l] = p[e / 3][e % 3];
+                    next[e * ns + l] = p[e / 3][e % 3];
             }
             fence_acc(acc);
             fence_acc(wb);
             fence_acc(hc);
-            const Cx<T>(*cur_tile)[NS] = tile[cur];
-            hop_fwd_tile<0, SP, LP, NT, NS>(a, s, fwd_site<0>(a, s, c[0], 0u), xf, l + 1,
-                                            cur_tile, acc);
-            fence_acc(acc);
-            hop_bwd_tile<0, SP, LP, NT, NS>(a, bwd_site<0>(a, s, c[0], 0u), xb, l - 1,
-                                            cur_tile, acc);
-            fence_acc(acc);
-            hop_fwd_tile<1, SP, LP, NT, NS>(a, s, fwd_site<1>(a, s, c[1], 0u), yf, l + TX,
-                                            cur_tile, acc);
-            fence_acc(acc);
-            hop_bwd_tile<1, SP, LP, NT, NS>(a, bwd_site<1>(a, s, c[1], 0u), yb, l - TX,
-                                            cur_tile, acc);
-            fence_acc(acc);
-            hop_fwd_tile<2, SP, LP, NT, NS>(a, s, fwd_site<2>(a, s, c[2], 0u), zf,
-                                            l + TX * TY, cur_tile, acc);
-            fence_acc(acc);
-            hop_bwd_tile<2, SP, LP, NT, NS>(a, bwd_site<2>(a, s, c[2], 0u), zb,
-                                            l - TX * TY, cur_tile, acc);
-            fence_acc(acc);
             RawVec<SP, 1> raw[12];
 #pragma unroll
             for (int e = 0; e < 12; ++e)
                 narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
-            store_entries<SP, 1, NT, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
-                                                  site_offset(a.gs, s), a.gs.plane, 1, raw);
+            store_entries<SP, 1, 2, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
+                                                 site_offset(a.gs, s), a.gs.plane, 1, raw);
         }
         __syncthreads();
-        cur ^= 1;
+        if constexpr (NB == 2)
+            cur ^= 1;
     }
+}
+
+template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB>
+static hipError_t launch_lds(int block, int grid, size_t shm, const su3i::DslashArgs &a,
+                             hipStream_t st)
+{
+    auto *k = k_dslash_lds<SP, LP, NT, TX, TY, TZ, NB>;
+    if (block > lds_max_lanes<SP, TX, TY, TZ>())
+        return hipErrorInvalidValue;
+    if (shm > 64 * 1024) {
+        // beyond the default dynamic LDS of a workgroup
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shm);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, a);
+    return hipGetLastError();
+}
+
+// The LDS-tiled walk by schedule and block (the shapes lds_shape accepts;
+// those over 48 KiB of double-precision buffers are not instantiated).
+template <int SP, int LP, int NT>
+static hipError_t go_lds(int block, int grid, size_t shm, const su3i::DslashArgs &a,
+                         hipStream_t st)
+{
+    constexpr bool single = SP != su3i::F64;
+    const int b = a.lds_tile >= 9 ? 0 : block;  // whole rows: any lane count
+    switch (a.lds_tile * 2048 + b) {
+    case 4 * 2048 + 128: return launch_lds<SP, LP, NT, 8, 8, 2, 2>(block, grid, shm, a, st);
+    case 5 * 2048 + 128: return launch_lds<SP, LP, NT, 8, 8, 2, 1>(block, grid, shm, a, st);
+    case 5 * 2048 + 256: return launch_lds<SP, LP, NT, 8, 8, 4, 1>(block, grid, shm, a, st);
+    case 6 * 2048 + 128: return launch_lds<SP, LP, NT, 8, 4, 4, 1>(block, grid, shm, a, st);
+    case 6 * 2048 + 256: return launch_lds<SP, LP, NT, 8, 4, 8, 1>(block, grid, shm, a, st);
+    case 7 * 2048 + 256: return launch_lds<SP, LP, NT, 16, 8, 2, 1>(block, grid, shm, a, st);
+    case 8 * 2048 + 256: return launch_lds<SP, LP, NT, 16, 4, 4, 1>(block, grid, shm, a, st);
+    case 9 * 2048: return launch_lds<SP, LP, NT, 0, 2, 2, 1>(block, grid, shm, a, st);
+    case 10 * 2048: return launch_lds<SP, LP, NT, 0, 2, 4, 1>(block, grid, shm, a, st);
+    case 11 * 2048: return launch_lds<SP, LP, NT, 0, 4, 2, 1>(block, grid, shm, a, st);
+    case 12 * 2048: return launch_lds<SP, LP, NT, 0, 4, 4, 1>(block, grid, shm, a, st);
+    default: break;
+    }
+    if constexpr (single) {
+        switch (a.lds_tile * 2048 + b) {
+        case 4 * 2048 + 256: return launch_lds<SP, LP, NT, 8, 8, 4, 2>(block, grid, shm, a, st);
+        case 5 * 2048 + 512: return launch_lds<SP, LP, NT, 8, 8, 8, 1>(block, grid, shm, a, st);
+        case 7 * 2048 + 512: return launch_lds<SP, LP, NT, 16, 8, 4, 1>(block, grid, shm, a, st);
+        case 8 * 2048 + 512: return launch_lds<SP, LP, NT, 16, 4, 8, 1>(block, grid, shm, a, st);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int SP, int LP, int NT>
 static void go_nt(int block, int grid, size_t shm, const su3i::DslashArgs &a,
                   hipStream_t st)
 {
-    if (a.lds_tile) {
-        // block 64 * TZ: 128 (8 x 8 x 2), or 256 (8 x 8 x 4, single only)
-        if constexpr (SP != su3i::F64) {
-            if (block == 256) {
-                hipLaunchKernelGGL((k_dslash_lds<SP, LP, NT, 4>), dim3(grid), dim3(block),
-                                   shm, st, a);
-                return;
-            }
-        }
-        if (block == 128)
-            hipLaunchKernelGGL((k_dslash_lds<SP, LP, NT, 2>), dim3(grid), dim3(block), shm,
-                               st, a);
-        return;
-    }
     if (a.walk > 1)
         hipLaunchKernelGGL((k_dslash_walk<SP, LP, NT>), dim3(grid), dim3(block), shm, st, a);
     else
@@ -564,6 +646,9 @@ template <int SP, int LP>
 static hipError_t go(int nt, int block, int grid, size_t shm, const su3i::DslashArgs &a,
                      hipStream_t st)
 {
+    if (a.lds_tile)  // nontemporal stores always; bit 0: nontemporal link loads
+        return (nt & 1) ? go_lds<SP, LP, 3>(block, grid, shm, a, st)
+                        : go_lds<SP, LP, 2>(block, grid, shm, a, st);
     switch (nt & 3) {
     case 0:
         go_nt<SP, LP, 0>(block, grid, shm, a, st);
@@ -591,10 +676,15 @@ hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
                          hipStream_t st)
 {
     using namespace su3k::dslash;
-    if (block > 256)
+    if (a.lds_tile) {
+        LdsShape sh;
+        const int cbytes = spinor_prec == F64 ? 16 : 8;
+        if (!lds_shape((int)a.lds_tile, block, cbytes, (int)a.dims[0], sh) ||
+            block != sh.tx * sh.ty * sh.tz || shm < lds_shape_bytes(sh, cbytes))
+            return hipErrorInvalidValue;
+    } else if (block > 256) {
         return hipErrorInvalidValue;
-    if (a.lds_tile && !(block == 128 || (block == 256 && spinor_prec != F64)))
-        return hipErrorInvalidValue;  // the tile is 8 x 8 x (block / 64)
+    }
     if (spinor_prec == F64 && link_prec == F64)
         return go<F64, F64>(nt, block, grid, shm, a, st);
     if (spinor_prec == F32 && link_prec == F32)

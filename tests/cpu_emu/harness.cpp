@@ -242,16 +242,26 @@ int main(int argc, char **argv)
                     // walks of 4 and 2 (ragged last walks)
                     // site tiles 8x4x2x2, 4x4x4x1, 8x2x2x8 (ragged against these lattices)
                     // LDS-tiled walks of 3 and of all of t, blocks 128 and 256
-                    // (run with one thread per lane: they synchronise)
-                    su3_launch cs[11] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
+                    // (run with one thread per lane: they synchronise); the
+                    // other tiles (one buffer: 8x8, 8x4, 16x8, 16x4, blocks up to
+                    // 512, walks of 2, 3, 5 and all of t); whole x rows
+                    // (x hops and their wrap from LDS)
+                    su3_launch cs[24] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
                                          {128, 0, 2, 0, 0, 4096, 0, 0}, {128, 0, 2, 1, 0, 4, 0, 0},
                                          {64, 0, 2, 0, 0, 2, 0, 0}, {128, 0, 2, 1, 0, 1, 0, 1},
                                          {64, 0, 2, 0, 0, 1, 0, 2}, {256, 0, 2, 1, 0, 1, 0, 3},
                                          {128, 0, 2, 0, 0, 3, 0, 4}, {256, 0, 2, 1, 0, 4096, 0, 4},
-                                         {128, 0, 3, 1, 0, 1, 0, 4}};
-                    for (int k = 0; k < 11; ++k) {
+                                         {128, 0, 3, 1, 0, 1, 0, 4},
+                                         {128, 0, 3, 0, 0, 3, 0, 5}, {256, 0, 2, 1, 0, 4096, 0, 5},
+                                         {512, 0, 2, 0, 0, 2, 0, 5}, {128, 0, 2, 1, 0, 5, 0, 6},
+                                         {256, 0, 3, 0, 0, 4096, 0, 6}, {256, 0, 2, 0, 0, 3, 0, 7},
+                                         {512, 0, 3, 1, 0, 4096, 0, 7}, {256, 0, 2, 1, 0, 3, 0, 8},
+                                         {512, 0, 2, 0, 0, 4096, 0, 8}, {64, 0, 2, 0, 0, 3, 0, 9},
+                                         {256, 0, 3, 1, 0, 4096, 0, 10}, {128, 0, 2, 0, 0, 2, 0, 11},
+                                         {256, 0, 2, 1, 0, 5, 0, 12}};
+                    for (int k = 0; k < 24; ++k) {
                         su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &cs[k]);
-                        emu_threaded = cs[k].schedule == 4;
+                        emu_threaded = cs[k].schedule >= 4;
                         if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("dslash %s\n", su3_last_error()); fails++; }
                         emu_threaded = false;
                         su3_field_download(fout, k ? got1.data() : got.data(), nullptr);
@@ -290,6 +300,28 @@ int main(int argc, char **argv)
         };
         for (auto &x : v)
             if (x.got != x.want) { printf("dslash validation %s: got %d want %d\n", x.what, x.got, x.want); fails++; }
+        // every LDS-tiled launch the table accepts runs, in both spinor
+        // precisions (a tile too large for doubles falls back)
+        {
+            su3_field *u32[4], *s32b;
+            for (int mu = 0; mu < 4; ++mu) su3_field_alloc(&u32[mu], d, SU3_F32, SU3_LAYOUT_SOA, 0);
+            su3_spinor_alloc(&s32b, d, SU3_F32, SU3_LAYOUT_SOA, 0);
+            for (int sched = 4; sched <= 13; ++sched)
+                for (int b : {64, 128, 256, 512, 1024})
+                    for (int lp : {0, 1}) {
+                        su3_launch c = {b, 0, 2, 0, 0, 2, 0, sched};
+                        if (su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, SU3_LAYOUT_SOA, 0, d, &c) != SU3_OK)
+                            continue;
+                        emu_threaded = true;
+                        su3_status st = lp == 0 ? su3_dslash(s64a, u64, s64b, nullptr)
+                                                : su3_dslash(s32, u32, s32b, nullptr);
+                        emu_threaded = false;
+                        if (st != SU3_OK) { printf("lds launch sched %d block %d prec %d: %s\n", sched, b, lp, su3_last_error()); fails++; }
+                    }
+            su3_launch_reset();
+            for (int mu = 0; mu < 4; ++mu) su3_field_free(u32[mu]);
+            su3_field_free(s32b);
+        }
         su3_field *links_c12[4];
         for (int mu = 0; mu < 4; ++mu) su3_field_alloc(&links_c12[mu], d, SU3_C12_F32, SU3_LAYOUT_SOA, 0);
         if (su3_dslash(s64a, links_c12, s64b, nullptr) != SU3_ERR_UNSUPPORTED) { printf("f64 spinor with c12 links accepted\n"); fails++; }

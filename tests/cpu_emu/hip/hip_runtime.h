@@ -35,6 +35,8 @@ enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
 enum { hipMemoryTypeDevice = 2 };
 enum { hipStreamNonBlocking = 1 };
 enum { hipStreamCaptureModeThreadLocal = 1 };
+enum { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
+inline hipError_t hipFuncSetAttribute(const void *, int, int) { return hipSuccess; }
 enum { hipDeviceAttributeMultiprocessorCount = 1, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor = 2, hipDeviceAttributeMaxSharedMemoryPerBlock = 3 };
 inline void __builtin_amdgcn_sched_barrier(int) {}
 struct hipPointerAttribute_t { int type; int device; };

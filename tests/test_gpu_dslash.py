@@ -104,7 +104,9 @@ def test_dslash_parity(pair, dims):
         prev = None
         # one site per lane; walks of 3 t-slices; one walk over all of t;
         # walks of 4 and 2; site tiles 8x4x2x2, 4x4x4x1, 8x2x2x8 (ragged
-        # against these lattices); LDS-tiled walks of 3 and of all of t
+        # against these lattices); LDS-tiled walks of 3 and of all of t;
+        # the one-buffer tiles 8x8, 8x4, 16x8 and 16x4 (blocks up to 512, walks of
+        # 2, 3, 5 and all of t, nontemporal link loads or not); whole x rows
         for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1,
                          schedule=0),
                     dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3,
@@ -124,7 +126,33 @@ def test_dslash_parity(pair, dims):
                     dict(block=128, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=3,
                          schedule=4),
                     dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=4096,
-                         schedule=4)):
+                         schedule=4),
+                    dict(block=128, nontemporal=3, occupancy=0, xcd_remap=0, tile_sites=3,
+                         schedule=5),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=4096,
+                         schedule=5),
+                    dict(block=512, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=2,
+                         schedule=5),
+                    dict(block=128, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=5,
+                         schedule=6),
+                    dict(block=256, nontemporal=3, occupancy=0, xcd_remap=0, tile_sites=4096,
+                         schedule=6),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=3,
+                         schedule=7),
+                    dict(block=512, nontemporal=3, occupancy=0, xcd_remap=1, tile_sites=4096,
+                         schedule=7),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=3,
+                         schedule=8),
+                    dict(block=512, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=4096,
+                         schedule=8),
+                    dict(block=64, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=3,
+                         schedule=9),
+                    dict(block=256, nontemporal=3, occupancy=0, xcd_remap=1, tile_sites=4096,
+                         schedule=10),
+                    dict(block=128, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=2,
+                         schedule=11),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=5,
+                         schedule=12)):
             full = dict(persistent=0, lds_stage=0, **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
