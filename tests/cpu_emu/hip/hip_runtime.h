@@ -63,23 +63,31 @@ inline void emu_run(K k, dim3 g, dim3 b, A... a)
     emu_launches++;
     gridDim = {g.x, 1, 1};
     blockDim = {b.x, 1, 1};
-    for (unsigned bi = 0; bi < g.x; ++bi) {
-        if (emu_threaded) {
-            std::barrier<> bar(b.x);
-            emu_bar = &bar;
-            std::vector<std::thread> th;
-            for (unsigned t = 0; t < b.x; ++t)
-                th.emplace_back([=]() { blockIdx = {bi, 0, 0}; threadIdx = {t, 0, 0}; k(a...); });
-            for (auto &x : th) x.join();
-            emu_bar = nullptr;
-        } else {
-            for (unsigned t = 0; t < b.x; ++t) {
-                blockIdx = {bi, 0, 0};
-                threadIdx = {t, 0, 0};
-                k(a...);
-            }
-        }
+    if (emu_threaded) {
+        // one thread per lane for the whole launch; the workgroups run one
+        // after another, all lanes meeting at a barrier between them
+        std::barrier<> bar(b.x);
+        emu_bar = &bar;
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < b.x; ++t)
+            th.emplace_back([=, &bar]() {
+                for (unsigned bi = 0; bi < g.x; ++bi) {
+                    blockIdx = {bi, 0, 0};
+                    threadIdx = {t, 0, 0};
+                    k(a...);
+                    bar.arrive_and_wait();
+                }
+            });
+        for (auto &x : th) x.join();
+        emu_bar = nullptr;
+        return;
     }
+    for (unsigned bi = 0; bi < g.x; ++bi)
+        for (unsigned t = 0; t < b.x; ++t) {
+            blockIdx = {bi, 0, 0};
+            threadIdx = {t, 0, 0};
+            k(a...);
+        }
 }
 
 template <class K, class... A>
