@@ -656,7 +656,6 @@ static bool g_cache_loaded = false;
 
 static su3_launch default_launch(int expr, int prec, int layout)
 {
-    (void)prec;
     su3_launch c;
     c.block = 64;
     c.persistent = 0;
@@ -672,14 +671,17 @@ static su3_launch default_launch(int expr, int prec, int layout)
         c.schedule = 0;
     }
     if (expr == SU3_EXPR_DSLASH) {
-        // neighbours re-read each spinor eight times: keep loads cached;
-        // each lane walks 8 t-slices
-        c.block = 128;
+        // the LDS-tiled walk over whole x rows (16 x 4 x 4 tiles where the
+        // rows are too long): Lx x 2 x 4 walking 8 t-slices for double
+        // spinors, Lx x 4 x 4 walking 4 for single (the fastest at 48^4);
+        // cached loads (neighbours re-read each spinor), nontemporal stores
+        const bool dbl = prec == SU3_F64;
+        c.block = 256;
         c.nontemporal = 2;
         c.occupancy = 0;
-        c.schedule = 0;
-        c.tile_sites = 8;
-        c.xcd_remap = 1;
+        c.schedule = dbl ? 10 : 12;
+        c.tile_sites = dbl ? 8 : 4;
+        c.xcd_remap = 0;
     }
     return c;
 }
