@@ -138,7 +138,9 @@ typedef struct su3_program su3_program;
  *               LDS-tiled walks)
  *   persistent  0: one lane per site group (one-shot grid); batches: one
  *               workgroup per tile.  k > 0: k workgroups per compute unit
- *               loop over the work (grid-stride over site groups or tiles)
+ *               loop over the work (grid-stride over site groups or tiles;
+ *               su3_dslash's LDS-tiled walks: each workgroup walks an equal
+ *               share of the (tile, t-slice) pairs, tile after tile)
  *   nontemporal bit 0: nontemporal loads, bit 1: nontemporal stores
  *               (su3_dslash: bit 0 applies to link loads only; the
  *               LDS-tiled walks always store nontemporal)
@@ -168,9 +170,11 @@ typedef struct su3_program su3_program;
  *               or 512), limited to 48 KiB of buffers (a larger tile falls
  *               back to the schedule's smallest); 9..12 take whole x rows,
  *               Lx x 2 x 2, Lx x 2 x 4, Lx x 4 x 2, Lx x 4 x 4, so that
- *               every x hop comes from LDS (B is ignored: the workgroup
- *               has one lane per tile site, at most 512 for double
- *               spinors and 1024 for single, else 16x4x4 is used)       */
+ *               every x hop comes from LDS, 13..16 the same with two slice
+ *               buffers (B is ignored: the workgroup has one lane per tile
+ *               site, at most 512 for double spinors and 1024 for single,
+ *               with the buffers in 160 KiB; a lattice too long in x gets
+ *               the rows with one buffer, Lx x 2 x 2, or 16x4x4)          */
 typedef struct su3_launch {
     int32_t block;
     int32_t persistent;

@@ -671,15 +671,16 @@ static su3_launch default_launch(int expr, int prec, int layout)
         c.schedule = 0;
     }
     if (expr == SU3_EXPR_DSLASH) {
-        // the LDS-tiled walk over whole x rows (16 x 4 x 4 tiles where the
-        // rows are too long): Lx x 2 x 4 walking 8 t-slices for double
-        // spinors, Lx x 4 x 4 walking 4 for single (the fastest at 48^4);
-        // cached loads (neighbours re-read each spinor), nontemporal stores
+        // the LDS-tiled walk over whole x rows (smaller tiles where the rows
+        // are too long): Lx x 4 x 2 with one buffer walking 8 t-slices for
+        // double spinors, Lx x 4 x 4 with two buffers walking 4 for single
+        // (the fastest at 48^4); cached loads (neighbours re-read each
+        // spinor), nontemporal stores
         const bool dbl = prec == SU3_F64;
         c.block = 256;
         c.nontemporal = 2;
         c.occupancy = 0;
-        c.schedule = dbl ? 10 : 12;
+        c.schedule = dbl ? 11 : 16;
         c.tile_sites = dbl ? 8 : 4;
         c.xcd_remap = 0;
     }
@@ -721,9 +722,9 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
                     c.occupancy);
     if (expr == SU3_EXPR_DSLASH) {
         LdsShape sh;
-        if (c.schedule < 0 || c.schedule > 12)
+        if (c.schedule < 0 || c.schedule > 16)
             return fail(SU3_ERR_INVALID_ARG,
-                        "Dslash schedule (site tile) must be in [0, 12]");
+                        "Dslash schedule (site tile) must be in [0, 16]");
         if (lds_walk && c.schedule <= 8 && !lds_shape(c.schedule, c.block, 8, 0, sh))
             return fail(SU3_ERR_INVALID_ARG,
                         "the LDS-tiled Dslash (schedule %d) has no tile for "
@@ -1082,11 +1083,19 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     const bool lds = !vn && c.schedule >= 4;
     if (lds && !lds_shape(c.schedule, c.block, cbytes, (int)out->dims[0], sh)) {
         // a tile too large for double spinors: the schedule's smallest;
-        // whole rows this lattice cannot take: 16 x 4 x 4
-        if (c.schedule >= 9)
-            c.schedule = 8;
-        c.block = c.schedule >= 7 ? 256 : 128;
-        lds_shape(c.schedule, c.block, cbytes, (int)out->dims[0], sh);
+        // whole rows this lattice cannot take: the same rows with one
+        // buffer, else Lx x 2 x 2, else 16 x 4 x 4
+        const int lx = (int)out->dims[0];
+        if (c.schedule >= 13 && lds_shape(c.schedule - 4, 0, cbytes, lx, sh))
+            c.schedule -= 4;
+        else if (c.schedule >= 9 && lds_shape(9, 0, cbytes, lx, sh))
+            c.schedule = 9;
+        else {
+            if (c.schedule >= 9)
+                c.schedule = 8;
+            c.block = c.schedule >= 7 ? 256 : 128;
+            lds_shape(c.schedule, c.block, cbytes, lx, sh);
+        }
     }
     if (lds)
         c.block = sh.tx * sh.ty * sh.tz;
@@ -1130,9 +1139,20 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
         a.walk = (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
         const uint32_t tdim[3] = {(uint32_t)sh.tx, (uint32_t)sh.ty, (uint32_t)sh.tz};
         grid = (Lt + a.walk - 1) / a.walk;
+        int64_t ntiles = 1;
         for (int mu = 0; mu < 3; ++mu) {
             a.ntile[mu] = (uint32_t)((out->dims[mu] + tdim[mu] - 1) / tdim[mu]);
-            grid *= a.ntile[mu];
+            ntiles *= a.ntile[mu];
+        }
+        grid *= ntiles;
+        if (c.persistent > 0) {
+            // k workgroups per CU, each an equal share of the (tile, slice)
+            // pairs: no tail of partly filled rounds, few walk starts
+            const int64_t pairs = ntiles * Lt;
+            const int64_t g = std::min<int64_t>(
+                pairs, (int64_t)device_cus(out->device) * c.persistent);
+            a.span = (uint32_t)((pairs + g - 1) / g);
+            grid = (pairs + a.span - 1) / a.span;
         }
     } else if (a.walk <= 1 && !vn && c.schedule > 0) {
         dslash_tile(c.schedule, c.block, a.tile);
@@ -1543,7 +1563,7 @@ static std::vector<su3_launch> dslash_candidates(int cbytes, int lx)
                     }
     // LDS-tiled walks: every tile shape that fits this spinor precision,
     // with and without nontemporal link loads
-    for (int sched = 4; sched <= 12; ++sched)
+    for (int sched = 4; sched <= 16; ++sched)
         for (int b : {128, 256, 512}) {
             LdsShape sh;
             if (!lds_shape(sched, b, cbytes, lx, sh) || (sched >= 9 && b != 256))
@@ -1559,6 +1579,18 @@ static std::vector<su3_launch> dslash_candidates(int cbytes, int lx)
                         c.nontemporal = nt;
                         out.push_back(c);
                     }
+            // k workgroups per CU, equal shares of the (tile, slice) pairs
+            for (int k : {1, 2, 3}) {
+                c.tile_sites = 1;
+                c.schedule = sched;
+                c.block = b;
+                c.occupancy = 0;
+                c.xcd_remap = 0;
+                c.nontemporal = 2;
+                c.persistent = k;
+                out.push_back(c);
+                c.persistent = 0;
+            }
         }
     return out;
 }

@@ -23,6 +23,7 @@ struct DslashArgs {
     int32_t nsites;
     int32_t xcd_remap;  // 1: contiguous workgroup ranges per XCD
     uint32_t walk;      // t-slices per lane (1: one site per lane)
+    uint32_t span;      // LDS-tiled walk: > 0, (tile, slice) pairs per workgroup
     uint32_t dims[4];   // outer extents
     uint32_t stride[4]; // outer strides (storage sites)
     uint32_t nlanes[4]; // virtual nodes per direction
@@ -55,18 +56,19 @@ struct LdsShape {
 // schedules 7 and 8: 256 or 512) when its buffers, nb * 12 * B complex
 // numbers of cbytes bytes each, fit in 48 KiB of LDS.
 // Schedules 9..12 take whole x rows, lx x 2 x 2, lx x 2 x 4, lx x 4 x 2,
-// lx x 4 x 4 for the lattice's x extent lx, one buffer, B ignored (the
-// workgroup has lx * ty * tz lanes): they exist when that is at most 512
-// lanes for double spinors (1024 for single) and the buffer fits the
-// 160 KiB of LDS of a compute unit.
+// lx x 4 x 4 for the lattice's x extent lx, with one buffer, 13..16 the
+// same with two; B ignored (the workgroup has lx * ty * tz lanes): they
+// exist when that is at most 512 lanes for double spinors (1024 for
+// single) and the buffers fit the 160 KiB of LDS of a compute unit.
 inline bool lds_shape(int schedule, int block, int cbytes, int lx, LdsShape &s)
 {
-    if (schedule >= 9 && schedule <= 12) {
+    if (schedule >= 9 && schedule <= 16) {
         static const int rows[4][2] = {{2, 2}, {2, 4}, {4, 2}, {4, 4}};
-        s = {lx, rows[schedule - 9][0], rows[schedule - 9][1], 1};
+        const int r = (schedule - 9) % 4;
+        s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1};
         const long lanes = (long)lx * s.ty * s.tz;
         return lx > 0 && lanes <= (cbytes == 16 ? 512 : 1024) &&
-               lanes * 12 * cbytes <= 160 * 1024;
+               s.nb * lanes * 12 * cbytes <= 160 * 1024;
     }
     if (block != 128 && block != 256 && block != 512)
         return false;
@@ -105,7 +107,8 @@ inline size_t lds_shape_bytes(const LdsShape &s, int cbytes)
 // grid * block >= stride[3] * ceil(dims[3] / walk).  With a tile:
 // grid = ntile[0] * ntile[1] * ntile[2] * ntile[3].  LDS-tiled walk
 // (lds_tile = schedule with a shape for this block and spinor precision):
-// grid = ntile[0] * ntile[1] * ntile[2] * ceil(dims[3] / walk), shm =
+// grid = ntile[0] * ntile[1] * ntile[2] * ceil(dims[3] / walk), or with
+// span > 0 ceil(ntile[0] * ntile[1] * ntile[2] * dims[3] / span); shm =
 // lds_shape_bytes; its stores are always nontemporal.
 // Nontemporal bit 0 applies to link loads only: each spinor is read by
 // nine sites and stays cached.

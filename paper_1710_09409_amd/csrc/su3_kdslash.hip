@@ -470,112 +470,127 @@ void k_dslash_lds(su3i::DslashArgs a)
     const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
                                      : blockIdx.x;
     const uint32_t ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
-    const uint32_t chunk = blk / ntiles, tid = blk - chunk * ntiles;
+    const uint32_t V3 = a.stride[3], Lt = a.dims[3];
     const int l = threadIdx.x;
     const int lx = l % tx, ly = (l / tx) % TY, lz = l / (tx * TY);
-    uint32_t c[3];
-    c[0] = (tid % a.ntile[0]) * tx + lx;
-    c[1] = (tid / a.ntile[0] % a.ntile[1]) * TY + ly;
-    c[2] = (tid / (a.ntile[0] * a.ntile[1])) * TZ + lz;
-    const bool valid = c[0] < a.dims[0] && c[1] < a.dims[1] && c[2] < a.dims[2];
-    const uint32_t V3 = a.stride[3], Lt = a.dims[3];
-    const uint32_t t0 = chunk * a.walk;
-    const uint32_t t1 = t0 + a.walk < Lt ? t0 + a.walk : Lt;
-    const uint32_t r = c[0] + a.dims[0] * (c[1] + a.dims[1] * c[2]);
-    // neighbours held by the tile (no periodic wrap, inside the lattice;
-    // whole rows hold both x neighbours, across the wrap too)
-    const bool xf = TX ? lx + 1 < TX && c[0] + 1 < a.dims[0] : true;
-    const bool xb = TX ? lx > 0 : true;
-    const int lxf = TX || lx + 1 < tx ? l + 1 : l - (tx - 1);
-    const int lxb = TX || lx > 0 ? l - 1 : l + (tx - 1);
-    const bool yf = ly + 1 < TY && c[1] + 1 < a.dims[1], yb = ly > 0;
-    const bool zf = lz + 1 < TZ && c[2] + 1 < a.dims[2], zb = lz > 0;
-
-    Cx<T> wb[2][3], hc[2][3];
-    if (valid && t0 < Lt) {
-        {   // backward t-hop of slice t0
-            const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
-            Cx<T> p[4][3], m[9], h[2][3];
-            load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
-            load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
-            project<3, +1>(p, h);
-            color_mul<1>(m, h, wb);
-        }
-        fence_acc(wb);
-        {   // psi(t0): P+ psi for the carry, and the tile's slice t0
-            Cx<T> p[4][3];
-            load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
-            project<3, +1>(p, hc);
-#pragma unroll
-            for (int e = 0; e < 12; ++e)
-                tile[e * ns + l] = p[e / 3][e % 3];
-        }
-        fence_acc(hc);
+    // the (tile, t-slice) pairs, tile-major, this workgroup walks: one
+    // chunk of `walk` slices of one tile (workgroups chunk-major), or with
+    // span > 0 the span pairs from blk * span on, continuing into the next
+    // tile after its last slice (the same for every lane)
+    uint32_t q, qend;
+    if (a.span) {
+        q = blk * a.span;
+        qend = q + a.span < ntiles * Lt ? q + a.span : ntiles * Lt;
+    } else {
+        const uint32_t chunk = blk / ntiles, tile_id = blk - chunk * ntiles;
+        q = tile_id * Lt + chunk * a.walk;
+        qend = tile_id * Lt + (chunk * a.walk + a.walk < Lt ? chunk * a.walk + a.walk : Lt);
     }
-    __syncthreads();
-    int cur = 0;
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t s = r + V3 * t;
-        Cx<T> acc[4][3];
+    while (q < qend) {
+        const uint32_t tid = q / Lt, t0 = q - tid * Lt;
+        const uint32_t t1 = t0 + (qend - q) < Lt ? t0 + (qend - q) : Lt;
+        q += t1 - t0;
+        uint32_t c[3];
+        c[0] = (tid % a.ntile[0]) * tx + lx;
+        c[1] = (tid / a.ntile[0] % a.ntile[1]) * TY + ly;
+        c[2] = (tid / (a.ntile[0] * a.ntile[1])) * TZ + lz;
+        const bool valid = c[0] < a.dims[0] && c[1] < a.dims[1] && c[2] < a.dims[2];
+        const uint32_t r = c[0] + a.dims[0] * (c[1] + a.dims[1] * c[2]);
+        // neighbours held by the tile (no periodic wrap, inside the lattice;
+        // whole rows hold both x neighbours, across the wrap too)
+        const bool xf = TX ? lx + 1 < TX && c[0] + 1 < a.dims[0] : true;
+        const bool xb = TX ? lx > 0 : true;
+        const int lxf = TX || lx + 1 < tx ? l + 1 : l - (tx - 1);
+        const int lxb = TX || lx > 0 ? l - 1 : l + (tx - 1);
+        const bool yf = ly + 1 < TY && c[1] + 1 < a.dims[1], yb = ly > 0;
+        const bool zf = lz + 1 < TZ && c[2] + 1 < a.dims[2], zb = lz > 0;
+
+        Cx<T> wb[2][3], hc[2][3];
         if (valid) {
-#pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    acc[sp][cc] = {T(0), T(0)};
-            reconstruct<3, +1>(wb, acc);
-            fence_acc(acc);
-            const Cx<T> *cur_tile = tile + cur * 12 * ns;
-            hop_fwd_tile<0, SP, LP, NT>(a, s, fwd_site<0>(a, s, c[0], 0u), xf, lxf,
-                                        cur_tile, ns, acc);
-            fence_acc(acc);
-            hop_bwd_tile<0, SP, LP, NT>(a, bwd_site<0>(a, s, c[0], 0u), xb, lxb, cur_tile,
-                                        ns, acc);
-            fence_acc(acc);
-            hop_fwd_tile<1, SP, LP, NT>(a, s, fwd_site<1>(a, s, c[1], 0u), yf, l + tx,
-                                        cur_tile, ns, acc);
-            fence_acc(acc);
-            hop_bwd_tile<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], 0u), yb, l - tx, cur_tile,
-                                        ns, acc);
-            fence_acc(acc);
-            hop_fwd_tile<2, SP, LP, NT>(a, s, fwd_site<2>(a, s, c[2], 0u), zf, l + tx * TY,
-                                        cur_tile, ns, acc);
-            fence_acc(acc);
-            hop_bwd_tile<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], 0u), zb, l - tx * TY,
-                                        cur_tile, ns, acc);
-            fence_acc(acc);
-        }
-        if constexpr (NB == 1)
-            __syncthreads();  // slice t read by the whole tile
-        if (valid) {
-            {   // forward t-hop; next slice's carry; next slice into LDS
-                const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
-                Cx<T> p[4][3], m[9], h[2][3], w[2][3];
-                load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
-                load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
-                project<3, -1>(p, h);
-                color_mul<0>(m, h, w);
-                reconstruct<3, -1>(w, acc);
-                color_mul<1>(m, hc, wb);
-                project<3, +1>(p, hc);
-                Cx<T> *next = tile + (NB == 1 ? 0 : (cur ^ 1) * 12 * ns);
-#pragma unroll
-                for (int e = 0; e < 12; ++e)
-                    next[e * ns + l] = p[e / 3][e % 3];
+            {   // backward t-hop of slice t0
+                const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
+                Cx<T> p[4][3], m[9], h[2][3];
+                load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
+                load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
+                project<3, +1>(p, h);
+                color_mul<1>(m, h, wb);
             }
-            fence_acc(acc);
             fence_acc(wb);
+            {   // psi(t0): P+ psi for the carry, and the tile's slice t0
+                Cx<T> p[4][3];
+                load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
+                project<3, +1>(p, hc);
+    #pragma unroll
+                for (int e = 0; e < 12; ++e)
+                    tile[e * ns + l] = p[e / 3][e % 3];
+            }
             fence_acc(hc);
-            RawVec<SP, 1> raw[12];
-#pragma unroll
-            for (int e = 0; e < 12; ++e)
-                narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
-            store_entries<SP, 1, 2, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
-                                                 site_offset(a.gs, s), a.gs.plane, 1, raw);
         }
         __syncthreads();
-        if constexpr (NB == 2)
-            cur ^= 1;
+        int cur = 0;
+        for (uint32_t t = t0; t < t1; ++t) {
+            const uint32_t s = r + V3 * t;
+            Cx<T> acc[4][3];
+            if (valid) {
+    #pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+    #pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+                        acc[sp][cc] = {T(0), T(0)};
+                reconstruct<3, +1>(wb, acc);
+                fence_acc(acc);
+                const Cx<T> *cur_tile = tile + cur * 12 * ns;
+                hop_fwd_tile<0, SP, LP, NT>(a, s, fwd_site<0>(a, s, c[0], 0u), xf, lxf,
+                                            cur_tile, ns, acc);
+                fence_acc(acc);
+                hop_bwd_tile<0, SP, LP, NT>(a, bwd_site<0>(a, s, c[0], 0u), xb, lxb, cur_tile,
+                                            ns, acc);
+                fence_acc(acc);
+                hop_fwd_tile<1, SP, LP, NT>(a, s, fwd_site<1>(a, s, c[1], 0u), yf, l + tx,
+                                            cur_tile, ns, acc);
+                fence_acc(acc);
+                hop_bwd_tile<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], 0u), yb, l - tx, cur_tile,
+                                            ns, acc);
+                fence_acc(acc);
+                hop_fwd_tile<2, SP, LP, NT>(a, s, fwd_site<2>(a, s, c[2], 0u), zf, l + tx * TY,
+                                            cur_tile, ns, acc);
+                fence_acc(acc);
+                hop_bwd_tile<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], 0u), zb, l - tx * TY,
+                                            cur_tile, ns, acc);
+                fence_acc(acc);
+            }
+            if constexpr (NB == 1)
+                __syncthreads();  // slice t read by the whole tile
+            if (valid) {
+                {   // forward t-hop; next slice's carry; next slice into LDS
+                    const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
+                    Cx<T> p[4][3], m[9], h[2][3], w[2][3];
+                    load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
+                    load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
+                    project<3, -1>(p, h);
+                    color_mul<0>(m, h, w);
+                    reconstruct<3, -1>(w, acc);
+                    color_mul<1>(m, hc, wb);
+                    project<3, +1>(p, hc);
+                    Cx<T> *next = tile + (NB == 1 ? 0 : (cur ^ 1) * 12 * ns);
+    #pragma unroll
+                    for (int e = 0; e < 12; ++e)
+                        next[e * ns + l] = p[e / 3][e % 3];
+                }
+                fence_acc(acc);
+                fence_acc(wb);
+                fence_acc(hc);
+                RawVec<SP, 1> raw[12];
+    #pragma unroll
+                for (int e = 0; e < 12; ++e)
+                    narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
+                store_entries<SP, 1, 2, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
+                                                     site_offset(a.gs, s), a.gs.plane, 1, raw);
+            }
+            __syncthreads();
+            if constexpr (NB == 2)
+                cur ^= 1;
+        }
     }
 }
 
@@ -618,6 +633,10 @@ static hipError_t go_lds(int block, int grid, size_t shm, const su3i::DslashArgs
     case 10 * 2048: return launch_lds<SP, LP, NT, 0, 2, 4, 1>(block, grid, shm, a, st);
     case 11 * 2048: return launch_lds<SP, LP, NT, 0, 4, 2, 1>(block, grid, shm, a, st);
     case 12 * 2048: return launch_lds<SP, LP, NT, 0, 4, 4, 1>(block, grid, shm, a, st);
+    case 13 * 2048: return launch_lds<SP, LP, NT, 0, 2, 2, 2>(block, grid, shm, a, st);
+    case 14 * 2048: return launch_lds<SP, LP, NT, 0, 2, 4, 2>(block, grid, shm, a, st);
+    case 15 * 2048: return launch_lds<SP, LP, NT, 0, 4, 2, 2>(block, grid, shm, a, st);
+    case 16 * 2048: return launch_lds<SP, LP, NT, 0, 4, 4, 2>(block, grid, shm, a, st);
     default: break;
     }
     if constexpr (single) {

@@ -248,8 +248,9 @@ int main(int argc, char **argv)
                     // (run with one thread per lane: they synchronise); the
                     // other tiles (one buffer: 8x8, 8x4, 16x8, 16x4, blocks up to
                     // 512, walks of 2, 3, 5 and all of t); whole x rows
-                    // (x hops and their wrap from LDS)
-                    su3_launch cs[24] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
+                    // (x hops and their wrap from LDS), one or two buffers;
+                    // persistent walks over (tile, slice) spans
+                    su3_launch cs[29] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
                                          {128, 0, 2, 0, 0, 4096, 0, 0}, {128, 0, 2, 1, 0, 4, 0, 0},
                                          {64, 0, 2, 0, 0, 2, 0, 0}, {128, 0, 2, 1, 0, 1, 0, 1},
                                          {64, 0, 2, 0, 0, 1, 0, 2}, {256, 0, 2, 1, 0, 1, 0, 3},
@@ -261,8 +262,10 @@ int main(int argc, char **argv)
                                          {512, 0, 3, 1, 0, 4096, 0, 7}, {256, 0, 2, 1, 0, 3, 0, 8},
                                          {512, 0, 2, 0, 0, 4096, 0, 8}, {64, 0, 2, 0, 0, 3, 0, 9},
                                          {256, 0, 3, 1, 0, 4096, 0, 10}, {128, 0, 2, 0, 0, 2, 0, 11},
-                                         {256, 0, 2, 1, 0, 5, 0, 12}};
-                    for (int k = 0; k < 24; ++k) {
+                                         {256, 0, 2, 1, 0, 5, 0, 12}, {64, 0, 2, 1, 0, 3, 0, 13},
+                                         {256, 0, 2, 0, 0, 4096, 0, 16}, {256, 1, 2, 0, 0, 1, 0, 8},
+                                         {256, 2, 2, 1, 0, 1, 0, 11}, {256, 3, 2, 0, 0, 1, 0, 16}};
+                    for (int k = 0; k < 29; ++k) {
                         if (cs[k].schedule >= 4 && !lds_too)
                             continue;
                         su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &cs[k]);
@@ -305,13 +308,53 @@ int main(int argc, char **argv)
         };
         for (auto &x : v)
             if (x.got != x.want) { printf("dslash validation %s: got %d want %d\n", x.what, x.got, x.want); fails++; }
+        // default launches (whole x rows) on lattices too long in x for
+        // them: the fallbacks (rows with one buffer, Lx x 2 x 2, 16 x 4 x 4)
+        // agree with the oracle
+        {
+            int fd[][5] = {{130, 1, 2, 2, 0}, {300, 1, 1, 2, 1}, {64, 4, 4, 2, 1}};
+            for (auto &q : fd) {
+                int dl[4] = {q[0], q[1], q[2], q[3]};
+                const int sp = q[4], lp = q[4];
+                int64_t V = (int64_t)dl[0] * dl[1] * dl[2] * dl[3];
+                std::vector<double> hu[4], qu[4], hin(24 * V), qin(24 * V), want(24 * V), got(24 * V);
+                const double *up[4];
+                su3_field *fu[4], *fin, *fout;
+                for (int mu = 0; mu < 4; ++mu) {
+                    hu[mu].resize(18 * V);
+                    qu[mu].resize(18 * V);
+                    su3gen_field(9, 2 + mu, 0, V, hu[mu].data());
+                    oracle_roundtrip(lp, hu[mu].data(), qu[mu].data(), V);
+                    up[mu] = qu[mu].data();
+                    su3_field_alloc(&fu[mu], dl, (su3_precision)lp, SU3_LAYOUT_SOA, 0);
+                    su3_field_upload(fu[mu], hu[mu].data(), nullptr);
+                }
+                su3gen_spinor(9, 200, 0, V, hin.data());
+                for (int64_t i = 0; i < 24 * V; ++i)
+                    qin[i] = sp == 0 ? hin[i] : (double)(float)hin[i];
+                oracle_dslash(up, qin.data(), want.data(), dl);
+                su3_spinor_alloc(&fin, dl, (su3_precision)sp, SU3_LAYOUT_SOA, 0);
+                su3_spinor_alloc(&fout, dl, (su3_precision)sp, SU3_LAYOUT_SOA, 0);
+                su3_field_upload(fin, hin.data(), nullptr);
+                su3_launch_reset();
+                emu_threaded = true;
+                if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("fallback dslash %s\n", su3_last_error()); fails++; }
+                emu_threaded = false;
+                su3_field_download(fout, got.data(), nullptr);
+                double err = 0;
+                for (int64_t i = 0; i < 24 * V; ++i) err = std::max(err, std::fabs(got[i] - want[i]));
+                if (err > (sp == 0 ? 1e-13 : 2e-5)) { printf("fallback dslash err %.3e dims %dx%dx%dx%d\n", err, dl[0], dl[1], dl[2], dl[3]); fails++; }
+                su3_field_free(fin); su3_field_free(fout);
+                for (int mu = 0; mu < 4; ++mu) su3_field_free(fu[mu]);
+            }
+        }
         // every LDS-tiled launch the table accepts runs, in both spinor
         // precisions (a tile too large for doubles falls back)
         {
             su3_field *u32[4], *s32b;
             for (int mu = 0; mu < 4; ++mu) su3_field_alloc(&u32[mu], d, SU3_F32, SU3_LAYOUT_SOA, 0);
             su3_spinor_alloc(&s32b, d, SU3_F32, SU3_LAYOUT_SOA, 0);
-            for (int sched = 4; sched <= 13; ++sched)
+            for (int sched = 4; sched <= 17; ++sched)
                 for (int b : {64, 128, 256, 512, 1024})
                     for (int lp : {0, 1}) {
                         su3_launch c = {b, 0, 2, 0, 0, 2, 0, sched};

@@ -93,7 +93,10 @@ inline void emu_run(K k, dim3 g, dim3 b, A... a)
 template <class K, class... A>
 inline void emu_launch(K k, dim3 g, dim3 b, size_t shm, A... a)
 {
-    (void)shm;
+    if (shm > (160u << 10)) {  // a compute unit's LDS
+        std::fprintf(stderr, "launch with %zu bytes of dynamic LDS\n", shm);
+        std::abort();
+    }
     if (emu_capturing)
         emu_graph.push_back([=]() { emu_run(k, g, b, a...); });
     else
@@ -112,8 +115,10 @@ inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, int, hipStrea
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, int) { std::memcpy(d, s, n); return hipSuccess; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 inline hipError_t hipPointerGetAttributes(hipPointerAttribute_t *a, const void *) { a->type = hipMemoryTypeDevice; a->device = 0; return hipSuccess; }
-inline hipError_t hipDeviceGetAttribute(int *v, int a, int) { *v = a == 1 ? 256 : (a == 2 ? 160 * 1024 : 64 * 1024); return hipSuccess; }
-inline hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) { std::strcpy(p->gcnArchName, "emu"); p->multiProcessorCount = 256; return hipSuccess; }
+// three compute units: persistent grids loop several times and the
+// Dslash walk's equal shares of (tile, slice) pairs cross tiles
+inline hipError_t hipDeviceGetAttribute(int *v, int a, int) { *v = a == 1 ? 3 : (a == 2 ? 160 * 1024 : 64 * 1024); return hipSuccess; }
+inline hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) { std::strcpy(p->gcnArchName, "emu"); p->multiProcessorCount = 3; return hipSuccess; }
 inline hipError_t hipEventCreate(hipEvent_t *e) { *e = nullptr; return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) { *ms = 1.0f; return hipSuccess; }

@@ -107,6 +107,8 @@ def test_dslash_parity(pair, dims):
         # against these lattices); LDS-tiled walks of 3 and of all of t;
         # the one-buffer tiles 8x8, 8x4, 16x8 and 16x4 (blocks up to 512, walks of
         # 2, 3, 5 and all of t, nontemporal link loads or not); whole x rows
+        # with one and with two buffers; persistent walks over (tile, slice)
+        # spans
         for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1,
                          schedule=0),
                     dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3,
@@ -152,8 +154,18 @@ def test_dslash_parity(pair, dims):
                     dict(block=128, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=2,
                          schedule=11),
                     dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=5,
-                         schedule=12)):
-            full = dict(persistent=0, lds_stage=0, **cfg)
+                         schedule=12),
+                    dict(block=64, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=3,
+                         schedule=13),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=4096,
+                         schedule=16),
+                    dict(block=256, persistent=1, nontemporal=2, occupancy=0, xcd_remap=0,
+                         tile_sites=1, schedule=8),
+                    dict(block=256, persistent=2, nontemporal=2, occupancy=0, xcd_remap=1,
+                         tile_sites=1, schedule=11),
+                    dict(block=256, persistent=3, nontemporal=2, occupancy=0, xcd_remap=0,
+                         tile_sites=1, schedule=16)):
+            full = dict(dict(persistent=0, lds_stage=0), **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
                 su3.su3_dslash(fout, fu, fin, s)
@@ -280,3 +292,38 @@ def test_dslash_full_48_tuned():
         want, mag = reference(sp, lp, links, psi, FULL)
         worst = assert_dslash(sp, lp, got, want, mag, f"48^4 {sp}/{lp} {cfg.as_dict()}")
         print(f"48^4 dslash spinor {sp} links {lp}: worst {worst:.3e} launch {cfg.as_dict()}")
+
+
+@pytest.mark.parametrize("pair", PAIRS, ids=PAIR_IDS)
+def test_dslash_persistent_spans(pair):
+    """LDS-tiled walks with k workgroups per CU, each walking an equal share
+    of the (tile, t-slice) pairs: at 16x16x16x40 there are more pairs than
+    workgroups and the shares (not divisors of 40) continue from one tile
+    into the next.  Parity with the oracle, bit-identical to the default
+    launch."""
+    sp, lp = pair
+    s = torch.cuda.current_stream()
+    dims = (16, 16, 16, 40)
+    links, psi = host_inputs(dims)
+    want, mag = reference(sp, lp, links, psi, dims)
+    lay, lanes = su3.SU3_LAYOUT_SOA, 0
+    fu, fin = device_inputs(dims, sp, lp, lay, lanes, links, psi, s)
+    fout = su3.spinor_tensor(dims, sp, lay, lanes)
+    su3.su3_launch_reset()
+    su3.su3_dslash(fout, fu, fin, s)
+    su3.su3_sync(s)
+    base = su3.su3_field_download(fout, s)
+    assert_dslash(sp, lp, base, want, mag, "default launch")
+    for sched in (8, 11, 12, 16):
+        for k in (1, 2, 3):
+            cfg = dict(block=256, persistent=k, nontemporal=2, xcd_remap=k & 1,
+                       lds_stage=0, tile_sites=1, occupancy=0, schedule=sched)
+            su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, cfg)
+            try:
+                fout.owner.zero_()
+                su3.su3_dslash(fout, fu, fin, s)
+            finally:
+                su3.su3_launch_reset()
+            su3.su3_sync(s)
+            got = su3.su3_field_download(fout, s)
+            assert np.array_equal(got, base), f"schedule {sched} persistent {k}"
