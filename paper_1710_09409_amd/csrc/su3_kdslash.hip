@@ -7,7 +7,10 @@
 // Each hop uses the spin projection: with h = psi_up + s A psi_dn,
 // (1 + s gamma) psi = (h, s A^dagger h), so only the two spin components of
 // h are colour-rotated (two 3x3 matrix-vector products instead of four).
-// One lane per site; neighbours from the site index (x fastest), periodic.
+// Three kernels, one lane per site each: k_dslash (sites in index order or
+// in 4D tiles), k_dslash_walk (a lane walks t) and k_dslash_lds (a
+// workgroup's tile of (x, y, z) sites walks t, sharing each slice through
+// LDS).  Neighbours from the site index (x fastest), periodic.
 #include "su3_device.h"
 #include "su3_dslash.h"
 
@@ -505,7 +508,7 @@ void k_dslash_lds(su3i::DslashArgs a)
         const bool yf = ly + 1 < TY && c[1] + 1 < a.dims[1], yb = ly > 0;
         const bool zf = lz + 1 < TZ && c[2] + 1 < a.dims[2], zb = lz > 0;
 
-        Cx<T> wb[2][3], hc[2][3];
+        Cx<T> wb[2][3];
         if (valid) {
             {   // backward t-hop of slice t0
                 const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
@@ -516,15 +519,13 @@ void k_dslash_lds(su3i::DslashArgs a)
                 color_mul<1>(m, h, wb);
             }
             fence_acc(wb);
-            {   // psi(t0): P+ psi for the carry, and the tile's slice t0
+            {   // the tile's slice t0
                 Cx<T> p[4][3];
                 load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, r + V3 * t0), a.gs.plane, p);
-                project<3, +1>(p, hc);
-    #pragma unroll
+#pragma unroll
                 for (int e = 0; e < 12; ++e)
                     tile[e * ns + l] = p[e / 3][e % 3];
             }
-            fence_acc(hc);
         }
         __syncthreads();
         int cur = 0;
@@ -532,9 +533,9 @@ void k_dslash_lds(su3i::DslashArgs a)
             const uint32_t s = r + V3 * t;
             Cx<T> acc[4][3];
             if (valid) {
-    #pragma unroll
+#pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
-    #pragma unroll
+#pragma unroll
                     for (int cc = 0; cc < 3; ++cc)
                         acc[sp][cc] = {T(0), T(0)};
                 reconstruct<3, +1>(wb, acc);
@@ -562,7 +563,9 @@ void k_dslash_lds(su3i::DslashArgs a)
             if constexpr (NB == 1)
                 __syncthreads();  // slice t read by the whole tile
             if (valid) {
-                {   // forward t-hop; next slice's carry; next slice into LDS
+                {   // forward t-hop; the next slice's backward t-hop from this
+                    // site's own psi(t) (still in LDS: each lane reads its
+                    // own slot before writing it); next slice into LDS
                     const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
                     Cx<T> p[4][3], m[9], h[2][3], w[2][3];
                     load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
@@ -570,18 +573,24 @@ void k_dslash_lds(su3i::DslashArgs a)
                     project<3, -1>(p, h);
                     color_mul<0>(m, h, w);
                     reconstruct<3, -1>(w, acc);
-                    color_mul<1>(m, hc, wb);
-                    project<3, +1>(p, hc);
+                    {
+                        const Cx<T> *own = tile + cur * 12 * ns + pin((uint32_t)l);
+                        Cx<T> q[4][3], hc[2][3];
+#pragma unroll
+                        for (int e = 0; e < 12; ++e)
+                            q[e / 3][e % 3] = own[e * ns];
+                        project<3, +1>(q, hc);
+                        color_mul<1>(m, hc, wb);
+                    }
                     Cx<T> *next = tile + (NB == 1 ? 0 : (cur ^ 1) * 12 * ns);
-    #pragma unroll
+#pragma unroll
                     for (int e = 0; e < 12; ++e)
                         next[e * ns + l] = p[e / 3][e % 3];
                 }
                 fence_acc(acc);
                 fence_acc(wb);
-                fence_acc(hc);
                 RawVec<SP, 1> raw[12];
-    #pragma unroll
+#pragma unroll
                 for (int e = 0; e < 12; ++e)
                     narrow<SP, 1>(raw[e], 0, acc[e / 3][e % 3]);
                 store_entries<SP, 1, 2, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
