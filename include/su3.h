@@ -161,7 +161,7 @@ typedef struct su3_program su3_program;
  *               su3_dslash (lexicographic layouts): with one site per
  *               lane, 0 takes sites in index order and 1..3 give each
  *               workgroup a 4D tile of sites, 8x4x2x(B/64), 4x4x4x(B/64),
- *               8x2x2x(B/32) for block B; 4..7 are LDS-tiled walks:
+ *               8x2x2x(B/32) for block B; 4..16 are LDS-tiled walks:
  *               each workgroup holds a tile of (x, y, z) sites and walks
  *               tile_sites t-slices, sharing each slice's spinors through
  *               LDS: 4: 8x8x(B/64) with two slice buffers, 5: 8x8x(B/64),

@@ -36,7 +36,7 @@ struct DslashArgs {
     // direction; tile[0] == 0 takes sites in index order
     uint32_t tile[4];
     uint32_t ntile[4];
-    // LDS-tiled walk: the schedule (4..7) whose tile each workgroup holds
+    // LDS-tiled walk: the schedule (4..16) whose tile each workgroup holds
     // (lds_shape), walking `walk` t-slices; ntile[0..2] tiles per
     // direction.  0: no LDS tile
     uint32_t lds_tile;

@@ -459,8 +459,7 @@ constexpr int lds_max_lanes()
 }
 
 template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB>
-__global__ __launch_bounds__(TX ? TX * TY * TZ : (SP == su3i::F64 ? 512 : 1024),
-                             SP == su3i::F64 ? 2 : 4)
+__global__ __launch_bounds__((lds_max_lanes<SP, TX, TY, TZ>()), SP == su3i::F64 ? 2 : 4)
 void k_dslash_lds(su3i::DslashArgs a)
 {
     using T = typename PrecT<SP>::T;
