@@ -327,3 +327,23 @@ def test_dslash_persistent_spans(pair):
             su3.su3_sync(s)
             got = su3.su3_field_download(fout, s)
             assert np.array_equal(got, base), f"schedule {sched} persistent {k}"
+
+
+@pytest.mark.parametrize("dims,pair", [((160, 2, 2, 4), (su3.SU3_F64, su3.SU3_F64)),
+                                       ((300, 2, 2, 2), (su3.SU3_F32, su3.SU3_F32)),
+                                       ((64, 4, 4, 4), (su3.SU3_F32, su3.SU3_C12_F32))],
+                         ids=["f64_rows_too_long", "f32_rows_too_long", "f32c12_one_buffer"])
+def test_dslash_default_fallbacks(dims, pair):
+    """The default launch takes whole x rows; rows too long for a workgroup
+    (or two buffers too large for the LDS) fall back to the rows with one
+    buffer, to Lx x 2 x 2 or to 16 x 4 x 4 tiles: still the hopping term."""
+    sp, lp = pair
+    s = torch.cuda.current_stream()
+    links, psi = host_inputs(dims)
+    want, mag = reference(sp, lp, links, psi, dims)
+    fu, fin = device_inputs(dims, sp, lp, su3.SU3_LAYOUT_SOA, 0, links, psi, s)
+    fout = su3.spinor_tensor(dims, sp, su3.SU3_LAYOUT_SOA)
+    su3.su3_launch_reset()
+    su3.su3_dslash(fout, fu, fin, s)
+    su3.su3_sync(s)
+    assert_dslash(sp, lp, su3.su3_field_download(fout, s), want, mag, f"{dims}")
