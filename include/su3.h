@@ -145,7 +145,9 @@ typedef struct su3_program su3_program;
  *               (su3_dslash: bit 0 applies to link loads only; the
  *               LDS-tiled walks always store nontemporal)
  *   xcd_remap   1: hand each of the 8 XCDs a contiguous range of
- *               workgroups instead of the hardware's round-robin
+ *               workgroups instead of the hardware's round-robin;
+ *               2 (su3_dslash's LDS-tiled walks): each XCD walks one
+ *               contiguous range of tiles, chunk after chunk
  *   lds_stage   AOS only: 1 stages each workgroup's sites through LDS with
  *               coalesced 16-byte copies (block <= 128)
  *   tile_sites  batched launch: sites per tile (multiple of 64).

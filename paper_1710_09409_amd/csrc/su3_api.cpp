@@ -700,8 +700,9 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
     if (c.nontemporal < 0 || c.nontemporal > 3)
         return fail(SU3_ERR_INVALID_ARG, "nontemporal %d not in [0, 3]",
                     c.nontemporal);
-    if (c.xcd_remap < 0 || c.xcd_remap > 1)
-        return fail(SU3_ERR_INVALID_ARG, "xcd_remap must be 0 or 1");
+    if (c.xcd_remap < 0 || c.xcd_remap > (lds_walk ? 2 : 1))
+        return fail(SU3_ERR_INVALID_ARG, "xcd_remap must be 0 or 1%s",
+                    lds_walk ? " or 2" : "");
     if (c.lds_stage < 0 || c.lds_stage > 1 ||
         (c.lds_stage && layout != SU3_LAYOUT_AOS))
         return fail(SU3_ERR_INVALID_ARG, "lds_stage is for the AoS layout only");
@@ -1145,6 +1146,8 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
             ntiles *= a.ntile[mu];
         }
         grid *= ntiles;
+        if (c.xcd_remap == 2)  // XCD slabs: 8 ranges of ceil(ntiles / 8) tiles
+            grid = (Lt + a.walk - 1) / a.walk * 8 * ((ntiles + 7) / 8);
         if (c.persistent > 0) {
             // k workgroups per CU, each an equal share of the (tile, slice)
             // pairs: no tail of partly filled rounds, few walk starts
@@ -1569,7 +1572,7 @@ static std::vector<su3_launch> dslash_candidates(int cbytes, int lx)
             if (!lds_shape(sched, b, cbytes, lx, sh) || (sched >= 9 && b != 256))
                 continue;
             for (int walk : {4, 8, 16, 48})
-                for (int x : {0, 1})
+                for (int x : {0, 1, 2})
                     for (int nt : {2, 3}) {
                         c.tile_sites = walk;
                         c.schedule = sched;

@@ -469,8 +469,8 @@ void k_dslash_lds(su3i::DslashArgs a)
     // complex numbers
     extern __shared__ char occupancy_reserve[];
     Cx<T> *tile = reinterpret_cast<Cx<T> *>(occupancy_reserve);
-    const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
-                                     : blockIdx.x;
+    const uint32_t blk = a.xcd_remap == 1 ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
+                                          : blockIdx.x;
     const uint32_t ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
     const uint32_t V3 = a.stride[3], Lt = a.dims[3];
     const int l = threadIdx.x;
@@ -484,9 +484,23 @@ void k_dslash_lds(su3i::DslashArgs a)
         q = blk * a.span;
         qend = q + a.span < ntiles * Lt ? q + a.span : ntiles * Lt;
     } else {
-        const uint32_t chunk = blk / ntiles, tile_id = blk - chunk * ntiles;
+        uint32_t chunk, tile_id;
+        if (a.xcd_remap == 2) {
+            // XCD slabs: workgroups are dealt to the 8 XCDs round-robin;
+            // XCD k walks the tiles k * T8 .. (k + 1) * T8 - 1, chunk after
+            // chunk, so the workgroups it runs together are neighbouring
+            // tiles at the same t (their shared faces can hit its L2)
+            const uint32_t t8 = (ntiles + 7) / 8, m = blk >> 3;
+            chunk = m / t8;
+            tile_id = (blk & 7) * t8 + (m - chunk * t8);
+        } else {
+            chunk = blk / ntiles;
+            tile_id = blk - chunk * ntiles;
+        }
         q = tile_id * Lt + chunk * a.walk;
         qend = tile_id * Lt + (chunk * a.walk + a.walk < Lt ? chunk * a.walk + a.walk : Lt);
+        if (tile_id >= ntiles)
+            qend = q;  // a slab's padding (the same for every lane)
     }
     while (q < qend) {
         const uint32_t tid = q / Lt, t0 = q - tid * Lt;

@@ -249,8 +249,8 @@ int main(int argc, char **argv)
                     // other tiles (one buffer: 8x8, 8x4, 16x8, 16x4, blocks up to
                     // 512, walks of 2, 3, 5 and all of t); whole x rows
                     // (x hops and their wrap from LDS), one or two buffers;
-                    // persistent walks over (tile, slice) spans
-                    su3_launch cs[29] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
+                    // persistent walks over (tile, slice) spans; XCD slabs
+                    su3_launch cs[31] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
                                          {128, 0, 2, 0, 0, 4096, 0, 0}, {128, 0, 2, 1, 0, 4, 0, 0},
                                          {64, 0, 2, 0, 0, 2, 0, 0}, {128, 0, 2, 1, 0, 1, 0, 1},
                                          {64, 0, 2, 0, 0, 1, 0, 2}, {256, 0, 2, 1, 0, 1, 0, 3},
@@ -264,8 +264,9 @@ int main(int argc, char **argv)
                                          {256, 0, 3, 1, 0, 4096, 0, 10}, {128, 0, 2, 0, 0, 2, 0, 11},
                                          {256, 0, 2, 1, 0, 5, 0, 12}, {64, 0, 2, 1, 0, 3, 0, 13},
                                          {256, 0, 2, 0, 0, 4096, 0, 16}, {256, 1, 2, 0, 0, 1, 0, 8},
-                                         {256, 2, 2, 1, 0, 1, 0, 11}, {256, 3, 2, 0, 0, 1, 0, 16}};
-                    for (int k = 0; k < 29; ++k) {
+                                         {256, 2, 2, 1, 0, 1, 0, 11}, {256, 3, 2, 0, 0, 1, 0, 16},
+                                         {256, 0, 2, 2, 0, 3, 0, 11}, {128, 0, 2, 2, 0, 4096, 0, 4}};
+                    for (int k = 0; k < 31; ++k) {
                         if (cs[k].schedule >= 4 && !lds_too)
                             continue;
                         su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &cs[k]);

@@ -214,6 +214,12 @@ def test_launch_table():
         good = dict(cfg, schedule=sched, block=block, tile_sites=8)
         su3.su3_launch_set(su3.SU3_EXPR_DSLASH, 0, 1, 0, dims, good)
         assert su3.su3_launch_get(su3.SU3_EXPR_DSLASH, 0, 1, 0, dims).as_dict() == good
+    # XCD slabs (xcd_remap 2) for the LDS-tiled walks only
+    su3.su3_launch_set(su3.SU3_EXPR_DSLASH, 0, 1, 0, dims,
+                       dict(cfg, schedule=11, block=256, xcd_remap=2))
+    for key, sched in ((su3.SU3_EXPR_DSLASH, 0), (0, 1)):
+        assert _status(su3.su3_launch_set, key, 0, 1, 0, dims,
+                       dict(cfg, schedule=sched, xcd_remap=2)) == su3.SU3_ERR_INVALID_ARG
     for sched, block in ((17, 256), (8, 128), (7, 128), (6, 512), (4, 64), (5, 1024), (0, 512),
                          (3, 512)):
         assert _status(su3.su3_launch_set, su3.SU3_EXPR_DSLASH, 0, 1, 0, dims,

@@ -108,7 +108,7 @@ def test_dslash_parity(pair, dims):
         # the one-buffer tiles 8x8, 8x4, 16x8 and 16x4 (blocks up to 512, walks of
         # 2, 3, 5 and all of t, nontemporal link loads or not); whole x rows
         # with one and with two buffers; persistent walks over (tile, slice)
-        # spans
+        # spans; tiles in XCD slabs
         for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1,
                          schedule=0),
                     dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3,
@@ -164,7 +164,11 @@ def test_dslash_parity(pair, dims):
                     dict(block=256, persistent=2, nontemporal=2, occupancy=0, xcd_remap=1,
                          tile_sites=1, schedule=11),
                     dict(block=256, persistent=3, nontemporal=2, occupancy=0, xcd_remap=0,
-                         tile_sites=1, schedule=16)):
+                         tile_sites=1, schedule=16),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=2, tile_sites=3,
+                         schedule=11),
+                    dict(block=128, nontemporal=2, occupancy=0, xcd_remap=2, tile_sites=4096,
+                         schedule=4)):
             full = dict(dict(persistent=0, lds_stage=0), **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
