@@ -11,6 +11,8 @@
 // in 4D tiles), k_dslash_walk (a lane walks t) and k_dslash_lds (a
 // workgroup's tile of (x, y, z) sites walks t, sharing each slice through
 // LDS).  Neighbours from the site index (x fastest), periodic.
+#include <mutex>
+
 #include "su3_device.h"
 #include "su3_dslash.h"
 
@@ -624,12 +626,23 @@ static hipError_t launch_lds(int block, int grid, size_t shm, const su3i::Dslash
     if (block > lds_max_lanes<SP, TX, TY, TZ>())
         return hipErrorInvalidValue;
     if (shm > 64 * 1024) {
-        // beyond the default dynamic LDS of a workgroup
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)shm);
+        // beyond the default dynamic LDS of a workgroup: raise this kernel's
+        // limit once per device (and whenever a larger tile needs more)
+        static std::mutex mu;
+        static int granted[64];
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess)
             return e;
+        std::lock_guard<std::mutex> lock(mu);
+        if (dev < 0 || dev >= 64 || granted[dev] < (int)shm) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            if (e != hipSuccess)
+                return e;
+            if (dev >= 0 && dev < 64)
+                granted[dev] = (int)shm;
+        }
     }
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, a);
     return hipGetLastError();
