@@ -407,8 +407,50 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
                         "launch": cfg}
             log(f"dslash {key}: {dsl[key]}")
             del U, fin, fout
-    del host_psi
     out["dslash_48^4"] = dsl
+
+    # Grid's virtual-node layout used in place (N_sub sites per outer site,
+    # one per virtual node): the streaming product and the hopping term in
+    # FP64 on the same inputs, for N_sub = 4 (t and z split in two, Grid's
+    # usual split) and 16 (every direction split in two)
+    vn = {}
+    hosts = {fid: testgen.su3_field(V, seed=args.seed, field_id=fid)
+             for fid in (testgen.FID_X, testgen.FID_Y) +
+             tuple(testgen.FID_U0 + mu for mu in range(4))}
+    host_x, host_y = hosts[testgen.FID_X], hosts[testgen.FID_Y]
+    for nsub, simd in ((4, (1, 1, 2, 2)), (16, (2, 2, 2, 2))):
+        F64, VN = su3.SU3_F64, su3.SU3_LAYOUT_VNODE
+
+        def vfield(host, kind=su3.SU3_KIND_MATRIX):
+            f = su3.vnode_tensor(dims, F64, simd, kind)
+            su3.su3_field_upload(f, host, stream)
+            return f
+
+        fx, fy = vfield(host_x), vfield(host_y)
+        fz = su3.vnode_tensor(dims, F64, simd)
+        cfg = tune(su3.SU3_EXPR_MUL, F64, VN, nsub, dims)
+        ms, _ = timer.run(lambda: su3.su3_mult(fz, fx, fy, stream), steps, 3)
+        b = BYTES_PER_SITE[F64] * V
+        vn[f"mul_nsub{nsub}"] = {"us": round(ms * 1e3, 2),
+                                 "gbps": round(b / (ms * 1e-3) / 1e9, 1),
+                                 "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                 "simd": list(simd), "launch": cfg}
+        log(f"vnode mul nsub {nsub}: {vn[f'mul_nsub{nsub}']}")
+        del fx, fy, fz
+        U = [vfield(hosts[testgen.FID_U0 + mu]) for mu in range(4)]
+        fin = vfield(host_psi, su3.SU3_KIND_SPINOR)
+        fout = su3.vnode_tensor(dims, F64, simd, su3.SU3_KIND_SPINOR)
+        cfg = tune(su3.SU3_EXPR_DSLASH, F64, VN, nsub, dims)
+        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+        b = DSLASH_BYTES_PER_SITE[(F64, F64)] * V
+        vn[f"dslash_nsub{nsub}"] = {"us": round(ms * 1e3, 2),
+                                    "gbps": round(b / (ms * 1e-3) / 1e9, 1),
+                                    "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                    "simd": list(simd), "launch": cfg}
+        log(f"vnode dslash nsub {nsub}: {vn[f'dslash_nsub{nsub}']}")
+        del U, fin, fout
+    del host_psi, host_x, host_y, hosts
+    out["vnode_f64_48^4"] = vn
 
     # expression programs at 48^4 (one precompiled kernel interpreting the
     # host-compiled expression): Listing 2 on double fields (two real

@@ -1709,6 +1709,9 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
                                                               : candidates(layout)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)
                 continue;  // a copy has no row phases
+            if (dslash && layout == SU3_LAYOUT_VNODE &&
+                (c.schedule != 0 || c.tile_sites != 1 || c.persistent != 0))
+                continue;  // virtual nodes: one site per lane in index order
             double us = 0;
             su3_status r = time_launch(
                 [&]() {
