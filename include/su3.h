@@ -143,7 +143,7 @@ typedef struct su3_program su3_program;
  *               share of the (tile, t-slice) pairs, tile after tile)
  *   nontemporal bit 0: nontemporal loads, bit 1: nontemporal stores
  *               (su3_dslash: bit 0 applies to link loads only; the
- *               LDS-tiled walks always store nontemporal)
+ *               LDS-tiled walks always load cached, store nontemporal)
  *   xcd_remap   1: hand each of the 8 XCDs a contiguous range of
  *               workgroups instead of the hardware's round-robin;
  *               2 (su3_dslash's LDS-tiled walks): each XCD walks one
@@ -170,13 +170,17 @@ typedef struct su3_program su3_program;
  *               6: 8x4x(B/32), 7: 16x8x(B/128), 8: 16x4x(B/64) with one
  *               buffer; B = 128, 256 or 512 (6: 128 or 256, 7 and 8: 256
  *               or 512), limited to 48 KiB of buffers (a larger tile falls
- *               back to the schedule's smallest); 9..12 take whole x rows,
- *               Lx x 2 x 2, Lx x 2 x 4, Lx x 4 x 2, Lx x 4 x 4, so that
- *               every x hop comes from LDS, 13..16 the same with two slice
- *               buffers (B is ignored: the workgroup has one lane per tile
- *               site, at most 512 for double spinors and 1024 for single,
- *               with the buffers in 160 KiB; a lattice too long in x gets
- *               the rows with one buffer, Lx x 2 x 2, or 16x4x4)          */
+ *               back to the schedule's smallest); 9..12 take x rows,
+ *               tx x 2 x 2, tx x 2 x 4, tx x 4 x 2, tx x 4 x 4, where tx
+ *               is the lattice's x extent (every x hop then comes from
+ *               LDS) or, when a workgroup cannot hold that, the largest
+ *               power of two it can; 13..16 the same with two slice
+ *               buffers.  B is ignored: one lane per tile site, at most
+ *               512 for double spinors and 1024 for single, buffers in
+ *               160 KiB (else the rows with one buffer, rows of 2 x 2, or
+ *               16x4x4).  On virtual-node fields only the row tiles apply,
+ *               over outer sites with all their virtual nodes (else one
+ *               site per lane)                                            */
 typedef struct su3_launch {
     int32_t block;
     int32_t persistent;

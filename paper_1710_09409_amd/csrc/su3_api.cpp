@@ -726,7 +726,7 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
         if (c.schedule < 0 || c.schedule > 16)
             return fail(SU3_ERR_INVALID_ARG,
                         "Dslash schedule (site tile) must be in [0, 16]");
-        if (lds_walk && c.schedule <= 8 && !lds_shape(c.schedule, c.block, 8, 0, sh))
+        if (lds_walk && c.schedule <= 8 && !lds_shape(c.schedule, c.block, 8, 0, 1, sh))
             return fail(SU3_ERR_INVALID_ARG,
                         "the LDS-tiled Dslash (schedule %d) has no tile for "
                         "block %d", c.schedule, c.block);
@@ -1080,26 +1080,31 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
                                u0->lanes, u0->V);
     const int cbytes = 2 * out->rbytes;  // one complex spinor entry
     const bool vn = out->layout == SU3_LAYOUT_VNODE;
-    LdsShape sh = {0, 0, 0, 0};
-    const bool lds = !vn && c.schedule >= 4;
-    if (lds && !lds_shape(c.schedule, c.block, cbytes, (int)out->dims[0], sh)) {
-        // a tile too large for double spinors: the schedule's smallest;
-        // whole rows this lattice cannot take: the same rows with one
-        // buffer, else Lx x 2 x 2, else 16 x 4 x 4
-        const int lx = (int)out->dims[0];
-        if (c.schedule >= 13 && lds_shape(c.schedule - 4, 0, cbytes, lx, sh))
+    const int nsub = vn ? (int)out->L : 1;
+    const int lx = (int)(out->dims[0] / out->simd[0]);  // (outer) x extent
+    LdsShape sh = {0, 0, 0, 0, 1};
+    // LDS-tiled walks: schedules 4.. on lexicographic fields, the row tiles
+    // (9..16) on virtual-node fields
+    bool lds = c.schedule >= (vn ? 9 : 4);
+    if (lds && !lds_shape(c.schedule, c.block, cbytes, lx, nsub, sh)) {
+        // buffers too large: the same rows with one buffer, else rows of
+        // 2 x 2; a fixed tile too large for double spinors: the schedule's
+        // smallest; else 16 x 4 x 4 (virtual nodes: one site per lane)
+        if (c.schedule >= 13 && lds_shape(c.schedule - 4, 0, cbytes, lx, nsub, sh)) {
             c.schedule -= 4;
-        else if (c.schedule >= 9 && lds_shape(9, 0, cbytes, lx, sh))
+        } else if (c.schedule >= 9 && lds_shape(9, 0, cbytes, lx, nsub, sh)) {
             c.schedule = 9;
-        else {
+        } else if (vn) {
+            lds = false;
+        } else {
             if (c.schedule >= 9)
                 c.schedule = 8;
             c.block = c.schedule >= 7 ? 256 : 128;
-            lds_shape(c.schedule, c.block, cbytes, lx, sh);
+            lds_shape(c.schedule, c.block, cbytes, lx, 1, sh);
         }
     }
     if (lds)
-        c.block = sh.tx * sh.ty * sh.tz;
+        c.block = sh.nsub * sh.tx * sh.ty * sh.tz;
     else if (c.block > 256)
         c.block = 256;  // the one-site and walk kernels take at most 256
     DslashArgs a;
@@ -1129,7 +1134,7 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     }
     // lanes: one per site, or (lexicographic site order only) one per
     // (x, y, z) site and chunk of `walk` t-slices
-    const int64_t Lt = out->dims[3];
+    const int64_t Lt = a.dims[3];  // (outer) t extent
     a.walk = vn ? 1u : (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
     const int64_t lanes = a.walk <= 1 ? out->V
                                       : a.stride[3] * ((Lt + a.walk - 1) / a.walk);
@@ -1137,12 +1142,13 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     if (lds) {
         // LDS-tiled walk: tiles of (x, y, z) sites walking t
         a.lds_tile = (uint32_t)c.schedule;
+        a.lds_tx = (uint32_t)sh.tx;
         a.walk = (uint32_t)std::min<int64_t>(std::max(c.tile_sites, 1), Lt);
         const uint32_t tdim[3] = {(uint32_t)sh.tx, (uint32_t)sh.ty, (uint32_t)sh.tz};
         grid = (Lt + a.walk - 1) / a.walk;
         int64_t ntiles = 1;
         for (int mu = 0; mu < 3; ++mu) {
-            a.ntile[mu] = (uint32_t)((out->dims[mu] + tdim[mu] - 1) / tdim[mu]);
+            a.ntile[mu] = (a.dims[mu] + tdim[mu] - 1) / tdim[mu];
             ntiles *= a.ntile[mu];
         }
         grid *= ntiles;
@@ -1547,16 +1553,19 @@ static std::vector<su3_launch> candidates(int layout)
 // XCD remapping (nontemporal stores, cached spinor loads); LDS-tiled
 // walks of every tile that fits the precision (cbytes per complex entry)
 // and the lattice's x extent lx (whole-row tiles).
-static std::vector<su3_launch> dslash_candidates(int cbytes, int lx)
+static std::vector<su3_launch> dslash_candidates(int cbytes, int lx, int nsub)
 {
     std::vector<su3_launch> out;
     su3_launch c = default_launch(SU3_EXPR_DSLASH, SU3_F64, SU3_LAYOUT_SOA);
     c.nontemporal = 2;
+    // virtual nodes: one site per lane in index order, or row tiles
     for (int walk : {1, 4, 8})
-        for (int sched = 0; sched <= (walk == 1 ? 3 : 0); ++sched)
+        for (int sched = 0; sched <= (walk == 1 && nsub == 1 ? 3 : 0); ++sched)
             for (int b : {64, 128, 256})
                 for (int occ : {0, 2, 3, 4, 6})
                     for (int x : {0, 1}) {
+                        if (nsub > 1 && walk > 1)
+                            continue;
                         c.tile_sites = walk;
                         c.schedule = sched;
                         c.block = b;
@@ -1564,24 +1573,22 @@ static std::vector<su3_launch> dslash_candidates(int cbytes, int lx)
                         c.xcd_remap = x;
                         out.push_back(c);
                     }
-    // LDS-tiled walks: every tile shape that fits this spinor precision,
-    // with and without nontemporal link loads
+    // LDS-tiled walks: every tile shape that fits this spinor precision and
+    // lattice (cached loads; nontemporal stores)
     for (int sched = 4; sched <= 16; ++sched)
         for (int b : {128, 256, 512}) {
             LdsShape sh;
-            if (!lds_shape(sched, b, cbytes, lx, sh) || (sched >= 9 && b != 256))
+            if (!lds_shape(sched, b, cbytes, lx, nsub, sh) || (sched >= 9 && b != 256))
                 continue;
             for (int walk : {4, 8, 16, 48})
-                for (int x : {0, 1, 2})
-                    for (int nt : {2, 3}) {
-                        c.tile_sites = walk;
-                        c.schedule = sched;
-                        c.block = b;
-                        c.occupancy = 0;
-                        c.xcd_remap = x;
-                        c.nontemporal = nt;
-                        out.push_back(c);
-                    }
+                for (int x : {0, 1, 2}) {
+                    c.tile_sites = walk;
+                    c.schedule = sched;
+                    c.block = b;
+                    c.occupancy = 0;
+                    c.xcd_remap = x;
+                    out.push_back(c);
+                }
             // k workgroups per CU, equal shares of the (tile, slice) pairs
             for (int k : {1, 2, 3}) {
                 c.tile_sites = 1;
@@ -1704,14 +1711,14 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     if (st == SU3_OK) {
         const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
         su3_field *links[4] = {f[2], f[3], f[4], f[5]};
-        for (const su3_launch &c : dslash ? dslash_candidates(2 * f[0]->rbytes, dims[0])
+        for (const su3_launch &c : dslash ? dslash_candidates(2 * f[0]->rbytes,
+                                                              f[0]->dims[0] / f[0]->simd[0],
+                                                              layout == SU3_LAYOUT_VNODE
+                                                                  ? (int)f[0]->L : 1)
                                    : expr == SU3_EXPR_PROGRAM ? program_candidates()
                                                               : candidates(layout)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)
                 continue;  // a copy has no row phases
-            if (dslash && layout == SU3_LAYOUT_VNODE &&
-                (c.schedule != 0 || c.tile_sites != 1 || c.persistent != 0))
-                continue;  // virtual nodes: one site per lane in index order
             double us = 0;
             su3_status r = time_launch(
                 [&]() {

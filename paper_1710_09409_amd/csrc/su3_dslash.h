@@ -40,12 +40,14 @@ struct DslashArgs {
     // (lds_shape), walking `walk` t-slices; ntile[0..2] tiles per
     // direction.  0: no LDS tile
     uint32_t lds_tile;
+    uint32_t lds_tx;    // row tiles (schedules 9..16): the tile's x extent
 };
 
-// Tile of the LDS-tiled walk: tx x ty x tz (x, y, z) sites, one lane each,
-// and nb slice buffers in LDS (2: one barrier per slice, 1: two).
+// Tile of the LDS-tiled walk: tx x ty x tz (x, y, z) sites -- outer sites
+// with all their nsub virtual nodes in the virtual-node layout -- one lane
+// per site, and nb slice buffers in LDS (2: one barrier per slice, 1: two).
 struct LdsShape {
-    int tx, ty, tz, nb;
+    int tx, ty, tz, nb, nsub;
 };
 
 // Tile by schedule and block B:
@@ -54,41 +56,55 @@ struct LdsShape {
 //   8: 16 x 4 x B/64, one buffer
 // A shape exists for block 128, 256 or 512 (schedule 6: 128 or 256,
 // schedules 7 and 8: 256 or 512) when its buffers, nb * 12 * B complex
-// numbers of cbytes bytes each, fit in 48 KiB of LDS.
-// Schedules 9..12 take whole x rows, lx x 2 x 2, lx x 2 x 4, lx x 4 x 2,
-// lx x 4 x 4 for the lattice's x extent lx, with one buffer, 13..16 the
-// same with two; B ignored (the workgroup has lx * ty * tz lanes): they
-// exist when that is at most 512 lanes for double spinors (1024 for
-// single) and the buffers fit the 160 KiB of LDS of a compute unit.
-inline bool lds_shape(int schedule, int block, int cbytes, int lx, LdsShape &s)
+// numbers of cbytes bytes each, fit in 48 KiB of LDS; lexicographic
+// fields only (nsub 1).
+// Schedules 9..12 take rows, tx x 2 x 2, tx x 2 x 4, tx x 4 x 2,
+// tx x 4 x 4 (outer) sites, with one buffer, 13..16 the same with two; B is
+// ignored: tx is the lattice's (outer) x extent lx when nsub * lx * ty * tz
+// lanes fit a workgroup (rows_max_lanes), else the largest divisor of lx
+// that does, and the buffers must fit the 160 KiB of LDS of a compute unit.
+// Most lanes of a row-tile workgroup: 512 for double spinors and for
+// virtual-node fields (whose kernels need more registers), else 1024.
+inline int rows_max_lanes(int cbytes, int nsub)
 {
+    return cbytes == 16 || nsub > 1 ? 512 : 1024;
+}
+
+inline bool lds_shape(int schedule, int block, int cbytes, int lx, int nsub, LdsShape &s)
+{
+    if (nsub < 1)
+        return false;
     if (schedule >= 9 && schedule <= 16) {
         static const int rows[4][2] = {{2, 2}, {2, 4}, {4, 2}, {4, 4}};
         const int r = (schedule - 9) % 4;
-        s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1};
-        const long lanes = (long)lx * s.ty * s.tz;
-        return lx > 0 && lanes <= (cbytes == 16 ? 512 : 1024) &&
-               s.nb * lanes * 12 * cbytes <= 160 * 1024;
+        const long maxl = rows_max_lanes(cbytes, nsub);
+        s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1, nsub};
+        const long per_x = (long)nsub * s.ty * s.tz;  // lanes per unit of tx
+        if (lx < 1 || per_x > maxl)
+            return false;
+        while (per_x * s.tx > maxl || lx % s.tx != 0)
+            --s.tx;
+        return s.nb * per_x * s.tx * 12 * cbytes <= 160 * 1024;
     }
-    if (block != 128 && block != 256 && block != 512)
+    if (nsub != 1 || (block != 128 && block != 256 && block != 512))
         return false;
     switch (schedule) {
-    case 4: s = {8, 8, block / 64, 2}; break;
-    case 5: s = {8, 8, block / 64, 1}; break;
+    case 4: s = {8, 8, block / 64, 2, 1}; break;
+    case 5: s = {8, 8, block / 64, 1, 1}; break;
     case 6:
         if (block > 256)
             return false;
-        s = {8, 4, block / 32, 1};
+        s = {8, 4, block / 32, 1, 1};
         break;
     case 7:
         if (block < 256)
             return false;
-        s = {16, 8, block / 128, 1};
+        s = {16, 8, block / 128, 1, 1};
         break;
     case 8:
         if (block < 256)
             return false;
-        s = {16, 4, block / 64, 1};
+        s = {16, 4, block / 64, 1, 1};
         break;
     default: return false;
     }
@@ -97,7 +113,7 @@ inline bool lds_shape(int schedule, int block, int cbytes, int lx, LdsShape &s)
 
 inline size_t lds_shape_bytes(const LdsShape &s, int cbytes)
 {
-    return (size_t)s.nb * 12 * s.tx * s.ty * s.tz * cbytes;
+    return (size_t)s.nb * 12 * s.nsub * s.tx * s.ty * s.tz * cbytes;
 }
 
 // Wilson hopping term: spinor precision F64 with F64 links, F32 with F32

@@ -452,21 +452,30 @@ __device__ __forceinline__ void hop_bwd_tile(const su3i::DslashArgs &a, uint32_t
     reconstruct<MU, +1>(w, acc);
 }
 
-// Most lanes a workgroup of the LDS-tiled walk has (whole-row tiles have
-// the lattice's x extent times TY * TZ).
-template <int SP, int TX, int TY, int TZ>
+// Most lanes a workgroup of the LDS-tiled walk has (row tiles: as many as
+// rows_max_lanes allows) and the fewest waves per SIMD it must fit.
+template <int SP, int TX, int TY, int TZ, bool VN>
 constexpr int lds_max_lanes()
 {
-    return TX ? TX * TY * TZ : (SP == su3i::F64 ? 512 : 1024);
+    return TX ? TX * TY * TZ : (SP == su3i::F64 || VN ? 512 : 1024);
+}
+template <int SP, bool VN>
+constexpr int lds_min_waves()
+{
+    return SP == su3i::F64 ? 2 : (VN ? 3 : 4);
 }
 
-template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB>
-__global__ __launch_bounds__((lds_max_lanes<SP, TX, TY, TZ>()), SP == su3i::F64 ? 2 : 4)
+template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB, bool VN>
+__global__ __launch_bounds__((lds_max_lanes<SP, TX, TY, TZ, VN>()), (lds_min_waves<SP, VN>()))
 void k_dslash_lds(su3i::DslashArgs a)
 {
     using T = typename PrecT<SP>::T;
-    const int tx = TX ? TX : (int)a.dims[0];
-    const int ns = tx * TY * TZ;
+    // VN: virtual-node fields, nl sites per outer site (one per virtual
+    // node) stored side by side; the tile is tx x TY x TZ outer sites with
+    // all their virtual nodes, lane l = node + nl * (outer site in tile)
+    const int nl = VN ? (int)a.lmask + 1 : 1;
+    const int tx = TX ? TX : (int)a.lds_tx;
+    const int ns = nl * tx * TY * TZ;
     // the slice buffers in the dynamic LDS the host sizes to NB * 12 * ns
     // complex numbers
     extern __shared__ char occupancy_reserve[];
@@ -476,7 +485,15 @@ void k_dslash_lds(su3i::DslashArgs a)
     const uint32_t ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
     const uint32_t V3 = a.stride[3], Lt = a.dims[3];
     const int l = threadIdx.x;
-    const int lx = l % tx, ly = (l / tx) % TY, lz = l / (tx * TY);
+    const int node = VN ? (l & (int)a.lmask) : 0, lo = VN ? (l >> a.lg) : l;
+    const int lx = lo % tx, ly = (lo / tx) % TY, lz = lo / (tx * TY);
+    // this site's virtual-node coordinate along each direction
+    uint32_t ln[4] = {0u, 0u, 0u, 0u};
+    if constexpr (VN) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+            ln[mu] = ((uint32_t)node / a.lstride[mu]) % a.nlanes[mu];
+    }
     // the (tile, t-slice) pairs, tile-major, this workgroup walks: one
     // chunk of `walk` slices of one tile (workgroups chunk-major), or with
     // span > 0 the span pairs from blk * span on, continuing into the next
@@ -513,20 +530,29 @@ void k_dslash_lds(su3i::DslashArgs a)
         c[1] = (tid / a.ntile[0] % a.ntile[1]) * TY + ly;
         c[2] = (tid / (a.ntile[0] * a.ntile[1])) * TZ + lz;
         const bool valid = c[0] < a.dims[0] && c[1] < a.dims[1] && c[2] < a.dims[2];
-        const uint32_t r = c[0] + a.dims[0] * (c[1] + a.dims[1] * c[2]);
+        const uint32_t r =
+            (uint32_t)node + c[0] * a.stride[0] + c[1] * a.stride[1] + c[2] * a.stride[2];
         // neighbours held by the tile (no periodic wrap, inside the lattice;
-        // whole rows hold both x neighbours, across the wrap too)
-        const bool xf = TX ? lx + 1 < TX && c[0] + 1 < a.dims[0] : true;
-        const bool xb = TX ? lx > 0 : true;
-        const int lxf = TX || lx + 1 < tx ? l + 1 : l - (tx - 1);
-        const int lxb = TX || lx > 0 ? l - 1 : l + (tx - 1);
+        // whole rows hold both x neighbours, across the wrap too, where the
+        // x neighbour of a row end is the next virtual node's row start)
+        const bool wrow = TX == 0 && tx == (int)a.dims[0];
+        const bool xf = wrow || (lx + 1 < tx && c[0] + 1 < a.dims[0]);
+        const bool xb = wrow || lx > 0;
+        int nxf = node, nxb = node;
+        if constexpr (VN) {
+            const int ls = (int)a.lstride[0], nx = (int)a.nlanes[0];
+            nxf = (int)ln[0] + 1 == nx ? node - (nx - 1) * ls : node + ls;
+            nxb = ln[0] == 0 ? node + (nx - 1) * ls : node - ls;
+        }
+        const int lxf = lx + 1 < tx ? l + nl : nxf + nl * (lo - (tx - 1));
+        const int lxb = lx > 0 ? l - nl : nxb + nl * (lo + (tx - 1));
         const bool yf = ly + 1 < TY && c[1] + 1 < a.dims[1], yb = ly > 0;
         const bool zf = lz + 1 < TZ && c[2] + 1 < a.dims[2], zb = lz > 0;
 
         Cx<T> wb[2][3];
         if (valid) {
             {   // backward t-hop of slice t0
-                const uint32_t sm = r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
+                const uint32_t sm = bwd_site<3>(a, r + V3 * t0, t0, ln[3]);
                 Cx<T> p[4][3], m[9], h[2][3];
                 load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
                 load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
@@ -556,22 +582,23 @@ void k_dslash_lds(su3i::DslashArgs a)
                 reconstruct<3, +1>(wb, acc);
                 fence_acc(acc);
                 const Cx<T> *cur_tile = tile + cur * 12 * ns;
-                hop_fwd_tile<0, SP, LP, NT>(a, s, fwd_site<0>(a, s, c[0], 0u), xf, lxf,
+                const int ry = nl * tx, rz = nl * tx * TY;  // LDS strides of y, z
+                hop_fwd_tile<0, SP, LP, NT>(a, s, fwd_site<0>(a, s, c[0], ln[0]), xf, lxf,
                                             cur_tile, ns, acc);
                 fence_acc(acc);
-                hop_bwd_tile<0, SP, LP, NT>(a, bwd_site<0>(a, s, c[0], 0u), xb, lxb, cur_tile,
-                                            ns, acc);
-                fence_acc(acc);
-                hop_fwd_tile<1, SP, LP, NT>(a, s, fwd_site<1>(a, s, c[1], 0u), yf, l + tx,
+                hop_bwd_tile<0, SP, LP, NT>(a, bwd_site<0>(a, s, c[0], ln[0]), xb, lxb,
                                             cur_tile, ns, acc);
                 fence_acc(acc);
-                hop_bwd_tile<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], 0u), yb, l - tx, cur_tile,
-                                            ns, acc);
-                fence_acc(acc);
-                hop_fwd_tile<2, SP, LP, NT>(a, s, fwd_site<2>(a, s, c[2], 0u), zf, l + tx * TY,
+                hop_fwd_tile<1, SP, LP, NT>(a, s, fwd_site<1>(a, s, c[1], ln[1]), yf, l + ry,
                                             cur_tile, ns, acc);
                 fence_acc(acc);
-                hop_bwd_tile<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], 0u), zb, l - tx * TY,
+                hop_bwd_tile<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], ln[1]), yb, l - ry,
+                                            cur_tile, ns, acc);
+                fence_acc(acc);
+                hop_fwd_tile<2, SP, LP, NT>(a, s, fwd_site<2>(a, s, c[2], ln[2]), zf, l + rz,
+                                            cur_tile, ns, acc);
+                fence_acc(acc);
+                hop_bwd_tile<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], ln[2]), zb, l - rz,
                                             cur_tile, ns, acc);
                 fence_acc(acc);
             }
@@ -581,7 +608,7 @@ void k_dslash_lds(su3i::DslashArgs a)
                 {   // forward t-hop; the next slice's backward t-hop from this
                     // site's own psi(t) (still in LDS: each lane reads its
                     // own slot before writing it); next slice into LDS
-                    const uint32_t sp1 = r + V3 * (t + 1 == Lt ? 0 : t + 1);
+                    const uint32_t sp1 = fwd_site<3>(a, s, t, ln[3]);
                     Cx<T> p[4][3], m[9], h[2][3], w[2][3];
                     load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
                     load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
@@ -618,12 +645,12 @@ void k_dslash_lds(su3i::DslashArgs a)
     }
 }
 
-template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB>
+template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB, bool VN = false>
 static hipError_t launch_lds(int block, int grid, size_t shm, const su3i::DslashArgs &a,
                              hipStream_t st)
 {
-    auto *k = k_dslash_lds<SP, LP, NT, TX, TY, TZ, NB>;
-    if (block > lds_max_lanes<SP, TX, TY, TZ>())
+    auto *k = k_dslash_lds<SP, LP, NT, TX, TY, TZ, NB, VN>;
+    if (block > lds_max_lanes<SP, TX, TY, TZ, VN>())
         return hipErrorInvalidValue;
     if (shm > 64 * 1024) {
         // beyond the default dynamic LDS of a workgroup: raise this kernel's
@@ -648,6 +675,24 @@ static hipError_t launch_lds(int block, int grid, size_t shm, const su3i::Dslash
     return hipGetLastError();
 }
 
+// Row tiles (schedules 9..16: tx x {2, 4} x {2, 4}, one or two buffers),
+// lexicographic or virtual-node fields.
+template <int SP, int LP, int NT, bool VN>
+static hipError_t go_rows(int block, int grid, size_t shm, const su3i::DslashArgs &a,
+                          hipStream_t st)
+{
+    switch (a.lds_tile) {
+    case 9: return launch_lds<SP, LP, NT, 0, 2, 2, 1, VN>(block, grid, shm, a, st);
+    case 10: return launch_lds<SP, LP, NT, 0, 2, 4, 1, VN>(block, grid, shm, a, st);
+    case 11: return launch_lds<SP, LP, NT, 0, 4, 2, 1, VN>(block, grid, shm, a, st);
+    case 12: return launch_lds<SP, LP, NT, 0, 4, 4, 1, VN>(block, grid, shm, a, st);
+    case 13: return launch_lds<SP, LP, NT, 0, 2, 2, 2, VN>(block, grid, shm, a, st);
+    case 14: return launch_lds<SP, LP, NT, 0, 2, 4, 2, VN>(block, grid, shm, a, st);
+    case 15: return launch_lds<SP, LP, NT, 0, 4, 2, 2, VN>(block, grid, shm, a, st);
+    default: return launch_lds<SP, LP, NT, 0, 4, 4, 2, VN>(block, grid, shm, a, st);
+    }
+}
+
 // The LDS-tiled walk by schedule and block (the shapes lds_shape accepts;
 // those over 48 KiB of double-precision buffers are not instantiated).
 template <int SP, int LP, int NT>
@@ -655,8 +700,12 @@ static hipError_t go_lds(int block, int grid, size_t shm, const su3i::DslashArgs
                          hipStream_t st)
 {
     constexpr bool single = SP != su3i::F64;
-    const int b = a.lds_tile >= 9 ? 0 : block;  // whole rows: any lane count
-    switch (a.lds_tile * 2048 + b) {
+    if (a.lds_tile >= 9)  // row tiles: any lane count
+        return a.lmask ? go_rows<SP, LP, NT, true>(block, grid, shm, a, st)
+                       : go_rows<SP, LP, NT, false>(block, grid, shm, a, st);
+    if (a.lmask)
+        return hipErrorInvalidValue;  // fixed tiles: lexicographic fields only
+    switch (a.lds_tile * 2048 + block) {
     case 4 * 2048 + 128: return launch_lds<SP, LP, NT, 8, 8, 2, 2>(block, grid, shm, a, st);
     case 5 * 2048 + 128: return launch_lds<SP, LP, NT, 8, 8, 2, 1>(block, grid, shm, a, st);
     case 5 * 2048 + 256: return launch_lds<SP, LP, NT, 8, 8, 4, 1>(block, grid, shm, a, st);
@@ -664,18 +713,10 @@ static hipError_t go_lds(int block, int grid, size_t shm, const su3i::DslashArgs
     case 6 * 2048 + 256: return launch_lds<SP, LP, NT, 8, 4, 8, 1>(block, grid, shm, a, st);
     case 7 * 2048 + 256: return launch_lds<SP, LP, NT, 16, 8, 2, 1>(block, grid, shm, a, st);
     case 8 * 2048 + 256: return launch_lds<SP, LP, NT, 16, 4, 4, 1>(block, grid, shm, a, st);
-    case 9 * 2048: return launch_lds<SP, LP, NT, 0, 2, 2, 1>(block, grid, shm, a, st);
-    case 10 * 2048: return launch_lds<SP, LP, NT, 0, 2, 4, 1>(block, grid, shm, a, st);
-    case 11 * 2048: return launch_lds<SP, LP, NT, 0, 4, 2, 1>(block, grid, shm, a, st);
-    case 12 * 2048: return launch_lds<SP, LP, NT, 0, 4, 4, 1>(block, grid, shm, a, st);
-    case 13 * 2048: return launch_lds<SP, LP, NT, 0, 2, 2, 2>(block, grid, shm, a, st);
-    case 14 * 2048: return launch_lds<SP, LP, NT, 0, 2, 4, 2>(block, grid, shm, a, st);
-    case 15 * 2048: return launch_lds<SP, LP, NT, 0, 4, 2, 2>(block, grid, shm, a, st);
-    case 16 * 2048: return launch_lds<SP, LP, NT, 0, 4, 4, 2>(block, grid, shm, a, st);
     default: break;
     }
     if constexpr (single) {
-        switch (a.lds_tile * 2048 + b) {
+        switch (a.lds_tile * 2048 + block) {
         case 4 * 2048 + 256: return launch_lds<SP, LP, NT, 8, 8, 4, 2>(block, grid, shm, a, st);
         case 5 * 2048 + 512: return launch_lds<SP, LP, NT, 8, 8, 8, 1>(block, grid, shm, a, st);
         case 7 * 2048 + 512: return launch_lds<SP, LP, NT, 16, 8, 4, 1>(block, grid, shm, a, st);
@@ -700,9 +741,8 @@ template <int SP, int LP>
 static hipError_t go(int nt, int block, int grid, size_t shm, const su3i::DslashArgs &a,
                      hipStream_t st)
 {
-    if (a.lds_tile)  // nontemporal stores always; bit 0: nontemporal link loads
-        return (nt & 1) ? go_lds<SP, LP, 3>(block, grid, shm, a, st)
-                        : go_lds<SP, LP, 2>(block, grid, shm, a, st);
+    if (a.lds_tile)  // cached loads and nontemporal stores, whatever nt asks
+        return go_lds<SP, LP, 2>(block, grid, shm, a, st);
     switch (nt & 3) {
     case 0:
         go_nt<SP, LP, 0>(block, grid, shm, a, st);
@@ -733,8 +773,9 @@ hipError_t launch_dslash(int spinor_prec, int link_prec, int nt, int block,
     if (a.lds_tile) {
         LdsShape sh;
         const int cbytes = spinor_prec == F64 ? 16 : 8;
-        if (!lds_shape((int)a.lds_tile, block, cbytes, (int)a.dims[0], sh) ||
-            block != sh.tx * sh.ty * sh.tz || shm < lds_shape_bytes(sh, cbytes))
+        if (!lds_shape((int)a.lds_tile, block, cbytes, (int)a.dims[0], (int)a.lmask + 1, sh) ||
+            block != sh.nsub * sh.tx * sh.ty * sh.tz || (uint32_t)sh.tx != a.lds_tx ||
+            shm < lds_shape_bytes(sh, cbytes))
             return hipErrorInvalidValue;
     } else if (block > 256) {
         return hipErrorInvalidValue;

@@ -458,10 +458,29 @@ int main(int argc, char **argv)
                     oracle_vnode_pack(hin.data(), d, c.simd, sp, 12, 12, img.data());
                     if (memcmp(p, img.data(), n) != 0) { printf("vnode spinor image differs\n"); fails++; }
                 }
-                if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("vnode dslash %s\n", su3_last_error()); fails++; }
-                su3_field_download(fout, got.data(), nullptr);
+                // one site per lane, then row tiles of outer sites with all
+                // their virtual nodes (one and two buffers, walks, persistent
+                // shares, XCD slabs), then the default launch
+                const int nsub = c.simd[0] * c.simd[1] * c.simd[2] * c.simd[3];
+                su3_launch vcs[7] = {{64, 0, 2, 0, 0, 1, 0, 0}, {256, 0, 2, 0, 0, 2, 0, 9},
+                                     {256, 0, 2, 1, 0, 4096, 0, 12}, {256, 0, 2, 0, 0, 3, 0, 13},
+                                     {256, 2, 2, 0, 0, 1, 0, 16}, {256, 0, 2, 2, 0, 1, 0, 11},
+                                     {0, 0, 0, 0, 0, 0, 0, 0}};
+                std::vector<double> got0(24 * V);
+                for (int k = 0; k < 7; ++k) {
+                    if (k < 6)
+                        su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, SU3_LAYOUT_VNODE, nsub, d, &vcs[k]);
+                    else
+                        su3_launch_reset();
+                    emu_threaded = k > 0;
+                    if (su3_dslash(fout, fu, fin, nullptr) != SU3_OK) { printf("vnode dslash %s\n", su3_last_error()); fails++; }
+                    emu_threaded = false;
+                    su3_field_download(fout, k ? got.data() : got0.data(), nullptr);
+                    if (k && memcmp(got.data(), got0.data(), 8 * 24 * V) != 0) { printf("vnode dslash launch %d differs simd %d%d%d%d\n", k, c.simd[0], c.simd[1], c.simd[2], c.simd[3]); fails++; }
+                }
+                su3_launch_reset();
                 double err = 0;
-                for (int64_t i = 0; i < 24 * V; ++i) err = std::max(err, std::fabs(got[i] - want[i]));
+                for (int64_t i = 0; i < 24 * V; ++i) err = std::max(err, std::fabs(got0[i] - want[i]));
                 if (err > (sp == 0 ? 1e-13 : 2e-5)) { printf("vnode dslash err %.3e sp %d lp %d simd %d%d%d%d\n", err, sp, lp, c.simd[0], c.simd[1], c.simd[2], c.simd[3]); fails++; }
                 su3_field_free(fin); su3_field_free(fout);
                 for (int mu = 0; mu < 4; ++mu) su3_field_free(fu[mu]);

@@ -99,11 +99,34 @@ def test_vnode_dslash(dims, simd):
         assert np.array_equal(su3.su3_field_download_raw(fin, s),
                               O.get().vnode_pack(psi, dims, simd, sp))
         fout = su3.vnode_tensor(dims, sp, simd, SP)
-        su3.su3_dslash(fout, fu, fin, s)
-        su3.su3_sync(s)
         want, mag = reference(sp, lp, links, psi, dims)
-        assert_dslash(sp, lp, su3.su3_field_download(fout, s), want, mag,
-                      f"vnode {dims} {simd} {sp}/{lp}")
+        # one site per lane, then row tiles of outer sites with all their
+        # virtual nodes (one and two buffers, walks, persistent shares, XCD
+        # slabs), then the default launch: all bit-identical
+        nsub = int(np.prod(simd))
+        first = None
+        for cfg in (dict(block=64, schedule=0, tile_sites=1),
+                    dict(block=256, schedule=9, tile_sites=2),
+                    dict(block=256, schedule=12, tile_sites=4096, xcd_remap=1),
+                    dict(block=256, schedule=13, tile_sites=3),
+                    dict(block=256, schedule=16, tile_sites=1, persistent=2),
+                    dict(block=256, schedule=11, tile_sites=1, xcd_remap=2),
+                    None):
+            if cfg is not None:
+                full = dict(dict(persistent=0, nontemporal=2, xcd_remap=0, lds_stage=0,
+                                 occupancy=0), **cfg)
+                su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, su3.SU3_LAYOUT_VNODE, nsub,
+                                   dims, full)
+            try:
+                su3.su3_dslash(fout, fu, fin, s)
+            finally:
+                su3.su3_launch_reset()
+            su3.su3_sync(s)
+            got = su3.su3_field_download(fout, s)
+            if first is None:
+                first = got
+                assert_dslash(sp, lp, got, want, mag, f"vnode {dims} {simd} {sp}/{lp}")
+            assert np.array_equal(got, first), f"vnode {dims} {simd} {sp}/{lp} {cfg}"
 
 
 def test_vnode_batch():
