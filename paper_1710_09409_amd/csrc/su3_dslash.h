@@ -61,8 +61,9 @@ struct LdsShape {
 // Schedules 9..12 take rows, tx x 2 x 2, tx x 2 x 4, tx x 4 x 2,
 // tx x 4 x 4 (outer) sites, with one buffer, 13..16 the same with two; B is
 // ignored: tx is the lattice's (outer) x extent lx when nsub * lx * ty * tz
-// lanes fit a workgroup (rows_max_lanes), else the largest divisor of lx
-// that does, and the buffers must fit the 160 KiB of LDS of a compute unit.
+// lanes fit a workgroup (rows_max_lanes), else (virtual-node fields only)
+// the largest divisor of lx that does, and the buffers must fit the 160 KiB
+// of LDS of a compute unit.
 // Most lanes of a row-tile workgroup: 512 for double spinors and for
 // virtual-node fields (whose kernels need more registers), else 1024.
 inline int rows_max_lanes(int cbytes, int nsub)
@@ -80,7 +81,7 @@ inline bool lds_shape(int schedule, int block, int cbytes, int lx, int nsub, Lds
         const long maxl = rows_max_lanes(cbytes, nsub);
         s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1, nsub};
         const long per_x = (long)nsub * s.ty * s.tz;  // lanes per unit of tx
-        if (lx < 1 || per_x > maxl)
+        if (lx < 1 || per_x > maxl || (nsub == 1 && per_x * lx > maxl))
             return false;
         while (per_x * s.tx > maxl || lx % s.tx != 0)
             --s.tx;

@@ -531,11 +531,13 @@ void k_dslash_lds(su3i::DslashArgs a)
         c[2] = (tid / (a.ntile[0] * a.ntile[1])) * TZ + lz;
         const bool valid = c[0] < a.dims[0] && c[1] < a.dims[1] && c[2] < a.dims[2];
         const uint32_t r =
-            (uint32_t)node + c[0] * a.stride[0] + c[1] * a.stride[1] + c[2] * a.stride[2];
+            VN ? (uint32_t)node + c[0] * a.stride[0] + c[1] * a.stride[1] + c[2] * a.stride[2]
+               : c[0] + a.dims[0] * (c[1] + a.dims[1] * c[2]);
         // neighbours held by the tile (no periodic wrap, inside the lattice;
         // whole rows hold both x neighbours, across the wrap too, where the
         // x neighbour of a row end is the next virtual node's row start)
-        const bool wrow = TX == 0 && tx == (int)a.dims[0];
+        // (lexicographic row tiles always span whole rows)
+        const bool wrow = TX == 0 && (!VN || tx == (int)a.dims[0]);
         const bool xf = wrow || (lx + 1 < tx && c[0] + 1 < a.dims[0]);
         const bool xb = wrow || lx > 0;
         int nxf = node, nxb = node;
@@ -546,13 +548,15 @@ void k_dslash_lds(su3i::DslashArgs a)
         }
         const int lxf = lx + 1 < tx ? l + nl : nxf + nl * (lo - (tx - 1));
         const int lxb = lx > 0 ? l - nl : nxb + nl * (lo + (tx - 1));
+        // (lexicographic fields: nl = 1, node = 0, l = lo)
         const bool yf = ly + 1 < TY && c[1] + 1 < a.dims[1], yb = ly > 0;
         const bool zf = lz + 1 < TZ && c[2] + 1 < a.dims[2], zb = lz > 0;
 
         Cx<T> wb[2][3];
         if (valid) {
             {   // backward t-hop of slice t0
-                const uint32_t sm = bwd_site<3>(a, r + V3 * t0, t0, ln[3]);
+                const uint32_t sm = VN ? bwd_site<3>(a, r + V3 * t0, t0, ln[3])
+                                       : r + V3 * (t0 == 0 ? Lt - 1 : t0 - 1);
                 Cx<T> p[4][3], m[9], h[2][3];
                 load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sm), a.gs.plane, p);
                 load_link<LP, NT>(a.u[3], site_offset(a.gl, sm), a.gl.plane, m);
@@ -608,7 +612,8 @@ void k_dslash_lds(su3i::DslashArgs a)
                 {   // forward t-hop; the next slice's backward t-hop from this
                     // site's own psi(t) (still in LDS: each lane reads its
                     // own slot before writing it); next slice into LDS
-                    const uint32_t sp1 = fwd_site<3>(a, s, t, ln[3]);
+                    const uint32_t sp1 = VN ? fwd_site<3>(a, s, t, ln[3])
+                                            : r + V3 * (t + 1 == Lt ? 0 : t + 1);
                     Cx<T> p[4][3], m[9], h[2][3], w[2][3];
                     load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, sp1), a.gs.plane, p);
                     load_link<LP, NT>(a.u[3], site_offset(a.gl, s), a.gl.plane, m);
