@@ -145,7 +145,8 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every "
               "site is independent, so a multi-GPU run would shard the lattice "
-              "with no exchange step; see DESIGN.md", file=sys.stderr)
+              "into t-slabs with no exchange step (the hopping term would add "
+              "a t-face halo)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

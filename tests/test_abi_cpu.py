@@ -278,3 +278,12 @@ def test_host_half_quantiser_rounds_twice():
     out = subprocess.run(["objdump", "-d", "--no-show-raw-insn", su3.LIB_PATH],
                          capture_output=True, text=True, check=True).stdout
     assert "__truncdfhf2" not in out
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: any other --gpus exits with status 2 and
+    says why, before touching a device."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr

@@ -4,7 +4,8 @@ storage precision, the fused expressions on four link fields at 32^4, and
 sampled sites of every lattice of the 64-lattice batch.  Also reports the
 end-to-end error of the reduced-precision forms against the FP64 truth
 (max elementwise error, normwise relative error, unitarity and determinant
-deviation) and writes it to gpurun_out/precision_errors.json."""
+deviation), printed and, when SU3_REPORT_DIR names a folder, written there
+as precision_errors.json."""
 import json
 import os
 
@@ -19,7 +20,6 @@ from gpu_util import PREC_NAMES, assert_parity
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 D48 = (48, 48, 48, 48)
 D32 = (32, 32, 32, 32)
 _host = {}
@@ -131,7 +131,8 @@ def test_precision_error_report():
         assert 1e-8 < r["f32"]["e_max"] < 1e-6 and r["f32"]["d_u"] < 1e-6
         assert 1e-5 < r["f16"]["e_max"] < 4e-3 and r["f16"]["d_u"] < 1e-2
         assert 1e-8 < r["c12"]["e_max"] < 2e-6 and r["c12"]["d_u"] < 2e-6
-    out = os.path.join(ROOT, "gpurun_out")
-    os.makedirs(out, exist_ok=True)
-    with open(os.path.join(out, "precision_errors.json"), "w") as f:
-        json.dump(report, f, indent=1)
+    out = os.environ.get("SU3_REPORT_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "precision_errors.json"), "w") as f:
+            json.dump(report, f, indent=1)
