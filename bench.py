@@ -343,28 +343,60 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
         del x, y, z
     out["layouts_f64_48^4"] = lay_out
 
+    def hot_and_cold(d, prec, fid_x, fid_y):
+        """z = x*y at lattice d (SoA): hot (the same buffers every launch)
+        and cold (rotating through k buffer sets of >= 1 GiB in all, so the
+        256 MiB Infinity Cache never holds the next launch's operands)."""
+        Vd = testgen.volume(d)
+        ws = BYTES_PER_SITE[prec] * Vd
+        x = make(d, prec, SOA, 0, fid_x)
+        y = make(d, prec, SOA, 0, fid_y)
+        z = su3.field_tensor(d, prec, SOA, 0)
+        cfg = tune(su3.SU3_EXPR_MUL, prec, SOA, 0, d)
+        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
+        k = max(2, -(-(1 << 30) // ws))
+        sets = [(x, y, z)]
+        for _ in range(k - 1):
+            xi = su3.field_tensor(d, prec, SOA, 0)
+            yi = su3.field_tensor(d, prec, SOA, 0)
+            xi.owner.copy_(x.owner)
+            yi.owner.copy_(y.owner)
+            sets.append((xi, yi, su3.field_tensor(d, prec, SOA, 0)))
+        turn = [0]
+
+        def rotating():
+            xs, ys, zs = sets[turn[0] % k]
+            turn[0] += 1
+            su3.su3_mult(zs, xs, ys, stream)
+
+        ms_cold, _ = timer.run(rotating, max(steps, 2 * k), k)
+        del sets
+        return {"us": round(ms * 1e3, 2), "gbps": round(ws / (ms * 1e-3) / 1e9, 1),
+                "cold_us": round(ms_cold * 1e3, 2),
+                "cold_gbps": round(ws / (ms_cold * 1e-3) / 1e9, 1),
+                "cold_frac_of_peak": round(ws / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "cold_sets": k, "working_set_bytes": ws,
+                "cache_resident": ws < 2 * 268435456, "launch": cfg}
+
     # volume sweep (FP64 SoA); sizes below 2x the 256 MiB Infinity Cache
-    # are cache-resident when hot, not HBM figures
+    # are cache-resident when hot, not HBM figures: the cold figures are
     sweep = {}
     for L in (16, 24, 32):
         d = (L, L, L, L)
-        Vs = testgen.volume(d)
-        x = make(d, su3.SU3_F64, SOA, 0, 10 + L)
-        y = make(d, su3.SU3_F64, SOA, 0, 11 + L)
-        z = su3.field_tensor(d, su3.SU3_F64, SOA, 0)
-        cfg = tune(su3.SU3_EXPR_MUL, su3.SU3_F64, SOA, 0, d)
-        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
-        ws = 432 * Vs
-        sweep[f"{L}^4"] = {"us": round(ms * 1e3, 2),
-                           "gbps": round(ws / (ms * 1e-3) / 1e9, 1),
-                           "working_set_bytes": ws,
-                           "cache_resident": ws < 2 * 268435456}
+        sweep[f"{L}^4"] = hot_and_cold(d, su3.SU3_F64, 10 + L, 11 + L)
         log(f"sweep {L}^4: {sweep[f'{L}^4']}")
-        del x, y, z
     sweep["48^4"] = {"us": round(ms_f64 * 1e3, 2),
                      "gbps": round(432 * V / (ms_f64 * 1e-3) / 1e9, 1),
                      "working_set_bytes": 432 * V, "cache_resident": False}
     out["sweep_f64_soa"] = sweep
+
+    # storage precisions at 32^4 (SoA): every working set fits the Infinity
+    # Cache, so the cold figures are the HBM ones
+    p32 = {}
+    for prec in (su3.SU3_F64, su3.SU3_F32, su3.SU3_F16_F32ACC, su3.SU3_C12_F32):
+        p32[PREC_NAME[prec]] = hot_and_cold((32, 32, 32, 32), prec, 40, 41)
+        log(f"precision 32^4 {PREC_NAME[prec]}: {p32[PREC_NAME[prec]]}")
+    out["precision_32^4"] = p32
 
     # shifted operands at 48^4 (FP64 SoA): Cshift moves 288 B/site, the
     # product with a shifted operand 432 B/site
