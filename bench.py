@@ -237,6 +237,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(host_field(V, testgen.FID_X),
                            host_field(V, testgen.FID_Y))
+        cpu["gpu_over_cpu"] = round(value / cpu["value"], 1)
 
     out = {
         "metric": METRIC,
@@ -634,12 +635,21 @@ def cpu_baseline(x, y):
     gbps1 = 432 * V * p1 / el1 / 1e9
     log(f"cpu baseline: {passes} passes in {el:.1f} s, {gbps:.2f} GB/s, "
         f"{threads} threads; 1 thread: {p1} passes in {el1:.1f} s, {gbps1:.3f} GB/s")
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f
+                          if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": round(gbps, 3), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{passes} full z=x*y passes over the 48^4 lattice "
                       f"({V} sites, same seeded inputs), {el:.1f} s wall",
+            "gflops": round(198 * V * passes / el / 1e9, 2),
             "value_1core": round(gbps1, 4),
-            "sample_1core": f"{p1} passes on one thread, {el1:.1f} s wall"}
+            "sample_1core": f"{p1} passes on one thread, {el1:.1f} s wall",
+            "cpu_model": model}
 
 
 if __name__ == "__main__":
