@@ -239,3 +239,39 @@ def test_vnode_full_size_matches_soa():
     su3.su3_dslash(gout, gu, gin, s)
     assert np.array_equal(got, su3.su3_field_download(gout, s))
     su3.su3_launch_reset()
+
+
+@pytest.mark.parametrize("simd", [(1, 1, 2, 2), (2, 2, 2, 2)], ids=["nsub4", "nsub16"])
+def test_vnode_dslash_tuned(simd):
+    """The autotuner's choice for the hopping term on virtual-node fields
+    (row tiles of outer sites among the candidates) at 16^3 x 32 gives the
+    one-site result bit for bit."""
+    from test_gpu_dslash import assert_dslash, reference
+    s = torch.cuda.current_stream()
+    dims = (16, 16, 16, 32)
+    V = testgen.volume(dims)
+    nsub = int(np.prod(simd))
+    links = [testgen.su3_field(V, field_id=testgen.FID_U0 + mu) for mu in range(4)]
+    psi = testgen.spinor_field(V, field_id=202)
+    fu = [vfield(dims, su3.SU3_F64, simd, u, s) for u in links]
+    fin = vfield(dims, su3.SU3_F64, simd, psi, s, SP)
+    fout = su3.vnode_tensor(dims, su3.SU3_F64, simd, SP)
+    one = dict(block=64, persistent=0, nontemporal=2, xcd_remap=0, lds_stage=0,
+               tile_sites=1, occupancy=0, schedule=0)
+    su3.su3_launch_set(su3.SU3_EXPR_DSLASH, su3.SU3_F64, su3.SU3_LAYOUT_VNODE, nsub, dims, one)
+    su3.su3_dslash(fout, fu, fin, s)
+    su3.su3_sync(s)
+    base = su3.su3_field_download(fout, s)
+    want, mag = reference(su3.SU3_F64, su3.SU3_F64, links, psi, dims)
+    assert_dslash(su3.SU3_F64, su3.SU3_F64, base, want, mag, f"vnode {simd} one site")
+    try:
+        cfg = su3.su3_autotune(su3.SU3_EXPR_DSLASH, su3.SU3_F64, su3.SU3_LAYOUT_VNODE, nsub,
+                               dims, s)
+        fout.owner.zero_()
+        su3.su3_dslash(fout, fu, fin, s)
+        su3.su3_sync(s)
+        got = su3.su3_field_download(fout, s)
+    finally:
+        su3.su3_launch_reset()
+    print(f"vnode {simd} tuned: {cfg.as_dict()}")
+    assert np.array_equal(got, base), cfg.as_dict()
