@@ -435,7 +435,10 @@ su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows, int64_t cap,
  * scratch fields and keep the fastest for every later call whose volume
  * falls in the same power-of-two bucket.  The result persists in the JSON
  * file named by the SU3_TUNE_CACHE environment variable, if set.  Fields
- * are allocated and freed internally.  `best` may be NULL. */
+ * are allocated and freed internally; when one set of operands takes 64
+ * to 512 MiB, enough sets for 1 GiB are allocated and launched in
+ * rotation, so the launch is tuned for operands that are not in the
+ * Infinity Cache.  `best` may be NULL. */
 su3_status su3_autotune(su3_expr expr, su3_precision prec, su3_layout layout,
                         int32_t lanes, const int32_t dims[4], void *stream,
                         su3_launch *best);

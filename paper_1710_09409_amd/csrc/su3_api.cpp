@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <array>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -1678,26 +1679,47 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     const int nops = expr == SU3_EXPR_CSHIFT ? 1
                      : dslash              ? 5
                                            : operands_of(expr);
-    su3_field *f[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int32_t simd[4] = {1, 1, 1, 1};
     if (layout == SU3_LAYOUT_VNODE)
         (void)default_simd(dims, lanes, simd);  // checked by key_of
-    for (int i = 0; i <= nops && st == SU3_OK; ++i) {
-        const bool spinor = dslash && i < 2;
-        const int fp = spinor ? spinor_prec_of_links(prec) : prec;
-        const int kind = spinor ? KIND_SPINOR : KIND_MATRIX;
-        if (layout == SU3_LAYOUT_VNODE)
-            st = alloc_of_kind(&f[i], dims, fp, layout, 0, kind, simd);
-        else
-            st = alloc_of_kind(&f[i], dims, fp, layout, lanes, kind);
-        if (st == SU3_OK) {
-            // a non-zero bit pattern (finite in every precision)
-            hipError_t e = hipMemsetD32Async((hipDeviceptr_t)f[i]->ptr,
-                                             0x3c003c00u, f[i]->bytes / 4, hs);
-            if (e != hipSuccess)
-                st = hip_fail(e, "fill");
+    // Operand sets: one, or -- when a set of 64 to 512 MiB fits twice into
+    // the 256 MiB Infinity Cache -- as many as make 1 GiB, launched in
+    // rotation, so that each timed launch finds its operands in HBM (tuning
+    // on one cache-resident set picked launches up to 23 % slower cold at
+    // 32^4).  Below 64 MiB launches are short enough that per-launch timing
+    // of rotating sets misleads (16^4: the hot choice is faster hot and
+    // cold), so they keep one set.
+    std::vector<std::array<su3_field *, 6>> sets(1);
+    sets[0].fill(nullptr);
+    for (size_t n = 0; n < sets.size() && st == SU3_OK; ++n) {
+        su3_field **f = sets[n].data();
+        size_t set_bytes = 0;
+        for (int i = 0; i <= nops && st == SU3_OK; ++i) {
+            const bool spinor = dslash && i < 2;
+            const int fp = spinor ? spinor_prec_of_links(prec) : prec;
+            const int kind = spinor ? KIND_SPINOR : KIND_MATRIX;
+            if (layout == SU3_LAYOUT_VNODE)
+                st = alloc_of_kind(&f[i], dims, fp, layout, 0, kind, simd);
+            else
+                st = alloc_of_kind(&f[i], dims, fp, layout, lanes, kind);
+            if (st == SU3_OK) {
+                set_bytes += f[i]->bytes;
+                // a non-zero bit pattern (finite in every precision)
+                hipError_t e = hipMemsetD32Async((hipDeviceptr_t)f[i]->ptr,
+                                                 0x3c003c00u, f[i]->bytes / 4, hs);
+                if (e != hipSuccess)
+                    st = hip_fail(e, "fill");
+            }
+        }
+        if (n == 0 && st == SU3_OK && set_bytes < ((size_t)512 << 20) &&
+            set_bytes >= ((size_t)64 << 20)) {
+            const size_t want = (((size_t)1 << 30) + set_bytes - 1) / set_bytes;
+            sets.resize(std::max<size_t>(2, want));
+            for (size_t m = 1; m < sets.size(); ++m)
+                sets[m].fill(nullptr);
         }
     }
+    size_t turn = 0;
     su3_launch win = default_launch(expr, prec, layout);
     double win_us = 1e300;
     // expression programs are timed on the streaming product a*b
@@ -1709,12 +1731,11 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
             st = fail(SU3_ERR_HIP, "internal program: %s", err);
     }
     if (st == SU3_OK) {
-        const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
-        su3_field *links[4] = {f[2], f[3], f[4], f[5]};
-        for (const su3_launch &c : dslash ? dslash_candidates(2 * f[0]->rbytes,
-                                                              f[0]->dims[0] / f[0]->simd[0],
+        const su3_field *f0 = sets[0][0];
+        for (const su3_launch &c : dslash ? dslash_candidates(2 * f0->rbytes,
+                                                              f0->dims[0] / f0->simd[0],
                                                               layout == SU3_LAYOUT_VNODE
-                                                                  ? (int)f[0]->L : 1)
+                                                                  ? (int)f0->L : 1)
                                    : expr == SU3_EXPR_PROGRAM ? program_candidates()
                                                               : candidates(layout)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)
@@ -1722,6 +1743,9 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
             double us = 0;
             su3_status r = time_launch(
                 [&]() {
+                    su3_field *const *f = sets[turn++ % sets.size()].data();
+                    const su3_field *ops[4] = {f[1], f[2], f[3], f[4]};
+                    su3_field *links[4] = {f[2], f[3], f[4], f[5]};
                     if (dslash)
                         return launch_dslash_op(f[0], links, f[1], stream, &c);
                     if (expr == SU3_EXPR_PROGRAM)
@@ -1747,8 +1771,9 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
         if (win_us >= 1e300)
             st = fail(SU3_ERR_HIP, "no candidate launch ran");
     }
-    for (int i = 0; i < 6; ++i)
-        su3_field_free(f[i]);
+    for (auto &set : sets)
+        for (su3_field *fi : set)
+            su3_field_free(fi);
     if (st != SU3_OK)
         return st;
     {
