@@ -391,6 +391,13 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
                      "working_set_bytes": 432 * V, "cache_resident": False}
     out["sweep_f64_soa"] = sweep
 
+    # one GPU's share of a 48^4 lattice cut into 8 t-slabs: 48^3 x 6 sites,
+    # 287 MB of operands, just above the Infinity Cache, so the cold figure
+    # is the HBM one
+    shard = hot_and_cold((48, 48, 48, 6), su3.SU3_F64, 60, 61)
+    log(f"shard 48^3x6: {shard}")
+    out["shard_f64_soa_48^3x6"] = shard
+
     # storage precisions at 32^4 (SoA): every working set fits the Infinity
     # Cache, so the cold figures are the HBM ones
     p32 = {}
@@ -442,6 +449,26 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
             log(f"dslash {key}: {dsl[key]}")
             del U, fin, fout
     out["dslash_48^4"] = dsl
+
+    # the hopping term at the same t-slab's shape (periodic in t over its 6
+    # slices: the traffic and work of a slab without its halo exchange);
+    # 637 MB of operands, more than twice the Infinity Cache
+    ds = (48, 48, 48, 6)
+    Vs = testgen.volume(ds)
+    U = [make(ds, su3.SU3_F64, SOA, 0, 60 + mu) for mu in range(4)]
+    fin = su3.spinor_tensor(ds, su3.SU3_F64, SOA, 0)
+    su3.su3_field_upload(fin, testgen.spinor_field(Vs, seed=args.seed, field_id=201),
+                         stream)
+    fout = su3.spinor_tensor(ds, su3.SU3_F64, SOA, 0)
+    cfg = tune(su3.SU3_EXPR_DSLASH, su3.SU3_F64, SOA, 0, ds)
+    ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+    b = DSLASH_BYTES_PER_SITE[(su3.SU3_F64, su3.SU3_F64)] * Vs
+    out["dslash_shard_f64_soa_48^3x6"] = {
+        "us": round(ms * 1e3, 2), "gbps": round(b / (ms * 1e-3) / 1e9, 1),
+        "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "launch": cfg}
+    log(f"dslash shard 48^3x6: {out['dslash_shard_f64_soa_48^3x6']}")
+    del U, fin, fout
 
     # Grid's virtual-node layout used in place (N_sub sites per outer site,
     # one per virtual node): the streaming product and the hopping term in

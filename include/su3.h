@@ -366,8 +366,12 @@ su3_status su3_program_info(const su3_program *p, su3_kind *result_kind,
  * field is SU3_F32 or SU3_C12_F32 (mixed: SU3_ERR_MISMATCH; half:
  * SU3_ERR_UNSUPPORTED).  A compressed output needs an SU(3)-valued
  * expression (products, adj, transpose, conj of matrices), and double
- * arithmetic at most 4 registers (SU3_ERR_UNSUPPORTED otherwise).  z may
- * be an operand exactly; a partial overlap is SU3_ERR_ALIAS. */
+ * arithmetic with matrix values at most 4 registers (SU3_ERR_UNSUPPORTED
+ * otherwise).  z may be an operand exactly; a partial overlap is
+ * SU3_ERR_ALIAS.  The launch setting of SU3_EXPR_PROGRAM (tuned or set)
+ * applies in full to programs with matrix values; programs without one
+ * take only its nontemporal bits and run 256-lane workgroups with no
+ * occupancy cap. */
 su3_status su3_program_eval(const su3_program *p, su3_field *z,
                             const su3_field *const *ops, int32_t n_ops,
                             void *stream);

@@ -1300,10 +1300,20 @@ static su3_status launch_program_op(const su3_program *p, su3_field *z,
                                     hipStream_t st,
                                     const su3_launch *forced = nullptr)
 {
-    const su3_launch c =
+    const int form = p->code.real_only ? PF_REAL
+                     : p->code.scalar_only ? PF_SCALAR
+                                           : PF_MATRIX;
+    su3_launch c =
         forced ? *forced
                : lookup_launch(SU3_EXPR_PROGRAM, arith, z->layout, z->lanes,
                                z->V);
+    if (!forced && form != PF_MATRIX) {
+        // the block and occupancy cap are the matrix kernel's (a wave of it
+        // keeps up to 18 KB of loads in flight); a scalar-valued wave keeps
+        // 2-4 KB per operand, so it runs in full workgroups, uncapped
+        c.block = 256;
+        c.occupancy = 0;
+    }
     ProgArgs a;
     std::memset(&a, 0, sizeof a);
     a.z = z->ptr;
@@ -1327,10 +1337,10 @@ static su3_status launch_program_op(const su3_program *p, su3_field *z,
         a.imm[k][0] = p->code.imm[k][0];
         a.imm[k][1] = p->code.imm[k][1];
     }
-    const int64_t per = program_sites_per_lane(arith, p->code.scalar_only);
+    const int64_t per = program_sites_per_lane(arith, form);
     const int64_t lanes = (z->V + per - 1) / per;
     const int64_t grid = (lanes + c.block - 1) / c.block;
-    hipError_t e = launch_program(arith, p->code.scalar_only, p->code.nregs,
+    hipError_t e = launch_program(arith, form, p->code.nregs,
                                   c.nontemporal, c.block, (int)grid,
                                   occupancy_reserve(z->device, c.occupancy), a,
                                   st);
@@ -1581,7 +1591,7 @@ static std::vector<su3_launch> dslash_candidates(int cbytes, int lx, int nsub)
             LdsShape sh;
             if (!lds_shape(sched, b, cbytes, lx, nsub, sh) || (sched >= 9 && b != 256))
                 continue;
-            for (int walk : {4, 8, 16, 48})
+            for (int walk : {4, 5, 6, 7, 8, 12, 16, 48})
                 for (int x : {0, 1, 2}) {
                     c.tile_sites = walk;
                     c.schedule = sched;

@@ -7,8 +7,10 @@
 //
 // A register holds a 3x3 complex matrix (NE = 9; a scalar uses entry 0).
 // Programs without matrix values run in their own kernel, whose registers
-// hold one complex value for each of the lane's S sites.  Register indices
-// are uniform across the wave and are resolved by a chain of
+// hold one complex value for each of the lane's S sites; programs whose
+// every value is real (operands, intermediates and result, the shape of
+// Listing 2) in a third, whose registers hold one real per site.  Register
+// indices are uniform across the wave and are resolved by a chain of
 // compare-and-copy branches, so the register file stays in VGPRs.
 #include <type_traits>
 
@@ -541,6 +543,218 @@ __global__ __launch_bounds__(256) void k_program_scalar(ProgArgs a)
         occupancy_reserve[threadIdx.x] = 0;
 }
 
+// ------------------------------------------------ real-valued programs
+//
+// Every operand, intermediate and the result are real fields (one value
+// per site).  A lane holds S = 2 W sites in each register, W = values per
+// 16-byte vector: vector q (0, 1) of lane l in the lane group g = gid / 64
+// is vector (2 g + q) * 64 + l of the field, so each load and store
+// instruction of a wave moves 1 KiB of consecutive bytes.  Block sizes
+// are multiples of 64, so the lane groups are the hardware waves.
+
+template <class T, int S>
+struct RVal {
+    T v[S];
+};
+
+template <class T, int S, int NR, int K>
+using RValIf = typename std::conditional<(K < NR), RVal<T, S>, NoReg>::type;
+
+template <class T, int S, int NR>
+struct RealFile {
+    RValIf<T, S, NR, 0> r0;
+    RValIf<T, S, NR, 1> r1;
+    RValIf<T, S, NR, 2> r2;
+    RValIf<T, S, NR, 3> r3;
+    RValIf<T, S, NR, 4> r4;
+    RValIf<T, S, NR, 5> r5;
+    RValIf<T, S, NR, 6> r6;
+    RValIf<T, S, NR, 7> r7;
+
+    template <int K>
+    __device__ __forceinline__ RValIf<T, S, NR, K> &at()
+    {
+        if constexpr (K == 0) return r0;
+        else if constexpr (K == 1) return r1;
+        else if constexpr (K == 2) return r2;
+        else if constexpr (K == 3) return r3;
+        else if constexpr (K == 4) return r4;
+        else if constexpr (K == 5) return r5;
+        else if constexpr (K == 6) return r6;
+        else return r7;
+    }
+};
+
+template <class T, int S, int NR, int K = 0>
+__device__ __forceinline__ void rget(RealFile<T, S, NR> &R, int i, RVal<T, S> &out)
+{
+    if constexpr (K < NR) {
+        if (i == K) {
+            out = R.template at<K>();
+            branch_end<K + 112>();
+        } else {
+            rget<T, S, NR, K + 1>(R, i, out);
+        }
+    }
+}
+
+template <class T, int S, int NR, int K = 0>
+__device__ __forceinline__ void rput(RealFile<T, S, NR> &R, int i, const RVal<T, S> &v)
+{
+    if constexpr (K < NR) {
+        if (i == K) {
+            R.template at<K>() = v;
+            branch_end<K + 120>();
+        } else {
+            rput<T, S, NR, K + 1>(R, i, v);
+        }
+    }
+}
+
+// The lane's values of a real field p of n sites; v0 = the lane's first
+// vector.  Sites past n read as zero.
+template <class T, int S, int NT>
+__device__ __forceinline__ void rload(const T *p, uint32_t v0, uint32_t n, RVal<T, S> &r)
+{
+    constexpr int W = 16 / sizeof(T);
+    using V = typename VecOf<T, W>::type;
+#pragma unroll
+    for (int q = 0; q < S / W; ++q) {
+        const uint32_t vi = v0 + 64u * q, s = vi * W;
+        if (s + W <= n) {
+            const V w = vload<NT & 1>(reinterpret_cast<const V *>(p) + vi);
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                r.v[q * W + j] = w[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                r.v[q * W + j] = s + j < n ? p[s + j] : T(0);
+        }
+    }
+}
+
+template <class T, int S, int NT>
+__device__ __forceinline__ void rstore(T *p, uint32_t v0, uint32_t n, const RVal<T, S> &r)
+{
+    constexpr int W = 16 / sizeof(T);
+    using V = typename VecOf<T, W>::type;
+#pragma unroll
+    for (int q = 0; q < S / W; ++q) {
+        const uint32_t vi = v0 + 64u * q, s = vi * W;
+        if (s + W <= n) {
+            V w;
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                w[j] = r.v[q * W + j];
+            vstore<NT & 2>(reinterpret_cast<V *>(p) + vi, w);
+        } else {
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                if (s + j < n)
+                    p[s + j] = r.v[q * W + j];
+        }
+    }
+}
+
+// One instruction on S sites: one branch on the opcode for all of them.
+// Real values take only the real-closed opcodes (constants are real, the
+// conjugate and the real part are the identity, the imaginary part is
+// zero).
+template <class T, int S>
+__device__ __forceinline__ void exec_real(const ProgInstr in, const ProgArgs &a,
+                                          const RVal<T, S> &A, const RVal<T, S> &B,
+                                          RVal<T, S> &C)
+{
+    switch (in.op) {
+    case su3i::OP_CONST: {
+        const T c = T(a.imm[in.a][0]);
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            C.v[j] = c;
+        branch_end<128>();
+        break;
+    }
+    case su3i::OP_ADD_SS:
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            C.v[j] = A.v[j] + B.v[j];
+        branch_end<129>();
+        break;
+    case su3i::OP_SUB_SS:
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            C.v[j] = A.v[j] - B.v[j];
+        branch_end<130>();
+        break;
+    case su3i::OP_MUL_SS:
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            C.v[j] = A.v[j] * B.v[j];
+        branch_end<131>();
+        break;
+    case su3i::OP_NEG_S:
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            C.v[j] = -A.v[j];
+        branch_end<132>();
+        break;
+    case su3i::OP_IMAG:
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            C.v[j] = T(0);
+        branch_end<133>();
+        break;
+    default:  // OP_CONJ_S, OP_REAL
+        C = A;
+        branch_end<134>();
+        break;
+    }
+}
+
+template <class T, int S, int NR, int NT, int K = 0>
+__device__ __forceinline__ void rload_all(const ProgArgs &a, uint32_t v0, uint32_t n,
+                                          RealFile<T, S, NR> &R)
+{
+    if constexpr (K < NR) {
+        if (K < a.nops) {
+            if ((a.used >> K) & 1) {
+                RVal<T, S> t;
+                rload<T, S, NT>(static_cast<const T *>(a.op[K]), v0, n, t);
+                rput<T, S, NR>(R, K, t);
+            }
+            rload_all<T, S, NR, NT, K + 1>(a, v0, n, R);
+        }
+    }
+}
+
+template <class T, int S, int NR, int NT>
+__global__ __launch_bounds__(256) void k_program_real(ProgArgs a)
+{
+    extern __shared__ char occupancy_reserve[];
+    constexpr int W = 16 / sizeof(T);
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t v0 = (gid >> 6) * (64u * (S / W)) + (gid & 63u);
+    const uint32_t n = (uint32_t)a.nsites;
+    if (a.nsites > 0 && v0 * W < n) {
+        RealFile<T, S, NR> R;
+        rload_all<T, S, NR, NT>(a, v0, n, R);
+        for (int pc = 0; pc < a.ninstr; ++pc) {
+            const ProgInstr in = a.ins[pc];
+            RVal<T, S> A, B, C;
+            rget(R, in.a, A);
+            rget(R, in.b, B);
+            exec_real<T, S>(in, a, A, B, C);
+            rput(R, in.d, C);
+        }
+        RVal<T, S> Z;
+        rget(R, a.result, Z);
+        rstore<T, S, NT>(static_cast<T *>(a.z), v0, n, Z);
+    }
+    if (a.nsites < 0)
+        occupancy_reserve[threadIdx.x] = 0;
+}
+
 template <class T, int NE, int NR>
 static hipError_t go(int nt, int block, int grid, size_t shm, const ProgArgs &a,
                      hipStream_t st)
@@ -573,11 +787,28 @@ static hipError_t go_scalar(int nt, int block, int grid, size_t shm,
     return hipGetLastError();
 }
 
+template <class T, int NR>
+static hipError_t go_real(int nt, int block, int grid, size_t shm,
+                          const ProgArgs &a, hipStream_t st)
+{
+    constexpr int S = kScalarSites<T>;
+    if ((nt & 3) == 3)
+        hipLaunchKernelGGL((k_program_real<T, S, NR, 3>), dim3(grid), dim3(block), shm, st, a);
+    else if ((nt & 3) == 2)
+        hipLaunchKernelGGL((k_program_real<T, S, NR, 2>), dim3(grid), dim3(block), shm, st, a);
+    else
+        hipLaunchKernelGGL((k_program_real<T, S, NR, 0>), dim3(grid), dim3(block), shm, st, a);
+    return hipGetLastError();
+}
+
 template <class T>
-static hipError_t go_t(bool scalar_only, int nregs, int nt, int block, int grid,
+static hipError_t go_t(int form, int nregs, int nt, int block, int grid,
                        size_t shm, const ProgArgs &a, hipStream_t st)
 {
-    if (scalar_only)
+    if (form == su3i::PF_REAL)
+        return nregs <= 4 ? go_real<T, 4>(nt, block, grid, shm, a, st)
+                          : go_real<T, 8>(nt, block, grid, shm, a, st);
+    if (form == su3i::PF_SCALAR)
         return nregs <= 4 ? go_scalar<T, 4>(nt, block, grid, shm, a, st)
                           : go_scalar<T, 8>(nt, block, grid, shm, a, st);
     if (nregs <= 4)
@@ -592,25 +823,26 @@ static hipError_t go_t(bool scalar_only, int nregs, int nt, int block, int grid,
 
 namespace su3i {
 
-int program_sites_per_lane(int arith, bool scalar_only)
+int program_sites_per_lane(int arith, int form)
 {
-    if (!scalar_only)
+    if (form == PF_MATRIX)
         return 1;
     return arith == F64 ? su3k::prog::kScalarSites<double>
                         : su3k::prog::kScalarSites<float>;
 }
 
-hipError_t launch_program(int arith, bool scalar_only, int nregs, int nt,
+hipError_t launch_program(int arith, int form, int nregs, int nt,
                           int block, int grid, size_t shm, const ProgArgs &a,
                           hipStream_t st)
 {
     using namespace su3k::prog;
-    if (block > 256 || nregs < 1 || nregs > kProgMaxRegs)
+    if (block > 256 || block % 64 || nregs < 1 || nregs > kProgMaxRegs ||
+        form < PF_MATRIX || form > PF_REAL)
         return hipErrorInvalidValue;
     if (arith == F64)
-        return go_t<double>(scalar_only, nregs, nt, block, grid, shm, a, st);
+        return go_t<double>(form, nregs, nt, block, grid, shm, a, st);
     if (arith == F32)
-        return go_t<float>(scalar_only, nregs, nt, block, grid, shm, a, st);
+        return go_t<float>(form, nregs, nt, block, grid, shm, a, st);
     return hipErrorInvalidValue;
 }
 

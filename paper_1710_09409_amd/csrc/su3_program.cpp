@@ -454,8 +454,14 @@ bool compile_program(const char *text, int nops, const int *kinds,
             return n && (n->ty == T_MATRIX || any_matrix(n->l.get()) ||
                          any_matrix(n->r.get()));
         }
+        static bool all_real(const Node *n)
+        {
+            return !n || (n->ty == T_REAL && all_real(n->l.get()) &&
+                          all_real(n->r.get()));
+        }
     };
     out->scalar_only = !Walk::any_matrix(root.get());
+    out->real_only = Walk::all_real(root.get());
     out->used = 0;
     for (int k = 0; k < nops; ++k)
         if (last[k] >= 0)

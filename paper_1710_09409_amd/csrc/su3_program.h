@@ -61,13 +61,18 @@ struct ProgArgs {
     ProgInstr ins[kProgMaxInstr];
 };
 
+// Kernel forms: PF_MATRIX (matrix values anywhere; one site per lane),
+// PF_SCALAR (no matrix value; complex registers), PF_REAL (every value
+// real: operands, intermediates and result).
+enum ProgForm { PF_MATRIX = 0, PF_SCALAR = 1, PF_REAL = 2 };
+
 // Arithmetic precision F64 (all fields F64) or F32 (F32 / C12 fields).
 // Programs with matrix values use at most 4 registers in F64 and 8 in F32,
-// one site per lane; scalar_only programs (no matrix value anywhere) at
-// most 8 in either, program_sites_per_lane() sites per lane.  grid * block
-// * sites per lane >= nsites.
-int program_sites_per_lane(int arith, bool scalar_only);
-hipError_t launch_program(int arith, bool scalar_only, int nregs, int nt,
+// one site per lane; the scalar and real forms at most 8 in either,
+// program_sites_per_lane() sites per lane.  block is 64, 128 or 256;
+// grid * block * sites per lane >= nsites.
+int program_sites_per_lane(int arith, int form);
+hipError_t launch_program(int arith, int form, int nregs, int nt,
                           int block, int grid, size_t shm, const ProgArgs &a,
                           hipStream_t stream);
 
@@ -86,6 +91,7 @@ struct ProgCode {
     int nops;
     bool su3_closed;  // only products, adjoints and transposes of matrices
     bool scalar_only; // no matrix-valued operand or intermediate
+    bool real_only;   // every operand, intermediate and the result real
     unsigned used;    // bit k: operand k is read
 };
 bool compile_program(const char *text, int nops, const int *kinds,

@@ -65,6 +65,17 @@ def test_mult_48(prec, lay, lanes):
     print(f"48^4 {PREC_NAMES[prec]}: worst {worst:.3e} with launch {cfg.as_dict()}")
 
 
+def test_mult_shard():
+    """One t-slab of a 48^4 lattice cut into 8 (48^3 x 6), FP64 SoA, in the
+    tuned launch; every site compared with the oracle."""
+    dims = (48, 48, 48, 6)
+    V = testgen.volume(dims)
+    fids = (60, 61)
+    got, cfg = run_tuned(dims, 0, su3.SU3_EXPR_MUL, fids)
+    want = O.get().reference(su3.SU3_EXPR_MUL, 0, [host(V, f) for f in fids])
+    assert_parity(0, su3.SU3_EXPR_MUL, got, want, f"48^3x6 f64 {cfg.as_dict()}")
+
+
 @pytest.mark.parametrize("lay,lanes", LAYS, ids=["soa", "aosoa64"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
 @pytest.mark.parametrize("expr", [su3.SU3_EXPR_MUL3, su3.SU3_EXPR_MULADD], ids=["mul3", "muladd"])
