@@ -673,16 +673,16 @@ static su3_launch default_launch(int expr, int prec, int layout)
     }
     if (expr == SU3_EXPR_DSLASH) {
         // the LDS-tiled walk over whole x rows (smaller tiles where the rows
-        // are too long): Lx x 4 x 2 with one buffer walking 8 t-slices for
-        // double spinors, Lx x 4 x 4 with two buffers walking 4 for single
-        // (the fastest at 48^4); cached loads (neighbours re-read each
-        // spinor), nontemporal stores
+        // are too long): Lx x 3 x 3 with one buffer walking 8 t-slices for
+        // double spinors, Lx x 4 x 4 with two buffers walking 7 for single
+        // (the fastest chunked walks at 48^4); cached loads (neighbours
+        // re-read each spinor), nontemporal stores
         const bool dbl = prec == SU3_F64;
         c.block = 256;
         c.nontemporal = 2;
         c.occupancy = 0;
-        c.schedule = dbl ? 11 : 16;
-        c.tile_sites = dbl ? 8 : 4;
+        c.schedule = dbl ? 17 : 16;
+        c.tile_sites = dbl ? 8 : 7;
         c.xcd_remap = 0;
     }
     return c;
@@ -724,9 +724,9 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
                     c.occupancy);
     if (expr == SU3_EXPR_DSLASH) {
         LdsShape sh;
-        if (c.schedule < 0 || c.schedule > 16)
+        if (c.schedule < 0 || c.schedule > 18)
             return fail(SU3_ERR_INVALID_ARG,
-                        "Dslash schedule (site tile) must be in [0, 16]");
+                        "Dslash schedule (site tile) must be in [0, 18]");
         if (lds_walk && c.schedule <= 8 && !lds_shape(c.schedule, c.block, 8, 0, 1, sh))
             return fail(SU3_ERR_INVALID_ARG,
                         "the LDS-tiled Dslash (schedule %d) has no tile for "
@@ -1091,8 +1091,11 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
         // buffers too large: the same rows with one buffer, else rows of
         // 2 x 2; a fixed tile too large for double spinors: the schedule's
         // smallest; else 16 x 4 x 4 (virtual nodes: one site per lane)
-        if (c.schedule >= 13 && lds_shape(c.schedule - 4, 0, cbytes, lx, nsub, sh)) {
-            c.schedule -= 4;
+        const int one_buffer = c.schedule == 18                         ? 17
+                               : c.schedule >= 13 && c.schedule <= 16 ? c.schedule - 4
+                                                                      : 0;
+        if (one_buffer && lds_shape(one_buffer, 0, cbytes, lx, nsub, sh)) {
+            c.schedule = one_buffer;
         } else if (c.schedule >= 9 && lds_shape(9, 0, cbytes, lx, nsub, sh)) {
             c.schedule = 9;
         } else if (vn) {
@@ -1586,7 +1589,7 @@ static std::vector<su3_launch> dslash_candidates(int cbytes, int lx, int nsub)
                     }
     // LDS-tiled walks: every tile shape that fits this spinor precision and
     // lattice (cached loads; nontemporal stores)
-    for (int sched = 4; sched <= 16; ++sched)
+    for (int sched = 4; sched <= 18; ++sched)
         for (int b : {128, 256, 512}) {
             LdsShape sh;
             if (!lds_shape(sched, b, cbytes, lx, nsub, sh) || (sched >= 9 && b != 256))

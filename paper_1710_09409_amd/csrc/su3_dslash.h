@@ -40,7 +40,7 @@ struct DslashArgs {
     // (lds_shape), walking `walk` t-slices; ntile[0..2] tiles per
     // direction.  0: no LDS tile
     uint32_t lds_tile;
-    uint32_t lds_tx;    // row tiles (schedules 9..16): the tile's x extent
+    uint32_t lds_tx;    // row tiles (schedules 9..18): the tile's x extent
 };
 
 // Tile of the LDS-tiled walk: tx x ty x tz (x, y, z) sites -- outer sites
@@ -59,7 +59,8 @@ struct LdsShape {
 // numbers of cbytes bytes each, fit in 48 KiB of LDS; lexicographic
 // fields only (nsub 1).
 // Schedules 9..12 take rows, tx x 2 x 2, tx x 2 x 4, tx x 4 x 2,
-// tx x 4 x 4 (outer) sites, with one buffer, 13..16 the same with two; B is
+// tx x 4 x 4 (outer) sites, with one buffer, 13..16 the same with two, 17
+// and 18 tx x 3 x 3 with one and two (lexicographic fields only); B is
 // ignored: tx is the lattice's (outer) x extent lx when nsub * lx * ty * tz
 // lanes fit a workgroup (rows_max_lanes), else (virtual-node fields only)
 // the largest divisor of lx that does, and the buffers must fit the 160 KiB
@@ -75,11 +76,17 @@ inline bool lds_shape(int schedule, int block, int cbytes, int lx, int nsub, Lds
 {
     if (nsub < 1)
         return false;
-    if (schedule >= 9 && schedule <= 16) {
+    if (schedule >= 9 && schedule <= 18) {
         static const int rows[4][2] = {{2, 2}, {2, 4}, {4, 2}, {4, 4}};
         const int r = (schedule - 9) % 4;
         const long maxl = rows_max_lanes(cbytes, nsub);
-        s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1, nsub};
+        if (schedule >= 17) {
+            if (nsub != 1)
+                return false;
+            s = {lx, 3, 3, schedule == 18 ? 2 : 1, 1};
+        } else {
+            s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1, nsub};
+        }
         const long per_x = (long)nsub * s.ty * s.tz;  // lanes per unit of tx
         if (lx < 1 || per_x > maxl || (nsub == 1 && per_x * lx > maxl))
             return false;

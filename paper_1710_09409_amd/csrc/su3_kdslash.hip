@@ -694,8 +694,16 @@ static hipError_t go_rows(int block, int grid, size_t shm, const su3i::DslashArg
     case 13: return launch_lds<SP, LP, NT, 0, 2, 2, 2, VN>(block, grid, shm, a, st);
     case 14: return launch_lds<SP, LP, NT, 0, 2, 4, 2, VN>(block, grid, shm, a, st);
     case 15: return launch_lds<SP, LP, NT, 0, 4, 2, 2, VN>(block, grid, shm, a, st);
-    default: return launch_lds<SP, LP, NT, 0, 4, 4, 2, VN>(block, grid, shm, a, st);
+    case 16: return launch_lds<SP, LP, NT, 0, 4, 4, 2, VN>(block, grid, shm, a, st);
+    default: break;
     }
+    if constexpr (!VN) {  // rows of 3 x 3: lexicographic fields only
+        if (a.lds_tile == 17)
+            return launch_lds<SP, LP, NT, 0, 3, 3, 1, VN>(block, grid, shm, a, st);
+        if (a.lds_tile == 18)
+            return launch_lds<SP, LP, NT, 0, 3, 3, 2, VN>(block, grid, shm, a, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 // The LDS-tiled walk by schedule and block (the shapes lds_shape accepts;

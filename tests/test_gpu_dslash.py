@@ -108,7 +108,7 @@ def test_dslash_parity(pair, dims):
         # the one-buffer tiles 8x8, 8x4, 16x8 and 16x4 (blocks up to 512, walks of
         # 2, 3, 5 and all of t, nontemporal link loads or not); whole x rows
         # with one and with two buffers; persistent walks over (tile, slice)
-        # spans; tiles in XCD slabs
+        # spans; tiles in XCD slabs; rows of 3 x 3 (one and two buffers)
         for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1,
                          schedule=0),
                     dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3,
@@ -168,7 +168,13 @@ def test_dslash_parity(pair, dims):
                     dict(block=256, nontemporal=2, occupancy=0, xcd_remap=2, tile_sites=3,
                          schedule=11),
                     dict(block=128, nontemporal=2, occupancy=0, xcd_remap=2, tile_sites=4096,
-                         schedule=4)):
+                         schedule=4),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=3,
+                         schedule=17),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=5,
+                         schedule=18),
+                    dict(block=256, persistent=2, nontemporal=2, occupancy=0, xcd_remap=0,
+                         tile_sites=1, schedule=18)):
             full = dict(dict(persistent=0, lds_stage=0), **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
@@ -318,7 +324,7 @@ def test_dslash_persistent_spans(pair):
     su3.su3_sync(s)
     base = su3.su3_field_download(fout, s)
     assert_dslash(sp, lp, base, want, mag, "default launch")
-    for sched in (8, 11, 12, 16):
+    for sched in (8, 11, 12, 16, 17):
         for k in (1, 2, 3):
             cfg = dict(block=256, persistent=k, nontemporal=2, xcd_remap=k & 1,
                        lds_stage=0, tile_sites=1, occupancy=0, schedule=sched)
@@ -334,9 +340,11 @@ def test_dslash_persistent_spans(pair):
 
 
 @pytest.mark.parametrize("dims,pair", [((160, 2, 2, 4), (su3.SU3_F64, su3.SU3_F64)),
+                                       ((100, 2, 3, 4), (su3.SU3_F64, su3.SU3_F64)),
                                        ((300, 2, 2, 2), (su3.SU3_F32, su3.SU3_F32)),
                                        ((64, 4, 4, 4), (su3.SU3_F32, su3.SU3_C12_F32))],
-                         ids=["f64_rows_too_long", "f32_rows_too_long", "f32c12_one_buffer"])
+                         ids=["f64_rows_too_long", "f64_rows_of_2x2", "f32_rows_too_long",
+                              "f32c12_one_buffer"])
 def test_dslash_default_fallbacks(dims, pair):
     """The default launch takes whole x rows; rows too long for a workgroup
     (or two buffers too large for the LDS) fall back to the rows with one
