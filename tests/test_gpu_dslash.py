@@ -286,22 +286,25 @@ FULL = (48, 48, 48, 48)
 
 
 def test_dslash_full_48_tuned():
-    """48^4 in the tuned launch for each precision pair; every site
-    compared with the oracle."""
+    """48^4 in the tuned launch for each precision pair, on SoA and
+    AoSoA(64) fields; every site compared with the oracle."""
     s = torch.cuda.current_stream()
     links, psi = host_inputs(FULL)
     for sp, lp in PAIRS:
-        cfg = su3.su3_autotune(su3.SU3_EXPR_DSLASH, lp, su3.SU3_LAYOUT_SOA, 0, FULL, s)
-        fu, fin = device_inputs(FULL, sp, lp, su3.SU3_LAYOUT_SOA, 0, links, psi, s)
-        fout = su3.spinor_tensor(FULL, sp, su3.SU3_LAYOUT_SOA)
-        su3.su3_dslash(fout, fu, fin, s)
-        su3.su3_sync(s)
-        got = su3.su3_field_download(fout, s)
-        del fu, fin, fout
-        torch.cuda.empty_cache()
         want, mag = reference(sp, lp, links, psi, FULL)
-        worst = assert_dslash(sp, lp, got, want, mag, f"48^4 {sp}/{lp} {cfg.as_dict()}")
-        print(f"48^4 dslash spinor {sp} links {lp}: worst {worst:.3e} launch {cfg.as_dict()}")
+        for lay, lanes in ((su3.SU3_LAYOUT_SOA, 0), (su3.SU3_LAYOUT_AOSOA, 64)):
+            cfg = su3.su3_autotune(su3.SU3_EXPR_DSLASH, lp, lay, lanes, FULL, s)
+            fu, fin = device_inputs(FULL, sp, lp, lay, lanes, links, psi, s)
+            fout = su3.spinor_tensor(FULL, sp, lay, lanes)
+            su3.su3_dslash(fout, fu, fin, s)
+            su3.su3_sync(s)
+            got = su3.su3_field_download(fout, s)
+            del fu, fin, fout
+            torch.cuda.empty_cache()
+            worst = assert_dslash(sp, lp, got, want, mag,
+                                  f"48^4 {sp}/{lp} layout {lay} {cfg.as_dict()}")
+            print(f"48^4 dslash spinor {sp} links {lp} layout {lay}: worst {worst:.3e} "
+                  f"launch {cfg.as_dict()}")
 
 
 @pytest.mark.parametrize("pair", PAIRS, ids=PAIR_IDS)

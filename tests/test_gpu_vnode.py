@@ -275,3 +275,44 @@ def test_vnode_dslash_tuned(simd):
         su3.su3_launch_reset()
     print(f"vnode {simd} tuned: {cfg.as_dict()}")
     assert np.array_equal(got, base), cfg.as_dict()
+
+
+def test_vnode_dslash_full_48_tuned():
+    """48^4 in the tuned launches the benchmark times: the hopping term on
+    virtual-node fields (N_sub = 4 and 16) equals, bit for bit, the tuned
+    hopping term on SoA fields (every kernel accumulates in one order)."""
+    s = torch.cuda.current_stream()
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    links = [testgen.su3_field(V, field_id=testgen.FID_U0 + mu) for mu in range(4)]
+    psi = testgen.spinor_field(V, field_id=203)
+    gu = []
+    for u in links:
+        f = su3.field_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+        su3.su3_field_upload(f, u, s)
+        gu.append(f)
+    gin = su3.spinor_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+    su3.su3_field_upload(gin, psi, s)
+    gout = su3.spinor_tensor(dims, su3.SU3_F64, su3.SU3_LAYOUT_SOA)
+    try:
+        su3.su3_autotune(su3.SU3_EXPR_DSLASH, su3.SU3_F64, su3.SU3_LAYOUT_SOA, 0, dims, s)
+        su3.su3_dslash(gout, gu, gin, s)
+        su3.su3_sync(s)
+        want = su3.su3_field_download(gout, s)
+        del gu, gin, gout
+        torch.cuda.empty_cache()
+        for simd in ((1, 1, 2, 2), (2, 2, 2, 2)):
+            nsub = int(np.prod(simd))
+            fu = [vfield(dims, su3.SU3_F64, simd, u, s) for u in links]
+            fin = vfield(dims, su3.SU3_F64, simd, psi, s, SP)
+            fout = su3.vnode_tensor(dims, su3.SU3_F64, simd, SP)
+            cfg = su3.su3_autotune(su3.SU3_EXPR_DSLASH, su3.SU3_F64, su3.SU3_LAYOUT_VNODE,
+                                   nsub, dims, s)
+            su3.su3_dslash(fout, fu, fin, s)
+            su3.su3_sync(s)
+            got = su3.su3_field_download(fout, s)
+            del fu, fin, fout
+            torch.cuda.empty_cache()
+            assert np.array_equal(got, want), f"{simd} {cfg.as_dict()}"
+    finally:
+        su3.su3_launch_reset()
