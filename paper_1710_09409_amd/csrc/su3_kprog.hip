@@ -811,6 +811,9 @@ static hipError_t go_t(int form, int nregs, int nt, int block, int grid,
     if (form == su3i::PF_SCALAR)
         return nregs <= 4 ? go_scalar<T, 4>(nt, block, grid, shm, a, st)
                           : go_scalar<T, 8>(nt, block, grid, shm, a, st);
+    // a product or a trace in double: two waves per SIMD instead of one
+    if (sizeof(T) == 8 && nregs <= 2)
+        return go<T, 9, 2>(nt, block, grid, shm, a, st);
     if (nregs <= 4)
         return go<T, 9, 4>(nt, block, grid, shm, a, st);
     if constexpr (sizeof(T) == 4)
