@@ -193,3 +193,35 @@ def test_program_product_full_size():
     su3.su3_mult(z2, fx, fy, s)
     su3.su3_sync(s)
     assert torch.equal(z1.owner, z2.owner)
+
+
+@pytest.mark.parametrize("prec", [su3.SU3_F64, su3.SU3_F32], ids=["f64", "f32"])
+def test_listing2_real_full_size(prec):
+    """Listing 2 on real fields at 48^4 in the launch the benchmark times
+    (the real-valued kernel): the constants 1.0 and 2.0 give 5.0 at every
+    site exactly, and seeded random fields agree with the oracle."""
+    s = torch.cuda.current_stream()
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    lay = (su3.SU3_LAYOUT_SOA, 0, None)
+    su3.su3_autotune(su3.SU3_EXPR_PROGRAM, prec, su3.SU3_LAYOUT_SOA, 0, dims, s)
+    try:
+        v1, v2, v3 = (make(dims, prec, R, lay, None, s) for _ in range(3))
+        su3.su3_program_eval(su3.Program("1.0", []), v1, [], s)
+        su3.su3_program_eval(su3.Program("2.0", []), v2, [], s)
+        prog = su3.Program("a+b+a*b", [R, R])
+        su3.su3_program_eval(prog, v3, [v1, v2], s)
+        su3.su3_sync(s)
+        assert np.array_equal(su3.su3_field_download(v3, s), np.full(V, 5.0))
+        hosts = [host_operand(V, R, k) for k in range(2)]
+        q = [quantise(h, R, prec) for h in hosts]
+        for f, h in zip((v1, v2), hosts):
+            su3.su3_field_upload(f, h, s)
+        su3.su3_program_eval(prog, v3, [v1, v2], s)
+        su3.su3_sync(s)
+        got = su3.su3_field_download(v3, s)
+        want = O.get().eval_expr("a+b+a*b", q, [int(R), int(R)], V=V)
+        err, bound = tol(got, want.reshape(got.shape), prec != su3.SU3_F64)
+        assert err <= bound, f"{err:.3e} > {bound:.3e}"
+    finally:
+        su3.su3_launch_reset()
