@@ -1085,7 +1085,7 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     const int lx = (int)(out->dims[0] / out->simd[0]);  // (outer) x extent
     LdsShape sh = {0, 0, 0, 0, 1};
     // LDS-tiled walks: schedules 4.. on lexicographic fields, the row tiles
-    // (9..16) on virtual-node fields
+    // (9..18) on virtual-node fields
     bool lds = c.schedule >= (vn ? 9 : 4);
     if (lds && !lds_shape(c.schedule, c.block, cbytes, lx, nsub, sh)) {
         // buffers too large: the same rows with one buffer, else rows of

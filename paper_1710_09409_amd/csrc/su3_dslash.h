@@ -60,7 +60,7 @@ struct LdsShape {
 // fields only (nsub 1).
 // Schedules 9..12 take rows, tx x 2 x 2, tx x 2 x 4, tx x 4 x 2,
 // tx x 4 x 4 (outer) sites, with one buffer, 13..16 the same with two, 17
-// and 18 tx x 3 x 3 with one and two (lexicographic fields only); B is
+// and 18 tx x 3 x 3 with one and two; B is
 // ignored: tx is the lattice's (outer) x extent lx when nsub * lx * ty * tz
 // lanes fit a workgroup (rows_max_lanes), else (virtual-node fields only)
 // the largest divisor of lx that does, and the buffers must fit the 160 KiB
@@ -81,9 +81,7 @@ inline bool lds_shape(int schedule, int block, int cbytes, int lx, int nsub, Lds
         const int r = (schedule - 9) % 4;
         const long maxl = rows_max_lanes(cbytes, nsub);
         if (schedule >= 17) {
-            if (nsub != 1)
-                return false;
-            s = {lx, 3, 3, schedule == 18 ? 2 : 1, 1};
+            s = {lx, 3, 3, schedule == 18 ? 2 : 1, nsub};
         } else {
             s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1, nsub};
         }

@@ -697,12 +697,10 @@ static hipError_t go_rows(int block, int grid, size_t shm, const su3i::DslashArg
     case 16: return launch_lds<SP, LP, NT, 0, 4, 4, 2, VN>(block, grid, shm, a, st);
     default: break;
     }
-    if constexpr (!VN) {  // rows of 3 x 3: lexicographic fields only
-        if (a.lds_tile == 17)
-            return launch_lds<SP, LP, NT, 0, 3, 3, 1, VN>(block, grid, shm, a, st);
-        if (a.lds_tile == 18)
-            return launch_lds<SP, LP, NT, 0, 3, 3, 2, VN>(block, grid, shm, a, st);
-    }
+    if (a.lds_tile == 17)
+        return launch_lds<SP, LP, NT, 0, 3, 3, 1, VN>(block, grid, shm, a, st);
+    if (a.lds_tile == 18)
+        return launch_lds<SP, LP, NT, 0, 3, 3, 2, VN>(block, grid, shm, a, st);
     return hipErrorInvalidValue;
 }
 

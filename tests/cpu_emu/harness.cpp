@@ -463,15 +463,16 @@ int main(int argc, char **argv)
                 }
                 // one site per lane, then row tiles of outer sites with all
                 // their virtual nodes (one and two buffers, walks, persistent
-                // shares, XCD slabs), then the default launch
+                // shares, XCD slabs, rows of 3 x 3), then the default launch
                 const int nsub = c.simd[0] * c.simd[1] * c.simd[2] * c.simd[3];
-                su3_launch vcs[7] = {{64, 0, 2, 0, 0, 1, 0, 0}, {256, 0, 2, 0, 0, 2, 0, 9},
+                su3_launch vcs[9] = {{64, 0, 2, 0, 0, 1, 0, 0}, {256, 0, 2, 0, 0, 2, 0, 9},
                                      {256, 0, 2, 1, 0, 4096, 0, 12}, {256, 0, 2, 0, 0, 3, 0, 13},
                                      {256, 2, 2, 0, 0, 1, 0, 16}, {256, 0, 2, 2, 0, 1, 0, 11},
+                                     {256, 0, 2, 0, 0, 3, 0, 17}, {256, 1, 2, 1, 0, 1, 0, 18},
                                      {0, 0, 0, 0, 0, 0, 0, 0}};
                 std::vector<double> got0(24 * V);
-                for (int k = 0; k < 7; ++k) {
-                    if (k < 6)
+                for (int k = 0; k < 9; ++k) {
+                    if (k < 8)
                         su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, SU3_LAYOUT_VNODE, nsub, d, &vcs[k]);
                     else
                         su3_launch_reset();

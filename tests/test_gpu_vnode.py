@@ -102,7 +102,7 @@ def test_vnode_dslash(dims, simd):
         want, mag = reference(sp, lp, links, psi, dims)
         # one site per lane, then row tiles of outer sites with all their
         # virtual nodes (one and two buffers, walks, persistent shares, XCD
-        # slabs), then the default launch: all bit-identical
+        # slabs, rows of 3 x 3), then the default launch: all bit-identical
         nsub = int(np.prod(simd))
         first = None
         for cfg in (dict(block=64, schedule=0, tile_sites=1),
@@ -111,6 +111,8 @@ def test_vnode_dslash(dims, simd):
                     dict(block=256, schedule=13, tile_sites=3),
                     dict(block=256, schedule=16, tile_sites=1, persistent=2),
                     dict(block=256, schedule=11, tile_sites=1, xcd_remap=2),
+                    dict(block=256, schedule=17, tile_sites=3),
+                    dict(block=256, schedule=18, tile_sites=1, persistent=1, xcd_remap=1),
                     None):
             if cfg is not None:
                 full = dict(dict(persistent=0, nontemporal=2, xcd_remap=0, lds_stage=0,
