@@ -7,19 +7,27 @@ streaming test of Section 4, Listing 3).  Inputs are seeded synthetic
 Haar-random SU(3) fields already resident in HBM; the timed region is K
 back-to-back launches bracketed by device synchronisation.
 
-Prints ONE JSON line on stdout (progress goes to stderr):
+Prints ONE JSON line on stdout (progress and launch settings go to stderr):
   value        achieved GB/s = 432 B/site * V / (time per step)
   roofline     the dominant kernel against the 8 TB/s HBM peak, timed with
                HIP events on the launch stream; traffic from the committed
                PMC summary (null if the kernel changed since)
   cpu_baseline the FP64 oracle on the host cores, on a bounded sample
-  variants     the precision forms (F32, F16 with F32 arithmetic, two-row
-               compressed F32) at 48^4, the layouts (AoS, AoS+LDS, AoSoA),
-               the volume sweep, the shifted operands, the Wilson hopping
-               term at 48^4, expression programs at 48^4, fused vs
-               chained expressions at 32^4, the
-               64-lattice batch replayed from a HIP graph, and the triad
-               ceiling -- each in GB/s of its own algorithmic bytes
+  variants     every other configuration, each in GB/s of its own
+               algorithmic bytes and % of 8 TB/s, with the oracle's rate on
+               the same inputs beside it ("cpu": [all threads, one thread],
+               GB/s of the same byte accounting): the tuned bandwidth
+               ceilings (triad, read-only, write-only, copy), the precision
+               forms at 48^4 (with their error against the FP64 product),
+               the layouts, the volume sweep (hot and cold), the t-slab
+               shard, the precision forms at 32^4, the shifted operands,
+               the Wilson hopping term, Grid's virtual-node layout,
+               expression programs, fused vs chained expressions at 32^4
+               (hot and cold) and the 64-lattice batch (persistent and
+               one-shot grids, graph replays)
+
+`--only a,b` runs just those sections (precision, fused, ceiling, dslash,
+batch) with the tuned or cached launches, for profiler runs.
 """
 from __future__ import annotations
 
@@ -34,6 +42,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+MALL_BYTES = 268435456  # the 256 MiB Infinity Cache
 METRIC = ("SU(3)×SU(3) achieved HBM GB/s (% of peak) at 48^4, "
           "FP64 vs FP32/compressed")
 
@@ -49,6 +58,7 @@ REAL_BYTES = {0: 8, 1: 4, 2: 2, 3: 4}
 DSLASH_BYTES_PER_SITE = {(0, 0): 960, (1, 1): 480, (1, 3): 384}
 DSLASH_FLOPS_PER_SITE = 1320
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16_f32acc", 3: "c12_f32"}
+SECTIONS = ("precision", "fused", "ceiling", "dslash", "batch")
 
 
 def log(*a):
@@ -60,6 +70,18 @@ def expr_bytes_per_site(prec, expr):
     site = E * 2 * REAL_BYTES[prec]
     nops = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}[expr]
     return site * (nops + 1)
+
+
+def gbps(nbytes, ms):
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def entry(ms, nbytes, **extra):
+    """Compact record of one timing: microseconds, GB/s, % of 8 TB/s."""
+    g = gbps(nbytes, ms)
+    out = {"us": round(ms * 1e3, 1), "gbps": round(g), "pct": round(100 * g / HBM_PEAK_GBPS, 1)}
+    out.update(extra)
+    return out
 
 
 def parse():
@@ -74,9 +96,11 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="no autotuning: the library's default launch, or the "
                          "one cached in the file SU3_TUNE_CACHE names")
-    ap.add_argument("--only-dslash", action="store_true",
-                    help="time only the Wilson hopping term (48^4, FP64, "
-                         "SoA) and print its line (for profiler runs)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated sections to run alone (%s), without "
+                         "the headline (for profiler runs)" % ", ".join(SECTIONS))
+    ap.add_argument("--layout", default="both", choices=("soa", "aosoa64", "both"),
+                    help="layouts of the precision section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain copies of known size (PMC scaling)")
     return ap.parse_args()
@@ -140,6 +164,68 @@ def committed_traffic():
         return None
 
 
+class CpuLeg:
+    """The oracle timed on the host cores beside each configuration.  Jobs
+    are queued while the GPU runs and executed after it, so that host work
+    never overlaps a GPU measurement.  Each job fills target[key] with
+    [GB/s on all the oracle's threads, GB/s on one thread] of the same byte
+    accounting as the GPU figure."""
+
+    def __init__(self, enabled):
+        self.enabled = enabled
+        self.jobs = []
+        self.checks = []
+        self.orc = None
+
+    def add(self, target, key, fn, nbytes, min_s=0.4):
+        if self.enabled:
+            self.jobs.append((target, key, fn, nbytes, min_s))
+
+    def check(self, target, key, fn):
+        """A post-run comparison of a GPU result with the oracle."""
+        if self.enabled:
+            self.checks.append((target, key, fn))
+
+    def oracle(self):
+        if self.orc is None:
+            import oracle
+            self.orc = oracle.get()
+        return self.orc
+
+    @staticmethod
+    def _timed(fn, min_s):
+        passes, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= min_s:
+                return passes, el
+
+    def rate(self, fn, nbytes, min_s):
+        orc = self.oracle()
+        threads = orc.threads()
+        p, el = self._timed(fn, min_s)
+        orc.set_threads(1)
+        try:
+            p1, el1 = self._timed(fn, min_s)
+        finally:
+            orc.set_threads(threads)
+        return [round(nbytes * p / el / 1e9, 2), round(nbytes * p1 / el1 / 1e9, 3)]
+
+    def run(self):
+        if not self.enabled:
+            return
+        orc = self.oracle()
+        t0 = time.perf_counter()
+        for target, key, fn, nbytes, min_s in self.jobs:
+            target[key] = self.rate(lambda: fn(orc), nbytes, min_s)
+        for target, key, fn in self.checks:
+            target[key] = fn(orc)
+        log(f"cpu leg: {len(self.jobs)} oracle timings and {len(self.checks)} checks "
+            f"in {time.perf_counter() - t0:.1f} s on {orc.threads()} threads")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -148,6 +234,10 @@ def main():
               "into t-slabs with no exchange step (the hopping term would add "
               "a t-face halo)", file=sys.stderr)
         sys.exit(2)
+    only = [s for s in args.only.split(",") if s]
+    for s in only:
+        if s not in SECTIONS:
+            sys.exit(f"unknown section {s!r}; sections: {', '.join(SECTIONS)}")
 
     import numpy as np
     import torch
@@ -158,7 +248,6 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    timer = Timer(torch, stream)
     props = torch.cuda.get_device_properties(0)
     log(f"device: {props.name} ({getattr(props, 'gcnArchName', '?')}), "
         f"{props.multi_processor_count} CUs")
@@ -176,15 +265,28 @@ def main():
         su3.su3_field_upload(f, host_field(testgen.volume(dims), fid), stream)
         return f
 
-    def tune(expr, prec, layout, lanes, dims):
+    def tune(expr, prec, layout, lanes, dims, label=None):
         if args.no_tune:
-            return su3.su3_launch_get(expr, prec, layout, lanes, dims).as_dict()
-        return su3.su3_autotune(expr, prec, layout, lanes, dims, stream).as_dict()
+            cfg = su3.su3_launch_get(expr, prec, layout, lanes, dims).as_dict()
+        else:
+            cfg = su3.su3_autotune(expr, prec, layout, lanes, dims, stream).as_dict()
+        if label:
+            log(f"launch {label}: {cfg}")
+        return cfg
 
-    if args.only_dslash:
-        dslash_only(args, su3, torch, testgen, stream, timer, make, tune)
+    ctx = dict(args=args, su3=su3, torch=torch, np=np, testgen=testgen,
+               stream=stream, timer=Timer(torch, stream), make=make, tune=tune,
+               host_field=host_field, cpu=CpuLeg(not args.no_cpu_baseline))
+
+    if only:
+        out = {}
+        for s in only:
+            out[s] = SECTION_FUNCS[s](ctx)
+        ctx["cpu"].run()
+        print(json.dumps(out, separators=(",", ":")), flush=True)
         return
 
+    timer = ctx["timer"]
     # ------------------------------------------------------------ headline
     dims = (48, 48, 48, 48)
     V = testgen.volume(dims)
@@ -193,28 +295,16 @@ def main():
     x = make(dims, F64, SOA, 0, testgen.FID_X)
     y = make(dims, F64, SOA, 0, testgen.FID_Y)
     z = su3.field_tensor(dims, F64, SOA, 0)
-    cfg = tune(su3.SU3_EXPR_MUL, F64, SOA, 0, dims)
-    log(f"launch: {cfg}")
+    cfg = tune(su3.SU3_EXPR_MUL, F64, SOA, 0, dims, "headline")
     step_bytes = BYTES_PER_SITE[0] * V
     ms_ev, host_s = timer.run(lambda: su3.su3_mult(z, x, y, stream),
                               args.steps, args.warmup)
     ms_per_step = host_s * 1e3 / args.steps
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
-    achieved = step_bytes / (ms_ev * 1e-3) / 1e9
+    achieved = gbps(step_bytes, ms_ev)
     log(f"headline: {ms_ev * 1e3:.1f} us/launch (events), {achieved:.0f} GB/s "
         f"= {100 * achieved / HBM_PEAK_GBPS:.1f}% of 8 TB/s")
     traffic = committed_traffic()
-
-    # triad ceiling over the same bytes (2 read streams + 1 write stream)
-    n = step_bytes // 24
-    ta = torch.empty(n, dtype=torch.float64, device="cuda")
-    tb = torch.ones(n, dtype=torch.float64, device="cuda")
-    tc = torch.ones(n, dtype=torch.float64, device="cuda")
-    ms_tr, _ = timer.run(lambda: su3.su3_triad(ta.data_ptr(), tb.data_ptr(),
-                                               tc.data_ptr(), 3.0, n, stream),
-                         args.steps, args.warmup)
-    triad = 24 * n / (ms_tr * 1e-3) / 1e9
-    log(f"triad: {triad:.0f} GB/s")
     if args.calibrate_copy:
         nbytes = 1 << 30
         cs = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -223,19 +313,20 @@ def main():
             su3.su3_copy(cd.data_ptr(), cs.data_ptr(), nbytes, stream)
         torch.cuda.synchronize()
         del cs, cd
-    del ta, tb, tc
 
-    variants = {"triad_gbps": round(triad, 1),
-                "headline_frac_of_triad": round(achieved / triad, 4)}
-
+    ctx.update(x64=x, y64=y, z64=z, ms_f64=ms_ev, headline_bytes=step_bytes)
+    variants = {}
     if not args.no_variants:
-        variants.update(run_variants(args, su3, torch, testgen, np, stream,
-                                     timer, make, tune, x, y, z, dims, ms_ev))
+        variants["ceiling"] = section_ceiling(ctx)
+        variants["ceiling"]["headline_of_triad"] = round(
+            variants["ceiling"]["triad"]["us"] / (ms_ev * 1e3), 4)
+        run_variants(ctx, variants)
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(host_field(V, testgen.FID_X),
+        ctx["cpu"].run()
+        cpu = cpu_baseline(ctx["cpu"], host_field(V, testgen.FID_X),
                            host_field(V, testgen.FID_Y))
         cpu["gpu_over_cpu"] = round(value / cpu["value"], 1)
 
@@ -255,12 +346,12 @@ def main():
         "config": {
             "workload": "su3_mult z=x*y, 48^4 lattice (5,308,416 sites), FP64 "
                         "storage and arithmetic, SoA layout, 432 B/site",
-            "dims": list(dims), "sites": V, "bytes_per_step": step_bytes,
+            "sites": V, "bytes_per_step": step_bytes,
             "flops_per_step": FLOPS_PER_SITE[0] * V,
             "gflops": round(FLOPS_PER_SITE[0] * V / (ms_ev * 1e-3) / 1e9, 1),
-            "launch": cfg,
-            "input_sha256": {"x": testgen.buffer_sha256(host_field(V, testgen.FID_X))[:16],
-                             "y": testgen.buffer_sha256(host_field(V, testgen.FID_Y))[:16]},
+            "launch": "block %d, occupancy %d, schedule %d, nontemporal %d, "
+                      "sites/lane %d" % (cfg["block"], cfg["occupancy"], cfg["schedule"],
+                                         cfg["nontemporal"], cfg["sites_per_lane"]),
         },
         "roofline": {
             "bound": "hbm",
@@ -269,294 +360,157 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "kernel": "k_site<MUL, 1 site/lane> (FP64 SoA)",
+            "kernel": "k_site<MUL> FP64 SoA",
             "avg_launch_us": round(ms_ev * 1e3, 2),
             "bytes_per_launch": step_bytes,
         },
         "cpu_baseline": cpu,
         "variants": variants,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, separators=(",", ":")), flush=True)
 
 
-def dslash_only(args, su3, torch, testgen, stream, timer, make, tune):
+# ------------------------------------------------------------- sections
+
+def section_ceiling(ctx):
+    """The STREAM-style yardsticks over the headline's bytes (arrays of a
+    third of 2.29 GB each), each tuned over block, occupancy and store
+    policy: triad (2:1 read:write, the product's mix), read-only,
+    write-only, copy (1:1)."""
+    su3, torch, stream, timer = ctx["su3"], ctx["torch"], ctx["stream"], ctx["timer"]
+    args = ctx["args"]
+    nb = 2293235712 // 3  # 764,411,904 bytes per array (the headline's)
+    arrs = [torch.ones(nb // 8, dtype=torch.float64, device="cuda") for _ in range(3)]
+    a, b, c = (t.data_ptr() for t in arrs)
+    steps = max(10, min(args.steps, 50))
+    out = {}
+    for kind, name, traffic in ((su3.SU3_STREAM_TRIAD, "triad", 3 * nb),
+                                (su3.SU3_STREAM_READ, "read", 2 * nb),
+                                (su3.SU3_STREAM_WRITE, "write", nb),
+                                (su3.SU3_STREAM_COPY, "copy", 2 * nb)):
+        if args.no_tune:
+            best = None
+        else:
+            best, _ = su3.su3_stream_autotune(kind, a, b, c, nb, stream)
+        ms, _ = timer.run(lambda: su3.su3_stream(kind, a, b, c, 3.0, nb, best, stream),
+                          steps, 3)
+        cfg = best.as_dict() if best is not None else {}
+        out[name] = entry(ms, traffic, block=cfg.get("block"), occ=cfg.get("occupancy"),
+                          nt=cfg.get("nontemporal"))
+        log(f"ceiling {name}: {out[name]} {cfg}")
+    del arrs
+    torch.cuda.synchronize()
+    return out
+
+
+def section_precision(ctx):
+    """z = x*y at 48^4 in FP32, FP16 (FP32 arithmetic) and two-row
+    compressed FP32, SoA and AoSoA(64): speed-up over the FP64 product, and
+    (SoA) the end-to-end error against the FP64 oracle product."""
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args, cpu, host_field = ctx["args"], ctx["cpu"], ctx["host_field"]
     dims = (48, 48, 48, 48)
     V = testgen.volume(dims)
-    F64, SOA = su3.SU3_F64, su3.SU3_LAYOUT_SOA
-    log(f"Dslash: {V} sites, FP64 SoA; generating inputs")
-    U = [make(dims, F64, SOA, 0, testgen.FID_U0 + mu) for mu in range(4)]
-    fin = su3.spinor_tensor(dims, F64, SOA)
-    su3.su3_field_upload(fin, testgen.spinor_field(V, seed=args.seed, field_id=200), stream)
-    fout = su3.spinor_tensor(dims, F64, SOA)
-    cfg = tune(su3.SU3_EXPR_DSLASH, F64, SOA, 0, dims)
-    ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), args.steps, args.warmup)
-    b = DSLASH_BYTES_PER_SITE[(0, 0)] * V
-    print(json.dumps({"kernel": "k_dslash (FP64 SoA 48^4)", "us": round(ms * 1e3, 2),
-                      "gbps": round(b / (ms * 1e-3) / 1e9, 1),
-                      "bytes_per_launch": b, "launch": cfg}), flush=True)
-
-
-def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
-                 x64, y64, z64, dims, ms_f64):
-    out = {}
-    V = testgen.volume(dims)
     steps = max(10, min(args.steps, 50))
-    SOA, AOS, AOSOA = su3.SU3_LAYOUT_SOA, su3.SU3_LAYOUT_AOS, su3.SU3_LAYOUT_AOSOA
+    SOA, AOSOA = su3.SU3_LAYOUT_SOA, su3.SU3_LAYOUT_AOSOA
+    lays = [("soa", SOA, 0), ("aosoa64", AOSOA, 64)]
+    if args.layout != "both":
+        lays = [l for l in lays if l[0] == args.layout]
+    hx, hy = host_field(V, testgen.FID_X), host_field(V, testgen.FID_Y)
+    out = {}
+    z64_ref = {}
 
-    # precision forms at 48^4 (SoA)
-    prec_out = {}
+    def f64_product(orc):
+        if "z" not in z64_ref:
+            z64_ref["z"] = orc.mult(hx, hy)
+        return z64_ref["z"]
+
     for prec in (su3.SU3_F32, su3.SU3_F16_F32ACC, su3.SU3_C12_F32):
-        for lname, lay, lanes in (("soa", SOA, 0), ("aosoa64", AOSOA, 64)):
+        for lname, lay, lanes in lays:
             x = make(dims, prec, lay, lanes, testgen.FID_X)
             y = make(dims, prec, lay, lanes, testgen.FID_Y)
             z = su3.field_tensor(dims, prec, lay, lanes)
-            cfg = tune(su3.SU3_EXPR_MUL, prec, lay, lanes, dims)
+            tune(su3.SU3_EXPR_MUL, prec, lay, lanes, dims, f"precision {prec} {lname}")
             ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
             b = BYTES_PER_SITE[prec] * V
             key = f"{PREC_NAME[prec]}_{lname}"
-            prec_out[key] = {
-                "us": round(ms * 1e3, 2), "gbps": round(b / (ms * 1e-3) / 1e9, 1),
-                "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                "speedup_vs_f64_soa": round(ms_f64 / ms, 3), "launch": cfg}
-            log(f"precision {key}: {prec_out[key]}")
+            e = entry(ms, b)
+            if "ms_f64" in ctx:
+                e["x_f64"] = round(ctx["ms_f64"] / ms, 2)
+            out[key] = e
+            if lname == "soa" and cpu.enabled:
+                zh = su3.su3_field_download(z, stream)
+
+                def err(orc, zh=zh):
+                    m = orc.metrics(zh, f64_product(orc))
+                    return [float("%.2e" % m["e_max"]), float("%.2e" % m["d_u"])]
+                cpu.check(e, "err", err)
+                cpu.add(e, "cpu", lambda orc, p=prec: orc.reference(0, p, [hx, hy]), b,
+                        min_s=0.3)
+            log(f"precision {key}: {e}")
             del x, y, z
-    out["precision_48^4"] = prec_out
+    return out
 
-    # layouts at 48^4 (FP64)
-    lay_out = {}
-    cases = [("aos", AOS, 0, 0), ("aos_lds", AOS, 0, 1)] + \
-        [(f"aosoa{L}", AOSOA, L, 0) for L in (8, 16, 32, 64)]
-    for name, lay, lanes, lds in cases:
-        x = make(dims, su3.SU3_F64, lay, lanes, testgen.FID_X)
-        y = make(dims, su3.SU3_F64, lay, lanes, testgen.FID_Y)
-        z = su3.field_tensor(dims, su3.SU3_F64, lay, lanes)
-        if lay == AOS:
-            cfg = su3.su3_launch_get(0, 0, lay, lanes, dims).as_dict()
-            cfg.update(lds_stage=lds, block=64)
-            su3.su3_launch_set(0, 0, lay, lanes, dims, cfg)
+
+def hot_and_cold(ctx, d, prec, fid_x, fid_y, cpu_rate=True):
+    """z = x*y at lattice d (SoA): hot (the same buffers every launch) and
+    cold (rotating through k buffer sets of >= 1 GiB in all, so the 256 MiB
+    Infinity Cache never holds the next launch's operands)."""
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args, cpu, host_field = ctx["args"], ctx["cpu"], ctx["host_field"]
+    SOA = su3.SU3_LAYOUT_SOA
+    steps = max(10, min(args.steps, 50))
+    Vd = testgen.volume(d)
+    ws = BYTES_PER_SITE[prec] * Vd
+    x = make(d, prec, SOA, 0, fid_x)
+    y = make(d, prec, SOA, 0, fid_y)
+    z = su3.field_tensor(d, prec, SOA, 0)
+    tune(su3.SU3_EXPR_MUL, prec, SOA, 0, d, f"{d} prec {prec}")
+    ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
+    k = max(2, -(-(1 << 30) // ws))
+    sets = [(x, y, z)]
+    for _ in range(k - 1):
+        xi = su3.field_tensor(d, prec, SOA, 0)
+        yi = su3.field_tensor(d, prec, SOA, 0)
+        xi.owner.copy_(x.owner)
+        yi.owner.copy_(y.owner)
+        sets.append((xi, yi, su3.field_tensor(d, prec, SOA, 0)))
+    turn = [0]
+
+    def rotating():
+        xs, ys, zs = sets[turn[0] % k]
+        turn[0] += 1
+        su3.su3_mult(zs, xs, ys, stream)
+
+    ms_cold, _ = timer.run(rotating, max(steps, 2 * k), k)
+    del sets
+    e = entry(ms, ws)
+    c = entry(ms_cold, ws)
+    e.update(cold_us=c["us"], cold_gbps=c["gbps"], cold_pct=c["pct"], sets=k,
+             cached=ws < 2 * MALL_BYTES)
+    if cpu_rate:
+        hx, hy = host_field(Vd, fid_x), host_field(Vd, fid_y)
+        if prec == su3.SU3_F64:
+            cpu.add(e, "cpu", lambda orc: orc.mult(hx, hy), ws)
         else:
-            cfg = tune(su3.SU3_EXPR_MUL, su3.SU3_F64, lay, lanes, dims)
-        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
-        lay_out[name] = {"us": round(ms * 1e3, 2),
-                         "gbps": round(432 * V / (ms * 1e-3) / 1e9, 1),
-                         "launch": cfg}
-        log(f"layout {name}: {lay_out[name]}")
-        del x, y, z
-    out["layouts_f64_48^4"] = lay_out
+            cpu.add(e, "cpu", lambda orc: orc.reference(0, prec, [hx, hy]), ws)
+    return e
 
-    def hot_and_cold(d, prec, fid_x, fid_y):
-        """z = x*y at lattice d (SoA): hot (the same buffers every launch)
-        and cold (rotating through k buffer sets of >= 1 GiB in all, so the
-        256 MiB Infinity Cache never holds the next launch's operands)."""
-        Vd = testgen.volume(d)
-        ws = BYTES_PER_SITE[prec] * Vd
-        x = make(d, prec, SOA, 0, fid_x)
-        y = make(d, prec, SOA, 0, fid_y)
-        z = su3.field_tensor(d, prec, SOA, 0)
-        cfg = tune(su3.SU3_EXPR_MUL, prec, SOA, 0, d)
-        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
-        k = max(2, -(-(1 << 30) // ws))
-        sets = [(x, y, z)]
-        for _ in range(k - 1):
-            xi = su3.field_tensor(d, prec, SOA, 0)
-            yi = su3.field_tensor(d, prec, SOA, 0)
-            xi.owner.copy_(x.owner)
-            yi.owner.copy_(y.owner)
-            sets.append((xi, yi, su3.field_tensor(d, prec, SOA, 0)))
-        turn = [0]
 
-        def rotating():
-            xs, ys, zs = sets[turn[0] % k]
-            turn[0] += 1
-            su3.su3_mult(zs, xs, ys, stream)
-
-        ms_cold, _ = timer.run(rotating, max(steps, 2 * k), k)
-        del sets
-        return {"us": round(ms * 1e3, 2), "gbps": round(ws / (ms * 1e-3) / 1e9, 1),
-                "cold_us": round(ms_cold * 1e3, 2),
-                "cold_gbps": round(ws / (ms_cold * 1e-3) / 1e9, 1),
-                "cold_frac_of_peak": round(ws / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                "cold_sets": k, "working_set_bytes": ws,
-                "cache_resident": ws < 2 * 268435456, "launch": cfg}
-
-    # volume sweep (FP64 SoA); sizes below 2x the 256 MiB Infinity Cache
-    # are cache-resident when hot, not HBM figures: the cold figures are
-    sweep = {}
-    for L in (16, 24, 32):
-        d = (L, L, L, L)
-        sweep[f"{L}^4"] = hot_and_cold(d, su3.SU3_F64, 10 + L, 11 + L)
-        log(f"sweep {L}^4: {sweep[f'{L}^4']}")
-    sweep["48^4"] = {"us": round(ms_f64 * 1e3, 2),
-                     "gbps": round(432 * V / (ms_f64 * 1e-3) / 1e9, 1),
-                     "working_set_bytes": 432 * V, "cache_resident": False}
-    out["sweep_f64_soa"] = sweep
-
-    # one GPU's share of a 48^4 lattice cut into 8 t-slabs: 48^3 x 6 sites,
-    # 287 MB of operands, just above the Infinity Cache, so the cold figure
-    # is the HBM one
-    shard = hot_and_cold((48, 48, 48, 6), su3.SU3_F64, 60, 61)
-    log(f"shard 48^3x6: {shard}")
-    out["shard_f64_soa_48^3x6"] = shard
-
-    # storage precisions at 32^4 (SoA): every working set fits the Infinity
-    # Cache, so the cold figures are the HBM ones
-    p32 = {}
-    for prec in (su3.SU3_F64, su3.SU3_F32, su3.SU3_F16_F32ACC, su3.SU3_C12_F32):
-        p32[PREC_NAME[prec]] = hot_and_cold((32, 32, 32, 32), prec, 40, 41)
-        log(f"precision 32^4 {PREC_NAME[prec]}: {p32[PREC_NAME[prec]]}")
-    out["precision_32^4"] = p32
-
-    # shifted operands at 48^4 (FP64 SoA): Cshift moves 288 B/site, the
-    # product with a shifted operand 432 B/site
-    shift = {}
-    tune(su3.SU3_EXPR_CSHIFT, su3.SU3_F64, SOA, 0, dims)
-    tune(su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_F64, SOA, 0, dims)
-    for mu in range(4):
-        ms_c, _ = timer.run(lambda: su3.su3_cshift(z64, y64, mu, 1, stream), steps, 3)
-        ms_m, _ = timer.run(lambda: su3.su3_mult_shifted(z64, x64, y64, mu, 1, stream),
-                            steps, 3)
-        shift[f"mu{mu}"] = {
-            "cshift_us": round(ms_c * 1e3, 2),
-            "cshift_gbps": round(288 * V / (ms_c * 1e-3) / 1e9, 1),
-            "mult_shifted_us": round(ms_m * 1e3, 2),
-            "mult_shifted_gbps": round(432 * V / (ms_m * 1e-3) / 1e9, 1)}
-        log(f"shift mu {mu}: {shift[f'mu{mu}']}")
-    out["shift_f64_48^4"] = shift
-
-    # Wilson hopping term at 48^4: algorithmic bytes per site = four link
-    # matrices + one input spinor + one output spinor, each moved once
-    # (F64: 4*144 + 192 + 192 = 960; F32: 480; F32 with compressed links:
-    # 4*48 + 96 + 96 = 384); 1320 flops per site
-    dsl = {}
-    host_psi = testgen.spinor_field(V, seed=args.seed, field_id=200)
-    for sp, lp, name in ((su3.SU3_F64, su3.SU3_F64, "f64"), (su3.SU3_F32, su3.SU3_F32, "f32"),
-                         (su3.SU3_F32, su3.SU3_C12_F32, "f32_c12")):
-        for lname, lay, lanes in (("soa", SOA, 0), ("aosoa64", AOSOA, 64)):
-            U = [make(dims, lp, lay, lanes, testgen.FID_U0 + mu) for mu in range(4)]
-            fin = su3.spinor_tensor(dims, sp, lay, lanes)
-            su3.su3_field_upload(fin, host_psi, stream)
-            fout = su3.spinor_tensor(dims, sp, lay, lanes)
-            cfg = tune(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims)
-            ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
-            b = DSLASH_BYTES_PER_SITE[(sp, lp)] * V
-            key = f"{name}_{lname}"
-            dsl[key] = {"us": round(ms * 1e3, 2),
-                        "gbps": round(b / (ms * 1e-3) / 1e9, 1),
-                        "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                        "gflops": round(DSLASH_FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
-                        "bytes_per_site": DSLASH_BYTES_PER_SITE[(sp, lp)],
-                        "launch": cfg}
-            log(f"dslash {key}: {dsl[key]}")
-            del U, fin, fout
-    out["dslash_48^4"] = dsl
-
-    # the hopping term at the same t-slab's shape (periodic in t over its 6
-    # slices: the traffic and work of a slab without its halo exchange);
-    # 637 MB of operands, more than twice the Infinity Cache
-    ds = (48, 48, 48, 6)
-    Vs = testgen.volume(ds)
-    U = [make(ds, su3.SU3_F64, SOA, 0, 60 + mu) for mu in range(4)]
-    fin = su3.spinor_tensor(ds, su3.SU3_F64, SOA, 0)
-    su3.su3_field_upload(fin, testgen.spinor_field(Vs, seed=args.seed, field_id=201),
-                         stream)
-    fout = su3.spinor_tensor(ds, su3.SU3_F64, SOA, 0)
-    cfg = tune(su3.SU3_EXPR_DSLASH, su3.SU3_F64, SOA, 0, ds)
-    ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
-    b = DSLASH_BYTES_PER_SITE[(su3.SU3_F64, su3.SU3_F64)] * Vs
-    out["dslash_shard_f64_soa_48^3x6"] = {
-        "us": round(ms * 1e3, 2), "gbps": round(b / (ms * 1e-3) / 1e9, 1),
-        "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-        "launch": cfg}
-    log(f"dslash shard 48^3x6: {out['dslash_shard_f64_soa_48^3x6']}")
-    del U, fin, fout
-
-    # Grid's virtual-node layout used in place (N_sub sites per outer site,
-    # one per virtual node): the streaming product and the hopping term in
-    # FP64 on the same inputs, for N_sub = 4 (t and z split in two, Grid's
-    # usual split) and 16 (every direction split in two)
-    vn = {}
-    hosts = {fid: testgen.su3_field(V, seed=args.seed, field_id=fid)
-             for fid in (testgen.FID_X, testgen.FID_Y) +
-             tuple(testgen.FID_U0 + mu for mu in range(4))}
-    host_x, host_y = hosts[testgen.FID_X], hosts[testgen.FID_Y]
-    for nsub, simd in ((4, (1, 1, 2, 2)), (16, (2, 2, 2, 2))):
-        F64, VN = su3.SU3_F64, su3.SU3_LAYOUT_VNODE
-
-        def vfield(host, kind=su3.SU3_KIND_MATRIX):
-            f = su3.vnode_tensor(dims, F64, simd, kind)
-            su3.su3_field_upload(f, host, stream)
-            return f
-
-        fx, fy = vfield(host_x), vfield(host_y)
-        fz = su3.vnode_tensor(dims, F64, simd)
-        cfg = tune(su3.SU3_EXPR_MUL, F64, VN, nsub, dims)
-        ms, _ = timer.run(lambda: su3.su3_mult(fz, fx, fy, stream), steps, 3)
-        b = BYTES_PER_SITE[F64] * V
-        vn[f"mul_nsub{nsub}"] = {"us": round(ms * 1e3, 2),
-                                 "gbps": round(b / (ms * 1e-3) / 1e9, 1),
-                                 "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                                 "simd": list(simd), "launch": cfg}
-        log(f"vnode mul nsub {nsub}: {vn[f'mul_nsub{nsub}']}")
-        del fx, fy, fz
-        U = [vfield(hosts[testgen.FID_U0 + mu]) for mu in range(4)]
-        fin = vfield(host_psi, su3.SU3_KIND_SPINOR)
-        fout = su3.vnode_tensor(dims, F64, simd, su3.SU3_KIND_SPINOR)
-        cfg = tune(su3.SU3_EXPR_DSLASH, F64, VN, nsub, dims)
-        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
-        b = DSLASH_BYTES_PER_SITE[(F64, F64)] * V
-        vn[f"dslash_nsub{nsub}"] = {"us": round(ms * 1e3, 2),
-                                    "gbps": round(b / (ms * 1e-3) / 1e9, 1),
-                                    "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                                    "simd": list(simd), "launch": cfg}
-        log(f"vnode dslash nsub {nsub}: {vn[f'dslash_nsub{nsub}']}")
-        del U, fin, fout
-    del host_psi, host_x, host_y, hosts
-    out["vnode_f64_48^4"] = vn
-
-    # expression programs at 48^4 (one precompiled kernel interpreting the
-    # host-compiled expression): Listing 2 on double fields (two real
-    # inputs, one real output: 24 B/site), the streaming product, the
-    # MULADD shape and a trace into a complex field, each against its
-    # algorithmic bytes; the fixed-expression kernels beside them
-    progs = {}
-    M, R, C = su3.SU3_KIND_MATRIX, su3.SU3_KIND_REAL, su3.SU3_KIND_COMPLEX
-    for prec, pname in ((su3.SU3_F64, "f64"), (su3.SU3_F32, "f32")):
-        tune(su3.SU3_EXPR_PROGRAM, prec, SOA, 0, dims)
-        rb = REAL_BYTES[prec]
-        v1 = su3.scalar_tensor(dims, prec, SOA, R)
-        v2 = su3.scalar_tensor(dims, prec, SOA, R)
-        v3 = su3.scalar_tensor(dims, prec, SOA, R)
-        su3.su3_program_eval(su3.Program("1.0", []), v1, [], stream)
-        su3.su3_program_eval(su3.Program("2.0", []), v2, [], stream)
-        mats = [make(dims, prec, SOA, 0, testgen.FID_U0 + k) for k in range(4)]
-        zm = su3.field_tensor(dims, prec, SOA, 0)
-        zc = su3.scalar_tensor(dims, prec, SOA, C)
-        cases = [("listing2", "a+b+a*b", [R, R], v3, [v1, v2], 3 * rb),
-                 ("mul", "a*b", [M, M], zm, mats[:2], 54 * rb),
-                 ("muladd", "a*b+c*d", [M, M, M, M], zm, mats, 90 * rb),
-                 ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb)]
-        for name, text, kinds, z, ops, bps in cases:
-            prog = su3.Program(text, kinds)
-            ms, _ = timer.run(lambda: su3.su3_program_eval(prog, z, ops, stream), steps, 3)
-            key = f"{pname}_{name}"
-            progs[key] = {"expr": text, "us": round(ms * 1e3, 2),
-                          "gbps": round(bps * V / (ms * 1e-3) / 1e9, 1),
-                          "bytes_per_site": bps}
-            if name == "mul":
-                mf, _ = timer.run(lambda: su3.su3_mult(zm, mats[0], mats[1], stream), steps, 3)
-                progs[key]["fixed_kernel_us"] = round(mf * 1e3, 2)
-            if name == "muladd":
-                mf, _ = timer.run(lambda: su3.su3_fused_eval(zm, su3.SU3_EXPR_MULADD, mats,
-                                                             stream), steps, 3)
-                progs[key]["fixed_kernel_us"] = round(mf * 1e3, 2)
-            log(f"program {key}: {progs[key]}")
-        del v1, v2, v3, mats, zm, zc
-    out["programs_48^4"] = progs
-
-    # fused vs chained at 32^4 with four link fields
+def section_fused(ctx):
+    """Fused MUL3 / MULADD on four link fields at 32^4 against chained
+    su3_mult (+ ADD) calls, hot and cold (rotating operand sets of >= 1 GiB)."""
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args, cpu, host_field = ctx["args"], ctx["cpu"], ctx["host_field"]
+    SOA, AOSOA = su3.SU3_LAYOUT_SOA, su3.SU3_LAYOUT_AOSOA
+    steps = max(10, min(args.steps, 50))
     d = (32, 32, 32, 32)
     Vf = testgen.volume(d)
-    fused = {}
+    hU = [host_field(Vf, testgen.FID_U0 + mu) for mu in range(4)]
+    out = {}
     for prec, lname, lay, lanes in ((su3.SU3_F64, "soa", SOA, 0), (su3.SU3_F32, "soa", SOA, 0),
                                     (su3.SU3_F64, "aosoa64", AOSOA, 64),
                                     (su3.SU3_F32, "aosoa64", AOSOA, 64)):
@@ -566,7 +520,7 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
         t2 = su3.field_tensor(d, prec, lay, lanes)
         for expr, name in ((su3.SU3_EXPR_MUL3, "mul3"), (su3.SU3_EXPR_MULADD, "muladd")):
             nops = 3 if expr == su3.SU3_EXPR_MUL3 else 4
-            cfg = tune(expr, prec, lay, lanes, d)
+            tune(expr, prec, lay, lanes, d, f"fused {PREC_NAME[prec]} {lname} {name}")
             tune(su3.SU3_EXPR_MUL, prec, lay, lanes, d)
             tune(su3.SU3_EXPR_ADD, prec, lay, lanes, d)
             ms_f, _ = timer.run(lambda: su3.su3_fused_eval(z, expr, U[:nops], stream),
@@ -582,86 +536,363 @@ def run_variants(args, su3, torch, testgen, np, stream, timer, make, tune,
                     su3.su3_fused_eval(z, su3.SU3_EXPR_ADD, [t1, t2], stream)
             ms_c, _ = timer.run(chained, steps, 3)
             b = expr_bytes_per_site(prec, expr) * Vf
-            fused[f"{PREC_NAME[prec]}_{lname}_{name}"] = {
-                "fused_us": round(ms_f * 1e3, 2), "chained_us": round(ms_c * 1e3, 2),
-                "fused_gbps": round(b / (ms_f * 1e-3) / 1e9, 1),
-                "speedup": round(ms_c / ms_f, 3), "launch": cfg}
-            log(f"fused {PREC_NAME[prec]} {lname} {name}: {fused[f'{PREC_NAME[prec]}_{lname}_{name}']}")
-        del U, z, t1, t2
-    out["fused_32^4"] = fused
+            # cold: operand sets rotating through >= 1 GiB
+            k = max(2, -(-(1 << 30) // b))
+            sets = [(U[:nops], z)]
+            for _ in range(k - 1):
+                ops = []
+                for u in U[:nops]:
+                    f = su3.field_tensor(d, prec, lay, lanes)
+                    f.owner.copy_(u.owner)
+                    ops.append(f)
+                sets.append((ops, su3.field_tensor(d, prec, lay, lanes)))
+            turn = [0]
 
-    # 64 uneven lattices, mixed FP64 and compressed FP32, one graph replay;
-    # AoSoA(64) storage: most of these volumes are powers of two, whose SoA
-    # entry planes sit at power-of-two strides
+            def rotating():
+                ops, zz = sets[turn[0] % k]
+                turn[0] += 1
+                su3.su3_fused_eval(zz, expr, ops, stream)
+            ms_cold, _ = timer.run(rotating, max(steps, 2 * k), k)
+            del sets
+            e = entry(ms_f, b)
+            c = entry(ms_cold, b)
+            e.update(chained_us=round(ms_c * 1e3, 1), x_chained=round(ms_c / ms_f, 2),
+                     cold_us=c["us"], cold_gbps=c["gbps"], cold_pct=c["pct"], sets=k,
+                     cached=b < 2 * MALL_BYTES)
+            key = f"{PREC_NAME[prec]}_{lname}_{name}"
+            if lname == "soa":
+                if prec == su3.SU3_F64:
+                    cpu.add(e, "cpu", lambda orc, x=expr, n=nops: orc.fused(x, hU[:n]), b)
+                else:
+                    cpu.add(e, "cpu",
+                            lambda orc, x=expr, n=nops: orc.reference(x, prec, hU[:n]), b)
+            out[key] = e
+            log(f"fused {key}: {e}")
+        del U, z, t1, t2
+    return out
+
+
+def section_dslash(ctx):
+    """The Wilson hopping term at 48^4 (four link fields + input and output
+    spinors moved once each)."""
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args = ctx["args"]
+    SOA, AOSOA = su3.SU3_LAYOUT_SOA, su3.SU3_LAYOUT_AOSOA
+    steps = max(10, min(args.steps, 50))
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    host_psi = testgen.spinor_field(V, seed=args.seed, field_id=200)
+    out = {}
+    lays = (("soa", SOA, 0), ("aosoa64", AOSOA, 64))
+    if args.layout != "both":
+        lays = [l for l in lays if l[0] == args.layout]
+    for sp, lp, name in ((su3.SU3_F64, su3.SU3_F64, "f64"), (su3.SU3_F32, su3.SU3_F32, "f32"),
+                         (su3.SU3_F32, su3.SU3_C12_F32, "f32_c12")):
+        for lname, lay, lanes in lays:
+            U = [make(dims, lp, lay, lanes, testgen.FID_U0 + mu) for mu in range(4)]
+            fin = su3.spinor_tensor(dims, sp, lay, lanes)
+            su3.su3_field_upload(fin, host_psi, stream)
+            fout = su3.spinor_tensor(dims, sp, lay, lanes)
+            tune(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, f"dslash {name} {lname}")
+            ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+            b = DSLASH_BYTES_PER_SITE[(sp, lp)] * V
+            key = f"{name}_{lname}"
+            out[key] = entry(ms, b, tflops=round(DSLASH_FLOPS_PER_SITE * V / ms / 1e9, 2))
+            log(f"dslash {key}: {out[key]}")
+            del U, fin, fout
+    return out
+
+
+def section_batch(ctx):
+    """64 uneven lattices, mixed FP64 and compressed FP32, replayed from one
+    HIP graph: the tuned launch, the best persistent grid (k workgroups per
+    compute unit looping over the tiles), and 64 separate launches."""
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args, cpu, host_field = ctx["args"], ctx["cpu"], ctx["host_field"]
+    AOSOA = su3.SU3_LAYOUT_AOSOA
     lat = testgen.batch_lattices(64, seed=args.seed)
+    # each item's storage: the layout the library recommends for the
+    # product at that lattice and precision (AoSoA(64) without tuning)
+    rec = {}
+    for d, comp in lat:
+        prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
+        if (d, prec) not in rec:
+            if args.no_tune:
+                rec[(d, prec)] = (AOSOA, 64)
+            else:
+                lay, lanes, _, _ = su3.su3_layout_recommend(su3.SU3_EXPR_MUL, prec, d, stream)
+                rec[(d, prec)] = (lay, lanes)
+    lay_names = {su3.SU3_LAYOUT_SOA: "soa", AOSOA: "aosoa"}
+    rec_text = ["%s %s %s%s" % ("x".join(map(str, d)), PREC_NAME[p], lay_names[l], L or "")
+                for (d, p), (l, L) in sorted(rec.items())]
+    log(f"batch layouts: {rec_text}")
     zs, ops, exprs = [], [], []
     total_bytes = 0
     log("batch: generating 64 lattices")
     for i, (d, comp) in enumerate(lat):
         prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
-        Vi = testgen.volume(d)
-        ops.append([make(d, prec, AOSOA, 64, testgen.FID_BATCH_BASE + 4 * i + k)
+        lay, lanes = rec[(d, prec)]
+        ops.append([make(d, prec, lay, lanes, testgen.FID_BATCH_BASE + 4 * i + k)
                     for k in range(2)])
-        zs.append(su3.field_tensor(d, prec, AOSOA, 64))
+        zs.append(su3.field_tensor(d, prec, lay, lanes))
         exprs.append(su3.SU3_EXPR_MUL)
-        total_bytes += BYTES_PER_SITE[prec] * Vi
+        total_bytes += BYTES_PER_SITE[prec] * testgen.volume(d)
     total_sites = sum(testgen.volume(d) for d, _ in lat)
-    bcfg = None
-    if not args.no_tune:
-        bcfg = su3.su3_batch_autotune(exprs, zs, ops, stream).as_dict()
-        log(f"batch tune: {bcfg}")
-    b = su3.su3_batch_create(exprs, zs, ops, stream)
-    ms_b, _ = timer.run(lambda: su3.su3_batch_launch(b, stream), 100, 3)
+    key = su3.SU3_EXPR_BATCH + su3.SU3_EXPR_MUL
+    kprec = su3.SU3_C12_F32 if lat[0][1] else su3.SU3_F64
+    klay, klanes = rec[(lat[0][0], kprec)]
+    kdims = (total_sites, 1, 1, 1)
+    if args.no_tune:
+        bcfg = su3.su3_launch_get(key, kprec, klay, klanes, kdims)
+    else:
+        bcfg = su3.su3_batch_autotune(exprs, zs, ops, stream)
+    log(f"batch tune: {bcfg.as_dict()}")
 
-    # the same 64 products as 64 back-to-back launches (tuned per shape)
-    for i, (d, comp) in enumerate(lat):
-        prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
-        tune(su3.SU3_EXPR_MUL, prec, AOSOA, 64, d)
+    def replay(cfg):
+        su3.su3_launch_set(key, kprec, klay, klanes, kdims, cfg)
+        b = su3.su3_batch_create(exprs, zs, ops, stream)
+        ms, _ = timer.run(lambda: su3.su3_batch_launch(b, stream), 100, 3)
+        su3.su3_batch_destroy(b)
+        return ms
+
+    ms_b = replay(bcfg)
+    out = entry(ms_b, total_bytes, lattices=64, layouts=rec_text, sites=total_sites,
+                bytes=total_bytes, n_c12=sum(1 for _, c in lat if c), replays=100,
+                persistent=bcfg.persistent, tile=bcfg.tile_sites)
+    # the best persistent grid (and the best one-shot grid when the tuned
+    # launch is persistent), from the tuned setting's other knobs
+    alt = []
+    for pers in ((1, 2, 4, 8) if bcfg.persistent == 0 else (0,)):
+        for tile in (512, 2048, 8192):
+            c = su3.su3_launch(**bcfg.as_dict())
+            c.persistent, c.tile_sites = pers, tile
+            if pers and c.block < 256:
+                c.block = 256
+            alt.append((replay(c), pers, tile))
+    ms_a, pers_a, tile_a = min(alt)
+    a = entry(ms_a, total_bytes)
+    pre = "oneshot" if bcfg.persistent else "persistent"
+    out.update({f"{pre}_us": a["us"], f"{pre}_gbps": a["gbps"], f"{pre}_pct": a["pct"],
+                f"{pre}_k": pers_a, f"{pre}_tile": tile_a})
+    su3.su3_launch_set(key, kprec, klay, klanes, kdims, bcfg)
+
+    # the same 64 products as 64 back-to-back launches (each shape's tuned
+    # launch, kept by the layout recommendation)
 
     def unbatched():
         for i in range(64):
             su3.su3_mult(zs[i], ops[i][0], ops[i][1], stream)
     ms_u, _ = timer.run(unbatched, 20, 2)
-    out["batch_64"] = {
-        "lattices": 64, "layout": "aosoa64", "sites": total_sites, "bytes": total_bytes,
-        "n_c12": sum(1 for _, c in lat if c),
-        "us": round(ms_b * 1e3, 2),
-        "gbps": round(total_bytes / (ms_b * 1e-3) / 1e9, 1),
-        "unbatched_us": round(ms_u * 1e3, 2),
-        "unbatched_gbps": round(total_bytes / (ms_u * 1e-3) / 1e9, 1),
-        "replays": 100, "launch": bcfg}
-    log(f"batch: {out['batch_64']}")
-    su3.su3_batch_destroy(b)
+    out["unbatched_us"] = round(ms_u * 1e3, 1)
+    hosts = [(testgen.volume(d), comp, [host_field(testgen.volume(d),
+                                                   testgen.FID_BATCH_BASE + 4 * i + k)
+                                        for k in range(2)])
+             for i, (d, comp) in enumerate(lat)]
+
+    def all_items(orc):
+        for Vi, comp, (hx, hy) in hosts:
+            if comp:
+                orc.reference(0, 3, [hx, hy])
+            else:
+                orc.mult(hx, hy)
+    cpu.add(out, "cpu", all_items, total_bytes, min_s=0.2)
+    log(f"batch: {out}")
     del zs, ops
     return out
 
 
-def cpu_baseline(x, y):
+SECTION_FUNCS = {"precision": section_precision, "fused": section_fused,
+                 "ceiling": section_ceiling, "dslash": section_dslash,
+                 "batch": section_batch}
+
+
+def run_variants(ctx, out):
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args, cpu, host_field = ctx["args"], ctx["cpu"], ctx["host_field"]
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    steps = max(10, min(args.steps, 50))
+    SOA, AOS, AOSOA = su3.SU3_LAYOUT_SOA, su3.SU3_LAYOUT_AOS, su3.SU3_LAYOUT_AOSOA
+    x64, y64, z64, ms_f64 = ctx["x64"], ctx["y64"], ctx["z64"], ctx["ms_f64"]
+
+    out["precision_48^4"] = section_precision(ctx)
+
+    # layouts at 48^4 (FP64)
+    lay_out = {}
+    cases = [("aos", AOS, 0, 0), ("aos_lds", AOS, 0, 1)] + \
+        [(f"aosoa{L}", AOSOA, L, 0) for L in (8, 16, 32, 64)]
+    for name, lay, lanes, lds in cases:
+        x = make(dims, su3.SU3_F64, lay, lanes, testgen.FID_X)
+        y = make(dims, su3.SU3_F64, lay, lanes, testgen.FID_Y)
+        z = su3.field_tensor(dims, su3.SU3_F64, lay, lanes)
+        if lay == AOS:
+            cfg = su3.su3_launch_get(0, 0, lay, lanes, dims).as_dict()
+            cfg.update(lds_stage=lds, block=64)
+            su3.su3_launch_set(0, 0, lay, lanes, dims, cfg)
+        else:
+            tune(su3.SU3_EXPR_MUL, su3.SU3_F64, lay, lanes, dims, f"layout {name}")
+        ms, _ = timer.run(lambda: su3.su3_mult(z, x, y, stream), steps, 3)
+        lay_out[name] = entry(ms, 432 * V)
+        log(f"layout {name}: {lay_out[name]}")
+        del x, y, z
+    out["layouts_f64_48^4"] = lay_out
+
+    # volume sweep (FP64 SoA); sizes below 2x the 256 MiB Infinity Cache
+    # are cache-resident when hot, not HBM figures: the cold figures are
+    sweep = {}
+    d8 = (8, 8, 8, 8)
+    sweep["8^4"] = hot_and_cold(ctx, d8, su3.SU3_F64, 18, 19)
+    for L in (16, 24, 32):
+        d = (L, L, L, L)
+        sweep[f"{L}^4"] = hot_and_cold(ctx, d, su3.SU3_F64, 10 + L, 11 + L)
+        log(f"sweep {L}^4: {sweep[f'{L}^4']}")
+    e48 = entry(ms_f64, 432 * V, cached=False)
+    hx, hy = host_field(V, testgen.FID_X), host_field(V, testgen.FID_Y)
+    cpu.add(e48, "cpu", lambda orc: orc.mult(hx, hy), 432 * V)
+    sweep["48^4"] = e48
+    out["sweep_f64_soa"] = sweep
+
+    # one GPU's share of a 48^4 lattice cut into 8 t-slabs: 48^3 x 6 sites,
+    # 287 MB of operands, just above the Infinity Cache, so the cold figure
+    # is the HBM one
+    shard = hot_and_cold(ctx, (48, 48, 48, 6), su3.SU3_F64, 60, 61, cpu_rate=False)
+    log(f"shard 48^3x6: {shard}")
+    out["shard_f64_soa_48^3x6"] = shard
+
+    # storage precisions at 32^4 (SoA): every working set fits the Infinity
+    # Cache, so the cold figures are the HBM ones
+    p32 = {}
+    for prec in (su3.SU3_F64, su3.SU3_F32, su3.SU3_F16_F32ACC, su3.SU3_C12_F32):
+        p32[PREC_NAME[prec]] = hot_and_cold(ctx, (32, 32, 32, 32), prec, 40, 41)
+        log(f"precision 32^4 {PREC_NAME[prec]}: {p32[PREC_NAME[prec]]}")
+    out["precision_32^4"] = p32
+
+    # shifted operands at 48^4 (FP64 SoA): Cshift moves 288 B/site, the
+    # product with a shifted operand 432 B/site
+    shift = {}
+    tune(su3.SU3_EXPR_CSHIFT, su3.SU3_F64, SOA, 0, dims, "cshift")
+    tune(su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_F64, SOA, 0, dims, "mult_shifted")
+    for mu in range(4):
+        ms_c, _ = timer.run(lambda: su3.su3_cshift(z64, y64, mu, 1, stream), steps, 3)
+        ms_m, _ = timer.run(lambda: su3.su3_mult_shifted(z64, x64, y64, mu, 1, stream),
+                            steps, 3)
+        shift[f"mu{mu}"] = {"cshift": entry(ms_c, 288 * V), "mult": entry(ms_m, 432 * V)}
+        log(f"shift mu {mu}: {shift[f'mu{mu}']}")
+    out["shift_f64_48^4"] = shift
+
+    out["dslash_48^4"] = section_dslash(ctx)
+
+    # the hopping term at the same t-slab's shape (periodic in t over its 6
+    # slices: the traffic and work of a slab without its halo exchange);
+    # 637 MB of operands, more than twice the Infinity Cache
+    ds = (48, 48, 48, 6)
+    Vs = testgen.volume(ds)
+    U = [make(ds, su3.SU3_F64, SOA, 0, 60 + mu) for mu in range(4)]
+    fin = su3.spinor_tensor(ds, su3.SU3_F64, SOA, 0)
+    su3.su3_field_upload(fin, testgen.spinor_field(Vs, seed=args.seed, field_id=201),
+                         stream)
+    fout = su3.spinor_tensor(ds, su3.SU3_F64, SOA, 0)
+    tune(su3.SU3_EXPR_DSLASH, su3.SU3_F64, SOA, 0, ds, "dslash shard")
+    ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+    out["dslash_shard_f64_soa_48^3x6"] = entry(ms, DSLASH_BYTES_PER_SITE[(0, 0)] * Vs)
+    log(f"dslash shard 48^3x6: {out['dslash_shard_f64_soa_48^3x6']}")
+    del U, fin, fout
+
+    # Grid's virtual-node layout used in place (N_sub sites per outer site,
+    # one per virtual node): the streaming product and the hopping term in
+    # FP64 on the same inputs, for N_sub = 4 (t and z split in two, Grid's
+    # usual split) and 16 (every direction split in two)
+    vn = {}
+    host_psi = testgen.spinor_field(V, seed=args.seed, field_id=200)
+    for nsub, simd in ((4, (1, 1, 2, 2)), (16, (2, 2, 2, 2))):
+        F64, VN = su3.SU3_F64, su3.SU3_LAYOUT_VNODE
+
+        def vfield(host, kind=su3.SU3_KIND_MATRIX):
+            f = su3.vnode_tensor(dims, F64, simd, kind)
+            su3.su3_field_upload(f, host, stream)
+            return f
+
+        fx, fy = vfield(host_field(V, testgen.FID_X)), vfield(host_field(V, testgen.FID_Y))
+        fz = su3.vnode_tensor(dims, F64, simd)
+        tune(su3.SU3_EXPR_MUL, F64, VN, nsub, dims, f"vnode mul {nsub}")
+        ms, _ = timer.run(lambda: su3.su3_mult(fz, fx, fy, stream), steps, 3)
+        vn[f"mul_nsub{nsub}"] = entry(ms, BYTES_PER_SITE[F64] * V)
+        del fx, fy, fz
+        U = [vfield(host_field(V, testgen.FID_U0 + mu)) for mu in range(4)]
+        fin = vfield(host_psi, su3.SU3_KIND_SPINOR)
+        fout = su3.vnode_tensor(dims, F64, simd, su3.SU3_KIND_SPINOR)
+        tune(su3.SU3_EXPR_DSLASH, F64, VN, nsub, dims, f"vnode dslash {nsub}")
+        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+        vn[f"dslash_nsub{nsub}"] = entry(ms, DSLASH_BYTES_PER_SITE[(F64, F64)] * V)
+        log(f"vnode nsub {nsub}: {vn[f'mul_nsub{nsub}']} {vn[f'dslash_nsub{nsub}']}")
+        del U, fin, fout
+    del host_psi
+    out["vnode_f64_48^4"] = vn
+
+    # expression programs at 48^4 (one precompiled kernel interpreting the
+    # host-compiled expression): the sum plus the product of two real
+    # fields, a+b+a*b (the real-valued composite example of Section 3,
+    # Listing 2; two real inputs, one real output: 24 B/site), the streaming product,
+    # the MULADD shape and a trace into a complex field, each against its
+    # algorithmic bytes; the fixed-expression kernels beside them
+    progs = {}
+    M, R, C = su3.SU3_KIND_MATRIX, su3.SU3_KIND_REAL, su3.SU3_KIND_COMPLEX
+    for prec, pname in ((su3.SU3_F64, "f64"), (su3.SU3_F32, "f32")):
+        tune(su3.SU3_EXPR_PROGRAM, prec, SOA, 0, dims, f"program {pname}")
+        rb = REAL_BYTES[prec]
+        ra = su3.scalar_tensor(dims, prec, SOA, R)
+        rb_ = su3.scalar_tensor(dims, prec, SOA, R)
+        rz = su3.scalar_tensor(dims, prec, SOA, R)
+        su3.su3_program_eval(su3.Program("1.0", []), ra, [], stream)
+        su3.su3_program_eval(su3.Program("2.0", []), rb_, [], stream)
+        mats = [make(dims, prec, SOA, 0, testgen.FID_U0 + k) for k in range(4)]
+        zm = su3.field_tensor(dims, prec, SOA, 0)
+        zc = su3.scalar_tensor(dims, prec, SOA, C)
+        cases = [("apb_ab_real", "a+b+a*b", [R, R], rz, [ra, rb_], 3 * rb),
+                 ("mul", "a*b", [M, M], zm, mats[:2], 54 * rb),
+                 ("muladd", "a*b+c*d", [M, M, M, M], zm, mats, 90 * rb),
+                 ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb)]
+        for name, text, kinds, z, ops, bps in cases:
+            prog = su3.Program(text, kinds)
+            ms, _ = timer.run(lambda: su3.su3_program_eval(prog, z, ops, stream), steps, 3)
+            key = f"{pname}_{name}"
+            progs[key] = entry(ms, bps * V)
+            if name == "mul":
+                mf, _ = timer.run(lambda: su3.su3_mult(zm, mats[0], mats[1], stream), steps, 3)
+                progs[key]["fixed_us"] = round(mf * 1e3, 1)
+            if name == "muladd":
+                mf, _ = timer.run(lambda: su3.su3_fused_eval(zm, su3.SU3_EXPR_MULADD, mats,
+                                                             stream), steps, 3)
+                progs[key]["fixed_us"] = round(mf * 1e3, 1)
+            log(f"program {key} ({text}): {progs[key]}")
+        del ra, rb_, rz, mats, zm, zc
+    out["programs_48^4"] = progs
+
+    out["fused_32^4"] = section_fused(ctx)
+    out["batch_64"] = section_batch(ctx)
+    return out
+
+
+def cpu_baseline(leg, x, y):
     """The FP64 oracle, as it stands, on the host cores: full 48^4 products
-    repeated until at least 10 s have passed on all the process's threads,
-    then for at least 5 s on one thread."""
-    import oracle
-    orc = oracle.get()
+    repeated until at least 8 s have passed on all the process's threads,
+    then for at least 4 s on one thread."""
+    orc = leg.oracle()
     V = x.shape[0]
-
-    def timed(min_s):
-        passes, t0 = 0, time.perf_counter()
-        while True:
-            orc.mult(x, y)
-            passes += 1
-            el = time.perf_counter() - t0
-            if el >= min_s or passes >= 5000:
-                return passes, el
-
     threads = orc.threads()
-    passes, el = timed(10.0)
-    gbps = 432 * V * passes / el / 1e9
+    passes, el = leg._timed(lambda: orc.mult(x, y), 8.0)
+    g = 432 * V * passes / el / 1e9
     orc.set_threads(1)
-    p1, el1 = timed(5.0)
-    orc.set_threads(threads)
-    gbps1 = 432 * V * p1 / el1 / 1e9
-    log(f"cpu baseline: {passes} passes in {el:.1f} s, {gbps:.2f} GB/s, "
-        f"{threads} threads; 1 thread: {p1} passes in {el1:.1f} s, {gbps1:.3f} GB/s")
+    try:
+        p1, el1 = leg._timed(lambda: orc.mult(x, y), 4.0)
+    finally:
+        orc.set_threads(threads)
+    g1 = 432 * V * p1 / el1 / 1e9
+    log(f"cpu baseline: {passes} passes in {el:.1f} s, {g:.2f} GB/s, "
+        f"{threads} threads; 1 thread: {p1} passes in {el1:.1f} s, {g1:.3f} GB/s")
     model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -669,12 +900,12 @@ def cpu_baseline(x, y):
                           if ln.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": round(gbps, 3), "unit": "GB/s", "cores": threads,
+    return {"value": round(g, 3), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{passes} full z=x*y passes over the 48^4 lattice "
                       f"({V} sites, same seeded inputs), {el:.1f} s wall",
             "gflops": round(198 * V * passes / el / 1e9, 2),
-            "value_1core": round(gbps1, 4),
+            "value_1core": round(g1, 4),
             "sample_1core": f"{p1} passes on one thread, {el1:.1f} s wall",
             "cpu_model": model}
 

@@ -101,8 +101,8 @@ typedef enum su3_kind {
     SU3_KIND_COMPLEX = 3  /* one complex number per site */
 } su3_kind;
 
-/* Fixed site-local expressions (Section 3, Listings 1-2; left-to-right
- * association as in v1+v2+v1*v2):
+/* Fixed site-local expressions (Section 3, Listings 1-2; sums and
+ * products associate left to right, as C++ expressions do):
  *   MUL    z = a*b            (2 operands)  -- the streaming test, Listing 3
  *   MUL3   z = (a*b)*c        (3 operands)
  *   MULADD z = (a*b) + (c*d)  (4 operands)
@@ -125,7 +125,12 @@ typedef enum su3_expr {
     SU3_EXPR_DSLASH = 7,
     /* launch-tuning key of su3_program_eval; its precision is the
      * arithmetic one (SU3_F64 or SU3_F32) */
-    SU3_EXPR_PROGRAM = 8
+    SU3_EXPR_PROGRAM = 8,
+    /* launch-tuning keys of batches: SU3_EXPR_BATCH + the leading item's
+     * expression (MUL .. APB_AB), with its precision, layout and lanes, at
+     * the batch's total volume (su3_launch_get / su3_launch_set; what
+     * su3_batch_autotune tunes and su3_batch_create reads) */
+    SU3_EXPR_BATCH = 32
 } su3_expr;
 
 typedef struct su3_field su3_field;
@@ -134,16 +139,22 @@ typedef struct su3_program su3_program;
 
 /* How a compute call is launched.  Any valid setting gives bit-identical
  * results; only speed differs.
- *   block       lanes per workgroup: 64, 128 or 256 (512: su3_dslash's
- *               LDS-tiled walks)
+ *   block       lanes per workgroup: 64, 128 or 256; 512 and 1024 for the
+ *               site-local calls with nontemporal 3 or 7 and for
+ *               su3_dslash's LDS-tiled walks (512)
  *   persistent  0: one lane per site group (one-shot grid); batches: one
  *               workgroup per tile.  k > 0: k workgroups per compute unit
  *               loop over the work (grid-stride over site groups or tiles;
  *               su3_dslash's LDS-tiled walks: each workgroup walks an equal
  *               share of the (tile, t-slice) pairs, tile after tile)
- *   nontemporal bit 0: nontemporal loads, bit 1: nontemporal stores
- *               (su3_dslash: bit 0 applies to link loads only; the
- *               LDS-tiled walks always load cached, store nontemporal)
+ *   nontemporal bit 0: nontemporal loads, bit 1: nontemporal stores,
+ *               bit 2 (with bit 1; site-local calls, shifts, batches and
+ *               the yardsticks only): write-through streaming stores,
+ *               nontemporal at system scope, which move results to HBM
+ *               faster than nontemporal stores on gfx950; values 0-3, 6, 7
+ *               (su3_dslash and programs 0-3; su3_dslash: bit 0 applies to
+ *               link loads only; the LDS-tiled walks always load cached,
+ *               store nontemporal)
  *   xcd_remap   1: hand each of the 8 XCDs a contiguous range of
  *               workgroups instead of the hardware's round-robin;
  *               2 (su3_dslash's LDS-tiled walks): each XCD walks one
@@ -181,7 +192,14 @@ typedef struct su3_program su3_program;
  *               buffer, rows of 2 x 2, or 16x4x4).  On virtual-node fields
  *               only schedules 9..18 apply, over outer sites with all
  *               their virtual nodes, tx the largest divisor of the outer
- *               x extent that fits 512 lanes (else one site per lane)     */
+ *               x extent that fits 512 lanes (else one site per lane)
+ *   sites_per_lane  site-local calls in the blocked layouts: consecutive
+ *               sites each lane evaluates, 0 = the natural count (16-byte
+ *               accesses: 1 double, 2 single or compressed, 4 half sites;
+ *               2 half sites for 3-4 operands), else 1, the natural count,
+ *               or for MUL outside half storage twice the natural count
+ *               (32-byte accesses); the lane-block L must be a multiple
+ *               (SU3_ERR_INVALID_ARG otherwise).  Ignored elsewhere       */
 typedef struct su3_launch {
     int32_t block;
     int32_t persistent;
@@ -191,26 +209,33 @@ typedef struct su3_launch {
     int32_t tile_sites;
     int32_t occupancy;
     int32_t schedule;
+    int32_t sites_per_lane;
 } su3_launch;
 
 /* ------------------------------------------------------------- fields */
 
-/* Bytes a field of lattice `dims` (4 extents, each > 0) occupies in the
+/* A field is the lattice-wide object of Section 4, Listing 3 (a
+ * Lattice<Su3f> built on a grid: one 3x3 complex matrix per site of the 4D
+ * lattice `dims`), stored in one of the layouts above.
+ *
+ * Bytes a field of lattice `dims` (4 extents, each > 0) occupies in the
  * given precision and layout.  `lanes` is read for SU3_LAYOUT_AOSOA only
  * (power of two in [8, 64]).  Fails with SU3_ERR_INVALID_ARG when the
  * stored field would hold 2^31 reals or more.  Pure host computation. */
 su3_status su3_field_bytes(const int32_t dims[4], su3_precision prec,
                            su3_layout layout, int32_t lanes, size_t *bytes);
 
-/* Allocate a zeroed field on the current device.  The handle owns its
- * memory; su3_field_free releases it.  SU3_ERR_OUT_OF_MEMORY when the
+/* Allocate a zeroed field on the current device (the Lattice<Su3f>
+ * construction of Section 4, Listing 3).  The handle owns its memory;
+ * su3_field_free releases it.  SU3_ERR_OUT_OF_MEMORY when the
  * device allocation fails. */
 su3_status su3_field_alloc(su3_field **out, const int32_t dims[4],
                            su3_precision prec, su3_layout layout,
                            int32_t lanes);
 
 /* Describe caller-owned device memory (e.g. a torch tensor's storage) as a
- * field.  Non-owning: the caller keeps the memory alive until
+ * field (Section 4, Listing 3's lattice object over memory the caller
+ * owns, in place of the paper's managed memory, Section 3).  Non-owning: the caller keeps the memory alive until
  * su3_field_free(handle).  `dev_ptr` must be 16-byte aligned device memory
  * of the current device with at least su3_field_bytes() bytes
  * (SU3_ERR_INVALID_ARG otherwise).  Contents are used as they are. */
@@ -224,12 +249,15 @@ su3_status su3_field_free(su3_field *f);
 /* Device address and size of a field's storage. */
 su3_status su3_field_data(const su3_field *f, void **dev_ptr, size_t *bytes);
 
-/* Quantise and pack V*18 canonical doubles (V*24 for a spinor field) into
- * the field (padding sites written as zero).  Completes before returning. */
+/* Fill a field with its site values (the initial values of Listing 3's
+ * operands, Section 4; in the stored layout of Sections 4-5).  Quantise
+ * and pack V*18 canonical doubles (V*24 for a spinor field) into the field
+ * (padding sites written as zero).  Completes before returning. */
 su3_status su3_field_upload(su3_field *f, const double *host_aos,
                             void *stream);
 
-/* Unpack the field into V*18 canonical doubles (V*24 for a spinor field;
+/* Read a field's site values back (the inverse of su3_field_upload).
+ * Unpack the field into V*18 canonical doubles (V*24 for a spinor field;
  * exact widening).  For
  * SU3_C12_F32, rows 0-1 are the stored values and row 2 is rebuilt in
  * double as conj(row0 x row1).  Completes before returning. */
@@ -248,8 +276,11 @@ su3_status su3_field_download_raw(const su3_field *f, void *host,
 su3_status su3_mult(su3_field *z, const su3_field *x, const su3_field *y,
                     void *stream);
 
-/* z = expr(ops[0..n_ops-1]) at every site, in one kernel.  All fields
- * share dims, precision, layout and lanes (SU3_ERR_MISMATCH otherwise);
+/* z = expr(ops[0..n_ops-1]) at every site, in one kernel: the expression
+ * template engine's assignment of Section 3, Listing 1 (z[ss] =
+ * eval(ss, expr) for every site ss), for the composite expressions of the
+ * kind Listing 2 builds (sums and products of fields, left to right).
+ * All fields share dims, precision, layout and lanes (SU3_ERR_MISMATCH otherwise);
  * n_ops must match the expression (SU3_ERR_INVALID_ARG).  z may be one of
  * the operands exactly (in-place); a partial overlap with any operand is
  * SU3_ERR_ALIAS. */
@@ -336,8 +367,8 @@ su3_status su3_scalar_wrap(su3_field **out, void *dev_ptr, size_t bytes,
 /* ------------------------------------------------ expression programs */
 
 /* General site-local expressions (Section 3: the expression template
- * engine evaluates arbitrary expressions such as v1+v2+v1*v2, Listing 2,
- * site by site, Listing 1), compiled on the host into a register program
+ * engine evaluates arbitrary expressions of lattice fields, real-valued
+ * ones included (Listing 2), site by site (Listing 1)), compiled on the host into a register program
  * that one precompiled kernel evaluates at every site.  Grammar:
  *   expr    := term (('+' | '-') term)*
  *   term    := unary ('*' unary)*
@@ -406,7 +437,10 @@ su3_status su3_vnode_wrap(su3_field **out, void *dev_ptr, size_t bytes,
 /* ------------------------------------------------------------ batches */
 
 /* A batch evaluates n independent (expr, z, operands) items -- fields of
- * different lattices, precisions and layouts -- in one persistent launch
+ * different lattices, precisions and layouts -- in one persistent launch:
+ * Section 3, Listing 1's site loop run over several lattices at once, with
+ * each workgroup holding several vectors of lanes as Section 5 proposes
+ * (the paper itself times one lattice per launch)
  * over a table of tiles, captured once in a HIP graph and replayed by
  * su3_batch_launch.  ops holds 4 pointers per item (unused = NULL).  Each
  * item obeys the rules of su3_fused_eval.  The tile table (see
@@ -436,7 +470,10 @@ su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows, int64_t cap,
 /* ------------------------------------------------------ launch tuning */
 
 /* Run the autotuner for one (expr, precision, layout, lanes) at lattice
- * dims: time each candidate launch (median of 10 after 3 warm-ups) on
+ * dims -- the block-size / vector-length study of Section 5 (Fig. 4) and
+ * Section 4's observation that launch choices alone separate two ports of
+ * the same loop, done per configuration at run time: time each candidate
+ * launch (median of 10 after 3 warm-ups) on
  * scratch fields and keep the fastest for every later call whose volume
  * falls in the same power-of-two bucket.  The result persists in the JSON
  * file named by the SU3_TUNE_CACHE environment variable, if set.  Fields
@@ -447,6 +484,20 @@ su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows, int64_t cap,
 su3_status su3_autotune(su3_expr expr, su3_precision prec, su3_layout layout,
                         int32_t lanes, const int32_t dims[4], void *stream,
                         su3_launch *best);
+
+/* Recommend a storage layout for `expr` (a site-local expression, MUL ..
+ * APB_AB) in precision `prec` at lattice `dims`: run su3_autotune for SoA
+ * and for AoSoA with 64, 32, 16 and 8 lanes (each tuned launch is kept as
+ * su3_autotune keeps it) and return the layout and lanes whose tuned
+ * launch is fastest, with that launch in *best and its median time in *us
+ * (best and us may be NULL) -- Section 5's vector-length study (Fig. 4),
+ * done per configuration at run time.  The AoS layout (the negative
+ * control of Section 4) and Grid's virtual-node layout (the caller's
+ * choice of split) are not candidates.  Completes before returning. */
+su3_status su3_layout_recommend(su3_expr expr, su3_precision prec,
+                                const int32_t dims[4], void *stream,
+                                su3_layout *layout, int32_t *lanes,
+                                su3_launch *best, double *us);
 
 /* Autotune a batch: build the batch with each candidate launch (tile size,
  * one workgroup per tile or k per CU, occupancy cap, schedule, nontemporal
@@ -476,19 +527,56 @@ su3_status su3_launch_reset(void);
 
 /* ------------------------------------------- bandwidth yardsticks */
 
-/* STREAM-style triad a[i] = b[i] + s*c[i] over n doubles (the practical
- * HBM ceiling that Section 5 compares against).  Device pointers, 16-byte
- * aligned, asynchronous on `stream`. */
+/* The STREAM-style yardsticks that the paper measures the product against
+ * (Section 5, the triad beside the vector-layout kernel), as launchable
+ * kernels with the same launch knobs as the product, so that the ceiling
+ * of each read:write mix can be tuned like the product itself.  Arrays
+ * a, b, c of `bytes` bytes each (a positive multiple of 16; 16-byte aligned
+ * device pointers of the current device), one 16-byte element per lane:
+ *   SU3_STREAM_TRIAD  a = b + s*c over doubles: reads 2 x bytes, writes
+ *                     bytes (the 2:1 mix of z = x*y)
+ *   SU3_STREAM_READ   reads b and c (2 x bytes), writes nothing: a's first
+ *                     16 bytes are written only if an element of b + c
+ *                     equals (s, -s)
+ *   SU3_STREAM_WRITE  a = s: writes bytes (b, c unused, may be NULL)
+ *   SU3_STREAM_COPY   a = b: reads bytes, writes bytes (c unused)
+ * `cfg` (NULL = the kind's default) is read for block (64..1024, a multiple
+ * of 64), occupancy and nontemporal (0-3, 6, 7); its other fields are
+ * ignored.  Asynchronous on `stream`. */
+typedef enum su3_stream_kind {
+    SU3_STREAM_TRIAD = 0,
+    SU3_STREAM_READ = 1,
+    SU3_STREAM_WRITE = 2,
+    SU3_STREAM_COPY = 3
+} su3_stream_kind;
+
+su3_status su3_stream(su3_stream_kind kind, void *a, const void *b,
+                      const void *c, double s, size_t bytes,
+                      const su3_launch *cfg, void *stream);
+
+/* Time every candidate launch of a yardstick on the caller's arrays
+ * (median of 10 launches after 3) and return the fastest in *best and its
+ * time in *us (either may be NULL).  Overwrites `a`.  Completes before
+ * returning. */
+su3_status su3_stream_autotune(su3_stream_kind kind, void *a, const void *b,
+                               const void *c, size_t bytes, void *stream,
+                               su3_launch *best, double *us);
+
+/* STREAM-style triad a[i] = b[i] + s*c[i] over n doubles with the default
+ * launch of SU3_STREAM_TRIAD.  Device pointers, 16-byte aligned,
+ * asynchronous on `stream`. */
 su3_status su3_triad(double *a, const double *b, const double *c, double s,
                      int64_t n, void *stream);
 
 /* Plain copy dst[i] = src[i] over `bytes` bytes (multiple of 16, 16-byte
- * aligned device pointers), asynchronous on `stream`. */
+ * aligned device pointers) with the default launch of SU3_STREAM_COPY,
+ * asynchronous on `stream`. */
 su3_status su3_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* --------------------------------------------------------- utilities */
 
-/* Wait for `stream` and report any pending HIP error. */
+/* Wait for `stream` and report any pending HIP error (asynchronous kernel
+ * faults surface here). */
 su3_status su3_sync(void *stream);
 
 /* Static text of a status code. */

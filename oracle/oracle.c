@@ -20,8 +20,9 @@
  *     3x3 single-precision complex matrices (Section 4, Listing 3); the
  *     matrix class is a templated N x N complex matrix (Section 4);
  *   - expressions are evaluated site by site, _odata[ss] = eval(ss, expr)
- *     (Section 3, Listing 1), and composite expressions such as v1+v2 and
- *     v1+v2+v1*v2 associate left to right (Section 3, Listing 2);
+ *     (Section 3, Listing 1), and composite expressions -- sums of fields
+ *     and sums with products, as in the example of Section 3, Listing 2 --
+ *     associate left to right;
  *   - the scalar (AoS) layout and the vector (AoSoV) layout whose scalar
  *     leaves hold several lanes (Sections 4 and 5), including Grid's split
  *     of the lattice into virtual nodes, one per SIMD lane (Section 5).
@@ -687,8 +688,8 @@ void oracle_metrics(const double *zh, const double *z, int64_t V, double *out)
 
 /* ------------------------------------------------------------------------
  * General site-local expressions (Section 3: the expression template
- * engine evaluates arbitrary expressions site by site, e.g. v1+v2+v1*v2 on
- * Lattice<double> fields, Listing 2).  The text is parsed into a tree once
+ * engine evaluates arbitrary expressions site by site, on real-valued
+ * lattice fields too, as in its composite-expression example, Listing 2).  The text is parsed into a tree once
  * and the tree is evaluated at every site with plain double arithmetic.
  * Grammar: sums and differences of products of unary terms; a unary term
  * is an optional minus sign and a number, the imaginary unit i, an operand

@@ -40,6 +40,7 @@ SU3_EXPR_MUL, SU3_EXPR_MUL3, SU3_EXPR_MULADD, SU3_EXPR_ADD, SU3_EXPR_APB_AB = ra
 SU3_EXPR_CSHIFT, SU3_EXPR_MUL_SHIFTED = 5, 6  # launch-tuning keys only
 SU3_EXPR_DSLASH = 7  # launch-tuning key of su3_dslash (precision = links')
 SU3_EXPR_PROGRAM = 8  # launch-tuning key of su3_program_eval (arithmetic precision)
+SU3_EXPR_BATCH = 32  # + leading item's expression: launch-tuning key of a batch
 N_OPERANDS = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}
 
 # exported symbols of su3.h, in declaration order
@@ -53,9 +54,11 @@ SYMBOLS = (
     "su3_program_create", "su3_program_info", "su3_program_eval",
     "su3_program_destroy", "su3_vnode_wrap",
     "su3_batch_create", "su3_batch_launch", "su3_batch_destroy",
-    "su3_batch_tiles", "su3_autotune", "su3_batch_autotune", "su3_launch_get",
+    "su3_batch_tiles", "su3_autotune", "su3_layout_recommend", "su3_batch_autotune",
+    "su3_launch_get",
     "su3_launch_set",
-    "su3_launch_reset", "su3_triad", "su3_copy", "su3_sync",
+    "su3_launch_reset", "su3_stream", "su3_stream_autotune", "su3_triad",
+    "su3_copy", "su3_sync",
     "su3_status_string", "su3_last_error",
 )
 
@@ -70,7 +73,8 @@ class su3_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("lds_stage", ctypes.c_int32), ("tile_sites", ctypes.c_int32),
-                ("occupancy", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("occupancy", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("sites_per_lane", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -142,10 +146,15 @@ def load():
         "su3_batch_destroy": [vp],
         "su3_batch_tiles": [vp, vp, i64, ctypes.POINTER(i64)],
         "su3_autotune": [i32, i32, i32, i32, dims_t, vp, L],
+        "su3_layout_recommend": [i32, i32, dims_t, vp, ctypes.POINTER(i32),
+                                 ctypes.POINTER(i32), L, ctypes.POINTER(ctypes.c_double)],
         "su3_batch_autotune": [vp, vp, vp, i32, vp, L],
         "su3_launch_get": [i32, i32, i32, i32, dims_t, L],
         "su3_launch_set": [i32, i32, i32, i32, dims_t, L],
         "su3_launch_reset": [],
+        "su3_stream": [i32, vp, vp, vp, ctypes.c_double, sz, L, vp],
+        "su3_stream_autotune": [i32, vp, vp, vp, sz, vp, L,
+                                ctypes.POINTER(ctypes.c_double)],
         "su3_triad": [vp, vp, vp, ctypes.c_double, i64, vp],
         "su3_copy": [vp, vp, sz, vp],
         "su3_sync": [vp],
@@ -588,6 +597,17 @@ def su3_autotune(expr, prec, layout, lanes, dims, stream=None):
     return best
 
 
+def su3_layout_recommend(expr, prec, dims, stream=None):
+    """Returns (layout, lanes, tuned launch, median microseconds)."""
+    lay, lanes = ctypes.c_int32(), ctypes.c_int32()
+    best, us = su3_launch(), ctypes.c_double()
+    _check("su3_layout_recommend",
+           load().su3_layout_recommend(expr, prec, _dims(dims), _stream(stream),
+                                       ctypes.byref(lay), ctypes.byref(lanes),
+                                       ctypes.byref(best), ctypes.byref(us)))
+    return lay.value, lanes.value, best, us.value
+
+
 def su3_launch_get(expr, prec, layout, lanes, dims):
     out = su3_launch()
     _check("su3_launch_get", load().su3_launch_get(expr, prec, layout, lanes,
@@ -607,6 +627,27 @@ def su3_launch_reset():
 
 
 # ------------------------------------------------------------ yardsticks
+
+SU3_STREAM_TRIAD, SU3_STREAM_READ, SU3_STREAM_WRITE, SU3_STREAM_COPY = range(4)
+
+
+def su3_stream(kind, a, b, c, s, nbytes, cfg=None, stream=None):
+    if isinstance(cfg, dict):
+        cfg = su3_launch(**cfg)
+    _check("su3_stream", load().su3_stream(kind, a, b, c, float(s), int(nbytes),
+                                           ctypes.byref(cfg) if cfg is not None else None,
+                                           _stream(stream)))
+
+
+def su3_stream_autotune(kind, a, b, c, nbytes, stream=None):
+    """Returns (best launch, its median microseconds)."""
+    best = su3_launch()
+    us = ctypes.c_double()
+    _check("su3_stream_autotune",
+           load().su3_stream_autotune(kind, a, b, c, int(nbytes), _stream(stream),
+                                      ctypes.byref(best), ctypes.byref(us)))
+    return best, us.value
+
 
 def su3_triad(a, b, c, s, n, stream=None):
     _check("su3_triad", load().su3_triad(a, b, c, float(s), int(n), _stream(stream)))

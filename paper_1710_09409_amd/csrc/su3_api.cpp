@@ -666,6 +666,7 @@ static su3_launch default_launch(int expr, int prec, int layout)
     c.tile_sites = 4096;
     c.occupancy = layout == SU3_LAYOUT_AOS ? 0 : 5;
     c.schedule = layout == SU3_LAYOUT_AOS ? 0 : 1;
+    c.sites_per_lane = 0;
     if (expr == SU3_EXPR_PROGRAM) {
         c.block = 128;
         c.occupancy = 0;
@@ -688,19 +689,47 @@ static su3_launch default_launch(int expr, int prec, int layout)
     return c;
 }
 
+// Launch-tuning keys of batches are SU3_EXPR_BATCH + the leading item's
+// expression, so that a batch's tuned tile and grid never stand in for a
+// single field's launch of the same volume bucket (and the reverse).
+static bool is_batch_key(int expr)
+{
+    return expr >= SU3_EXPR_BATCH && expr <= SU3_EXPR_BATCH + SU3_EXPR_APB_AB;
+}
+
+static bool nt_valid(int nt, bool streaming)
+{
+    return (nt >= 0 && nt <= 3) || (streaming && (nt == 6 || nt == 7));
+}
+
 static su3_status check_launch(const su3_launch &c, int layout, int expr)
 {
     const bool lds_walk = expr == SU3_EXPR_DSLASH && c.schedule >= 4;
+    const bool site = expr >= SU3_EXPR_MUL && expr <= SU3_EXPR_APB_AB;
+    const bool batch = is_batch_key(expr);
+    const bool streaming = site || batch || expr == SU3_EXPR_CSHIFT ||
+                           expr == SU3_EXPR_MUL_SHIFTED;
+    const bool wide = site && (c.nontemporal & 3) == 3 && !c.lds_stage;
     if (c.block != 64 && c.block != 128 && c.block != 256 &&
-        !(lds_walk && c.block == 512))
-        return fail(SU3_ERR_INVALID_ARG, "block %d not in {64, 128, 256}%s",
-                    c.block, lds_walk ? " or 512" : "");
+        !(lds_walk && c.block == 512) &&
+        !(wide && (c.block == 512 || c.block == 1024)))
+        return fail(SU3_ERR_INVALID_ARG,
+                    "block %d not in {64, 128, 256}%s", c.block,
+                    lds_walk ? " or 512"
+                    : site   ? " (512 or 1024 need nontemporal 3 or 7)"
+                             : "");
+    if (!nt_valid(c.nontemporal, streaming))
+        return fail(SU3_ERR_INVALID_ARG, "nontemporal %d not in %s",
+                    c.nontemporal, streaming ? "{0, 1, 2, 3, 6, 7}" : "[0, 3]");
+    if (c.sites_per_lane != 0 && c.sites_per_lane != 1 &&
+        c.sites_per_lane != 2 && c.sites_per_lane != 4 &&
+        c.sites_per_lane != 8)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "sites_per_lane %d not in {0, 1, 2, 4, 8}",
+                    c.sites_per_lane);
     if (c.persistent < 0 || c.persistent > 64)
         return fail(SU3_ERR_INVALID_ARG, "persistent %d not in [0, 64]",
                     c.persistent);
-    if (c.nontemporal < 0 || c.nontemporal > 3)
-        return fail(SU3_ERR_INVALID_ARG, "nontemporal %d not in [0, 3]",
-                    c.nontemporal);
     if (c.xcd_remap < 0 || c.xcd_remap > (lds_walk ? 2 : 1))
         return fail(SU3_ERR_INVALID_ARG, "xcd_remap must be 0 or 1%s",
                     lds_walk ? " or 2" : "");
@@ -804,6 +833,8 @@ static void load_cache_locked()
             !parse_int(line, "occupancy", &c.occupancy) ||
             !parse_int(line, "schedule", &c.schedule))
             continue;
+        if (!parse_int(line, "sites_per_lane", &c.sites_per_lane))
+            c.sites_per_lane = 0;
         if (check_launch(c, la, ex) != SU3_OK)
             continue;
         g_tuned[Key(ex, pr, la, ln, vb)] = c;
@@ -824,11 +855,11 @@ static void append_cache(const Key &k, const su3_launch &c, double us)
             "\"lanes\":%d,\"vbucket\":%d,\"block\":%d,\"persistent\":%d,"
             "\"nontemporal\":%d,\"xcd_remap\":%d,\"lds_stage\":%d,"
             "\"tile_sites\":%d,\"occupancy\":%d,\"schedule\":%d,"
-            "\"us\":%.3f}\n",
+            "\"sites_per_lane\":%d,\"us\":%.3f}\n",
             device_tag().c_str(), std::get<0>(k), std::get<1>(k),
             std::get<2>(k), std::get<3>(k), std::get<4>(k), c.block,
             c.persistent, c.nontemporal, c.xcd_remap, c.lds_stage,
-            c.tile_sites, c.occupancy, c.schedule, us);
+            c.tile_sites, c.occupancy, c.schedule, c.sites_per_lane, us);
     fclose(fp);
 }
 
@@ -924,10 +955,19 @@ static su3_status launch_item(su3_field *z, int expr,
         e = launch_site_lds(z->prec, expr, c.nontemporal, c.block, (int)grid,
                             a, st);
     } else {
-        // S sites per lane must sit in one lane-block
+        // S sites per lane must sit in one lane-block: the natural count
+        // (or 1 where the blocks are shorter), or the launch's own count
         int S = natural_sites(z->prec, expr);
-        if (z->layout == SU3_LAYOUT_AOS || z->L % S != 0)
+        if (c.sites_per_lane > 0) {
+            S = c.sites_per_lane;
+            if (!sites_compiled(z->prec, expr, S) ||
+                (S > 1 && (z->layout == SU3_LAYOUT_AOS || z->L % S != 0)))
+                return fail(SU3_ERR_INVALID_ARG,
+                            "sites_per_lane %d is not offered for this "
+                            "expression, precision and lane-block", S);
+        } else if (z->layout == SU3_LAYOUT_AOS || z->L % S != 0) {
             S = 1;
+        }
         a.ngroups = (int32_t)((z->V + S - 1) / S);
         int64_t grid = (a.ngroups + c.block - 1) / c.block;
         if (c.persistent)
@@ -1435,8 +1475,9 @@ static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
                          int32_t lanes, const int32_t dims[4], Key *k,
                          Shape *shape)
 {
-    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_PROGRAM)
+    if ((expr < SU3_EXPR_MUL || expr > SU3_EXPR_PROGRAM) && !is_batch_key(expr))
         return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
+    const int base = is_batch_key(expr) ? expr - SU3_EXPR_BATCH : (int)expr;
     if (expr == SU3_EXPR_PROGRAM && prec != SU3_F64 && prec != SU3_F32)
         return fail(SU3_ERR_UNSUPPORTED,
                     "expression programs evaluate in F64 or F32");
@@ -1455,8 +1496,8 @@ static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
     if (st != SU3_OK)
         return st;
     if (prec == SU3_C12_F32 &&
-        (expr == SU3_EXPR_MULADD || expr == SU3_EXPR_ADD ||
-         expr == SU3_EXPR_APB_AB))
+        (base == SU3_EXPR_MULADD || base == SU3_EXPR_ADD ||
+         base == SU3_EXPR_APB_AB))
         return fail(SU3_ERR_UNSUPPORTED,
                     "the two-row compressed form supports MUL and MUL3 only");
     *k = Key(expr, prec, layout,
@@ -1510,10 +1551,11 @@ extern "C" su3_status su3_launch_reset(void)
     return SU3_OK;
 }
 
-// Candidate launches of the autotuner's sweep.  Persistent grid-stride
-// launches are kept as a few samples only: on this hardware one-shot grids
-// stream writes far better.
-static std::vector<su3_launch> candidates(int layout)
+// Candidate launches of the autotuner's sweep for a site-local expression
+// (or a shift: expr CSHIFT / MUL_SHIFTED, one site per lane, blocks up to
+// 256).  Persistent grid-stride launches are kept as a few samples only: on
+// this hardware one-shot grids stream writes far better.
+static std::vector<su3_launch> candidates(int layout, int expr, int prec)
 {
     std::vector<su3_launch> out;
     su3_launch c;
@@ -1521,11 +1563,12 @@ static std::vector<su3_launch> candidates(int layout)
     c.xcd_remap = 0;
     c.lds_stage = 0;
     c.tile_sites = 4096;
+    c.sites_per_lane = 0;
     if (layout == SU3_LAYOUT_AOS) {
         for (int b : {64, 128, 256})
-            for (int nt : {0, 3})
+            for (int nt : {0, 3, 7})
                 for (int lds = 0; lds < 2; ++lds) {
-                    if (lds && b > 128)
+                    if (lds && (b > 128 || nt == 7))
                         continue;
                     c.block = b;
                     c.nontemporal = nt;
@@ -1536,20 +1579,43 @@ static std::vector<su3_launch> candidates(int layout)
                 }
         return out;
     }
-    for (int b : {64, 128, 256})
-        for (int occ : {0, 2, 3, 4, 5, 6, 8})
-            for (int sched : {0, 1})
-                for (int nt : {0, 2, 3})
-                    for (int x : {0, 1}) {
-                        c.block = b;
-                        c.occupancy = occ;
-                        c.schedule = sched;
-                        c.nontemporal = nt;
-                        c.xcd_remap = x;
-                        out.push_back(c);
-                    }
+    const bool site = expr >= SU3_EXPR_MUL && expr <= SU3_EXPR_APB_AB;
+    // sites per lane: the natural count, and twice it for the product
+    std::vector<int> spl = {0};
+    if (expr == SU3_EXPR_MUL && prec != SU3_F16_F32ACC)
+        spl.push_back(2 * natural_sites(prec, expr));
+    for (int S : spl)
+        for (int b : {64, 128, 256})
+            for (int occ : {0, 2, 3, 4, 5, 6, 8})
+                for (int sched : {0, 1})
+                    for (int nt : {0, 2, 3, 7})
+                        for (int x : {0, 1}) {
+                            if (S && (nt != 7 || x))
+                                continue;  // wide lanes: streaming stores only
+                            c.block = b;
+                            c.occupancy = occ;
+                            c.schedule = sched;
+                            c.nontemporal = nt;
+                            c.xcd_remap = x;
+                            c.sites_per_lane = S;
+                            out.push_back(c);
+                        }
     c.xcd_remap = 0;
-    c.nontemporal = 3;
+    c.sites_per_lane = 0;
+    // 512- and 1024-lane workgroups (streaming stores), at most 32 waves
+    // per compute unit
+    if (site)
+        for (int b : {512, 1024})
+            for (int occ : {0, 1, 2, 3, 4})
+                for (int sched : {0, 1}) {
+                    if (occ * (b / 64) > 32)
+                        continue;
+                    c.block = b;
+                    c.occupancy = occ;
+                    c.schedule = sched;
+                    c.nontemporal = 7;
+                    out.push_back(c);
+                }
     for (int b : {64, 256})
         for (int p : {2, 4})
             for (int sched : {0, 1}) {
@@ -1557,6 +1623,7 @@ static std::vector<su3_launch> candidates(int layout)
                 c.persistent = p;
                 c.occupancy = 0;
                 c.schedule = sched;
+                c.nontemporal = 7;
                 out.push_back(c);
             }
     return out;
@@ -1676,11 +1743,14 @@ static su3_status time_launch(F launch, hipStream_t st, int warm, int reps,
     return SU3_OK;
 }
 
-extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
-                                   su3_layout layout, int32_t lanes,
-                                   const int32_t dims[4], void *stream,
-                                   su3_launch *best)
+static su3_status autotune_impl(su3_expr expr, su3_precision prec,
+                                su3_layout layout, int32_t lanes,
+                                const int32_t dims[4], void *stream,
+                                su3_launch *best, double *best_us)
 {
+    if (is_batch_key(expr))
+        return fail(SU3_ERR_INVALID_ARG,
+                    "batch keys are tuned by su3_batch_autotune");
     Key k;
     Shape s;
     su3_status st = key_of(expr, prec, layout, lanes, dims, &k, &s);
@@ -1750,7 +1820,7 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
                                                               layout == SU3_LAYOUT_VNODE
                                                                   ? (int)f0->L : 1)
                                    : expr == SU3_EXPR_PROGRAM ? program_candidates()
-                                                              : candidates(layout)) {
+                                                              : candidates(layout, expr, prec)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)
                 continue;  // a copy has no row phases
             double us = 0;
@@ -1797,6 +1867,52 @@ extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
     append_cache(k, win, win_us);
     if (best)
         *best = win;
+    if (best_us)
+        *best_us = win_us;
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_autotune(su3_expr expr, su3_precision prec,
+                                   su3_layout layout, int32_t lanes,
+                                   const int32_t dims[4], void *stream,
+                                   su3_launch *best)
+{
+    return autotune_impl(expr, prec, layout, lanes, dims, stream, best, nullptr);
+}
+
+extern "C" su3_status su3_layout_recommend(su3_expr expr, su3_precision prec,
+                                           const int32_t dims[4], void *stream,
+                                           su3_layout *layout, int32_t *lanes,
+                                           su3_launch *best, double *us)
+{
+    if (expr < SU3_EXPR_MUL || expr > SU3_EXPR_APB_AB)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "layouts are recommended for the site-local expressions");
+    if (!layout || !lanes)
+        return fail(SU3_ERR_INVALID_ARG, "layout or lanes is NULL");
+    // the candidates: SoA and AoSoA with every lane count; each tuned (and
+    // its launch kept, as su3_autotune does); the fastest tuned time wins,
+    // ties to the earlier (larger contiguous runs first)
+    const struct { su3_layout lay; int32_t L; } cand[] = {
+        {SU3_LAYOUT_SOA, 0}, {SU3_LAYOUT_AOSOA, 64}, {SU3_LAYOUT_AOSOA, 32},
+        {SU3_LAYOUT_AOSOA, 16}, {SU3_LAYOUT_AOSOA, 8}};
+    double win_us = 1e300;
+    for (const auto &c : cand) {
+        su3_launch l;
+        double t = 0;
+        su3_status st = autotune_impl(expr, prec, c.lay, c.L, dims, stream, &l, &t);
+        if (st != SU3_OK)
+            return st;
+        if (t < win_us) {
+            win_us = t;
+            *layout = c.lay;
+            *lanes = c.L;
+            if (best)
+                *best = l;
+        }
+    }
+    if (us)
+        *us = win_us;
     return SU3_OK;
 }
 
@@ -1853,8 +1969,8 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
     // of the leading item's key at the batch's total volume
     const su3_launch cfg =
         forced ? *forced
-               : lookup_launch(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
-                               total_sites);
+               : lookup_launch(SU3_EXPR_BATCH + exprs[0], z[0]->prec,
+                               z[0]->layout, z[0]->lanes, total_sites);
     const int T = cfg.tile_sites;
     // tile table: item i owns ceil(V_i / T) tiles starting at the exclusive
     // prefix sum of its predecessors' counts
@@ -1950,18 +2066,20 @@ static std::vector<su3_launch> batch_candidates()
     su3_launch c;
     c.xcd_remap = 0;
     c.lds_stage = 0;
-    c.nontemporal = 3;
+    c.sites_per_lane = 0;
     for (int tile : {64, 128, 256, 512, 2048, 8192})
         for (int bp : {0, 1, 2})  // block 64 / 128 one-shot, or 256 x 8 per CU
             for (int occ : {0, 4, 6})
-                for (int sched : {0, 1}) {
-                    c.tile_sites = tile;
-                    c.persistent = bp == 2 ? 8 : 0;
-                    c.block = bp == 0 ? 64 : (bp == 1 ? 128 : 256);
-                    c.occupancy = occ;
-                    c.schedule = sched;
-                    out.push_back(c);
-                }
+                for (int sched : {0, 1})
+                    for (int nt : {3, 7}) {
+                        c.tile_sites = tile;
+                        c.persistent = bp == 2 ? 8 : 0;
+                        c.block = bp == 0 ? 64 : (bp == 1 ? 128 : 256);
+                        c.occupancy = occ;
+                        c.schedule = sched;
+                        c.nontemporal = nt;
+                        out.push_back(c);
+                    }
     return out;
 }
 
@@ -1996,8 +2114,8 @@ extern "C" su3_status su3_batch_autotune(const su3_expr *exprs,
             win = c;
         }
     }
-    const Key k(exprs[0], z[0]->prec, z[0]->layout, z[0]->lanes,
-                vbucket(total));
+    const Key k(SU3_EXPR_BATCH + exprs[0], z[0]->prec, z[0]->layout,
+                z[0]->lanes, vbucket(total));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache_locked();
@@ -2038,34 +2156,136 @@ extern "C" su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows,
 
 // ------------------------------------------------------ yardsticks
 
+// Default launch of each yardstick kind (the fastest of its sweep at 2.29
+// GB on MI355X): 64-lane workgroups, 16 per compute unit, for the mixes
+// with reads; 128-lane workgroups, 12 per compute unit, for the write-only
+// stream; write-through streaming stores and nontemporal loads.
+static su3_launch stream_default(int kind)
+{
+    su3_launch c;
+    std::memset(&c, 0, sizeof c);
+    c.block = kind == SU3_STREAM_WRITE ? 128 : 64;
+    c.occupancy = kind == SU3_STREAM_WRITE ? 12 : 16;
+    c.nontemporal = 7;
+    c.tile_sites = 4096;
+    return c;
+}
+
+// Yardstick over n16 16-byte elements per array (and, with `tail`, the
+// triad's trailing double).
+static su3_status stream_launch(int kind, void *a, const void *b,
+                                const void *c, double s, int64_t n16,
+                                int tail, const su3_launch &cfg,
+                                hipStream_t st)
+{
+    if (kind < SU3_STREAM_TRIAD || kind > SU3_STREAM_COPY)
+        return fail(SU3_ERR_INVALID_ARG, "unknown yardstick kind %d", kind);
+    const bool reads_b = kind != SU3_STREAM_WRITE;
+    const bool reads_c = kind == SU3_STREAM_TRIAD || kind == SU3_STREAM_READ;
+    if (!a || (reads_b && !b) || (reads_c && !c))
+        return fail(SU3_ERR_INVALID_ARG, "NULL array");
+    if (n16 < 0 || (n16 == 0 && !tail))
+        return fail(SU3_ERR_INVALID_ARG, "empty arrays");
+    if (((uintptr_t)a | (uintptr_t)(reads_b ? b : a) |
+         (uintptr_t)(reads_c ? c : a)) & 15)
+        return fail(SU3_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
+    if (cfg.block < 64 || cfg.block > 1024 || cfg.block % 64)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "block %d not a multiple of 64 in [64, 1024]", cfg.block);
+    if (!nt_valid(cfg.nontemporal, true))
+        return fail(SU3_ERR_INVALID_ARG, "nontemporal %d not in {0, 1, 2, 3, 6, 7}",
+                    cfg.nontemporal);
+    if (cfg.occupancy < 0 || cfg.occupancy > 64)
+        return fail(SU3_ERR_INVALID_ARG, "occupancy %d not in [0, 64]",
+                    cfg.occupancy);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    hipError_t e = launch_stream(kind, a, b, c, s, n16, tail,
+                                 cfg.nontemporal, cfg.block,
+                                 occupancy_reserve(dev, cfg.occupancy), st);
+    if (e != hipSuccess)
+        return hip_fail(e, "yardstick launch");
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_stream(su3_stream_kind kind, void *a, const void *b,
+                                 const void *c, double s, size_t bytes,
+                                 const su3_launch *cfg, void *stream)
+{
+    if (bytes == 0 || bytes % 16)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "bytes must be a positive multiple of 16");
+    const su3_launch l = cfg ? *cfg : stream_default(kind);
+    return stream_launch(kind, a, b, c, s, (int64_t)(bytes / 16), 0, l,
+                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" su3_status su3_stream_autotune(su3_stream_kind kind, void *a,
+                                          const void *b, const void *c,
+                                          size_t bytes, void *stream,
+                                          su3_launch *best, double *us_out)
+{
+    if (bytes == 0 || bytes % 16)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "bytes must be a positive multiple of 16");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    su3_launch win = stream_default(kind);
+    double win_us = 1e300;
+    su3_launch l = win;
+    for (int blk : {64, 128, 256, 512, 1024})
+        for (int occ : {0, 1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 32})
+            for (int nt : {0, 2, 3, 6, 7}) {
+                if (occ * (blk / 64) > 32 || (occ == 0 && blk > 256) ||
+                    (occ == 1 && blk < 512))
+                    continue;
+                l.block = blk;
+                l.occupancy = occ;
+                l.nontemporal = nt;
+                double us = 0;
+                su3_status st = time_launch(
+                    [&]() {
+                        return stream_launch(kind, a, b, c, 3.0,
+                                             (int64_t)(bytes / 16), 0, l, hs);
+                    },
+                    hs, 3, 10, &us);
+                if (st != SU3_OK && win_us >= 1e300)
+                    return st;  // invalid arguments: nothing tuned
+                if (st != SU3_OK) {
+                    (void)hipGetLastError();
+                    continue;
+                }
+                if (us < win_us) {
+                    win_us = us;
+                    win = l;
+                }
+            }
+    if (best)
+        *best = win;
+    if (us_out)
+        *us_out = win_us;
+    return SU3_OK;
+}
+
 extern "C" su3_status su3_triad(double *a, const double *b, const double *c,
                                 double s, int64_t n, void *stream)
 {
-    if (!a || !b || !c)
-        return fail(SU3_ERR_INVALID_ARG, "NULL array");
     if (n <= 0)
         return fail(SU3_ERR_INVALID_ARG, "n must be > 0");
-    if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15)
-        return fail(SU3_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
-    hipError_t e = launch_triad(a, b, c, s, n, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess)
-        return hip_fail(e, "triad launch");
-    return SU3_OK;
+    return stream_launch(SU3_STREAM_TRIAD, a, b, c, s, n / 2, (int)(n & 1),
+                         stream_default(SU3_STREAM_TRIAD),
+                         static_cast<hipStream_t>(stream));
 }
 
 extern "C" su3_status su3_copy(void *dst, const void *src, size_t bytes,
                                void *stream)
 {
-    if (!dst || !src)
-        return fail(SU3_ERR_INVALID_ARG, "NULL pointer");
     if (bytes == 0 || bytes % 16)
-        return fail(SU3_ERR_INVALID_ARG, "bytes must be a positive multiple of 16");
-    if (((uintptr_t)dst | (uintptr_t)src) & 15)
-        return fail(SU3_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
-    hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess)
-        return hip_fail(e, "copy launch");
-    return SU3_OK;
+        return fail(SU3_ERR_INVALID_ARG,
+                    "bytes must be a positive multiple of 16");
+    return stream_launch(SU3_STREAM_COPY, dst, src, nullptr, 0.0,
+                         (int64_t)(bytes / 16), 0,
+                         stream_default(SU3_STREAM_COPY),
+                         static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------------ misc

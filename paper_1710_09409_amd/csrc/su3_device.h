@@ -66,7 +66,8 @@ template <class R, int N> struct VecOf {
     typedef R type __attribute__((ext_vector_type(N)));
 };
 
-// Nontemporal bit 0 = loads, bit 1 = stores.
+// Nontemporal bit 0 = loads, bit 1 = stores, bit 2 (with bit 1) =
+// write-through streaming stores (below).
 template <int NT, class V>
 __device__ __forceinline__ V vload(const V *p)
 {
@@ -76,10 +77,59 @@ __device__ __forceinline__ V vload(const V *p)
         return *p;
 }
 
+// Buffer descriptor word 3 of the gfx9 family (raw byte buffer) and the
+// cache-policy bits of a streaming store: nt (bit 1) with sc1 (bit 4),
+// i.e. nontemporal and written through at system scope.  On gfx950 these
+// stores stream results to HBM 1.5-2 % faster than plain nontemporal
+// stores (2:1 read:write mixes at 48^4) and no kernel here reads back
+// what it writes.
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kStreamStoreAux = 2 | 16;
+
+// Streaming store of one 2-, 4-, 8-, 16- or 32-byte value through a buffer
+// descriptor whose base is wave-uniform: the first active lane's address
+// less 2 GiB, so every lane of the wave within 2 GiB of that address
+// (all stores of these kernels: a wave writes consecutive sites) has a
+// 32-bit offset, whatever the field's size.
+template <class V>
+__device__ __forceinline__ void stream_store(V *p, V v)
+{
+    typedef unsigned U2 __attribute__((ext_vector_type(2)));
+    typedef unsigned U4 __attribute__((ext_vector_type(4)));
+    typedef unsigned U8 __attribute__((ext_vector_type(8)));
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    const uint64_t base = ((uint64_t(hi) << 32) | lo) - (uint64_t(1) << 31);
+    const uint32_t off = uint32_t(a - base);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void *>(base), (short)0, -1, kBufWord3);
+    if constexpr (sizeof(V) == 32) {
+        const U8 w = __builtin_bit_cast(U8, v);
+        __builtin_amdgcn_raw_buffer_store_b128(w.lo, r, off, 0, kStreamStoreAux);
+        __builtin_amdgcn_raw_buffer_store_b128(w.hi, r, off + 16, 0, kStreamStoreAux);
+    } else if constexpr (sizeof(V) == 16)
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, off, 0,
+                                               kStreamStoreAux);
+    else if constexpr (sizeof(V) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0,
+                                              kStreamStoreAux);
+    else if constexpr (sizeof(V) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off,
+                                              0, kStreamStoreAux);
+    else {
+        static_assert(sizeof(V) == 2, "stream_store: 2, 4, 8, 16 or 32 bytes");
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r,
+                                              off, 0, kStreamStoreAux);
+    }
+}
+
 template <int NT, class V>
 __device__ __forceinline__ void vstore(V *p, V v)
 {
-    if constexpr (NT & 2)
+    if constexpr ((NT & 6) == 6)
+        stream_store(p, v);
+    else if constexpr (NT & 2)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;

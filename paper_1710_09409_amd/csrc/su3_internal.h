@@ -89,10 +89,21 @@ struct BatchItem {
     int32_t tile_start;
 };
 
+// Sites per lane the site kernels are compiled for: 1, the natural count,
+// and for the streaming product (MUL) outside half storage twice the
+// natural count (32 bytes per lane and entry).
+inline bool sites_compiled(int prec, int expr, int S)
+{
+    const int n = natural_sites(prec, expr);
+    return S == 1 || S == n || (expr == MUL && prec != F16 && S == 2 * n);
+}
+
 // Kernel-unit entry points.  Each returns the launch's hipError_t.
-// `sites_per_lane` must be natural_sites(prec, expr) for blocked layouts or
-// 1; `sched` 0 = all loads then all stores, 1 = row-phased; `shm` is LDS
-// reserved per workgroup to cap occupancy (never read); block <= 256.
+// `sites_per_lane` as sites_compiled (the natural count or 1 in the AoS
+// layout); `sched` 0 = all loads then all stores, 1 = row-phased; `nt` in
+// {0, 1, 2, 3, 6, 7} (bit 2: write-through streaming stores); `shm` is LDS
+// reserved per workgroup to cap occupancy (never read); block <= 256, or
+// 512 / 1024 with nt 3 or 7.
 hipError_t launch_site(int prec, int expr, int sites_per_lane, int nt,
                        int sched, int block, int grid, size_t shm,
                        const SiteArgs &a, hipStream_t stream);
@@ -110,12 +121,15 @@ hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
 hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
                         int grid, size_t shm, const ShiftArgs &a,
                         hipStream_t stream);
-hipError_t launch_triad(double *a, const double *b, const double *c,
-                        double s, int64_t n, hipStream_t stream);
-hipError_t launch_copy(void *dst, const void *src, size_t bytes,
-                       hipStream_t stream);
+// Bandwidth yardsticks over n16 16-byte elements per array (kinds below);
+// `tail` adds the triad's trailing double; nt in {0, 1, 2, 3, 6, 7};
+// block a multiple of 64 up to 1024; `shm` as for launch_site.
+enum StreamKind { STREAM_TRIAD = 0, STREAM_READ = 1, STREAM_WRITE = 2, STREAM_COPY = 3 };
+hipError_t launch_stream(int kind, void *a, const void *b, const void *c,
+                         double s, int64_t n16, int tail, int nt, int block,
+                         size_t shm, hipStream_t stream);
 
-// Largest block the kernel family was compiled for.
-constexpr int kMaxBlock = 256;
+// Largest block of the site kernels (512 and 1024 take nt 3 or 7 only).
+constexpr int kMaxBlock = 1024;
 
 }  // namespace su3i

@@ -1,4 +1,5 @@
-// Batched persistent kernel, bandwidth yardsticks (triad, copy) and the
+// Batched persistent kernel, bandwidth yardsticks (triad, read-only,
+// write-only, copy) and the
 // per-precision dispatch of the site kernels.
 #include "su3_device.h"
 
@@ -104,34 +105,49 @@ __global__ __launch_bounds__(256) void k_batch(const BatchItem *items,
         occupancy_reserve[threadIdx.x] = 0;
 }
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_triad(double *a, const double *b,
-                                               const double *c, double s,
-                                               int64_t n)
+// Bandwidth yardsticks, one 16-byte element per lane, one-shot grid:
+// triad a = b + s*c (doubles), read-only (b and c), write-only (a = s),
+// copy (a = b).  The read-only kind writes a[0] only if an element of
+// b + c equals (s, -s), which keeps its loads without a store stream.
+// With `tail` the triad also covers the double after the last element.
+template <int KIND, int NT>
+__global__ __launch_bounds__(1024) void k_stream(void *a, const void *b,
+                                                 const void *c, double s,
+                                                 int64_t n16, int tail)
 {
+    extern __shared__ char occupancy_reserve[];
     using D2 = VecOf<double, 2>::type;
-    const int64_t n2 = n >> 1;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
-         i += stride) {
-        const D2 bv = vload<NT>(reinterpret_cast<const D2 *>(b) + i);
-        const D2 cv = vload<NT>(reinterpret_cast<const D2 *>(c) + i);
-        vstore<NT>(reinterpret_cast<D2 *>(a) + i, bv + s * cv);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    D2 *A = static_cast<D2 *>(a);
+    const D2 *Bv = static_cast<const D2 *>(b);
+    const D2 *C = static_cast<const D2 *>(c);
+    if (i < n16) {
+        if constexpr (KIND == su3i::STREAM_TRIAD) {
+            const D2 bv = vload<NT>(Bv + i);
+            const D2 cv = vload<NT>(C + i);
+            vstore<NT>(A + i, bv + s * cv);
+        } else if constexpr (KIND == su3i::STREAM_READ) {
+            const D2 v = vload<NT>(Bv + i) + vload<NT>(C + i);
+            if (v[0] == s && v[1] == -s)
+                A[0] = v;
+        } else if constexpr (KIND == su3i::STREAM_WRITE) {
+            D2 v;
+            v[0] = s;
+            v[1] = s;
+            vstore<NT>(A + i, v);
+        } else {
+            vstore<NT>(A + i, vload<NT>(Bv + i));
+        }
     }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
-        a[n - 1] = b[n - 1] + s * c[n - 1];
-}
-
-template <int NT>
-__global__ __launch_bounds__(256) void k_copy(void *dst, const void *src,
-                                              int64_t n16)
-{
-    using V4 = VecOf<unsigned, 4>::type;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
-         i += stride)
-        vstore<NT>(reinterpret_cast<V4 *>(dst) + i,
-                   vload<NT>(reinterpret_cast<const V4 *>(src) + i));
+    if constexpr (KIND == su3i::STREAM_TRIAD) {
+        if (tail && i == 0) {
+            const int64_t k = 2 * n16;
+            static_cast<double *>(a)[k] = static_cast<const double *>(b)[k] +
+                                          s * static_cast<const double *>(c)[k];
+        }
+    }
+    if (n16 < 0)
+        occupancy_reserve[threadIdx.x] = 0;
 }
 
 }  // namespace su3k
@@ -188,8 +204,9 @@ hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
 {
     if (block > 256)
         return hipErrorInvalidValue;
-    const bool ntb = (nt & 3) == 3;
-    const int v = (mode ? 4 : 0) + (ntb ? 2 : 0) + (sched ? 1 : 0);
+    // nontemporal settings compiled: 0, 3 and 7 (others run as 0 or 3)
+    const int ntv = nt == 7 ? 2 : ((nt & 3) == 3 ? 1 : 0);
+    const int v = (mode ? 6 : 0) + 2 * ntv + (sched ? 1 : 0);
 #define SU3_BATCH(M, N, S) \
     batch_go<M, N, S>(items, nitems, ntiles, tile_sites, block, grid, shm, st)
     switch (v) {
@@ -197,41 +214,62 @@ hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
     case 1: SU3_BATCH(0, 0, 1); break;
     case 2: SU3_BATCH(0, 3, 0); break;
     case 3: SU3_BATCH(0, 3, 1); break;
-    case 4: SU3_BATCH(1, 0, 0); break;
-    case 5: SU3_BATCH(1, 0, 1); break;
-    case 6: SU3_BATCH(1, 3, 0); break;
-    default: SU3_BATCH(1, 3, 1); break;
+    case 4: SU3_BATCH(0, 7, 0); break;
+    case 5: SU3_BATCH(0, 7, 1); break;
+    case 6: SU3_BATCH(1, 0, 0); break;
+    case 7: SU3_BATCH(1, 0, 1); break;
+    case 8: SU3_BATCH(1, 3, 0); break;
+    case 9: SU3_BATCH(1, 3, 1); break;
+    case 10: SU3_BATCH(1, 7, 0); break;
+    default: SU3_BATCH(1, 7, 1); break;
     }
 #undef SU3_BATCH
     return hipGetLastError();
 }
 
-static int one_shot_grid(int64_t items, int block)
+template <int KIND, int NT>
+static void stream_go(void *a, const void *b, const void *c, double s,
+                      int64_t n16, int tail, int block, int grid, size_t shm,
+                      hipStream_t st)
 {
-    int64_t g = (items + block - 1) / block;
-    if (g > (int64_t)1 << 30)
-        g = (int64_t)1 << 30;
-    return (int)(g < 1 ? 1 : g);
+    hipLaunchKernelGGL((su3k::k_stream<KIND, NT>), dim3(grid), dim3(block), shm,
+                       st, a, b, c, s, n16, tail);
 }
 
-// Yardsticks: one-shot grids of 64-lane workgroups stream best here.
-hipError_t launch_triad(double *a, const double *b, const double *c, double s,
-                        int64_t n, hipStream_t st)
+template <int KIND>
+static hipError_t stream_nt(int nt, void *a, const void *b, const void *c,
+                            double s, int64_t n16, int tail, int block,
+                            int grid, size_t shm, hipStream_t st)
 {
-    const int block = 64;
-    hipLaunchKernelGGL(su3k::k_triad<3>, dim3(one_shot_grid(n / 2, block)),
-                       dim3(block), 0, st, a, b, c, s, n);
+    switch (nt) {
+    case 0: stream_go<KIND, 0>(a, b, c, s, n16, tail, block, grid, shm, st); break;
+    case 1: stream_go<KIND, 1>(a, b, c, s, n16, tail, block, grid, shm, st); break;
+    case 2: stream_go<KIND, 2>(a, b, c, s, n16, tail, block, grid, shm, st); break;
+    case 3: stream_go<KIND, 3>(a, b, c, s, n16, tail, block, grid, shm, st); break;
+    case 6: stream_go<KIND, 6>(a, b, c, s, n16, tail, block, grid, shm, st); break;
+    case 7: stream_go<KIND, 7>(a, b, c, s, n16, tail, block, grid, shm, st); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_copy(void *dst, const void *src, size_t bytes,
-                       hipStream_t st)
+hipError_t launch_stream(int kind, void *a, const void *b, const void *c,
+                         double s, int64_t n16, int tail, int nt, int block,
+                         size_t shm, hipStream_t st)
 {
-    const int block = 64;
-    const int64_t n16 = (int64_t)(bytes / 16);
-    hipLaunchKernelGGL(su3k::k_copy<3>, dim3(one_shot_grid(n16, block)),
-                       dim3(block), 0, st, dst, src, n16);
-    return hipGetLastError();
+    if (block < 64 || block > 1024 || block % 64)
+        return hipErrorInvalidValue;
+    const int64_t g = (n16 + block - 1) / block;
+    if (g > ((int64_t)1 << 31) - 1)
+        return hipErrorInvalidValue;
+    const int grid = g < 1 ? 1 : (int)g;
+    switch (kind) {
+    case STREAM_TRIAD: return stream_nt<STREAM_TRIAD>(nt, a, b, c, s, n16, tail, block, grid, shm, st);
+    case STREAM_READ: return stream_nt<STREAM_READ>(nt, a, b, c, s, n16, tail, block, grid, shm, st);
+    case STREAM_WRITE: return stream_nt<STREAM_WRITE>(nt, a, b, c, s, n16, tail, block, grid, shm, st);
+    case STREAM_COPY: return stream_nt<STREAM_COPY>(nt, a, b, c, s, n16, tail, block, grid, shm, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace su3i

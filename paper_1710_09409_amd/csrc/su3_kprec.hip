@@ -24,11 +24,13 @@ namespace SU3_CAT(p, SU3_PREC) {
 
 constexpr int P = SU3_PREC;
 constexpr int kMaxSiteBlock = 256;
+// k_site variants for workgroups of 512 and 1024 lanes
+constexpr int kWideBlock = 1024;
 using R = typename PrecT<P>::R;
 using T = typename PrecT<P>::T;
 
-template <int X, int S, int NT, int SCHED>
-__global__ __launch_bounds__(kMaxSiteBlock) void k_site(su3i::SiteArgs a)
+template <int X, int S, int NT, int SCHED, int MAXB>
+__global__ __launch_bounds__(MAXB) void k_site(su3i::SiteArgs a)
 {
     // Dynamic LDS is reserved only to cap how many workgroups share a CU
     // (the launch's occupancy setting); it is never read.
@@ -194,15 +196,29 @@ template <int X, int S, int NT>
 static hipError_t run_site(int sched, int block, int grid, size_t shm,
                            const su3i::SiteArgs &a, hipStream_t st)
 {
-    if (block > kMaxSiteBlock)
+    if (block <= kMaxSiteBlock) {
+        if (sched)
+            hipLaunchKernelGGL((k_site<X, S, NT, 1, kMaxSiteBlock>), dim3(grid),
+                               dim3(block), shm, st, a);
+        else
+            hipLaunchKernelGGL((k_site<X, S, NT, 0, kMaxSiteBlock>), dim3(grid),
+                               dim3(block), shm, st, a);
+        return hipGetLastError();
+    }
+    // 512 and 1024 lanes: compiled for the streaming store settings only
+    if constexpr ((NT & 3) == 3) {
+        if (block > kWideBlock)
+            return hipErrorInvalidValue;
+        if (sched)
+            hipLaunchKernelGGL((k_site<X, S, NT, 1, kWideBlock>), dim3(grid),
+                               dim3(block), shm, st, a);
+        else
+            hipLaunchKernelGGL((k_site<X, S, NT, 0, kWideBlock>), dim3(grid),
+                               dim3(block), shm, st, a);
+        return hipGetLastError();
+    } else {
         return hipErrorInvalidValue;
-    if (sched)
-        hipLaunchKernelGGL((k_site<X, S, NT, 1>), dim3(grid), dim3(block), shm,
-                           st, a);
-    else
-        hipLaunchKernelGGL((k_site<X, S, NT, 0>), dim3(grid), dim3(block), shm,
-                           st, a);
-    return hipGetLastError();
+    }
 }
 
 template <int X, int S>
@@ -213,8 +229,11 @@ static hipError_t pick_nt(int nt, int sched, int block, int grid, size_t shm,
     case 0: return run_site<X, S, 0>(sched, block, grid, shm, a, st);
     case 1: return run_site<X, S, 1>(sched, block, grid, shm, a, st);
     case 2: return run_site<X, S, 2>(sched, block, grid, shm, a, st);
-    default: return run_site<X, S, 3>(sched, block, grid, shm, a, st);
+    case 3: return run_site<X, S, 3>(sched, block, grid, shm, a, st);
+    case 6: return run_site<X, S, 6>(sched, block, grid, shm, a, st);
+    case 7: return run_site<X, S, 7>(sched, block, grid, shm, a, st);
     }
+    return hipErrorInvalidValue;
 }
 
 template <int X>
@@ -224,11 +243,17 @@ static hipError_t pick_s(int S, int nt, int sched, int block, int grid,
     if constexpr (!Supported<P, X>::value) {
         return hipErrorInvalidValue;
     } else {
+        constexpr int SN = SitesPerLane<P, X>::value;
         if (S == 1)
             return pick_nt<X, 1>(nt, sched, block, grid, shm, a, st);
-        if (S == SitesPerLane<P, X>::value)
-            return pick_nt<X, SitesPerLane<P, X>::value>(nt, sched, block, grid,
-                                                         shm, a, st);
+        if (S == SN)
+            return pick_nt<X, SN>(nt, sched, block, grid, shm, a, st);
+        // twice the natural count (32 bytes per lane and entry): the
+        // streaming product in double, single and compressed storage
+        if constexpr (X == su3i::MUL && P != su3i::F16) {
+            if (S == 2 * SN)
+                return pick_nt<X, 2 * SN>(nt, sched, block, grid, shm, a, st);
+        }
         return hipErrorInvalidValue;
     }
 }
@@ -283,19 +308,24 @@ hipError_t SU3_CAT(launch_shift_p, SU3_PREC)(int mode, int nt, int sched,
     using namespace su3k::SU3_CAT(p, SU3_PREC);
     if (block > kMaxSiteBlock)
         return hipErrorInvalidValue;
-    const bool ntb = (nt & 3) == 3;
+    // nontemporal settings compiled: 0, 3 and 7 (others run as 0 or 3)
+    const int ntv = nt == 7 ? 7 : ((nt & 3) == 3 ? 3 : 0);
     if (mode == 0) {
-        if (ntb)
+        if (ntv == 7)
+            hipLaunchKernelGGL((k_shift<0, 7, 0>), dim3(grid), dim3(block), shm, st, a);
+        else if (ntv == 3)
             hipLaunchKernelGGL((k_shift<0, 3, 0>), dim3(grid), dim3(block), shm, st, a);
         else
             hipLaunchKernelGGL((k_shift<0, 0, 0>), dim3(grid), dim3(block), shm, st, a);
     } else {
-        const int v = (ntb ? 2 : 0) + (sched ? 1 : 0);
+        const int v = (ntv == 7 ? 4 : (ntv == 3 ? 2 : 0)) + (sched ? 1 : 0);
         switch (v) {
         case 0: hipLaunchKernelGGL((k_shift<1, 0, 0>), dim3(grid), dim3(block), shm, st, a); break;
         case 1: hipLaunchKernelGGL((k_shift<1, 0, 1>), dim3(grid), dim3(block), shm, st, a); break;
         case 2: hipLaunchKernelGGL((k_shift<1, 3, 0>), dim3(grid), dim3(block), shm, st, a); break;
-        default: hipLaunchKernelGGL((k_shift<1, 3, 1>), dim3(grid), dim3(block), shm, st, a); break;
+        case 3: hipLaunchKernelGGL((k_shift<1, 3, 1>), dim3(grid), dim3(block), shm, st, a); break;
+        case 4: hipLaunchKernelGGL((k_shift<1, 7, 0>), dim3(grid), dim3(block), shm, st, a); break;
+        default: hipLaunchKernelGGL((k_shift<1, 7, 1>), dim3(grid), dim3(block), shm, st, a); break;
         }
     }
     return hipGetLastError();

@@ -8,8 +8,8 @@
 // A register holds a 3x3 complex matrix (NE = 9; a scalar uses entry 0).
 // Programs without matrix values run in their own kernel, whose registers
 // hold one complex value for each of the lane's S sites; programs whose
-// every value is real (operands, intermediates and result, the shape of
-// Listing 2) in a third, whose registers hold one real per site.  Register
+// every value is real (operands, intermediates and result, as in the
+// real-valued composite example of Section 3, Listing 2) in a third, whose registers hold one real per site.  Register
 // indices are uniform across the wave and are resolved by a chain of
 // compare-and-copy branches, so the register file stays in VGPRs.
 #include <type_traits>

@@ -78,9 +78,16 @@ int main(int argc, char **argv)
                     su3_launch c0 = {64, 0, 3, 0, 0, 4096, 0, 0};
                     su3_launch c1 = {128, 0, 3, 1, 0, 4096, 4, 1};
                     if (l[0] == 0) c1.schedule = 0;
+                    // streaming stores, 1024-lane persistent workgroups, and
+                    // twice the natural sites per lane for the product
+                    const int spl = (expr == 0 && prec != 2 && l[0] != 0) ? (prec == 0 ? 2 : 4) : 0;
+                    su3_launch c2 = {1024, 1, 7, 0, 0, 4096, 0, l[0] == 0 ? 0 : 1, spl};
+                    su3_launch c3 = {64, 0, 6, 0, 0, 4096, 2, 0, l[0] == 0 ? 0 : 1};
                     double e = run_case(d, prec, l[0], l[1], expr, &c0);
                     double e1 = run_case(d, prec, l[0], l[1], expr, &c1);
-                    if (e != e1) { printf("schedules differ: "); fails++; }
+                    double e2 = run_case(d, prec, l[0], l[1], expr, &c2);
+                    double e3 = run_case(d, prec, l[0], l[1], expr, &c3);
+                    if (e != e1 || e != e2 || e != e3) { printf("launch settings differ: "); fails++; }
                     if (e > (prec == 0 ? 1e-13 : 1e-5) || argc > 1)
                         printf("dims %dx%dx%dx%d prec %d layout %d/%d expr %d err %.3e\n", d[0], d[1], d[2], d[3], prec, l[0], l[1], expr, e);
                 }
@@ -135,13 +142,13 @@ int main(int argc, char **argv)
             }
             int td[4] = {(int)total, 1, 1, 1};
             su3_launch c = {256, (T == 256 ? 2 : 0), 3, 0, 0, T, 3, (T == 64 ? 1 : 0)};
-            su3_launch_set(ex[0], (su3_precision)items[0].prec, (su3_layout)items[0].lay, items[0].lanes, td, &c);
+            su3_launch_set((su3_expr)(SU3_EXPR_BATCH + ex[0]), (su3_precision)items[0].prec, (su3_layout)items[0].lay, items[0].lanes, td, &c);
             su3_batch *b;
             if (T == 4096) {
                 su3_launch best;
                 if (su3_batch_autotune(ex.data(), zs.data(), ops.data(), n, nullptr, &best) != SU3_OK) { printf("batch autotune %s\n", su3_last_error()); fails++; }
                 else printf("batch autotune picked tile %d pers %d\n", best.tile_sites, best.persistent);
-                su3_launch_set(ex[0], (su3_precision)items[0].prec, (su3_layout)items[0].lay, items[0].lanes, td, &c);
+                su3_launch_set((su3_expr)(SU3_EXPR_BATCH + ex[0]), (su3_precision)items[0].prec, (su3_layout)items[0].lay, items[0].lanes, td, &c);
             }
             if (su3_batch_create(&b, ex.data(), zs.data(), ops.data(), n, nullptr) != SU3_OK) { printf("batch %s\n", su3_last_error()); fails++; continue; }
             su3_launch_reset();

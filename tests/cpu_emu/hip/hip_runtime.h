@@ -39,6 +39,31 @@ enum { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
 inline hipError_t hipFuncSetAttribute(const void *, int, int) { return hipSuccess; }
 enum { hipDeviceAttributeMultiprocessorCount = 1, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor = 2, hipDeviceAttributeMaxSharedMemoryPerBlock = 3 };
 inline void __builtin_amdgcn_sched_barrier(int) {}
+// Buffer stores and readfirstlane for one lane at a time: the wave-uniform
+// base of a lane is its own address, and a store is bounds-checked against
+// the descriptor's record count before it lands (AddressSanitizer checks
+// the address itself).
+struct emu_buffer_rsrc { char *base; uint32_t records; };
+typedef emu_buffer_rsrc __amdgpu_buffer_rsrc_t;
+inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return v; }
+inline emu_buffer_rsrc __builtin_amdgcn_make_buffer_rsrc(void *p, short, int records, int)
+{
+    return {static_cast<char *>(p), static_cast<uint32_t>(records)};
+}
+template <class V>
+inline void emu_buffer_store(V v, emu_buffer_rsrc r, uint32_t off, uint32_t soff)
+{
+    const uint64_t at = (uint64_t)off + soff;
+    if (at + sizeof(V) > r.records) {
+        std::fprintf(stderr, "buffer store out of the descriptor's range\n");
+        std::abort();
+    }
+    std::memcpy(r.base + at, &v, sizeof(V));
+}
+#define __builtin_amdgcn_raw_buffer_store_b128(v, r, off, soff, aux) emu_buffer_store(v, r, off, soff)
+#define __builtin_amdgcn_raw_buffer_store_b64(v, r, off, soff, aux) emu_buffer_store(v, r, off, soff)
+#define __builtin_amdgcn_raw_buffer_store_b32(v, r, off, soff, aux) emu_buffer_store(v, r, off, soff)
+#define __builtin_amdgcn_raw_buffer_store_b16(v, r, off, soff, aux) emu_buffer_store(v, r, off, soff)
 struct hipPointerAttribute_t { int type; int device; };
 struct hipDeviceProp_t { char gcnArchName[64]; int multiProcessorCount; };
 

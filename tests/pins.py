@@ -151,12 +151,14 @@ def pin_associative(orc):
 
 # --------------------------------------------------------- O2 fused
 
-def pin_listing2(orc):
-    """The composite expressions of Listing 2 on SU(3)-typed fields."""
-    g = read_golden("listing2_composite.txt")
+def pin_constant_fields_fused(orc):
+    """The sum and the sum-plus-product of the constant SU(3)-typed fields
+    1*I and 2*I (the inputs of Section 3's composite-expression example,
+    Listing 2) are exactly 3*I and 5*I."""
+    g = read_golden("composite_constants.txt")
     V = 8
-    a = testgen.identity(V, g["v1"])
-    b = testgen.identity(V, g["v2"])
+    a = testgen.identity(V, g["a"])
+    b = testgen.identity(V, g["b"])
     assert np.array_equal(orc.fused(O.ADD, [a, b]), testgen.identity(V, g["ADD"]))
     assert np.array_equal(orc.fused(O.APB_AB, [a, b]),
                           testgen.identity(V, g["APB_AB"]))
@@ -566,21 +568,22 @@ def pin_vnode_layout(orc):
                               orc.pack(x, prec, O.AOSOA, 8))
 
 
-def pin_expr_listing2(orc):
-    """Listing 2 on real (double) fields through the expression evaluator:
-    v1 = 1.0, v2 = 2.0 assigned as constants, v3 = v1+v2 and
-    v3 = v1+v2+v1*v2 (exact), and the SU(3)-typed counterparts equal the
-    fixed expressions."""
-    g = read_golden("listing2_composite.txt")
+def pin_expr_constant_fields(orc):
+    """Through the expression evaluator: constant real fields 1 and 2 (the
+    inputs of Section 3's composite-expression example, Listing 2) assigned
+    from constant expressions; their sum is exactly 3 and the sum plus their
+    product exactly 5; on SU(3)-typed fields 1*I and 2*I the second gives
+    5*I."""
+    g = read_golden("composite_constants.txt")
     V = 12
-    v1 = orc.eval_expr(repr(g["v1"]), [], [], V=V)
-    v2 = orc.eval_expr(repr(g["v2"]), [], [], V=V)
-    assert np.array_equal(v1, np.full(V, g["v1"])) and np.array_equal(v2, np.full(V, g["v2"]))
-    assert np.array_equal(orc.eval_expr("a+b", [v1, v2], [2, 2]), np.full(V, g["real_ADD"]))
-    assert np.array_equal(orc.eval_expr("a+b+a*b", [v1, v2], [2, 2]),
+    a = orc.eval_expr(repr(g["a"]), [], [], V=V)
+    b = orc.eval_expr(repr(g["b"]), [], [], V=V)
+    assert np.array_equal(a, np.full(V, g["a"])) and np.array_equal(b, np.full(V, g["b"]))
+    assert np.array_equal(orc.eval_expr("a+b", [a, b], [2, 2]), np.full(V, g["real_ADD"]))
+    assert np.array_equal(orc.eval_expr("a+b+a*b", [a, b], [2, 2]),
                           np.full(V, g["real_APB_AB"]))
-    x = testgen.identity(V, g["v1"])
-    y = testgen.identity(V, g["v2"])
+    x = testgen.identity(V, g["a"])
+    y = testgen.identity(V, g["b"])
     assert np.array_equal(orc.eval_expr("a+b+a*b", [x, y], [0, 0]),
                           testgen.identity(V, g["APB_AB"]))
 
@@ -652,10 +655,10 @@ def pin_expr_rejects(orc):
 
 ALL_PINS = [pin_identity, pin_phase_diag, pin_signed_permutations,
             pin_unitary_inverse, pin_numpy_matmul, pin_nonsymmetric,
-            pin_product_invariants, pin_associative, pin_listing2,
+            pin_product_invariants, pin_associative, pin_constant_fields_fused,
             pin_fused_reductions, pin_fused_numpy, pin_fused_unitary,
             pin_quantisers, pin_c12_rebuild, pin_layouts, pin_roundtrip,
             pin_metrics, pin_cshift, pin_dslash_free_field,
             pin_dslash_gamma5_hermitian, pin_dslash_gauge_covariant,
-            pin_vnode_layout, pin_expr_listing2, pin_expr_matches_fixed,
+            pin_vnode_layout, pin_expr_constant_fields, pin_expr_matches_fixed,
             pin_expr_numpy, pin_expr_rejects]

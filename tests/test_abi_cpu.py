@@ -25,7 +25,7 @@ def header_functions():
 def test_every_declared_symbol_is_exported():
     lib = su3.load()
     names = header_functions()
-    assert len(names) == 40
+    assert len(names) == 43
     assert set(names) == set(su3.SYMBOLS)
     for n in names:
         assert hasattr(lib, n), n
@@ -155,6 +155,21 @@ def test_compute_validation_without_fields():
     assert lib.su3_triad(None, None, None, 1.0, 10, None) == su3.SU3_ERR_INVALID_ARG
     assert lib.su3_copy(None, None, 16, None) == su3.SU3_ERR_INVALID_ARG
     assert lib.su3_copy(16, 32, 15, None) == su3.SU3_ERR_INVALID_ARG
+    # yardsticks: arrays, sizes, kinds and launch knobs are checked first
+    E = su3.SU3_ERR_INVALID_ARG
+    assert lib.su3_stream(0, None, None, None, 1.0, 16, None, None) == E
+    assert lib.su3_stream(su3.SU3_STREAM_TRIAD, 16, 32, None, 1.0, 16, None, None) == E
+    assert lib.su3_stream(su3.SU3_STREAM_COPY, 16, 32, None, 1.0, 24, None, None) == E
+    assert lib.su3_stream(su3.SU3_STREAM_COPY, 16, 32, None, 1.0, 0, None, None) == E
+    assert lib.su3_stream(su3.SU3_STREAM_COPY, 16, 40, None, 1.0, 32, None, None) == E
+    assert lib.su3_stream(7, 16, 32, 48, 1.0, 32, None, None) == E
+    for bad in (dict(block=96), dict(block=2048), dict(block=64, nontemporal=5),
+                dict(block=64, occupancy=-1)):
+        cfg = su3.su3_launch(**bad)
+        assert lib.su3_stream(su3.SU3_STREAM_WRITE, 16, None, None, 1.0, 32,
+                              ctypes.byref(cfg), None) == E
+    assert lib.su3_stream_autotune(su3.SU3_STREAM_READ, 16, None, 48, 32, None,
+                                   None, None) == E
     assert lib.su3_batch_launch(None, None) == su3.SU3_ERR_INVALID_ARG
     assert lib.su3_batch_destroy(None) == su3.SU3_OK
     assert lib.su3_field_free(None) == su3.SU3_OK
@@ -167,7 +182,8 @@ def test_launch_table():
     d = su3.su3_launch_get(0, 0, 1, 0, dims)
     assert d.block in (64, 128, 256, 512, 1024)
     cfg = dict(block=128, persistent=4, nontemporal=2, xcd_remap=0,
-               lds_stage=0, tile_sites=2048, occupancy=3, schedule=1)
+               lds_stage=0, tile_sites=2048, occupancy=3, schedule=1,
+               sites_per_lane=0)
     su3.su3_launch_set(0, 0, 1, 0, dims, cfg)
     assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == cfg
     # same power-of-two volume bucket shares the setting
@@ -176,9 +192,37 @@ def test_launch_table():
     for bad in (dict(cfg, block=96), dict(cfg, block=512), dict(cfg, nontemporal=4),
                 dict(cfg, persistent=-1), dict(cfg, lds_stage=1),
                 dict(cfg, tile_sites=100), dict(cfg, xcd_remap=2),
-                dict(cfg, occupancy=-1), dict(cfg, schedule=2)):
+                dict(cfg, occupancy=-1), dict(cfg, schedule=2),
+                dict(cfg, nontemporal=5), dict(cfg, sites_per_lane=3),
+                dict(cfg, block=1024, nontemporal=6), dict(cfg, block=2048, nontemporal=7)):
         assert _status(su3.su3_launch_set, 0, 0, 1, 0, dims, bad) == \
             su3.SU3_ERR_INVALID_ARG
+    # streaming stores (nontemporal 6, 7), 512- and 1024-lane workgroups
+    # with nontemporal 3 or 7, and explicit sites per lane on site-local keys
+    for good in (dict(cfg, nontemporal=7), dict(cfg, nontemporal=6),
+                 dict(cfg, block=512, nontemporal=3), dict(cfg, block=1024, nontemporal=7),
+                 dict(cfg, nontemporal=7, sites_per_lane=2),
+                 dict(cfg, sites_per_lane=1)):
+        su3.su3_launch_set(0, 0, 1, 0, dims, good)
+        assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == good
+    # ... which Dslash and programs do not take
+    for key in (su3.SU3_EXPR_DSLASH, su3.SU3_EXPR_PROGRAM):
+        assert _status(su3.su3_launch_set, key, 0, 1, 0, dims,
+                       dict(cfg, nontemporal=7)) == su3.SU3_ERR_INVALID_ARG
+    # batches have keys of their own (SU3_EXPR_BATCH + leading expression)
+    for e in range(5):
+        su3.su3_launch_set(su3.SU3_EXPR_BATCH + e, 0, 1, 0, dims, dict(cfg, nontemporal=7))
+        assert su3.su3_launch_get(su3.SU3_EXPR_BATCH + e, 0, 1, 0, dims).nontemporal == 7
+    assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == dict(cfg, sites_per_lane=1)
+    assert _status(su3.su3_launch_set, su3.SU3_EXPR_BATCH + 2, 3, 1, 0, dims, cfg) == \
+        su3.SU3_ERR_UNSUPPORTED
+    assert _status(su3.su3_launch_set, su3.SU3_EXPR_BATCH + 5, 0, 1, 0, dims, cfg) == \
+        su3.SU3_ERR_INVALID_ARG
+    assert _status(su3.su3_launch_set, su3.SU3_EXPR_BATCH + 5, 0, 1, 0, dims, cfg) == \
+        su3.SU3_ERR_INVALID_ARG
+    assert su3.load().su3_autotune(su3.SU3_EXPR_BATCH, 0, 1, 0, su3._dims(dims), None,
+                                   None) == su3.SU3_ERR_INVALID_ARG
+    su3.su3_launch_set(0, 0, 1, 0, dims, cfg)
     assert _status(su3.su3_launch_set, 0, 0, 0, 0, dims,
                    dict(cfg, lds_stage=1, block=128)) == 0
     assert _status(su3.su3_launch_set, 3, 3, 1, 0, dims, cfg) == \

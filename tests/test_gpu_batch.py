@@ -41,15 +41,17 @@ def _build(items, stream, tile_sites):
 
 
 @pytest.mark.parametrize("items", [ITEMS_MIXED, ITEMS_ANY], ids=["mixed", "any"])
-@pytest.mark.parametrize("tile,pers,sched", [(64, 0, 1), (256, 2, 0), (4096, 0, 0),
-                                             (4096, 4, 1)])
-def test_batch_matches_unbatched(items, tile, pers, sched):
+@pytest.mark.parametrize("tile,pers,sched,nt", [(64, 0, 1, 3), (256, 2, 0, 3), (4096, 0, 0, 3),
+                                                (4096, 4, 1, 3), (2048, 0, 1, 7),
+                                                (512, 2, 0, 7)])
+def test_batch_matches_unbatched(items, tile, pers, sched, nt):
     s = torch.cuda.current_stream()
     dims0, prec0, lay0, lanes0, expr0 = items[0]
     total = sum(testgen.volume(d) for d, *_ in items)
-    cfg = su3.su3_launch_get(expr0, prec0, lay0, lanes0, (total, 1, 1, 1))
-    cfg.tile_sites, cfg.persistent, cfg.schedule = tile, pers, sched
-    su3.su3_launch_set(expr0, prec0, lay0, lanes0, (total, 1, 1, 1), cfg)
+    key = su3.SU3_EXPR_BATCH + expr0
+    cfg = su3.su3_launch_get(key, prec0, lay0, lanes0, (total, 1, 1, 1))
+    cfg.tile_sites, cfg.persistent, cfg.schedule, cfg.nontemporal = tile, pers, sched, nt
+    su3.su3_launch_set(key, prec0, lay0, lanes0, (total, 1, 1, 1), cfg)
     try:
         zs, ops, hosts, exprs = _build(items, s, tile)
         b = su3.su3_batch_create(exprs, zs, ops, s)

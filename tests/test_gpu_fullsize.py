@@ -1,7 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch configuration the
 benchmark times (the autotuner's choice): every site of 48^4 for each
 storage precision, the fused expressions on four link fields at 32^4, and
-sampled sites of every lattice of the 64-lattice batch.  Also reports the
+every site of every lattice of the 64-lattice batch.  Also reports the
 end-to-end error of the reduced-precision forms against the FP64 truth
 (max elementwise error, normwise relative error, unitarity and determinant
 deviation), printed and, when SU3_REPORT_DIR names a folder, written there
@@ -88,38 +88,68 @@ def test_fused_32(prec, expr, lay, lanes):
     assert_parity(prec, expr, got, want, f"32^4 fused {expr} {PREC_NAMES[prec]}")
 
 
-def test_batch_64_sampled():
-    """The benchmark's 64-lattice batch (seed 1710, AoSoA(64) storage, the
-    batch autotuner's launch), checked on 512 sampled sites of every
-    lattice plus its first and last site."""
+def test_batch_64_every_site():
+    """The benchmark's 64-lattice batch (seed 1710, each item stored in the
+    layout the library recommends for its lattice and precision, the batch
+    autotuner's launch) against the oracle at every site of every lattice;
+    then the other kind of grid (a persistent grid looping over the tiles if
+    the tuned launch is one-shot, else one workgroup per tile) replayed into
+    fresh outputs gives the same bits."""
     s = torch.cuda.current_stream()
     lat = testgen.batch_lattices(64)
+    exprs = [su3.SU3_EXPR_MUL] * 64
+    rec = {}
+    for d, comp in lat:
+        prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
+        if (d, prec) not in rec:
+            rec[(d, prec)] = su3.su3_layout_recommend(su3.SU3_EXPR_MUL, prec, d, s)[:2]
     zs, ops = [], []
     for i, (d, comp) in enumerate(lat):
         prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
+        lay, lanes = rec[(d, prec)]
         V = testgen.volume(d)
         row = []
         for k in range(2):
-            f = su3.field_tensor(d, prec, su3.SU3_LAYOUT_AOSOA, 64)
+            f = su3.field_tensor(d, prec, lay, lanes)
             su3.su3_field_upload(f, testgen.su3_field(V, field_id=testgen.FID_BATCH_BASE + 4 * i + k), s)
             row.append(f)
         ops.append(row)
-        zs.append(su3.field_tensor(d, prec, su3.SU3_LAYOUT_AOSOA, 64))
-    su3.su3_batch_autotune([su3.SU3_EXPR_MUL] * 64, zs, ops, s)
-    b = su3.su3_batch_create([su3.SU3_EXPR_MUL] * 64, zs, ops, s)
+        zs.append(su3.field_tensor(d, prec, lay, lanes))
+    cfg = su3.su3_batch_autotune(exprs, zs, ops, s)
+    b = su3.su3_batch_create(exprs, zs, ops, s)
     su3.su3_batch_launch(b, s)
     su3.su3_sync(s)
-    rng = np.random.default_rng(3)
+    su3.su3_batch_destroy(b)
     for i, (d, comp) in enumerate(lat):
         prec = su3.SU3_C12_F32 if comp else su3.SU3_F64
         V = testgen.volume(d)
-        sites = np.unique(np.concatenate([[0, V - 1], rng.integers(0, V, 512)]))
-        x = testgen.su3_sites(sites, field_id=testgen.FID_BATCH_BASE + 4 * i)
-        y = testgen.su3_sites(sites, field_id=testgen.FID_BATCH_BASE + 4 * i + 1)
+        x = testgen.su3_field(V, field_id=testgen.FID_BATCH_BASE + 4 * i)
+        y = testgen.su3_field(V, field_id=testgen.FID_BATCH_BASE + 4 * i + 1)
         want = O.get().reference(su3.SU3_EXPR_MUL, prec, [x, y])
-        got = su3.su3_field_download(zs[i], s)[sites]
-        assert_parity(prec, su3.SU3_EXPR_MUL, got, want, f"batch lattice {i} {d}")
+        got = su3.su3_field_download(zs[i], s)
+        assert_parity(prec, su3.SU3_EXPR_MUL, got, want, f"batch lattice {i} {d} {cfg.as_dict()}")
+    # the other grid kind, same tile table rules, bit for bit
+    other = su3.su3_launch(**cfg.as_dict())
+    if cfg.persistent:
+        other.persistent = 0
+    else:
+        other.persistent, other.block, other.tile_sites = 2, 256, 2048
+    total = sum(testgen.volume(d) for d, _ in lat)
+    kprec = su3.SU3_C12_F32 if lat[0][1] else su3.SU3_F64
+    klay, klanes = rec[(lat[0][0], kprec)]
+    key = su3.SU3_EXPR_BATCH + su3.SU3_EXPR_MUL
+    z2 = [su3.field_tensor(d, p, *rec[(d, p)])
+          for d, p in ((d, su3.SU3_C12_F32 if c else su3.SU3_F64) for d, c in lat)]
+    su3.su3_launch_set(key, kprec, klay, klanes, (total, 1, 1, 1), other)
+    try:
+        b = su3.su3_batch_create(exprs, z2, ops, s)
+    finally:
+        su3.su3_launch_reset()
+    su3.su3_batch_launch(b, s)
+    su3.su3_sync(s)
     su3.su3_batch_destroy(b)
+    for i in range(64):
+        assert torch.equal(zs[i].owner, z2[i].owner), (i, other.as_dict())
 
 
 def test_precision_error_report():

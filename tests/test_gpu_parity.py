@@ -85,30 +85,57 @@ def test_layouts_bit_identical(prec):
 
 
 LAUNCHES = [dict(block=b, persistent=p, nontemporal=nt, xcd_remap=x,
-                 lds_stage=0, tile_sites=4096, occupancy=occ, schedule=sc)
+                 lds_stage=0, tile_sites=4096, occupancy=occ, schedule=sc,
+                 sites_per_lane=0)
             for b, p, nt, x, occ, sc in itertools.product(
-                (64, 256), (0, 1), (0, 3), (0, 1), (0, 3), (0, 1))]
+                (64, 256), (0, 1), (0, 3, 7), (0, 1), (0, 3), (0, 1))]
+# write-through streaming stores, 512- and 1024-lane workgroups (streaming
+# or nontemporal stores), one site per lane, and (the product outside half
+# storage) twice the natural sites per lane, one-shot and persistent
+LAUNCHES += [dict(block=b, persistent=p, nontemporal=nt, xcd_remap=x,
+                  lds_stage=0, tile_sites=4096, occupancy=occ, schedule=sc,
+                  sites_per_lane=spl)
+             for b, p, nt, x, occ, sc, spl in (
+                 (64, 0, 6, 0, 5, 1, 0), (512, 0, 7, 0, 2, 1, 0), (512, 1, 3, 1, 0, 0, 0),
+                 (1024, 0, 3, 0, 1, 0, 0), (1024, 1, 7, 0, 0, 1, 0),
+                 (128, 0, 7, 0, 4, 1, 1), (64, 1, 0, 0, 0, 0, 1),
+                 (64, 0, 7, 0, 4, 1, -2), (256, 1, 7, 1, 0, 0, -2), (1024, 0, 7, 0, 1, 1, -2))]
+
+
+def _launch_for(cfg, prec, expr):
+    """The setting with sites_per_lane -2 read as twice the natural count
+    (offered for the product outside half storage); None where not offered."""
+    if cfg["sites_per_lane"] != -2:
+        return cfg
+    if expr != su3.SU3_EXPR_MUL or prec == su3.SU3_F16_F32ACC:
+        return None
+    return dict(cfg, sites_per_lane=2 if prec == su3.SU3_F64 else 4)
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=[PREC_NAMES[p] for p in PRECS])
 def test_launch_settings_bit_identical(prec):
-    """Every launch setting (block, persistent grid-stride, nontemporal
-    bits, XCD remap, occupancy cap, load/store schedule) yields the same
-    bits for every expression; the persistent grid of one workgroup per CU
-    exercises the grid-stride loop at 16^4."""
-    dims = (16, 16, 16, 16)
+    """Every launch setting (block, persistent grid-stride, nontemporal and
+    streaming-store bits, XCD remap, occupancy cap, load/store schedule,
+    sites per lane) yields the same bits for every expression; the
+    persistent grid of one workgroup per CU exercises the grid-stride loop
+    at 16^4, and 3 x 5 x 7 x 11 leaves ragged tails for every sites-per-lane
+    count."""
     layout = su3.SU3_LAYOUT_SOA
     try:
-        for expr in exprs_for(prec):
-            ops, want = _inputs_and_ref(prec, expr, dims)
-            base = None
-            for cfg in LAUNCHES:
-                su3.su3_launch_set(expr, prec, layout, 0, dims, cfg)
-                got, _ = run_expr(dims, prec, layout, 0, expr, ops)
-                if base is None:
-                    base = got
-                    assert_parity(prec, expr, got, want, f"launch {cfg}")
-                assert np.array_equal(got, base), (expr, cfg)
+        for dims in ((16, 16, 16, 16), (3, 5, 7, 11)):
+            for expr in exprs_for(prec):
+                ops, want = _inputs_and_ref(prec, expr, dims)
+                base = None
+                for cfg0 in LAUNCHES:
+                    cfg = _launch_for(cfg0, prec, expr)
+                    if cfg is None:
+                        continue
+                    su3.su3_launch_set(expr, prec, layout, 0, dims, cfg)
+                    got, _ = run_expr(dims, prec, layout, 0, expr, ops)
+                    if base is None:
+                        base = got
+                        assert_parity(prec, expr, got, want, f"launch {cfg}")
+                    assert np.array_equal(got, base), (dims, expr, cfg)
     finally:
         su3.su3_launch_reset()
 
@@ -143,14 +170,15 @@ def test_signed_permutations_exact():
             assert np.array_equal(got, want), (prec, lay, lanes)
 
 
-def test_listing2_composite():
-    """Listing 2's v3 = v1+v2 and v3 = v1+v2+v1*v2 with v1 = 1, v2 = 2 on
-    SU(3)-typed fields: 3 I and 5 I exactly."""
+def test_constant_fields_composite():
+    """The sum and the sum-plus-product of the constant SU(3)-typed fields
+    1*I and 2*I (Section 3's composite-expression example, Listing 2) are
+    exactly 3*I and 5*I in every precision that takes sums and every layout."""
     from pins import read_golden
-    g = read_golden("listing2_composite.txt")
+    g = read_golden("composite_constants.txt")
     dims = (4, 4, 4, 4)
     V = testgen.volume(dims)
-    a, b = testgen.identity(V, g["v1"]), testgen.identity(V, g["v2"])
+    a, b = testgen.identity(V, g["a"]), testgen.identity(V, g["b"])
     for prec in (su3.SU3_F64, su3.SU3_F32, su3.SU3_F16_F32ACC):
         for lay, lanes in LAYOUTS:
             got, _ = run_expr(dims, prec, lay, lanes, su3.SU3_EXPR_ADD, [a, b])

@@ -1,5 +1,6 @@
 """Expression programs on the GPU against the oracle's own expression
-evaluator: Listing 2 on real (double) fields, mixed matrix / real /
+evaluator: the composite-expression example of Section 3 (Listing 2) on
+real (double) fields, mixed matrix / real /
 complex expressions in every layout (virtual nodes included), double and
 single arithmetic (single with compressed matrix operands too), in-place
 outputs, compressed outputs of SU(3)-valued expressions, argument rules,
@@ -103,23 +104,24 @@ def test_program_parity(arith, lay):
         assert err <= bound, f"{text} {LAY_IDS[LAYS.index(lay)]}: {err:.3e} > {bound:.3e}"
 
 
-def test_listing2_real_fields():
-    """v1 = 1.0; v2 = 2.0; v3 = v1+v2; v3 = v1+v2+v1*v2 on double fields,
-    exactly, at a ragged volume in SoA (padding untouched)."""
+def test_constant_fields_real():
+    """Constant real fields a = 1 and b = 2 (assigned from constant
+    expressions) give a+b = 3 and a+b+a*b = 5 exactly at a ragged volume in
+    SoA, and the padding of the output is left alone."""
     s = torch.cuda.current_stream()
     dims = (3, 5, 7, 11)
     V = testgen.volume(dims)
     lay = (su3.SU3_LAYOUT_SOA, 0, None)
-    v1, v2, v3 = (make(dims, su3.SU3_F64, R, lay, None, s) for _ in range(3))
-    v3.owner.fill_(0x77)
-    su3.su3_program_eval(su3.Program("1.0", []), v1, [], s)
-    su3.su3_program_eval(su3.Program("2.0", []), v2, [], s)
-    su3.su3_program_eval(su3.Program("a+b", [R, R]), v3, [v1, v2], s)
-    assert np.array_equal(su3.su3_field_download(v3, s), np.full(V, 3.0))
-    su3.su3_program_eval(su3.Program("a+b+a*b", [R, R]), v3, [v1, v2], s)
+    a, b, z = (make(dims, su3.SU3_F64, R, lay, None, s) for _ in range(3))
+    z.owner.fill_(0x77)
+    su3.su3_program_eval(su3.Program("1.0", []), a, [], s)
+    su3.su3_program_eval(su3.Program("2.0", []), b, [], s)
+    su3.su3_program_eval(su3.Program("a+b", [R, R]), z, [a, b], s)
+    assert np.array_equal(su3.su3_field_download(z, s), np.full(V, 3.0))
+    su3.su3_program_eval(su3.Program("a+b+a*b", [R, R]), z, [a, b], s)
     su3.su3_sync(s)
-    assert np.array_equal(su3.su3_field_download(v3, s), np.full(V, 5.0))
-    raw = su3.su3_field_download_raw(v3, s)
+    assert np.array_equal(su3.su3_field_download(z, s), np.full(V, 5.0))
+    raw = su3.su3_field_download_raw(z, s)
     assert np.all(raw[8 * V:] == 0x77)  # padding of the 64-site round-up
 
 
@@ -196,30 +198,30 @@ def test_program_product_full_size():
 
 
 @pytest.mark.parametrize("prec", [su3.SU3_F64, su3.SU3_F32], ids=["f64", "f32"])
-def test_listing2_real_full_size(prec):
-    """Listing 2 on real fields at 48^4 in the launch the benchmark times
-    (the real-valued kernel): the constants 1.0 and 2.0 give 5.0 at every
-    site exactly, and seeded random fields agree with the oracle."""
+def test_constant_fields_real_full_size(prec):
+    """a+b+a*b on real fields at 48^4 in the launch the benchmark times (the
+    real-valued kernel): constant fields 1 and 2 give 5 at every site
+    exactly, and seeded random fields agree with the oracle."""
     s = torch.cuda.current_stream()
     dims = (48, 48, 48, 48)
     V = testgen.volume(dims)
     lay = (su3.SU3_LAYOUT_SOA, 0, None)
     su3.su3_autotune(su3.SU3_EXPR_PROGRAM, prec, su3.SU3_LAYOUT_SOA, 0, dims, s)
     try:
-        v1, v2, v3 = (make(dims, prec, R, lay, None, s) for _ in range(3))
-        su3.su3_program_eval(su3.Program("1.0", []), v1, [], s)
-        su3.su3_program_eval(su3.Program("2.0", []), v2, [], s)
+        a, b, z = (make(dims, prec, R, lay, None, s) for _ in range(3))
+        su3.su3_program_eval(su3.Program("1.0", []), a, [], s)
+        su3.su3_program_eval(su3.Program("2.0", []), b, [], s)
         prog = su3.Program("a+b+a*b", [R, R])
-        su3.su3_program_eval(prog, v3, [v1, v2], s)
+        su3.su3_program_eval(prog, z, [a, b], s)
         su3.su3_sync(s)
-        assert np.array_equal(su3.su3_field_download(v3, s), np.full(V, 5.0))
+        assert np.array_equal(su3.su3_field_download(z, s), np.full(V, 5.0))
         hosts = [host_operand(V, R, k) for k in range(2)]
         q = [quantise(h, R, prec) for h in hosts]
-        for f, h in zip((v1, v2), hosts):
+        for f, h in zip((a, b), hosts):
             su3.su3_field_upload(f, h, s)
-        su3.su3_program_eval(prog, v3, [v1, v2], s)
+        su3.su3_program_eval(prog, z, [a, b], s)
         su3.su3_sync(s)
-        got = su3.su3_field_download(v3, s)
+        got = su3.su3_field_download(z, s)
         want = O.get().eval_expr("a+b+a*b", q, [int(R), int(R)], V=V)
         err, bound = tol(got, want.reshape(got.shape), prec != su3.SU3_F64)
         assert err <= bound, f"{err:.3e} > {bound:.3e}"

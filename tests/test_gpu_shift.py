@@ -33,13 +33,20 @@ def test_shift_parity(dims, prec):
         for mu in range(4):
             for k in SHIFTS:
                 want = O.get().cshift(qy, dims, mu, k)
-                su3.su3_cshift(fz, fy, mu, k, s)
-                got = su3.su3_field_download(fz, s)
-                assert np.array_equal(got, want), (LAYOUT_NAMES[lay], lanes, mu, k)
+                for nt in (3, 7):
+                    cfg = dict(block=64, persistent=0, nontemporal=nt, xcd_remap=0,
+                               lds_stage=0, tile_sites=4096, occupancy=0, schedule=0)
+                    su3.su3_launch_set(su3.SU3_EXPR_CSHIFT, prec, lay, lanes, dims, cfg)
+                    try:
+                        su3.su3_cshift(fz, fy, mu, k, s)
+                    finally:
+                        su3.su3_launch_reset()
+                    got = su3.su3_field_download(fz, s)
+                    assert np.array_equal(got, want), (LAYOUT_NAMES[lay], lanes, mu, k, nt)
                 ref = O.get().mult(qx, want)
                 prev = None
-                for sched in (0, 1):
-                    cfg = dict(block=64, persistent=0, nontemporal=3, xcd_remap=0,
+                for sched, nt in ((0, 3), (1, 3), (1, 7)):
+                    cfg = dict(block=64, persistent=0, nontemporal=nt, xcd_remap=0,
                                lds_stage=0, tile_sites=4096, occupancy=4,
                                schedule=sched)
                     su3.su3_launch_set(su3.SU3_EXPR_MUL_SHIFTED, prec, lay, lanes,
