@@ -100,7 +100,10 @@ def parse():
                     help="comma-separated sections to run alone (%s), without "
                          "the headline (for profiler runs)" % ", ".join(SECTIONS))
     ap.add_argument("--layout", default="both", choices=("soa", "aosoa64", "both"),
-                    help="layouts of the precision section")
+                    help="layouts of the precision, fused and dslash sections")
+    ap.add_argument("--lean", action="store_true",
+                    help="sections time only their configured kernels (no chained, "
+                         "cold or alternative-grid runs), for profiler runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain copies of known size (PMC scaling)")
     return ap.parse_args()
@@ -514,6 +517,8 @@ def section_fused(ctx):
     for prec, lname, lay, lanes in ((su3.SU3_F64, "soa", SOA, 0), (su3.SU3_F32, "soa", SOA, 0),
                                     (su3.SU3_F64, "aosoa64", AOSOA, 64),
                                     (su3.SU3_F32, "aosoa64", AOSOA, 64)):
+        if args.layout != "both" and lname != args.layout:
+            continue
         U = [make(d, prec, lay, lanes, testgen.FID_U0 + mu) for mu in range(4)]
         z = su3.field_tensor(d, prec, lay, lanes)
         t1 = su3.field_tensor(d, prec, lay, lanes)
@@ -525,6 +530,11 @@ def section_fused(ctx):
             tune(su3.SU3_EXPR_ADD, prec, lay, lanes, d)
             ms_f, _ = timer.run(lambda: su3.su3_fused_eval(z, expr, U[:nops], stream),
                                 steps, 3)
+            b = expr_bytes_per_site(prec, expr) * Vf
+            key = f"{PREC_NAME[prec]}_{lname}_{name}"
+            if args.lean:
+                out[key] = entry(ms_f, b)
+                continue
             if expr == su3.SU3_EXPR_MUL3:
                 def chained():
                     su3.su3_mult(t1, U[0], U[1], stream)
@@ -535,7 +545,6 @@ def section_fused(ctx):
                     su3.su3_mult(t2, U[2], U[3], stream)
                     su3.su3_fused_eval(z, su3.SU3_EXPR_ADD, [t1, t2], stream)
             ms_c, _ = timer.run(chained, steps, 3)
-            b = expr_bytes_per_site(prec, expr) * Vf
             # cold: operand sets rotating through >= 1 GiB
             k = max(2, -(-(1 << 30) // b))
             sets = [(U[:nops], z)]
@@ -559,7 +568,6 @@ def section_fused(ctx):
             e.update(chained_us=round(ms_c * 1e3, 1), x_chained=round(ms_c / ms_f, 2),
                      cold_us=c["us"], cold_gbps=c["gbps"], cold_pct=c["pct"], sets=k,
                      cached=b < 2 * MALL_BYTES)
-            key = f"{PREC_NAME[prec]}_{lname}_{name}"
             if lname == "soa":
                 if prec == su3.SU3_F64:
                     cpu.add(e, "cpu", lambda orc, x=expr, n=nops: orc.fused(x, hU[:n]), b)

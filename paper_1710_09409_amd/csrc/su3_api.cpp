@@ -2157,22 +2157,24 @@ extern "C" su3_status su3_batch_tiles(const su3_batch *b, int32_t *rows,
 // ------------------------------------------------------ yardsticks
 
 // Default launch of each yardstick kind (the fastest of its sweep at 2.29
-// GB on MI355X): 64-lane workgroups, 16 per compute unit, for the mixes
-// with reads; 128-lane workgroups, 12 per compute unit, for the write-only
-// stream; write-through streaming stores and nontemporal loads.
+// GB on MI355X): 64-lane workgroups, 20 per compute unit for the triad,
+// 16 for read-only, no cap for copy; 128-lane workgroups, 12 per compute
+// unit, for the write-only stream; write-through streaming stores and
+// nontemporal loads.
 static su3_launch stream_default(int kind)
 {
     su3_launch c;
     std::memset(&c, 0, sizeof c);
     c.block = kind == SU3_STREAM_WRITE ? 128 : 64;
-    c.occupancy = kind == SU3_STREAM_WRITE ? 12 : 16;
+    c.occupancy = kind == SU3_STREAM_TRIAD  ? 20
+                  : kind == SU3_STREAM_READ ? 16
+                  : kind == SU3_STREAM_WRITE ? 12
+                                             : 0;
     c.nontemporal = 7;
     c.tile_sites = 4096;
     return c;
 }
 
-// Yardstick over n16 16-byte elements per array (and, with `tail`, the
-// triad's trailing double).
 static su3_status stream_launch(int kind, void *a, const void *b,
                                 const void *c, double s, int64_t n16,
                                 int tail, const su3_launch &cfg,

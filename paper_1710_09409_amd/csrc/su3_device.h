@@ -86,24 +86,36 @@ __device__ __forceinline__ V vload(const V *p)
 constexpr int kBufWord3 = 0x00020000;
 constexpr int kStreamStoreAux = 2 | 16;
 
-// Streaming store of one 2-, 4-, 8-, 16- or 32-byte value through a buffer
-// descriptor whose base is wave-uniform: the first active lane's address
-// less 2 GiB, so every lane of the wave within 2 GiB of that address
-// (all stores of these kernels: a wave writes consecutive sites) has a
-// 32-bit offset, whatever the field's size.
-template <class V>
-__device__ __forceinline__ void stream_store(V *p, V v)
+// A wave-uniform buffer base for streaming stores: the first active lane's
+// address less 2 GiB, and this lane's 32-bit offset from it.  Every lane of
+// the wave within 2 GiB of that address (all stores of these kernels: a
+// wave writes consecutive sites) gets a valid offset, whatever the field's
+// size; a uniform displacement (another entry plane) moves the base only.
+struct StreamBase {
+    uint64_t base;  // wave-uniform
+    uint32_t off;   // per lane
+};
+
+__device__ __forceinline__ StreamBase stream_base(const void *p)
 {
-    typedef unsigned U2 __attribute__((ext_vector_type(2)));
-    typedef unsigned U4 __attribute__((ext_vector_type(4)));
-    typedef unsigned U8 __attribute__((ext_vector_type(8)));
     const uint64_t a = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
     const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
     const uint64_t base = ((uint64_t(hi) << 32) | lo) - (uint64_t(1) << 31);
-    const uint32_t off = uint32_t(a - base);
+    return {base, uint32_t(a - base)};
+}
+
+// Streaming store of one 2-, 4-, 8-, 16- or 32-byte value at b.base +
+// delta + b.off (delta wave-uniform).
+template <class V>
+__device__ __forceinline__ void stream_store_at(const StreamBase &b, uint64_t delta, V v)
+{
+    typedef unsigned U2 __attribute__((ext_vector_type(2)));
+    typedef unsigned U4 __attribute__((ext_vector_type(4)));
+    typedef unsigned U8 __attribute__((ext_vector_type(8)));
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-        reinterpret_cast<void *>(base), (short)0, -1, kBufWord3);
+        reinterpret_cast<void *>(b.base + delta), (short)0, -1, kBufWord3);
+    const uint32_t off = b.off;
     if constexpr (sizeof(V) == 32) {
         const U8 w = __builtin_bit_cast(U8, v);
         __builtin_amdgcn_raw_buffer_store_b128(w.lo, r, off, 0, kStreamStoreAux);
@@ -122,6 +134,13 @@ __device__ __forceinline__ void stream_store(V *p, V v)
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r,
                                               off, 0, kStreamStoreAux);
     }
+}
+
+// Streaming store of one value at p (its own wave-uniform base).
+template <class V>
+__device__ __forceinline__ void stream_store(V *p, V v)
+{
+    stream_store_at(stream_base(p), 0, v);
 }
 
 template <int NT, class V>
@@ -305,6 +324,15 @@ __device__ __forceinline__ void store_entries(typename PrecT<P>::R *base,
     using R = typename PrecT<P>::R;
     using V = RawVec<P, S>;
     using V2 = typename VecOf<R, 2>::type;
+    if constexpr (FULL && (NT & 6) == 6) {
+        // streaming stores: one wave-uniform base for every entry, each
+        // entry plane a uniform displacement of it
+        const StreamBase b = stream_base(base + off + E0 * plane);
+#pragma unroll
+        for (int t = 0; t < NE; ++t)
+            stream_store_at(b, uint64_t(t) * plane * sizeof(R), raw[t]);
+        return;
+    }
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
         R *p = base + off + (E0 + t) * plane;
