@@ -672,18 +672,26 @@ def section_batch(ctx):
     # the best persistent grid (and the best one-shot grid when the tuned
     # launch is persistent), from the tuned setting's other knobs
     alt = []
-    for pers in ((1, 2, 4, 8) if bcfg.persistent == 0 else (0,)):
-        for tile in (512, 2048, 8192):
+    if bcfg.persistent == 0:
+        # persistent grids drawing tiles from the ticket counter: blocks of
+        # 64-256 lanes, 4-16 waves per compute unit, tiles of 256-8192 sites
+        shapes = [(64, 4), (64, 8), (64, 16), (128, 2), (128, 4), (128, 8),
+                  (256, 1), (256, 2), (256, 4)]
+        tiles = (256, 512, 2048, 8192)
+    else:
+        shapes, tiles = [(bcfg.block, 0)], (bcfg.tile_sites,)
+    for block, pers in shapes:
+        for tile in tiles:
             c = su3.su3_launch(**bcfg.as_dict())
-            c.persistent, c.tile_sites = pers, tile
-            if pers and c.block < 256:
-                c.block = 256
-            alt.append((replay(c), pers, tile))
-    ms_a, pers_a, tile_a = min(alt)
+            c.block, c.persistent, c.tile_sites, c.occupancy = block, pers, tile, 0
+            if pers:
+                c.nontemporal = 7
+            alt.append((replay(c), pers, tile, block))
+    ms_a, pers_a, tile_a, block_a = min(alt)
     a = entry(ms_a, total_bytes)
     pre = "oneshot" if bcfg.persistent else "persistent"
     out.update({f"{pre}_us": a["us"], f"{pre}_gbps": a["gbps"], f"{pre}_pct": a["pct"],
-                f"{pre}_k": pers_a, f"{pre}_tile": tile_a})
+                f"{pre}_k": pers_a, f"{pre}_tile": tile_a, f"{pre}_block": block_a})
     su3.su3_launch_set(key, kprec, klay, klanes, kdims, bcfg)
 
     # the same 64 products as 64 back-to-back launches (each shape's tuned
@@ -862,7 +870,9 @@ def run_variants(ctx, out):
         cases = [("apb_ab_real", "a+b+a*b", [R, R], rz, [ra, rb_], 3 * rb),
                  ("mul", "a*b", [M, M], zm, mats[:2], 54 * rb),
                  ("muladd", "a*b+c*d", [M, M, M, M], zm, mats, 90 * rb),
-                 ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb)]
+                 ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb),
+                 # eight matrix registers (in double: the spilling variant)
+                 ("deep", "(a*b)*(c*d)+a-d", [M, M, M, M], zm, mats, 90 * rb)]
         for name, text, kinds, z, ops, bps in cases:
             prog = su3.Program(text, kinds)
             ms, _ = timer.run(lambda: su3.su3_program_eval(prog, z, ops, stream), steps, 3)

@@ -48,6 +48,8 @@ enum { KIND_MATRIX = 0, KIND_SPINOR = 1, KIND_REAL = 2, KIND_COMPLEX = 3 };
 static const int kSpinorEntries = 12;
 
 struct su3_batch {
+    void *d_mem;       // one allocation: the ticket counter, then the items
+    unsigned long long *d_queue;  // persistent grids only, else nullptr
     BatchItem *d_items;
     int32_t nitems;
     int32_t ntiles;
@@ -1436,10 +1438,6 @@ extern "C" su3_status su3_program_eval(const su3_program *p, su3_field *z,
         return fail(SU3_ERR_UNSUPPORTED,
                     "a compressed output needs an SU(3)-valued expression "
                     "(products, adjoints, transposes, conjugates of matrices)");
-    if (arith == SU3_F64 && p->code.nregs > 4 && !p->code.scalar_only)
-        return fail(SU3_ERR_UNSUPPORTED,
-                    "the expression needs %d matrix registers; double "
-                    "precision evaluates with at most 4", p->code.nregs);
     return launch_program_op(p, z, ops, arith, static_cast<hipStream_t>(stream));
 }
 
@@ -1988,17 +1986,24 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
     b->mode = mode;
     b->cfg = cfg;
     b->device = dev;
-    // persistent k > 0: k workgroups per CU loop over the tiles; 0: one
-    // workgroup per tile
+    // persistent k > 0: k workgroups per CU draw the tiles from a ticket
+    // counter; 0: one workgroup per tile
     b->grid = cfg.persistent > 0
                   ? (int32_t)std::min<int64_t>(b->ntiles, (int64_t)cfg.persistent *
                                                               device_cus(dev))
                   : b->ntiles;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMalloc(&b->d_items, sizeof(BatchItem) * n);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * n,
-                           hipMemcpyHostToDevice, hs);
+    // the counter (16 bytes, zero) and the item table in one allocation
+    const size_t bytes = 16 + sizeof(BatchItem) * n;
+    std::vector<unsigned char> image(bytes, 0);
+    std::memcpy(image.data() + 16, items.data(), sizeof(BatchItem) * n);
+    hipError_t e = hipMalloc(&b->d_mem, bytes);
+    if (e == hipSuccess) {
+        b->d_queue = cfg.persistent > 0 ? static_cast<unsigned long long *>(b->d_mem)
+                                        : nullptr;
+        b->d_items = reinterpret_cast<BatchItem *>(static_cast<unsigned char *>(b->d_mem) + 16);
+        e = hipMemcpyAsync(b->d_mem, image.data(), bytes, hipMemcpyHostToDevice, hs);
+    }
     if (e == hipSuccess)
         e = hipStreamSynchronize(hs);
     // Capture the one launch on a private stream and instantiate the graph.
@@ -2011,7 +2016,7 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
         hipError_t le = launch_batch(b->mode, b->d_items, b->nitems, b->ntiles,
                                      T, cfg.nontemporal, cfg.schedule, cfg.block,
                                      b->grid, occupancy_reserve(dev, cfg.occupancy),
-                                     cap);
+                                     b->d_queue, cap);
         hipError_t ce = hipStreamEndCapture(cap, &b->graph);
         e = le != hipSuccess ? le : ce;
     }
@@ -2053,13 +2058,17 @@ extern "C" su3_status su3_batch_destroy(su3_batch *b)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
-    if (b->d_items)
-        (void)hipFree(b->d_items);
+    if (b->d_mem)
+        (void)hipFree(b->d_mem);
     delete b;
     return SU3_OK;
 }
 
-// Candidate launches of the batch autotuner.
+// Candidate launches of the batch autotuner: for each tile size, one-shot
+// grids (one workgroup per tile: blocks of 64 or 128, occupancy caps,
+// schedules, nontemporal or streaming stores) and persistent grids drawing
+// the tiles from the ticket counter (blocks of 64 or 256, 2-8 workgroups
+// per CU, streaming stores).
 static std::vector<su3_launch> batch_candidates()
 {
     std::vector<su3_launch> out;
@@ -2067,19 +2076,30 @@ static std::vector<su3_launch> batch_candidates()
     c.xcd_remap = 0;
     c.lds_stage = 0;
     c.sites_per_lane = 0;
-    for (int tile : {64, 128, 256, 512, 2048, 8192})
-        for (int bp : {0, 1, 2})  // block 64 / 128 one-shot, or 256 x 8 per CU
+    for (int tile : {64, 128, 256, 512, 2048, 8192}) {
+        c.tile_sites = tile;
+        c.persistent = 0;
+        for (int b : {64, 128})
             for (int occ : {0, 4, 6})
                 for (int sched : {0, 1})
                     for (int nt : {3, 7}) {
-                        c.tile_sites = tile;
-                        c.persistent = bp == 2 ? 8 : 0;
-                        c.block = bp == 0 ? 64 : (bp == 1 ? 128 : 256);
+                        c.block = b;
                         c.occupancy = occ;
                         c.schedule = sched;
                         c.nontemporal = nt;
                         out.push_back(c);
                     }
+        c.occupancy = 0;
+        c.nontemporal = 7;
+        for (int b : {64, 256})
+            for (int k : {2, 4, 8})
+                for (int sched : {0, 1}) {
+                    c.block = b;
+                    c.persistent = k;
+                    c.schedule = sched;
+                    out.push_back(c);
+                }
+    }
     return out;
 }
 

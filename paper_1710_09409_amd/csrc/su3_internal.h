@@ -110,13 +110,17 @@ hipError_t launch_site(int prec, int expr, int sites_per_lane, int nt,
 // AoS with LDS staging: one lane per site, `block` sites per workgroup.
 hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
                            const SiteArgs &a, hipStream_t stream);
-// Batched launch over `ntiles` tiles of `tile_sites` sites, `grid`
-// workgroups each taking tiles blockIdx.x, blockIdx.x + grid, ...
-// mode 0: every item is MUL in F64 or C12 (the mixed-precision streaming
-// workload, smallest register footprint); mode 1: any supported item.
+// Batched launch over `ntiles` tiles of `tile_sites` sites.  queue ==
+// nullptr: `grid` workgroups each taking tiles blockIdx.x, blockIdx.x +
+// grid, ... (one per tile when grid == ntiles); else a persistent grid
+// drawing tiles from the ticket counter *queue, which must start at 0 and
+// is left at a multiple of ntiles + grid by every launch.  mode 0: every
+// item is MUL in F64 or C12 (the mixed-precision streaming workload,
+// smallest register footprint); mode 1: any supported item.
 hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
                         int32_t ntiles, int32_t tile_sites, int nt, int sched,
-                        int block, int grid, size_t shm, hipStream_t stream);
+                        int block, int grid, size_t shm, unsigned long long *queue,
+                        hipStream_t stream);
 // mode 0: z(s) = y(s'); mode 1: z(s) = x(s) * y(s').  One site per lane.
 hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
                         int grid, size_t shm, const ShiftArgs &a,

@@ -61,48 +61,89 @@ __device__ __forceinline__ void tile_any_expr(const BatchItem &it, int first,
     }
 }
 
-// Batched kernel over the tile table.  Item i owns tiles tile_start_i ..
-// tile_start_{i+1} - 1, each of T sites (the item's last tile may be
-// shorter).  Workgroup b takes tiles b, b + G, b + 2G, ...; it finds a
-// tile's item by binary search over the items' tile starts -- a small
-// array every workgroup reads, so it stays in the scalar cache and no
-// per-tile record has to come from memory before the data loads start.
-// The branch on precision and expression is uniform across the workgroup.
-// Every workgroup leaves after its last tile.
+// One tile of the batch: find its item by binary search over the items'
+// tile starts -- a small array every workgroup reads, so it stays in the
+// scalar cache and no per-tile record has to come from memory before the
+// data loads start -- and evaluate it.  The branch on precision and
+// expression is uniform across the workgroup.
 template <int MODE, int NT, int SCHED>
-__global__ __launch_bounds__(256) void k_batch(const BatchItem *items,
-                                               int nitems, int ntiles, int T)
+__device__ __forceinline__ void batch_tile(const BatchItem *items, int nitems, int t,
+                                           int T)
 {
-    // dynamic LDS only caps the workgroups per CU; never read
-    extern __shared__ char occupancy_reserve[];
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int lo = 0, hi = nitems - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].tile_start <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const BatchItem &it = items[lo];
-        const int first = (t - it.tile_start) * T;
-        const int count = min(T, it.nsites - first);
-        if constexpr (MODE == 0) {
-            if (it.prec == su3i::F64)
-                tile_run<su3i::F64, su3i::MUL, NT, SCHED>(it, first, count);
-            else
-                tile_run<su3i::C12, su3i::MUL, NT, SCHED>(it, first, count);
-        } else {
-            switch (it.prec) {
-            case su3i::F64: tile_any_expr<su3i::F64, NT, SCHED>(it, first, count); break;
-            case su3i::F32: tile_any_expr<su3i::F32, NT, SCHED>(it, first, count); break;
-            case su3i::F16: tile_any_expr<su3i::F16, NT, SCHED>(it, first, count); break;
-            case su3i::C12: tile_any_expr<su3i::C12, NT, SCHED>(it, first, count); break;
-            }
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_start <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchItem &it = items[lo];
+    const int first = (t - it.tile_start) * T;
+    const int count = min(T, it.nsites - first);
+    if constexpr (MODE == 0) {
+        if (it.prec == su3i::F64)
+            tile_run<su3i::F64, su3i::MUL, NT, SCHED>(it, first, count);
+        else
+            tile_run<su3i::C12, su3i::MUL, NT, SCHED>(it, first, count);
+    } else {
+        switch (it.prec) {
+        case su3i::F64: tile_any_expr<su3i::F64, NT, SCHED>(it, first, count); break;
+        case su3i::F32: tile_any_expr<su3i::F32, NT, SCHED>(it, first, count); break;
+        case su3i::F16: tile_any_expr<su3i::F16, NT, SCHED>(it, first, count); break;
+        case su3i::C12: tile_any_expr<su3i::C12, NT, SCHED>(it, first, count); break;
         }
     }
-    if (ntiles < 0)
-        occupancy_reserve[threadIdx.x] = 0;
+}
+
+// Batched kernel over the tile table.  Item i owns tiles tile_start_i ..
+// tile_start_{i+1} - 1, each of T sites (the item's last tile may be
+// shorter).
+//   queue == nullptr: one workgroup per tile (a one-shot grid; workgroup b
+//     takes tiles b, b + G, ... when the grid is smaller).
+//   queue != nullptr: a persistent grid whose workgroups take tiles from a
+//     ticket counter in queue[0], in order, until the tiles run out: lane 0
+//     draws ticket v and the workgroup takes tile v mod (ntiles + G); a
+//     value >= ntiles means no tile is left and the workgroup leaves.  Every
+//     workgroup draws once more after its last tile, so a launch draws
+//     exactly ntiles + G tickets and leaves the counter at the next
+//     multiple of it: the queue never needs resetting between launches of
+//     the same batch (it starts at 0).  The next ticket is drawn while the
+//     current tile is evaluated, so its latency is hidden.  The ticket goes
+//     from lane 0 to the workgroup through the first bytes of the dynamic
+//     LDS (the host reserves at least 16).
+template <int MODE, int NT, int SCHED>
+__global__ __launch_bounds__(256) void k_batch(const BatchItem *items, int nitems,
+                                               int ntiles, int T,
+                                               unsigned long long *queue)
+{
+    // dynamic LDS: the ticket of the queued form, and the reserve that
+    // caps the workgroups per CU (otherwise never read)
+    extern __shared__ char occupancy_reserve[];
+    if (!queue) {
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
+            batch_tile<MODE, NT, SCHED>(items, nitems, t, T);
+        if (ntiles < 0)
+            occupancy_reserve[threadIdx.x] = 0;
+        return;
+    }
+    volatile int *ticket = reinterpret_cast<volatile int *>(occupancy_reserve);
+    const unsigned long long m = (unsigned long long)ntiles + gridDim.x;
+    unsigned long long next = 0;
+    if (threadIdx.x == 0)
+        next = atomicAdd(queue, 1ull);
+    for (;;) {
+        if (threadIdx.x == 0)
+            *ticket = (int)(next % m);
+        __syncthreads();
+        const int t = *ticket;
+        __syncthreads();
+        if (t >= ntiles)
+            break;
+        if (threadIdx.x == 0)
+            next = atomicAdd(queue, 1ull);
+        batch_tile<MODE, NT, SCHED>(items, nitems, t, T);
+    }
 }
 
 // Bandwidth yardsticks, one 16-byte element per lane, one-shot grid:
@@ -191,24 +232,28 @@ hipError_t launch_site_lds(int prec, int expr, int nt, int block, int grid,
 }
 
 template <int MODE, int NT, int SCHED>
-static void batch_go(const BatchItem *items, int32_t nitems, int32_t ntiles,
-                     int32_t T, int block, int grid, size_t shm, hipStream_t st)
+static void batch_go(const BatchItem *items, int32_t nitems, int32_t ntiles, int32_t T,
+                     unsigned long long *queue, int block, int grid, size_t shm,
+                     hipStream_t st)
 {
-    hipLaunchKernelGGL((su3k::k_batch<MODE, NT, SCHED>), dim3(grid), dim3(block),
-                       shm, st, items, nitems, ntiles, T);
+    hipLaunchKernelGGL((su3k::k_batch<MODE, NT, SCHED>), dim3(grid), dim3(block), shm, st,
+                       items, nitems, ntiles, T, queue);
 }
 
 hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
                         int32_t ntiles, int32_t tile_sites, int nt, int sched,
-                        int block, int grid, size_t shm, hipStream_t st)
+                        int block, int grid, size_t shm, unsigned long long *queue,
+                        hipStream_t st)
 {
     if (block > 256)
         return hipErrorInvalidValue;
+    if (queue && shm < 16)
+        shm = 16;  // the ticket
     // nontemporal settings compiled: 0, 3 and 7 (others run as 0 or 3)
     const int ntv = nt == 7 ? 2 : ((nt & 3) == 3 ? 1 : 0);
     const int v = (mode ? 6 : 0) + 2 * ntv + (sched ? 1 : 0);
 #define SU3_BATCH(M, N, S) \
-    batch_go<M, N, S>(items, nitems, ntiles, tile_sites, block, grid, shm, st)
+    batch_go<M, N, S>(items, nitems, ntiles, tile_sites, queue, block, grid, shm, st)
     switch (v) {
     case 0: SU3_BATCH(0, 0, 0); break;
     case 1: SU3_BATCH(0, 0, 1); break;

@@ -816,9 +816,10 @@ static hipError_t go_t(int form, int nregs, int nt, int block, int grid,
         return go<T, 9, 2>(nt, block, grid, shm, a, st);
     if (nregs <= 4)
         return go<T, 9, 4>(nt, block, grid, shm, a, st);
-    if constexpr (sizeof(T) == 4)
-        return go<T, 9, 8>(nt, block, grid, shm, a, st);
-    return hipErrorInvalidValue;  // four double matrices fill the register file
+    // eight registers: in double the matrices fill the VGPRs and AGPRs of
+    // one wave per SIMD and spill about 140 bytes per lane to scratch --
+    // slow, but any expression of the grammar evaluates
+    return go<T, 9, 8>(nt, block, grid, shm, a, st);
 }
 
 }  // namespace prog

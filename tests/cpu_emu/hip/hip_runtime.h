@@ -46,6 +46,10 @@ inline void __builtin_amdgcn_sched_barrier(int) {}
 struct emu_buffer_rsrc { char *base; uint32_t records; };
 typedef emu_buffer_rsrc __amdgpu_buffer_rsrc_t;
 inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return v; }
+inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v)
+{
+    return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
 inline emu_buffer_rsrc __builtin_amdgcn_make_buffer_rsrc(void *p, short, int records, int)
 {
     return {static_cast<char *>(p), static_cast<uint32_t>(records)};

@@ -92,11 +92,6 @@ def test_program_parity(arith, lay):
         z = make(DIMS, zprec, rk, lay, None, s)
         q = [quantise(h, k, p) for h, k, p in zip(hosts, kinds, precs)]
         want = O.get().eval_expr(text, q, [int(k) for k in kinds], V=V)
-        if arith == 0 and info["n_regs"] > 4 and M in kinds:
-            with pytest.raises(su3.Su3Error) as e:
-                su3.su3_program_eval(prog, z, fs, s)
-            assert e.value.status == su3.SU3_ERR_UNSUPPORTED
-            continue
         su3.su3_program_eval(prog, z, fs, s)
         su3.su3_sync(s)
         got = su3.su3_field_download(z, s)
