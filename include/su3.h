@@ -454,6 +454,25 @@ su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
                             su3_field *const *z, const su3_field *const *ops,
                             int32_t n, void *stream);
 
+/* Evaluate the items of a batch once, in one launch, allocating no device
+ * memory -- for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The items, their
+ * rules and the results are those of su3_batch_create + su3_batch_launch;
+ * the launch is the tuned (or set) setting of the batch key
+ * (SU3_EXPR_BATCH + exprs[0], leading item's precision, layout and lanes,
+ * total volume).  The item table (and a persistent grid's ticket counter)
+ * go into a fixed scratch array that each device holds for the life of
+ * the process, about 72 KiB for at most 1024 items (SU3_ERR_INVALID_ARG
+ * beyond); small kernels on `stream` write it from their arguments, with
+ * no copy from host memory, so the call can be captured into a graph.
+ * Every call on a device shares that device's array and leaves its last
+ * contents there: calls that overlap on one device (different streams, or
+ * threads issuing to one stream unordered) race and give wrong results --
+ * the caller orders them.  The fields must be on the current device
+ * (SU3_ERR_MISMATCH).  Asynchronous on `stream`. */
+su3_status su3_batch_run(const su3_expr *exprs, su3_field *const *z,
+                         const su3_field *const *ops, int32_t n, void *stream);
+
 /* Replay the batch's graph on `stream` (asynchronous). */
 su3_status su3_batch_launch(su3_batch *b, void *stream);
 

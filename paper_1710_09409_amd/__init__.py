@@ -53,7 +53,7 @@ SYMBOLS = (
     "su3_scalar_bytes", "su3_scalar_alloc", "su3_scalar_wrap",
     "su3_program_create", "su3_program_info", "su3_program_eval",
     "su3_program_destroy", "su3_vnode_wrap",
-    "su3_batch_create", "su3_batch_launch", "su3_batch_destroy",
+    "su3_batch_create", "su3_batch_run", "su3_batch_launch", "su3_batch_destroy",
     "su3_batch_tiles", "su3_autotune", "su3_layout_recommend", "su3_batch_autotune",
     "su3_launch_get",
     "su3_launch_set",
@@ -142,6 +142,7 @@ def load():
         "su3_vnode_alloc": [pp, dims_t, i32, i32, dims_t],
         "su3_vnode_wrap": [pp, vp, sz, dims_t, i32, i32, dims_t],
         "su3_batch_create": [pp, vp, vp, vp, i32, vp],
+        "su3_batch_run": [vp, vp, vp, i32, vp],
         "su3_batch_launch": [vp, vp],
         "su3_batch_destroy": [vp],
         "su3_batch_tiles": [vp, vp, i64, ctypes.POINTER(i64)],
@@ -567,6 +568,12 @@ def su3_batch_autotune(exprs, zs, ops, stream=None):
     _check("su3_batch_autotune",
            load().su3_batch_autotune(ex, zz, oo, n, _stream(stream), ctypes.byref(best)))
     return best
+
+
+def su3_batch_run(exprs, zs, ops, stream=None):
+    """The batch's items evaluated once, with no device allocation."""
+    n, ex, zz, oo = _batch_args(exprs, zs, ops)
+    _check("su3_batch_run", load().su3_batch_run(ex, zz, oo, n, _stream(stream)))
 
 
 def su3_batch_launch(b: Batch, stream=None):

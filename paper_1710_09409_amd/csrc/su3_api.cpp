@@ -1916,15 +1916,29 @@ extern "C" su3_status su3_layout_recommend(su3_expr expr, su3_precision prec,
 
 // ------------------------------------------------------------ batches
 
-static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
-                               su3_field *const *z, const su3_field *const *ops,
-                               int32_t n, void *stream, const su3_launch *forced)
+// The items of a batch as the kernel reads them, validated (each item by
+// su3_fused_eval's rules; batch-level rules here), with the tile table
+// of the launch `cfg`: forced (the autotuner), else the tuned (or default)
+// setting of the batch key (SU3_EXPR_BATCH + leading expression, leading
+// item's precision, layout, lanes) at the total volume.
+struct BatchPlan {
+    std::vector<BatchItem> items;
+    int mode;
+    int device;
+    int64_t ntiles;
+    su3_launch cfg;
+};
+
+static su3_status plan_batch(const su3_expr *exprs, su3_field *const *z,
+                             const su3_field *const *ops, int32_t n,
+                             const su3_launch *forced, BatchPlan *plan)
 {
-    if (!out || !exprs || !z || !ops)
+    if (!exprs || !z || !ops)
         return fail(SU3_ERR_INVALID_ARG, "NULL argument");
     if (n <= 0)
         return fail(SU3_ERR_INVALID_ARG, "batch needs at least one item");
-    std::vector<BatchItem> items(n);
+    std::vector<BatchItem> &items = plan->items;
+    items.assign(n, BatchItem());
     int mode = 0;
     int64_t total_sites = 0;
     int dev = -1;
@@ -1963,8 +1977,6 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
             mode = 1;
         total_sites += z[i]->V;
     }
-    // launch: forced by the autotuner, else the tuned (or default) setting
-    // of the leading item's key at the batch's total volume
     const su3_launch cfg =
         forced ? *forced
                : lookup_launch(SU3_EXPR_BATCH + exprs[0], z[0]->prec,
@@ -1979,6 +1991,38 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
         if (ntiles >= ((int64_t)1 << 31))
             return fail(SU3_ERR_INVALID_ARG, "too many tiles");
     }
+    plan->mode = mode;
+    plan->device = dev;
+    plan->ntiles = ntiles;
+    plan->cfg = cfg;
+    return SU3_OK;
+}
+
+// Workgroups of a batch launch: k per CU for a persistent grid (at most one
+// per tile), else one per tile.
+static int32_t batch_grid(const BatchPlan &p)
+{
+    return p.cfg.persistent > 0
+               ? (int32_t)std::min<int64_t>(p.ntiles, (int64_t)p.cfg.persistent *
+                                                          device_cus(p.device))
+               : (int32_t)p.ntiles;
+}
+
+static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
+                               su3_field *const *z, const su3_field *const *ops,
+                               int32_t n, void *stream, const su3_launch *forced)
+{
+    if (!out)
+        return fail(SU3_ERR_INVALID_ARG, "NULL argument");
+    BatchPlan plan;
+    su3_status pst = plan_batch(exprs, z, ops, n, forced, &plan);
+    if (pst != SU3_OK)
+        return pst;
+    const std::vector<BatchItem> &items = plan.items;
+    const int mode = plan.mode, dev = plan.device;
+    const int64_t ntiles = plan.ntiles;
+    const su3_launch cfg = plan.cfg;
+    const int T = cfg.tile_sites;
     su3_batch *b = new su3_batch();
     std::memset(b, 0, sizeof *b);
     b->nitems = n;
@@ -1988,10 +2032,7 @@ static su3_status batch_create(su3_batch **out, const su3_expr *exprs,
     b->device = dev;
     // persistent k > 0: k workgroups per CU draw the tiles from a ticket
     // counter; 0: one workgroup per tile
-    b->grid = cfg.persistent > 0
-                  ? (int32_t)std::min<int64_t>(b->ntiles, (int64_t)cfg.persistent *
-                                                              device_cus(dev))
-                  : b->ntiles;
+    b->grid = batch_grid(plan);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     // the counter (16 bytes, zero) and the item table in one allocation
     const size_t bytes = 16 + sizeof(BatchItem) * n;
@@ -2039,6 +2080,77 @@ extern "C" su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
                                        void *stream)
 {
     return batch_create(out, exprs, z, ops, n, stream, nullptr);
+}
+
+// ------------------------------------------- allocation-free batches
+
+// Scratch of su3_batch_run: the persistent grid's ticket counter (bytes
+// 0..15) and up to kRunMaxItems item records (from byte 256).  A
+// file-scope device array: every device the library runs on holds one
+// copy for the life of the process, at its own address, which host code
+// reaches only through run_scratch() (the array's name is a host-side
+// stand-in, not a device address).
+static const int kRunMaxItems = 1024;
+static const size_t kRunScratchBytes = 256 + sizeof(BatchItem) * kRunMaxItems;
+static __device__ __align__(256) unsigned char scratch[kRunScratchBytes];
+
+// Device address of `scratch` on device `dev` (the current device),
+// looked up once per device.
+static su3_status run_scratch(int dev, unsigned char **out)
+{
+    static std::mutex mu;
+    static unsigned char *ptrs[64];
+    if (dev < 0 || dev >= 64)
+        return fail(SU3_ERR_UNSUPPORTED, "device %d beyond the 64 the library serves", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return fail(SU3_ERR_HIP, "no device address for the batch scratch");
+        ptrs[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = ptrs[dev];
+    return SU3_OK;
+}
+
+extern "C" su3_status su3_batch_run(const su3_expr *exprs, su3_field *const *z,
+                                    const su3_field *const *ops, int32_t n,
+                                    void *stream)
+{
+    if (n > kRunMaxItems)
+        return fail(SU3_ERR_INVALID_ARG,
+                    "su3_batch_run takes at most %d items (got %d); "
+                    "su3_batch_create takes any number", kRunMaxItems, n);
+    BatchPlan plan;
+    su3_status st = plan_batch(exprs, z, ops, n, nullptr, &plan);
+    if (st != SU3_OK)
+        return st;
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != plan.device)
+        return fail(SU3_ERR_MISMATCH,
+                    "the batch's fields are on device %d, the current device is %d",
+                    plan.device, cur);
+    unsigned char *sp = nullptr;
+    st = run_scratch(plan.device, &sp);
+    if (st != SU3_OK)
+        return st;
+    unsigned long long *queue =
+        plan.cfg.persistent > 0 ? reinterpret_cast<unsigned long long *>(sp) : nullptr;
+    BatchItem *items = reinterpret_cast<BatchItem *>(sp + 256);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_put_items(items, plan.items.data(), n, queue, hs);
+    if (e == hipSuccess)
+        e = launch_batch(plan.mode, items, n, (int32_t)plan.ntiles,
+                         plan.cfg.tile_sites, plan.cfg.nontemporal, plan.cfg.schedule,
+                         plan.cfg.block, batch_grid(plan),
+                         occupancy_reserve(plan.device, plan.cfg.occupancy), queue, hs);
+    if (e != hipSuccess)
+        return hip_fail(e, "batch run launch");
+    return SU3_OK;
 }
 
 extern "C" su3_status su3_batch_launch(su3_batch *b, void *stream)

@@ -125,6 +125,17 @@ hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
 hipError_t launch_shift(int prec, int mode, int nt, int sched, int block,
                         int grid, size_t shm, const ShiftArgs &a,
                         hipStream_t stream);
+// Item records passed by value to the kernel that writes a batch's table
+// (kItemChunk per launch, well inside the kernel-argument space).
+constexpr int kItemChunk = 24;
+struct ItemChunk {
+    BatchItem it[kItemChunk];
+};
+// Write items[0 .. n-1] to dst on `stream` with kernels (ceil(n /
+// kItemChunk) launches, no host-to-device copy); queue != nullptr: also
+// zero the ticket counter *queue.
+hipError_t launch_put_items(BatchItem *dst, const BatchItem *items, int n,
+                            unsigned long long *queue, hipStream_t stream);
 // Bandwidth yardsticks over n16 16-byte elements per array (kinds below);
 // `tail` adds the triad's trailing double; nt in {0, 1, 2, 3, 6, 7};
 // block a multiple of 64 up to 1024; `shm` as for launch_site.

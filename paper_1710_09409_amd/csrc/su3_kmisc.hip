@@ -146,6 +146,19 @@ __global__ __launch_bounds__(256) void k_batch(const BatchItem *items, int nitem
     }
 }
 
+// Item records of a batch written from kernel arguments (the allocation-
+// free batch: no copy from host memory, so the write can sit in a captured
+// graph); with `queue`, also zero the persistent grid's ticket counter.
+__global__ __launch_bounds__(64) void k_put_items(BatchItem *dst, su3i::ItemChunk c,
+                                                  int count, unsigned long long *queue)
+{
+    const int i = threadIdx.x;
+    if (i < count)
+        dst[i] = c.it[i];
+    if (queue && i == 0)
+        *queue = 0ull;
+}
+
 // Bandwidth yardsticks, one 16-byte element per lane, one-shot grid:
 // triad a = b + s*c (doubles), read-only (b and c), write-only (a = s),
 // copy (a = b).  The read-only kind writes a[0] only if an element of
@@ -270,6 +283,23 @@ hipError_t launch_batch(int mode, const BatchItem *items, int32_t nitems,
     }
 #undef SU3_BATCH
     return hipGetLastError();
+}
+
+hipError_t launch_put_items(BatchItem *dst, const BatchItem *items, int n,
+                            unsigned long long *queue, hipStream_t st)
+{
+    for (int first = 0; first < n; first += kItemChunk) {
+        ItemChunk c;
+        const int count = n - first < kItemChunk ? n - first : kItemChunk;
+        for (int i = 0; i < count; ++i)
+            c.it[i] = items[first + i];
+        hipLaunchKernelGGL(su3k::k_put_items, dim3(1), dim3(64), 0, st, dst + first, c,
+                           count, first == 0 ? queue : nullptr);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 template <int KIND, int NT>

@@ -181,6 +181,25 @@ int main(int argc, char **argv)
                 fails += bad;
             }
             emu_threaded = false;
+            // the allocation-free form on the same items (the whole batch,
+            // then its first items only), into zeroed outputs
+            for (int m : {n, (n + 1) / 2}) {
+                su3_launch_set((su3_expr)(SU3_EXPR_BATCH + ex[0]), (su3_precision)items[0].prec, (su3_layout)items[0].lay, items[0].lanes, td, &c);
+                for (int i = 0; i < m; ++i) { void *p; size_t nb; su3_field_data(zs[i], &p, &nb); memset(p, 0, nb); }
+                emu_threaded = true;
+                if (su3_batch_run(ex.data(), zs.data(), ops.data(), m, nullptr) != SU3_OK) { printf("batch run %s\n", su3_last_error()); fails++; }
+                emu_threaded = false;
+                su3_launch_reset();
+                int bad = 0;
+                for (int i = 0; i < m; ++i) {
+                    void *p1, *p2; size_t n1, n2;
+                    su3_field_data(zs[i], &p1, &n1);
+                    su3_field_data(ref[i], &p2, &n2);
+                    if (memcmp(p1, p2, n1) != 0) bad++;
+                }
+                printf("batch run mode %d T %d items %d mismatching %d\n", mode, T, m, bad);
+                fails += bad;
+            }
             su3_batch_destroy(b);
             for (auto *f : zs) su3_field_free(f);
             for (auto *f : ref) su3_field_free(f);

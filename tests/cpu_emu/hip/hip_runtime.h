@@ -23,6 +23,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__
+#define __align__(n) __attribute__((aligned(n)))
 
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
@@ -133,6 +134,8 @@ inline void emu_launch(K k, dim3 g, dim3 b, size_t shm, A... a)
 }
 #define hipLaunchKernelGGL(K, G, B, SHM, ST, ...) emu_launch(K, G, B, SHM, __VA_ARGS__)
 
+#define HIP_SYMBOL(x) (reinterpret_cast<const void *>(&(x)))
+inline hipError_t hipGetSymbolAddress(void **p, const void *symbol) { *p = const_cast<void *>(symbol); return hipSuccess; }
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline const char *hipGetErrorString(hipError_t e) { return e ? "emu error" : "success"; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
