@@ -185,8 +185,12 @@ typedef struct su3_program su3_program;
  *               rows, tx x 2 x 2, tx x 2 x 4, tx x 4 x 2, tx x 4 x 4,
  *               where tx is the lattice's x extent (every x hop then
  *               comes from LDS); 13..16 the same with two slice buffers;
- *               17 and 18 take tx x 3 x 3 with one and two buffers.
- *               B is ignored: one lane per
+ *               17 and 18 take tx x 3 x 3 with one and two buffers;
+ *               19..28 are the shapes of 9..18 with a halo: the tile's y
+ *               and z face sites of each slice are loaded, spin
+ *               projected, into LDS in the step before the slice
+ *               (lexicographic fields; too large: one buffer, else no
+ *               halo).  B is ignored: one lane per
  *               tile site, at most 512 for double spinors and 1024 for
  *               single, buffers in 160 KiB (else the rows with one
  *               buffer, rows of 2 x 2, or 16x4x4).  On virtual-node fields

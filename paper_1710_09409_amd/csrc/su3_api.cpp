@@ -755,9 +755,9 @@ static su3_status check_launch(const su3_launch &c, int layout, int expr)
                     c.occupancy);
     if (expr == SU3_EXPR_DSLASH) {
         LdsShape sh;
-        if (c.schedule < 0 || c.schedule > 18)
+        if (c.schedule < 0 || c.schedule > 28)
             return fail(SU3_ERR_INVALID_ARG,
-                        "Dslash schedule (site tile) must be in [0, 18]");
+                        "Dslash schedule (site tile) must be in [0, 28]");
         if (lds_walk && c.schedule <= 8 && !lds_shape(c.schedule, c.block, 8, 0, 1, sh))
             return fail(SU3_ERR_INVALID_ARG,
                         "the LDS-tiled Dslash (schedule %d) has no tile for "
@@ -1129,6 +1129,15 @@ static su3_status launch_dslash_op(su3_field *out, su3_field *const links[4],
     // LDS-tiled walks: schedules 4.. on lexicographic fields, the row tiles
     // (9..18) on virtual-node fields
     bool lds = c.schedule >= (vn ? 9 : 4);
+    if (lds && c.schedule >= 19 && !lds_shape(c.schedule, c.block, cbytes, lx, nsub, sh)) {
+        // a halo walk that does not fit: its rows with one buffer and a
+        // halo, else the same rows without a halo (and their fallbacks)
+        const int rows = c.schedule - 10;
+        const int one_buffer = rows == 18 ? 17 : rows >= 13 && rows <= 16 ? rows - 4 : 0;
+        c.schedule = one_buffer && lds_shape(one_buffer + 10, 0, cbytes, lx, nsub, sh)
+                         ? one_buffer + 10
+                         : rows;
+    }
     if (lds && !lds_shape(c.schedule, c.block, cbytes, lx, nsub, sh)) {
         // buffers too large: the same rows with one buffer, else rows of
         // 2 x 2; a fixed tile too large for double spinors: the schedule's
@@ -1653,8 +1662,8 @@ static std::vector<su3_launch> dslash_candidates(int cbytes, int lx, int nsub)
                         out.push_back(c);
                     }
     // LDS-tiled walks: every tile shape that fits this spinor precision and
-    // lattice (cached loads; nontemporal stores)
-    for (int sched = 4; sched <= 18; ++sched)
+    // lattice (cached loads; nontemporal stores), with and without a halo
+    for (int sched = 4; sched <= 28; ++sched)
         for (int b : {128, 256, 512}) {
             LdsShape sh;
             if (!lds_shape(sched, b, cbytes, lx, nsub, sh) || (sched >= 9 && b != 256))

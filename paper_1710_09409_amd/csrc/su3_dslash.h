@@ -36,7 +36,7 @@ struct DslashArgs {
     // direction; tile[0] == 0 takes sites in index order
     uint32_t tile[4];
     uint32_t ntile[4];
-    // LDS-tiled walk: the schedule (4..16) whose tile each workgroup holds
+    // LDS-tiled walk: the schedule (4..28) whose tile each workgroup holds
     // (lds_shape), walking `walk` t-slices; ntile[0..2] tiles per
     // direction.  0: no LDS tile
     uint32_t lds_tile;
@@ -46,9 +46,25 @@ struct DslashArgs {
 // Tile of the LDS-tiled walk: tx x ty x tz (x, y, z) sites -- outer sites
 // with all their nsub virtual nodes in the virtual-node layout -- one lane
 // per site, and nb slice buffers in LDS (2: one barrier per slice, 1: two).
+// halo: each buffer also holds the slice's y and z face sites, spin
+// projected for the hop that reads them (6 complex numbers each).
 struct LdsShape {
     int tx, ty, tz, nb, nsub;
+    int halo;
 };
+
+// Face sites of a row tile's halo: the rows just below and just above the
+// tile in y (tx * tz sites each) and in z (tx * ty each).
+inline long halo_faces(const LdsShape &s)
+{
+    return s.halo ? 2L * s.tx * (s.ty + s.tz) : 0L;
+}
+
+inline size_t lds_shape_bytes(const LdsShape &s, int cbytes)
+{
+    return (size_t)s.nb *
+           ((size_t)12 * s.nsub * s.tx * s.ty * s.tz + (size_t)6 * halo_faces(s)) * cbytes;
+}
 
 // Tile by schedule and block B:
 //   4: 8 x 8 x B/64, two buffers     5: 8 x 8 x B/64, one buffer
@@ -64,7 +80,10 @@ struct LdsShape {
 // ignored: tx is the lattice's (outer) x extent lx when nsub * lx * ty * tz
 // lanes fit a workgroup (rows_max_lanes), else (virtual-node fields only)
 // the largest divisor of lx that does, and the buffers must fit the 160 KiB
-// of LDS of a compute unit.
+// of LDS of a compute unit.  19..28: the shapes of 9..18 on lexicographic
+// fields with a halo (the tile's y and z face sites of each slice, loaded
+// and spin projected in the step before the slice, next to the interior
+// loads of the tiles that own them).
 // Most lanes of a row-tile workgroup: 512 for double spinors and for
 // virtual-node fields (whose kernels need more registers), else 1024.
 inline int rows_max_lanes(int cbytes, int nsub)
@@ -76,21 +95,27 @@ inline bool lds_shape(int schedule, int block, int cbytes, int lx, int nsub, Lds
 {
     if (nsub < 1)
         return false;
+    const int halo = schedule >= 19 && schedule <= 28;
+    if (halo) {
+        if (nsub != 1)
+            return false;
+        schedule -= 10;
+    }
     if (schedule >= 9 && schedule <= 18) {
         static const int rows[4][2] = {{2, 2}, {2, 4}, {4, 2}, {4, 4}};
         const int r = (schedule - 9) % 4;
         const long maxl = rows_max_lanes(cbytes, nsub);
         if (schedule >= 17) {
-            s = {lx, 3, 3, schedule == 18 ? 2 : 1, nsub};
+            s = {lx, 3, 3, schedule == 18 ? 2 : 1, nsub, halo};
         } else {
-            s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1, nsub};
+            s = {lx, rows[r][0], rows[r][1], schedule >= 13 ? 2 : 1, nsub, halo};
         }
         const long per_x = (long)nsub * s.ty * s.tz;  // lanes per unit of tx
         if (lx < 1 || per_x > maxl || (nsub == 1 && per_x * lx > maxl))
             return false;
         while (per_x * s.tx > maxl || lx % s.tx != 0)
             --s.tx;
-        return s.nb * per_x * s.tx * 12 * cbytes <= 160 * 1024;
+        return lds_shape_bytes(s, cbytes) <= 160 * 1024;
     }
     if (nsub != 1 || (block != 128 && block != 256 && block != 512))
         return false;
@@ -115,11 +140,6 @@ inline bool lds_shape(int schedule, int block, int cbytes, int lx, int nsub, Lds
     default: return false;
     }
     return (long)s.nb * 12 * block * cbytes <= 48 * 1024;
-}
-
-inline size_t lds_shape_bytes(const LdsShape &s, int cbytes)
-{
-    return (size_t)s.nb * 12 * s.nsub * s.tx * s.ty * s.tz * cbytes;
 }
 
 // Wilson hopping term: spinor precision F64 with F64 links, F32 with F32

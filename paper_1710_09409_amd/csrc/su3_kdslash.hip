@@ -452,6 +452,142 @@ __device__ __forceinline__ void hop_bwd_tile(const su3i::DslashArgs &a, uint32_t
     reconstruct<MU, +1>(w, acc);
 }
 
+// Halo walks (row tiles on lexicographic fields): the y and z neighbours
+// across the tile's faces are taken from the halo, where each face site
+// waits already projected for the hop that reads it.  Face f of a halo
+// buffer of nf sites holds its 6 complex numbers at f, f + nf, ...
+template <int MU, int SP, int LP, int NT>
+__device__ __forceinline__ void hop_fwd_halo(const su3i::DslashArgs &a, uint32_t s,
+                                             bool in_tile, int lf,
+                                             const Cx<typename PrecT<SP>::T> *tile, int ns,
+                                             const Cx<typename PrecT<SP>::T> *halo, int nf,
+                                             int face, Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    using T = typename PrecT<SP>::T;
+    Cx<T> m[9], h[2][3], w[2][3];
+    if (in_tile) {
+        Cx<T> p[4][3];
+        const Cx<T> *q = tile + pin((uint32_t)lf);
+#pragma unroll
+        for (int e = 0; e < 12; ++e)
+            p[e / 3][e % 3] = q[e * ns];
+        project<MU, -1>(p, h);
+    } else {
+        const Cx<T> *q = halo + pin((uint32_t)face);
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            h[e / 3][e % 3] = q[e * nf];
+    }
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, s), a.gl.plane, m);
+    color_mul<0>(m, h, w);
+    reconstruct<MU, -1>(w, acc);
+}
+
+template <int MU, int SP, int LP, int NT>
+__device__ __forceinline__ void hop_bwd_halo(const su3i::DslashArgs &a, uint32_t sb,
+                                             bool in_tile, int lb,
+                                             const Cx<typename PrecT<SP>::T> *tile, int ns,
+                                             const Cx<typename PrecT<SP>::T> *halo, int nf,
+                                             int face, Cx<typename PrecT<SP>::T> (&acc)[4][3])
+{
+    using T = typename PrecT<SP>::T;
+    Cx<T> m[9], h[2][3], w[2][3];
+    if (in_tile) {
+        Cx<T> p[4][3];
+        const Cx<T> *q = tile + pin((uint32_t)lb);
+#pragma unroll
+        for (int e = 0; e < 12; ++e)
+            p[e / 3][e % 3] = q[e * ns];
+        project<MU, +1>(p, h);
+    } else {
+        const Cx<T> *q = halo + pin((uint32_t)face);
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            h[e / 3][e % 3] = q[e * nf];
+    }
+    load_link<LP, NT>(a.u[MU], site_offset(a.gl, sb), a.gl.plane, m);
+    color_mul<1>(m, h, w);
+    reconstruct<MU, +1>(w, acc);
+}
+
+// Face f of the halo of slice tt of tile (y0, z0): faces 0 .. tx*TZ-1 are
+// the row below the tile in y (y0 - 1, periodic), then the row above its
+// last row (y0 + TY, or 0 past the lattice's end), then the same two in z
+// (tx*TY each); x fastest within a face.  Returns the face's kind (0, 1:
+// below and above in y, 2, 3 in z) and its site, or -1 for a face site
+// past the lattice in the other direction (a partial tile: no lane of the
+// tile reads it).
+template <int TY, int TZ>
+__device__ __forceinline__ int halo_face(const su3i::DslashArgs &a, uint32_t y0, uint32_t z0,
+                                         uint32_t tt, int tx, int f, uint32_t &site)
+{
+    const int fy = tx * TZ, fz = tx * TY;
+    const uint32_t Ly = a.dims[1], Lz = a.dims[2];
+    int kind, g;
+    if (f < 2 * fy) {
+        kind = f < fy ? 0 : 1;
+        g = f - kind * fy;
+    } else {
+        kind = f < 2 * fy + fz ? 2 : 3;
+        g = f - 2 * fy - (kind - 2) * fz;
+    }
+    const uint32_t x = (uint32_t)(g % tx), w = (uint32_t)(g / tx);
+    uint32_t y, z;
+    if (kind < 2) {
+        z = z0 + w;
+        y = kind == 0 ? (y0 == 0 ? Ly - 1 : y0 - 1) : (y0 + TY < Ly ? y0 + TY : 0u);
+        if (z >= Lz)
+            return -1;
+    } else {
+        y = y0 + w;
+        z = kind == 2 ? (z0 == 0 ? Lz - 1 : z0 - 1) : (z0 + TZ < Lz ? z0 + TZ : 0u);
+        if (y >= Ly)
+            return -1;
+    }
+    site = x + a.stride[1] * y + a.stride[2] * z + a.stride[3] * tt;
+    return kind;
+}
+
+// Project a face site's spinor for the hop that reads it (the sites below
+// for backward hops, those above for forward ones) into halo slot f.
+template <class T>
+__device__ __forceinline__ void put_face(int kind, const Cx<T> (&p)[4][3], Cx<T> *halo,
+                                         int nf, int f)
+{
+    Cx<T> h[2][3];
+    if (kind == 0)
+        project<1, +1>(p, h);
+    else if (kind == 1)
+        project<1, -1>(p, h);
+    else if (kind == 2)
+        project<2, +1>(p, h);
+    else
+        project<2, -1>(p, h);
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+        halo[e * nf + f] = h[e / 3][e % 3];
+}
+
+// Fill halo faces first, first + nlanes, ... of slice tt (the workgroup's
+// lanes share them).
+template <int SP, int NT, int TY, int TZ>
+__device__ __forceinline__ void load_halo(const su3i::DslashArgs &a, uint32_t y0, uint32_t z0,
+                                          uint32_t tt, int tx, int first, int nlanes,
+                                          Cx<typename PrecT<SP>::T> *halo)
+{
+    using T = typename PrecT<SP>::T;
+    const int nf = 2 * tx * (TY + TZ);
+    for (int f = first; f < nf; f += nlanes) {
+        uint32_t site;
+        const int kind = halo_face<TY, TZ>(a, y0, z0, tt, tx, f, site);
+        if (kind < 0)
+            continue;
+        Cx<T> p[4][3];
+        load_spinor<SP, NT & 2>(a.in, site_offset(a.gs, site), a.gs.plane, p);
+        put_face(kind, p, halo, nf, f);
+    }
+}
+
 // Most lanes a workgroup of the LDS-tiled walk has (row tiles: as many as
 // rows_max_lanes allows) and the fewest waves per SIMD it must fit.
 template <int SP, int TX, int TY, int TZ, bool VN>
@@ -465,7 +601,7 @@ constexpr int lds_min_waves()
     return SP == su3i::F64 ? 2 : (VN ? 3 : 4);
 }
 
-template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB, bool VN>
+template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB, bool VN, bool HALO>
 __global__ __launch_bounds__((lds_max_lanes<SP, TX, TY, TZ, VN>()), (lds_min_waves<SP, VN>()))
 void k_dslash_lds(su3i::DslashArgs a)
 {
@@ -476,10 +612,13 @@ void k_dslash_lds(su3i::DslashArgs a)
     const int nl = VN ? (int)a.lmask + 1 : 1;
     const int tx = TX ? TX : (int)a.lds_tx;
     const int ns = nl * tx * TY * TZ;
+    static_assert(!HALO || (!VN && TX == 0), "halos are built for whole rows of lexicographic fields");
     // the slice buffers in the dynamic LDS the host sizes to NB * 12 * ns
-    // complex numbers
+    // complex numbers, then (halo walks) NB halo buffers of 6 * nf
     extern __shared__ char occupancy_reserve[];
     Cx<T> *tile = reinterpret_cast<Cx<T> *>(occupancy_reserve);
+    const int nf = HALO ? 2 * tx * (TY + TZ) : 0;
+    Cx<T> *halo = tile + NB * 12 * ns;
     const uint32_t blk = a.xcd_remap == 1 ? (uint32_t)xcd_remap(blockIdx.x, gridDim.x)
                                           : blockIdx.x;
     const uint32_t ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
@@ -572,6 +711,9 @@ void k_dslash_lds(su3i::DslashArgs a)
                     tile[e * ns + l] = p[e / 3][e % 3];
             }
         }
+        const uint32_t y0 = c[1] - ly, z0 = c[2] - lz;  // the tile's corner
+        if constexpr (HALO)
+            load_halo<SP, NT, TY, TZ>(a, y0, z0, t0, tx, l, (int)blockDim.x, halo);
         __syncthreads();
         int cur = 0;
         for (uint32_t t = t0; t < t1; ++t) {
@@ -593,18 +735,35 @@ void k_dslash_lds(su3i::DslashArgs a)
                 hop_bwd_tile<0, SP, LP, NT>(a, bwd_site<0>(a, s, c[0], ln[0]), xb, lxb,
                                             cur_tile, ns, acc);
                 fence_acc(acc);
-                hop_fwd_tile<1, SP, LP, NT>(a, s, fwd_site<1>(a, s, c[1], ln[1]), yf, l + ry,
-                                            cur_tile, ns, acc);
-                fence_acc(acc);
-                hop_bwd_tile<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], ln[1]), yb, l - ry,
-                                            cur_tile, ns, acc);
-                fence_acc(acc);
-                hop_fwd_tile<2, SP, LP, NT>(a, s, fwd_site<2>(a, s, c[2], ln[2]), zf, l + rz,
-                                            cur_tile, ns, acc);
-                fence_acc(acc);
-                hop_bwd_tile<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], ln[2]), zb, l - rz,
-                                            cur_tile, ns, acc);
-                fence_acc(acc);
+                if constexpr (HALO) {
+                    const Cx<T> *cur_halo = halo + cur * 6 * nf;
+                    const int fy = tx * TZ, fz = 2 * fy + lx;
+                    hop_fwd_halo<1, SP, LP, NT>(a, s, yf, l + ry, cur_tile, ns, cur_halo, nf,
+                                                fy + lx + tx * lz, acc);
+                    fence_acc(acc);
+                    hop_bwd_halo<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], ln[1]), yb, l - ry,
+                                                cur_tile, ns, cur_halo, nf, lx + tx * lz, acc);
+                    fence_acc(acc);
+                    hop_fwd_halo<2, SP, LP, NT>(a, s, zf, l + rz, cur_tile, ns, cur_halo, nf,
+                                                fz + tx * TY + tx * ly, acc);
+                    fence_acc(acc);
+                    hop_bwd_halo<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], ln[2]), zb, l - rz,
+                                                cur_tile, ns, cur_halo, nf, fz + tx * ly, acc);
+                    fence_acc(acc);
+                } else {
+                    hop_fwd_tile<1, SP, LP, NT>(a, s, fwd_site<1>(a, s, c[1], ln[1]), yf,
+                                                l + ry, cur_tile, ns, acc);
+                    fence_acc(acc);
+                    hop_bwd_tile<1, SP, LP, NT>(a, bwd_site<1>(a, s, c[1], ln[1]), yb,
+                                                l - ry, cur_tile, ns, acc);
+                    fence_acc(acc);
+                    hop_fwd_tile<2, SP, LP, NT>(a, s, fwd_site<2>(a, s, c[2], ln[2]), zf,
+                                                l + rz, cur_tile, ns, acc);
+                    fence_acc(acc);
+                    hop_bwd_tile<2, SP, LP, NT>(a, bwd_site<2>(a, s, c[2], ln[2]), zb,
+                                                l - rz, cur_tile, ns, acc);
+                    fence_acc(acc);
+                }
             }
             if constexpr (NB == 1)
                 __syncthreads();  // slice t read by the whole tile
@@ -643,6 +802,13 @@ void k_dslash_lds(su3i::DslashArgs a)
                 store_entries<SP, 1, 2, true, 0, 12>(static_cast<typename PrecT<SP>::R *>(a.out),
                                                      site_offset(a.gs, s), a.gs.plane, 1, raw);
             }
+            if constexpr (HALO) {
+                // the next slice's faces, in the step in which the tiles
+                // that own them load that slice (the same for every lane)
+                if (t + 1 < t1)
+                    load_halo<SP, NT, TY, TZ>(a, y0, z0, t + 1, tx, l, (int)blockDim.x,
+                                              halo + (NB == 1 ? 0 : (cur ^ 1) * 6 * nf));
+            }
             __syncthreads();
             if constexpr (NB == 2)
                 cur ^= 1;
@@ -650,11 +816,12 @@ void k_dslash_lds(su3i::DslashArgs a)
     }
 }
 
-template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB, bool VN = false>
+template <int SP, int LP, int NT, int TX, int TY, int TZ, int NB, bool VN = false,
+          bool HALO = false>
 static hipError_t launch_lds(int block, int grid, size_t shm, const su3i::DslashArgs &a,
                              hipStream_t st)
 {
-    auto *k = k_dslash_lds<SP, LP, NT, TX, TY, TZ, NB, VN>;
+    auto *k = k_dslash_lds<SP, LP, NT, TX, TY, TZ, NB, VN, HALO>;
     if (block > lds_max_lanes<SP, TX, TY, TZ, VN>())
         return hipErrorInvalidValue;
     if (shm > 64 * 1024) {
@@ -680,28 +847,39 @@ static hipError_t launch_lds(int block, int grid, size_t shm, const su3i::Dslash
     return hipGetLastError();
 }
 
-// Row tiles (schedules 9..16: tx x {2, 4} x {2, 4}, one or two buffers),
-// lexicographic or virtual-node fields.
+// Row tiles (schedules 9..16: tx x {2, 4} x {2, 4}, one or two buffers;
+// 17, 18: tx x 3 x 3), lexicographic or virtual-node fields; 19..28 the
+// same shapes with a halo (lexicographic fields).
+template <int SP, int LP, int NT, bool VN, bool HALO>
+static hipError_t go_rows_as(int shape, int block, int grid, size_t shm,
+                             const su3i::DslashArgs &a, hipStream_t st)
+{
+    switch (shape) {
+    case 9: return launch_lds<SP, LP, NT, 0, 2, 2, 1, VN, HALO>(block, grid, shm, a, st);
+    case 10: return launch_lds<SP, LP, NT, 0, 2, 4, 1, VN, HALO>(block, grid, shm, a, st);
+    case 11: return launch_lds<SP, LP, NT, 0, 4, 2, 1, VN, HALO>(block, grid, shm, a, st);
+    case 12: return launch_lds<SP, LP, NT, 0, 4, 4, 1, VN, HALO>(block, grid, shm, a, st);
+    case 13: return launch_lds<SP, LP, NT, 0, 2, 2, 2, VN, HALO>(block, grid, shm, a, st);
+    case 14: return launch_lds<SP, LP, NT, 0, 2, 4, 2, VN, HALO>(block, grid, shm, a, st);
+    case 15: return launch_lds<SP, LP, NT, 0, 4, 2, 2, VN, HALO>(block, grid, shm, a, st);
+    case 16: return launch_lds<SP, LP, NT, 0, 4, 4, 2, VN, HALO>(block, grid, shm, a, st);
+    case 17: return launch_lds<SP, LP, NT, 0, 3, 3, 1, VN, HALO>(block, grid, shm, a, st);
+    case 18: return launch_lds<SP, LP, NT, 0, 3, 3, 2, VN, HALO>(block, grid, shm, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int SP, int LP, int NT, bool VN>
 static hipError_t go_rows(int block, int grid, size_t shm, const su3i::DslashArgs &a,
                           hipStream_t st)
 {
-    switch (a.lds_tile) {
-    case 9: return launch_lds<SP, LP, NT, 0, 2, 2, 1, VN>(block, grid, shm, a, st);
-    case 10: return launch_lds<SP, LP, NT, 0, 2, 4, 1, VN>(block, grid, shm, a, st);
-    case 11: return launch_lds<SP, LP, NT, 0, 4, 2, 1, VN>(block, grid, shm, a, st);
-    case 12: return launch_lds<SP, LP, NT, 0, 4, 4, 1, VN>(block, grid, shm, a, st);
-    case 13: return launch_lds<SP, LP, NT, 0, 2, 2, 2, VN>(block, grid, shm, a, st);
-    case 14: return launch_lds<SP, LP, NT, 0, 2, 4, 2, VN>(block, grid, shm, a, st);
-    case 15: return launch_lds<SP, LP, NT, 0, 4, 2, 2, VN>(block, grid, shm, a, st);
-    case 16: return launch_lds<SP, LP, NT, 0, 4, 4, 2, VN>(block, grid, shm, a, st);
-    default: break;
-    }
-    if (a.lds_tile == 17)
-        return launch_lds<SP, LP, NT, 0, 3, 3, 1, VN>(block, grid, shm, a, st);
-    if (a.lds_tile == 18)
-        return launch_lds<SP, LP, NT, 0, 3, 3, 2, VN>(block, grid, shm, a, st);
-    return hipErrorInvalidValue;
+    if (a.lds_tile <= 18)
+        return go_rows_as<SP, LP, NT, VN, false>((int)a.lds_tile, block, grid, shm, a, st);
+    if constexpr (VN)
+        return hipErrorInvalidValue;
+    else
+        return go_rows_as<SP, LP, NT, false, true>((int)a.lds_tile - 10, block, grid, shm, a,
+                                                  st);
 }
 
 // The LDS-tiled walk by schedule and block (the shapes lds_shape accepts;

@@ -280,8 +280,9 @@ int main(int argc, char **argv)
                     // 512, walks of 2, 3, 5 and all of t); whole x rows
                     // (x hops and their wrap from LDS), one or two buffers;
                     // persistent walks over (tile, slice) spans; XCD slabs;
-                    // rows of 3 x 3 (ragged here), one and two buffers
-                    su3_launch cs[34] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
+                    // rows of 3 x 3 (ragged here), one and two buffers; the same
+                    // rows with a halo of projected face sites
+                    su3_launch cs[41] = {{64, 0, 0, 0, 0, 1, 0, 0}, {256, 0, 3, 1, 0, 3, 4, 0},
                                          {128, 0, 2, 0, 0, 4096, 0, 0}, {128, 0, 2, 1, 0, 4, 0, 0},
                                          {64, 0, 2, 0, 0, 2, 0, 0}, {128, 0, 2, 1, 0, 1, 0, 1},
                                          {64, 0, 2, 0, 0, 1, 0, 2}, {256, 0, 2, 1, 0, 1, 0, 3},
@@ -298,8 +299,12 @@ int main(int argc, char **argv)
                                          {256, 2, 2, 1, 0, 1, 0, 11}, {256, 3, 2, 0, 0, 1, 0, 16},
                                          {256, 0, 2, 2, 0, 3, 0, 11}, {128, 0, 2, 2, 0, 4096, 0, 4},
                                          {256, 0, 2, 0, 0, 3, 0, 17}, {256, 0, 2, 1, 0, 5, 0, 18},
-                                         {256, 2, 2, 0, 0, 1, 0, 18}};
-                    for (int k = 0; k < 34; ++k) {
+                                         {256, 2, 2, 0, 0, 1, 0, 18},
+                                         {64, 0, 2, 0, 0, 3, 0, 19}, {256, 0, 2, 1, 0, 4096, 0, 22},
+                                         {256, 2, 2, 0, 0, 1, 0, 26}, {256, 0, 2, 0, 0, 5, 0, 27},
+                                         {256, 0, 2, 2, 0, 3, 0, 28}, {128, 0, 2, 0, 0, 2, 0, 23},
+                                         {256, 1, 2, 0, 0, 1, 0, 20}};
+                    for (int k = 0; k < 41; ++k) {
                         if (cs[k].schedule >= 4 && !lds_too)
                             continue;
                         su3_launch_set(SU3_EXPR_DSLASH, (su3_precision)lp, (su3_layout)l[0], l[1], d, &cs[k]);
@@ -388,7 +393,7 @@ int main(int argc, char **argv)
             su3_field *u32[4], *s32b;
             for (int mu = 0; mu < 4; ++mu) su3_field_alloc(&u32[mu], d, SU3_F32, SU3_LAYOUT_SOA, 0);
             su3_spinor_alloc(&s32b, d, SU3_F32, SU3_LAYOUT_SOA, 0);
-            for (int sched = 4; sched <= 19; ++sched)
+            for (int sched = 4; sched <= 29; ++sched)
                 for (int b : {64, 128, 256, 512, 1024})
                     for (int lp : {0, 1}) {
                         su3_launch c = {b, 0, 2, 0, 0, 2, 0, sched};

@@ -251,11 +251,12 @@ def test_launch_table():
     su3.su3_launch_set(su3.SU3_EXPR_DSLASH, 0, 1, 0, dims, dict(cfg, tile_sites=3))
     assert _status(su3.su3_launch_set, su3.SU3_EXPR_DSLASH, 0, 1, 0, dims,
                    dict(cfg, tile_sites=0)) == su3.SU3_ERR_INVALID_ARG
-    # LDS-tiled walks: schedules 4..18, block 512 only there, 16-wide
-    # tiles need a block of at least 256 (whole rows take any block)
+    # LDS-tiled walks: schedules 4..28, block 512 only there, 16-wide
+    # tiles need a block of at least 256 (whole rows, with or without a
+    # halo, take any block)
     for sched, block in ((4, 128), (4, 256), (5, 512), (6, 256), (7, 256), (7, 512),
                          (8, 256), (8, 512), (9, 64), (12, 256), (16, 128), (17, 256),
-                         (18, 64)):
+                         (18, 64), (19, 256), (27, 64), (28, 128)):
         good = dict(cfg, schedule=sched, block=block, tile_sites=8)
         su3.su3_launch_set(su3.SU3_EXPR_DSLASH, 0, 1, 0, dims, good)
         assert su3.su3_launch_get(su3.SU3_EXPR_DSLASH, 0, 1, 0, dims).as_dict() == good
@@ -265,8 +266,8 @@ def test_launch_table():
     for key, sched in ((su3.SU3_EXPR_DSLASH, 0), (0, 1)):
         assert _status(su3.su3_launch_set, key, 0, 1, 0, dims,
                        dict(cfg, schedule=sched, xcd_remap=2)) == su3.SU3_ERR_INVALID_ARG
-    for sched, block in ((19, 256), (8, 128), (7, 128), (6, 512), (4, 64), (5, 1024), (0, 512),
-                         (3, 512)):
+    for sched, block in ((29, 256), (8, 128), (7, 128), (6, 512), (4, 64), (5, 1024), (0, 512),
+                         (3, 512), (-1, 256)):
         assert _status(su3.su3_launch_set, su3.SU3_EXPR_DSLASH, 0, 1, 0, dims,
                        dict(cfg, schedule=sched, block=block)) == su3.SU3_ERR_INVALID_ARG
     su3.su3_launch_reset()

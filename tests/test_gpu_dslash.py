@@ -108,7 +108,9 @@ def test_dslash_parity(pair, dims):
         # the one-buffer tiles 8x8, 8x4, 16x8 and 16x4 (blocks up to 512, walks of
         # 2, 3, 5 and all of t, nontemporal link loads or not); whole x rows
         # with one and with two buffers; persistent walks over (tile, slice)
-        # spans; tiles in XCD slabs; rows of 3 x 3 (one and two buffers)
+        # spans; tiles in XCD slabs; rows of 3 x 3 (one and two buffers);
+        # the same rows with a halo of projected face sites (lexicographic
+        # layouts; the virtual-node layout falls back to rows without one)
         for cfg in (dict(block=64, nontemporal=0, occupancy=0, xcd_remap=0, tile_sites=1,
                          schedule=0),
                     dict(block=256, nontemporal=3, occupancy=4, xcd_remap=1, tile_sites=3,
@@ -174,7 +176,19 @@ def test_dslash_parity(pair, dims):
                     dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=5,
                          schedule=18),
                     dict(block=256, persistent=2, nontemporal=2, occupancy=0, xcd_remap=0,
-                         tile_sites=1, schedule=18)):
+                         tile_sites=1, schedule=18),
+                    dict(block=64, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=3,
+                         schedule=19),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=1, tile_sites=4096,
+                         schedule=22),
+                    dict(block=256, persistent=2, nontemporal=2, occupancy=0, xcd_remap=0,
+                         tile_sites=1, schedule=26),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=2, tile_sites=5,
+                         schedule=27),
+                    dict(block=256, nontemporal=2, occupancy=0, xcd_remap=0, tile_sites=3,
+                         schedule=28),
+                    dict(block=256, persistent=1, nontemporal=2, occupancy=0, xcd_remap=0,
+                         tile_sites=1, schedule=20)):
             full = dict(dict(persistent=0, lds_stage=0), **cfg)
             su3.su3_launch_set(su3.SU3_EXPR_DSLASH, lp, lay, lanes, dims, full)
             try:
