@@ -826,8 +826,8 @@ def run_variants(ctx, out):
     for nsub, simd in ((4, (1, 1, 2, 2)), (16, (2, 2, 2, 2))):
         F64, VN = su3.SU3_F64, su3.SU3_LAYOUT_VNODE
 
-        def vfield(host, kind=su3.SU3_KIND_MATRIX):
-            f = su3.vnode_tensor(dims, F64, simd, kind)
+        def vfield(host, kind=su3.SU3_KIND_MATRIX, prec=F64):
+            f = su3.vnode_tensor(dims, prec, simd, kind)
             su3.su3_field_upload(f, host, stream)
             return f
 
@@ -844,6 +844,16 @@ def run_variants(ctx, out):
         ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
         vn[f"dslash_nsub{nsub}"] = entry(ms, DSLASH_BYTES_PER_SITE[(F64, F64)] * V)
         log(f"vnode nsub {nsub}: {vn[f'mul_nsub{nsub}']} {vn[f'dslash_nsub{nsub}']}")
+        del U, fin, fout
+        # the same hopping term with single-precision spinors and links
+        F32 = su3.SU3_F32
+        U = [vfield(host_field(V, testgen.FID_U0 + mu), prec=F32) for mu in range(4)]
+        fin = vfield(host_psi, su3.SU3_KIND_SPINOR, prec=F32)
+        fout = su3.vnode_tensor(dims, F32, simd, su3.SU3_KIND_SPINOR)
+        tune(su3.SU3_EXPR_DSLASH, F32, VN, nsub, dims, f"vnode dslash f32 {nsub}")
+        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+        vn[f"dslash_f32_nsub{nsub}"] = entry(ms, DSLASH_BYTES_PER_SITE[(F32, F32)] * V)
+        log(f"vnode nsub {nsub} f32 dslash: {vn[f'dslash_f32_nsub{nsub}']}")
         del U, fin, fout
     del host_psi
     out["vnode_f64_48^4"] = vn
