@@ -247,10 +247,12 @@ su3_status su3_field_wrap(su3_field **out, void *dev_ptr, size_t bytes,
                           const int32_t dims[4], su3_precision prec,
                           su3_layout layout, int32_t lanes);
 
-/* Release a handle (and its memory if owning).  NULL is accepted. */
+/* Release a handle (and its memory if owning): the end of the lattice
+ * object of Section 4, Listing 3.  NULL is accepted. */
 su3_status su3_field_free(su3_field *f);
 
-/* Device address and size of a field's storage. */
+/* Device address and size of a field's storage (the stored layouts of
+ * Sections 4-5). */
 su3_status su3_field_data(const su3_field *f, void **dev_ptr, size_t *bytes);
 
 /* Fill a field with its site values (the initial values of Listing 3's
@@ -260,7 +262,8 @@ su3_status su3_field_data(const su3_field *f, void **dev_ptr, size_t *bytes);
 su3_status su3_field_upload(su3_field *f, const double *host_aos,
                             void *stream);
 
-/* Read a field's site values back (the inverse of su3_field_upload).
+/* Read a field's site values back (the inverse of su3_field_upload; the
+ * result of Section 4, Listing 3's assignment, read back to check it).
  * Unpack the field into V*18 canonical doubles (V*24 for a spinor field;
  * exact widening).  For
  * SU3_C12_F32, rows 0-1 are the stored values and row 2 is rebuilt in
@@ -269,7 +272,8 @@ su3_status su3_field_download(const su3_field *f, double *host_aos,
                               void *stream);
 
 /* Copy the stored image byte for byte into host memory (`bytes` must be at
- * least the field's size).  Completes before returning. */
+ * least the field's size): the layouts of Sections 4-5 as stored.
+ * Completes before returning. */
 su3_status su3_field_download_raw(const su3_field *f, void *host,
                                   size_t bytes, void *stream);
 
@@ -305,7 +309,8 @@ su3_status su3_cshift(su3_field *dst, const su3_field *src, int32_t mu,
                       int32_t shift, void *stream);
 
 /* z(x) = x(x) * y(x + shift * mu_hat), periodic, in one kernel without an
- * intermediate shifted field.  z may be x exactly; z must not overlap y
+ * intermediate shifted field: a product with a Cshift-ed operand, the
+ * stencil pattern of the outlook (Section 6).  z may be x exactly; z must not overlap y
  * (SU3_ERR_ALIAS).  The compressed form rebuilds the shifted operand's
  * third row in registers. */
 su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
@@ -316,7 +321,8 @@ su3_status su3_mult_shifted(su3_field *z, const su3_field *x,
 
 /* A spinor field holds 4 spins x 3 colours of complex numbers per site
  * (12 complex entries, entry 3 * spin + colour, stored like a matrix
- * field's entries in the same layouts).  Precisions SU3_F64 and SU3_F32
+ * field's entries in the same layouts): the fermion fields the Dslash of
+ * Section 6 acts on.  Precisions SU3_F64 and SU3_F32
  * (SU3_ERR_UNSUPPORTED otherwise).  The handles are su3_field handles:
  * su3_field_free, su3_field_data, su3_field_upload / su3_field_download
  * (V*24 canonical doubles: site, spin, colour, re/im) and
@@ -391,7 +397,8 @@ su3_status su3_scalar_wrap(su3_field **out, void *dev_ptr, size_t bytes,
 su3_status su3_program_create(su3_program **out, const char *expr,
                               int32_t n_ops, const su3_kind *kinds);
 
-/* Result kind (matrix, real or complex), instruction and register count. */
+/* Result kind (matrix, real or complex), instruction and register count
+ * of a compiled expression (Section 3's expression, as compiled here). */
 su3_status su3_program_info(const su3_program *p, su3_kind *result_kind,
                             int32_t *n_instr, int32_t *n_regs);
 
@@ -414,7 +421,8 @@ su3_status su3_program_eval(const su3_program *p, su3_field *z,
                             const su3_field *const *ops, int32_t n_ops,
                             void *stream);
 
-/* Release a program.  NULL is accepted. */
+/* Release a program (Section 3's expression, as compiled here).  NULL is
+ * accepted. */
 su3_status su3_program_destroy(su3_program *p);
 
 /* --------------------------------------------- Grid virtual-node layout */
@@ -477,9 +485,12 @@ su3_status su3_batch_create(su3_batch **out, const su3_expr *exprs,
 su3_status su3_batch_run(const su3_expr *exprs, su3_field *const *z,
                          const su3_field *const *ops, int32_t n, void *stream);
 
-/* Replay the batch's graph on `stream` (asynchronous). */
+/* Replay the batch's graph on `stream` (asynchronous): one pass of
+ * Section 3, Listing 1's site loop over every item. */
 su3_status su3_batch_launch(su3_batch *b, void *stream);
 
+/* Release a batch (the batch of Section 3's site loop over several
+ * lattices): its tile table and graph; the fields are untouched. */
 su3_status su3_batch_destroy(su3_batch *b);
 
 /* Copy the batch's tile table from the device: 4 int32 per tile, (item,
@@ -524,7 +535,9 @@ su3_status su3_layout_recommend(su3_expr expr, su3_precision prec,
                                 su3_layout *layout, int32_t *lanes,
                                 su3_launch *best, double *us);
 
-/* Autotune a batch: build the batch with each candidate launch (tile size,
+/* Autotune a batch (Section 5's launch-shape study, applied to the batch
+ * of Section 3's loop over several lattices): build the batch with each
+ * candidate launch (tile size,
  * one workgroup per tile or k per CU, occupancy cap, schedule, nontemporal
  * bits), time graph replays (median of 5 after 2), and keep the fastest for
  * later su3_batch_create calls on items of the same leading (expr,
@@ -536,18 +549,20 @@ su3_status su3_batch_autotune(const su3_expr *exprs, su3_field *const *z,
                               const su3_field *const *ops, int32_t n,
                               void *stream, su3_launch *best);
 
-/* Launch settings used for a key (tuned, set, or the built-in default). */
+/* Launch settings used for a key (tuned, set, or the built-in default):
+ * the launch choices of Sections 4-5 that the autotuner makes. */
 su3_status su3_launch_get(su3_expr expr, su3_precision prec,
                           su3_layout layout, int32_t lanes,
                           const int32_t dims[4], su3_launch *out);
 
 /* Force the launch settings for a key (validated; SU3_ERR_INVALID_ARG for
- * an unsupported setting). */
+ * an unsupported setting), as su3_launch_get (Sections 4-5). */
 su3_status su3_launch_set(su3_expr expr, su3_precision prec,
                           su3_layout layout, int32_t lanes,
                           const int32_t dims[4], const su3_launch *cfg);
 
-/* Forget every tuned or set launch (the JSON cache file is left alone). */
+/* Forget every tuned or set launch (the JSON cache file is left alone),
+ * as su3_launch_get (Sections 4-5). */
 su3_status su3_launch_reset(void);
 
 /* ------------------------------------------- bandwidth yardsticks */
@@ -579,7 +594,8 @@ su3_status su3_stream(su3_stream_kind kind, void *a, const void *b,
                       const void *c, double s, size_t bytes,
                       const su3_launch *cfg, void *stream);
 
-/* Time every candidate launch of a yardstick on the caller's arrays
+/* Section 5's yardstick, tuned: time every candidate launch of a
+ * yardstick on the caller's arrays
  * (median of 10 launches after 3) and return the fastest in *best and its
  * time in *us (either may be NULL).  Overwrites `a`.  Completes before
  * returning. */
@@ -587,27 +603,32 @@ su3_status su3_stream_autotune(su3_stream_kind kind, void *a, const void *b,
                                const void *c, size_t bytes, void *stream,
                                su3_launch *best, double *us);
 
-/* STREAM-style triad a[i] = b[i] + s*c[i] over n doubles with the default
+/* STREAM-style triad (Section 5's yardstick) a[i] = b[i] + s*c[i] over n
+ * doubles with the default
  * launch of SU3_STREAM_TRIAD.  Device pointers, 16-byte aligned,
  * asynchronous on `stream`. */
 su3_status su3_triad(double *a, const double *b, const double *c, double s,
                      int64_t n, void *stream);
 
 /* Plain copy dst[i] = src[i] over `bytes` bytes (multiple of 16, 16-byte
- * aligned device pointers) with the default launch of SU3_STREAM_COPY,
+ * aligned device pointers) with the default launch of SU3_STREAM_COPY
+ * (Section 5's yardsticks; the copy that calibrates the HBM counters),
  * asynchronous on `stream`. */
 su3_status su3_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* --------------------------------------------------------- utilities */
 
 /* Wait for `stream` and report any pending HIP error (asynchronous kernel
- * faults surface here). */
+ * faults surface here): where a timed pass of Section 4, Listing 3's loop
+ * ends. */
 su3_status su3_sync(void *stream);
 
-/* Static text of a status code. */
+/* Static text of a status code (the boundary's own error reporting; no
+ * passage of the paper defines it). */
 const char *su3_status_string(su3_status s);
 
-/* Detail of the last failing call on this thread ("" if none). */
+/* Detail of the last failing call on this thread ("" if none; the
+ * boundary's own error reporting, as su3_status_string). */
 const char *su3_last_error(void);
 
 #ifdef __cplusplus
