@@ -40,7 +40,7 @@ struct DslashArgs {
     // (lds_shape), walking `walk` t-slices; ntile[0..2] tiles per
     // direction.  0: no LDS tile
     uint32_t lds_tile;
-    uint32_t lds_tx;    // row tiles (schedules 9..18): the tile's x extent
+    uint32_t lds_tx;    // row tiles (schedules 9..28): the tile's x extent
 };
 
 // Tile of the LDS-tiled walk: tx x ty x tz (x, y, z) sites -- outer sites
