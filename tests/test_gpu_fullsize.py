@@ -177,3 +177,95 @@ def test_precision_error_report():
         os.makedirs(out, exist_ok=True)
         with open(os.path.join(out, "precision_errors.json"), "w") as f:
             json.dump(report, f, indent=1)
+
+
+# Fields at the size limit: 2^31 - 1 reals per field (offsets are 32-bit in
+# units of reals).  128^3 x 56 FP64 sites hold 18 x 117,440,512 =
+# 2,113,929,216 reals and 128^3 x 85 two-row FP32 sites 12 x 178,257,920 =
+# 2,139,095,040 (one more t-slice of either passes the limit): about 51
+# and 26 GB for three fields.  The inputs are made
+# on the device from a seeded 16^4 block of SU(3) matrices: site s holds
+# block matrix s mod 65536 times the cube root of unity w^k(s), k a hash of
+# s, so every site stays in SU(3) (w^k is central) and a site offset by a
+# multiple of the block reads a different matrix.  Sampled sites -- the
+# first and last 64 and 4096 drawn at random -- are read back from the
+# stored operands and checked against the oracle's product.
+LIMIT_CASES = [(su3.SU3_F64, (128, 128, 128, 56)), (su3.SU3_C12_F32, (128, 128, 128, 85))]
+LIMIT_LAUNCHES = (  # the headline's launch (write-through stores), a plain one, wide blocks
+    dict(block=64, persistent=0, nontemporal=7, xcd_remap=0, lds_stage=0, tile_sites=4096,
+         occupancy=5, schedule=1, sites_per_lane=0),
+    dict(block=256, persistent=0, nontemporal=0, xcd_remap=1, lds_stage=0, tile_sites=4096,
+         occupancy=0, schedule=0, sites_per_lane=0),
+    dict(block=1024, persistent=0, nontemporal=3, xcd_remap=0, lds_stage=0, tile_sites=4096,
+         occupancy=0, schedule=1, sites_per_lane=0),
+)
+
+
+def _stored(f, prec, V):
+    """The SoA image of a field as a (E, V, 2) tensor (V a multiple of 64)."""
+    E = 9 if prec == su3.SU3_F64 else 6
+    dt = torch.float64 if prec == su3.SU3_F64 else torch.float32
+    return f.owner.view(dt).view(E, V, 2)
+
+
+def _limit_field(dims, prec, fid, salt, s):
+    n0 = 65536
+    small = su3.field_tensor((16, 16, 16, 16), prec, su3.SU3_LAYOUT_SOA)
+    su3.su3_field_upload(small, testgen.su3_field(n0, field_id=fid), s)
+    sv = _stored(small, prec, n0).to(torch.float64)
+    V = testgen.volume(dims)
+    big = su3.field_tensor(dims, prec, su3.SU3_LAYOUT_SOA)
+    bv = _stored(big, prec, V)
+    cw = torch.tensor([1.0, -0.5, -0.5], dtype=torch.float64, device="cuda")
+    sw = torch.tensor([0.0, 0.75 ** 0.5, -(0.75 ** 0.5)], dtype=torch.float64, device="cuda")
+    chunk = 1 << 23
+    for a in range(0, V, chunk):
+        idx = torch.arange(a, min(V, a + chunk), dtype=torch.int64, device="cuda")
+        k = ((idx * 2654435761 + salt) >> 11) % 3
+        blk = sv[:, idx % n0, :]
+        re, im = blk[..., 0], blk[..., 1]
+        bv[:, a:a + idx.numel(), 0] = (re * cw[k] - im * sw[k]).to(bv.dtype)
+        bv[:, a:a + idx.numel(), 1] = (re * sw[k] + im * cw[k]).to(bv.dtype)
+    del small, sv
+    return big
+
+
+def _canonical(stored, prec):
+    """(E, n, 2) stored values at sampled sites -> (n, 3, 3, 2) doubles
+    (two-row form: row 2 left zero; the oracle's reference rebuilds it)."""
+    a = stored.to(torch.float64).cpu().numpy().transpose(1, 0, 2)
+    n = a.shape[0]
+    out = np.zeros((n, 3, 3, 2))
+    rows = 3 if prec == su3.SU3_F64 else 2
+    out[:, :rows] = a.reshape(n, rows, 3, 2)
+    return out
+
+
+@pytest.mark.parametrize("prec,dims", LIMIT_CASES, ids=["f64", "c12"])
+def test_mult_at_field_size_limit(prec, dims):
+    s = torch.cuda.current_stream()
+    V = testgen.volume(dims)
+    E = 9 if prec == su3.SU3_F64 else 6
+    assert V % 64 == 0 and E * 2 * V <= 2 ** 31 - 1 < E * 2 * (V + 128 ** 3)
+    x = _limit_field(dims, prec, testgen.FID_X, 11, s)
+    y = _limit_field(dims, prec, testgen.FID_Y, 29, s)
+    z = su3.field_tensor(dims, prec, su3.SU3_LAYOUT_SOA)
+    g = np.random.default_rng(1710)
+    sites = np.unique(np.concatenate([np.arange(64), np.arange(V - 64, V),
+                                      g.integers(0, V, 4096)]))
+    si = torch.from_numpy(sites).cuda()
+    xs = _canonical(_stored(x, prec, V)[:, si, :], prec)
+    ys = _canonical(_stored(y, prec, V)[:, si, :], prec)
+    want = O.get().reference(su3.SU3_EXPR_MUL, prec, [xs, ys])
+    try:
+        for cfg in LIMIT_LAUNCHES:
+            su3.su3_launch_set(su3.SU3_EXPR_MUL, prec, su3.SU3_LAYOUT_SOA, 0, dims, cfg)
+            z.owner.zero_()
+            su3.su3_mult(z, x, y, s)
+            su3.su3_sync(s)
+            got = _canonical(_stored(z, prec, V)[:, si, :], prec)
+            assert_parity(prec, su3.SU3_EXPR_MUL, got, want, f"size limit {dims} {cfg}")
+    finally:
+        su3.su3_launch_reset()
+        del x, y, z
+        torch.cuda.empty_cache()
