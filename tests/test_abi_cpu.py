@@ -143,6 +143,11 @@ def test_field_validation():
     assert _status(su3.su3_field_bytes, (128, 128, 128, 64), 0, 1) == E
     assert _status(su3.su3_field_bytes, (104, 104, 104, 104), 0, 1) == 0
     assert _status(su3.su3_field_alloc, (4, 4, 4, 0), 0, 1) == E
+    # an empty lattice is refused for every kind of field
+    for dims in ((0, 4, 4, 4), (4, 4, 4, 0)):
+        assert _status(su3.su3_spinor_bytes, dims, 0, 1, 0) == E
+        assert _status(su3.su3_scalar_bytes, dims, 0, 1, 0, su3.SU3_KIND_REAL) == E
+        assert _status(su3.su3_vnode_bytes, dims, 0, su3.SU3_KIND_MATRIX, (1, 1, 1, 1)) == E
     assert _status(su3.su3_field_wrap, 0, (4, 4, 4, 4), 0, 1, 0, 1 << 20) == E
     assert _status(su3.su3_field_wrap, 8, (4, 4, 4, 4), 0, 1, 0, 1 << 20) == E
     assert _status(su3.su3_field_wrap, 4096, (4, 4, 4, 4), 0, 1, 0, 100) == E
@@ -171,6 +176,15 @@ def test_compute_validation_without_fields():
     assert lib.su3_stream_autotune(su3.SU3_STREAM_READ, 16, None, 48, 32, None,
                                    None, None) == E
     assert lib.su3_batch_launch(None, None) == su3.SU3_ERR_INVALID_ARG
+    # empty inputs: a batch of no items (or a negative count) is refused
+    # before any device call, by both the graph and the allocation-free form
+    exprs = (ctypes.c_int32 * 1)(su3.SU3_EXPR_MUL)
+    zs = (ctypes.c_void_p * 1)()
+    ops = (ctypes.c_void_p * 4)()
+    h = ctypes.c_void_p()
+    for n in (0, -1):
+        assert lib.su3_batch_create(ctypes.byref(h), exprs, zs, ops, n, None) == E
+        assert lib.su3_batch_run(exprs, zs, ops, n, None) == E
     assert lib.su3_batch_destroy(None) == su3.SU3_OK
     assert lib.su3_field_free(None) == su3.SU3_OK
     assert "NULL" in su3.su3_last_error() or su3.su3_last_error()
