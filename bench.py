@@ -909,6 +909,7 @@ def run_variants(ctx, out):
     M, R, C = su3.SU3_KIND_MATRIX, su3.SU3_KIND_REAL, su3.SU3_KIND_COMPLEX
     for prec, pname in ((su3.SU3_F64, "f64"), (su3.SU3_F32, "f32")):
         tune(su3.SU3_EXPR_PROGRAM, prec, SOA, 0, dims, f"program {pname}")
+        tune(su3.SU3_EXPR_PROGRAM_SCALAR, prec, SOA, 0, dims, f"program {pname} scalar result")
         rb = REAL_BYTES[prec]
         ra = su3.scalar_tensor(dims, prec, SOA, R)
         rb_ = su3.scalar_tensor(dims, prec, SOA, R)

@@ -126,6 +126,10 @@ typedef enum su3_expr {
     /* launch-tuning key of su3_program_eval; its precision is the
      * arithmetic one (SU3_F64 or SU3_F32) */
     SU3_EXPR_PROGRAM = 8,
+    /* the same for programs with matrix values and a real or complex
+     * result (a trace: nearly read-only streams, whose best launch differs
+     * from a matrix result's); su3_autotune times it on trace(a*adj(b)) */
+    SU3_EXPR_PROGRAM_SCALAR = 9,
     /* launch-tuning keys of batches: SU3_EXPR_BATCH + the leading item's
      * expression (MUL .. APB_AB), with its precision, layout and lanes, at
      * the batch's total volume (su3_launch_get / su3_launch_set; what
@@ -414,7 +418,9 @@ su3_status su3_program_info(const su3_program *p, su3_kind *result_kind,
  * keeps part of its register file in scratch memory and is several times
  * slower than the others.  z may be an operand exactly; a partial overlap is
  * SU3_ERR_ALIAS.  The launch setting of SU3_EXPR_PROGRAM (tuned or set)
- * applies in full to programs with matrix values; programs without one
+ * applies in full to programs with matrix values and a matrix result,
+ * that of SU3_EXPR_PROGRAM_SCALAR to programs with matrix values and a
+ * real or complex result; programs without a matrix value
  * take only its nontemporal bits and run 256-lane workgroups with no
  * occupancy cap. */
 su3_status su3_program_eval(const su3_program *p, su3_field *z,

@@ -40,6 +40,7 @@ SU3_EXPR_MUL, SU3_EXPR_MUL3, SU3_EXPR_MULADD, SU3_EXPR_ADD, SU3_EXPR_APB_AB = ra
 SU3_EXPR_CSHIFT, SU3_EXPR_MUL_SHIFTED = 5, 6  # launch-tuning keys only
 SU3_EXPR_DSLASH = 7  # launch-tuning key of su3_dslash (precision = links')
 SU3_EXPR_PROGRAM = 8  # launch-tuning key of su3_program_eval (arithmetic precision)
+SU3_EXPR_PROGRAM_SCALAR = 9  # the same for matrix-valued programs with a scalar result
 SU3_EXPR_BATCH = 32  # + leading item's expression: launch-tuning key of a batch
 N_OPERANDS = {0: 2, 1: 3, 2: 4, 3: 2, 4: 2}
 

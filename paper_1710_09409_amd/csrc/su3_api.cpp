@@ -669,7 +669,7 @@ static su3_launch default_launch(int expr, int prec, int layout)
     c.occupancy = layout == SU3_LAYOUT_AOS ? 0 : 5;
     c.schedule = layout == SU3_LAYOUT_AOS ? 0 : 1;
     c.sites_per_lane = 0;
-    if (expr == SU3_EXPR_PROGRAM) {
+    if (expr == SU3_EXPR_PROGRAM || expr == SU3_EXPR_PROGRAM_SCALAR) {
         c.block = 128;
         c.occupancy = 0;
         c.schedule = 0;
@@ -1357,10 +1357,13 @@ static su3_status launch_program_op(const su3_program *p, su3_field *z,
     const int form = p->code.real_only ? PF_REAL
                      : p->code.scalar_only ? PF_SCALAR
                                            : PF_MATRIX;
+    // matrix-valued programs with a real or complex result (a trace) read
+    // far more than they write, and are tuned under their own key
+    const su3_expr key = form == PF_MATRIX && p->code.result_kind != FK_MATRIX
+                             ? SU3_EXPR_PROGRAM_SCALAR
+                             : SU3_EXPR_PROGRAM;
     su3_launch c =
-        forced ? *forced
-               : lookup_launch(SU3_EXPR_PROGRAM, arith, z->layout, z->lanes,
-                               z->V);
+        forced ? *forced : lookup_launch(key, arith, z->layout, z->lanes, z->V);
     if (!forced && form != PF_MATRIX) {
         // the block and occupancy cap are the matrix kernel's (a wave of it
         // keeps up to 18 KB of loads in flight); a scalar-valued wave keeps
@@ -1482,10 +1485,11 @@ static su3_status key_of(su3_expr expr, su3_precision prec, su3_layout layout,
                          int32_t lanes, const int32_t dims[4], Key *k,
                          Shape *shape)
 {
-    if ((expr < SU3_EXPR_MUL || expr > SU3_EXPR_PROGRAM) && !is_batch_key(expr))
+    if ((expr < SU3_EXPR_MUL || expr > SU3_EXPR_PROGRAM_SCALAR) && !is_batch_key(expr))
         return fail(SU3_ERR_INVALID_ARG, "unknown expression %d", expr);
     const int base = is_batch_key(expr) ? expr - SU3_EXPR_BATCH : (int)expr;
-    if (expr == SU3_EXPR_PROGRAM && prec != SU3_F64 && prec != SU3_F32)
+    if ((expr == SU3_EXPR_PROGRAM || expr == SU3_EXPR_PROGRAM_SCALAR) && prec != SU3_F64 &&
+        prec != SU3_F32)
         return fail(SU3_ERR_UNSUPPORTED,
                     "expression programs evaluate in F64 or F32");
     if (expr == SU3_EXPR_DSLASH && prec == SU3_F16_F32ACC)
@@ -1787,7 +1791,9 @@ static su3_status autotune_impl(su3_expr expr, su3_precision prec,
         for (int i = 0; i <= nops && st == SU3_OK; ++i) {
             const bool spinor = dslash && i < 2;
             const int fp = spinor ? spinor_prec_of_links(prec) : prec;
-            const int kind = spinor ? KIND_SPINOR : KIND_MATRIX;
+            const int kind = spinor                                          ? KIND_SPINOR
+                             : i == 0 && expr == SU3_EXPR_PROGRAM_SCALAR ? KIND_COMPLEX
+                                                                          : KIND_MATRIX;
             if (layout == SU3_LAYOUT_VNODE)
                 st = alloc_of_kind(&f[i], dims, fp, layout, 0, kind, simd);
             else
@@ -1812,12 +1818,15 @@ static su3_status autotune_impl(su3_expr expr, su3_precision prec,
     size_t turn = 0;
     su3_launch win = default_launch(expr, prec, layout);
     double win_us = 1e300;
-    // expression programs are timed on the streaming product a*b
+    // expression programs are timed on the streaming product a*b, those
+    // with a scalar result on the trace of a product
+    const bool program = expr == SU3_EXPR_PROGRAM || expr == SU3_EXPR_PROGRAM_SCALAR;
     su3_program prog;
-    if (st == SU3_OK && expr == SU3_EXPR_PROGRAM) {
+    if (st == SU3_OK && program) {
         const int kinds[2] = {KIND_MATRIX, KIND_MATRIX};
         char err[128];
-        if (!compile_program("a*b", 2, kinds, &prog.code, err, sizeof err))
+        const char *text = expr == SU3_EXPR_PROGRAM ? "a*b" : "trace(a*adj(b))";
+        if (!compile_program(text, 2, kinds, &prog.code, err, sizeof err))
             st = fail(SU3_ERR_HIP, "internal program: %s", err);
     }
     if (st == SU3_OK) {
@@ -1826,7 +1835,7 @@ static su3_status autotune_impl(su3_expr expr, su3_precision prec,
                                                               f0->dims[0] / f0->simd[0],
                                                               layout == SU3_LAYOUT_VNODE
                                                                   ? (int)f0->L : 1)
-                                   : expr == SU3_EXPR_PROGRAM ? program_candidates()
+                                   : program ? program_candidates()
                                                               : candidates(layout, expr, prec)) {
             if (expr == SU3_EXPR_CSHIFT && c.schedule)
                 continue;  // a copy has no row phases
@@ -1838,7 +1847,7 @@ static su3_status autotune_impl(su3_expr expr, su3_precision prec,
                     su3_field *links[4] = {f[2], f[3], f[4], f[5]};
                     if (dslash)
                         return launch_dslash_op(f[0], links, f[1], stream, &c);
-                    if (expr == SU3_EXPR_PROGRAM)
+                    if (program)
                         return launch_program_op(&prog, f[0], ops, prec, hs, &c);
                     if (expr == SU3_EXPR_CSHIFT)
                         return launch_shift_op(0, f[0], nullptr, f[1], 1, 1,

@@ -220,7 +220,7 @@ def test_launch_table():
         su3.su3_launch_set(0, 0, 1, 0, dims, good)
         assert su3.su3_launch_get(0, 0, 1, 0, dims).as_dict() == good
     # ... which Dslash and programs do not take
-    for key in (su3.SU3_EXPR_DSLASH, su3.SU3_EXPR_PROGRAM):
+    for key in (su3.SU3_EXPR_DSLASH, su3.SU3_EXPR_PROGRAM, su3.SU3_EXPR_PROGRAM_SCALAR):
         assert _status(su3.su3_launch_set, key, 0, 1, 0, dims,
                        dict(cfg, nontemporal=7)) == su3.SU3_ERR_INVALID_ARG
     # batches have keys of their own (SU3_EXPR_BATCH + leading expression)
@@ -244,13 +244,14 @@ def test_launch_table():
     # the shifted operations' and Dslash's tuning keys are accepted,
     # unknown ones not
     for key in (su3.SU3_EXPR_CSHIFT, su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_EXPR_DSLASH,
-                su3.SU3_EXPR_PROGRAM):
+                su3.SU3_EXPR_PROGRAM, su3.SU3_EXPR_PROGRAM_SCALAR):
         su3.su3_launch_set(key, 0, 1, 0, dims, cfg)
         assert su3.su3_launch_get(key, 0, 1, 0, dims).as_dict() == cfg
-    assert _status(su3.su3_launch_set, 9, 0, 1, 0, dims, cfg) == su3.SU3_ERR_INVALID_ARG
+    assert _status(su3.su3_launch_set, 10, 0, 1, 0, dims, cfg) == su3.SU3_ERR_INVALID_ARG
     # programs evaluate in double or single
-    assert _status(su3.su3_launch_set, su3.SU3_EXPR_PROGRAM, 3, 1, 0, dims, cfg) == \
-        su3.SU3_ERR_UNSUPPORTED
+    for key in (su3.SU3_EXPR_PROGRAM, su3.SU3_EXPR_PROGRAM_SCALAR):
+        assert _status(su3.su3_launch_set, key, 3, 1, 0, dims, cfg) == \
+            su3.SU3_ERR_UNSUPPORTED
     # virtual-node keys: N_sub lanes
     su3.su3_launch_set(0, 0, su3.SU3_LAYOUT_VNODE, 16, dims, cfg)
     assert su3.su3_launch_get(0, 0, su3.SU3_LAYOUT_VNODE, 16, dims).as_dict() == cfg

@@ -222,3 +222,35 @@ def test_constant_fields_real_full_size(prec):
         assert err <= bound, f"{err:.3e} > {bound:.3e}"
     finally:
         su3.su3_launch_reset()
+
+
+@pytest.mark.parametrize("prec", [su3.SU3_F64, su3.SU3_F32], ids=["f64", "f32"])
+def test_trace_full_size_scalar_result_key(prec):
+    """A matrix-valued program with a complex result (the trace of a
+    product) at 48^4, in the launch tuned for its own key
+    (SU3_EXPR_PROGRAM_SCALAR, as the benchmark tunes it), against the
+    oracle on every site; the matrix-result key keeps its own setting."""
+    s = torch.cuda.current_stream()
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    lay = (su3.SU3_LAYOUT_SOA, 0, None)
+    try:
+        other = su3.su3_launch_get(su3.SU3_EXPR_PROGRAM, prec, su3.SU3_LAYOUT_SOA, 0, dims)
+        best = su3.su3_autotune(su3.SU3_EXPR_PROGRAM_SCALAR, prec, su3.SU3_LAYOUT_SOA, 0,
+                                dims, s)
+        assert su3.su3_launch_get(su3.SU3_EXPR_PROGRAM_SCALAR, prec, su3.SU3_LAYOUT_SOA, 0,
+                                  dims).as_dict() == best.as_dict()
+        assert su3.su3_launch_get(su3.SU3_EXPR_PROGRAM, prec, su3.SU3_LAYOUT_SOA, 0,
+                                  dims).as_dict() == other.as_dict()
+        hosts = [testgen.su3_field(V, field_id=testgen.FID_U0 + k) for k in range(2)]
+        a, b = (make(dims, prec, M, lay, h, s) for h in hosts)
+        z = make(dims, prec, C, lay, None, s)
+        su3.su3_program_eval(su3.Program("trace(a*adj(b))", [M, M]), z, [a, b], s)
+        su3.su3_sync(s)
+        got = su3.su3_field_download(z, s)
+        q = [quantise(h, M, prec) for h in hosts]
+        want = O.get().eval_expr("trace(a*adj(b))", q, [int(M), int(M)], V=V)
+        err, bound = tol(got, want.reshape(got.shape), prec != su3.SU3_F64)
+        assert err <= bound, f"{err:.3e} > {bound:.3e}"
+    finally:
+        su3.su3_launch_reset()
