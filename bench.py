@@ -934,6 +934,8 @@ def run_variants(ctx, out):
                 mf, _ = timer.run(lambda: su3.su3_mult(zm, mats[0], mats[1], stream), steps, 3)
                 progs[key]["fixed_us"] = round(mf * 1e3, 1)
             if name == "muladd":
+                # the fixed kernel in its own tuned launch at this size
+                tune(su3.SU3_EXPR_MULADD, prec, SOA, 0, dims, f"muladd {pname}")
                 mf, _ = timer.run(lambda: su3.su3_fused_eval(zm, su3.SU3_EXPR_MULADD, mats,
                                                              stream), steps, 3)
                 progs[key]["fixed_us"] = round(mf * 1e3, 1)
