@@ -29,7 +29,8 @@ Prints ONE JSON line on stdout (progress and launch settings go to stderr):
                median over --repeats blocks of K launches (default 5)
 
 `--only a,b` runs just those sections (precision, fused, ceiling, dslash,
-batch) with the tuned or cached launches, for profiler runs.
+batch, shift, programs) with the tuned or cached launches, for profiler
+runs.
 """
 from __future__ import annotations
 
@@ -61,7 +62,7 @@ REAL_BYTES = {0: 8, 1: 4, 2: 2, 3: 4}
 DSLASH_BYTES_PER_SITE = {(0, 0): 960, (1, 1): 480, (1, 3): 384}
 DSLASH_FLOPS_PER_SITE = 1320
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16_f32acc", 3: "c12_f32"}
-SECTIONS = ("precision", "fused", "ceiling", "dslash", "batch")
+SECTIONS = ("precision", "fused", "ceiling", "dslash", "batch", "shift", "programs")
 
 
 def log(*a):
@@ -760,9 +761,95 @@ def section_batch(ctx):
     return out
 
 
+def section_shift(ctx):
+    """Cshift and the product with a shifted operand at 48^4, FP64 SoA, in
+    each direction (288 and 432 B/site)."""
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args = ctx["args"]
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    steps = max(10, min(args.steps, 50))
+    SOA = su3.SU3_LAYOUT_SOA
+    if "x64" in ctx:
+        x64, y64, z64 = ctx["x64"], ctx["y64"], ctx["z64"]
+    else:
+        x64 = make(dims, su3.SU3_F64, SOA, 0, testgen.FID_X)
+        y64 = make(dims, su3.SU3_F64, SOA, 0, testgen.FID_Y)
+        z64 = su3.field_tensor(dims, su3.SU3_F64, SOA, 0)
+    shift = {}
+    tune(su3.SU3_EXPR_CSHIFT, su3.SU3_F64, SOA, 0, dims, "cshift")
+    tune(su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_F64, SOA, 0, dims, "mult_shifted")
+    for mu in range(4):
+        ms_c, _ = timer.run(lambda: su3.su3_cshift(z64, y64, mu, 1, stream), steps, 3)
+        ms_m, _ = timer.run(lambda: su3.su3_mult_shifted(z64, x64, y64, mu, 1, stream),
+                            steps, 3)
+        shift[f"mu{mu}"] = {"cshift": entry(ms_c, 288 * V), "mult": entry(ms_m, 432 * V)}
+        log(f"shift mu {mu}: {shift[f'mu{mu}']}")
+    return shift
+
+
+def section_programs(ctx):
+    """Expression programs at 48^4, SoA, in double and single arithmetic."""
+    su3, testgen, stream, timer, make, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "make", "tune"))
+    args = ctx["args"]
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    steps = max(10, min(args.steps, 50))
+    SOA = su3.SU3_LAYOUT_SOA
+    # expression programs at 48^4 (one precompiled kernel interpreting the
+    # host-compiled expression): the sum plus the product of two real
+    # fields, a+b+a*b (the real-valued composite example of Section 3,
+    # Listing 2; two real inputs, one real output: 24 B/site), the streaming product,
+    # the MULADD shape and a trace into a complex field, each against its
+    # algorithmic bytes; the fixed-expression kernels beside them
+    progs = {}
+    M, R, C = su3.SU3_KIND_MATRIX, su3.SU3_KIND_REAL, su3.SU3_KIND_COMPLEX
+    for prec, pname in ((su3.SU3_F64, "f64"), (su3.SU3_F32, "f32")):
+        tune(su3.SU3_EXPR_PROGRAM, prec, SOA, 0, dims, f"program {pname}")
+        tune(su3.SU3_EXPR_PROGRAM_SCALAR, prec, SOA, 0, dims, f"program {pname} scalar result")
+        rb = REAL_BYTES[prec]
+        ra = su3.scalar_tensor(dims, prec, SOA, R)
+        rb_ = su3.scalar_tensor(dims, prec, SOA, R)
+        rz = su3.scalar_tensor(dims, prec, SOA, R)
+        su3.su3_program_eval(su3.Program("1.0", []), ra, [], stream)
+        su3.su3_program_eval(su3.Program("2.0", []), rb_, [], stream)
+        mats = [make(dims, prec, SOA, 0, testgen.FID_U0 + k) for k in range(4)]
+        zm = su3.field_tensor(dims, prec, SOA, 0)
+        zc = su3.scalar_tensor(dims, prec, SOA, C)
+        cases = [("apb_ab_real", "a+b+a*b", [R, R], rz, [ra, rb_], 3 * rb),
+                 ("mul", "a*b", [M, M], zm, mats[:2], 54 * rb),
+                 ("muladd", "a*b+c*d", [M, M, M, M], zm, mats, 90 * rb),
+                 ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb),
+                 # seven matrix registers: the 8-register kernel (in double
+                 # it keeps part of its registers in scratch memory)
+                 ("deep", "(a*b+c*d)*(a*c+b*d)+(a-b)*(c-d)", [M, M, M, M], zm, mats,
+                  90 * rb)]
+        for name, text, kinds, z, ops, bps in cases:
+            prog = su3.Program(text, kinds)
+            ms, _ = timer.run(lambda: su3.su3_program_eval(prog, z, ops, stream), steps, 3)
+            key = f"{pname}_{name}"
+            progs[key] = entry(ms, bps * V)
+            if name == "mul":
+                tune(su3.SU3_EXPR_MUL, prec, SOA, 0, dims)
+                mf, _ = timer.run(lambda: su3.su3_mult(zm, mats[0], mats[1], stream), steps, 3)
+                progs[key]["fixed_us"] = round(mf * 1e3, 1)
+            if name == "muladd":
+                # the fixed kernel in its own tuned launch at this size
+                tune(su3.SU3_EXPR_MULADD, prec, SOA, 0, dims, f"muladd {pname}")
+                mf, _ = timer.run(lambda: su3.su3_fused_eval(zm, su3.SU3_EXPR_MULADD, mats,
+                                                             stream), steps, 3)
+                progs[key]["fixed_us"] = round(mf * 1e3, 1)
+            log(f"program {key} ({text}): {progs[key]}")
+        del ra, rb_, rz, mats, zm, zc
+    return progs
+
+
 SECTION_FUNCS = {"precision": section_precision, "fused": section_fused,
                  "ceiling": section_ceiling, "dslash": section_dslash,
-                 "batch": section_batch}
+                 "batch": section_batch, "shift": section_shift,
+                 "programs": section_programs}
 
 
 def run_variants(ctx, out):
@@ -829,16 +916,7 @@ def run_variants(ctx, out):
 
     # shifted operands at 48^4 (FP64 SoA): Cshift moves 288 B/site, the
     # product with a shifted operand 432 B/site
-    shift = {}
-    tune(su3.SU3_EXPR_CSHIFT, su3.SU3_F64, SOA, 0, dims, "cshift")
-    tune(su3.SU3_EXPR_MUL_SHIFTED, su3.SU3_F64, SOA, 0, dims, "mult_shifted")
-    for mu in range(4):
-        ms_c, _ = timer.run(lambda: su3.su3_cshift(z64, y64, mu, 1, stream), steps, 3)
-        ms_m, _ = timer.run(lambda: su3.su3_mult_shifted(z64, x64, y64, mu, 1, stream),
-                            steps, 3)
-        shift[f"mu{mu}"] = {"cshift": entry(ms_c, 288 * V), "mult": entry(ms_m, 432 * V)}
-        log(f"shift mu {mu}: {shift[f'mu{mu}']}")
-    out["shift_f64_48^4"] = shift
+    out["shift_f64_48^4"] = section_shift(ctx)
 
     out["dslash_48^4"] = section_dslash(ctx)
 
@@ -899,49 +977,7 @@ def run_variants(ctx, out):
     del host_psi
     out["vnode_f64_48^4"] = vn
 
-    # expression programs at 48^4 (one precompiled kernel interpreting the
-    # host-compiled expression): the sum plus the product of two real
-    # fields, a+b+a*b (the real-valued composite example of Section 3,
-    # Listing 2; two real inputs, one real output: 24 B/site), the streaming product,
-    # the MULADD shape and a trace into a complex field, each against its
-    # algorithmic bytes; the fixed-expression kernels beside them
-    progs = {}
-    M, R, C = su3.SU3_KIND_MATRIX, su3.SU3_KIND_REAL, su3.SU3_KIND_COMPLEX
-    for prec, pname in ((su3.SU3_F64, "f64"), (su3.SU3_F32, "f32")):
-        tune(su3.SU3_EXPR_PROGRAM, prec, SOA, 0, dims, f"program {pname}")
-        tune(su3.SU3_EXPR_PROGRAM_SCALAR, prec, SOA, 0, dims, f"program {pname} scalar result")
-        rb = REAL_BYTES[prec]
-        ra = su3.scalar_tensor(dims, prec, SOA, R)
-        rb_ = su3.scalar_tensor(dims, prec, SOA, R)
-        rz = su3.scalar_tensor(dims, prec, SOA, R)
-        su3.su3_program_eval(su3.Program("1.0", []), ra, [], stream)
-        su3.su3_program_eval(su3.Program("2.0", []), rb_, [], stream)
-        mats = [make(dims, prec, SOA, 0, testgen.FID_U0 + k) for k in range(4)]
-        zm = su3.field_tensor(dims, prec, SOA, 0)
-        zc = su3.scalar_tensor(dims, prec, SOA, C)
-        cases = [("apb_ab_real", "a+b+a*b", [R, R], rz, [ra, rb_], 3 * rb),
-                 ("mul", "a*b", [M, M], zm, mats[:2], 54 * rb),
-                 ("muladd", "a*b+c*d", [M, M, M, M], zm, mats, 90 * rb),
-                 ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb),
-                 # eight matrix registers (in double: the spilling variant)
-                 ("deep", "(a*b)*(c*d)+a-d", [M, M, M, M], zm, mats, 90 * rb)]
-        for name, text, kinds, z, ops, bps in cases:
-            prog = su3.Program(text, kinds)
-            ms, _ = timer.run(lambda: su3.su3_program_eval(prog, z, ops, stream), steps, 3)
-            key = f"{pname}_{name}"
-            progs[key] = entry(ms, bps * V)
-            if name == "mul":
-                mf, _ = timer.run(lambda: su3.su3_mult(zm, mats[0], mats[1], stream), steps, 3)
-                progs[key]["fixed_us"] = round(mf * 1e3, 1)
-            if name == "muladd":
-                # the fixed kernel in its own tuned launch at this size
-                tune(su3.SU3_EXPR_MULADD, prec, SOA, 0, dims, f"muladd {pname}")
-                mf, _ = timer.run(lambda: su3.su3_fused_eval(zm, su3.SU3_EXPR_MULADD, mats,
-                                                             stream), steps, 3)
-                progs[key]["fixed_us"] = round(mf * 1e3, 1)
-            log(f"program {key} ({text}): {progs[key]}")
-        del ra, rb_, rz, mats, zm, zc
-    out["programs_48^4"] = progs
+    out["programs_48^4"] = section_programs(ctx)
 
     out["fused_32^4"] = section_fused(ctx)
     out["batch_64"] = section_batch(ctx)

@@ -30,6 +30,8 @@ EXPRS = [
     ("trace(a*adj(b)) * c + d", (M, M, C, C)),
     ("2*i*a - b*c", (M, M, C)),
     ("(a*b)*(c*d) + a - d", (M, M, M, M)),
+    # seven matrix registers: the 8-register kernel (in double it spills)
+    ("(a*b+c*d)*(a*c+b*d) + (a-b)*(c-d)", (M, M, M, M)),
     ("real(trace(a)) * b + c", (M, M, R)),
     ("adj(a)*transpose(b) - conj(a)", (M, M)),
     ("c*d - imag(c) + 0.5", (M, M, C, R)),
