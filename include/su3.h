@@ -413,10 +413,10 @@ su3_status su3_program_info(const su3_program *p, su3_kind *result_kind,
  * field is SU3_F32 or SU3_C12_F32 (mixed: SU3_ERR_MISMATCH; half:
  * SU3_ERR_UNSUPPORTED).  A compressed output needs an SU(3)-valued
  * expression (products, adj, transpose, conj of matrices)
- * (SU3_ERR_UNSUPPORTED otherwise).  Double arithmetic with matrix values
- * runs up to 2, 4 or 8 registers per kernel variant; the 8-register one
- * keeps part of its register file in scratch memory and is several times
- * slower than the others.  z may be an operand exactly; a partial overlap is
+ * (SU3_ERR_UNSUPPORTED otherwise).  Programs with matrix values run in
+ * kernel variants of 2, 4 or 8 registers; the 8-register one runs one
+ * wave per SIMD in double and two in single, and is slower per byte than
+ * the others.  z may be an operand exactly; a partial overlap is
  * SU3_ERR_ALIAS.  The launch setting of SU3_EXPR_PROGRAM (tuned or set)
  * applies in full to programs with matrix values and a matrix result,
  * that of SU3_EXPR_PROGRAM_SCALAR to programs with matrix values and a

@@ -2,8 +2,8 @@
 // su3_program.cpp) at every site.  One site per lane.  The operand fields
 // the program reads are loaded into registers 0 .. nops-1 up front, so all
 // of a lane's loads are in flight together; the instructions then run on
-// registers, each a uniform branch on the opcode, and the result register
-// is stored.
+// registers, each a uniform branch on the opcode (matrix programs through
+// an accumulator, below), and the result register is stored.
 //
 // A register holds a 3x3 complex matrix (NE = 9; a scalar uses entry 0).
 // Programs without matrix values run in their own kernel, whose registers
@@ -154,102 +154,175 @@ __device__ __forceinline__ void load_operand(const ProgArgs &a, int k, uint32_t 
     }
 }
 
-// Matrix instructions (NE = 9 only).
+// Matrix-form instructions work on an accumulator X: X holds r[a] when an
+// instruction starts (it is copied in only when it holds another register)
+// and r[d] when it ends (it is copied out every time, so the register file
+// stays current).  A binary instruction reads r[b] in place through a
+// branch per register, so the kernel keeps the file, X and a row of
+// temporaries live instead of three matrix copies.
+
+// X = X * B, one row at a time (row i of the product needs row i of X
+// only); each entry is summed as in mat_mul.
 template <class T>
-__device__ __forceinline__ void exec_matrix(const ProgInstr in, const Reg<T, 9> &A,
-                                            const Reg<T, 9> &B, Reg<T, 9> &C)
+__device__ __forceinline__ void mul_into(Reg<T, 9> &X, const Reg<T, 9> &B)
 {
-    switch (in.op) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Cx<T> r[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T re = X.m[3 * i].re * B.m[j].re;
+            T im = X.m[3 * i].re * B.m[j].im;
+            re = fma_t(-X.m[3 * i].im, B.m[j].im, re);
+            im = fma_t(X.m[3 * i].im, B.m[j].re, im);
+#pragma unroll
+            for (int k = 1; k < 3; ++k) {
+                re = fma_t(X.m[3 * i + k].re, B.m[3 * k + j].re, re);
+                re = fma_t(-X.m[3 * i + k].im, B.m[3 * k + j].im, re);
+                im = fma_t(X.m[3 * i + k].re, B.m[3 * k + j].im, im);
+                im = fma_t(X.m[3 * i + k].im, B.m[3 * k + j].re, im);
+            }
+            r[j] = {re, im};
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            X.m[3 * i + j] = r[j];
+    }
+}
+
+// X = X (op) B for the binary opcodes OP_ADD_MM .. OP_SUB_MS.  Where a
+// scalar X meets a matrix B, entry 0 of X is read by every entry of the
+// result and is overwritten last.
+template <class T>
+__device__ __forceinline__ void binary(int op, Reg<T, 9> &X, const Reg<T, 9> &B)
+{
+    switch (op) {
+    case su3i::OP_ADD_SS:
+        X.m[0] = {X.m[0].re + B.m[0].re, X.m[0].im + B.m[0].im};
+        break;
+    case su3i::OP_SUB_SS:
+        X.m[0] = {X.m[0].re - B.m[0].re, X.m[0].im - B.m[0].im};
+        break;
+    case su3i::OP_MUL_SS:
+        X.m[0] = cmul(X.m[0], B.m[0]);
+        break;
     case su3i::OP_ADD_MM:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
-            C.m[e] = {A.m[e].re + B.m[e].re, A.m[e].im + B.m[e].im};
-        branch_end<64>();
+            X.m[e] = {X.m[e].re + B.m[e].re, X.m[e].im + B.m[e].im};
         break;
     case su3i::OP_SUB_MM:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
-            C.m[e] = {A.m[e].re - B.m[e].re, A.m[e].im - B.m[e].im};
-        branch_end<65>();
+            X.m[e] = {X.m[e].re - B.m[e].re, X.m[e].im - B.m[e].im};
         break;
     case su3i::OP_MUL_MM:
-        mat_mul<3>(A.m, B.m, C.m);
-        branch_end<66>();
+        mul_into(X, B);
         break;
     case su3i::OP_MUL_SM:
 #pragma unroll
-        for (int e = 0; e < 9; ++e)
-            C.m[e] = cmul(A.m[0], B.m[e]);
-        branch_end<67>();
+        for (int e = 8; e >= 0; --e)
+            X.m[e] = cmul(X.m[0], B.m[e]);
         break;
     case su3i::OP_MUL_MS:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
-            C.m[e] = cmul(A.m[e], B.m[0]);
-        branch_end<68>();
+            X.m[e] = cmul(X.m[e], B.m[0]);
         break;
     case su3i::OP_ADD_SM:
 #pragma unroll
-        for (int e = 0; e < 9; ++e)
-            C.m[e] = e % 4 == 0 ? Cx<T>{A.m[0].re + B.m[e].re, A.m[0].im + B.m[e].im}
-                                : B.m[e];
-        branch_end<69>();
+        for (int e = 8; e >= 0; --e)
+            X.m[e] = e % 4 == 0 ? Cx<T>{X.m[0].re + B.m[e].re, X.m[0].im + B.m[e].im} : B.m[e];
         break;
     case su3i::OP_ADD_MS:
 #pragma unroll
-        for (int e = 0; e < 9; ++e)
-            C.m[e] = e % 4 == 0 ? Cx<T>{A.m[e].re + B.m[0].re, A.m[e].im + B.m[0].im}
-                                : A.m[e];
-        branch_end<70>();
+        for (int e = 0; e < 9; e += 4)
+            X.m[e] = {X.m[e].re + B.m[0].re, X.m[e].im + B.m[0].im};
         break;
     case su3i::OP_SUB_SM:
 #pragma unroll
-        for (int e = 0; e < 9; ++e)
-            C.m[e] = e % 4 == 0 ? Cx<T>{A.m[0].re - B.m[e].re, A.m[0].im - B.m[e].im}
+        for (int e = 8; e >= 0; --e)
+            X.m[e] = e % 4 == 0 ? Cx<T>{X.m[0].re - B.m[e].re, X.m[0].im - B.m[e].im}
                                 : Cx<T>{-B.m[e].re, -B.m[e].im};
-        branch_end<71>();
         break;
-    case su3i::OP_SUB_MS:
+    default:  // OP_SUB_MS
 #pragma unroll
-        for (int e = 0; e < 9; ++e)
-            C.m[e] = e % 4 == 0 ? Cx<T>{A.m[e].re - B.m[0].re, A.m[e].im - B.m[0].im}
-                                : A.m[e];
-        branch_end<72>();
+        for (int e = 0; e < 9; e += 4)
+            X.m[e] = {X.m[e].re - B.m[0].re, X.m[e].im - B.m[0].im};
+        break;
+    }
+}
+
+// The binary instruction with r[i] as B, read where it lives.
+template <class T, int NR, int K = 0>
+__device__ __forceinline__ void binary_with(RegFile<T, 9, NR> &R, int i, int op, Reg<T, 9> &X)
+{
+    if constexpr (K < NR) {
+        if (i == K) {
+            binary<T>(op, X, R.template at<K>());
+            branch_end<K + 48>();
+        } else {
+            binary_with<T, NR, K + 1>(R, i, op, X);
+        }
+    }
+}
+
+// X = op(X) for the other opcodes (OP_CONST ignores X and sets imm[a]).
+template <class T>
+__device__ __forceinline__ void unary(const ProgInstr in, const ProgArgs &a, Reg<T, 9> &X)
+{
+    switch (in.op) {
+    case su3i::OP_CONST:
+        X.m[0] = {T(a.imm[in.a][0]), T(a.imm[in.a][1])};
+        break;
+    case su3i::OP_NEG_S:
+        X.m[0] = {-X.m[0].re, -X.m[0].im};
+        break;
+    case su3i::OP_CONJ_S:
+        X.m[0] = {X.m[0].re, -X.m[0].im};
+        break;
+    case su3i::OP_REAL:
+        X.m[0] = {X.m[0].re, T(0)};
+        break;
+    case su3i::OP_IMAG:
+        X.m[0] = {X.m[0].im, T(0)};
         break;
     case su3i::OP_NEG_M:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
-            C.m[e] = {-A.m[e].re, -A.m[e].im};
-        branch_end<73>();
-        break;
-    case su3i::OP_ADJ_M:
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                C.m[3 * i + j] = {A.m[3 * j + i].re, -A.m[3 * j + i].im};
-        branch_end<74>();
+            X.m[e] = {-X.m[e].re, -X.m[e].im};
         break;
     case su3i::OP_CONJ_M:
 #pragma unroll
         for (int e = 0; e < 9; ++e)
-            C.m[e] = {A.m[e].re, -A.m[e].im};
-        branch_end<75>();
+            X.m[e] = {X.m[e].re, -X.m[e].im};
         break;
-    case su3i::OP_TRACE:
-        C.m[0] = {(A.m[0].re + A.m[4].re) + A.m[8].re, (A.m[0].im + A.m[4].im) + A.m[8].im};
-        branch_end<76>();
+    case su3i::OP_ADJ_M:
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            X.m[4 * i].im = -X.m[4 * i].im;
+#pragma unroll
+            for (int j = i + 1; j < 3; ++j) {
+                const Cx<T> u = X.m[3 * i + j], v = X.m[3 * j + i];
+                X.m[3 * i + j] = {v.re, -v.im};
+                X.m[3 * j + i] = {u.re, -u.im};
+            }
+        }
         break;
     case su3i::OP_TRANS_M:
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                C.m[3 * i + j] = A.m[3 * j + i];
-        branch_end<77>();
+            for (int j = i + 1; j < 3; ++j) {
+                const Cx<T> u = X.m[3 * i + j];
+                X.m[3 * i + j] = X.m[3 * j + i];
+                X.m[3 * j + i] = u;
+            }
+        break;
+    case su3i::OP_TRACE:
+        X.m[0] = {(X.m[0].re + X.m[4].re) + X.m[8].re, (X.m[0].im + X.m[4].im) + X.m[8].im};
         break;
     default:
-        branch_end<78>();
         break;
     }
 }
@@ -293,8 +366,6 @@ __device__ __forceinline__ void exec(const ProgInstr in, const ProgArgs &a,
         branch_end<103>();
         break;
     default:
-        if constexpr (NE == 9)
-            exec_matrix<T>(in, A, B, C);
         branch_end<104>();
         break;
     }
@@ -321,16 +392,21 @@ __global__ __launch_bounds__(256) void k_program(ProgArgs a)
     if (s < (uint32_t)a.nsites) {
         RegFile<T, NE, NR> R;
         load_all<T, NE, NR, NT>(a, s, R);
+        Reg<T, NE> Z;   // the accumulator
+        int held = -1;  // the register Z is a copy of (the same in every lane)
         for (int pc = 0; pc < a.ninstr; ++pc) {
             const ProgInstr in = a.ins[pc];
-            Reg<T, NE> A, B, C;
-            get(R, in.a, A);
-            get(R, in.b, B);
-            exec<T, NE>(in, a, A, B, C);
-            put(R, in.d, C);
+            if (in.op != su3i::OP_CONST && in.a != held)
+                get(R, in.a, Z);
+            if (in.op >= su3i::OP_ADD_MM && in.op <= su3i::OP_SUB_MS)
+                binary_with<T, NR>(R, in.b, in.op, Z);
+            else
+                unary<T>(in, a, Z);
+            put(R, in.d, Z);
+            held = in.d;
         }
-        Reg<T, NE> Z;
-        get(R, a.result, Z);
+        if (a.result != held)
+            get(R, a.result, Z);
         switch (a.zkind) {
         case su3i::FK_MATRIX:
             if constexpr (NE == 9) {
@@ -811,14 +887,13 @@ static hipError_t go_t(int form, int nregs, int nt, int block, int grid,
     if (form == su3i::PF_SCALAR)
         return nregs <= 4 ? go_scalar<T, 4>(nt, block, grid, shm, a, st)
                           : go_scalar<T, 8>(nt, block, grid, shm, a, st);
-    // a product or a trace in double: two waves per SIMD instead of one
-    if (sizeof(T) == 8 && nregs <= 2)
+    // waves per SIMD the register file allows (double / single): 2 / 5
+    // for two registers, 1 / 3 for four, 1 / 2 for eight (in double the
+    // eight matrices fill the VGPRs and AGPRs of one wave)
+    if (nregs <= 2)
         return go<T, 9, 2>(nt, block, grid, shm, a, st);
     if (nregs <= 4)
         return go<T, 9, 4>(nt, block, grid, shm, a, st);
-    // eight registers: in double the matrices fill the VGPRs and AGPRs of
-    // one wave per SIMD and spill about 140 bytes per lane to scratch --
-    // slow, but any expression of the grammar evaluates
     return go<T, 9, 8>(nt, block, grid, shm, a, st);
 }
 

@@ -67,9 +67,9 @@ struct ProgArgs {
 enum ProgForm { PF_MATRIX = 0, PF_SCALAR = 1, PF_REAL = 2 };
 
 // Arithmetic precision F64 (all fields F64) or F32 (F32 / C12 fields).
-// Programs with matrix values use at most 4 registers in F64 and 8 in F32,
-// one site per lane; the scalar and real forms at most 8 in either,
-// program_sites_per_lane() sites per lane.  block is 64, 128 or 256;
+// Every form takes up to 8 registers; programs with matrix values run one
+// site per lane, the scalar and real forms program_sites_per_lane() sites
+// per lane.  block is 64, 128 or 256;
 // grid * block * sites per lane >= nsites.
 int program_sites_per_lane(int arith, int form);
 hipError_t launch_program(int arith, int form, int nregs, int nt,
