@@ -334,6 +334,8 @@ def main():
         variants["ceiling"] = section_ceiling(ctx)
         variants["ceiling"]["headline_of_triad"] = round(
             variants["ceiling"]["triad"]["us"] / (ms_ev * 1e3), 4)
+        variants["ceiling"]["headline_of_sum"] = round(
+            variants["ceiling"]["sum_48^4"]["us"] / (ms_ev * 1e3), 4)
         run_variants(ctx, variants)
 
     # ------------------------------------------------------- CPU baseline
@@ -390,7 +392,9 @@ def section_ceiling(ctx):
     """The STREAM-style yardsticks over the headline's bytes (arrays of a
     third of 2.29 GB each), each tuned over block, occupancy and store
     policy: triad (2:1 read:write, the product's mix), read-only,
-    write-only, copy (1:1)."""
+    write-only, copy (1:1); and the tuned sum z = x + y of two 48^4 FP64
+    SoA fields, which moves the product's bytes in the product's 27 entry
+    planes."""
     su3, torch, stream, timer = ctx["su3"], ctx["torch"], ctx["stream"], ctx["timer"]
     args = ctx["args"]
     nb = 2293235712 // 3  # 764,411,904 bytes per array (the headline's)
@@ -414,6 +418,22 @@ def section_ceiling(ctx):
         log(f"ceiling {name}: {out[name]} {cfg}")
     del arrs
     torch.cuda.synchronize()
+    # the sum z = x + y of the same fields: the product's bytes and its 27
+    # entry planes per wave (18 read, 9 written), without the products
+    dims = (48, 48, 48, 48)
+    V = ctx["testgen"].volume(dims)
+    F64, SOA = su3.SU3_F64, su3.SU3_LAYOUT_SOA
+    if "x64" in ctx:
+        x, y, z = ctx["x64"], ctx["y64"], ctx["z64"]
+    else:
+        x = ctx["make"](dims, F64, SOA, 0, ctx["testgen"].FID_X)
+        y = ctx["make"](dims, F64, SOA, 0, ctx["testgen"].FID_Y)
+        z = su3.field_tensor(dims, F64, SOA, 0)
+    cfg = ctx["tune"](su3.SU3_EXPR_ADD, F64, SOA, 0, dims, "ceiling sum")
+    ms, _ = timer.run(lambda: su3.su3_fused_eval(z, su3.SU3_EXPR_ADD, [x, y], stream), steps, 3)
+    out["sum_48^4"] = entry(ms, 432 * V, block=cfg.get("block"), occ=cfg.get("occupancy"),
+                            nt=cfg.get("nontemporal"))
+    log(f"ceiling sum z = x + y: {out['sum_48^4']}")
     return out
 
 

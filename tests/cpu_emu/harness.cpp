@@ -550,6 +550,8 @@ int main(int argc, char **argv)
                     {"trace(a*adj(b)) * c + d", 4, {0, 0, 3, 3}}, {"2*i*a - b*c", 3, {0, 0, 3}},
                     {"(a*b)*(c*d) + a - d", 4, {0, 0, 0, 0}}, {"real(trace(a)) * b + c", 3, {0, 0, 2}},
                     {"adj(a)*transpose(b) - conj(a)", 2, {0, 0}}, {"a", 1, {3}},
+                    {"a*a - 2*a + 1.5", 1, {0}}, {"c - a*b*c + trace(a)*c - 0.5*i - (-b)", 3, {0, 0, 3}},
+                    {"trace(a) + b*adj(b)", 2, {0, 0}},
                     {"((a*b)*(c*d))*((a*c)*(b*d))", 4, {0, 0, 0, 0}},
                     {"-(a - b) * imag(a) + conj(b) - 0.25 * c", 3, {2, 2, 2}},
                     {"((a*b)*(c*a))*((b*c)*(a-b)) + ((a+c)*(b+c))*((a*a)*(c-b))", 3, {2, 2, 2}}};

@@ -33,6 +33,10 @@ EXPRS = [
     # seven matrix registers: the 8-register kernel (in double it spills)
     ("(a*b+c*d)*(a*c+b*d) + (a-b)*(c-d)", (M, M, M, M)),
     ("real(trace(a)) * b + c", (M, M, R)),
+    # every mixed scalar/matrix opcode, a self product and a negated matrix
+    ("a*a - 2*a + 1.5", (M,)),
+    ("c - a*b*c + trace(a)*c - 0.5*i - (-b)", (M, M, C)),
+    ("trace(a) + b*adj(b)", (M, M)),
     ("adj(a)*transpose(b) - conj(a)", (M, M)),
     ("c*d - imag(c) + 0.5", (M, M, C, R)),
     ("1.0", ()),
