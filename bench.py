@@ -843,7 +843,7 @@ def section_programs(ctx):
                  ("muladd", "a*b+c*d", [M, M, M, M], zm, mats, 90 * rb),
                  ("trace", "trace(a*adj(b))", [M, M], zc, mats[:2], 38 * rb),
                  # seven matrix registers: the 8-register kernel (in double
-                 # it keeps part of its registers in scratch memory)
+                 # one wave per SIMD, part of its registers in AGPRs)
                  ("deep", "(a*b+c*d)*(a*c+b*d)+(a-b)*(c-d)", [M, M, M, M], zm, mats,
                   90 * rb)]
         for name, text, kinds, z, ops, bps in cases:
