@@ -37,6 +37,10 @@ EXPRS = [
     ("a*a - 2*a + 1.5", (M,)),
     ("c - a*b*c + trace(a)*c - 0.5*i - (-b)", (M, M, C)),
     ("trace(a) + b*adj(b)", (M, M)),
+    # a multiply-add in programs of two registers (run by the 4-register
+    # variant) and of one
+    ("a*b + a", (M, M)),
+    ("a*a + a*a", (M,)),
     ("adj(a)*transpose(b) - conj(a)", (M, M)),
     ("c*d - imag(c) + 0.5", (M, M, C, R)),
     ("1.0", ()),
