@@ -84,11 +84,12 @@ inline size_t lds_shape_bytes(const LdsShape &s, int cbytes)
 // fields with a halo (the tile's y and z face sites of each slice, loaded
 // and spin projected in the step before the slice, next to the interior
 // loads of the tiles that own them).
-// Most lanes of a row-tile workgroup: 512 for double spinors and for
-// virtual-node fields (whose kernels need more registers), else 1024.
+// Most lanes of a row-tile workgroup: 512 for double spinors, 768 for
+// single ones on virtual-node fields (whose kernels need more registers:
+// three waves per SIMD), else 1024.
 inline int rows_max_lanes(int cbytes, int nsub)
 {
-    return cbytes == 16 || nsub > 1 ? 512 : 1024;
+    return cbytes == 16 ? 512 : nsub > 1 ? 768 : 1024;
 }
 
 inline bool lds_shape(int schedule, int block, int cbytes, int lx, int nsub, LdsShape &s)

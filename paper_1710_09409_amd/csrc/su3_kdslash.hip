@@ -593,7 +593,7 @@ __device__ __forceinline__ void load_halo(const su3i::DslashArgs &a, uint32_t y0
 template <int SP, int TX, int TY, int TZ, bool VN>
 constexpr int lds_max_lanes()
 {
-    return TX ? TX * TY * TZ : (SP == su3i::F64 || VN ? 512 : 1024);
+    return TX ? TX * TY * TZ : (SP == su3i::F64 ? 512 : VN ? 768 : 1024);
 }
 template <int SP, bool VN>
 constexpr int lds_min_waves()
