@@ -552,7 +552,8 @@ int main(int argc, char **argv)
                     {"adj(a)*transpose(b) - conj(a)", 2, {0, 0}}, {"a", 1, {3}},
                     {"a*a - 2*a + 1.5", 1, {0}}, {"c - a*b*c + trace(a)*c - 0.5*i - (-b)", 3, {0, 0, 3}},
                     {"trace(a) + b*adj(b)", 2, {0, 0}},
-                    {"a*b + a", 2, {0, 0}}, {"a*a + a*a", 1, {0}},
+                    {"a*b + a", 2, {0, 0}}, {"a*a + a*a", 1, {0}}, {"a", 1, {0}},
+                    {"adj(adj(a)) - transpose(transpose(b)) + conj(conj(a))", 2, {0, 0}},
                     {"(a*b+c*d)*(a*c+b*d) + (a-b)*(c-d)", 4, {0, 0, 0, 0}},
                     {"((a*b)*(c*d))*((a*c)*(b*d))", 4, {0, 0, 0, 0}},
                     {"-(a - b) * imag(a) + conj(b) - 0.25 * c", 3, {2, 2, 2}},

@@ -41,6 +41,10 @@ EXPRS = [
     # variant) and of one
     ("a*b + a", (M, M)),
     ("a*a + a*a", (M,)),
+    # a matrix operand as the result (no instruction), and unary opcodes
+    # applied twice in place
+    ("a", (M,)),
+    ("adj(adj(a)) - transpose(transpose(b)) + conj(conj(a))", (M, M)),
     ("adj(a)*transpose(b) - conj(a)", (M, M)),
     ("c*d - imag(c) + 0.5", (M, M, C, R)),
     ("1.0", ()),
