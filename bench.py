@@ -62,7 +62,8 @@ REAL_BYTES = {0: 8, 1: 4, 2: 2, 3: 4}
 DSLASH_BYTES_PER_SITE = {(0, 0): 960, (1, 1): 480, (1, 3): 384}
 DSLASH_FLOPS_PER_SITE = 1320
 PREC_NAME = {0: "f64", 1: "f32", 2: "f16_f32acc", 3: "c12_f32"}
-SECTIONS = ("precision", "fused", "ceiling", "dslash", "batch", "shift", "programs")
+SECTIONS = ("precision", "fused", "ceiling", "dslash", "batch", "shift", "programs",
+            "vnode")
 
 
 def log(*a):
@@ -866,10 +867,62 @@ def section_programs(ctx):
     return progs
 
 
+def section_vnode(ctx):
+    """Grid's virtual-node layout used in place at 48^4: the streaming
+    product (FP64) and the hopping term (FP64 and FP32) for N_sub = 4 and
+    16."""
+    su3, testgen, stream, timer, tune = (ctx[k] for k in (
+        "su3", "testgen", "stream", "timer", "tune"))
+    args, host_field = ctx["args"], ctx["host_field"]
+    dims = (48, 48, 48, 48)
+    V = testgen.volume(dims)
+    steps = max(10, min(args.steps, 50))
+    # Grid's virtual-node layout used in place (N_sub sites per outer site,
+    # one per virtual node): the streaming product and the hopping term in
+    # FP64 on the same inputs, for N_sub = 4 (t and z split in two, Grid's
+    # usual split) and 16 (every direction split in two)
+    vn = {}
+    host_psi = testgen.spinor_field(V, seed=args.seed, field_id=200)
+    for nsub, simd in ((4, (1, 1, 2, 2)), (16, (2, 2, 2, 2))):
+        F64, VN = su3.SU3_F64, su3.SU3_LAYOUT_VNODE
+
+        def vfield(host, kind=su3.SU3_KIND_MATRIX, prec=F64):
+            f = su3.vnode_tensor(dims, prec, simd, kind)
+            su3.su3_field_upload(f, host, stream)
+            return f
+
+        fx, fy = vfield(host_field(V, testgen.FID_X)), vfield(host_field(V, testgen.FID_Y))
+        fz = su3.vnode_tensor(dims, F64, simd)
+        tune(su3.SU3_EXPR_MUL, F64, VN, nsub, dims, f"vnode mul {nsub}")
+        ms, _ = timer.run(lambda: su3.su3_mult(fz, fx, fy, stream), steps, 3)
+        vn[f"mul_nsub{nsub}"] = entry(ms, BYTES_PER_SITE[F64] * V)
+        del fx, fy, fz
+        U = [vfield(host_field(V, testgen.FID_U0 + mu)) for mu in range(4)]
+        fin = vfield(host_psi, su3.SU3_KIND_SPINOR)
+        fout = su3.vnode_tensor(dims, F64, simd, su3.SU3_KIND_SPINOR)
+        tune(su3.SU3_EXPR_DSLASH, F64, VN, nsub, dims, f"vnode dslash {nsub}")
+        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+        vn[f"dslash_nsub{nsub}"] = entry(ms, DSLASH_BYTES_PER_SITE[(F64, F64)] * V)
+        log(f"vnode nsub {nsub}: {vn[f'mul_nsub{nsub}']} {vn[f'dslash_nsub{nsub}']}")
+        del U, fin, fout
+        # the same hopping term with single-precision spinors and links
+        F32 = su3.SU3_F32
+        U = [vfield(host_field(V, testgen.FID_U0 + mu), prec=F32) for mu in range(4)]
+        fin = vfield(host_psi, su3.SU3_KIND_SPINOR, prec=F32)
+        fout = su3.vnode_tensor(dims, F32, simd, su3.SU3_KIND_SPINOR)
+        tune(su3.SU3_EXPR_DSLASH, F32, VN, nsub, dims, f"vnode dslash f32 {nsub}")
+        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
+        vn[f"dslash_f32_nsub{nsub}"] = entry(ms, DSLASH_BYTES_PER_SITE[(F32, F32)] * V)
+        log(f"vnode nsub {nsub} f32 dslash: {vn[f'dslash_f32_nsub{nsub}']}")
+        del U, fin, fout
+    del host_psi
+    return vn
+
+
 SECTION_FUNCS = {"precision": section_precision, "fused": section_fused,
                  "ceiling": section_ceiling, "dslash": section_dslash,
                  "batch": section_batch, "shift": section_shift,
-                 "programs": section_programs}
+                 "programs": section_programs, "vnode": section_vnode}
 
 
 def run_variants(ctx, out):
@@ -956,46 +1009,7 @@ def run_variants(ctx, out):
     log(f"dslash shard 48^3x6: {out['dslash_shard_f64_soa_48^3x6']}")
     del U, fin, fout
 
-    # Grid's virtual-node layout used in place (N_sub sites per outer site,
-    # one per virtual node): the streaming product and the hopping term in
-    # FP64 on the same inputs, for N_sub = 4 (t and z split in two, Grid's
-    # usual split) and 16 (every direction split in two)
-    vn = {}
-    host_psi = testgen.spinor_field(V, seed=args.seed, field_id=200)
-    for nsub, simd in ((4, (1, 1, 2, 2)), (16, (2, 2, 2, 2))):
-        F64, VN = su3.SU3_F64, su3.SU3_LAYOUT_VNODE
-
-        def vfield(host, kind=su3.SU3_KIND_MATRIX, prec=F64):
-            f = su3.vnode_tensor(dims, prec, simd, kind)
-            su3.su3_field_upload(f, host, stream)
-            return f
-
-        fx, fy = vfield(host_field(V, testgen.FID_X)), vfield(host_field(V, testgen.FID_Y))
-        fz = su3.vnode_tensor(dims, F64, simd)
-        tune(su3.SU3_EXPR_MUL, F64, VN, nsub, dims, f"vnode mul {nsub}")
-        ms, _ = timer.run(lambda: su3.su3_mult(fz, fx, fy, stream), steps, 3)
-        vn[f"mul_nsub{nsub}"] = entry(ms, BYTES_PER_SITE[F64] * V)
-        del fx, fy, fz
-        U = [vfield(host_field(V, testgen.FID_U0 + mu)) for mu in range(4)]
-        fin = vfield(host_psi, su3.SU3_KIND_SPINOR)
-        fout = su3.vnode_tensor(dims, F64, simd, su3.SU3_KIND_SPINOR)
-        tune(su3.SU3_EXPR_DSLASH, F64, VN, nsub, dims, f"vnode dslash {nsub}")
-        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
-        vn[f"dslash_nsub{nsub}"] = entry(ms, DSLASH_BYTES_PER_SITE[(F64, F64)] * V)
-        log(f"vnode nsub {nsub}: {vn[f'mul_nsub{nsub}']} {vn[f'dslash_nsub{nsub}']}")
-        del U, fin, fout
-        # the same hopping term with single-precision spinors and links
-        F32 = su3.SU3_F32
-        U = [vfield(host_field(V, testgen.FID_U0 + mu), prec=F32) for mu in range(4)]
-        fin = vfield(host_psi, su3.SU3_KIND_SPINOR, prec=F32)
-        fout = su3.vnode_tensor(dims, F32, simd, su3.SU3_KIND_SPINOR)
-        tune(su3.SU3_EXPR_DSLASH, F32, VN, nsub, dims, f"vnode dslash f32 {nsub}")
-        ms, _ = timer.run(lambda: su3.su3_dslash(fout, U, fin, stream), steps, 3)
-        vn[f"dslash_f32_nsub{nsub}"] = entry(ms, DSLASH_BYTES_PER_SITE[(F32, F32)] * V)
-        log(f"vnode nsub {nsub} f32 dslash: {vn[f'dslash_f32_nsub{nsub}']}")
-        del U, fin, fout
-    del host_psi
-    out["vnode_f64_48^4"] = vn
+    out["vnode_f64_48^4"] = section_vnode(ctx)
 
     out["programs_48^4"] = section_programs(ctx)
 
